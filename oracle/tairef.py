@@ -1,0 +1,378 @@
+"""Plain FP64 oracle of the tensorized approximation (TA) of the long-range
+two-electron integrals tensor (Badreddine, Chollet, Grigori, arXiv 2210.13069).
+
+TEST INFRASTRUCTURE ONLY: imported by tests, the smoke check and the benchmark's
+CPU-baseline leg.  It shares no code with the GPU library.
+
+What the method computes (paper section 3, eqs. kernel/TEI2/chebcheb and
+Theorem 3.1 with eq. tensors):
+
+  erf(w r)/r = (2/sqrt(pi)) * int_0^w exp(-s^2 r^2) ds                (eq. kernel)
+             ~ (2/sqrt(pi)) * sum_k w_k exp(-t_k^2 r^2)                   (eq. TEI2)
+
+with Gauss-Legendre nodes t_k and weights w_k mapped to [0, omega].  Each 1D
+factor exp(-t_k^2 (x-y)^2) on [-L,L]^2 is replaced by its tensor Chebyshev
+interpolant (eq. chebcheb).  We keep that interpolant in Lagrange (node-value)
+form, which is the same polynomial as the paper's coefficient form:
+
+  exp(-t_k^2 (x-y)^2) ~ sum_{a,b} K_k(a,b) l_a(x) l_b(y),   K_k(a,b) = exp(-t_k^2 (xi_a-xi_b)^2)
+
+The 1D moment of a basis pair against the Lagrange basis (eq. defV, node form)
+
+  m_{p,d}(a) = int_{-L}^{L} g_mu,d(x) g_nu,d(x) l_a(x) dx
+
+gives Theorem 3.1 in node form:
+
+  B(p,q) = (2/sqrt(pi)) sum_k w_k prod_{d=1..3} m_{p,d}^T K_k m_{q,d}
+
+Every function below cites the passage it follows.  All arithmetic is FP64.
+Notation: nb basis functions, pairs p=(mu,nu) with mu<=nu in row-major upper
+triangle order, npair = nb(nb+1)/2; n Chebyshev nodes per direction; nq
+quadrature nodes in t.
+"""
+import math
+
+import numpy as np
+
+SQRT_PI = math.sqrt(math.pi)
+
+NODES_LOBATTO = 0
+NODES_GAUSS = 1
+
+
+# ---------------------------------------------------------------------------
+# Quadrature in t (section 3.1, eq. TEI2; Gauss quadrature, Prop. 2.4)
+# ---------------------------------------------------------------------------
+def gauss_legendre(nq):
+    """Gauss-Legendre nodes z_i and weights on [-1, 1] (Prop. 2.4).
+
+    Newton iteration on the Legendre polynomial P_nq, evaluated with the
+    three-term recurrence (j+1) P_{j+1} = (2j+1) x P_j - j P_{j-1}, started from
+    the classical estimate cos(pi (i - 1/4) / (nq + 1/2)).  Returned in
+    increasing order of z.
+    """
+    if nq < 1:
+        raise ValueError("nq must be >= 1")
+    i = np.arange(1, nq + 1, dtype=np.float64)
+    x = np.cos(np.pi * (i - 0.25) / (nq + 0.5))
+    for _ in range(100):
+        p0 = np.ones_like(x)
+        p1 = x.copy()
+        for j in range(1, nq):
+            p0, p1 = p1, ((2 * j + 1) * x * p1 - j * p0) / (j + 1)
+        # p1 = P_nq(x), p0 = P_{nq-1}(x)
+        dp = nq * (x * p1 - p0) / (x * x - 1.0)
+        dx = p1 / dp
+        x = x - dx
+        if np.max(np.abs(dx)) < 1e-15:
+            break
+    # final derivative at the converged nodes for the weights
+    p0 = np.ones_like(x)
+    p1 = x.copy()
+    for j in range(1, nq):
+        p0, p1 = p1, ((2 * j + 1) * x * p1 - j * p0) / (j + 1)
+    dp = nq * (x * p1 - p0) / (x * x - 1.0)
+    wts = 2.0 / ((1.0 - x * x) * dp * dp)
+    order = np.argsort(x)
+    return x[order], wts[order]
+
+
+def time_nodes(omega, nq):
+    """Nodes t_k and weights w_k of int_0^omega f(s) ds (eq. TEI2).
+
+    t_k = (omega/2)(1 + z_k), w_k = (omega/2) zw_k.  With these weights the
+    paper's prefactor (omega/sqrt(pi)) sum_i zw_i equals (2/sqrt(pi)) sum_k w_k.
+    """
+    z, zw = gauss_legendre(nq)
+    return 0.5 * omega * (1.0 + z), 0.5 * omega * zw
+
+
+# ---------------------------------------------------------------------------
+# Chebyshev nodes and the Lagrange basis (Def. 2.2; Lobatto nodes for TA per
+# the remark closing section 5.1)
+# ---------------------------------------------------------------------------
+def cheb_nodes(n, L, kind=NODES_LOBATTO):
+    """Chebyshev nodes xi_a on [-L, L] and their barycentric weights beta_a.
+
+    Lobatto (second kind): xi_a = L cos(pi (a-1)/(n-1)), beta_a = (-1)^(a-1),
+    halved at both ends.  Gauss (first kind): xi_a = L cos((2a-1) pi / (2n)),
+    beta_a = (-1)^(a-1) sin((2a-1) pi / (2n)).  a = 1..n (Def. 2.2).  The
+    barycentric weights are those of Berrut and Trefethen (SIAM Review 2004).
+    """
+    if n < 2:
+        raise ValueError("n must be >= 2")
+    a = np.arange(n, dtype=np.float64)
+    sign = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    if kind == NODES_LOBATTO:
+        xi = L * np.cos(np.pi * a / (n - 1))
+        beta = sign.copy()
+        beta[0] *= 0.5
+        beta[-1] *= 0.5
+    elif kind == NODES_GAUSS:
+        theta = (2.0 * a + 1.0) * np.pi / (2.0 * n)
+        xi = L * np.cos(theta)
+        beta = sign * np.sin(theta)
+    else:
+        raise ValueError("unknown node kind")
+    return xi, beta
+
+
+def lagrange_basis(xi, beta, x):
+    """Values l_a(x) of the Lagrange basis on the nodes xi, shape (len(x), n).
+
+    Barycentric formula of the second kind:
+    l_a(x) = (beta_a / (x - xi_a)) / sum_b beta_b / (x - xi_b),
+    with l_a(xi_b) = delta_ab taken exactly when x hits a node.
+    """
+    x = np.asarray(x, dtype=np.float64).reshape(-1)
+    diff = x[:, None] - xi[None, :]
+    hit = diff == 0.0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        terms = beta[None, :] / diff
+        ell = terms / np.sum(terms, axis=1, keepdims=True)
+    rows = np.any(hit, axis=1)
+    if np.any(rows):
+        ell[rows] = hit[rows].astype(np.float64)
+    return ell
+
+
+def ktables(t, xi):
+    """Node-value interpolation matrices K_k(a,b) = exp(-t_k^2 (xi_a - xi_b)^2).
+
+    These are the values of each 1D factor of eq. TEI2 on the n x n Chebyshev
+    grid, i.e. the Lagrange-form counterpart of the coefficient matrices A^(i)
+    of eq. chebcheb.  Shape (nq, n, n).
+    """
+    d2 = (xi[:, None] - xi[None, :]) ** 2
+    return np.exp(-(np.asarray(t)[:, None, None] ** 2) * d2[None, :, :])
+
+
+# ---------------------------------------------------------------------------
+# Basis and pairs (eqs. basis, primi; Prop. 2.1; symmetric pairs, section 6.3)
+# ---------------------------------------------------------------------------
+def _double_factorial_odd(l):
+    """(2l-1)!! with (-1)!! = 1."""
+    r = 1
+    for k in range(2 * l - 1, 0, -2):
+        r *= k
+    return float(r)
+
+
+def norm_1d(alpha, l):
+    """Constant making one Cartesian factor (x^l exp(-alpha x^2)) unit-norm.
+
+    N = [ (2 alpha/pi)^(1/2) (4 alpha)^l / (2l-1)!! ]^(1/2).  The paper only
+    names c_j a normalisation constant (eq. primi); per-factor unit norm is the
+    reading taken here.
+    """
+    return math.sqrt(math.sqrt(2.0 * alpha / math.pi) * (4.0 * alpha) ** l
+                     / _double_factorial_odd(l))
+
+
+def pair_list(nb):
+    """(mu, nu) of every pair mu <= nu, row-major upper triangle.
+
+    Pair index p(mu,nu) = mu*nb - mu(mu-1)/2 + (nu - mu) (0-based), which is the
+    order of this list.  Pair symmetry g_mu g_nu = g_nu g_mu (section 6.3).
+    """
+    mu, nu = np.triu_indices(nb)
+    return mu.astype(np.int64), nu.astype(np.int64)
+
+
+def pair_index(nb, mu, nu):
+    """Pair index of (mu, nu) with mu <= nu."""
+    return mu * nb - (mu * (mu - 1)) // 2 + (nu - mu)
+
+
+def basis_scale(alpha, lxyz, coef):
+    """Per-function scale s_mu and per-direction unit-norm factors.
+
+    Returns (c, nd): nd[mu, d] = norm_1d(alpha_mu, l_mu,d) when coef is None;
+    otherwise nd = 1 and c = coef (multiplier of the whole 3D function).
+    """
+    nb = len(alpha)
+    if coef is None:
+        nd = np.empty((nb, 3))
+        for m in range(nb):
+            for d in range(3):
+                nd[m, d] = norm_1d(alpha[m], int(lxyz[m, d]))
+        return np.ones(nb), nd
+    return np.asarray(coef, dtype=np.float64), np.ones((nb, 3))
+
+
+# ---------------------------------------------------------------------------
+# 1D moments (eq. defV, with the Lagrange basis in place of T_n)
+# ---------------------------------------------------------------------------
+def moments(center, alpha, lxyz, L, n, kind=NODES_LOBATTO, coef=None,
+            pairs=None, panels=8, order=48, cutoff=9.0):
+    """Moments M[d, a, p] = int_{-L}^{L} g_mu,d(x) g_nu,d(x) l_a(x) dx.
+
+    Follows eq. defV: the 1D factor of the pair product, by the Gaussian
+    product rule (Prop. 2.1, eq. gauss_prod),
+        g_mu,d g_nu,d (x) = N N' (x-A)^l (x-B)^l' E exp(-p (x-P)^2),
+        p = a+b, P = (aA+bB)/p, E = exp(-ab/p (A-B)^2),
+    is integrated against each Lagrange basis function over the box [-L,L]
+    (eq. compact).  The integral is taken by composite Gauss-Legendre
+    (`panels` panels of `order` nodes) on [-L,L] intersected with
+    [P - cutoff/sqrt(p), P + cutoff/sqrt(p)]; outside it the Gaussian is below
+    exp(-cutoff^2) of its peak.  A non-None `coef` multiplies the pair's
+    d = 0 factor by coef_mu coef_nu.
+
+    `pairs` optionally restricts to a list of pair indices (columns are then
+    in that order).  Returns shape (3, n, npair_selected).
+    """
+    center = np.asarray(center, dtype=np.float64).reshape(-1, 3)
+    alpha = np.asarray(alpha, dtype=np.float64).reshape(-1)
+    lxyz = np.asarray(lxyz, dtype=np.int64).reshape(-1, 3)
+    nb = len(alpha)
+    xi, beta = cheb_nodes(n, L, kind)
+    c, nd = basis_scale(alpha, lxyz, coef)
+    mu_all, nu_all = pair_list(nb)
+    if pairs is None:
+        sel = np.arange(len(mu_all))
+    else:
+        sel = np.asarray(pairs, dtype=np.int64)
+    mu = mu_all[sel]
+    nu = nu_all[sel]
+    z, zw = gauss_legendre(order)
+    M = np.zeros((3, n, len(sel)))
+    chunk = 512
+    for d in range(3):
+        for s in range(0, len(sel), chunk):
+            m_ = mu[s:s + chunk]
+            n_ = nu[s:s + chunk]
+            A = center[m_, d]
+            B = center[n_, d]
+            a = alpha[m_]
+            b = alpha[n_]
+            la = lxyz[m_, d]
+            lb = lxyz[n_, d]
+            p = a + b
+            P = (a * A + b * B) / p
+            E = np.exp(-a * b / p * (A - B) ** 2)
+            pref = nd[m_, d] * nd[n_, d] * E
+            if d == 0:
+                pref = pref * c[m_] * c[n_]
+            lo = np.maximum(-L, P - cutoff / np.sqrt(p))
+            hi = np.minimum(L, P + cutoff / np.sqrt(p))
+            empty = lo >= hi
+            hi = np.where(empty, lo, hi)
+            h = (hi - lo) / panels
+            # quadrature points x[j, i]: pair j, point i
+            k = np.arange(panels)
+            mid = lo[:, None] + (k[None, :] + 0.5) * h[:, None]
+            x = (mid[:, :, None] + 0.5 * h[:, None, None] * z[None, None, :]).reshape(len(m_), -1)
+            wq = (0.5 * h[:, None, None] * np.ones((1, panels, 1)) * zw[None, None, :]).reshape(len(m_), -1)
+            f = (pref[:, None] * (x - A[:, None]) ** la[:, None] * (x - B[:, None]) ** lb[:, None]
+                 * np.exp(-p[:, None] * (x - P[:, None]) ** 2))
+            ell = lagrange_basis(xi, beta, x.reshape(-1)).reshape(len(m_), -1, n)
+            M[d, :, s:s + chunk] = np.einsum("ji,jia->aj", f * wq, ell)
+            M[d, :, s:s + chunk][:, empty] = 0.0
+    return M
+
+
+# ---------------------------------------------------------------------------
+# B: Algorithm 1 (entry-wise) and Theorem 3.1 in matrix form
+# ---------------------------------------------------------------------------
+def B_entries(M, K, w, p_idx, q_idx):
+    """Entries B(p,q) by Algorithm 1: loop over quadrature nodes k, form
+    F = prod_d m_{p,d}^T K_k m_{q,d} (the Hadamard product of Theorem 3.1 for a
+    single pair of pairs), accumulate s += w_k F, return (2/sqrt(pi)) s.
+
+    M has shape (3, n, npair); p_idx/q_idx index its columns.
+    """
+    p_idx = np.asarray(p_idx, dtype=np.int64).reshape(-1)
+    q_idx = np.asarray(q_idx, dtype=np.int64).reshape(-1)
+    s = np.zeros(len(p_idx))
+    for k in range(K.shape[0]):
+        F = np.ones(len(p_idx))
+        for d in range(3):
+            mp = M[d][:, p_idx]                      # (n, e)
+            mq = M[d][:, q_idx]
+            F *= np.einsum("ae,ab,be->e", mp, K[k], mq)
+        s += w[k] * F
+    return (2.0 / SQRT_PI) * s
+
+
+def B_full(M, K, w, rows=None):
+    """B (npair x npair, or the given rows) by Theorem 3.1 in matrix form:
+    B = (2/sqrt(pi)) sum_k w_k  (M_1^T K_k M_1) o (M_2^T K_k M_2) o (M_3^T K_k M_3)
+    where o is the Hadamard product (eq. Fi with Prop. 2.5)."""
+    npair = M.shape[2]
+    r = np.arange(npair) if rows is None else np.asarray(rows, dtype=np.int64)
+    B = np.zeros((len(r), npair))
+    for k in range(K.shape[0]):
+        F = np.ones((len(r), npair))
+        for d in range(3):
+            F *= M[d][:, r].T @ (K[k] @ M[d])
+        B += w[k] * F
+    return (2.0 / SQRT_PI) * B
+
+
+def B_kronecker(M, K, w):
+    """B by eq. tensors: B = (2/sqrt(pi)) sum_k w_k Mt (K_k (x) K_k (x) K_k) Mt^T,
+    Mt(p, a1 a2 a3) = prod_d m_{p,d}(a_d).  Forms the n^3 x n^3 Kronecker
+    product explicitly: tiny inputs only."""
+    n = M.shape[1]
+    npair = M.shape[2]
+    Mt = np.einsum("ap,bp,cp->pabc", M[0], M[1], M[2]).reshape(npair, n ** 3)
+    B = np.zeros((npair, npair))
+    for k in range(K.shape[0]):
+        kron = np.kron(np.kron(K[k], K[k]), K[k])
+        B += w[k] * (Mt @ kron @ Mt.T)
+    return (2.0 / SQRT_PI) * B
+
+
+# ---------------------------------------------------------------------------
+# Coulomb matrix J (section 6, eqs. Coul and coulapprox, with eq. ig1)
+# ---------------------------------------------------------------------------
+def density_pairs(D):
+    """Pair vector Dt_q = D(k,l) (2 - delta_kl) for q = (k,l), k <= l.
+
+    J(mu,nu) = sum over ALL ordered (k,l) of B(mu nu, k l) D(k,l); with a
+    symmetric D the two orders of an off-diagonal pair are folded into one
+    pair term.  Only the upper triangle of D is read.
+    """
+    D = np.asarray(D, dtype=np.float64)
+    mu, nu = pair_list(D.shape[0])
+    return D[mu, nu] * np.where(mu == nu, 1.0, 2.0)
+
+
+def unpack_pairs(v, nb):
+    """Symmetric nb x nb matrix from a pair vector."""
+    mu, nu = pair_list(nb)
+    J = np.zeros((nb, nb))
+    J[mu, nu] = v
+    J[nu, mu] = v
+    return J
+
+
+def J_grid(M, K, w, D):
+    """J through the n^3 Chebyshev grid tensor, B never formed.
+
+    Follows eq. coulapprox with the mode-product evaluation of eq. ig1:
+      rho(a1,a2,a3) = sum_q Dt_q prod_d m_{q,d}(a_d)          (Dt^T Mt)
+      Phi = (2/sqrt(pi)) sum_k w_k rho x_1 K_k x_2 K_k x_3 K_k   ((x) K_k applied)
+      J_p = sum_a prod_d m_{p,d}(a_d) Phi(a)                     (Mt Phi)
+    and unpacks J_p into the symmetric nb x nb matrix.
+    """
+    nb = D.shape[0]
+    Dt = density_pairs(D)
+    rho = np.einsum("q,aq,bq,cq->abc", Dt, M[0], M[1], M[2], optimize=True)
+    Phi = np.zeros_like(rho)
+    for k in range(K.shape[0]):
+        Kk = K[k]
+        T = np.einsum("ia,abc->ibc", Kk, rho, optimize=True)
+        T = np.einsum("jb,ibc->ijc", Kk, T, optimize=True)
+        T = np.einsum("kc,ijc->ijk", Kk, T, optimize=True)
+        Phi += w[k] * T
+    Phi *= 2.0 / SQRT_PI
+    Jp = np.einsum("ap,bp,cp,abc->p", M[0], M[1], M[2], Phi, optimize=True)
+    return unpack_pairs(Jp, nb)
+
+
+def J_direct_rows(M, K, w, D, rows):
+    """J_p = sum_q B(p,q) Dt_q for the given pair rows, with the rows of B
+    from Theorem 3.1 (eq. Coul in the atomic-orbital basis)."""
+    Dt = density_pairs(D)
+    return B_full(M, K, w, rows=rows) @ Dt
