@@ -1,0 +1,303 @@
+#!/usr/bin/env python3
+"""Benchmark of the tensorized-approximation (TA) long-range TEI hot path on
+one MI355X.
+
+One step = one pass of the hot path over the Nb = 400 workload (40 atoms with
+s, p, d shells, 80200 pairs, omega = 0.3, nq = 32, n = 40, L = 16): FP64
+quadrature tables and moments, operand preparation, and the fused assembly of
+the full 80200 x 80200 B, in the headline arithmetic (split FP16, 3 products).
+`value` = stored B entries per second of that step, inputs resident on the
+device.  The same line reports the FP64 / FP32 / BF16 forms of the same step,
+the batched persistent assembly of 64 molecules (graph replay vs one launch
+sequence per molecule), the J-build through the grid tensor (Nb = 1000), the
+error of every form against the FP64 oracle on sampled entries, the roofline
+of the dominant kernel, and the oracle timed on the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-headline] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "long-range TEI entries/s: split-BF16/FP32 vs FP64 GPU, at stated rel. error"
+# MI355X published dense peaks, TFLOP/s
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0, "f16x3": 2500.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(npair, nq, n):
+    """Unique entries x nodes x (three length-n dot products + two Hadamard
+    products + the weighted accumulation) = npair(npair+1)/2 * nq * (6n + 4)."""
+    return npair * (npair + 1) / 2 * nq * (6 * n + 4)
+
+
+def traffic_from_profiles(kernel_src_sha, workload):
+    """HBM bytes per launch from committed counter summaries, or None when
+    the kernel source changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return None
+    rec = data.get(workload)
+    if not rec or rec.get("kernel_src_sha") != kernel_src_sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def src_sha():
+    h = hashlib.sha256()
+    for f in ("k_assemble.hip",):
+        h.update(open(os.path.join(ROOT, "paper_2210_13069_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="f16x3", help="headline arithmetic")
+    ap.add_argument("--only-headline", action="store_true", help="skip the comparison paths")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU layout is described in "
+              "DESIGN.md (shard tiles / pairs, one all-reduce of the grid density). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2210_13069_amd import inputs as I
+    from paper_2210_13069_amd import tai
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    ctx = tai.Context(0)
+    K, W = args.steps, args.warmup
+    head = tai.PREC_BY_NAME[args.prec]
+
+    # ---------------- headline workload --------------------------------------
+    b, P = I.spd400(omega=0.3)
+    npair, n, nq = b.npair, P.n, P.nq
+    ba = tai.BasisArrays(b)
+    M = torch.empty((3, n, npair), dtype=torch.float64, device=dev)
+    B32 = torch.empty((npair, npair), dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(11)
+    sp = np.concatenate([rng.integers(0, npair, 240), [0, npair - 1]])
+    sq = np.concatenate([rng.integers(0, npair, 240), [npair - 1, 0]])
+    spt = torch.as_tensor(sp, device=dev)
+    sqt = torch.as_tensor(sq, device=dev)
+
+    def run_steps(prec, Bbuf, steps, warmup):
+        params = tai.make_params(P, prec)
+        for _ in range(warmup):
+            ctx.moments(ba, P, M)
+            ctx.assemble_B(M, npair, params, Bbuf)
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.moments(ba, P, M)
+            ctx.assemble_B(M, npair, params, Bbuf)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stages = {s: ctx.profile_read(s) for s in ("nodes", "moments", "pack", "project", "assemble")}
+        ctx.profile_enable(False)
+        ms = (t1 - t0) * 1e3 / steps
+        sample = Bbuf[spt, sqt].double().cpu().numpy()
+        return ms, stages, sample
+
+    log(f"headline {args.prec}: Nb={b.nb} npair={npair} steps={K} warmup={W}")
+    ms_head, st_head, samp_head = run_steps(head, B32 if head != tai.FP64 else None, K, W)
+    asm_ms = st_head["assemble"][0] / max(1, st_head["assemble"][1])
+    entries = float(npair) * npair
+    value = entries / (ms_head / 1e3)
+    log(f"headline {ms_head:.2f} ms/step, assemble kernel {asm_ms:.2f} ms")
+
+    flops = algorithmic_flops(npair, nq, n)
+    achieved = flops / (asm_ms / 1e3) / 1e12
+    peak = PEAK_TFLOPS[args.prec]
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 5), "traffic": traffic_from_profiles(src_sha(), "spd400"),
+                "kernel": "assemble_kernel", "flops_per_launch": flops,
+                "launch_ms": round(asm_ms, 4)}
+
+    paths = {args.prec: {"ms_per_step": round(ms_head, 3), "entries_per_s": value,
+                         "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st_head.items()}}}
+    samples = {args.prec: samp_head}
+
+    if not args.only_headline:
+        B64 = torch.empty((npair, npair), dtype=torch.float64, device=dev)
+        for name in ("fp64", "fp32", "bf16x6", "bf16x3"):
+            if name == args.prec:
+                continue
+            prec = tai.PREC_BY_NAME[name]
+            steps = max(1, K // 2)
+            log(f"path {name}: steps={steps}")
+            ms, st, samp = run_steps(prec, B64 if prec == tai.FP64 else B32, steps, 1)
+            paths[name] = {"ms_per_step": round(ms, 3), "entries_per_s": entries / (ms / 1e3),
+                           "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()}}
+            samples[name] = samp
+        del B64
+        torch.cuda.empty_cache()
+        if "fp64" in paths:
+            for name in paths:
+                paths[name]["speedup_vs_fp64"] = round(paths[name]["entries_per_s"] / paths["fp64"]["entries_per_s"], 3)
+    del B32
+    torch.cuda.empty_cache()
+
+    # ---------------- batched persistent assembly (64 molecules) --------------
+    batched = None
+    if not args.only_headline:
+        mols = I.batch64()
+        structs, keep, bufs = [], [], []
+        for mb, mp in mols:
+            bam = tai.BasisArrays(mb)
+            Mm = torch.empty((3, mp.n, mb.npair), dtype=torch.float64, device=dev)
+            Bm = torch.empty((mb.npair, mb.npair), dtype=torch.float32, device=dev)
+            keep.append(bam)
+            bufs.append((Mm, Bm))
+            structs.append(tai.tai_mol(bam.struct, tai.make_params(mp, head), Mm.data_ptr(), Bm.data_ptr(), mb.npair))
+        ent = float(sum(mb.npair ** 2 for mb, _ in mols))
+        log("batched: 64 molecules")
+        for _ in range(W):
+            ctx.assemble_B_batched(structs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            ctx.assemble_B_batched(structs)
+        torch.cuda.synchronize()
+        ms_b = (time.perf_counter() - t0) * 1e3 / K
+
+        def per_mol():
+            for (mb, mp), bam, (Mm, Bm) in zip(mols, keep, bufs):
+                ctx.moments(bam, mp, Mm)
+                ctx.assemble_B(Mm, mb.npair, tai.make_params(mp, head), Bm)
+        for _ in range(W):
+            per_mol()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            per_mol()
+        torch.cuda.synchronize()
+        ms_p = (time.perf_counter() - t0) * 1e3 / K
+        batched = {"workload": "64 molecules, atoms 5..30 in [-5,5]^3, s+p, omega in {0.3,0.5,1.0}, nq=24, n=32, L=12",
+                   "entries": ent, "ms_batched_graph": round(ms_b, 3), "ms_per_molecule_launches": round(ms_p, 3),
+                   "entries_per_s_batched": ent / (ms_b / 1e3), "speedup": round(ms_p / ms_b, 3)}
+        del bufs
+        torch.cuda.empty_cache()
+
+    # ---------------- J through the grid tensor (Nb = 1000) -------------------
+    japply = None
+    if not args.only_headline:
+        jb, jP, D = I.jbuild1000()
+        jba = tai.BasisArrays(jb)
+        Mj = torch.empty((3, jP.n, jb.npair), dtype=torch.float64, device=dev)
+        Dj = torch.as_tensor(D, device=dev)
+        Jj = torch.empty((jb.nb, jb.nb), dtype=torch.float64, device=dev)
+        jparams = tai.make_params(jP, tai.FP64)
+        log("J-build: Nb=1000")
+        for _ in range(W):
+            ctx.moments(jba, jP, Mj)
+            ctx.apply_J(Mj, jb.nb, jparams, Dj, Jj)
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            ctx.moments(jba, jP, Mj)
+            ctx.apply_J(Mj, jb.nb, jparams, Dj, Jj)
+        torch.cuda.synchronize()
+        ms_j = (time.perf_counter() - t0) * 1e3 / K
+        stj = {s: ctx.profile_read(s) for s in ("moments", "apply_J")}
+        ctx.profile_enable(False)
+        japply = {"workload": "Nb=1000 (100 atoms s,p,d), 500500 pairs, omega=0.4, nq=32, n=48, L=24; moments + J",
+                  "dtype": "fp64", "ms_per_step": round(ms_j, 3),
+                  "effective_entries_per_s": float(jb.npair) ** 2 / (ms_j / 1e3),
+                  "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stj.items()}}
+        del Mj, Jj
+        torch.cuda.empty_cache()
+
+    # ---------------- oracle on the host (bounded sample) ---------------------
+    cpu = None
+    rel_error = None
+    if not args.no_cpu:
+        from oracle import tairef as T
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        log(f"oracle sample on the host ({cores} threads)")
+        sel = np.unique(np.concatenate([sp, sq]))
+        rows = rng.choice(npair, 48, replace=False)
+        cols_extra = rng.choice(npair, 1536, replace=False)
+        allp = np.unique(np.concatenate([sel, rows, cols_extra]))
+        t0 = time.perf_counter()
+        Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, pairs=allp)
+        t, w = T.time_nodes(P.omega, P.nq)
+        xi, _ = T.cheb_nodes(P.n, P.L)
+        Kt = T.ktables(t, xi)
+        Brows = T.B_full(Mr, Kt, w, rows=np.searchsorted(allp, rows))
+        t_or = time.perf_counter() - t0
+        n_or = Brows.size
+        cpu = {"value": n_or / t_or, "unit": "entries/s", "cores": int(cores), "kind": "oracle",
+               "sample": f"moments of {len(allp)} pairs + B on {len(rows)} x {len(allp)} entries "
+                         f"(Theorem 3.1 matrix route) of the Nb=400 workload; {t_or:.1f} s"}
+        ref = T.B_entries(Mr, Kt, w, np.searchsorted(allp, sp), np.searchsorted(allp, sq))
+        dref = T.B_entries(Mr, Kt, w, np.searchsorted(allp, sel), np.searchsorted(allp, sel))
+        scale = float(np.max(np.abs(dref)))
+        rel_error = {}
+        big = np.abs(ref) >= 1e-8 * scale
+        for name, sv in samples.items():
+            err = np.abs(sv - ref)
+            rel_error[name] = {"normwise": float(np.max(err) / scale),
+                               "elementwise_mean": float(np.mean(err[big] / np.abs(ref[big]))),
+                               "elementwise_max": float(np.max(err[big] / np.abs(ref[big])))}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_head, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": "spd400: Nb=400 (40 atoms in [-8,8]^3, s+p+d shells), 80200 pairs, "
+                               "omega=0.3, nq=32, n=40, L=16; step = moments + full B (6.43e9 entries)",
+                   "nb": b.nb, "npair": npair, "entries": entries, "omega": P.omega, "nq": nq, "n": n, "L": P.L,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "rel_error_vs_oracle": rel_error,
+        "paths": paths,
+        "batched": batched,
+        "japply": japply,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * tai.h -- C ABI of the MI355X (gfx950) library for the tensorized
+ * approximation (TA) of the long-range two-electron integrals tensor
+ * (Badreddine, Chollet, Grigori, arXiv 2210.13069).
+ *
+ * Method (section 3 of the paper).  The long-range kernel is written as
+ *     erf(w r)/r = (2/sqrt(pi)) int_0^w exp(-s^2 r^2) ds             (eq. kernel)
+ * and discretised by Gauss-Legendre nodes t_k, weights w_k on [0, w]
+ * (eq. TEI2).  Each 1D factor exp(-t_k^2 (x-y)^2) on the box [-L,L]^2 is
+ * replaced by its tensor Chebyshev interpolant (eq. chebcheb), kept here in
+ * node-value (Lagrange) form with the n x n matrices
+ *     K_k(a,b) = exp(-t_k^2 (xi_a - xi_b)^2),
+ * xi_a the Chebyshev nodes on [-L,L].  With the 1D moments of every basis pair
+ * p = (mu,nu), mu <= nu, against the Lagrange basis l_a (eq. defV),
+ *     m_{p,d}(a) = int_{-L}^{L} g_{mu,d}(x) g_{nu,d}(x) l_a(x) dx,
+ * Theorem 3.1 with eq. tensors gives
+ *     B(p,q) = (2/sqrt(pi)) sum_k w_k prod_{d=1..3} m_{p,d}^T K_k m_{q,d}.
+ * The Coulomb matrix (eqs. Coul, coulapprox; atomic-orbital form)
+ *     J(mu,nu) = sum over all ordered (k,l) of B(mu nu, k l) D(k,l)
+ * is applied through the n^3 Chebyshev-grid tensor (eq. ig1), never forming B.
+ *
+ * Conventions for every entry point
+ *   - Return value: TAI_OK (0) or a negative TAI_ERR_* code; nothing throws
+ *     across the ABI.  tai_last_error() gives a message for the last failure
+ *     on a context.
+ *   - Arguments are validated before any device work; on TAI_ERR_INVALID_ARG
+ *     and TAI_ERR_UNSUPPORTED no output is written.
+ *   - Pointers marked DEVICE are device memory owned by the caller, on the
+ *     context's device; HOST pointers are read during the call only.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *     stream-ordered and asynchronous: they return once the work is enqueued.
+ *     A device fault surfaces from a later call or from tai_sync().
+ *   - A context owns its workspace and caches; it is not thread-safe (use one
+ *     context per host thread).  Calls on one context that run concurrently
+ *     on different streams must not overlap in time, since they share the
+ *     context's workspace.
+ *   - Pair index (0-based, mu <= nu, row-major upper triangle):
+ *         p(mu,nu) = mu*nb - mu*(mu-1)/2 + (nu - mu),  npair = nb*(nb+1)/2.
+ */
+#ifndef TAI_H
+#define TAI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TAI_OK = 0,
+  TAI_ERR_INVALID_ARG = -1,   /* a bad argument; nothing was written           */
+  TAI_ERR_NOMEM = -2,         /* workspace allocation failed or over the limit
+                                 set by the environment variable
+                                 TAI_WORKSPACE_LIMIT (bytes)                   */
+  TAI_ERR_HIP = -3,           /* a HIP runtime error (launch, fault, ...)      */
+  TAI_ERR_UNSUPPORTED = -4,   /* valid but unsupported combination             */
+  TAI_ERR_NOT_READY = -5      /* context not usable (e.g. failed creation)     */
+};
+
+/* Chebyshev node family (Def. 2.2): Lobatto (second kind) is the paper's
+   choice for TA (remark closing section 5.1); Gauss is the first kind. */
+enum { TAI_NODES_LOBATTO = 0, TAI_NODES_GAUSS = 1 };
+
+/* Arithmetic of the B contraction (tai_assemble_B) and of the grid
+   projections of tai_apply_J.  Node generation, moments and the K tables are
+   FP64 in every mode; the cross-k accumulation of B is FP32 within the
+   low-precision modes and FP64 for TAI_FP64.
+     TAI_FP64   FP64 MFMA.
+     TAI_FP32   FP32 MFMA.
+     TAI_BF16X3 each operand split into 2 bfloat16 slices, 3 products
+                (hi*hi + hi*lo + lo*hi), FP32 MFMA accumulation.
+     TAI_BF16X6 3 bfloat16 slices, 6 products.
+     TAI_F16X3  2 float16 slices, 3 products; operands are scaled per
+                (pair, direction) by powers of two so the slices stay in range.
+   Low-precision modes write B as float32. */
+enum { TAI_FP64 = 0, TAI_FP32 = 1, TAI_BF16X3 = 2, TAI_BF16X6 = 3, TAI_F16X3 = 4 };
+
+/* One molecule's basis: nb functions, each ONE primitive Cartesian Gaussian
+     g_mu(x) = c_mu prod_d (x_d - A_mu,d)^{l_mu,d} exp(-alpha_mu |x - A_mu|^2)
+   (eqs. basis and primi with I_mu = 1).  HOST pointers. */
+typedef struct {
+  int32_t        nb;      /* 1 <= nb, npair = nb(nb+1)/2 <= 2^31 - 1          */
+  const double*  center;  /* [nb][3], finite                                  */
+  const double*  alpha;   /* [nb], finite and > 0                             */
+  const int32_t* lxyz;    /* [nb][3], each power in 0..4                      */
+  const double*  coef;    /* [nb] multiplier c_mu, or NULL: then c_mu makes
+                             each Cartesian factor unit-norm,
+                             prod_d [(2a/pi)^(1/2) (4a)^l / (2l-1)!!]^(1/2)   */
+} tai_basis;
+
+/* Method parameters.  omega > 0; 1 <= nq <= 128 Gauss-Legendre nodes in t;
+   2 <= n <= 64 Chebyshev nodes per direction; L > 0 the half-width of the box
+   [-L,L]^3 (the paper's b, eq. compact); nodes and prec from the enums. */
+typedef struct {
+  double  omega;
+  int32_t nq;
+  int32_t n;
+  double  L;
+  int32_t nodes;
+  int32_t prec;
+} tai_params;
+
+/* ---- context ------------------------------------------------------------ */
+
+typedef struct tai_ctx tai_ctx;   /* opaque */
+
+/* Create a context on HIP device `hip_device` (>= 0).  hip_device == -1
+   makes a host-only context: every entry point validates its arguments and
+   then returns TAI_ERR_NOT_READY instead of touching a device (used to check
+   argument handling on machines without a GPU).  *ctx is set to NULL on
+   error; TAI_ERR_HIP if the device does not exist. */
+int tai_create(tai_ctx** ctx, int hip_device);
+
+/* Free the context's workspace and caches.  NULL is accepted. */
+int tai_destroy(tai_ctx* ctx);
+
+/* Static description of a status code; never NULL. */
+const char* tai_status_string(int status);
+
+/* Message of the last failure on ctx (empty string if none); never NULL.
+   The string stays valid until the next call on ctx. */
+const char* tai_last_error(const tai_ctx* ctx);
+
+/* Wait for `stream` and report any pending device error as TAI_ERR_HIP. */
+int tai_sync(tai_ctx* ctx, void* stream);
+
+/* ---- hot path ----------------------------------------------------------- */
+
+/* Quadrature nodes and interpolation tables, computed on the device in FP64.
+   t[k], w[k] (k < nq): Gauss-Legendre nodes/weights of int_0^omega (eq. TEI2,
+   Prop. 2.4); xi[a] (a < n): Chebyshev nodes on [-L,L] (Def. 2.2);
+   K[k][a][b] = exp(-t_k^2 (xi_a - xi_b)^2) (eq. chebcheb, node form).
+   All DEVICE double; any of the four pointers may be NULL to skip it. */
+int tai_quadrature(tai_ctx* ctx, const tai_params* params,
+                   double* t, double* w, double* xi, double* K, void* stream);
+
+/* 1D moments (eq. defV, Lagrange basis), FP64 on the device:
+     M[d][a][p] = int_{-L}^{L} g_{mu,d}(x) g_{nu,d}(x) l_a(x) dx
+   for d < 3, a < n, p < npair.  M is DEVICE double [3][n][npair].  With
+   coef == NULL the unit-norm constants are applied per direction; with coef
+   the factor c_mu c_nu goes into the d = 0 moments.  params->prec is ignored. */
+int tai_moments(tai_ctx* ctx, const tai_basis* basis, const tai_params* params,
+                double* M, void* stream);
+
+/* The full pair matrix (Theorem 3.1, Algorithm 1 for all pairs):
+     B[p*ldb + q] = (2/sqrt(pi)) sum_k w_k prod_d (M_d^T K_k M_d)(p,q)
+   for p, q < npair, written for both triangles (B is symmetric; each tile
+   p-block <= q-block is computed once and stored with its mirror).
+   M: DEVICE double [3][n][npair] (as from tai_moments).  B: DEVICE, row-major
+   npair x ldb (ldb >= npair), double if params->prec == TAI_FP64 else float.
+   Columns npair..ldb-1 are not touched. */
+int tai_assemble_B(tai_ctx* ctx, const double* M, int32_t npair, const tai_params* params,
+                   void* B, int64_t ldb, void* stream);
+
+/* One molecule of a batch: its own basis (HOST), parameters, moment buffer M
+   (DEVICE double [3][n][npair], written by the call) and output B (DEVICE,
+   as in tai_assemble_B).  All molecules of one batch must share nq, n, nodes
+   and prec; omega and L may differ. */
+typedef struct {
+  tai_basis  basis;
+  tai_params params;
+  double*    M;
+  void*      B;
+  int64_t    ldb;
+} tai_mol;
+
+/* Moments and B for every molecule of a batch: per-molecule node, moment and
+   operand kernels, then ONE persistent assembly launch whose work groups
+   drain a queue of (molecule, tile) items.  With a non-NULL stream the
+   kernel sequence is recorded once into a HIP graph and replayed while the
+   batch description (sizes, parameters, M/B pointers) is unchanged; the
+   bases themselves are uploaded on every call.  Setting the environment
+   variable TAI_NO_GRAPH launches the kernels directly.  Results equal those
+   of tai_moments + tai_assemble_B per molecule. */
+int tai_assemble_B_batched(tai_ctx* ctx, int32_t nmol, const tai_mol* mols, void* stream);
+
+/* Coulomb matrix through the grid tensor, B never formed (eq. coulapprox with
+   the mode products of eq. ig1):
+     Dt_q   = D(k,l) (2 - delta_kl),  q = (k,l), k <= l
+     rho(a) = sum_q Dt_q prod_d m_{q,d}(a_d)                 (a in [n]^3)
+     Phi    = (2/sqrt(pi)) sum_k w_k rho x_1 K_k x_2 K_k x_3 K_k
+     J(mu,nu) = J(nu,mu) = sum_a prod_d m_{p,d}(a_d) Phi(a),  p = (mu,nu)
+   which equals sum over all ordered (k,l) of B(mu nu, k l) D(k,l) for a
+   symmetric D.  M: DEVICE double [3][n][npair]; D: DEVICE double [nb][nb],
+   only its upper triangle is read; J: DEVICE double [nb][nb], fully written.
+   All arithmetic is FP64; params->prec must be TAI_FP64 (other modes return
+   TAI_ERR_UNSUPPORTED). */
+int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* params,
+                const double* D, double* J, void* stream);
+
+/* ---- timing ------------------------------------------------------------- */
+
+/* Per-stage device timing.  While enabled, every call brackets each stage it
+   enqueues with HIP events recorded on the call's stream (outside graph
+   capture).  Stages: "nodes", "moments", "pack", "project", "assemble",
+   "apply_J", "batched" (a whole tai_assemble_B_batched launch or graph
+   replay).  tai_profile_enable clears the totals (enable = 0 turns timing
+   off); tai_profile_read waits for the recorded events and returns the total
+   milliseconds and the number of timed launches of one stage. */
+int tai_profile_enable(tai_ctx* ctx, int enable);
+int tai_profile_read(tai_ctx* ctx, const char* stage, double* total_ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TAI_H */

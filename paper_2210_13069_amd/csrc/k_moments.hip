@@ -1,0 +1,122 @@
+// 1D moments of basis pairs against the Lagrange basis on the Chebyshev
+// nodes (eq. defV in node form), FP64:
+//
+//   M[d][a][p] = int_{-L}^{L} g_{mu,d}(x) g_{nu,d}(x) l_a(x) dx.
+//
+// By the Gaussian product rule (Prop. 2.1, eq. gauss_prod) the integrand is
+//   N N' (x-A)^l (x-B)^l' E exp(-p (x-P)^2),  p = a+b, P = (aA+bB)/p,
+//   E = exp(-ab/p (A-B)^2).
+// One thread owns one (pair, direction).  It integrates over the box
+// intersected with P +- 9/sqrt(p) (beyond which the Gaussian is below e^-81
+// of its peak) with a fixed composite Gauss-Legendre rule, accumulating the
+// Chebyshev moments int f(x) T_k(x/L) dx by the three-term recurrence -- the
+// paper's own W matrices of eq. defV in the T_k basis -- and maps them to the
+// Lagrange basis with the fixed n x n matrix gam.  Every thread runs the same
+// instruction stream, so the wavefront never diverges.
+#include "tai_internal.h"
+#include "tai_device.h"
+
+#include <cmath>
+
+namespace tai {
+namespace {
+
+__device__ inline double norm_1d(double a, int l) {
+  // [(2a/pi)^(1/2) (4a)^l / (2l-1)!!]^(1/2)
+  double df = 1.0;
+  for (int k = 2 * l - 1; k > 0; k -= 2) df *= k;
+  double p4 = 1.0;
+  for (int k = 0; k < l; ++k) p4 *= 4.0 * a;
+  return sqrt(sqrt(2.0 * a / M_PI) * p4 / df);
+}
+
+__device__ inline double ipow(double x, int l) {
+  double r = 1.0;
+  for (int k = 0; k < l; ++k) r *= x;
+  return r;
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(128)
+moments_kernel(DevBasis bs, int n, double L, NodeTables tb, double* __restrict__ M, int64_t npair) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 3 * npair) return;
+  const int d = (int)(g / npair);
+  const int64_t p = g - d * npair;
+  int mu, nu;
+  decode_pair(bs.nb, p, mu, nu);
+
+  const double a = bs.alpha[mu], b = bs.alpha[nu];
+  const double A = bs.center[3 * mu + d], B = bs.center[3 * nu + d];
+  const int la = bs.lxyz[3 * mu + d], lb = bs.lxyz[3 * nu + d];
+  double nrm;
+  if (bs.coef) {
+    nrm = (d == 0) ? bs.coef[mu] * bs.coef[nu] : 1.0;
+  } else {
+    nrm = norm_1d(a, la) * norm_1d(b, lb);
+  }
+  const double pp = a + b;
+  const double P = (a * A + b * B) / pp;
+  const double E = exp(-a * b / pp * (A - B) * (A - B));
+  const double pref = nrm * E;
+  const double half = 9.0 / sqrt(pp);
+  const double lo = fmax(-L, P - half);
+  const double hi = fmin(L, P + half);
+  const double h = (hi > lo) ? (hi - lo) / kMomPanels : 0.0;
+  const double invL = 1.0 / L;
+
+  double mom[NMAX];
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) mom[k] = 0.0;
+
+  for (int s = 0; s < kMomPanels; ++s) {
+    const double mid = lo + (s + 0.5) * h;
+    for (int j = 0; j < kMomOrder; ++j) {
+      const double x = mid + 0.5 * h * tb.pz[j];
+      const double dxp = x - P;
+      const double f = pref * (0.5 * h * tb.pw[j]) * ipow(x - A, la) * ipow(x - B, lb) * exp(-pp * dxp * dxp);
+      const double u = x * invL;
+      double t0 = 1.0, t1 = u;
+      mom[0] += f;
+      if (NMAX > 1) mom[1] += f * u;
+#pragma unroll
+      for (int k = 2; k < NMAX; ++k) {
+        const double t2 = 2.0 * u * t1 - t0;
+        mom[k] += f * t2;
+        t0 = t1;
+        t1 = t2;
+      }
+    }
+  }
+
+  double* out = M + (int64_t)d * n * npair + p;
+  for (int ai = 0; ai < n; ++ai) {
+    const double* gr = tb.gam + ai * n;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k)
+      if (k < n) s += gr[k] * mom[k];
+    out[(int64_t)ai * npair] = s;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_moments(const DevBasis& b, int n, double L, const NodeTables& tb,
+                          double* M, hipStream_t s) {
+  const int64_t npair = (int64_t)b.nb * (b.nb + 1) / 2;
+  const int64_t total = 3 * npair;
+  const int threads = 128;
+  const unsigned blocks = (unsigned)((total + threads - 1) / threads);
+  if (n <= 16)
+    hipLaunchKernelGGL(moments_kernel<16>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair);
+  else if (n <= 32)
+    hipLaunchKernelGGL(moments_kernel<32>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair);
+  else if (n <= 48)
+    hipLaunchKernelGGL(moments_kernel<48>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair);
+  else
+    hipLaunchKernelGGL(moments_kernel<64>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair);
+  return hipGetLastError();
+}
+
+}  // namespace tai

@@ -1,0 +1,141 @@
+// Quadrature and interpolation tables on the device, FP64.
+//
+// * Gauss-Legendre nodes/weights for int_0^omega ds (eq. TEI2 with the
+//   Gauss rule of Prop. 2.4), by Newton's method on the Legendre polynomial.
+// * Chebyshev nodes on [-L, L], Lobatto or first kind (Def. 2.2).
+// * K_k(a,b) = exp(-t_k^2 (xi_a - xi_b)^2): the 1D Gaussian factor of
+//   eq. TEI2 on the Chebyshev grid, i.e. the node-value form of the
+//   interpolant of eq. chebcheb.
+// * The map from Chebyshev moments to Lagrange moments used by the moment
+//   kernel: l_a(x) = sum_k gam[a][k] T_k(x/L).
+// * The composite Gauss-Legendre panel rule of the moment kernel.
+#include "tai_internal.h"
+
+#include <cmath>
+
+namespace tai {
+namespace {
+
+constexpr int kNodeThreads = 256;
+constexpr int kPanelBase = 128;  // threads [128, 128 + kMomOrder) build the panel rule
+constexpr int kXiBase = 160;     // threads [160, 160 + n) build the Chebyshev nodes
+
+// Legendre P_m and P_{m-1} at x by the three-term recurrence.
+__device__ inline void legendre_pair(int m, double x, double& pm, double& pm1) {
+  double p0 = 1.0, p1 = x;
+  for (int j = 1; j < m; ++j) {
+    const double p2 = ((2.0 * j + 1.0) * x * p1 - j * p0) / (j + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  pm = p1;
+  pm1 = p0;
+}
+
+// Root `i` (0-based, descending) of P_m and its Gauss weight.
+__device__ inline void gauss_root(int m, int i, double& x, double& wt) {
+  x = cos(M_PI * (i + 0.75) / (m + 0.5));
+  for (int it = 0; it < 100; ++it) {
+    double pm, pm1;
+    legendre_pair(m, x, pm, pm1);
+    const double dp = m * (x * pm - pm1) / (x * x - 1.0);
+    const double dx = pm / dp;
+    x -= dx;
+    if (fabs(dx) < 1e-15) break;
+  }
+  double pm, pm1;
+  legendre_pair(m, x, pm, pm1);
+  const double dp = m * (x * pm - pm1) / (x * x - 1.0);
+  wt = 2.0 / ((1.0 - x * x) * dp * dp);
+}
+
+__global__ void __launch_bounds__(kNodeThreads)
+nodes_kernel(double omega, int nq, int n, double L, int kind, NodeTables tb) {
+  const int tid = threadIdx.x;
+  if (tid < nq) {
+    double z, zw;
+    gauss_root(nq, tid, z, zw);
+    const int k = nq - 1 - tid;  // ascending order
+    tb.t[k] = 0.5 * omega * (1.0 + z);
+    tb.w[k] = 0.5 * omega * zw;
+  } else if (tid >= kPanelBase && tid < kPanelBase + kMomOrder) {
+    const int i = tid - kPanelBase;
+    double z, zw;
+    gauss_root(kMomOrder, i, z, zw);
+    tb.pz[kMomOrder - 1 - i] = z;
+    tb.pw[kMomOrder - 1 - i] = zw;
+  } else if (tid >= kXiBase && tid < kXiBase + n) {
+    const int a = tid - kXiBase;
+    const double th = (kind == 0) ? M_PI * a / (n - 1) : (2.0 * a + 1.0) * M_PI / (2.0 * n);
+    tb.xi[a] = L * cos(th);
+  }
+}
+
+// K tables (nq*n*n entries) followed by the n*n Chebyshev-to-Lagrange map.
+__global__ void __launch_bounds__(256)
+ktables_kernel(int nq, int n, int kind, NodeTables tb) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nk = (int64_t)nq * n * n;
+  if (g < nk) {
+    const int k = (int)(g / ((int64_t)n * n));
+    const int ab = (int)(g % ((int64_t)n * n));
+    const int a = ab / n, b = ab % n;
+    const double dx = tb.xi[a] - tb.xi[b];
+    const double t = tb.t[k];
+    tb.K[g] = exp(-t * t * dx * dx);
+  } else if (g < nk + (int64_t)n * n) {
+    const int ak = (int)(g - nk);
+    const int a = ak / n, k = ak % n;
+    double v;
+    if (kind == 0) {
+      // Lobatto: l_a(u) = sum_k 2/(N c_a c_k) T_k(u_a) T_k(u), N = n-1,
+      // c_0 = c_N = 2, other c = 1; T_k(u_a) = cos(pi a k / N)
+      const int N = n - 1;
+      const double ca = (a == 0 || a == N) ? 2.0 : 1.0;
+      const double ck = (k == 0 || k == N) ? 2.0 : 1.0;
+      v = 2.0 / (N * ca * ck) * cos(M_PI * (double)((int64_t)a * k % (2 * N)) / N);
+    } else {
+      // first kind: l_a(u) = sum_k (2 - delta_k0)/n T_k(u_a) T_k(u),
+      // T_k(u_a) = cos(k (2a+1) pi / (2n))
+      const double ck = (k == 0) ? 1.0 : 2.0;
+      v = ck / n * cos(M_PI * (double)((int64_t)k * (2 * a + 1) % (4 * n)) / (2.0 * n));
+    }
+    tb.gam[ak] = v;
+  }
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+size_t node_tables_bytes(int nq, int n) {
+  return align256(sizeof(double) * nq) * 2 + align256(sizeof(double) * n) +
+         align256(sizeof(double) * (size_t)nq * n * n) + align256(sizeof(double) * n * n) +
+         align256(sizeof(double) * kMomOrder) * 2;
+}
+
+NodeTables carve_node_tables(void* base, int nq, int n) {
+  char* p = static_cast<char*>(base);
+  NodeTables tb;
+  tb.t = reinterpret_cast<double*>(p); p += align256(sizeof(double) * nq);
+  tb.w = reinterpret_cast<double*>(p); p += align256(sizeof(double) * nq);
+  tb.xi = reinterpret_cast<double*>(p); p += align256(sizeof(double) * n);
+  tb.K = reinterpret_cast<double*>(p); p += align256(sizeof(double) * (size_t)nq * n * n);
+  tb.gam = reinterpret_cast<double*>(p); p += align256(sizeof(double) * n * n);
+  tb.pz = reinterpret_cast<double*>(p); p += align256(sizeof(double) * kMomOrder);
+  tb.pw = reinterpret_cast<double*>(p);
+  return tb;
+}
+
+hipError_t launch_nodes(double omega, int nq, int n, double L, int kind,
+                        const NodeTables& tb, hipStream_t s) {
+  hipLaunchKernelGGL(nodes_kernel, dim3(1), dim3(kNodeThreads), 0, s, omega, nq, n, L, kind, tb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)nq * n * n + (int64_t)n * n;
+  const int blocks = (int)((total + 255) / 256);
+  hipLaunchKernelGGL(ktables_kernel, dim3(blocks), dim3(256), 0, s, nq, n, kind, tb);
+  return hipGetLastError();
+}
+
+}  // namespace tai

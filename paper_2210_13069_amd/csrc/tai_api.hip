@@ -1,0 +1,654 @@
+// Host layer of libtai: the C ABI of include/tai.h.  Validates arguments
+// before any device work, owns the context's workspace, and enqueues the
+// kernels of the hot path on the caller's stream.
+#include "tai_internal.h"
+#include "../../include/tai.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+using tai::NodeTables;
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct tai_ctx {
+  int device = -1;        // -1: host-only context (validation only)
+  std::string err;
+  size_t limit = 0;       // workspace limit in bytes (0 = none)
+  size_t total = 0;       // bytes currently allocated
+  Buf nodes;              // NodeTables for single-molecule calls
+  Buf basis;              // device copy of a basis
+  Buf host_basis;         // pinned staging of a basis
+  hipEvent_t host_basis_done = nullptr;
+  Buf opA, opEx, opY;     // assembly operands
+  Buf jwork;              // apply_J intermediates
+  // batched path
+  Buf b_nodes, b_basis, b_opA, b_opEx, b_opY, b_mols, b_counter;
+  Buf b_host;             // pinned staging of all bases of a batch
+  hipEvent_t b_host_done = nullptr;
+  hipGraphExec_t graph = nullptr;
+  std::vector<unsigned char> graph_key;
+  // per-stage device timing (tai_profile_enable / tai_profile_read)
+  bool prof_on = false;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> prof_pending;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[8] = {0};
+  int64_t prof_n[8] = {0};
+};
+
+namespace {
+
+int fail(tai_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(tai_ctx* c, hipError_t e, const char* where) {
+  return fail(c, TAI_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+int validate_params(tai_ctx* c, const tai_params* p) {
+  if (!p) return fail(c, TAI_ERR_INVALID_ARG, "params is NULL");
+  if (!finite(p->omega) || !(p->omega > 0)) return fail(c, TAI_ERR_INVALID_ARG, "omega must be finite and > 0");
+  if (p->nq < 1 || p->nq > 128) return fail(c, TAI_ERR_INVALID_ARG, "nq must be in [1, 128]");
+  if (p->n < 2 || p->n > 64) return fail(c, TAI_ERR_INVALID_ARG, "n must be in [2, 64]");
+  if (!finite(p->L) || !(p->L > 0)) return fail(c, TAI_ERR_INVALID_ARG, "L must be finite and > 0");
+  if (p->nodes != TAI_NODES_LOBATTO && p->nodes != TAI_NODES_GAUSS)
+    return fail(c, TAI_ERR_INVALID_ARG, "nodes must be TAI_NODES_LOBATTO or TAI_NODES_GAUSS");
+  if (p->prec < TAI_FP64 || p->prec > TAI_F16X3) return fail(c, TAI_ERR_INVALID_ARG, "unknown prec");
+  return TAI_OK;
+}
+
+int validate_basis(tai_ctx* c, const tai_basis* b) {
+  if (!b) return fail(c, TAI_ERR_INVALID_ARG, "basis is NULL");
+  if (b->nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
+  const int64_t npair = (int64_t)b->nb * (b->nb + 1) / 2;
+  if (npair > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
+  if (!b->center || !b->alpha || !b->lxyz) return fail(c, TAI_ERR_INVALID_ARG, "basis center/alpha/lxyz is NULL");
+  for (int i = 0; i < b->nb; ++i) {
+    if (!finite(b->alpha[i]) || !(b->alpha[i] > 0))
+      return fail(c, TAI_ERR_INVALID_ARG, "alpha[" + std::to_string(i) + "] must be finite and > 0");
+    for (int d = 0; d < 3; ++d) {
+      if (!finite(b->center[3 * i + d]))
+        return fail(c, TAI_ERR_INVALID_ARG, "center[" + std::to_string(i) + "] is not finite");
+      const int l = b->lxyz[3 * i + d];
+      if (l < 0 || l > 4) return fail(c, TAI_ERR_INVALID_ARG, "lxyz[" + std::to_string(i) + "] out of [0, 4]");
+    }
+    if (b->coef && !finite(b->coef[i]))
+      return fail(c, TAI_ERR_INVALID_ARG, "coef[" + std::to_string(i) + "] is not finite");
+  }
+  return TAI_OK;
+}
+
+int check_ctx(tai_ctx* c) {
+  if (!c) return TAI_ERR_INVALID_ARG;
+  c->err.clear();
+  return TAI_OK;
+}
+
+int need_device(tai_ctx* c) {
+  if (c->device < 0) return fail(c, TAI_ERR_NOT_READY, "host-only context: no device work possible");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  return TAI_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+const char* const kStageNames[] = {"nodes", "moments", "pack", "project", "assemble", "apply_J", "batched"};
+constexpr int kNumStages = 7;
+enum { kStNodes = 0, kStMoments, kStPack, kStProject, kStAssemble, kStApplyJ, kStBatched };
+
+hipEvent_t take_event(tai_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one stage's launches with timing events on the stream it runs on.
+struct Timed {
+  tai_ctx* c;
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Timed(tai_ctx* c_, int st, hipStream_t s_) : c(c_), stage(st), s(s_) {
+    if (c->prof_on && (a = take_event(c)) && hipEventRecord(a, s) != hipSuccess) {
+      c->ev_pool.push_back(a);
+      a = nullptr;
+    }
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (b && hipEventRecord(b, s) == hipSuccess) {
+      c->prof_pending.push_back({stage, a, b});
+    } else {
+      c->ev_pool.push_back(a);
+      if (b) c->ev_pool.push_back(b);
+    }
+  }
+};
+
+
+// Grow a device buffer to at least `bytes`.
+int ensure(tai_ctx* c, Buf& b, size_t bytes) {
+  bytes = align256(bytes ? bytes : 256);
+  if (b.cap >= bytes) return TAI_OK;
+  if (c->limit && c->total - b.cap + bytes > c->limit)
+    return fail(c, TAI_ERR_NOMEM, "workspace of " + std::to_string(c->total - b.cap + bytes) +
+                                      " bytes exceeds TAI_WORKSPACE_LIMIT");
+  if (b.p) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+    hipFree(b.p);
+    c->total -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, TAI_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.cap = bytes;
+  c->total += bytes;
+  return TAI_OK;
+}
+
+// Grow a pinned host buffer; waits for the copy that last read it.
+int ensure_host(tai_ctx* c, Buf& b, hipEvent_t& done, size_t bytes) {
+  if (done) {
+    hipError_t e = hipEventSynchronize(done);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+  } else {
+    hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+  }
+  bytes = align256(bytes ? bytes : 256);
+  if (b.cap >= bytes) return TAI_OK;
+  if (b.p) hipHostFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  hipError_t e = hipHostMalloc(&b.p, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, TAI_ERR_NOMEM, "hipHostMalloc failed");
+  }
+  b.cap = bytes;
+  return TAI_OK;
+}
+
+void free_buf(tai_ctx* c, Buf& b) {
+  if (b.p) hipFree(b.p);
+  c->total -= b.cap;
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+int64_t npair_of(int nb) { return (int64_t)nb * (nb + 1) / 2; }
+
+// Serialised basis: center[3nb] alpha[nb] coef[nb] (doubles), lxyz[3nb] (int32).
+size_t basis_bytes(int nb) { return align256(sizeof(double) * 5 * (size_t)nb) + align256(sizeof(int32_t) * 3 * (size_t)nb); }
+
+void pack_basis_host(const tai_basis* b, char* dst) {
+  double* dd = reinterpret_cast<double*>(dst);
+  std::memcpy(dd, b->center, sizeof(double) * 3 * b->nb);
+  std::memcpy(dd + 3 * b->nb, b->alpha, sizeof(double) * b->nb);
+  if (b->coef) std::memcpy(dd + 4 * b->nb, b->coef, sizeof(double) * b->nb);
+  else std::memset(dd + 4 * b->nb, 0, sizeof(double) * b->nb);
+  std::memcpy(dst + align256(sizeof(double) * 5 * (size_t)b->nb), b->lxyz, sizeof(int32_t) * 3 * b->nb);
+}
+
+tai::DevBasis dev_basis_view(const tai_basis* b, char* dev) {
+  tai::DevBasis d;
+  d.nb = b->nb;
+  double* dd = reinterpret_cast<double*>(dev);
+  d.center = dd;
+  d.alpha = dd + 3 * b->nb;
+  d.coef = b->coef ? dd + 4 * b->nb : nullptr;
+  d.lxyz = reinterpret_cast<const int32_t*>(dev + align256(sizeof(double) * 5 * (size_t)b->nb));
+  return d;
+}
+
+int prow_of(int prec, int64_t npair) {
+  const int t = tai::assemble_tile(prec);
+  return (int)((npair + t - 1) / t * t);
+}
+
+size_t opA_bytes(int prec, int n, int prow) {
+  return align256((size_t)3 * prow * tai::operand_kc(prec, n) * tai::operand_esize(prec));
+}
+size_t opY_bytes(int prec, int n, int nq, int prow) {
+  return align256((size_t)nq * 3 * prow * tai::operand_kc(prec, n) * tai::operand_esize(prec));
+}
+size_t opEx_bytes(int prow) { return align256(sizeof(int32_t) * 3 * (size_t)prow); }
+
+}  // namespace
+
+extern "C" {
+
+int tai_create(tai_ctx** ctx, int hip_device) {
+  if (!ctx) return TAI_ERR_INVALID_ARG;
+  *ctx = nullptr;
+  if (hip_device < -1) return TAI_ERR_INVALID_ARG;
+  tai_ctx* c = new (std::nothrow) tai_ctx();
+  if (!c) return TAI_ERR_NOMEM;
+  if (const char* lim = std::getenv("TAI_WORKSPACE_LIMIT")) c->limit = (size_t)std::strtoull(lim, nullptr, 10);
+  if (hip_device >= 0) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || hip_device >= count) {
+      (void)hipGetLastError();
+      delete c;
+      return TAI_ERR_HIP;
+    }
+    c->device = hip_device;
+  }
+  *ctx = c;
+  return TAI_OK;
+}
+
+int tai_destroy(tai_ctx* c) {
+  if (!c) return TAI_OK;
+  if (c->device >= 0) {
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->jwork, &c->b_nodes, &c->b_basis,
+                   &c->b_opA, &c->b_opEx, &c->b_opY, &c->b_mols, &c->b_counter})
+      free_buf(c, *b);
+    if (c->host_basis.p) hipHostFree(c->host_basis.p);
+    if (c->b_host.p) hipHostFree(c->b_host.p);
+    if (c->host_basis_done) hipEventDestroy(c->host_basis_done);
+    if (c->b_host_done) hipEventDestroy(c->b_host_done);
+    if (c->graph) hipGraphExecDestroy(c->graph);
+    for (auto& rec : c->prof_pending) {
+      hipEventDestroy(rec.a);
+      hipEventDestroy(rec.b);
+    }
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  }
+  delete c;
+  return TAI_OK;
+}
+
+const char* tai_status_string(int status) {
+  switch (status) {
+    case TAI_OK: return "TAI_OK";
+    case TAI_ERR_INVALID_ARG: return "TAI_ERR_INVALID_ARG: invalid argument";
+    case TAI_ERR_NOMEM: return "TAI_ERR_NOMEM: workspace allocation failed or over the limit";
+    case TAI_ERR_HIP: return "TAI_ERR_HIP: HIP runtime error";
+    case TAI_ERR_UNSUPPORTED: return "TAI_ERR_UNSUPPORTED: unsupported combination";
+    case TAI_ERR_NOT_READY: return "TAI_ERR_NOT_READY: context not usable";
+    default: return "unknown tai status";
+  }
+}
+
+const char* tai_last_error(const tai_ctx* c) { return c ? c->err.c_str() : ""; }
+
+int tai_sync(tai_ctx* c, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = need_device(c))) return r;
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "pending error");
+  return TAI_OK;
+}
+
+int tai_quadrature(tai_ctx* c, const tai_params* p, double* t, double* w, double* xi, double* K, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(p->nq, p->n)))) return r;
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, p->nq, p->n);
+  hipError_t e;
+  {
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, tb, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  const size_t nq = p->nq, n = p->n;
+  if (t && (e = hipMemcpyAsync(t, tb.t, 8 * nq, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(c, e, "copy t");
+  if (w && (e = hipMemcpyAsync(w, tb.w, 8 * nq, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(c, e, "copy w");
+  if (xi && (e = hipMemcpyAsync(xi, tb.xi, 8 * n, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(c, e, "copy xi");
+  if (K && (e = hipMemcpyAsync(K, tb.K, 8 * nq * n * n, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(c, e, "copy K");
+  return TAI_OK;
+}
+
+int tai_moments(tai_ctx* c, const tai_basis* b, const tai_params* p, double* M, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_basis(c, b))) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M) return fail(c, TAI_ERR_INVALID_ARG, "M is NULL");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t bb = basis_bytes(b->nb);
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(p->nq, p->n)))) return r;
+  if ((r = ensure(c, c->basis, bb))) return r;
+  if ((r = ensure_host(c, c->host_basis, c->host_basis_done, bb))) return r;
+  pack_basis_host(b, static_cast<char*>(c->host_basis.p));
+  hipError_t e = hipMemcpyAsync(c->basis.p, c->host_basis.p, bb, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "basis upload");
+  if ((e = hipEventRecord(c->host_basis_done, s)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, p->nq, p->n);
+  {
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, tb, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  tai::DevBasis db = dev_basis_view(b, static_cast<char*>(c->basis.p));
+  {
+    Timed tm(c, kStMoments, s);
+    e = tai::launch_moments(db, p->n, p->L, tb, M, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "moments kernel");
+  return TAI_OK;
+}
+
+int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params* p, void* B, int64_t ldb,
+                   void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !B) return fail(c, TAI_ERR_INVALID_ARG, "M or B is NULL");
+  if (npair < 1) return fail(c, TAI_ERR_INVALID_ARG, "npair must be >= 1");
+  if (ldb < npair) return fail(c, TAI_ERR_INVALID_ARG, "ldb must be >= npair");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int prec = p->prec, n = p->n, nq = p->nq;
+  const int prow = prow_of(prec, npair);
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
+  if ((r = ensure(c, c->opA, opA_bytes(prec, n, prow)))) return r;
+  if ((r = ensure(c, c->opEx, opEx_bytes(prow)))) return r;
+  if ((r = ensure(c, c->opY, opY_bytes(prec, n, nq, prow)))) return r;
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
+  hipError_t e;
+  {
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, tb, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  int32_t* ex = static_cast<int32_t*>(c->opEx.p);
+  {
+    Timed tm(c, kStPack, s);
+    e = tai::launch_pack(prec, M, n, npair, prow, c->opA.p, ex, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "pack kernel");
+  {
+    Timed tm(c, kStProject, s);
+    e = tai::launch_project(prec, M, n, npair, prow, nq, tb, ex, c->opY.p, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "project kernel");
+  tai::AsmMol m;
+  m.A = c->opA.p;
+  m.Y = c->opY.p;
+  m.ex = ex;
+  m.B = B;
+  m.ldb = ldb;
+  m.npair = npair;
+  m.prow = prow;
+  m.nq = nq;
+  m.kc = tai::operand_kc(prec, n);
+  m.tiles = prow / tai::assemble_tile(prec);
+  m.tile0 = 0;
+  {
+    Timed tm(c, kStAssemble, s);
+    e = tai::launch_assemble(prec, m, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "assemble kernel");
+  return TAI_OK;
+}
+
+int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if (nmol < 1 || !mols) return fail(c, TAI_ERR_INVALID_ARG, "nmol must be >= 1 and mols non-NULL");
+  for (int i = 0; i < nmol; ++i) {
+    if ((r = validate_basis(c, &mols[i].basis))) return fail(c, r, "molecule " + std::to_string(i) + ": " + c->err);
+    if ((r = validate_params(c, &mols[i].params))) return fail(c, r, "molecule " + std::to_string(i) + ": " + c->err);
+    if (!mols[i].M || !mols[i].B) return fail(c, TAI_ERR_INVALID_ARG, "molecule " + std::to_string(i) + ": M or B is NULL");
+    if (mols[i].ldb < npair_of(mols[i].basis.nb))
+      return fail(c, TAI_ERR_INVALID_ARG, "molecule " + std::to_string(i) + ": ldb must be >= npair");
+    const tai_params& p0 = mols[0].params;
+    const tai_params& pi = mols[i].params;
+    if (pi.nq != p0.nq || pi.n != p0.n || pi.nodes != p0.nodes || pi.prec != p0.prec)
+      return fail(c, TAI_ERR_INVALID_ARG, "molecules of a batch must share nq, n, nodes and prec");
+  }
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int prec = mols[0].params.prec, n = mols[0].params.n, nq = mols[0].params.nq;
+  const int tile = tai::assemble_tile(prec);
+
+  // layout of the batch workspace
+  std::vector<size_t> off_nodes(nmol), off_basis(nmol), off_A(nmol), off_Ex(nmol), off_Y(nmol);
+  std::vector<int> prow(nmol);
+  size_t sz_nodes = 0, sz_basis = 0, sz_A = 0, sz_Ex = 0, sz_Y = 0;
+  int64_t nitems = 0;
+  std::vector<tai::AsmMol> am(nmol);
+  for (int i = 0; i < nmol; ++i) {
+    const int64_t np = npair_of(mols[i].basis.nb);
+    prow[i] = prow_of(prec, np);
+    off_nodes[i] = sz_nodes; sz_nodes += align256(tai::node_tables_bytes(nq, n));
+    off_basis[i] = sz_basis; sz_basis += basis_bytes(mols[i].basis.nb);
+    off_A[i] = sz_A; sz_A += opA_bytes(prec, n, prow[i]);
+    off_Ex[i] = sz_Ex; sz_Ex += opEx_bytes(prow[i]);
+    off_Y[i] = sz_Y; sz_Y += opY_bytes(prec, n, nq, prow[i]);
+  }
+  if ((r = ensure(c, c->b_nodes, sz_nodes))) return r;
+  if ((r = ensure(c, c->b_basis, sz_basis))) return r;
+  if ((r = ensure(c, c->b_opA, sz_A))) return r;
+  if ((r = ensure(c, c->b_opEx, sz_Ex))) return r;
+  if ((r = ensure(c, c->b_opY, sz_Y))) return r;
+  if ((r = ensure(c, c->b_mols, sizeof(tai::AsmMol) * nmol))) return r;
+  if ((r = ensure(c, c->b_counter, 256))) return r;
+  for (int i = 0; i < nmol; ++i) {
+    tai::AsmMol& m = am[i];
+    m.A = static_cast<char*>(c->b_opA.p) + off_A[i];
+    m.Y = static_cast<char*>(c->b_opY.p) + off_Y[i];
+    m.ex = reinterpret_cast<const int32_t*>(static_cast<char*>(c->b_opEx.p) + off_Ex[i]);
+    m.B = mols[i].B;
+    m.ldb = mols[i].ldb;
+    m.npair = (int32_t)npair_of(mols[i].basis.nb);
+    m.prow = prow[i];
+    m.nq = nq;
+    m.kc = tai::operand_kc(prec, n);
+    m.tiles = prow[i] / tile;
+    m.tile0 = nitems;
+    nitems += (int64_t)m.tiles * (m.tiles + 1) / 2;
+  }
+
+  // upload bases and the molecule table (outside any graph)
+  const size_t host_bytes = sz_basis + align256(sizeof(tai::AsmMol) * nmol);
+  if ((r = ensure_host(c, c->b_host, c->b_host_done, host_bytes))) return r;
+  char* hb = static_cast<char*>(c->b_host.p);
+  for (int i = 0; i < nmol; ++i) pack_basis_host(&mols[i].basis, hb + off_basis[i]);
+  std::memcpy(hb + sz_basis, am.data(), sizeof(tai::AsmMol) * nmol);
+  hipError_t e = hipMemcpyAsync(c->b_basis.p, hb, sz_basis, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->b_mols.p, hb + sz_basis, sizeof(tai::AsmMol) * nmol, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(c->b_host_done, s);
+  if (e != hipSuccess) return hip_fail(c, e, "batch upload");
+
+  // the kernel sequence; recorded into a graph when a stream is given
+  auto enqueue = [&](hipStream_t st) -> hipError_t {
+    hipError_t err = hipSuccess;
+    for (int i = 0; i < nmol && err == hipSuccess; ++i) {
+      const tai_params& pi = mols[i].params;
+      NodeTables tb = tai::carve_node_tables(static_cast<char*>(c->b_nodes.p) + off_nodes[i], nq, n);
+      err = tai::launch_nodes(pi.omega, nq, n, pi.L, pi.nodes, tb, st);
+      if (err != hipSuccess) break;
+      tai::DevBasis db = dev_basis_view(&mols[i].basis, static_cast<char*>(c->b_basis.p) + off_basis[i]);
+      err = tai::launch_moments(db, n, pi.L, tb, mols[i].M, st);
+      if (err != hipSuccess) break;
+      int32_t* ex = const_cast<int32_t*>(am[i].ex);
+      err = tai::launch_pack(prec, mols[i].M, n, am[i].npair, prow[i], const_cast<void*>(am[i].A), ex, st);
+      if (err != hipSuccess) break;
+      err = tai::launch_project(prec, mols[i].M, n, am[i].npair, prow[i], nq, tb, ex, const_cast<void*>(am[i].Y), st);
+    }
+    if (err != hipSuccess) return err;
+    unsigned* counter = static_cast<unsigned*>(c->b_counter.p);
+    err = tai::launch_reset_counter(counter, st);
+    if (err != hipSuccess) return err;
+    int blocks = tai::assemble_queue_blocks(prec, c->device);
+    if (blocks > nitems) blocks = (int)nitems;
+    return tai::launch_assemble_queue(prec, static_cast<const tai::AsmMol*>(c->b_mols.p), nmol, nitems, counter,
+                                      blocks, st);
+  };
+
+  const bool use_graph = s != nullptr && !std::getenv("TAI_NO_GRAPH");
+  if (!use_graph) {
+    {
+      Timed tm(c, kStBatched, s);
+      e = enqueue(s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "batched launch");
+    return TAI_OK;
+  }
+  // graph key: everything the recorded kernels capture by value
+  std::vector<unsigned char> key;
+  auto put = [&key](const void* v, size_t nbytes) {
+    const unsigned char* b = static_cast<const unsigned char*>(v);
+    key.insert(key.end(), b, b + nbytes);
+  };
+  put(&nmol, sizeof nmol);
+  for (int i = 0; i < nmol; ++i) {
+    put(&mols[i].params, sizeof(tai_params));
+    put(&mols[i].basis.nb, sizeof(int32_t));
+    const int has_coef = mols[i].basis.coef != nullptr;
+    put(&has_coef, sizeof has_coef);
+    put(&mols[i].M, sizeof(void*));
+    put(&mols[i].B, sizeof(void*));
+    put(&mols[i].ldb, sizeof(int64_t));
+  }
+  void* bases[] = {c->b_nodes.p, c->b_basis.p, c->b_opA.p, c->b_opEx.p, c->b_opY.p, c->b_mols.p, c->b_counter.p};
+  put(bases, sizeof bases);
+  if (!c->graph || key != c->graph_key) {
+    if (c->graph) {
+      hipGraphExecDestroy(c->graph);
+      c->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(c, e, "begin capture");
+    hipError_t le = enqueue(s);
+    e = hipStreamEndCapture(s, &g);
+    if (le != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return hip_fail(c, le, "batched capture");
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "end capture");
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->graph = nullptr;
+      return hip_fail(c, e, "graph instantiate");
+    }
+    c->graph_key = key;
+  }
+  {
+    Timed tm(c, kStBatched, s);
+    e = hipGraphLaunch(c->graph, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+  return TAI_OK;
+}
+
+int tai_apply_J(tai_ctx* c, const double* M, int32_t nb, const tai_params* p, const double* D, double* J,
+                void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !D || !J) return fail(c, TAI_ERR_INVALID_ARG, "M, D or J is NULL");
+  if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
+  const int64_t npair = npair_of(nb);
+  if (npair > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
+  if (p->prec != TAI_FP64) return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J supports prec TAI_FP64");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = p->n, nq = p->nq;
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
+  if ((r = ensure(c, c->jwork, tai::j_work_bytes(nq, n, (int)npair)))) return r;
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
+  hipError_t e;
+  {
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, tb, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  tai::JWork w = tai::carve_j_work(c->jwork.p, nq, n, (int)npair);
+  {
+    Timed tm(c, kStApplyJ, s);
+    e = tai::launch_apply_j(M, nb, (int)npair, n, nq, tb, D, J, w, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "apply_J kernels");
+  return TAI_OK;
+}
+
+int tai_profile_enable(tai_ctx* c, int enable) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = need_device(c))) return r;
+  for (auto& rec : c->prof_pending) {
+    hipEventSynchronize(rec.b);
+    c->ev_pool.push_back(rec.a);
+    c->ev_pool.push_back(rec.b);
+  }
+  c->prof_pending.clear();
+  for (int i = 0; i < kNumStages; ++i) {
+    c->prof_ms[i] = 0.0;
+    c->prof_n[i] = 0;
+  }
+  c->prof_on = enable != 0;
+  return TAI_OK;
+}
+
+int tai_profile_read(tai_ctx* c, const char* stage, double* total_ms, int64_t* count) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!stage || !total_ms || !count) return fail(c, TAI_ERR_INVALID_ARG, "stage, total_ms or count is NULL");
+  int st = -1;
+  for (int i = 0; i < kNumStages; ++i)
+    if (std::strcmp(stage, kStageNames[i]) == 0) st = i;
+  if (st < 0) return fail(c, TAI_ERR_INVALID_ARG, std::string("unknown stage ") + stage);
+  if ((r = need_device(c))) return r;
+  for (auto& rec : c->prof_pending) {
+    hipError_t e = hipEventSynchronize(rec.b);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, rec.a, rec.b);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+    c->prof_ms[rec.stage] += ms;
+    c->prof_n[rec.stage] += 1;
+    c->ev_pool.push_back(rec.a);
+    c->ev_pool.push_back(rec.b);
+  }
+  c->prof_pending.clear();
+  *total_ms = c->prof_ms[st];
+  *count = c->prof_n[st];
+  return TAI_OK;
+}
+
+}  // extern "C"

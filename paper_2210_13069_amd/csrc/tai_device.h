@@ -1,0 +1,25 @@
+// Device helpers shared by the kernel files of libtai.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tai {
+
+// First pair index of row mu in the row-major upper triangle of an
+// nb x nb pair list: p(mu, nu) = mu*nb - mu(mu-1)/2 + (nu - mu).
+__device__ inline int64_t pair_row_start(int64_t nb, int64_t mu) { return mu * nb - (mu * (mu - 1)) / 2; }
+
+// Inverse of the pair index.
+__device__ inline void decode_pair(int64_t nb, int64_t p, int& mu, int& nu) {
+  const double b2 = 2.0 * nb + 1.0;
+  int64_t m = (int64_t)floor(0.5 * (b2 - sqrt(b2 * b2 - 8.0 * (double)p)));
+  if (m < 0) m = 0;
+  if (m > nb - 1) m = nb - 1;
+  while (m > 0 && pair_row_start(nb, m) > p) --m;
+  while (m + 1 < nb && pair_row_start(nb, m + 1) <= p) ++m;
+  mu = (int)m;
+  nu = (int)(m + (p - pair_row_start(nb, m)));
+}
+
+}  // namespace tai

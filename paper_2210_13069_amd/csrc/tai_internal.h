@@ -1,0 +1,105 @@
+// Internal declarations shared by the host layer and the kernel files of
+// libtai.  Not part of the public ABI (include/tai.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tai {
+
+// Composite Gauss-Legendre rule used for the 1D moments: the pair's support
+// is split into kMomPanels equal panels of kMomOrder nodes each.
+constexpr int kMomPanels = 4;
+constexpr int kMomOrder = 24;
+
+// Device-resident FP64 tables for one (omega, nq, n, L, nodes).
+struct NodeTables {
+  double* t;     // [nq]      Gauss-Legendre nodes on (0, omega)
+  double* w;     // [nq]      weights
+  double* xi;    // [n]       Chebyshev nodes on [-L, L]
+  double* K;     // [nq][n][n] exp(-t_k^2 (xi_a - xi_b)^2)
+  double* gam;   // [n][n]    Chebyshev-to-Lagrange map: l_a(x) = sum_k gam[a][k] T_k(x/L)
+  double* pz;    // [kMomOrder] panel rule nodes on [-1, 1]
+  double* pw;    // [kMomOrder] panel rule weights
+};
+
+// Bytes needed by the node tables (each array 256-byte aligned).
+size_t node_tables_bytes(int nq, int n);
+NodeTables carve_node_tables(void* base, int nq, int n);
+
+hipError_t launch_nodes(double omega, int nq, int n, double L, int kind,
+                        const NodeTables& tb, hipStream_t s);
+
+// Device copy of one molecule's basis.
+struct DevBasis {
+  int32_t nb;
+  const double* center;   // [nb][3]
+  const double* alpha;    // [nb]
+  const int32_t* lxyz;    // [nb][3]
+  const double* coef;     // [nb] or nullptr
+};
+
+hipError_t launch_moments(const DevBasis& b, int n, double L, const NodeTables& tb,
+                          double* M, hipStream_t s);
+
+// ---- assembly -------------------------------------------------------------
+
+enum Prec { kFP64 = 0, kFP32 = 1, kBF16X3 = 2, kBF16X6 = 3, kF16X3 = 4 };
+
+// Length of one operand K-vector (all slices concatenated, zero padded).
+int operand_kc(int prec, int n);
+// Bytes per operand element.
+int operand_esize(int prec);
+// Square output tile edge of the assembly kernel (rows of operands are
+// padded to a multiple of it).
+int assemble_tile(int prec);
+
+struct AsmMol {
+  // operands (device): A[d][prow][kc], Y[k][d][prow][kc]; prow = padded rows
+  const void* A;
+  const void* Y;
+  const int32_t* ex;     // [3][prow] power-of-two exponents (zeros for FP64)
+  void* B;               // output
+  int64_t ldb;
+  int32_t npair;
+  int32_t prow;          // padded row count
+  int32_t nq;
+  int32_t kc;
+  int32_t tiles;         // tiles per side
+  int64_t tile0;         // first linear work item of this molecule
+};
+
+hipError_t launch_pack(int prec, const double* M, int n, int npair, int prow,
+                       void* A, int32_t* ex, hipStream_t s);
+hipError_t launch_project(int prec, const double* M, int n, int npair, int prow, int nq,
+                          const NodeTables& tb, const int32_t* ex, void* Y, hipStream_t s);
+// Single molecule, one work group per tile.
+hipError_t launch_assemble(int prec, const AsmMol& m, hipStream_t s);
+// Persistent launch over a device work list of molecules; `counter` is a
+// device int zeroed by launch_reset_counter before each launch.
+hipError_t launch_assemble_queue(int prec, const AsmMol* mols_dev, int nmol, int64_t nitems,
+                                 unsigned* counter, int nblocks, hipStream_t s);
+hipError_t launch_reset_counter(unsigned* counter, hipStream_t s);
+int assemble_queue_blocks(int prec, int device);
+
+// ---- Coulomb matrix through the grid tensor --------------------------------
+
+struct JWork {
+  double* Dt;      // [npair]
+  double* rho_part;// [nchunk][n^3]
+  double* rho;     // [n^3]
+  double* T1;      // [nq][n^3]
+  double* T2;      // [nq][n^3]
+  double* T3;      // [nq][n^3]
+  double* Phi;     // [n^3]
+  double* Jp;      // [npair]
+  int nchunk;
+};
+int j_nchunk(int n, int npair);
+size_t j_work_bytes(int nq, int n, int npair);
+JWork carve_j_work(void* base, int nq, int n, int npair);
+hipError_t launch_apply_j(const double* M, int nb, int npair, int n, int nq,
+                          const NodeTables& tb, const double* D, double* J,
+                          const JWork& w, hipStream_t s);
+
+}  // namespace tai

@@ -1,0 +1,250 @@
+"""ctypes binding of libtai (include/tai.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch supplies device buffers and the current HIP stream.
+The binding refuses to run when the library is missing: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtai.so")
+
+TAI_OK = 0
+TAI_ERR_INVALID_ARG = -1
+TAI_ERR_NOMEM = -2
+TAI_ERR_HIP = -3
+TAI_ERR_UNSUPPORTED = -4
+TAI_ERR_NOT_READY = -5
+
+NODES_LOBATTO = 0
+NODES_GAUSS = 1
+
+FP64, FP32, BF16X3, BF16X6, F16X3 = 0, 1, 2, 3, 4
+PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3", BF16X6: "bf16x6", F16X3: "f16x3"}
+PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
+
+# exported symbols declared in include/tai.h
+SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
+           "tai_quadrature", "tai_moments", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
+           "tai_profile_enable", "tai_profile_read"]
+STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched"]
+
+
+class TaiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+class tai_basis(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int32),
+                ("center", ctypes.POINTER(ctypes.c_double)),
+                ("alpha", ctypes.POINTER(ctypes.c_double)),
+                ("lxyz", ctypes.POINTER(ctypes.c_int32)),
+                ("coef", ctypes.POINTER(ctypes.c_double))]
+
+
+class tai_params(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double),
+                ("nq", ctypes.c_int32),
+                ("n", ctypes.c_int32),
+                ("L", ctypes.c_double),
+                ("nodes", ctypes.c_int32),
+                ("prec", ctypes.c_int32)]
+
+
+class tai_mol(ctypes.Structure):
+    _fields_ = [("basis", tai_basis),
+                ("params", tai_params),
+                ("M", ctypes.c_void_p),
+                ("B", ctypes.c_void_p),
+                ("ldb", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libtai.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2210_13069_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.tai_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.tai_destroy.argtypes = [vp]
+    lib.tai_status_string.argtypes = [ctypes.c_int]
+    lib.tai_status_string.restype = ctypes.c_char_p
+    lib.tai_last_error.argtypes = [vp]
+    lib.tai_last_error.restype = ctypes.c_char_p
+    lib.tai_sync.argtypes = [vp, vp]
+    lib.tai_quadrature.argtypes = [vp, ctypes.POINTER(tai_params), vp, vp, vp, vp, vp]
+    lib.tai_moments.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.POINTER(tai_params), vp, vp]
+    lib.tai_assemble_B.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, ctypes.c_int64, vp]
+    lib.tai_assemble_B_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(tai_mol), vp]
+    lib.tai_apply_J.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, vp, vp]
+    lib.tai_profile_enable.argtypes = [vp, ctypes.c_int]
+    lib.tai_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64)]
+    for name in SYMBOLS:
+        if name not in ("tai_status_string", "tai_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_params(p, prec=None):
+    """tai_params from an object with omega, nq, n, L, nodes (and prec)."""
+    return tai_params(float(p.omega), int(p.nq), int(p.n), float(p.L), int(getattr(p, "nodes", 0)),
+                      int(prec if prec is not None else getattr(p, "prec", FP64)))
+
+
+class BasisArrays:
+    """Keeps the contiguous host arrays of a basis alive for a call."""
+
+    def __init__(self, basis, coef=None):
+        self.center = np.ascontiguousarray(basis.center, dtype=np.float64)
+        self.alpha = np.ascontiguousarray(basis.alpha, dtype=np.float64)
+        self.lxyz = np.ascontiguousarray(basis.lxyz, dtype=np.int32)
+        self.coef = None if coef is None else np.ascontiguousarray(coef, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.struct = tai_basis(int(self.alpha.shape[0]),
+                                self.center.ctypes.data_as(dp),
+                                self.alpha.ctypes.data_as(dp),
+                                self.lxyz.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                None if self.coef is None else self.coef.ctypes.data_as(dp))
+
+
+class Context:
+    """One libtai context on a HIP device (device=-1: validation only)."""
+
+    def __init__(self, device=0):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        st = self.lib.tai_create(ctypes.byref(h), int(device))
+        if st != TAI_OK:
+            raise TaiError(st, f"tai_create failed: {self.lib.tai_status_string(st).decode()}")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self.lib.tai_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st, what):
+        if st != TAI_OK:
+            raise TaiError(st, f"{what}: {self.lib.tai_status_string(st).decode()}: "
+                               f"{self.lib.tai_last_error(self.h).decode()}")
+
+    def sync(self, stream=None):
+        self.check(self.lib.tai_sync(self.h, _stream(stream)), "tai_sync")
+
+    # ---- raw entry points (device tensors in, device tensors out) ----------
+    def quadrature(self, params, t=None, w=None, xi=None, K=None, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        self.check(self.lib.tai_quadrature(self.h, ctypes.byref(p), _ptr(t), _ptr(w), _ptr(xi), _ptr(K),
+                                           _stream(stream)), "tai_quadrature")
+
+    def moments(self, basis_arrays, params, M, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        self.check(self.lib.tai_moments(self.h, ctypes.byref(basis_arrays.struct), ctypes.byref(p), _ptr(M),
+                                        _stream(stream)), "tai_moments")
+
+    def assemble_B(self, M, npair, params, B, ldb=None, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        ldb = npair if ldb is None else ldb
+        self.check(self.lib.tai_assemble_B(self.h, _ptr(M), int(npair), ctypes.byref(p), _ptr(B), int(ldb),
+                                           _stream(stream)), "tai_assemble_B")
+
+    def assemble_B_batched(self, mols, stream=None):
+        arr = (tai_mol * len(mols))(*mols)
+        self.check(self.lib.tai_assemble_B_batched(self.h, len(mols), arr, _stream(stream)),
+                   "tai_assemble_B_batched")
+
+    def profile_enable(self, enable=True):
+        self.check(self.lib.tai_profile_enable(self.h, int(bool(enable))), "tai_profile_enable")
+
+    def profile_read(self, stage):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        self.check(self.lib.tai_profile_read(self.h, stage.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
+                   "tai_profile_read")
+        return ms.value, cnt.value
+
+    def apply_J(self, M, nb, params, D, J, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        self.check(self.lib.tai_apply_J(self.h, _ptr(M), int(nb), ctypes.byref(p), _ptr(D), _ptr(J),
+                                        _stream(stream)), "tai_apply_J")
+
+
+# ---- convenience wrappers allocating torch outputs ---------------------------
+_default = {}
+
+
+def context(device=0):
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def quadrature(params, device=0):
+    import torch
+    nq, n = int(params.nq), int(params.n)
+    dev = torch.device("cuda", device)
+    t = torch.empty(nq, dtype=torch.float64, device=dev)
+    w = torch.empty(nq, dtype=torch.float64, device=dev)
+    xi = torch.empty(n, dtype=torch.float64, device=dev)
+    K = torch.empty((nq, n, n), dtype=torch.float64, device=dev)
+    context(device).quadrature(params, t, w, xi, K)
+    return t, w, xi, K
+
+
+def moments(basis, params, coef=None, device=0):
+    """M[3][n][npair] (FP64, on the device) of a basis."""
+    import torch
+    ba = BasisArrays(basis, coef)
+    npair = ba.alpha.shape[0] * (ba.alpha.shape[0] + 1) // 2
+    M = torch.empty((3, int(params.n), npair), dtype=torch.float64, device=torch.device("cuda", device))
+    context(device).moments(ba, params, M)
+    return M
+
+
+def assemble_B(M, params, prec=FP64, ldb=None, out=None, device=0):
+    """Full npair x npair B (FP64 for prec FP64, else FP32) on the device."""
+    import torch
+    npair = int(M.shape[2])
+    ldb = npair if ldb is None else ldb
+    dt = torch.float64 if prec == FP64 else torch.float32
+    B = out if out is not None else torch.empty((npair, ldb), dtype=dt, device=M.device)
+    context(device).assemble_B(M, npair, make_params(params, prec), B, ldb)
+    return B
+
+
+def apply_J(M, D, params, prec=FP64, device=0):
+    import torch
+    nb = int(D.shape[0])
+    J = torch.empty((nb, nb), dtype=torch.float64, device=M.device)
+    context(device).apply_J(M, nb, make_params(params, prec), D, J)
+    return J

@@ -1,0 +1,163 @@
+"""The C-ABI library loads, exports every entry point of include/tai.h, and
+validates arguments before any device work (host-only context, no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2210_13069_amd import tai
+from paper_2210_13069_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "tai.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tai_[a-zA-Z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(tai.LIB_PATH):
+        pytest.fail("libtai.so is not built; run `python -m paper_2210_13069_amd.build`")
+    return tai.load_library()
+
+
+@pytest.fixture()
+def hctx(lib):
+    c = tai.Context(device=-1)
+    yield c
+    c.close()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared_functions()
+    assert set(declared) == set(tai.SYMBOLS), declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for st in (0, -1, -2, -3, -4, -5, 7):
+        s = lib.tai_status_string(st)
+        assert s is not None and len(s) > 0
+
+
+def test_null_context_rejected(lib):
+    p = tai.tai_params(0.5, 8, 8, 4.0, 0, 0)
+    assert lib.tai_quadrature(None, ctypes.byref(p), None, None, None, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_sync(None, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_destroy(None) == tai.TAI_OK
+    assert lib.tai_last_error(None) == b""
+    assert lib.tai_create(None, 0) == tai.TAI_ERR_INVALID_ARG
+
+
+def _params(**kw):
+    base = dict(omega=0.5, nq=8, n=16, L=8.0, nodes=0, prec=0)
+    base.update(kw)
+    return tai.tai_params(base["omega"], base["nq"], base["n"], base["L"], base["nodes"], base["prec"])
+
+
+@pytest.mark.parametrize("bad", [dict(omega=0.0), dict(omega=-1.0), dict(omega=float("nan")),
+                                 dict(omega=float("inf")), dict(nq=0), dict(nq=129), dict(n=1),
+                                 dict(n=65), dict(L=0.0), dict(L=float("nan")), dict(nodes=2),
+                                 dict(prec=5), dict(prec=-1)])
+def test_invalid_params(hctx, bad):
+    p = _params(**bad)
+    st = hctx.lib.tai_quadrature(hctx.h, ctypes.byref(p), None, None, None, None, None)
+    assert st == tai.TAI_ERR_INVALID_ARG
+    assert len(hctx.lib.tai_last_error(hctx.h)) > 0
+
+
+def test_valid_params_host_only_not_ready(hctx):
+    p = _params()
+    assert hctx.lib.tai_quadrature(hctx.h, ctypes.byref(p), None, None, None, None, None) == tai.TAI_ERR_NOT_READY
+
+
+def _basis(**mut):
+    b, _ = I.tiny_s()
+    center = b.center.copy()
+    alpha = b.alpha.copy()
+    lxyz = b.lxyz.copy()
+    if "alpha" in mut:
+        alpha[2] = mut["alpha"]
+    if "center" in mut:
+        center[1, 2] = mut["center"]
+    if "l" in mut:
+        lxyz[0, 1] = mut["l"]
+    return I.Basis(center, alpha, lxyz)
+
+
+@pytest.mark.parametrize("mut", [dict(alpha=0.0), dict(alpha=-2.0), dict(alpha=float("nan")),
+                                 dict(center=float("inf")), dict(l=-1), dict(l=5)])
+def test_invalid_basis(hctx, mut):
+    ba = tai.BasisArrays(_basis(**mut))
+    p = _params()
+    dummy = ctypes.c_void_p(16)
+    st = hctx.lib.tai_moments(hctx.h, ctypes.byref(ba.struct), ctypes.byref(p), dummy, None)
+    assert st == tai.TAI_ERR_INVALID_ARG
+
+
+def test_invalid_coef_and_nb(hctx):
+    b = _basis()
+    coef = np.ones(b.nb)
+    coef[3] = np.nan
+    ba = tai.BasisArrays(b, coef)
+    p = _params()
+    dummy = ctypes.c_void_p(16)
+    assert hctx.lib.tai_moments(hctx.h, ctypes.byref(ba.struct), ctypes.byref(p), dummy, None) == tai.TAI_ERR_INVALID_ARG
+    ba = tai.BasisArrays(b)
+    ba.struct.nb = 0
+    assert hctx.lib.tai_moments(hctx.h, ctypes.byref(ba.struct), ctypes.byref(p), dummy, None) == tai.TAI_ERR_INVALID_ARG
+    ba.struct.nb = 70000  # npair > 2^31 - 1
+    assert hctx.lib.tai_moments(hctx.h, ctypes.byref(ba.struct), ctypes.byref(p), dummy, None) == tai.TAI_ERR_INVALID_ARG
+    ba = tai.BasisArrays(b)
+    assert hctx.lib.tai_moments(hctx.h, ctypes.byref(ba.struct), ctypes.byref(p), None, None) == tai.TAI_ERR_INVALID_ARG
+    assert hctx.lib.tai_moments(hctx.h, ctypes.byref(ba.struct), ctypes.byref(p), dummy, None) == tai.TAI_ERR_NOT_READY
+
+
+def test_assemble_argument_checks(hctx):
+    p = _params()
+    d = ctypes.c_void_p(16)
+    L = hctx.lib
+    assert L.tai_assemble_B(hctx.h, None, 36, ctypes.byref(p), d, 36, None) == tai.TAI_ERR_INVALID_ARG
+    assert L.tai_assemble_B(hctx.h, d, 36, ctypes.byref(p), None, 36, None) == tai.TAI_ERR_INVALID_ARG
+    assert L.tai_assemble_B(hctx.h, d, 0, ctypes.byref(p), d, 36, None) == tai.TAI_ERR_INVALID_ARG
+    assert L.tai_assemble_B(hctx.h, d, 36, ctypes.byref(p), d, 35, None) == tai.TAI_ERR_INVALID_ARG
+    assert L.tai_assemble_B(hctx.h, d, 36, ctypes.byref(_params(n=1)), d, 36, None) == tai.TAI_ERR_INVALID_ARG
+    assert L.tai_assemble_B(hctx.h, d, 36, ctypes.byref(p), d, 36, None) == tai.TAI_ERR_NOT_READY
+
+
+def test_apply_j_argument_checks(hctx):
+    d = ctypes.c_void_p(16)
+    L = hctx.lib
+    p = _params()
+    assert L.tai_apply_J(hctx.h, d, 0, ctypes.byref(p), d, d, None) == tai.TAI_ERR_INVALID_ARG
+    assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(p), None, d, None) == tai.TAI_ERR_INVALID_ARG
+    assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(_params(prec=1)), d, d, None) == tai.TAI_ERR_UNSUPPORTED
+    assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(p), d, d, None) == tai.TAI_ERR_NOT_READY
+
+
+def test_batched_argument_checks(hctx):
+    b1 = tai.BasisArrays(_basis())
+    mk = lambda nq, ldb: tai.tai_mol(b1.struct, _params(nq=nq), 16, 16, ldb)
+    L = hctx.lib
+    arr = (tai.tai_mol * 2)(mk(8, 36), mk(9, 36))
+    assert L.tai_assemble_B_batched(hctx.h, 2, arr, None) == tai.TAI_ERR_INVALID_ARG  # nq differs
+    arr = (tai.tai_mol * 2)(mk(8, 36), mk(8, 10))
+    assert L.tai_assemble_B_batched(hctx.h, 2, arr, None) == tai.TAI_ERR_INVALID_ARG  # ldb < npair
+    assert L.tai_assemble_B_batched(hctx.h, 0, arr, None) == tai.TAI_ERR_INVALID_ARG
+    arr = (tai.tai_mol * 2)(mk(8, 36), mk(8, 36))
+    assert L.tai_assemble_B_batched(hctx.h, 2, arr, None) == tai.TAI_ERR_NOT_READY
+
+
+def test_device_context_without_gpu_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    h = ctypes.c_void_p()
+    assert lib.tai_create(ctypes.byref(h), 0) == tai.TAI_ERR_HIP
+    assert not h.value
