@@ -39,11 +39,6 @@ constexpr double kTwoOverSqrtPi = 1.1283791670955126;  // 2/sqrt(pi)
 // ---------------------------------------------------------------------------
 // operand formats
 // ---------------------------------------------------------------------------
-__device__ inline int scale_exponent(double mx) {
-  if (!(mx > 0.0)) return 0;
-  int e = ilogb(mx) + 1;  // mx * 2^-e in [0.5, 1)
-  return e < -100 ? -100 : (e > 100 ? 100 : e);
-}
 
 template <typename T>
 __device__ inline T to_slice(double x);
@@ -52,122 +47,96 @@ __device__ inline __bf16 to_slice<__bf16>(double x) { return (__bf16)(float)x; }
 template <>
 __device__ inline _Float16 to_slice<_Float16>(double x) { return (_Float16)(float)x; }
 
-// Write element a of an operand row (all its slice segments); pad writes
-// the zero tail [nseg*n, kc).
-__device__ inline void write_elem(int prec, int side, double x, int n, int a, void* rowp) {
+// Operand rows are staged through LDS so that the global writes coalesce: a
+// work group of kRowsPerTile threads builds that many consecutive rows (one
+// per thread) in an LDS tile whose row stride is an odd number of 32-bit
+// words (per-thread element writes hit distinct banks), then copies the tile
+// out word by word.
+constexpr int kRowsPerTile = 64;
+
+__device__ inline int tile_stride_words(int prec, int kc) {
+  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
+  return kc * es / 4 + 1;
+}
+
+template <typename T>
+__device__ inline void put16(uint32_t* row, int x, T v) {
+  reinterpret_cast<T*>(row)[x] = v;
+}
+
+// Write element a (all its slice segments) of an operand row held in LDS.
+// side 0 = A layout, side 1 = Y layout.
+__device__ inline void tile_elem(int prec, int side, double x, int n, int a, uint32_t* row) {
   if (prec == kFP64) {
-    static_cast<double*>(rowp)[a] = x;
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    row[2 * a] = (uint32_t)u;
+    row[2 * a + 1] = (uint32_t)(u >> 32);
   } else if (prec == kFP32) {
-    static_cast<float*>(rowp)[a] = (float)x;
+    row[a] = __float_as_uint((float)x);
   } else if (prec == kF16X3) {
-    _Float16* r = static_cast<_Float16*>(rowp);
+    // A = [h0 | h0 | h1], Y = [h0 | h1 | h0]
     const _Float16 h0 = to_slice<_Float16>(x);
     const _Float16 h1 = to_slice<_Float16>(x - (double)h0);
-    r[a] = h0;
-    r[n + a] = side ? h1 : h0;
-    r[2 * n + a] = side ? h0 : h1;
+    put16(row, seg_pos(prec, n, 0, a), h0);
+    put16(row, seg_pos(prec, n, 1, a), side ? h1 : h0);
+    put16(row, seg_pos(prec, n, 2, a), side ? h0 : h1);
   } else {
-    __bf16* r = static_cast<__bf16*>(rowp);
+    // BF16X3: A = [s0 | s0 | s1], Y = [s0 | s1 | s0]
+    // BF16X6: A = [s0|s0|s1|s0|s1|s2], Y = [s0|s1|s0|s2|s1|s0]
     const __bf16 s0 = to_slice<__bf16>(x);
     const double r1 = x - (double)(float)s0;
     const __bf16 s1 = to_slice<__bf16>(r1);
-    r[a] = s0;
-    r[n + a] = side ? s1 : s0;
-    r[2 * n + a] = side ? s0 : s1;
+    put16(row, seg_pos(prec, n, 0, a), s0);
+    put16(row, seg_pos(prec, n, 1, a), side ? s1 : s0);
+    put16(row, seg_pos(prec, n, 2, a), side ? s0 : s1);
     if (prec == kBF16X6) {
       const __bf16 s2 = to_slice<__bf16>(r1 - (double)(float)s1);
-      r[3 * n + a] = side ? s2 : s0;
-      r[4 * n + a] = s1;
-      r[5 * n + a] = side ? s0 : s2;
+      put16(row, 3 * n + a, side ? s2 : s0);
+      put16(row, 4 * n + a, s1);
+      put16(row, 5 * n + a, side ? s0 : s2);
     }
   }
 }
 
-__device__ inline void write_pad(int prec, int n, int kc, void* rowp) {
-  const int nseg = prec == kFP64 || prec == kFP32 ? 1 : (prec == kBF16X6 ? 6 : 3);
-  for (int c = nseg * n; c < kc; ++c) {
-    if (prec == kFP64) static_cast<double*>(rowp)[c] = 0.0;
-    else if (prec == kFP32) static_cast<float*>(rowp)[c] = 0.0f;
-    else if (prec == kF16X3) static_cast<_Float16*>(rowp)[c] = (_Float16)0.0f;
-    else static_cast<__bf16*>(rowp)[c] = (__bf16)0.0f;
+// Zero the padding [nseg*n, kc) of a row held in LDS.
+__device__ inline void tile_pad(int prec, int n, int kc, uint32_t* row) {
+  if (prec == kFP64 || prec == kFP32) {
+    const int w = prec == kFP64 ? 2 : 1;
+    for (int x = n * w; x < kc * w; ++x) row[x] = 0u;
+  } else {
+    const int nseg = prec == kBF16X6 ? 6 : 3;
+    for (int x = nseg * n; x < kc; ++x) put16<unsigned short>(row, x, 0);
   }
 }
 
-// Write one operand row from the n FP64 values v (already scaled).
-// side 0 = A layout, side 1 = Y layout.  v is indexed only at compile-time
-// positions so it stays in registers.
+// Copy the LDS tile of kRowsPerTile rows to dst (rows contiguous, kc elements each).
+__device__ inline void tile_store(int prec, int kc, const uint32_t* tile, int stride_w, uint32_t* __restrict__ dst) {
+  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
+  const int wpr = kc * es / 4;
+  const int total = kRowsPerTile * wpr;
+  for (int w = threadIdx.x; w < total; w += blockDim.x) {
+    const int r = w / wpr, j = w - r * wpr;
+    dst[w] = tile[r * stride_w + j];
+  }
+}
+
+__device__ inline int scale_exponent(double mx) {
+  if (!(mx > 0.0)) return 0;
+  int e = ilogb(mx) + 1;  // mx * 2^-e in [0.5, 1)
+  return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+
+// grid (prow / kRowsPerTile, 3): A_d rows and the exponents e(p, d).
 template <int NMAX>
-__device__ inline void write_row(int prec, int side, const double (&v)[NMAX], int n, int kc, void* rowp) {
-  if (prec == kFP64) {
-    double* r = static_cast<double*>(rowp);
-#pragma unroll
-    for (int a = 0; a < NMAX; ++a)
-      if (a < n) r[a] = v[a];
-    for (int c = n; c < kc; ++c) r[c] = 0.0;
-    return;
-  }
-  if (prec == kFP32) {
-    float* r = static_cast<float*>(rowp);
-#pragma unroll
-    for (int a = 0; a < NMAX; ++a)
-      if (a < n) r[a] = (float)v[a];
-    for (int c = n; c < kc; ++c) r[c] = 0.0f;
-    return;
-  }
-  if (prec == kF16X3) {
-    // A = [h0 | h0 | h1], Y = [h0 | h1 | h0]
-    _Float16* r = static_cast<_Float16*>(rowp);
-#pragma unroll
-    for (int a = 0; a < NMAX; ++a) {
-      if (a < n) {
-        const _Float16 h0 = to_slice<_Float16>(v[a]);
-        const _Float16 h1 = to_slice<_Float16>(v[a] - (double)h0);
-        r[a] = h0;
-        r[n + a] = side ? h1 : h0;
-        r[2 * n + a] = side ? h0 : h1;
-      }
-    }
-    for (int c = 3 * n; c < kc; ++c) r[c] = (_Float16)0.0f;
-    return;
-  }
-  __bf16* r = static_cast<__bf16*>(rowp);
-  const bool six = prec == kBF16X6;
-#pragma unroll
-  for (int a = 0; a < NMAX; ++a) {
-    if (a < n) {
-      const __bf16 s0 = to_slice<__bf16>(v[a]);
-      const double r1 = v[a] - (double)(float)s0;
-      const __bf16 s1 = to_slice<__bf16>(r1);
-      if (!six) {
-        // A = [s0 | s0 | s1], Y = [s0 | s1 | s0]
-        r[a] = s0;
-        r[n + a] = side ? s1 : s0;
-        r[2 * n + a] = side ? s0 : s1;
-      } else {
-        // A = [s0|s0|s1|s0|s1|s2], Y = [s0|s1|s0|s2|s1|s0]
-        const __bf16 s2 = to_slice<__bf16>(r1 - (double)(float)s1);
-        r[a] = s0;
-        r[n + a] = side ? s1 : s0;
-        r[2 * n + a] = side ? s0 : s1;
-        r[3 * n + a] = side ? s2 : s0;
-        r[4 * n + a] = s1;
-        r[5 * n + a] = side ? s0 : s2;
-      }
-    }
-  }
-  for (int c = (six ? 6 : 3) * n; c < kc; ++c) r[c] = (__bf16)0.0f;
-}
-
-template <int NMAX>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kRowsPerTile)
 pack_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int kc,
             char* __restrict__ A, int32_t* __restrict__ ex) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= 3 * (int64_t)prow) return;
-  const int d = (int)(g / prow);
-  const int64_t p = g - (int64_t)d * prow;
-  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
-  char* rowp = A + g * kc * es;
+  extern __shared__ uint32_t tile[];
+  const int d = blockIdx.y;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsPerTile;
+  const int64_t p = row0 + threadIdx.x;
+  const int sw = tile_stride_words(prec, kc);
+  uint32_t* row = tile + threadIdx.x * sw;
   double v[NMAX];
 #pragma unroll
   for (int a = 0; a < NMAX; ++a) v[a] = 0.0;
@@ -181,29 +150,39 @@ pack_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int pr
         mx = fmax(mx, fabs(v[a]));
       }
     }
-    if (prec != kFP64) {
-      e = scale_exponent(mx);
-#pragma unroll
-      for (int a = 0; a < NMAX; ++a) v[a] = ldexp(v[a], -e);
-    }
+    if (prec != kFP64) e = scale_exponent(mx);
   }
-  ex[g] = e;
-  write_row<NMAX>(prec, 0, v, n, kc, rowp);
+  ex[(int64_t)d * prow + p] = e;
+#pragma unroll
+  for (int a = 0; a < NMAX; ++a)
+    if (a < n) tile_elem(prec, 0, ldexp(v[a], -e), n, a, row);
+  tile_pad(prec, n, kc, row);
+  __syncthreads();
+  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
+  tile_store(prec, kc, tile, sw, reinterpret_cast<uint32_t*>(A + (((int64_t)d * prow + row0) * kc) * es));
 }
 
+// grid (prow / kRowsPerTile, 3 nq): Y_{k,d} rows = (K_k M_d)(:, q) scaled by
+// 2^-e(q,d), and by w_k for d = 2; FP64 arithmetic.  K_k is staged in LDS,
+// zero padded to NMAX x NMAX, and read at wave-uniform addresses.
 template <int NMAX>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kRowsPerTile)
 project_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
                int kc, const double* __restrict__ K, const double* __restrict__ w,
                const int32_t* __restrict__ ex, char* __restrict__ Y) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (int64_t)nq * 3 * prow) return;
-  const int k = (int)(g / (3 * (int64_t)prow));
-  const int64_t rem = g - (int64_t)k * 3 * prow;
-  const int d = (int)(rem / prow);
-  const int64_t q = rem - (int64_t)d * prow;
-  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
-  char* rowp = Y + g * kc * es;
+  extern __shared__ uint32_t tile[];
+  const int sl = blockIdx.y;
+  const int k = sl / 3, d = sl - 3 * (sl / 3);
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsPerTile;
+  const int64_t q = row0 + threadIdx.x;
+  const int sw = tile_stride_words(prec, kc);
+  uint32_t* row = tile + threadIdx.x * sw;
+  double* Ks = reinterpret_cast<double*>(tile + ((kRowsPerTile * sw + 1) & ~1));
+  const double* Kk = K + (int64_t)k * n * n;
+  for (int i = threadIdx.x; i < NMAX * NMAX; i += kRowsPerTile) {
+    const int a = i / NMAX, b = i - a * NMAX;
+    Ks[i] = (a < n && b < n) ? Kk[a * n + b] : 0.0;
+  }
   double m[NMAX];
 #pragma unroll
   for (int b = 0; b < NMAX; ++b) m[b] = 0.0;
@@ -215,15 +194,122 @@ project_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int
     scale = ldexp(1.0, -ex[(int64_t)d * prow + q]);
     if (d == 2) scale *= w[k];
   }
-  const double* Kk = K + (int64_t)k * n * n;
+  __syncthreads();
   for (int a = 0; a < n; ++a) {
+    const double* kr = Ks + a * NMAX;
     double s = 0.0;
 #pragma unroll
-    for (int b = 0; b < NMAX; ++b)
-      if (b < n) s += Kk[a * n + b] * m[b];
-    write_elem(prec, 1, s * scale, n, a, rowp);
+    for (int b = 0; b < NMAX; ++b) s += kr[b] * m[b];
+    tile_elem(prec, 1, s * scale, n, a, row);
   }
-  write_pad(prec, n, kc, rowp);
+  tile_pad(prec, n, kc, row);
+  __syncthreads();
+  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
+  tile_store(prec, kc, tile, sw, reinterpret_cast<uint32_t*>(Y + ((((int64_t)k * 3 + d) * prow + row0) * kc) * es));
+}
+
+// Same contraction for n % 8 == 0 with direct 16-byte stores: 256 rows per
+// work group (one per thread), eight outputs at a time, each slice segment
+// written as aligned 16-byte vectors; full rows are merged in L2 before they
+// reach HBM.  K_k is staged once per work group in LDS, zero padded.
+template <typename T>
+__device__ inline void store8(char* rowp, int pos, const T (&v)[8]) {
+  if constexpr (sizeof(T) == 2) {
+    uint4 u;
+    unsigned short h[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h[i] = __builtin_bit_cast(unsigned short, v[i]);
+    u.x = h[0] | ((uint32_t)h[1] << 16);
+    u.y = h[2] | ((uint32_t)h[3] << 16);
+    u.z = h[4] | ((uint32_t)h[5] << 16);
+    u.w = h[6] | ((uint32_t)h[7] << 16);
+    *reinterpret_cast<uint4*>(rowp + 2 * pos) = u;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; i += 16 / (int)sizeof(T))
+      *reinterpret_cast<uint4*>(rowp + sizeof(T) * (pos + i)) = *reinterpret_cast<const uint4*>(&v[i]);
+  }
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(256)
+project8_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
+                int kc, const double* __restrict__ K, const double* __restrict__ w,
+                const int32_t* __restrict__ ex, char* __restrict__ Y) {
+  __shared__ double Ks[NMAX * NMAX];
+  const int sl = blockIdx.y;
+  const int k = sl / 3, d = sl - 3 * (sl / 3);
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double* Kk = K + (int64_t)k * n * n;
+  for (int i = threadIdx.x; i < NMAX * NMAX; i += 256) {
+    const int a = i / NMAX, b = i - a * NMAX;
+    Ks[i] = (a < n && b < n) ? Kk[a * n + b] : 0.0;
+  }
+  double m[NMAX];
+#pragma unroll
+  for (int b = 0; b < NMAX; ++b) m[b] = 0.0;
+  double scale = 0.0;
+  if (q < npair) {
+#pragma unroll
+    for (int b = 0; b < NMAX; ++b)
+      if (b < n) m[b] = M[((int64_t)d * n + b) * npair + q];
+    scale = ldexp(1.0, -ex[(int64_t)d * prow + q]);
+    if (d == 2) scale *= w[k];
+  }
+  __syncthreads();
+  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
+  char* rowp = Y + ((((int64_t)k * 3 + d) * prow + q) * kc) * es;
+  for (int a0 = 0; a0 < n; a0 += 8) {
+    double y[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double* kr = Ks + (a0 + i) * NMAX;
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < NMAX; ++b) s += kr[b] * m[b];
+      y[i] = s * scale;
+    }
+    if (prec == kFP64) {
+      store8<double>(rowp, a0, y);
+    } else if (prec == kFP32) {
+      float f[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) f[i] = (float)y[i];
+      store8<float>(rowp, a0, f);
+    } else if (prec == kF16X3) {
+      _Float16 h0[8], h1[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        h0[i] = to_slice<_Float16>(y[i]);
+        h1[i] = to_slice<_Float16>(y[i] - (double)h0[i]);
+      }
+      // Y = [h0 | h1 | h0]
+      store8<_Float16>(rowp, seg_pos(prec, n, 0, a0), h0);
+      store8<_Float16>(rowp, seg_pos(prec, n, 1, a0), h1);
+      store8<_Float16>(rowp, seg_pos(prec, n, 2, a0), h0);
+    } else {
+      __bf16 s0[8], s1[8], s2[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        s0[i] = to_slice<__bf16>(y[i]);
+        const double r1 = y[i] - (double)(float)s0[i];
+        s1[i] = to_slice<__bf16>(r1);
+        s2[i] = to_slice<__bf16>(r1 - (double)(float)s1[i]);
+      }
+      // BF16X3: Y = [s0 | s1 | s0];  BF16X6: Y = [s0|s1|s0|s2|s1|s0]
+      store8<__bf16>(rowp, seg_pos(prec, n, 0, a0), s0);
+      store8<__bf16>(rowp, seg_pos(prec, n, 1, a0), s1);
+      store8<__bf16>(rowp, seg_pos(prec, n, 2, a0), s0);
+      if (prec == kBF16X6) {
+        store8<__bf16>(rowp, 3 * n + a0, s2);
+        store8<__bf16>(rowp, 4 * n + a0, s1);
+        store8<__bf16>(rowp, 5 * n + a0, s0);
+      }
+    }
+  }
+  // zero tail [nseg*n, kc): a multiple of 8 elements, 16-byte aligned
+  const int nseg = (prec == kFP64 || prec == kFP32) ? 1 : (prec == kBF16X6 ? 6 : 3);
+  for (int c = nseg * n * es; c < kc * es; c += 16) *reinterpret_cast<uint4*>(rowp + c) = uint4{0u, 0u, 0u, 0u};
 }
 
 // ---------------------------------------------------------------------------
@@ -445,8 +531,9 @@ template <int NMAX>
 hipError_t launch_pack_t(int prec, const double* M, int n, int npair, int prow, void* A,
                          int32_t* ex, hipStream_t s) {
   const int kc = operand_kc(prec, n);
-  const int64_t total = 3 * (int64_t)prow;
-  hipLaunchKernelGGL(pack_kernel<NMAX>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
+  const size_t lds = sizeof(uint32_t) * kRowsPerTile * (kc * es / 4 + 1);
+  hipLaunchKernelGGL(pack_kernel<NMAX>, dim3(prow / kRowsPerTile, 3), dim3(kRowsPerTile), lds, s,
                      prec, M, n, (int64_t)npair, prow, kc, static_cast<char*>(A), ex);
   return hipGetLastError();
 }
@@ -455,8 +542,15 @@ template <int NMAX>
 hipError_t launch_project_t(int prec, const double* M, int n, int npair, int prow, int nq,
                             const NodeTables& tb, const int32_t* ex, void* Y, hipStream_t s) {
   const int kc = operand_kc(prec, n);
-  const int64_t total = (int64_t)nq * 3 * prow;
-  hipLaunchKernelGGL(project_kernel<NMAX>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
+  if (n % 8 == 0 && prow % 256 == 0) {
+    hipLaunchKernelGGL(project8_kernel<NMAX>, dim3(prow / 256, 3 * nq), dim3(256), 0, s,
+                       prec, M, n, (int64_t)npair, prow, nq, kc, tb.K, tb.w, ex, static_cast<char*>(Y));
+    return hipGetLastError();
+  }
+  const size_t tile_words = ((size_t)kRowsPerTile * (kc * es / 4 + 1) + 1) & ~size_t(1);
+  const size_t lds = sizeof(uint32_t) * tile_words + sizeof(double) * NMAX * NMAX;
+  hipLaunchKernelGGL(project_kernel<NMAX>, dim3(prow / kRowsPerTile, 3 * nq), dim3(kRowsPerTile), lds, s,
                      prec, M, n, (int64_t)npair, prow, nq, kc, tb.K, tb.w, ex, static_cast<char*>(Y));
   return hipGetLastError();
 }
@@ -477,7 +571,9 @@ int operand_kc(int prec, int n) {
   }
 }
 
-int assemble_tile(int /*prec*/) { return 64; }
+// rows of the operands are padded to this multiple (the 16-bit kernel's row
+// panels are up to 256 rows; the generic kernel's tiles are 64)
+int assemble_tile(int prec) { return (prec == kBF16X3 || prec == kBF16X6 || prec == kF16X3) ? 256 : 64; }
 
 hipError_t launch_pack(int prec, const double* M, int n, int npair, int prow, void* A,
                        int32_t* ex, hipStream_t s) {

@@ -4,6 +4,7 @@
 #include "tai_internal.h"
 #include "../../include/tai.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -32,6 +33,10 @@ struct tai_ctx {
   Buf host_basis;         // pinned staging of a basis
   hipEvent_t host_basis_done = nullptr;
   Buf opA, opEx, opY;     // assembly operands
+  Buf asm_tab, asm_counter;  // 16-bit kernel: device molecule table + items, queue counter
+  Buf asm_host;           // pinned staging of the table
+  hipEvent_t asm_host_done = nullptr;
+  int cus = 0;            // compute units of the device
   Buf jwork;              // apply_J intermediates
   // batched path
   Buf b_nodes, b_basis, b_opA, b_opEx, b_opY, b_mols, b_counter;
@@ -231,8 +236,27 @@ tai::DevBasis dev_basis_view(const tai_basis* b, char* dev) {
   return d;
 }
 
-int prow_of(int prec, int64_t npair) {
-  const int t = tai::assemble_tile(prec);
+// True when the 16-bit A-stationary kernel assembles this (prec, n).
+bool use16(int prec, int n) {
+  return tai::is_split16(prec) && tai::operand_kc(prec, n) <= tai::asm16_max_kc() &&
+         !std::getenv("TAI_ASM16_GENERIC");
+}
+
+// Padded operand row count: a multiple of the generic kernel's tile (64),
+// of the projection kernel's 256-row blocks and of the 16-bit kernel's
+// row panel.
+int prow_of(int prec, int n, int64_t npair) {
+  int64_t t = 256;
+  if (use16(prec, n)) {
+    const int64_t r = tai::asm16_rows_for(tai::operand_kc(prec, n), tai::operand_dup_chunks(prec, n));
+    int64_t a = r, b = 256;
+    while (b) {
+      const int64_t tmp = a % b;
+      a = b;
+      b = tmp;
+    }
+    t = r / a * 256;  // lcm(r, 256)
+  }
   return (int)((npair + t - 1) / t * t);
 }
 
@@ -243,6 +267,22 @@ size_t opY_bytes(int prec, int n, int nq, int prow) {
   return align256((size_t)nq * 3 * prow * tai::operand_kc(prec, n) * tai::operand_esize(prec));
 }
 size_t opEx_bytes(int prow) { return align256(sizeof(int32_t) * 3 * (size_t)prow); }
+
+// Work items of the 16-bit assembly kernel for one molecule: row panels of
+// R rows x ranges of up to kChunk 32-column blocks, restricted to blocks that
+// hold entries with col >= row; column-chunk-major so that concurrently
+// running work groups share the Y blocks.
+void build_items16(std::vector<int4>& out, int mol, int64_t npair, int64_t R) {
+  constexpr int64_t kChunk = 16;
+  const int64_t ncb = (npair + 31) / 32;
+  const int64_t nrp = (npair + R - 1) / R;
+  for (int64_t j = 0; j * kChunk < ncb; ++j)
+    for (int64_t rp = 0; rp < nrp; ++rp) {
+      const int64_t lo = std::max(j * kChunk, rp * R / 32);
+      const int64_t hi = std::min((j + 1) * kChunk, ncb);
+      if (lo < hi) out.push_back(int4{mol, (int)rp, (int)lo, (int)hi});
+    }
+}
 
 }  // namespace
 
@@ -264,6 +304,7 @@ int tai_create(tai_ctx** ctx, int hip_device) {
       return TAI_ERR_HIP;
     }
     c->device = hip_device;
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess) c->cus = 256;
   }
   *ctx = c;
   return TAI_OK;
@@ -274,11 +315,13 @@ int tai_destroy(tai_ctx* c) {
   if (c->device >= 0) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->jwork, &c->b_nodes, &c->b_basis,
+    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->asm_tab, &c->asm_counter, &c->jwork, &c->b_nodes, &c->b_basis,
                    &c->b_opA, &c->b_opEx, &c->b_opY, &c->b_mols, &c->b_counter})
       free_buf(c, *b);
     if (c->host_basis.p) hipHostFree(c->host_basis.p);
     if (c->b_host.p) hipHostFree(c->b_host.p);
+    if (c->asm_host.p) hipHostFree(c->asm_host.p);
+    if (c->asm_host_done) hipEventDestroy(c->asm_host_done);
     if (c->host_basis_done) hipEventDestroy(c->host_basis_done);
     if (c->b_host_done) hipEventDestroy(c->b_host_done);
     if (c->graph) hipGraphExecDestroy(c->graph);
@@ -381,7 +424,7 @@ int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params*
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int prec = p->prec, n = p->n, nq = p->nq;
-  const int prow = prow_of(prec, npair);
+  const int prow = prow_of(prec, n, npair);
   if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
   if ((r = ensure(c, c->opA, opA_bytes(prec, n, prow)))) return r;
   if ((r = ensure(c, c->opEx, opEx_bytes(prow)))) return r;
@@ -416,7 +459,31 @@ int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params*
   m.kc = tai::operand_kc(prec, n);
   m.tiles = prow / tai::assemble_tile(prec);
   m.tile0 = 0;
-  {
+  if (use16(prec, n)) {
+    std::vector<int4> items;
+    build_items16(items, 0, npair, tai::asm16_rows_for(m.kc, tai::operand_dup_chunks(prec, n)));
+    const size_t tab_bytes = align256(sizeof(tai::AsmMol)) + sizeof(int4) * items.size();
+    if ((r = ensure(c, c->asm_tab, tab_bytes))) return r;
+    if ((r = ensure(c, c->asm_counter, 256))) return r;
+    if ((r = ensure_host(c, c->asm_host, c->asm_host_done, tab_bytes))) return r;
+    char* hb = static_cast<char*>(c->asm_host.p);
+    std::memcpy(hb, &m, sizeof m);
+    std::memcpy(hb + align256(sizeof(tai::AsmMol)), items.data(), sizeof(int4) * items.size());
+    if ((e = hipMemcpyAsync(c->asm_tab.p, hb, tab_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return hip_fail(c, e, "table upload");
+    if ((e = hipEventRecord(c->asm_host_done, s)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+    unsigned* counter = static_cast<unsigned*>(c->asm_counter.p);
+    if ((e = tai::launch_reset_counter(counter, s)) != hipSuccess) return hip_fail(c, e, "reset kernel");
+    const int nitems = (int)items.size();
+    const int nblocks = std::min(nitems, c->cus > 0 ? c->cus : 256);
+    const auto* mols_dev = static_cast<const tai::AsmMol*>(c->asm_tab.p);
+    const auto* items_dev = reinterpret_cast<const int4*>(static_cast<char*>(c->asm_tab.p) + align256(sizeof(tai::AsmMol)));
+    {
+      Timed tm(c, kStAssemble, s);
+      e = tai::launch_assemble16(prec, m.kc, tai::operand_dup_chunks(prec, n), mols_dev, items_dev, nitems, counter,
+                                 nblocks, s);
+    }
+  } else {
     Timed tm(c, kStAssemble, s);
     e = tai::launch_assemble(prec, m, s);
   }
@@ -452,7 +519,7 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
   std::vector<tai::AsmMol> am(nmol);
   for (int i = 0; i < nmol; ++i) {
     const int64_t np = npair_of(mols[i].basis.nb);
-    prow[i] = prow_of(prec, np);
+    prow[i] = prow_of(prec, n, np);
     off_nodes[i] = sz_nodes; sz_nodes += align256(tai::node_tables_bytes(nq, n));
     off_basis[i] = sz_basis; sz_basis += basis_bytes(mols[i].basis.nb);
     off_A[i] = sz_A; sz_A += opA_bytes(prec, n, prow[i]);
@@ -464,7 +531,6 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
   if ((r = ensure(c, c->b_opA, sz_A))) return r;
   if ((r = ensure(c, c->b_opEx, sz_Ex))) return r;
   if ((r = ensure(c, c->b_opY, sz_Y))) return r;
-  if ((r = ensure(c, c->b_mols, sizeof(tai::AsmMol) * nmol))) return r;
   if ((r = ensure(c, c->b_counter, 256))) return r;
   for (int i = 0; i < nmol; ++i) {
     tai::AsmMol& m = am[i];
@@ -481,15 +547,29 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
     m.tile0 = nitems;
     nitems += (int64_t)m.tiles * (m.tiles + 1) / 2;
   }
+  // the 16-bit kernel drains (molecule, row panel, column range) items,
+  // largest molecules first so the tail of the queue holds small items
+  const bool split16 = use16(prec, n);
+  std::vector<int4> items16;
+  if (split16) {
+    std::vector<int> order(nmol);
+    for (int i = 0; i < nmol; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return am[a].npair > am[b].npair; });
+    for (int i : order) build_items16(items16, i, am[i].npair, tai::asm16_rows_for(am[i].kc, tai::operand_dup_chunks(prec, n)));
+  }
+  const size_t tab_bytes = align256(sizeof(tai::AsmMol) * nmol) + sizeof(int4) * items16.size();
+  if ((r = ensure(c, c->b_mols, tab_bytes))) return r;
 
-  // upload bases and the molecule table (outside any graph)
-  const size_t host_bytes = sz_basis + align256(sizeof(tai::AsmMol) * nmol);
+  // upload bases, the molecule table and the items (outside any graph)
+  const size_t host_bytes = sz_basis + tab_bytes;
   if ((r = ensure_host(c, c->b_host, c->b_host_done, host_bytes))) return r;
   char* hb = static_cast<char*>(c->b_host.p);
   for (int i = 0; i < nmol; ++i) pack_basis_host(&mols[i].basis, hb + off_basis[i]);
   std::memcpy(hb + sz_basis, am.data(), sizeof(tai::AsmMol) * nmol);
+  if (!items16.empty())
+    std::memcpy(hb + sz_basis + align256(sizeof(tai::AsmMol) * nmol), items16.data(), sizeof(int4) * items16.size());
   hipError_t e = hipMemcpyAsync(c->b_basis.p, hb, sz_basis, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->b_mols.p, hb + sz_basis, sizeof(tai::AsmMol) * nmol, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->b_mols.p, hb + sz_basis, tab_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(c->b_host_done, s);
   if (e != hipSuccess) return hip_fail(c, e, "batch upload");
 
@@ -513,10 +593,18 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
     unsigned* counter = static_cast<unsigned*>(c->b_counter.p);
     err = tai::launch_reset_counter(counter, st);
     if (err != hipSuccess) return err;
+    const auto* mols_dev = static_cast<const tai::AsmMol*>(c->b_mols.p);
+    if (split16) {
+      const auto* items_dev = reinterpret_cast<const int4*>(static_cast<char*>(c->b_mols.p) +
+                                                            align256(sizeof(tai::AsmMol) * nmol));
+      const int ni = (int)items16.size();
+      const int blocks = std::min(ni, c->cus > 0 ? c->cus : 256);
+      return tai::launch_assemble16(prec, am[0].kc, tai::operand_dup_chunks(prec, n), mols_dev, items_dev, ni, counter,
+                                    blocks, st);
+    }
     int blocks = tai::assemble_queue_blocks(prec, c->device);
     if (blocks > nitems) blocks = (int)nitems;
-    return tai::launch_assemble_queue(prec, static_cast<const tai::AsmMol*>(c->b_mols.p), nmol, nitems, counter,
-                                      blocks, st);
+    return tai::launch_assemble_queue(prec, mols_dev, nmol, nitems, counter, blocks, st);
   };
 
   const bool use_graph = s != nullptr && !std::getenv("TAI_NO_GRAPH");

@@ -7,6 +7,8 @@
 
 namespace tai {
 
+enum Prec { kFP64 = 0, kFP32 = 1, kBF16X3 = 2, kBF16X6 = 3, kF16X3 = 4 };
+
 // Composite Gauss-Legendre rule used for the 1D moments: the pair's support
 // is split into kMomPanels equal panels of kMomOrder nodes each.
 constexpr int kMomPanels = 4;
@@ -44,10 +46,29 @@ hipError_t launch_moments(const DevBasis& b, int n, double L, const NodeTables& 
 
 // ---- assembly -------------------------------------------------------------
 
-enum Prec { kFP64 = 0, kFP32 = 1, kBF16X3 = 2, kBF16X6 = 3, kF16X3 = 4 };
-
 // Length of one operand K-vector (all slices concatenated, zero padded).
 int operand_kc(int prec, int n);
+
+// Order of the inner (K) index of the split operands.  The three slice
+// segments of the X3 modes (A = [s0|s0|s1], Y = [s0|s1|s0]) are laid out in
+// groups of 8 so that, for n % 8 == 0, the first dup_chunks(n) 32-wide
+// chunks of segment 0 and segment 1 sit in chunks c and c + Q: the A
+// operand then has Q pairs of identical MFMA fragments, which the 16-bit
+// kernel keeps in registers once.  Any such permutation of K, applied to A
+// and Y alike, leaves every inner product unchanged.
+__host__ __device__ inline int operand_dup_chunks(int prec, int n) {
+  return ((prec == kBF16X3 || prec == kF16X3) && n % 8 == 0) ? n / 32 : 0;
+}
+__host__ __device__ inline int seg_pos(int prec, int n, int s, int a) {
+  const int Q = operand_dup_chunks(prec, n);
+  if (Q == 0) return s * n + a;
+  const int G = n / 8, g = a >> 3, o = a & 7;
+  int p;
+  if (s == 0) p = g < 4 * Q ? g : 8 * Q + (g - 4 * Q);
+  else if (s == 1) p = g < 4 * Q ? 4 * Q + g : 8 * Q + (G - 4 * Q) + (g - 4 * Q);
+  else p = 8 * Q + 2 * (G - 4 * Q) + g;
+  return 8 * p + o;
+}
 // Bytes per operand element.
 int operand_esize(int prec);
 // Square output tile edge of the assembly kernel (rows of operands are
@@ -81,6 +102,15 @@ hipError_t launch_assemble_queue(int prec, const AsmMol* mols_dev, int nmol, int
                                  unsigned* counter, int nblocks, hipStream_t s);
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t s);
 int assemble_queue_blocks(int prec, int device);
+
+// 16-bit split arithmetics: A-stationary persistent kernel over work items
+// int4 {molecule, row panel, first column block, end column block}; row
+// panels are asm16_rows_per_block(kc) rows, column blocks 32 columns.
+int asm16_max_kc();
+int asm16_rows_for(int kc, int q);
+hipError_t launch_assemble16(int prec, int kc, int q, const AsmMol* mols_dev, const int4* items_dev, int nitems,
+                             unsigned* counter, int nblocks, hipStream_t s);
+inline bool is_split16(int prec) { return prec == kBF16X3 || prec == kBF16X6 || prec == kF16X3; }
 
 // ---- Coulomb matrix through the grid tensor --------------------------------
 
