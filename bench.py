@@ -60,7 +60,7 @@ def traffic_from_profiles(kernel_src_sha, workload):
 
 def src_sha():
     h = hashlib.sha256()
-    for f in ("k_assemble.hip",):
+    for f in ("k_assemble.hip", "k_assemble16.hip", "tai_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2210_13069_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--prec", default="f16x3", help="headline arithmetic")
     ap.add_argument("--only-headline", action="store_true", help="skip the comparison paths")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target length of the oracle sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -148,7 +149,8 @@ def main():
     peak = PEAK_TFLOPS[args.prec]
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 5), "traffic": traffic_from_profiles(src_sha(), "spd400"),
-                "kernel": "assemble_kernel", "flops_per_launch": flops,
+                "kernel": "assemble16_kernel" if args.prec in ("f16x3", "bf16x3", "bf16x6") else "assemble_kernel",
+                "flops_per_launch": flops,
                 "launch_ms": round(asm_ms, 4)}
 
     paths = {args.prec: {"ms_per_step": round(ms_head, 3), "entries_per_s": value,
@@ -258,20 +260,29 @@ def main():
             cores = os.cpu_count()
         log(f"oracle sample on the host ({cores} threads)")
         sel = np.unique(np.concatenate([sp, sq]))
-        rows = rng.choice(npair, 48, replace=False)
-        cols_extra = rng.choice(npair, 1536, replace=False)
-        allp = np.unique(np.concatenate([sel, rows, cols_extra]))
+        cols_extra = rng.choice(npair, 14000, replace=False)
+        allp = np.unique(np.concatenate([sel, cols_extra]))
+        # the sample: oracle moments of `allp` and a block of B rows against all
+        # of them; the row count is sized from a short probe so that the timed
+        # oracle work takes about args.cpu_seconds
         t0 = time.perf_counter()
         Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, pairs=allp)
         t, w = T.time_nodes(P.omega, P.nq)
         xi, _ = T.cheb_nodes(P.n, P.L)
         Kt = T.ktables(t, xi)
-        Brows = T.B_full(Mr, Kt, w, rows=np.searchsorted(allp, rows))
-        t_or = time.perf_counter() - t0
+        t_mom = time.perf_counter() - t0
+        tp = time.perf_counter()
+        T.B_full(Mr, Kt, w, rows=np.arange(64))
+        per_row = (time.perf_counter() - tp) / 64
+        nrows = int(min(len(allp), max(16, (args.cpu_seconds - t_mom) / max(per_row, 1e-6))))
+        rows = np.sort(rng.choice(len(allp), nrows, replace=False))
+        tb = time.perf_counter()
+        Brows = T.B_full(Mr, Kt, w, rows=rows)
+        t_or = t_mom + (time.perf_counter() - tb)
         n_or = Brows.size
         cpu = {"value": n_or / t_or, "unit": "entries/s", "cores": int(cores), "kind": "oracle",
-               "sample": f"moments of {len(allp)} pairs + B on {len(rows)} x {len(allp)} entries "
-                         f"(Theorem 3.1 matrix route) of the Nb=400 workload; {t_or:.1f} s"}
+               "sample": f"moments of {len(allp)} sampled pairs + B on {len(rows)} x {len(allp)} entries "
+                         f"(Theorem 3.1 matrix route) of the Nb=400 workload, {t_or:.1f} s of oracle work"}
         ref = T.B_entries(Mr, Kt, w, np.searchsorted(allp, sp), np.searchsorted(allp, sq))
         dref = T.B_entries(Mr, Kt, w, np.searchsorted(allp, sel), np.searchsorted(allp, sel))
         scale = float(np.max(np.abs(dref)))

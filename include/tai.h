@@ -58,7 +58,7 @@ enum {
 };
 
 /* Chebyshev node family (Def. 2.2): Lobatto (second kind) is the paper's
-   choice for TA (remark closing section 5.1); Gauss is the first kind. */
+   choice for TA (remark closing section 4.3); Gauss is the first kind. */
 enum { TAI_NODES_LOBATTO = 0, TAI_NODES_GAUSS = 1 };
 
 /* Arithmetic of the B contraction (tai_assemble_B) and of the grid

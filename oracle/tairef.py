@@ -89,7 +89,7 @@ def time_nodes(omega, nq):
 
 # ---------------------------------------------------------------------------
 # Chebyshev nodes and the Lagrange basis (Def. 2.2; Lobatto nodes for TA per
-# the remark closing section 5.1)
+# the remark closing section 4.3)
 # ---------------------------------------------------------------------------
 def cheb_nodes(n, L, kind=NODES_LOBATTO):
     """Chebyshev nodes xi_a on [-L, L] and their barycentric weights beta_a.
@@ -148,7 +148,7 @@ def ktables(t, xi):
 
 
 # ---------------------------------------------------------------------------
-# Basis and pairs (eqs. basis, primi; Prop. 2.1; symmetric pairs, section 6.3)
+# Basis and pairs (eqs. basis, primi; Prop. 2.1; symmetric pairs, section 5.3)
 # ---------------------------------------------------------------------------
 def _double_factorial_odd(l):
     """(2l-1)!! with (-1)!! = 1."""
@@ -173,7 +173,7 @@ def pair_list(nb):
     """(mu, nu) of every pair mu <= nu, row-major upper triangle.
 
     Pair index p(mu,nu) = mu*nb - mu(mu-1)/2 + (nu - mu) (0-based), which is the
-    order of this list.  Pair symmetry g_mu g_nu = g_nu g_mu (section 6.3).
+    order of this list.  Pair symmetry g_mu g_nu = g_nu g_mu (section 5.3).
     """
     mu, nu = np.triu_indices(nb)
     return mu.astype(np.int64), nu.astype(np.int64)
@@ -324,7 +324,7 @@ def B_kronecker(M, K, w):
 
 
 # ---------------------------------------------------------------------------
-# Coulomb matrix J (section 6, eqs. Coul and coulapprox, with eq. ig1)
+# Coulomb matrix J (section 5, eqs. Coul and coulapprox, with eq. ig1)
 # ---------------------------------------------------------------------------
 def density_pairs(D):
     """Pair vector Dt_q = D(k,l) (2 - delta_kl) for q = (k,l), k <= l.

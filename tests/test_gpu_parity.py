@@ -119,6 +119,21 @@ def test_assemble_ldb_and_ragged_tail(tai):
         assert _normwise(o[:, :npair].astype(np.float64), Br) <= (1e-10 if prec == 0 else 1e-6)
 
 
+def test_assemble_matches_stored_tiny_s(tai):
+    """The tiny 36-pair workload against the stored oracle matrix
+    (tests/golden/tiny_s.json), every precision form."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tiny_s.json")))
+    ref = np.array(g["B_ta"])
+    b, P = I.tiny_s()
+    Mg = tai.moments(b, P)
+    for prec in (0, 1, 2, 3, 4):
+        Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+        assert Bg.shape == ref.shape
+        assert _normwise(Bg, ref) <= (1e-10 if prec == 0 else LOWP_TOL[prec]), prec
+
+
 def test_assemble_deterministic(tai):
     b, P = I.sp16()
     Mg = tai.moments(b, P)

@@ -102,7 +102,7 @@ def test_tight_parameters_match_semi_analytic_pd():
 
 def test_config_params_error_and_convergence_in_n():
     # tiny_s at its own parameters (n=24, L=8, nq=16): the interpolation error
-    # dominates; it must fall as n grows (paper section 7.1.1)
+    # dominates; it must fall as n grows (paper section 6.1)
     b, P = I.tiny_s()
     Bc = X.B_closed_form_s(b.center, b.alpha, P.omega)
     errs = []
@@ -168,7 +168,7 @@ def test_small_omega_limit():
 
 
 def test_large_omega_is_reported_not_asserted(capsys):
-    # the paper finds TA degrades as omega grows (section 7.1.1); report it
+    # the paper finds TA degrades as omega grows (section 6.1); report it
     b, _ = I.tiny_s()
     Bc = X.B_closed_form_s(b.center, b.alpha, 1.0)
     M, K, w = _ta(b, 1.0, 32, 40, 16.0)
