@@ -25,6 +25,7 @@
 #include "tai_internal.h"
 
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 
 namespace tai {
@@ -36,21 +37,30 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 constexpr double kTwoOverSqrtPi = 1.1283791670955126;
-constexpr int kCB = 2;      // 16-column blocks per 32-column block
-constexpr int kGroup16 = 8; // FP32 accumulation group of quadrature nodes
-constexpr int kOutStride = 33;  // floats per row of the output tile
+constexpr int kGroup16 = 8;  // FP32 accumulation group of quadrature nodes
 
-template <int KC, int Q>
+// Compile-time shape: NW waves per work group, RB row blocks of 16 per wave,
+// CB column blocks of 16 per item block, an LDS ring of NBUF nodes.
+template <int KC, int Q, int NW, int RB, int CB, int NBUF>
 struct Cfg16 {
-  static constexpr int NCH = KC / 32;                       // 32-wide inner chunks
-  static constexpr int U = NCH - Q;                         // distinct A fragments
-  static constexpr int RB = U <= 3 ? 4 : (U <= 4 ? 3 : (U <= 6 ? 2 : 1));
-  static constexpr int ROWS = 64 * RB;                      // rows per work group
-  static constexpr int NFRAG = 3 * kCB * NCH;               // 1 KB fragments per node
-  static constexpr int LPW = (NFRAG + 3) / 4;               // loads per wave per node
-  static constexpr int NV = RB * kCB * 4;                   // accumulator values per lane
-  static constexpr int ACC_BYTES = 4 * NV * 64 * 8;         // FP64 partial sums, all waves
-  static constexpr int NBUF = (3 * NFRAG * 1024 + ACC_BYTES <= 150 * 1024) ? 3 : 2;
+  static constexpr int KC_ = KC, Q_ = Q, NW_ = NW, RB_ = RB, CB_ = CB, NBUF_ = NBUF;
+  static constexpr int NCH = KC / 32;                    // 32-wide inner chunks
+  static constexpr int U = NCH - Q;                      // distinct A fragments
+  static constexpr int NT = 64 * NW;                     // threads per work group
+  static constexpr int ROWS = 16 * RB * NW;              // rows per panel
+  static constexpr int COLS = 16 * CB;                   // columns per block
+  static constexpr int NFRAG = 3 * CB * NCH;             // 1 KB fragments per node
+  static constexpr int LPW_HI = (NFRAG + NW - 1) / NW;   // loads of waves < N_HI
+  static constexpr int LPW_LO = NFRAG / NW;              // loads of the others
+  static constexpr int N_HI = NFRAG % NW == 0 ? NW : NFRAG % NW;
+  static constexpr int NV = RB * CB * 4;                 // accumulator values per lane
+  static constexpr int OS = COLS + 1;                    // floats per output-tile row
+  static constexpr int SUM_BYTES = NW * NV * 64 * 8;     // FP64 partial sums, all waves
+  static constexpr int TILE_BYTES = ROWS * OS * 4;
+  static constexpr int SCRATCH_BYTES = SUM_BYTES > TILE_BYTES ? SUM_BYTES : TILE_BYTES;
+  static constexpr int LDS_BYTES = NBUF * NFRAG * 1024 + SCRATCH_BYTES;
+  static_assert(NBUF == 2 || NBUF == 3, "ring depth");
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
 // A fragment register index of MFMA chunk ch (chunks Q..2Q-1 repeat 0..Q-1),
@@ -66,83 +76,93 @@ __device__ inline void wait_vmcnt() {
 __device__ inline v4f mma(v8h a, v8h b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 __device__ inline v4f mma(v8bf a, v8bf b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 
-// Issue the direct-to-LDS loads of the Y fragments of node k into buf.
-// Fragment f = (d*kCB + c)*NCH + ch holds, for lane l, the 16 bytes
+// Direct-to-LDS loads of the Y fragments of one node.  Fragment
+// f = (d*CB + c)*NCH + ch holds, for lane l, the 16 bytes
 // Y[k][d][col0 + 16c + l%16][32ch + 8(l/16) .. +8].  Wave w loads fragments
-// w, w+4, ...; the index is clamped so that every wave issues exactly LPW
-// loads (a clamped duplicate rewrites identical bytes).
-template <int KC, int Q>
-__device__ inline void stage_y(const char* __restrict__ Y, int64_t prow, int k, int64_t col0, uint4* buf,
-                               int wave, int lane) {
-  using C = Cfg16<KC, Q>;
-  const int r16 = lane & 15, kg = lane >> 4;
+// w, w + NW, ... (LPW_HI of them for w < N_HI, else LPW_LO), the same count
+// for every node, so that a wave's wait can count its own loads.  The byte
+// offsets of a wave's fragments within a node are fixed for a column block
+// (yoff); the node base is a uniform pointer.
+template <class C>
+struct YLoads {
+  uint32_t off[C::LPW_HI];
+  __device__ void init(int64_t prow, int64_t col0, int wave, int lane) {
+    const int r16 = lane & 15, kg = lane >> 4;
 #pragma unroll
-  for (int i = 0; i < C::LPW; ++i) {
-    int f = wave + 4 * i;
-    f = f < C::NFRAG ? f : C::NFRAG - 1;
-    const int ch = f % C::NCH;
-    const int c = (f / C::NCH) % kCB;
-    const int d = f / (C::NCH * kCB);
-    const int64_t row = ((int64_t)k * 3 + d) * prow + col0 + 16 * c + r16;
-    const char* src = Y + (row * KC + 32 * ch + 8 * kg) * 2;
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src), (lds_ptr_t)(buf + f * 64), 16, 0, 0);
+    for (int i = 0; i < C::LPW_HI; ++i) {
+      int f = wave + C::NW_ * i;
+      f = f < C::NFRAG ? f : 0;
+      const int ch = f % C::NCH;
+      const int c = (f / C::NCH) % C::CB_;
+      const int d = f / (C::NCH * C::CB_);
+      off[i] = (uint32_t)((((int64_t)d * prow + col0 + 16 * c + r16) * C::KC_ + 32 * ch + 8 * kg) * 2);
+    }
   }
+  __device__ void issue(const char* __restrict__ Y, int64_t prow, int k, uint4* buf, int wave) const {
+    const char* node = Y + (int64_t)k * 3 * prow * C::KC_ * 2;
+#pragma unroll
+    for (int i = 0; i < C::LPW_HI; ++i) {
+      const int f = wave + C::NW_ * i;
+      if (f < C::NFRAG)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(node + off[i]), (lds_ptr_t)(buf + f * 64),
+                                         16, 0, 0);
+    }
+  }
+};
+
+// Wait until this wave's loads of node k have landed.  Loads complete in
+// issue order, so with node k+1's loads already issued (ring of 3) it is
+// enough to allow this wave's per-node count to remain outstanding.
+template <class C>
+__device__ inline void wait_node(bool next_issued, int wave) {
+  if constexpr (C::NBUF_ == 3) {
+    if (next_issued) {
+      if (wave < C::N_HI) wait_vmcnt<C::LPW_HI>();
+      else wait_vmcnt<C::LPW_LO>();
+      return;
+    }
+  }
+  wait_vmcnt<0>();
 }
 
-template <int KC, int Q>
-__device__ inline void wait_stage(int k, int nq) {
-  using C = Cfg16<KC, Q>;
-  if constexpr (C::NBUF == 3) {
-    if (k + 1 < nq) wait_vmcnt<C::LPW>();  // stage k+1 may stay in flight
-    else wait_vmcnt<0>();
-  } else {
-    wait_vmcnt<0>();
-  }
-}
-
-// One node k of a 32-column block: wait for its Y fragments (buffer CUR),
-// issue the loads of node k + NBUF - 1 into buffer NXT, and accumulate.
-// The buffers are distinct __shared__ objects chosen at compile time, so the
-// compiler can tell the in-flight direct-to-LDS writes from the reads.
-template <int KC, int Q, bool BF, int RB, int NCH>
-__device__ inline void node_step(int k, int nq, int64_t prow, int64_t col0, const char* __restrict__ Yb,
+// One node k of a column block: wait for its Y fragments (buffer cur),
+// issue the loads of node k + NBUF - 1 into buffer nxt, and accumulate
+// w_k G_0 o G_1 o G_2 (w_k is folded into Y of direction 2).
+template <class C, bool BF>
+__device__ inline void node_step(int k, int nq, int64_t prow, const YLoads<C>& yl, const char* __restrict__ Yb,
                                  const uint4* cur, uint4* nxt,
-                                 const typename std::conditional<BF, v8bf, v8h>::type (&af)[3][RB][NCH - Q],
-                                 v4f (&acc)[RB][kCB], int wave, int lane) {
-  using C = Cfg16<KC, Q>;
+                                 const typename std::conditional<BF, v8bf, v8h>::type (&af)[3][C::RB_][C::U],
+                                 v4f (&acc)[C::RB_][C::CB_], int wave, int lane) {
   using Frag = typename std::conditional<BF, v8bf, v8h>::type;
-  constexpr int D = C::NBUF - 1;
+  constexpr int RB = C::RB_, CB = C::CB_, NCH = C::NCH;
   // Every wave waits for its own loads of node k, then all waves meet: node
-  // k is then in LDS for everyone, and every wave has consumed node k-1 (its
-  // fragments fed MFMAs that already issued), whose buffer the loads below
-  // reuse.  A plain s_barrier (memory clobber for the compiler) instead of
-  // __syncthreads, whose fence would also drain the loads still in flight.
-  wait_stage<KC, Q>(k, nq);
+  // k is in LDS for everyone and every wave has consumed node k-1, whose
+  // buffer the loads below reuse.  A plain s_barrier (memory clobber for the
+  // compiler) instead of __syncthreads, whose fence would also drain the
+  // loads still in flight.
+  wait_node<C>(k + 1 < nq, wave);
   __asm__ volatile("s_barrier" ::: "memory");
-  if (k + D < nq) stage_y<KC, Q>(Yb, prow, k + D, col0, nxt, wave, lane);
-  v4f H[RB][kCB];
+  if (k + C::NBUF_ - 1 < nq) yl.issue(Yb, prow, k + C::NBUF_ - 1, nxt, wave);
+  v4f H[RB][CB];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    v4f G[RB][kCB];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int c = 0; c < kCB; ++c) G[rb][c] = v4f{0.f, 0.f, 0.f, 0.f};
+    v4f G[RB][CB];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
-      Frag bfr[kCB];
+      Frag bfr[CB];
 #pragma unroll
-      for (int c = 0; c < kCB; ++c)
-        bfr[c] = *reinterpret_cast<const Frag*>(cur + ((d * kCB + c) * NCH + ch) * 64 + lane);
+      for (int c = 0; c < CB; ++c)
+        bfr[c] = *reinterpret_cast<const Frag*>(cur + ((d * CB + c) * NCH + ch) * 64 + lane);
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int c = 0; c < kCB; ++c) G[rb][c] = mma(af[d][rb][a_slot<Q>(ch)], bfr[c], G[rb][c]);
+        for (int c = 0; c < CB; ++c)
+          G[rb][c] = mma(af[d][rb][a_slot<C::Q_>(ch)], bfr[c], ch == 0 ? v4f{0.f, 0.f, 0.f, 0.f} : G[rb][c]);
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int c = 0; c < kCB; ++c) {
+      for (int c = 0; c < CB; ++c) {
         if (d == 0) H[rb][c] = G[rb][c];
         else if (d == 1) H[rb][c] *= G[rb][c];
         else acc[rb][c] += H[rb][c] * G[rb][c];
@@ -150,16 +170,17 @@ __device__ inline void node_step(int k, int nq, int64_t prow, int64_t col0, cons
   }
 }
 
-template <int KC, int Q, bool BF>
+template <class C, bool BF>
 __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4* yb0, uint4* yb1, uint4* yb2,
-                                double* accs, float* outt) {
-  using C = Cfg16<KC, Q>;
+                                double* sums, float* tile) {
   using Frag = typename std::conditional<BF, v8bf, v8h>::type;
-  constexpr int RB = C::RB, NCH = C::NCH, NBUF = C::NBUF;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int RB = C::RB_, CB = C::CB_, NCH = C::NCH, U = C::U, NBUF = C::NBUF_;
+  constexpr int ROWS = C::ROWS, COLS = C::COLS, OS = C::OS, NT = C::NT, NV = C::NV;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
   const int64_t prow = m.prow;
-  const int64_t row_wg = (int64_t)rp * C::ROWS;
+  const int64_t row_wg = (int64_t)rp * ROWS;
   const int64_t row_base = row_wg + wave * 16 * RB;
   const char* __restrict__ Ab = static_cast<const char*>(m.A);
   const char* __restrict__ Yb = static_cast<const char*>(m.Y);
@@ -168,84 +189,85 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
   const int64_t ldb = m.ldb;
   float* __restrict__ Bout = static_cast<float*>(m.B);
   const bool vec_ok = ((ldb & 3) == 0) && ((reinterpret_cast<uintptr_t>(Bout) & 15) == 0);
-  double* myacc = accs + wave * C::NV * 64 + lane;   // value v at myacc[v * 64]
+  double* mysum = sums + wave * NV * 64 + lane;   // value v at mysum[v * 64]
 
   // k-invariant A operand of this wave's rows, all directions
-  Frag af[3][RB][NCH - Q];
+  Frag af[3][RB][U];
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int u = 0; u < NCH - Q; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int64_t row = (int64_t)d * prow + row_base + 16 * rb + r16;
-        af[d][rb][u] = *reinterpret_cast<const Frag*>(Ab + (row * KC + 32 * a_chunk<Q>(u) + 8 * kg) * 2);
+        af[d][rb][u] = *(const __attribute__((address_space(1))) Frag*)(Ab + (row * C::KC_ + 32 * a_chunk<C::Q_>(u) + 8 * kg) * 2);
       }
 
   for (int cb = cb0; cb < cb1; ++cb) {
-    const int64_t col0 = (int64_t)cb * 32;
+    const int64_t col0 = (int64_t)cb * COLS;
     // prologue: the first NBUF-1 nodes
-    stage_y<KC, Q>(Yb, prow, 0, col0, yb0, wave, lane);
-    if (NBUF == 3 && nq > 1) stage_y<KC, Q>(Yb, prow, 1, col0, yb1, wave, lane);
+    YLoads<C> yl;
+    yl.init(prow, col0, wave, lane);
+    yl.issue(Yb, prow, 0, yb0, wave);
+    if (NBUF == 3 && nq > 1) yl.issue(Yb, prow, 1, yb1, wave);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) mysum[v * 64] = 0.0;
 
-    v4f acc[RB][kCB];
+    v4f acc[RB][CB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int c = 0; c < kCB; ++c) acc[rb][c] = v4f{0.f, 0.f, 0.f, 0.f};
-    bool first_flush = true;
+      for (int c = 0; c < CB; ++c) acc[rb][c] = v4f{0.f, 0.f, 0.f, 0.f};
     auto flush = [&](int k) {
       if ((k + 1) % kGroup16 == 0 || k + 1 == nq) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-          for (int c = 0; c < kCB; ++c)
+          for (int c = 0; c < CB; ++c)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int v = (rb * kCB + c) * 4 + r;
-              const double x = (double)acc[rb][c][r];
-              myacc[v * 64] = first_flush ? x : myacc[v * 64] + x;
+              const int v = (rb * CB + c) * 4 + r;
+              mysum[v * 64] += (double)acc[rb][c][r];
             }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-          for (int c = 0; c < kCB; ++c) acc[rb][c] = v4f{0.f, 0.f, 0.f, 0.f};
-        first_flush = false;
+          for (int c = 0; c < CB; ++c) acc[rb][c] = v4f{0.f, 0.f, 0.f, 0.f};
       }
     };
 
     if constexpr (NBUF == 3) {
       for (int k = 0; k < nq; k += 3) {
-        node_step<KC, Q, BF, RB, NCH>(k, nq, prow, col0, Yb, yb0, yb2, af, acc, wave, lane);
+        node_step<C, BF>(k, nq, prow, yl, Yb, yb0, yb2, af, acc, wave, lane);
         flush(k);
         if (k + 1 < nq) {
-          node_step<KC, Q, BF, RB, NCH>(k + 1, nq, prow, col0, Yb, yb1, yb0, af, acc, wave, lane);
+          node_step<C, BF>(k + 1, nq, prow, yl, Yb, yb1, yb0, af, acc, wave, lane);
           flush(k + 1);
         }
         if (k + 2 < nq) {
-          node_step<KC, Q, BF, RB, NCH>(k + 2, nq, prow, col0, Yb, yb2, yb1, af, acc, wave, lane);
+          node_step<C, BF>(k + 2, nq, prow, yl, Yb, yb2, yb1, af, acc, wave, lane);
           flush(k + 2);
         }
       }
     } else {
       for (int k = 0; k < nq; k += 2) {
-        node_step<KC, Q, BF, RB, NCH>(k, nq, prow, col0, Yb, yb0, yb1, af, acc, wave, lane);
+        node_step<C, BF>(k, nq, prow, yl, Yb, yb0, yb1, af, acc, wave, lane);
         flush(k);
         if (k + 1 < nq) {
-          node_step<KC, Q, BF, RB, NCH>(k + 1, nq, prow, col0, Yb, yb1, yb0, af, acc, wave, lane);
+          node_step<C, BF>(k + 1, nq, prow, yl, Yb, yb1, yb0, af, acc, wave, lane);
           flush(k + 1);
         }
       }
     }
 
     // finished block: FP64 sums -> scaled floats in the output tile
-    double fin[C::NV];
+    double fin[NV];
 #pragma unroll
-    for (int v = 0; v < C::NV; ++v) fin[v] = myacc[v * 64];
+    for (int v = 0; v < NV; ++v) fin[v] = mysum[v * 64];
     __syncthreads();  // every wave has read its sums before the tile reuses the space
-    int ecol[kCB];
+    int ecol[CB];
 #pragma unroll
-    for (int c = 0; c < kCB; ++c) {
+    for (int c = 0; c < CB; ++c) {
       const int64_t col = col0 + 16 * c + r16;
       ecol[c] = m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col];
     }
@@ -257,19 +279,20 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
         const int64_t row = row_wg + rl;
         const int erow = m.ex[row] + m.ex[prow + row] + m.ex[2 * prow + row];
 #pragma unroll
-        for (int c = 0; c < kCB; ++c) {
-          const int v = (rb * kCB + c) * 4 + r;
-          outt[rl * kOutStride + 16 * c + r16] = (float)ldexp(fin[v] * kTwoOverSqrtPi, erow + ecol[c]);
+        for (int c = 0; c < CB; ++c) {
+          const int v = (rb * CB + c) * 4 + r;
+          tile[rl * OS + 16 * c + r16] = (float)ldexp(fin[v] * kTwoOverSqrtPi, erow + ecol[c]);
         }
       }
     __syncthreads();
 
-    // rows: B[row][col0 .. col0+31] for row <= col
-    for (int i = threadIdx.x; i < C::ROWS * 8; i += 256) {
-      const int rl = i >> 3, c4 = (i & 7) * 4;
+    // rows: B[row][col0 .. col0+COLS) for row <= col
+    constexpr int Q4 = COLS / 4;
+    for (int i = threadIdx.x; i < ROWS * Q4; i += NT) {
+      const int rl = i / Q4, c4 = (i % Q4) * 4;
       const int64_t row = row_wg + rl;
       const int64_t col = col0 + c4;
-      const float* src = outt + rl * kOutStride + c4;
+      const float* src = tile + rl * OS + c4;
       float* dst = Bout + row * ldb + col;
       if (vec_ok && row <= col && col + 3 < npair) {
         *reinterpret_cast<float4*>(dst) = make_float4(src[0], src[1], src[2], src[3]);
@@ -280,37 +303,36 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
       }
     }
     // mirrored columns: B[col][row .. row+3] for row < col
-    for (int i = threadIdx.x; i < 32 * (C::ROWS / 4); i += 256) {
-      const int cl = i / (C::ROWS / 4), r4 = (i % (C::ROWS / 4)) * 4;
+    constexpr int R4 = ROWS / 4;
+    for (int i = threadIdx.x; i < COLS * R4; i += NT) {
+      const int cl = i / R4, r4 = (i % R4) * 4;
       const int64_t col = col0 + cl;
       const int64_t row = row_wg + r4;
       if (col >= npair) continue;
-      const float* src = outt + r4 * kOutStride + cl;
+      const float* src = tile + r4 * OS + cl;
       float* dst = Bout + col * ldb + row;
       if (vec_ok && row + 3 < col) {
-        *reinterpret_cast<float4*>(dst) =
-            make_float4(src[0], src[kOutStride], src[2 * kOutStride], src[3 * kOutStride]);
+        *reinterpret_cast<float4*>(dst) = make_float4(src[0], src[OS], src[2 * OS], src[3 * OS]);
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (row + e < col) dst[e] = src[e * kOutStride];
+          if (row + e < col) dst[e] = src[e * OS];
       }
     }
     __syncthreads();  // tile and sums space free for the next block
   }
 }
 
-template <int KC, int Q, bool BF>
-__global__ void __launch_bounds__(256, 1)
+// Two waves per SIMD: one work group of 8 (or 12) waves, or two of 4.
+template <class C, bool BF>
+__global__ void __launch_bounds__(C::NT, C::NW_ >= 8 ? 1 : 8 / C::NW_)
 assemble16_kernel(const AsmMol* __restrict__ mols, const int4* __restrict__ items, int nitems,
                   unsigned* __restrict__ counter) {
-  using C = Cfg16<KC, Q>;
   __shared__ uint4 yb0[C::NFRAG * 64];
   __shared__ uint4 yb1[C::NFRAG * 64];
-  __shared__ uint4 yb2[C::NBUF == 3 ? C::NFRAG * 64 : 1];
-  __shared__ double accs[C::ACC_BYTES / 8];  // FP64 sums; reused as the output tile
+  __shared__ uint4 yb2[C::NBUF_ == 3 ? C::NFRAG * 64 : 1];
+  __shared__ double sums[C::SCRATCH_BYTES / 8];  // FP64 sums; reused as the output tile
   __shared__ int item_s;
-  static_assert(C::ROWS * kOutStride * 4 <= C::ACC_BYTES, "output tile fits in the sums space");
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) item_s = (int)atomicAdd(counter, 1u);
@@ -319,39 +341,115 @@ assemble16_kernel(const AsmMol* __restrict__ mols, const int4* __restrict__ item
     if (it >= nitems) break;
     const int4 item = items[it];
     const AsmMol m = mols[item.x];
-    run_item<KC, Q, BF>(m, item.y, item.z, item.w, yb0, yb1, yb2, accs, reinterpret_cast<float*>(accs));
+    run_item<C, BF>(m, item.y, item.z, item.w, yb0, yb1, yb2, sums, reinterpret_cast<float*>(sums));
   }
 }
-
-template <int KC, int Q>
-hipError_t launch16(bool bf, const AsmMol* mols, const int4* items, int nitems, unsigned* counter, int nblocks,
-                    hipStream_t s) {
+template <class C>
+hipError_t launch_shape(bool bf, const AsmMol* mols, const int4* items, int nitems, unsigned* counter, int nblocks,
+                        hipStream_t s) {
   if (bf)
-    hipLaunchKernelGGL((assemble16_kernel<KC, Q, true>), dim3(nblocks), dim3(256), 0, s, mols, items, nitems, counter);
+    hipLaunchKernelGGL((assemble16_kernel<C, true>), dim3(nblocks), dim3(C::NT), 0, s, mols, items, nitems, counter);
   else
-    hipLaunchKernelGGL((assemble16_kernel<KC, Q, false>), dim3(nblocks), dim3(256), 0, s, mols, items, nitems, counter);
+    hipLaunchKernelGGL((assemble16_kernel<C, false>), dim3(nblocks), dim3(C::NT), 0, s, mols, items, nitems, counter);
   return hipGetLastError();
+}
+
+template <class C>
+int resident_wgs() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&assemble16_kernel<C, false>),
+                                                    C::NT, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+
+using LaunchFn = hipError_t (*)(bool, const AsmMol*, const int4*, int, unsigned*, int, hipStream_t);
+struct ShapeEntry {
+  int kc, q, nw, rb, cb, nbuf;
+  LaunchFn launch;
+  int (*occupancy)();
+};
+
+#define TAI_S16(KC, Q, NW, RB, CB, NBUF) \
+  {KC, Q, NW, RB, CB, NBUF, &launch_shape<Cfg16<KC, Q, NW, RB, CB, NBUF>>, &resident_wgs<Cfg16<KC, Q, NW, RB, CB, NBUF>>}
+
+// Per inner length (kc) and duplicated chunk count (q): the shapes that fit
+// the register file (A operand 12*RB*U VGPRs plus 12*RB*CB for the
+// accumulators) and the LDS, in order of preference.
+const ShapeEntry kShapes[] = {
+    TAI_S16(32, 0, 8, 4, 2, 3),   TAI_S16(32, 0, 8, 4, 1, 3),
+    TAI_S16(64, 0, 8, 4, 1, 3),   TAI_S16(64, 0, 8, 3, 2, 2),
+    TAI_S16(96, 0, 8, 4, 1, 3),   TAI_S16(96, 0, 8, 3, 2, 2),
+    TAI_S16(96, 1, 8, 4, 1, 3),   TAI_S16(96, 1, 8, 3, 2, 2),
+    TAI_S16(128, 0, 8, 2, 2, 3),  TAI_S16(128, 0, 8, 3, 1, 3),
+    TAI_S16(128, 1, 4, 4, 1, 3),  TAI_S16(128, 1, 8, 4, 1, 3),  TAI_S16(128, 1, 4, 4, 1, 2),
+    TAI_S16(128, 1, 4, 3, 1, 3),  TAI_S16(128, 1, 8, 2, 2, 3),  TAI_S16(128, 1, 4, 2, 2, 3),
+    TAI_S16(160, 0, 8, 2, 2, 3),  TAI_S16(160, 0, 8, 1, 2, 3),
+    TAI_S16(160, 1, 8, 2, 2, 3),  TAI_S16(160, 1, 8, 3, 1, 3),
+    TAI_S16(192, 0, 8, 2, 2, 2),  TAI_S16(192, 0, 8, 1, 2, 3),
+    TAI_S16(192, 1, 8, 2, 2, 2),  TAI_S16(192, 2, 8, 2, 2, 2),
+    TAI_S16(224, 0, 8, 1, 2, 2),  TAI_S16(256, 0, 8, 1, 2, 2),
+    TAI_S16(288, 0, 8, 1, 2, 2),  TAI_S16(320, 0, 8, 1, 2, 2),
+    TAI_S16(352, 0, 8, 1, 1, 2),
+};
+#undef TAI_S16
+
+Asm16Shape to_shape(int id) {
+  const ShapeEntry& e = kShapes[id];
+  Asm16Shape sh;
+  sh.id = id;
+  sh.waves = e.nw;
+  sh.rb = e.rb;
+  sh.cb = e.cb;
+  sh.nbuf = e.nbuf;
+  sh.rows = 16 * e.rb * e.nw;
+  sh.cols = 16 * e.cb;
+  sh.wgs_per_cu = 1;  // asm16_shape asks the runtime
+  sh.kc_key = e.kc;
+  sh.q_key = e.q;
+  return sh;
 }
 
 }  // namespace
 
 int asm16_max_kc() { return 352; }
 
-int asm16_rows_for(int kc, int q) {
-  const int u = kc / 32 - q;
-  return 64 * (u <= 3 ? 4 : (u <= 4 ? 3 : (u <= 6 ? 2 : 1)));
+int asm16_shapes(int kc, int q, Asm16Shape* out, int cap) {
+  int n = 0;
+  for (int i = 0; i < (int)(sizeof(kShapes) / sizeof(kShapes[0])); ++i)
+    if (kShapes[i].kc == kc && kShapes[i].q == q) {
+      if (n < cap) out[n] = to_shape(i);
+      ++n;
+    }
+  return n;
 }
 
-hipError_t launch_assemble16(int prec, int kc, int q, const AsmMol* mols_dev, const int4* items_dev, int nitems,
-                             unsigned* counter, int nblocks, hipStream_t s) {
-  const bool bf = prec != kF16X3;
-#define TAI_L16(KC_, Q_) \
-  if (kc == KC_ && q == Q_) return launch16<KC_, Q_>(bf, mols_dev, items_dev, nitems, counter, nblocks, s);
-  TAI_L16(32, 0) TAI_L16(64, 0) TAI_L16(96, 0) TAI_L16(96, 1) TAI_L16(128, 0) TAI_L16(128, 1)
-  TAI_L16(160, 0) TAI_L16(160, 1) TAI_L16(192, 0) TAI_L16(192, 1) TAI_L16(192, 2)
-  TAI_L16(224, 0) TAI_L16(256, 0) TAI_L16(288, 0) TAI_L16(320, 0) TAI_L16(352, 0)
-#undef TAI_L16
-  return hipErrorInvalidValue;
+Asm16Shape asm16_shape(int kc, int q) {
+  Asm16Shape c[8];
+  const int n = asm16_shapes(kc, q, c, 8);
+  if (n == 0) {
+    Asm16Shape none{};
+    none.id = -1;
+    return none;
+  }
+  int pick = 0;
+  if (const char* v = std::getenv("TAI_ASM16_SHAPE")) {
+    const int want = std::atoi(v);
+    if (want >= 0 && want < n && want < 8) pick = want;
+  }
+  Asm16Shape sh = c[pick];
+  sh.wgs_per_cu = kShapes[sh.id].occupancy();
+  return sh;
+}
+
+hipError_t launch_assemble16(int prec, int kc, int q, const Asm16Shape& shape, const AsmMol* mols_dev,
+                             const int4* items_dev, int nitems, unsigned* counter, int nblocks, hipStream_t s) {
+  if (shape.id < 0 || shape.id >= (int)(sizeof(kShapes) / sizeof(kShapes[0])) || kShapes[shape.id].kc != kc ||
+      kShapes[shape.id].q != q)
+    return hipErrorInvalidValue;
+  return kShapes[shape.id].launch(prec != kF16X3, mols_dev, items_dev, nitems, counter, nblocks, s);
 }
 
 }  // namespace tai

@@ -37,6 +37,7 @@ struct tai_ctx {
   Buf asm_host;           // pinned staging of the table
   hipEvent_t asm_host_done = nullptr;
   int cus = 0;            // compute units of the device
+  std::vector<tai::Asm16Shape> shapes16;  // 16-bit kernel shape per (kc, q), chosen once
   Buf jwork;              // apply_J intermediates
   // batched path
   Buf b_nodes, b_basis, b_opA, b_opEx, b_opY, b_mols, b_counter;
@@ -245,10 +246,23 @@ bool use16(int prec, int n) {
 // Padded operand row count: a multiple of the generic kernel's tile (64),
 // of the projection kernel's 256-row blocks and of the 16-bit kernel's
 // row panel.
-int prow_of(int prec, int n, int64_t npair) {
+// Shape of the 16-bit kernel for this arithmetic and degree (cached; the
+// device must be current).
+tai::Asm16Shape shape16(tai_ctx* c, int prec, int n) {
+  const int kc = tai::operand_kc(prec, n), q = tai::operand_dup_chunks(prec, n);
+  for (const auto& sh : c->shapes16)
+    if (sh.id >= 0 && sh.rb > 0 && sh.kc_key == kc && sh.q_key == q) return sh;
+  tai::Asm16Shape sh = tai::asm16_shape(kc, q);
+  sh.kc_key = kc;
+  sh.q_key = q;
+  c->shapes16.push_back(sh);
+  return sh;
+}
+
+int prow_of(tai_ctx* c, int prec, int n, int64_t npair) {
   int64_t t = 256;
   if (use16(prec, n)) {
-    const int64_t r = tai::asm16_rows_for(tai::operand_kc(prec, n), tai::operand_dup_chunks(prec, n));
+    const int64_t r = shape16(c, prec, n).rows;
     int64_t a = r, b = 256;
     while (b) {
       const int64_t tmp = a % b;
@@ -272,14 +286,17 @@ size_t opEx_bytes(int prow) { return align256(sizeof(int32_t) * 3 * (size_t)prow
 // R rows x ranges of up to kChunk 32-column blocks, restricted to blocks that
 // hold entries with col >= row; column-chunk-major so that concurrently
 // running work groups share the Y blocks.
-void build_items16(std::vector<int4>& out, int mol, int64_t npair, int64_t R) {
-  constexpr int64_t kChunk = 16;
-  const int64_t ncb = (npair + 31) / 32;
+// Work items of one molecule: (row panel of R rows) x (runs of up to 512
+// columns in blocks of C), upper triangle only, ordered column-run-major so
+// that work groups running together share the Y blocks in L2.
+void build_items16(std::vector<int4>& out, int mol, int64_t npair, int64_t R, int64_t C) {
+  const int64_t chunk = std::max<int64_t>(1, 512 / C);
+  const int64_t ncb = (npair + C - 1) / C;
   const int64_t nrp = (npair + R - 1) / R;
-  for (int64_t j = 0; j * kChunk < ncb; ++j)
+  for (int64_t j = 0; j * chunk < ncb; ++j)
     for (int64_t rp = 0; rp < nrp; ++rp) {
-      const int64_t lo = std::max(j * kChunk, rp * R / 32);
-      const int64_t hi = std::min((j + 1) * kChunk, ncb);
+      const int64_t lo = std::max(j * chunk, rp * R / C);
+      const int64_t hi = std::min((j + 1) * chunk, ncb);
       if (lo < hi) out.push_back(int4{mol, (int)rp, (int)lo, (int)hi});
     }
 }
@@ -424,7 +441,7 @@ int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params*
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int prec = p->prec, n = p->n, nq = p->nq;
-  const int prow = prow_of(prec, n, npair);
+  const int prow = prow_of(c, prec, n, npair);
   if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
   if ((r = ensure(c, c->opA, opA_bytes(prec, n, prow)))) return r;
   if ((r = ensure(c, c->opEx, opEx_bytes(prow)))) return r;
@@ -461,7 +478,8 @@ int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params*
   m.tile0 = 0;
   if (use16(prec, n)) {
     std::vector<int4> items;
-    build_items16(items, 0, npair, tai::asm16_rows_for(m.kc, tai::operand_dup_chunks(prec, n)));
+    const tai::Asm16Shape sh = shape16(c, prec, n);
+    build_items16(items, 0, npair, sh.rows, sh.cols);
     const size_t tab_bytes = align256(sizeof(tai::AsmMol)) + sizeof(int4) * items.size();
     if ((r = ensure(c, c->asm_tab, tab_bytes))) return r;
     if ((r = ensure(c, c->asm_counter, 256))) return r;
@@ -475,13 +493,13 @@ int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params*
     unsigned* counter = static_cast<unsigned*>(c->asm_counter.p);
     if ((e = tai::launch_reset_counter(counter, s)) != hipSuccess) return hip_fail(c, e, "reset kernel");
     const int nitems = (int)items.size();
-    const int nblocks = std::min(nitems, c->cus > 0 ? c->cus : 256);
+    const int nblocks = std::min(nitems, (c->cus > 0 ? c->cus : 256) * sh.wgs_per_cu);
     const auto* mols_dev = static_cast<const tai::AsmMol*>(c->asm_tab.p);
     const auto* items_dev = reinterpret_cast<const int4*>(static_cast<char*>(c->asm_tab.p) + align256(sizeof(tai::AsmMol)));
     {
       Timed tm(c, kStAssemble, s);
-      e = tai::launch_assemble16(prec, m.kc, tai::operand_dup_chunks(prec, n), mols_dev, items_dev, nitems, counter,
-                                 nblocks, s);
+      e = tai::launch_assemble16(prec, m.kc, tai::operand_dup_chunks(prec, n), sh, mols_dev, items_dev, nitems,
+                                 counter, nblocks, s);
     }
   } else {
     Timed tm(c, kStAssemble, s);
@@ -519,7 +537,7 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
   std::vector<tai::AsmMol> am(nmol);
   for (int i = 0; i < nmol; ++i) {
     const int64_t np = npair_of(mols[i].basis.nb);
-    prow[i] = prow_of(prec, n, np);
+    prow[i] = prow_of(c, prec, n, np);
     off_nodes[i] = sz_nodes; sz_nodes += align256(tai::node_tables_bytes(nq, n));
     off_basis[i] = sz_basis; sz_basis += basis_bytes(mols[i].basis.nb);
     off_A[i] = sz_A; sz_A += opA_bytes(prec, n, prow[i]);
@@ -551,11 +569,12 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
   // largest molecules first so the tail of the queue holds small items
   const bool split16 = use16(prec, n);
   std::vector<int4> items16;
+  const tai::Asm16Shape sh16 = split16 ? shape16(c, prec, n) : tai::Asm16Shape{};
   if (split16) {
     std::vector<int> order(nmol);
     for (int i = 0; i < nmol; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return am[a].npair > am[b].npair; });
-    for (int i : order) build_items16(items16, i, am[i].npair, tai::asm16_rows_for(am[i].kc, tai::operand_dup_chunks(prec, n)));
+    for (int i : order) build_items16(items16, i, am[i].npair, sh16.rows, sh16.cols);
   }
   const size_t tab_bytes = align256(sizeof(tai::AsmMol) * nmol) + sizeof(int4) * items16.size();
   if ((r = ensure(c, c->b_mols, tab_bytes))) return r;
@@ -598,9 +617,9 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
       const auto* items_dev = reinterpret_cast<const int4*>(static_cast<char*>(c->b_mols.p) +
                                                             align256(sizeof(tai::AsmMol) * nmol));
       const int ni = (int)items16.size();
-      const int blocks = std::min(ni, c->cus > 0 ? c->cus : 256);
-      return tai::launch_assemble16(prec, am[0].kc, tai::operand_dup_chunks(prec, n), mols_dev, items_dev, ni, counter,
-                                    blocks, st);
+      const int blocks = std::min(ni, (c->cus > 0 ? c->cus : 256) * sh16.wgs_per_cu);
+      return tai::launch_assemble16(prec, am[0].kc, tai::operand_dup_chunks(prec, n), sh16, mols_dev, items_dev, ni,
+                                    counter, blocks, st);
     }
     int blocks = tai::assemble_queue_blocks(prec, c->device);
     if (blocks > nitems) blocks = (int)nitems;

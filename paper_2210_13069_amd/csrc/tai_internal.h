@@ -104,12 +104,24 @@ hipError_t launch_reset_counter(unsigned* counter, hipStream_t s);
 int assemble_queue_blocks(int prec, int device);
 
 // 16-bit split arithmetics: A-stationary persistent kernel over work items
-// int4 {molecule, row panel, first column block, end column block}; row
-// panels are asm16_rows_per_block(kc) rows, column blocks 32 columns.
+// int4 {molecule, row panel, first column block, end column block}.  A shape
+// fixes the waves per work group, the row blocks (16 rows) per wave, the
+// column blocks (16 columns) per item block and the depth of the LDS ring;
+// rows = 16 * rb * waves per panel, cols = 16 * cb per column block.
+struct Asm16Shape {
+  int id;          // index into the shape table (-1: none fits)
+  int waves, rb, cb, nbuf;
+  int rows, cols;  // panel rows, block columns
+  int wgs_per_cu;  // resident work groups per CU (register / LDS bound)
+  int kc_key, q_key;  // the (kc, q) the shape was chosen for
+};
 int asm16_max_kc();
-int asm16_rows_for(int kc, int q);
-hipError_t launch_assemble16(int prec, int kc, int q, const AsmMol* mols_dev, const int4* items_dev, int nitems,
-                             unsigned* counter, int nblocks, hipStream_t s);
+// Shapes that compile for (kc, q), best first; `asm16_shape` picks the first
+// unless TAI_ASM16_SHAPE names another table index.
+int asm16_shapes(int kc, int q, Asm16Shape* out, int cap);
+Asm16Shape asm16_shape(int kc, int q);
+hipError_t launch_assemble16(int prec, int kc, int q, const Asm16Shape& shape, const AsmMol* mols_dev,
+                             const int4* items_dev, int nitems, unsigned* counter, int nblocks, hipStream_t s);
 inline bool is_split16(int prec) { return prec == kBF16X3 || prec == kBF16X6 || prec == kF16X3; }
 
 // ---- Coulomb matrix through the grid tensor --------------------------------
