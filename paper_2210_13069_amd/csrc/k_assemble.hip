@@ -571,9 +571,9 @@ int operand_kc(int prec, int n) {
   }
 }
 
-// rows of the operands are padded to this multiple (the 16-bit kernel's row
-// panels are up to 256 rows; the generic kernel's tiles are 64)
-int assemble_tile(int prec) { return (prec == kBF16X3 || prec == kBF16X6 || prec == kF16X3) ? 256 : 64; }
+// Edge of the generic kernel's square output tiles, for every arithmetic
+// (operand rows are padded further, to a multiple of 256, by the host).
+int assemble_tile(int) { return 64; }
 
 hipError_t launch_pack(int prec, const double* M, int n, int npair, int prow, void* A,
                        int32_t* ex, hipStream_t s) {

@@ -54,11 +54,9 @@ struct Cfg16 {
   static constexpr int LPW_LO = NFRAG / NW;              // loads of the others
   static constexpr int N_HI = NFRAG % NW == 0 ? NW : NFRAG % NW;
   static constexpr int NV = RB * CB * 4;                 // accumulator values per lane
-  static constexpr int OS = COLS + 1;                    // floats per output-tile row
   static constexpr int SUM_BYTES = NW * NV * 64 * 8;     // FP64 partial sums, all waves
-  static constexpr int TILE_BYTES = ROWS * OS * 4;
-  static constexpr int SCRATCH_BYTES = SUM_BYTES > TILE_BYTES ? SUM_BYTES : TILE_BYTES;
-  static constexpr int LDS_BYTES = NBUF * NFRAG * 1024 + SCRATCH_BYTES;
+  static constexpr int ITEM_COLS = COLS * (512 / COLS);  // columns of the longest item
+  static constexpr int LDS_BYTES = NBUF * NFRAG * 1024 + SUM_BYTES + 4 * (ROWS + ITEM_COLS);
   static_assert(NBUF == 2 || NBUF == 3, "ring depth");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
@@ -76,13 +74,13 @@ __device__ inline void wait_vmcnt() {
 __device__ inline v4f mma(v8h a, v8h b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 __device__ inline v4f mma(v8bf a, v8bf b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 
-// Direct-to-LDS loads of the Y fragments of one node.  Fragment
+// Direct-to-LDS loads of the Y fragments of one step.  Fragment
 // f = (d*CB + c)*NCH + ch holds, for lane l, the 16 bytes
 // Y[k][d][col0 + 16c + l%16][32ch + 8(l/16) .. +8].  Wave w loads fragments
 // w, w + NW, ... (LPW_HI of them for w < N_HI, else LPW_LO), the same count
-// for every node, so that a wave's wait can count its own loads.  The byte
-// offsets of a wave's fragments within a node are fixed for a column block
-// (yoff); the node base is a uniform pointer.
+// for every step, so that a wave's wait can count its own loads.  The byte
+// offsets of a wave's fragments are fixed for an item (off); a step's
+// (node, column block) only moves the uniform base pointer.
 template <class C>
 struct YLoads {
   uint32_t off[C::LPW_HI];
@@ -98,23 +96,22 @@ struct YLoads {
       off[i] = (uint32_t)((((int64_t)d * prow + col0 + 16 * c + r16) * C::KC_ + 32 * ch + 8 * kg) * 2);
     }
   }
-  __device__ void issue(const char* __restrict__ Y, int64_t prow, int k, uint4* buf, int wave) const {
-    const char* node = Y + (int64_t)k * 3 * prow * C::KC_ * 2;
+  __device__ void issue(const char* base, uint4* buf, int wave) const {
 #pragma unroll
     for (int i = 0; i < C::LPW_HI; ++i) {
       const int f = wave + C::NW_ * i;
       if (f < C::NFRAG)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(node + off[i]), (lds_ptr_t)(buf + f * 64),
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(base + off[i]), (lds_ptr_t)(buf + f * 64),
                                          16, 0, 0);
     }
   }
 };
 
-// Wait until this wave's loads of node k have landed.  Loads complete in
-// issue order, so with node k+1's loads already issued (ring of 3) it is
-// enough to allow this wave's per-node count to remain outstanding.
+// Wait until this wave's loads of the current step have landed.  Loads
+// complete in issue order, so with the next step's loads already issued
+// (ring of 3) it is enough to leave this wave's per-step count outstanding.
 template <class C>
-__device__ inline void wait_node(bool next_issued, int wave) {
+__device__ inline void wait_step(bool next_issued, int wave) {
   if constexpr (C::NBUF_ == 3) {
     if (next_issued) {
       if (wave < C::N_HI) wait_vmcnt<C::LPW_HI>();
@@ -125,24 +122,15 @@ __device__ inline void wait_node(bool next_issued, int wave) {
   wait_vmcnt<0>();
 }
 
-// One node k of a column block: wait for its Y fragments (buffer cur),
-// issue the loads of node k + NBUF - 1 into buffer nxt, and accumulate
-// w_k G_0 o G_1 o G_2 (w_k is folded into Y of direction 2).
+// The MFMA work of one node on one column block: the three G_d tiles from
+// the A fragments in registers and the Y fragments in buffer cur, then
+// acc += G_0 o G_1 o G_2 (w_k is folded into Y of direction 2).
 template <class C, bool BF>
-__device__ inline void node_step(int k, int nq, int64_t prow, const YLoads<C>& yl, const char* __restrict__ Yb,
-                                 const uint4* cur, uint4* nxt,
+__device__ inline void node_mfma(const uint4* cur,
                                  const typename std::conditional<BF, v8bf, v8h>::type (&af)[3][C::RB_][C::U],
-                                 v4f (&acc)[C::RB_][C::CB_], int wave, int lane) {
+                                 v4f (&acc)[C::RB_][C::CB_], int lane) {
   using Frag = typename std::conditional<BF, v8bf, v8h>::type;
   constexpr int RB = C::RB_, CB = C::CB_, NCH = C::NCH;
-  // Every wave waits for its own loads of node k, then all waves meet: node
-  // k is in LDS for everyone and every wave has consumed node k-1, whose
-  // buffer the loads below reuse.  A plain s_barrier (memory clobber for the
-  // compiler) instead of __syncthreads, whose fence would also drain the
-  // loads still in flight.
-  wait_node<C>(k + 1 < nq, wave);
-  __asm__ volatile("s_barrier" ::: "memory");
-  if (k + C::NBUF_ - 1 < nq) yl.issue(Yb, prow, k + C::NBUF_ - 1, nxt, wave);
   v4f H[RB][CB];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -170,12 +158,18 @@ __device__ inline void node_step(int k, int nq, int64_t prow, const YLoads<C>& y
   }
 }
 
+// One work item: the rows of panel rp against column blocks [cb0, cb1).
+// The steps (column block, node) run as one stream through the LDS ring, so
+// the loads of the next block start while the current one finishes.  Each
+// wave owns its rows: FP32 sums over kGroup16 nodes are added into its FP64
+// partial sums in LDS, and a finished block leaves straight from registers
+// (rows for row <= col, the mirror for row < col) without a work-group barrier.
 template <class C, bool BF>
 __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4* yb0, uint4* yb1, uint4* yb2,
-                                double* sums, float* tile) {
+                                double* sums, int* erow_s, int* ecol_s) {
   using Frag = typename std::conditional<BF, v8bf, v8h>::type;
-  constexpr int RB = C::RB_, CB = C::CB_, NCH = C::NCH, U = C::U, NBUF = C::NBUF_;
-  constexpr int ROWS = C::ROWS, COLS = C::COLS, OS = C::OS, NT = C::NT, NV = C::NV;
+  constexpr int RB = C::RB_, CB = C::CB_, U = C::U, NBUF = C::NBUF_;
+  constexpr int ROWS = C::ROWS, COLS = C::COLS, NT = C::NT, NV = C::NV;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
@@ -190,6 +184,20 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
   float* __restrict__ Bout = static_cast<float*>(m.B);
   const bool vec_ok = ((ldb & 3) == 0) && ((reinterpret_cast<uintptr_t>(Bout) & 15) == 0);
   double* mysum = sums + wave * NV * 64 + lane;   // value v at mysum[v * 64]
+  const int nblk = cb1 - cb0;
+  const int64_t col_first = (int64_t)cb0 * COLS;
+
+  // summed power-of-two exponents of the panel's rows and the item's columns
+  for (int i = threadIdx.x; i < ROWS; i += NT) {
+    const int64_t row = row_wg + i;
+    erow_s[i] = m.ex[row] + m.ex[prow + row] + m.ex[2 * prow + row];
+  }
+  for (int i = threadIdx.x; i < nblk * COLS; i += NT) {
+    const int64_t col = col_first + i;
+    ecol_s[i] = m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) mysum[v * 64] = 0.0;
 
   // k-invariant A operand of this wave's rows, all directions
   Frag af[3][RB][U];
@@ -202,124 +210,142 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
         const int64_t row = (int64_t)d * prow + row_base + 16 * rb + r16;
         af[d][rb][u] = *(const __attribute__((address_space(1))) Frag*)(Ab + (row * C::KC_ + 32 * a_chunk<C::Q_>(u) + 8 * kg) * 2);
       }
+  __syncthreads();  // exponent tables written
 
-  for (int cb = cb0; cb < cb1; ++cb) {
-    const int64_t col0 = (int64_t)cb * COLS;
-    // prologue: the first NBUF-1 nodes
-    YLoads<C> yl;
-    yl.init(prow, col0, wave, lane);
-    yl.issue(Yb, prow, 0, yb0, wave);
-    if (NBUF == 3 && nq > 1) yl.issue(Yb, prow, 1, yb1, wave);
+  // step t = (block t / nq, node t % nq); its Y base pointer
+  const int64_t node_bytes = 3 * prow * C::KC_ * 2;
+  const int64_t block_bytes = (int64_t)COLS * C::KC_ * 2;
+  const int T = nblk * nq;
+  YLoads<C> yl;
+  yl.init(prow, col_first, wave, lane);
+  int ib = 0, ik = 0;  // (block, node) of the next step to load
+  auto issue_next = [&](uint4* buf) {
+    yl.issue(Yb + ik * node_bytes + ib * block_bytes, buf, wave);
+    if (++ik == nq) {
+      ik = 0;
+      ++ib;
+    }
+  };
+  issue_next(yb0);
+  if (NBUF == 3) issue_next(yb1);
+
+  v4f acc[RB][CB];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) mysum[v * 64] = 0.0;
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[rb][c] = v4f{0.f, 0.f, 0.f, 0.f};
+  int k = 0, blk = 0;  // (block, node) of the current step
 
-    v4f acc[RB][CB];
+  // Output addressing: a uniform base per (row block, column block) plus
+  // 32-bit per-lane byte offsets, and 32-bit row/column tests relative to
+  // the block, so that nothing 64-bit per lane stays live across the node
+  // loop.  Stores go through the global address space (a generic pointer
+  // could alias LDS and would make the compiler drain the Y loads).
+  typedef __attribute__((address_space(1))) float gfloat;
+  typedef __attribute__((address_space(1))) v4f gv4f;
+  typedef __attribute__((address_space(1))) char gchar;
+  gchar* Bbytes = (gchar*)Bout;
+  const uint32_t ldb4 = (uint32_t)ldb * 4u;
+  const int npair32 = (int)npair;
+  auto finish_block = [&](int fb) {
+    const int64_t col0 = col_first + (int64_t)fb * COLS;
+    int ecol[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) ecol[c] = ecol_s[fb * COLS + 16 * c + r16];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int rl0 = wave * 16 * RB + 16 * rb + 4 * kg;
+      const int4 er = *reinterpret_cast<const int4*>(erow_s + rl0);
+      const int erow[4] = {er.x, er.y, er.z, er.w};
+      const int64_t rowu = row_wg + wave * 16 * RB + 16 * rb;  // uniform first row of the block
+      const int row0 = 4 * kg;                                 // this lane's first row, relative
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int64_t colu = col0 + 16 * c;                    // uniform first column
+        const int dc = (int)(colu - rowu) + r16;               // col - rowu for this lane
+        float val[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int v = (rb * CB + c) * 4 + r;
+          val[r] = (float)ldexp(mysum[v * 64] * kTwoOverSqrtPi, erow[r] + ecol[c]);
+          mysum[v * 64] = 0.0;
+        }
+        if ((int)colu + r16 < npair32) {
+          // rows: B[row][col] for row <= col
+          gchar* rbase = Bbytes + (rowu * ldb + colu) * 4;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (row0 + r <= dc) *(gfloat*)(rbase + ((uint32_t)(row0 + r) * ldb4 + (uint32_t)r16 * 4u)) = val[r];
+          // mirror: B[col][row .. row+3] for row < col
+          gchar* mbase = Bbytes + (colu * ldb + rowu) * 4;
+          gfloat* dst = (gfloat*)(mbase + ((uint32_t)r16 * ldb4 + (uint32_t)row0 * 4u));
+          if (vec_ok && row0 + 3 < dc) {
+            *(gv4f*)dst = v4f{val[0], val[1], val[2], val[3]};
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (row0 + r < dc) dst[r] = val[r];
+          }
+        }
+      }
+    }
+  };
+
+  auto flush = [&]() {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mysum[((rb * CB + c) * 4 + r) * 64] += (double)acc[rb][c][r];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int c = 0; c < CB; ++c) acc[rb][c] = v4f{0.f, 0.f, 0.f, 0.f};
-    auto flush = [&](int k) {
-      if ((k + 1) % kGroup16 == 0 || k + 1 == nq) {
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-          for (int c = 0; c < CB; ++c)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int v = (rb * CB + c) * 4 + r;
-              mysum[v * 64] += (double)acc[rb][c][r];
-            }
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-          for (int c = 0; c < CB; ++c) acc[rb][c] = v4f{0.f, 0.f, 0.f, 0.f};
-      }
-    };
+  };
 
-    if constexpr (NBUF == 3) {
-      for (int k = 0; k < nq; k += 3) {
-        node_step<C, BF>(k, nq, prow, yl, Yb, yb0, yb2, af, acc, wave, lane);
-        flush(k);
-        if (k + 1 < nq) {
-          node_step<C, BF>(k + 1, nq, prow, yl, Yb, yb1, yb0, af, acc, wave, lane);
-          flush(k + 1);
-        }
-        if (k + 2 < nq) {
-          node_step<C, BF>(k + 2, nq, prow, yl, Yb, yb2, yb1, af, acc, wave, lane);
-          flush(k + 2);
-        }
-      }
-    } else {
-      for (int k = 0; k < nq; k += 2) {
-        node_step<C, BF>(k, nq, prow, yl, Yb, yb0, yb1, af, acc, wave, lane);
-        flush(k);
-        if (k + 1 < nq) {
-          node_step<C, BF>(k + 1, nq, prow, yl, Yb, yb1, yb0, af, acc, wave, lane);
-          flush(k + 1);
-        }
-      }
+  // With nq >= NBUF (the host routes smaller nq to the generic kernel) a
+  // block ends at most once per group of NBUF steps, and the next block's
+  // first flush comes more than NBUF-1 steps later, so the finished block's
+  // sums can wait for the end of the group.
+  int done = -1;  // block finished within the current group
+  auto step = [&](int t, const uint4* cur, uint4* nxt) {
+    // Every wave waits for its own loads of step t, then all waves meet:
+    // step t is in LDS for everyone and every wave has consumed step t-1,
+    // whose buffer the loads below reuse.  A plain s_barrier (memory clobber
+    // for the compiler) instead of __syncthreads, whose fence would also
+    // drain the loads still in flight.
+    wait_step<C>(t + 1 < T, wave);
+    __asm__ volatile("s_barrier" ::: "memory");
+    if (t + NBUF - 1 < T) issue_next(nxt);
+    node_mfma<C, BF>(cur, af, acc, lane);
+    if ((k + 1) % kGroup16 == 0 || k + 1 == nq) flush();
+    if (++k == nq) {
+      done = blk;
+      k = 0;
+      ++blk;
     }
+  };
 
-    // finished block: FP64 sums -> scaled floats in the output tile
-    double fin[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) fin[v] = mysum[v * 64];
-    __syncthreads();  // every wave has read its sums before the tile reuses the space
-    int ecol[CB];
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      const int64_t col = col0 + 16 * c + r16;
-      ecol[c] = m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col];
-    }
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rl = wave * 16 * RB + 16 * rb + 4 * kg + r;
-        const int64_t row = row_wg + rl;
-        const int erow = m.ex[row] + m.ex[prow + row] + m.ex[2 * prow + row];
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-          const int v = (rb * CB + c) * 4 + r;
-          tile[rl * OS + 16 * c + r16] = (float)ldexp(fin[v] * kTwoOverSqrtPi, erow + ecol[c]);
-        }
-      }
-    __syncthreads();
-
-    // rows: B[row][col0 .. col0+COLS) for row <= col
-    constexpr int Q4 = COLS / 4;
-    for (int i = threadIdx.x; i < ROWS * Q4; i += NT) {
-      const int rl = i / Q4, c4 = (i % Q4) * 4;
-      const int64_t row = row_wg + rl;
-      const int64_t col = col0 + c4;
-      const float* src = tile + rl * OS + c4;
-      float* dst = Bout + row * ldb + col;
-      if (vec_ok && row <= col && col + 3 < npair) {
-        *reinterpret_cast<float4*>(dst) = make_float4(src[0], src[1], src[2], src[3]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (row <= col + e && col + e < npair) dst[e] = src[e];
+  if constexpr (NBUF == 3) {
+    for (int t = 0; t < T; t += 3) {
+      step(t, yb0, yb2);
+      if (t + 1 < T) step(t + 1, yb1, yb0);
+      if (t + 2 < T) step(t + 2, yb2, yb1);
+      if (done >= 0) {
+        finish_block(done);
+        done = -1;
       }
     }
-    // mirrored columns: B[col][row .. row+3] for row < col
-    constexpr int R4 = ROWS / 4;
-    for (int i = threadIdx.x; i < COLS * R4; i += NT) {
-      const int cl = i / R4, r4 = (i % R4) * 4;
-      const int64_t col = col0 + cl;
-      const int64_t row = row_wg + r4;
-      if (col >= npair) continue;
-      const float* src = tile + r4 * OS + cl;
-      float* dst = Bout + col * ldb + row;
-      if (vec_ok && row + 3 < col) {
-        *reinterpret_cast<float4*>(dst) = make_float4(src[0], src[OS], src[2 * OS], src[3 * OS]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (row + e < col) dst[e] = src[e * OS];
+  } else {
+    for (int t = 0; t < T; t += 2) {
+      step(t, yb0, yb1);
+      if (t + 1 < T) step(t + 1, yb1, yb0);
+      if (done >= 0) {
+        finish_block(done);
+        done = -1;
       }
     }
-    __syncthreads();  // tile and sums space free for the next block
   }
 }
 
@@ -331,19 +357,22 @@ assemble16_kernel(const AsmMol* __restrict__ mols, const int4* __restrict__ item
   __shared__ uint4 yb0[C::NFRAG * 64];
   __shared__ uint4 yb1[C::NFRAG * 64];
   __shared__ uint4 yb2[C::NBUF_ == 3 ? C::NFRAG * 64 : 1];
-  __shared__ double sums[C::SCRATCH_BYTES / 8];  // FP64 sums; reused as the output tile
+  __shared__ double sums[C::SUM_BYTES / 8];
+  __shared__ int erow_s[C::ROWS];
+  __shared__ int ecol_s[C::ITEM_COLS];
   __shared__ int item_s;
   for (;;) {
-    __syncthreads();
+    __syncthreads();  // the previous item is done with every LDS buffer
     if (threadIdx.x == 0) item_s = (int)atomicAdd(counter, 1u);
     __syncthreads();
     const int it = item_s;
     if (it >= nitems) break;
     const int4 item = items[it];
     const AsmMol m = mols[item.x];
-    run_item<C, BF>(m, item.y, item.z, item.w, yb0, yb1, yb2, sums, reinterpret_cast<float*>(sums));
+    run_item<C, BF>(m, item.y, item.z, item.w, yb0, yb1, yb2, sums, erow_s, ecol_s);
   }
 }
+
 template <class C>
 hipError_t launch_shape(bool bf, const AsmMol* mols, const int4* items, int nitems, unsigned* counter, int nblocks,
                         hipStream_t s) {

@@ -238,10 +238,6 @@ tai::DevBasis dev_basis_view(const tai_basis* b, char* dev) {
 }
 
 // True when the 16-bit A-stationary kernel assembles this (prec, n).
-bool use16(int prec, int n) {
-  return tai::is_split16(prec) && tai::operand_kc(prec, n) <= tai::asm16_max_kc() &&
-         !std::getenv("TAI_ASM16_GENERIC");
-}
 
 // Padded operand row count: a multiple of the generic kernel's tile (64),
 // of the projection kernel's 256-row blocks and of the 16-bit kernel's
@@ -259,9 +255,19 @@ tai::Asm16Shape shape16(tai_ctx* c, int prec, int n) {
   return sh;
 }
 
-int prow_of(tai_ctx* c, int prec, int n, int64_t npair) {
+// Whether the 16-bit persistent kernel takes this call: a split 16-bit
+// arithmetic whose inner length it supports, and at least as many nodes as
+// the depth of its LDS ring (fewer go to the generic kernel).
+bool use16(tai_ctx* c, int prec, int n, int nq) {
+  if (!tai::is_split16(prec) || tai::operand_kc(prec, n) > tai::asm16_max_kc() || std::getenv("TAI_ASM16_GENERIC"))
+    return false;
+  const tai::Asm16Shape sh = shape16(c, prec, n);
+  return sh.id >= 0 && nq >= sh.nbuf;
+}
+
+int prow_of(tai_ctx* c, int prec, int n, int nq, int64_t npair) {
   int64_t t = 256;
-  if (use16(prec, n)) {
+  if (use16(c, prec, n, nq)) {
     const int64_t r = shape16(c, prec, n).rows;
     int64_t a = r, b = 256;
     while (b) {
@@ -441,7 +447,7 @@ int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params*
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int prec = p->prec, n = p->n, nq = p->nq;
-  const int prow = prow_of(c, prec, n, npair);
+  const int prow = prow_of(c, prec, n, nq, npair);
   if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
   if ((r = ensure(c, c->opA, opA_bytes(prec, n, prow)))) return r;
   if ((r = ensure(c, c->opEx, opEx_bytes(prow)))) return r;
@@ -476,7 +482,7 @@ int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params*
   m.kc = tai::operand_kc(prec, n);
   m.tiles = prow / tai::assemble_tile(prec);
   m.tile0 = 0;
-  if (use16(prec, n)) {
+  if (use16(c, prec, n, nq)) {
     std::vector<int4> items;
     const tai::Asm16Shape sh = shape16(c, prec, n);
     build_items16(items, 0, npair, sh.rows, sh.cols);
@@ -537,7 +543,7 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
   std::vector<tai::AsmMol> am(nmol);
   for (int i = 0; i < nmol; ++i) {
     const int64_t np = npair_of(mols[i].basis.nb);
-    prow[i] = prow_of(c, prec, n, np);
+    prow[i] = prow_of(c, prec, n, nq, np);
     off_nodes[i] = sz_nodes; sz_nodes += align256(tai::node_tables_bytes(nq, n));
     off_basis[i] = sz_basis; sz_basis += basis_bytes(mols[i].basis.nb);
     off_A[i] = sz_A; sz_A += opA_bytes(prec, n, prow[i]);
@@ -567,7 +573,7 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
   }
   // the 16-bit kernel drains (molecule, row panel, column range) items,
   // largest molecules first so the tail of the queue holds small items
-  const bool split16 = use16(prec, n);
+  const bool split16 = use16(c, prec, n, nq);
   std::vector<int4> items16;
   const tai::Asm16Shape sh16 = split16 ? shape16(c, prec, n) : tai::Asm16Shape{};
   if (split16) {

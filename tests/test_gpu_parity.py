@@ -102,6 +102,22 @@ def test_assemble_B_small(tai, prec, case):
     assert _normwise(Bg, Bg.T) <= (1e-14 if prec == 0 else tol)
 
 
+@pytest.mark.parametrize("nq", [1, 2, 3, 4, 5, 7, 8, 9, 17])
+def test_assemble_16bit_node_counts(tai, nq):
+    """Split 16-bit forms at node counts around the LDS ring depth (fewer
+    than three nodes take the generic kernel) and around the FP32 group of
+    eight, with column blocks ending anywhere within a group of steps."""
+    b = I.small_random(41, natoms=6, shells=("s", "p"), box=3.0)   # nb = 24, npair = 300
+    P = I.Params(omega=0.6, nq=nq, n=24, L=8.0)
+    Mr, K, w = _oracle(b, P)
+    Br = T.B_full(Mr, K, w)
+    Mg = tai.moments(b, P)
+    for prec in (4, 2):
+        Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+        assert _normwise(Bg, Br) <= LOWP_TOL[prec], (nq, prec)
+        assert np.array_equal(Bg, Bg.T) or _normwise(Bg, Bg.T) <= LOWP_TOL[prec]
+
+
 def test_assemble_ldb_and_ragged_tail(tai):
     import torch
     b = I.small_random(31, natoms=4, shells=("s", "p"), box=2.5)   # nb = 16, npair = 136 (ragged)
