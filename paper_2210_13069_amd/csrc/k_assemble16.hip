@@ -130,31 +130,38 @@ __device__ inline void node_mfma(const uint4* cur,
                                  const typename std::conditional<BF, v8bf, v8h>::type (&af)[3][C::RB_][C::U],
                                  v4f (&acc)[C::RB_][C::CB_], int lane) {
   using Frag = typename std::conditional<BF, v8bf, v8h>::type;
-  constexpr int RB = C::RB_, CB = C::CB_, NCH = C::NCH;
-  v4f H[RB][CB];
+  constexpr int RB = C::RB_, CB = C::CB_, NCH = C::NCH, NF = 3 * NCH;
+  // The Y fragments are read one chunk ahead of the MFMAs that use them
+  // (two register sets), so the LDS latency hides behind the RB*CB MFMAs
+  // of the current chunk.
+  Frag bf[2][CB];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    v4f G[RB][CB];
+  for (int c = 0; c < CB; ++c) bf[0][c] = *reinterpret_cast<const Frag*>(cur + (c * NCH) * 64 + lane);
+  v4f H[RB][CB], G[RB][CB];
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-      Frag bfr[CB];
+  for (int f = 0; f < NF; ++f) {
+    const int d = f / NCH, ch = f % NCH;
+    if (f + 1 < NF) {
+      const int d1 = (f + 1) / NCH, ch1 = (f + 1) % NCH;
 #pragma unroll
       for (int c = 0; c < CB; ++c)
-        bfr[c] = *reinterpret_cast<const Frag*>(cur + ((d * CB + c) * NCH + ch) * 64 + lane);
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int c = 0; c < CB; ++c)
-          G[rb][c] = mma(af[d][rb][a_slot<C::Q_>(ch)], bfr[c], ch == 0 ? v4f{0.f, 0.f, 0.f, 0.f} : G[rb][c]);
+        bf[(f + 1) & 1][c] = *reinterpret_cast<const Frag*>(cur + ((d1 * CB + c) * NCH + ch1) * 64 + lane);
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        if (d == 0) H[rb][c] = G[rb][c];
-        else if (d == 1) H[rb][c] *= G[rb][c];
-        else acc[rb][c] += H[rb][c] * G[rb][c];
-      }
+      for (int c = 0; c < CB; ++c)
+        G[rb][c] = mma(af[d][rb][a_slot<C::Q_>(ch)], bf[f & 1][c], ch == 0 ? v4f{0.f, 0.f, 0.f, 0.f} : G[rb][c]);
+    if (ch == NCH - 1) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          if (d == 0) H[rb][c] = G[rb][c];
+          else if (d == 1) H[rb][c] *= G[rb][c];
+          else acc[rb][c] += H[rb][c] * G[rb][c];
+        }
+    }
   }
 }
 
