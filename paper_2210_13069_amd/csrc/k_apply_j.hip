@@ -7,9 +7,17 @@
 //   J_p        = sum_a m_{p,0}(a0) m_{p,1}(a1) m_{p,2}(a2) Phi(a)
 //   J(mu,nu)   = J(nu,mu) = J_p,                           p = (mu,nu)
 //
-// rho is a split-K contraction over pairs: each work group owns one a0 and
-// one chunk of pairs and writes an n x n partial; the partials are summed in
-// a fixed order, so the result does not depend on scheduling.
+// Both pair contractions run on the FP64 matrix cores (v_mfma_f64_16x16x4):
+//  * rho: for each a0, rho_a0 = (c_a0 o M_1) M_2^T with c_a0(q) = Dt_q m_{q,0}(a0),
+//    an n x n product over the pairs.  A work group owns 8*A0W values of a0
+//    and one chunk of pairs, stages the chunk's moments in LDS 64 pairs at a
+//    time (loads for the next batch in flight during the MFMAs) and writes an
+//    n^3 partial; the partials are summed in a fixed order, so the result does
+//    not depend on scheduling.
+//  * J_p: for a tile of 16 pairs, X(a0, a1, p) = sum_a2 Phi(a0, a1, a2) m_{p,2}(a2)
+//    is an MFMA product with Phi staged in LDS one a0 slab at a time; the
+//    output fragment is contracted at once with m_{p,1} (in registers) and
+//    m_{p,0}, so X is never stored.
 #include "tai_internal.h"
 #include "tai_device.h"
 
@@ -17,8 +25,6 @@ namespace tai {
 namespace {
 
 constexpr double kTwoOverSqrtPi = 1.1283791670955126;
-constexpr int kQB = 32;          // pairs staged per LDS batch in the rho kernel
-constexpr int kRhoBlocks = 2048; // target work groups of the rho kernel
 
 __global__ void __launch_bounds__(256)
 density_pairs_kernel(const double* __restrict__ D, int nb, int64_t npair, double* __restrict__ Dt) {
@@ -29,66 +35,124 @@ density_pairs_kernel(const double* __restrict__ D, int nb, int64_t npair, double
   Dt[p] = D[(int64_t)mu * nb + nu] * (mu == nu ? 1.0 : 2.0);
 }
 
-// grid (n, nchunk); 256 threads as 16 x 16, each an MT x MT micro-tile of
-// (a1, a2) = (ty + 16 i, tx + 16 j).
-template <int MT>
-__global__ void __launch_bounds__(256)
-rho_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int n, int64_t npair,
-           int64_t chunk, double* __restrict__ part) {
-  constexpr int NM = 16 * MT;
-  __shared__ double c_s[kQB];
-  __shared__ double m1_s[kQB][NM];
-  __shared__ double m2_s[kQB][NM];
-  const int a0 = blockIdx.x;
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kKB = 64;          // pairs per LDS batch of the rho kernel
+constexpr int kRhoGroups = 512;  // target work groups of the rho kernel
+
+__device__ inline v4d mfma64(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// grid (ceil(n / (8*A0W)), nchunk), 512 threads.  Wave w owns
+// a0 = blockIdx.x*8*A0W + w*A0W + {0..A0W-1} and all (a1, a2) in NT x NT
+// output tiles of 16 x 16 (n padded to 16*NT with zeros).
+template <int NT, int A0W>
+__global__ void __launch_bounds__(512, 1)
+rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int n, int64_t npair,
+                int64_t chunk, double* __restrict__ part) {
+  constexpr int NP = 16 * NT;                  // padded extent of a1 and a2
+  constexpr int A0G = 8 * A0W;                 // a0 per work group
+  constexpr int ROWS = A0G + 2 * NP;           // staged rows: c (A0G), m1 (NP), m2 (NP)
+  constexpr int PER = ROWS * kKB / 512;        // staged values per thread
+  constexpr int CS = A0G + 1, MS = NP + 1;     // LDS row strides (doubles)
+  __shared__ double s_c[kKB * CS];
+  __shared__ double s_m1[kKB * MS];
+  __shared__ double s_m2[kKB * MS];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int a0base = blockIdx.x * A0G;
   const int64_t q0 = (int64_t)blockIdx.y * chunk;
   const int64_t q1 = (q0 + chunk < npair) ? q0 + chunk : npair;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const double* M0 = M;
   const double* M1 = M + (int64_t)n * npair;
   const double* M2 = M + 2 * (int64_t)n * npair;
-  double acc[MT][MT];
-#pragma unroll
-  for (int i = 0; i < MT; ++i)
-#pragma unroll
-    for (int j = 0; j < MT; ++j) acc[i][j] = 0.0;
 
-  for (int64_t qb = q0; qb < q1; qb += kQB) {
+  // staged value e = threadIdx.x + 512 i of a batch: row e / kKB, pair e % kKB
+  double pre[PER];
+  auto load = [&](int64_t qb) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 512 * i;
+      const int row = e / kKB;
+      const int64_t q = qb + (e % kKB);
+      double v = 0.0;
+      if (q < q1) {
+        if (row < A0G) {
+          const int a0 = a0base + row;
+          if (a0 < n) v = Dt[q] * M0[(int64_t)a0 * npair + q];
+        } else if (row < A0G + NP) {
+          const int a = row - A0G;
+          if (a < n) v = M1[(int64_t)a * npair + q];
+        } else {
+          const int a = row - A0G - NP;
+          if (a < n) v = M2[(int64_t)a * npair + q];
+        }
+      }
+      pre[i] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 512 * i;
+      const int row = e / kKB, qq = e % kKB;
+      if (row < A0G) s_c[qq * CS + row] = pre[i];
+      else if (row < A0G + NP) s_m1[qq * MS + row - A0G] = pre[i];
+      else s_m2[qq * MS + row - A0G - NP] = pre[i];
+    }
+  };
+
+  v4d acc[A0W][NT][NT];
+#pragma unroll
+  for (int a = 0; a < A0W; ++a)
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[a][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  load(q0);
+  for (int64_t qb = q0; qb < q1; qb += kKB) {
+    __syncthreads();  // the previous batch is consumed
+    store();
     __syncthreads();
-    // stage: thread t loads column (t % kQB) for rows a = t / kQB + 8 r
-    {
-      const int qq = threadIdx.x % kQB;
-      const int64_t q = qb + qq;
-      const bool ok = q < q1;
-      if (threadIdx.x < kQB) c_s[qq] = ok ? Dt[q] * M0[(int64_t)a0 * npair + q] : 0.0;
-      for (int a = threadIdx.x / kQB; a < NM; a += 256 / kQB) {
-        const bool in = ok && a < n;
-        m1_s[qq][a] = in ? M1[(int64_t)a * npair + q] : 0.0;
-        m2_s[qq][a] = in ? M2[(int64_t)a * npair + q] : 0.0;
+    if (qb + kKB < q1) load(qb + kKB);  // next batch in flight during the MFMAs
+#pragma unroll 2
+    for (int st = 0; st < kKB / 4; ++st) {
+      const int kk = 4 * st + kg;  // this lane's pair within the batch
+      double bm[NT], am[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) bm[j] = s_m2[kk * MS + 16 * j + r16];
+#pragma unroll
+      for (int i = 0; i < NT; ++i) am[i] = s_m1[kk * MS + 16 * i + r16];
+#pragma unroll
+      for (int a = 0; a < A0W; ++a) {
+        const double cq = s_c[kk * CS + wave * A0W + a];
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+          const double av = cq * am[i];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) acc[a][i][j] = mfma64(av, bm[j], acc[a][i][j]);
+        }
       }
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int qq = 0; qq < kQB; ++qq) {
-      const double cq = c_s[qq];
-      double x[MT], y[MT];
-#pragma unroll
-      for (int i = 0; i < MT; ++i) x[i] = cq * m1_s[qq][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < MT; ++j) y[j] = m2_s[qq][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int j = 0; j < MT; ++j) acc[i][j] += x[i] * y[j];
-    }
   }
-  double* out = part + ((int64_t)blockIdx.y * n + a0) * n * n;
+
+  // lane l holds column a2 = 16 j + l%16 and rows a1 = 16 i + l/16 + 4 r
+  const int64_t n2 = (int64_t)n * n;
 #pragma unroll
-  for (int i = 0; i < MT; ++i)
+  for (int a = 0; a < A0W; ++a) {
+    const int a0 = a0base + wave * A0W + a;
+    if (a0 >= n) continue;
+    double* out = part + ((int64_t)blockIdx.y * n + a0) * n2;
 #pragma unroll
-    for (int j = 0; j < MT; ++j) {
-      const int a1 = ty + 16 * i, a2 = tx + 16 * j;
-      if (a1 < n && a2 < n) out[a1 * n + a2] = acc[i][j];
-    }
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a1 = 16 * i + kg + 4 * r, a2 = 16 * j + r16;
+          if (a1 < n && a2 < n) out[a1 * n + a2] = acc[a][i][j][r];
+        }
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -134,36 +198,110 @@ phi_kernel(const double* __restrict__ T3, const double* __restrict__ w, int nq, 
   Phi[i] = kTwoOverSqrtPi * s;
 }
 
-// One thread per pair: J_p = sum_a0 m0(a0) sum_a1 m1(a1) sum_a2 m2(a2) Phi,
-// with the pair's m2 column in registers; Phi rows are read at wave-uniform
-// addresses.
-template <int NMAX>
-__global__ void __launch_bounds__(128)
-jp_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int n, int64_t npair,
-          double* __restrict__ Jp) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = p < npair;
-  const int64_t pc = ok ? p : 0;
+// J_p for 256 pairs per work group of 512 threads: wave w owns the two
+// 16-pair tiles at blockIdx.x*256 + 32 w.  Per a0 the slab Phi(a0, :, :) is
+// staged in LDS (double-buffered, the next slab's loads in flight during the
+// MFMAs); X = Phi(a0) m_2 comes out of the matrix cores one 16-row block of
+// a1 at a time and is contracted at once with m_1 and m_0.
+template <int NT>
+__global__ void __launch_bounds__(512, 1)
+jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int n, int64_t npair,
+               double* __restrict__ Jp) {
+  constexpr int NP = 16 * NT, NK = NP / 4, PT = 2;
+  constexpr int PS = NP + 1;                        // LDS row stride (doubles)
+  constexpr int SLAB = NP * NP;                     // padded slab values
+  constexpr int PER = (SLAB + 511) / 512;           // staged values per thread
+  __shared__ double s_phi[2][NP * PS];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, kg = lane >> 4;
   const double* M0 = M;
   const double* M1 = M + (int64_t)n * npair;
   const double* M2 = M + 2 * (int64_t)n * npair;
-  double m2[NMAX];
+  const int64_t n2 = (int64_t)n * n;
+
+  int64_t pc[PT];
+  bool pok[PT];
 #pragma unroll
-  for (int a = 0; a < NMAX; ++a) m2[a] = (a < n) ? M2[(int64_t)a * npair + pc] : 0.0;
-  double jp = 0.0;
-  for (int a0 = 0; a0 < n; ++a0) {
-    double y = 0.0;
-    for (int a1 = 0; a1 < n; ++a1) {
-      const double* row = Phi + ((int64_t)a0 * n + a1) * n;
-      double z = 0.0;
-#pragma unroll
-      for (int a2 = 0; a2 < NMAX; ++a2)
-        if (a2 < n) z += m2[a2] * row[a2];
-      y += M1[(int64_t)a1 * npair + pc] * z;
-    }
-    jp += M0[(int64_t)a0 * npair + pc] * y;
+  for (int t = 0; t < PT; ++t) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + wave * 32 + 16 * t + r16;
+    pok[t] = p < npair;
+    pc[t] = pok[t] ? p : 0;
   }
-  if (ok) Jp[p] = jp;
+  // B fragments m_2(a2 = 4 s + l/16, p) and the weights m_1(a1, p) of this
+  // lane's output rows a1 = 16 i + l/16 + 4 r
+  double bm[PT][NK], w1[PT][NT][4];
+#pragma unroll
+  for (int t = 0; t < PT; ++t) {
+#pragma unroll
+    for (int st = 0; st < NK; ++st) {
+      const int a2 = 4 * st + kg;
+      bm[t][st] = (pok[t] && a2 < n) ? M2[(int64_t)a2 * npair + pc[t]] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a1 = 16 * i + kg + 4 * r;
+        w1[t][i][r] = (pok[t] && a1 < n) ? M1[(int64_t)a1 * npair + pc[t]] : 0.0;
+      }
+  }
+
+  double pre[PER];
+  auto load = [&](int a0) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 512 * i;
+      const int a1 = e / NP, a2 = e % NP;
+      pre[i] = (e < SLAB && a1 < n && a2 < n) ? Phi[a0 * n2 + (int64_t)a1 * n + a2] : 0.0;
+    }
+  };
+  auto store = [&](double* buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 512 * i;
+      if (e < SLAB) buf[(e / NP) * PS + (e % NP)] = pre[i];
+    }
+  };
+
+  double jacc[PT] = {};
+  load(0);
+  for (int a0 = 0; a0 < n; ++a0) {
+    double* buf = s_phi[a0 & 1];
+    store(buf);
+    __syncthreads();  // slab a0 in LDS; every wave is past slab a0-2 in this buffer
+    if (a0 + 1 < n) load(a0 + 1);
+    double m0v[PT];
+#pragma unroll
+    for (int t = 0; t < PT; ++t) m0v[t] = pok[t] ? M0[(int64_t)a0 * npair + pc[t]] : 0.0;
+    double y[PT] = {};
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      v4d X[PT];
+#pragma unroll
+      for (int t = 0; t < PT; ++t) X[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < NK; ++st) {
+        const double av = buf[(16 * i + r16) * PS + 4 * st + kg];
+#pragma unroll
+        for (int t = 0; t < PT; ++t) X[t] = mfma64(av, bm[t][st], X[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < PT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[t] += w1[t][i][r] * X[t][r];
+    }
+#pragma unroll
+    for (int t = 0; t < PT; ++t) jacc[t] += m0v[t] * y[t];
+  }
+  // the four lanes l/16 = 0..3 of a column hold partial sums over a1
+#pragma unroll
+  for (int t = 0; t < PT; ++t) {
+    double v = jacc[t];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    if (kg == 0 && pok[t]) Jp[pc[t]] = v;
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -181,10 +319,15 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
+namespace {
+int rho_a0_per_wave(int n) { return n <= 48 ? 2 : 1; }
+int rho_groups(int n) { return (n + 8 * rho_a0_per_wave(n) - 1) / (8 * rho_a0_per_wave(n)); }
+}  // namespace
+
 int j_nchunk(int n, int npair) {
-  int c = kRhoBlocks / (n > 0 ? n : 1);
+  int c = kRhoGroups / rho_groups(n);
   if (c < 1) c = 1;
-  const int maxc = (npair + 255) / 256;  // at least 256 pairs per chunk
+  const int maxc = (npair + 4 * kKB - 1) / (4 * kKB);  // at least four batches per chunk
   if (c > maxc) c = maxc;
   return c < 1 ? 1 : c;
 }
@@ -217,22 +360,22 @@ hipError_t launch_apply_j(const double* M, int nb, int npair, int n, int nq, con
   const int64_t n3 = (int64_t)n * n * n;
   hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, D, nb, (int64_t)npair, w.Dt);
   const int64_t chunk = ((int64_t)npair + w.nchunk - 1) / w.nchunk;
-  const dim3 rg(n, w.nchunk);
-  if (n <= 16) hipLaunchKernelGGL(rho_kernel<1>, rg, dim3(256), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
-  else if (n <= 32) hipLaunchKernelGGL(rho_kernel<2>, rg, dim3(256), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
-  else if (n <= 48) hipLaunchKernelGGL(rho_kernel<3>, rg, dim3(256), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
-  else hipLaunchKernelGGL(rho_kernel<4>, rg, dim3(256), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  const dim3 rg(rho_groups(n), w.nchunk);
+  if (n <= 16) hipLaunchKernelGGL((rho_mfma_kernel<1, 2>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  else if (n <= 32) hipLaunchKernelGGL((rho_mfma_kernel<2, 2>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  else if (n <= 48) hipLaunchKernelGGL((rho_mfma_kernel<3, 2>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  else hipLaunchKernelGGL((rho_mfma_kernel<4, 1>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
   hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.rho_part, w.nchunk, n3, w.rho);
   const unsigned mb = nblk(n3 * nq, 256);
   hipLaunchKernelGGL(mode_product_kernel, dim3(mb), dim3(256), 0, s, tb.K, w.rho, (int64_t)0, w.T1, n, nq, 0);
   hipLaunchKernelGGL(mode_product_kernel, dim3(mb), dim3(256), 0, s, tb.K, w.T1, n3, w.T2, n, nq, 1);
   hipLaunchKernelGGL(mode_product_kernel, dim3(mb), dim3(256), 0, s, tb.K, w.T2, n3, w.T3, n, nq, 2);
   hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.T3, tb.w, nq, n3, w.Phi);
-  const unsigned jb = nblk(npair, 128);
-  if (n <= 16) hipLaunchKernelGGL(jp_kernel<16>, dim3(jb), dim3(128), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
-  else if (n <= 32) hipLaunchKernelGGL(jp_kernel<32>, dim3(jb), dim3(128), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
-  else if (n <= 48) hipLaunchKernelGGL(jp_kernel<48>, dim3(jb), dim3(128), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
-  else hipLaunchKernelGGL(jp_kernel<64>, dim3(jb), dim3(128), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
+  const unsigned jb = nblk(npair, 256);
+  if (n <= 16) hipLaunchKernelGGL(jp_mfma_kernel<1>, dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
+  else if (n <= 32) hipLaunchKernelGGL(jp_mfma_kernel<2>, dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
+  else if (n <= 48) hipLaunchKernelGGL(jp_mfma_kernel<3>, dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
+  else hipLaunchKernelGGL(jp_mfma_kernel<4>, dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
   hipLaunchKernelGGL(unpack_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, w.Jp, nb, (int64_t)npair, J);
   return hipGetLastError();
 }
