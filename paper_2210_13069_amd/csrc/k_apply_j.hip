@@ -164,37 +164,80 @@ sum_parts_kernel(const double* __restrict__ part, int nchunk, int64_t len, doubl
   out[i] = s;
 }
 
-// out[k][...] = mode-`mode` product of K_k with in (in shared by all k when
-// in_stride == 0).  Index (i0, i1, i2) of an n^3 tensor, i0 slowest.
+// Phi = (2/sqrt(pi)) sum_k w_k rho x_0 K_k x_1 K_k x_2 K_k in two passes.
+// Pass 1, one work group per (a0 slab, node k): S = K_k rho(a0, :, :) K_k^T,
+// both products in LDS, written to T[k][a0][:][:].
+template <int NMAX>
 __global__ void __launch_bounds__(256)
-mode_product_kernel(const double* __restrict__ K, const double* __restrict__ in, int64_t in_stride,
-                    double* __restrict__ out, int n, int nq, int mode) {
-  const int64_t n3 = (int64_t)n * n * n;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n3 * nq) return;
-  const int k = (int)(g / n3);
-  const int64_t e = g - k * n3;
-  const int i0 = (int)(e / (n * n)), i1 = (int)((e / n) % n), i2 = (int)(e % n);
-  const double* Kk = K + (int64_t)k * n * n;
-  const double* src = in + k * in_stride;
-  double s = 0.0;
-  if (mode == 0) {
-    for (int a = 0; a < n; ++a) s += Kk[i0 * n + a] * src[((int64_t)a * n + i1) * n + i2];
-  } else if (mode == 1) {
-    for (int a = 0; a < n; ++a) s += Kk[i1 * n + a] * src[((int64_t)i0 * n + a) * n + i2];
-  } else {
-    for (int a = 0; a < n; ++a) s += Kk[i2 * n + a] * src[((int64_t)i0 * n + i1) * n + a];
+slab_modes_kernel(const double* __restrict__ K, const double* __restrict__ rho, int n,
+                  double* __restrict__ T) {
+  constexpr int ST = NMAX + 1;
+  __shared__ double s_k[NMAX * ST];
+  __shared__ double s_r[NMAX * ST];
+  __shared__ double s_u[NMAX * ST];
+  const int a0 = blockIdx.x, k = blockIdx.y;
+  const int64_t n2 = (int64_t)n * n;
+  const double* Kk = K + (int64_t)k * n2;
+  const double* R = rho + a0 * n2;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i = e / n, j = e % n;
+    s_k[i * ST + j] = Kk[e];
+    s_r[i * ST + j] = R[e];
   }
-  out[g] = s;
+  __syncthreads();
+  // U(i1, b) = sum_a K(i1, a) rho(a, b)
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i1 = e / n, b = e % n;
+    double u = 0.0;
+    for (int a = 0; a < n; ++a) u += s_k[i1 * ST + a] * s_r[a * ST + b];
+    s_u[i1 * ST + b] = u;
+  }
+  __syncthreads();
+  // S(i1, i2) = sum_b U(i1, b) K(i2, b)
+  double* out = T + ((int64_t)k * n + a0) * n2;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i1 = e / n, i2 = e % n;
+    double v = 0.0;
+    for (int b = 0; b < n; ++b) v += s_u[i1 * ST + b] * s_k[i2 * ST + b];
+    out[e] = v;
+  }
 }
 
+// Pass 2: P[k](i0, c) = sum_a K_k(i0, a) T[k][a][c] for c = (i1, i2); one
+// thread per (c, k) with all i0 in registers, K_k read at uniform addresses.
+template <int NMAX>
 __global__ void __launch_bounds__(256)
-phi_kernel(const double* __restrict__ T3, const double* __restrict__ w, int nq, int64_t n3,
+mode0_kernel(const double* __restrict__ K, const double* __restrict__ T, int n, double* __restrict__ P) {
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int k = blockIdx.y;
+  const int64_t cc = c < n2 ? c : 0;
+  const double* Kk = K + (int64_t)k * n2;
+  const double* Tk = T + (int64_t)k * n * n2;
+  double acc[NMAX];
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) acc[i] = 0.0;
+  for (int a = 0; a < n; ++a) {
+    const double t = Tk[a * n2 + cc];
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i)
+      if (i < n) acc[i] += Kk[i * n + a] * t;
+  }
+  if (c >= n2) return;
+  double* out = P + (int64_t)k * n * n2;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    if (i < n) out[i * n2 + c] = acc[i];
+}
+
+// Phi = (2/sqrt(pi)) sum_k w_k P[k], summed in node order.
+__global__ void __launch_bounds__(256)
+phi_kernel(const double* __restrict__ P, const double* __restrict__ w, int nq, int64_t n3,
            double* __restrict__ Phi) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n3) return;
   double s = 0.0;
-  for (int k = 0; k < nq; ++k) s += w[k] * T3[(int64_t)k * n3 + i];
+  for (int k = 0; k < nq; ++k) s += w[k] * P[(int64_t)k * n3 + i];
   Phi[i] = kTwoOverSqrtPi * s;
 }
 
@@ -335,8 +378,7 @@ int j_nchunk(int n, int npair) {
 size_t j_work_bytes(int nq, int n, int npair) {
   const size_t n3 = (size_t)n * n * n;
   const int nc = j_nchunk(n, npair);
-  return align256(8 * (size_t)npair) * 2 + align256(8 * n3 * nc) + align256(8 * n3) * 2 +
-         align256(8 * n3 * nq) * 3;
+  return align256(8 * (size_t)npair) * 2 + align256(8 * n3 * nc) + align256(8 * n3) * 2 + align256(8 * n3 * nq) * 2;
 }
 
 JWork carve_j_work(void* base, int nq, int n, int npair) {
@@ -350,8 +392,7 @@ JWork carve_j_work(void* base, int nq, int n, int npair) {
   w.rho = reinterpret_cast<double*>(p); p += align256(8 * n3);
   w.Phi = reinterpret_cast<double*>(p); p += align256(8 * n3);
   w.T1 = reinterpret_cast<double*>(p); p += align256(8 * n3 * nq);
-  w.T2 = reinterpret_cast<double*>(p); p += align256(8 * n3 * nq);
-  w.T3 = reinterpret_cast<double*>(p);
+  w.T2 = reinterpret_cast<double*>(p);
   return w;
 }
 
@@ -366,11 +407,16 @@ hipError_t launch_apply_j(const double* M, int nb, int npair, int n, int nq, con
   else if (n <= 48) hipLaunchKernelGGL((rho_mfma_kernel<3, 2>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
   else hipLaunchKernelGGL((rho_mfma_kernel<4, 1>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
   hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.rho_part, w.nchunk, n3, w.rho);
-  const unsigned mb = nblk(n3 * nq, 256);
-  hipLaunchKernelGGL(mode_product_kernel, dim3(mb), dim3(256), 0, s, tb.K, w.rho, (int64_t)0, w.T1, n, nq, 0);
-  hipLaunchKernelGGL(mode_product_kernel, dim3(mb), dim3(256), 0, s, tb.K, w.T1, n3, w.T2, n, nq, 1);
-  hipLaunchKernelGGL(mode_product_kernel, dim3(mb), dim3(256), 0, s, tb.K, w.T2, n3, w.T3, n, nq, 2);
-  hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.T3, tb.w, nq, n3, w.Phi);
+  if (n <= 16) hipLaunchKernelGGL(slab_modes_kernel<16>, dim3(n, nq), dim3(256), 0, s, tb.K, w.rho, n, w.T1);
+  else if (n <= 32) hipLaunchKernelGGL(slab_modes_kernel<32>, dim3(n, nq), dim3(256), 0, s, tb.K, w.rho, n, w.T1);
+  else if (n <= 48) hipLaunchKernelGGL(slab_modes_kernel<48>, dim3(n, nq), dim3(256), 0, s, tb.K, w.rho, n, w.T1);
+  else hipLaunchKernelGGL(slab_modes_kernel<64>, dim3(n, nq), dim3(256), 0, s, tb.K, w.rho, n, w.T1);
+  const dim3 mg(nblk((int64_t)n * n, 256), nq);
+  if (n <= 16) hipLaunchKernelGGL(mode0_kernel<16>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
+  else if (n <= 32) hipLaunchKernelGGL(mode0_kernel<32>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
+  else if (n <= 48) hipLaunchKernelGGL(mode0_kernel<48>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
+  else hipLaunchKernelGGL(mode0_kernel<64>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
+  hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.T2, tb.w, nq, n3, w.Phi);
   const unsigned jb = nblk(npair, 256);
   if (n <= 16) hipLaunchKernelGGL(jp_mfma_kernel<1>, dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
   else if (n <= 32) hipLaunchKernelGGL(jp_mfma_kernel<2>, dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);

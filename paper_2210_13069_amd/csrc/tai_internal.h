@@ -130,9 +130,8 @@ struct JWork {
   double* Dt;      // [npair]
   double* rho_part;// [nchunk][n^3]
   double* rho;     // [n^3]
-  double* T1;      // [nq][n^3]
-  double* T2;      // [nq][n^3]
-  double* T3;      // [nq][n^3]
+  double* T1;      // [nq][n^3] slab products K_k rho(a0) K_k^T
+  double* T2;      // [nq][n^3] mode-0 products, before the sum over nodes
   double* Phi;     // [n^3]
   double* Jp;      // [npair]
   int nchunk;
