@@ -225,26 +225,33 @@ def main():
         jba = tai.BasisArrays(jb)
         Mj = torch.empty((3, jP.n, jb.npair), dtype=torch.float64, device=dev)
         Dj = torch.as_tensor(D, device=dev)
-        Jj = torch.empty((jb.nb, jb.nb), dtype=torch.float64, device=dev)
-        jparams = tai.make_params(jP, tai.FP64)
-        log("J-build: Nb=1000")
-        for _ in range(W):
-            ctx.moments(jba, jP, Mj)
-            ctx.apply_J(Mj, jb.nb, jparams, Dj, Jj)
-        torch.cuda.synchronize()
-        ctx.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(K):
-            ctx.moments(jba, jP, Mj)
-            ctx.apply_J(Mj, jb.nb, jparams, Dj, Jj)
-        torch.cuda.synchronize()
-        ms_j = (time.perf_counter() - t0) * 1e3 / K
-        stj = {s: ctx.profile_read(s) for s in ("moments", "apply_J")}
-        ctx.profile_enable(False)
-        japply = {"workload": "Nb=1000 (100 atoms s,p,d), 500500 pairs, omega=0.4, nq=32, n=48, L=24; moments + J",
-                  "dtype": "fp64", "ms_per_step": round(ms_j, 3),
-                  "effective_entries_per_s": float(jb.npair) ** 2 / (ms_j / 1e3),
-                  "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stj.items()}}
+        Jj = {name: torch.empty((jb.nb, jb.nb), dtype=torch.float64, device=dev) for name in ("fp64", "fp32")}
+        japply = {"workload": "Nb=1000 (100 atoms s,p,d), 500500 pairs, omega=0.4, nq=32, n=48, L=24; "
+                              "step = moments + J (B never stored)"}
+        for name in ("fp64", "fp32"):
+            jparams = tai.make_params(jP, tai.PREC_BY_NAME[name])
+            log(f"J-build {name}: Nb=1000")
+            for _ in range(W):
+                ctx.moments(jba, jP, Mj)
+                ctx.apply_J(Mj, jb.nb, jparams, Dj, Jj[name])
+            torch.cuda.synchronize()
+            ctx.profile_enable(True)
+            t0 = time.perf_counter()
+            for _ in range(K):
+                ctx.moments(jba, jP, Mj)
+                ctx.apply_J(Mj, jb.nb, jparams, Dj, Jj[name])
+            torch.cuda.synchronize()
+            ms_j = (time.perf_counter() - t0) * 1e3 / K
+            stj = {s_: ctx.profile_read(s_) for s_ in ("moments", "apply_J")}
+            ctx.profile_enable(False)
+            japply[name] = {"ms_per_step": round(ms_j, 3),
+                            "effective_entries_per_s": float(jb.npair) ** 2 / (ms_j / 1e3),
+                            "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stj.items()}}
+        ref, got = Jj["fp64"], Jj["fp32"]
+        japply["fp32"]["rel_2norm_vs_fp64_gpu"] = float(torch.linalg.matrix_norm(got - ref, 2) /
+                                                        torch.linalg.matrix_norm(ref, 2))
+        japply["fp32"]["normwise_vs_fp64_gpu"] = float((got - ref).abs().max() / ref.abs().max())
+        japply["fp32"]["speedup_vs_fp64"] = round(japply["fp64"]["ms_per_step"] / japply["fp32"]["ms_per_step"], 3)
         del Mj, Jj
         torch.cuda.empty_cache()
 

@@ -183,8 +183,14 @@ int tai_assemble_B_batched(tai_ctx* ctx, int32_t nmol, const tai_mol* mols, void
    which equals sum over all ordered (k,l) of B(mu nu, k l) D(k,l) for a
    symmetric D.  M: DEVICE double [3][n][npair]; D: DEVICE double [nb][nb],
    only its upper triangle is read; J: DEVICE double [nb][nb], fully written.
-   All arithmetic is FP64; params->prec must be TAI_FP64 (other modes return
-   TAI_ERR_UNSUPPORTED). */
+   params->prec selects the arithmetic of the two pair contractions (rho and
+   the projection onto the pairs), both on the matrix cores:
+     TAI_FP64  FP64 throughout;
+     TAI_FP32  FP32 operands and products, summed in FP32 within a batch of
+               64 pairs (rho) or one 16-row block (projection) and in FP64
+               beyond; the mode products and the contraction with m_{p,0},
+               m_{p,1} stay FP64.
+   Other modes return TAI_ERR_UNSUPPORTED. */
 int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* params,
                 const double* D, double* J, void* stream);
 

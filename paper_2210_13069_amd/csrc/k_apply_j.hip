@@ -36,15 +36,33 @@ density_pairs_kernel(const double* __restrict__ D, int nb, int64_t npair, double
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kKB = 64;          // pairs per LDS batch of the rho kernel
 constexpr int kRhoGroups = 512;  // target work groups of the rho kernel
 
-__device__ inline v4d mfma64(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+// The arithmetic of the two pair contractions: FP64, or FP32 with the
+// products summed in FP32 within one LDS batch of pairs (rho) or one a1
+// block (J_p) and in FP64 beyond.  Both use 16x16x4 MFMAs, whose operand
+// fragments have the same lane layout; the output rows differ (row_of).
+struct JF64 {
+  using T = double;
+  using Acc = v4d;
+  static constexpr bool kSplitSum = false;
+  __device__ static Acc mma(double a, double b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row_of(int kg, int r) { return kg + 4 * r; }
+};
+struct JF32 {
+  using T = float;
+  using Acc = v4f;
+  static constexpr bool kSplitSum = true;
+  __device__ static Acc mma(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row_of(int kg, int r) { return 4 * kg + r; }
+};
 
 // grid (ceil(n / (8*A0W)), nchunk), 512 threads.  Wave w owns
 // a0 = blockIdx.x*8*A0W + w*A0W + {0..A0W-1} and all (a1, a2) in NT x NT
 // output tiles of 16 x 16 (n padded to 16*NT with zeros).
-template <int NT, int A0W>
+template <class Op, int NT, int A0W>
 __global__ void __launch_bounds__(512, 1)
 rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int n, int64_t npair,
                 int64_t chunk, double* __restrict__ part) {
@@ -53,9 +71,11 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
   constexpr int ROWS = A0G + 2 * NP;           // staged rows: c (A0G), m1 (NP), m2 (NP)
   constexpr int PER = ROWS * kKB / 512;        // staged values per thread
   constexpr int CS = A0G + 1, MS = NP + 1;     // LDS row strides (doubles)
-  __shared__ double s_c[kKB * CS];
-  __shared__ double s_m1[kKB * MS];
-  __shared__ double s_m2[kKB * MS];
+  using T = typename Op::T;
+  using Acc = typename Op::Acc;
+  __shared__ T s_c[kKB * CS];
+  __shared__ T s_m1[kKB * MS];
+  __shared__ T s_m2[kKB * MS];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
@@ -67,7 +87,7 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
   const double* M2 = M + 2 * (int64_t)n * npair;
 
   // staged value e = threadIdx.x + 512 i of a batch: row e / kKB, pair e % kKB
-  double pre[PER];
+  T pre[PER];
   auto load = [&](int64_t qb) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -87,7 +107,7 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
           if (a < n) v = M2[(int64_t)a * npair + q];
         }
       }
-      pre[i] = v;
+      pre[i] = (T)v;
     }
   };
   auto store = [&]() {
@@ -101,13 +121,17 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
     }
   };
 
-  v4d acc[A0W][NT][NT];
+  Acc acc[A0W][NT][NT];
+  v4d tot[Op::kSplitSum ? A0W : 1][NT][NT];  // FP64 sums of the FP32 batches
 #pragma unroll
   for (int a = 0; a < A0W; ++a)
 #pragma unroll
     for (int i = 0; i < NT; ++i)
 #pragma unroll
-      for (int j = 0; j < NT; ++j) acc[a][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < NT; ++j) {
+        acc[a][i][j] = Acc{0, 0, 0, 0};
+        if constexpr (Op::kSplitSum) tot[a][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      }
 
   load(q0);
   for (int64_t qb = q0; qb < q1; qb += kKB) {
@@ -118,25 +142,37 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
 #pragma unroll 2
     for (int st = 0; st < kKB / 4; ++st) {
       const int kk = 4 * st + kg;  // this lane's pair within the batch
-      double bm[NT], am[NT];
+      T bm[NT], am[NT];
 #pragma unroll
       for (int j = 0; j < NT; ++j) bm[j] = s_m2[kk * MS + 16 * j + r16];
 #pragma unroll
       for (int i = 0; i < NT; ++i) am[i] = s_m1[kk * MS + 16 * i + r16];
 #pragma unroll
       for (int a = 0; a < A0W; ++a) {
-        const double cq = s_c[kk * CS + wave * A0W + a];
+        const T cq = s_c[kk * CS + wave * A0W + a];
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
-          const double av = cq * am[i];
+          const T av = cq * am[i];
 #pragma unroll
-          for (int j = 0; j < NT; ++j) acc[a][i][j] = mfma64(av, bm[j], acc[a][i][j]);
+          for (int j = 0; j < NT; ++j) acc[a][i][j] = Op::mma(av, bm[j], acc[a][i][j]);
         }
       }
     }
+    if constexpr (Op::kSplitSum) {
+#pragma unroll
+      for (int a = 0; a < A0W; ++a)
+#pragma unroll
+        for (int i = 0; i < NT; ++i)
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tot[a][i][j][r] += (double)acc[a][i][j][r];
+            acc[a][i][j] = Acc{0, 0, 0, 0};
+          }
+    }
   }
 
-  // lane l holds column a2 = 16 j + l%16 and rows a1 = 16 i + l/16 + 4 r
+  // lane l holds column a2 = 16 j + l%16 and rows a1 = 16 i + row_of(l/16, r)
   const int64_t n2 = (int64_t)n * n;
 #pragma unroll
   for (int a = 0; a < A0W; ++a) {
@@ -149,8 +185,11 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
       for (int j = 0; j < NT; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int a1 = 16 * i + kg + 4 * r, a2 = 16 * j + r16;
-          if (a1 < n && a2 < n) out[a1 * n + a2] = acc[a][i][j][r];
+          const int a1 = 16 * i + Op::row_of(kg, r), a2 = 16 * j + r16;
+          double v;
+          if constexpr (Op::kSplitSum) v = tot[a][i][j][r];
+          else v = acc[a][i][j][r];
+          if (a1 < n && a2 < n) out[a1 * n + a2] = v;
         }
   }
 }
@@ -246,7 +285,7 @@ phi_kernel(const double* __restrict__ P, const double* __restrict__ w, int nq, i
 // staged in LDS (double-buffered, the next slab's loads in flight during the
 // MFMAs); X = Phi(a0) m_2 comes out of the matrix cores one 16-row block of
 // a1 at a time and is contracted at once with m_1 and m_0.
-template <int NT>
+template <class Op, int NT>
 __global__ void __launch_bounds__(512, 1)
 jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int n, int64_t npair,
                double* __restrict__ Jp) {
@@ -254,7 +293,9 @@ jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int
   constexpr int PS = NP + 1;                        // LDS row stride (doubles)
   constexpr int SLAB = NP * NP;                     // padded slab values
   constexpr int PER = (SLAB + 511) / 512;           // staged values per thread
-  __shared__ double s_phi[2][NP * PS];
+  using T = typename Op::T;
+  using Acc = typename Op::Acc;
+  __shared__ T s_phi[2][NP * PS];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
@@ -272,20 +313,21 @@ jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int
     pc[t] = pok[t] ? p : 0;
   }
   // B fragments m_2(a2 = 4 s + l/16, p) and the weights m_1(a1, p) of this
-  // lane's output rows a1 = 16 i + l/16 + 4 r
-  double bm[PT][NK], w1[PT][NT][4];
+  // lane's output rows a1 = 16 i + row_of(l/16, r)
+  T bm[PT][NK];
+  double w1[PT][NT][4];
 #pragma unroll
   for (int t = 0; t < PT; ++t) {
 #pragma unroll
     for (int st = 0; st < NK; ++st) {
       const int a2 = 4 * st + kg;
-      bm[t][st] = (pok[t] && a2 < n) ? M2[(int64_t)a2 * npair + pc[t]] : 0.0;
+      bm[t][st] = (T)((pok[t] && a2 < n) ? M2[(int64_t)a2 * npair + pc[t]] : 0.0);
     }
 #pragma unroll
     for (int i = 0; i < NT; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int a1 = 16 * i + kg + 4 * r;
+        const int a1 = 16 * i + Op::row_of(kg, r);
         w1[t][i][r] = (pok[t] && a1 < n) ? M1[(int64_t)a1 * npair + pc[t]] : 0.0;
       }
   }
@@ -299,18 +341,18 @@ jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int
       pre[i] = (e < SLAB && a1 < n && a2 < n) ? Phi[a0 * n2 + (int64_t)a1 * n + a2] : 0.0;
     }
   };
-  auto store = [&](double* buf) {
+  auto store = [&](T* buf) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + 512 * i;
-      if (e < SLAB) buf[(e / NP) * PS + (e % NP)] = pre[i];
+      if (e < SLAB) buf[(e / NP) * PS + (e % NP)] = (T)pre[i];
     }
   };
 
   double jacc[PT] = {};
   load(0);
   for (int a0 = 0; a0 < n; ++a0) {
-    double* buf = s_phi[a0 & 1];
+    T* buf = s_phi[a0 & 1];
     store(buf);
     __syncthreads();  // slab a0 in LDS; every wave is past slab a0-2 in this buffer
     if (a0 + 1 < n) load(a0 + 1);
@@ -320,19 +362,19 @@ jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int
     double y[PT] = {};
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
-      v4d X[PT];
+      Acc X[PT];
 #pragma unroll
-      for (int t = 0; t < PT; ++t) X[t] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < PT; ++t) X[t] = Acc{0, 0, 0, 0};
 #pragma unroll
       for (int st = 0; st < NK; ++st) {
-        const double av = buf[(16 * i + r16) * PS + 4 * st + kg];
+        const T av = buf[(16 * i + r16) * PS + 4 * st + kg];
 #pragma unroll
-        for (int t = 0; t < PT; ++t) X[t] = mfma64(av, bm[t][st], X[t]);
+        for (int t = 0; t < PT; ++t) X[t] = Op::mma(av, bm[t][st], X[t]);
       }
 #pragma unroll
       for (int t = 0; t < PT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) y[t] += w1[t][i][r] * X[t][r];
+        for (int r = 0; r < 4; ++r) y[t] += w1[t][i][r] * (double)X[t][r];
     }
 #pragma unroll
     for (int t = 0; t < PT; ++t) jacc[t] += m0v[t] * y[t];
@@ -363,28 +405,29 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 }  // namespace
 
 namespace {
-int rho_a0_per_wave(int n) { return n <= 48 ? 2 : 1; }
-int rho_groups(int n) { return (n + 8 * rho_a0_per_wave(n) - 1) / (8 * rho_a0_per_wave(n)); }
+// a0 values per wave of the rho kernel: two where the accumulators allow
+int rho_a0_per_wave(int prec, int n) { return (prec == kFP64 && n <= 48) ? 2 : 1; }
+int rho_groups(int prec, int n) { return (n + 8 * rho_a0_per_wave(prec, n) - 1) / (8 * rho_a0_per_wave(prec, n)); }
 }  // namespace
 
-int j_nchunk(int n, int npair) {
-  int c = kRhoGroups / rho_groups(n);
+int j_nchunk(int prec, int n, int npair) {
+  int c = kRhoGroups / rho_groups(prec, n);
   if (c < 1) c = 1;
   const int maxc = (npair + 4 * kKB - 1) / (4 * kKB);  // at least four batches per chunk
   if (c > maxc) c = maxc;
   return c < 1 ? 1 : c;
 }
 
-size_t j_work_bytes(int nq, int n, int npair) {
+size_t j_work_bytes(int prec, int nq, int n, int npair) {
   const size_t n3 = (size_t)n * n * n;
-  const int nc = j_nchunk(n, npair);
+  const int nc = j_nchunk(prec, n, npair);
   return align256(8 * (size_t)npair) * 2 + align256(8 * n3 * nc) + align256(8 * n3) * 2 + align256(8 * n3 * nq) * 2;
 }
 
-JWork carve_j_work(void* base, int nq, int n, int npair) {
+JWork carve_j_work(void* base, int prec, int nq, int n, int npair) {
   const size_t n3 = (size_t)n * n * n;
   JWork w;
-  w.nchunk = j_nchunk(n, npair);
+  w.nchunk = j_nchunk(prec, n, npair);
   char* p = static_cast<char*>(base);
   w.Dt = reinterpret_cast<double*>(p); p += align256(8 * (size_t)npair);
   w.Jp = reinterpret_cast<double*>(p); p += align256(8 * (size_t)npair);
@@ -396,16 +439,32 @@ JWork carve_j_work(void* base, int nq, int n, int npair) {
   return w;
 }
 
-hipError_t launch_apply_j(const double* M, int nb, int npair, int n, int nq, const NodeTables& tb,
+template <class Op, int A0W>
+void launch_pair_contraction_rho(const double* M, int n, int npair, const JWork& w, hipStream_t s) {
+  const int64_t chunk = ((int64_t)npair + w.nchunk - 1) / w.nchunk;
+  const dim3 rg((n + 8 * A0W - 1) / (8 * A0W), w.nchunk);
+  if (n <= 16) hipLaunchKernelGGL((rho_mfma_kernel<Op, 1, A0W>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  else if (n <= 32) hipLaunchKernelGGL((rho_mfma_kernel<Op, 2, A0W>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  else if (n <= 48) hipLaunchKernelGGL((rho_mfma_kernel<Op, 3, A0W>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  else hipLaunchKernelGGL((rho_mfma_kernel<Op, 4, 1>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+}
+
+template <class Op>
+void launch_pair_contraction_jp(const double* M, int n, int npair, const JWork& w, hipStream_t s) {
+  const unsigned jb = nblk(npair, 256);
+  if (n <= 16) hipLaunchKernelGGL((jp_mfma_kernel<Op, 1>), dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
+  else if (n <= 32) hipLaunchKernelGGL((jp_mfma_kernel<Op, 2>), dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
+  else if (n <= 48) hipLaunchKernelGGL((jp_mfma_kernel<Op, 3>), dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
+  else hipLaunchKernelGGL((jp_mfma_kernel<Op, 4>), dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
+}
+
+hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, int n, int nq, const NodeTables& tb,
                           const double* D, double* J, const JWork& w, hipStream_t s) {
   const int64_t n3 = (int64_t)n * n * n;
   hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, D, nb, (int64_t)npair, w.Dt);
-  const int64_t chunk = ((int64_t)npair + w.nchunk - 1) / w.nchunk;
-  const dim3 rg(rho_groups(n), w.nchunk);
-  if (n <= 16) hipLaunchKernelGGL((rho_mfma_kernel<1, 2>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
-  else if (n <= 32) hipLaunchKernelGGL((rho_mfma_kernel<2, 2>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
-  else if (n <= 48) hipLaunchKernelGGL((rho_mfma_kernel<3, 2>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
-  else hipLaunchKernelGGL((rho_mfma_kernel<4, 1>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  if (prec == kFP32) launch_pair_contraction_rho<JF32, 1>(M, n, npair, w, s);
+  else if (n <= 48) launch_pair_contraction_rho<JF64, 2>(M, n, npair, w, s);
+  else launch_pair_contraction_rho<JF64, 1>(M, n, npair, w, s);
   hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.rho_part, w.nchunk, n3, w.rho);
   if (n <= 16) hipLaunchKernelGGL(slab_modes_kernel<16>, dim3(n, nq), dim3(256), 0, s, tb.K, w.rho, n, w.T1);
   else if (n <= 32) hipLaunchKernelGGL(slab_modes_kernel<32>, dim3(n, nq), dim3(256), 0, s, tb.K, w.rho, n, w.T1);
@@ -417,11 +476,8 @@ hipError_t launch_apply_j(const double* M, int nb, int npair, int n, int nq, con
   else if (n <= 48) hipLaunchKernelGGL(mode0_kernel<48>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
   else hipLaunchKernelGGL(mode0_kernel<64>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
   hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.T2, tb.w, nq, n3, w.Phi);
-  const unsigned jb = nblk(npair, 256);
-  if (n <= 16) hipLaunchKernelGGL(jp_mfma_kernel<1>, dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
-  else if (n <= 32) hipLaunchKernelGGL(jp_mfma_kernel<2>, dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
-  else if (n <= 48) hipLaunchKernelGGL(jp_mfma_kernel<3>, dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
-  else hipLaunchKernelGGL(jp_mfma_kernel<4>, dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
+  if (prec == kFP32) launch_pair_contraction_jp<JF32>(M, n, npair, w, s);
+  else launch_pair_contraction_jp<JF64>(M, n, npair, w, s);
   hipLaunchKernelGGL(unpack_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, w.Jp, nb, (int64_t)npair, J);
   return hipGetLastError();
 }

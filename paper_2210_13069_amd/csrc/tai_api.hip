@@ -698,12 +698,13 @@ int tai_apply_J(tai_ctx* c, const double* M, int32_t nb, const tai_params* p, co
   if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
   const int64_t npair = npair_of(nb);
   if (npair > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
-  if (p->prec != TAI_FP64) return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J supports prec TAI_FP64");
+  if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J supports prec TAI_FP64 and TAI_FP32");
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = p->n, nq = p->nq;
   if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
-  if ((r = ensure(c, c->jwork, tai::j_work_bytes(nq, n, (int)npair)))) return r;
+  if ((r = ensure(c, c->jwork, tai::j_work_bytes(p->prec, nq, n, (int)npair)))) return r;
   NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
   hipError_t e;
   {
@@ -711,10 +712,10 @@ int tai_apply_J(tai_ctx* c, const double* M, int32_t nb, const tai_params* p, co
     e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, tb, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
-  tai::JWork w = tai::carve_j_work(c->jwork.p, nq, n, (int)npair);
+  tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, n, (int)npair);
   {
     Timed tm(c, kStApplyJ, s);
-    e = tai::launch_apply_j(M, nb, (int)npair, n, nq, tb, D, J, w, s);
+    e = tai::launch_apply_j(p->prec, M, nb, (int)npair, n, nq, tb, D, J, w, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "apply_J kernels");
   return TAI_OK;

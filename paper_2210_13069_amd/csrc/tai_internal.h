@@ -136,10 +136,10 @@ struct JWork {
   double* Jp;      // [npair]
   int nchunk;
 };
-int j_nchunk(int n, int npair);
-size_t j_work_bytes(int nq, int n, int npair);
-JWork carve_j_work(void* base, int nq, int n, int npair);
-hipError_t launch_apply_j(const double* M, int nb, int npair, int n, int nq,
+int j_nchunk(int prec, int n, int npair);
+size_t j_work_bytes(int prec, int nq, int n, int npair);
+JWork carve_j_work(void* base, int prec, int nq, int n, int npair);
+hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, int n, int nq,
                           const NodeTables& tb, const double* D, double* J,
                           const JWork& w, hipStream_t s);
 

@@ -137,7 +137,7 @@ def test_apply_j_argument_checks(hctx):
     p = _params()
     assert L.tai_apply_J(hctx.h, d, 0, ctypes.byref(p), d, d, None) == tai.TAI_ERR_INVALID_ARG
     assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(p), None, d, None) == tai.TAI_ERR_INVALID_ARG
-    assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(_params(prec=1)), d, d, None) == tai.TAI_ERR_UNSUPPORTED
+    assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(_params(prec=2)), d, d, None) == tai.TAI_ERR_UNSUPPORTED
     assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(p), d, d, None) == tai.TAI_ERR_NOT_READY
 
 
