@@ -164,9 +164,11 @@ typedef struct {
   int64_t    ldb;
 } tai_mol;
 
-/* Moments and B for every molecule of a batch: per-molecule node, moment and
-   operand kernels, then ONE persistent assembly launch whose work groups
-   drain a queue of (molecule, tile) items.  With a non-NULL stream the
+/* Moments and B for every molecule of a batch (1 <= nmol <= 65535; the
+   molecules share nq, n, nodes and prec, each has its own omega, L, basis,
+   M and B): one launch per preparation stage (nodes, moments, operand
+   packing, projection) covering all molecules, then ONE persistent assembly
+   launch whose work groups drain a queue of (molecule, tile) items.  With a non-NULL stream the
    kernel sequence is recorded once into a HIP graph and replayed while the
    batch description (sizes, parameters, M/B pointers) is unchanged; the
    bases themselves are uploaded on every call.  Setting the environment
@@ -193,6 +195,25 @@ int tai_assemble_B_batched(tai_ctx* ctx, int32_t nmol, const tai_mol* mols, void
    Other modes return TAI_ERR_UNSUPPORTED. */
 int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* params,
                 const double* D, double* J, void* stream);
+
+/* ---- tuning ------------------------------------------------------------- */
+
+/* Shape autotuner of the split 16-bit assembly (TAI_BF16X3, TAI_BF16X6,
+   TAI_F16X3).  Its persistent kernel has several compiled shapes per inner
+   length (waves per work group, row and column blocks per wave, LDS ring
+   depth).  With mode 1 (the default) the first tai_assemble_B or
+   tai_assemble_B_batched call of a signature -- arithmetic, n, nq and a size
+   class (npair rounded up to a power of two; for a batch, its list of basis
+   sizes) -- runs every candidate twice on the call's stream, times the second
+   run with HIP events and keeps the fastest for later calls of the
+   signature.  That first call therefore takes about twice the number of
+   candidates times longer and synchronizes the stream.  Candidates compute
+   every entry with the same arithmetic in the same order: results do not
+   depend on the choice.  mode 0 uses the table default shape without
+   timing; mode 2 forgets the choices made so far (the mode is unchanged).
+   The environment variable TAI_ASM16_SHAPE=<k> forces candidate k.
+   TAI_ERR_INVALID_ARG for another mode. */
+int tai_tune(tai_ctx* ctx, int mode);
 
 /* ---- timing ------------------------------------------------------------- */
 

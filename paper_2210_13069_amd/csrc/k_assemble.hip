@@ -128,9 +128,8 @@ __device__ inline int scale_exponent(double mx) {
 
 // grid (prow / kRowsPerTile, 3): A_d rows and the exponents e(p, d).
 template <int NMAX>
-__global__ void __launch_bounds__(kRowsPerTile)
-pack_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int kc,
-            char* __restrict__ A, int32_t* __restrict__ ex) {
+__device__ inline void pack_body(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int kc,
+                                 char* __restrict__ A, int32_t* __restrict__ ex) {
   extern __shared__ uint32_t tile[];
   const int d = blockIdx.y;
   const int64_t row0 = (int64_t)blockIdx.x * kRowsPerTile;
@@ -166,10 +165,9 @@ pack_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int pr
 // 2^-e(q,d), and by w_k for d = 2; FP64 arithmetic.  K_k is staged in LDS,
 // zero padded to NMAX x NMAX, and read at wave-uniform addresses.
 template <int NMAX>
-__global__ void __launch_bounds__(kRowsPerTile)
-project_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
-               int kc, const double* __restrict__ K, const double* __restrict__ w,
-               const int32_t* __restrict__ ex, char* __restrict__ Y) {
+__device__ inline void project_body(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
+                                    int kc, const double* __restrict__ K, const double* __restrict__ w,
+                                    const int32_t* __restrict__ ex, char* __restrict__ Y) {
   extern __shared__ uint32_t tile[];
   const int sl = blockIdx.y;
   const int k = sl / 3, d = sl - 3 * (sl / 3);
@@ -232,10 +230,9 @@ __device__ inline void store8(char* rowp, int pos, const T (&v)[8]) {
 }
 
 template <int NMAX>
-__global__ void __launch_bounds__(256)
-project8_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
-                int kc, const double* __restrict__ K, const double* __restrict__ w,
-                const int32_t* __restrict__ ex, char* __restrict__ Y) {
+__device__ inline void project8_body(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
+                                     int kc, const double* __restrict__ K, const double* __restrict__ w,
+                                     const int32_t* __restrict__ ex, char* __restrict__ Y) {
   __shared__ double Ks[NMAX * NMAX];
   const int sl = blockIdx.y;
   const int k = sl / 3, d = sl - 3 * (sl / 3);
@@ -527,6 +524,56 @@ assemble_queue_kernel(const AsmMol* __restrict__ mols, int nmol, int64_t nitems,
 
 __global__ void reset_counter_kernel(unsigned* c) { *c = 0u; }
 
+// Single-molecule kernels and their batch forms: blockIdx.z = molecule of
+// the batch; blocks beyond a molecule's padded rows return at once (the
+// test is uniform per work group, before any barrier).
+template <int NMAX>
+__global__ void __launch_bounds__(kRowsPerTile)
+pack_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int kc,
+            char* __restrict__ A, int32_t* __restrict__ ex) {
+  pack_body<NMAX>(prec, M, n, npair, prow, kc, A, ex);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(kRowsPerTile)
+pack_batch_kernel(int prec, const PrepMol* __restrict__ mols, int n, int kc) {
+  const PrepMol& m = mols[blockIdx.z];
+  if ((int64_t)blockIdx.x * kRowsPerTile >= m.prow) return;
+  pack_body<NMAX>(prec, m.M, n, m.npair, m.prow, kc, static_cast<char*>(m.A), m.ex);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(kRowsPerTile)
+project_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
+               int kc, const double* __restrict__ K, const double* __restrict__ w,
+               const int32_t* __restrict__ ex, char* __restrict__ Y) {
+  project_body<NMAX>(prec, M, n, npair, prow, nq, kc, K, w, ex, Y);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(kRowsPerTile)
+project_batch_kernel(int prec, const PrepMol* __restrict__ mols, int n, int nq, int kc) {
+  const PrepMol& m = mols[blockIdx.z];
+  if ((int64_t)blockIdx.x * kRowsPerTile >= m.prow) return;
+  project_body<NMAX>(prec, m.M, n, m.npair, m.prow, nq, kc, m.tb.K, m.tb.w, m.ex, static_cast<char*>(m.Y));
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(256)
+project8_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
+                int kc, const double* __restrict__ K, const double* __restrict__ w,
+                const int32_t* __restrict__ ex, char* __restrict__ Y) {
+  project8_body<NMAX>(prec, M, n, npair, prow, nq, kc, K, w, ex, Y);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(256)
+project8_batch_kernel(int prec, const PrepMol* __restrict__ mols, int n, int nq, int kc) {
+  const PrepMol& m = mols[blockIdx.z];
+  if ((int64_t)blockIdx.x * 256 >= m.prow) return;
+  project8_body<NMAX>(prec, m.M, n, m.npair, m.prow, nq, kc, m.tb.K, m.tb.w, m.ex, static_cast<char*>(m.Y));
+}
+
 template <int NMAX>
 hipError_t launch_pack_t(int prec, const double* M, int n, int npair, int prow, void* A,
                          int32_t* ex, hipStream_t s) {
@@ -555,7 +602,50 @@ hipError_t launch_project_t(int prec, const double* M, int n, int npair, int pro
   return hipGetLastError();
 }
 
+template <int NMAX>
+hipError_t launch_pack_batch_t(int prec, const PrepMol* mols, int nmol, int max_prow, int n, hipStream_t s) {
+  const int kc = operand_kc(prec, n);
+  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
+  const size_t lds = sizeof(uint32_t) * kRowsPerTile * (kc * es / 4 + 1);
+  hipLaunchKernelGGL(pack_batch_kernel<NMAX>, dim3(max_prow / kRowsPerTile, 3, nmol), dim3(kRowsPerTile), lds, s,
+                     prec, mols, n, kc);
+  return hipGetLastError();
+}
+
+// every prow of a batch is a multiple of 256 (the host pads rows to it)
+template <int NMAX>
+hipError_t launch_project_batch_t(int prec, const PrepMol* mols, int nmol, int max_prow, int n, int nq,
+                                  hipStream_t s) {
+  const int kc = operand_kc(prec, n);
+  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
+  if (n % 8 == 0) {
+    hipLaunchKernelGGL(project8_batch_kernel<NMAX>, dim3(max_prow / 256, 3 * nq, nmol), dim3(256), 0, s,
+                       prec, mols, n, nq, kc);
+    return hipGetLastError();
+  }
+  const size_t tile_words = ((size_t)kRowsPerTile * (kc * es / 4 + 1) + 1) & ~size_t(1);
+  const size_t lds = sizeof(uint32_t) * tile_words + sizeof(double) * NMAX * NMAX;
+  hipLaunchKernelGGL(project_batch_kernel<NMAX>, dim3(max_prow / kRowsPerTile, 3 * nq, nmol), dim3(kRowsPerTile),
+                     lds, s, prec, mols, n, nq, kc);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_pack_batch(int prec, const PrepMol* mols, int nmol, int max_prow, int n, hipStream_t s) {
+  if (n <= 16) return launch_pack_batch_t<16>(prec, mols, nmol, max_prow, n, s);
+  if (n <= 32) return launch_pack_batch_t<32>(prec, mols, nmol, max_prow, n, s);
+  if (n <= 48) return launch_pack_batch_t<48>(prec, mols, nmol, max_prow, n, s);
+  return launch_pack_batch_t<64>(prec, mols, nmol, max_prow, n, s);
+}
+
+hipError_t launch_project_batch(int prec, const PrepMol* mols, int nmol, int max_prow, int n, int nq,
+                                hipStream_t s) {
+  if (n <= 16) return launch_project_batch_t<16>(prec, mols, nmol, max_prow, n, nq, s);
+  if (n <= 32) return launch_project_batch_t<32>(prec, mols, nmol, max_prow, n, nq, s);
+  if (n <= 48) return launch_project_batch_t<48>(prec, mols, nmol, max_prow, n, nq, s);
+  return launch_project_batch_t<64>(prec, mols, nmol, max_prow, n, nq, s);
+}
 
 int operand_esize(int prec) {
   return prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);

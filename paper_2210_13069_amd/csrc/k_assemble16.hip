@@ -418,10 +418,11 @@ const ShapeEntry kShapes[] = {
     TAI_S16(32, 0, 8, 4, 2, 3),   TAI_S16(32, 0, 8, 4, 1, 3),
     TAI_S16(64, 0, 8, 4, 1, 3),   TAI_S16(64, 0, 8, 3, 2, 2),
     TAI_S16(96, 0, 8, 4, 1, 3),   TAI_S16(96, 0, 8, 3, 2, 2),
-    TAI_S16(96, 1, 8, 4, 1, 3),   TAI_S16(96, 1, 8, 3, 2, 2),
+    TAI_S16(96, 1, 8, 4, 1, 3),   TAI_S16(96, 1, 8, 3, 2, 2),   TAI_S16(96, 1, 4, 4, 1, 3),
+    TAI_S16(96, 1, 4, 2, 1, 3),   TAI_S16(96, 1, 4, 2, 2, 2),
     TAI_S16(128, 0, 8, 2, 2, 3),  TAI_S16(128, 0, 8, 3, 1, 3),
     TAI_S16(128, 1, 4, 4, 1, 3),  TAI_S16(128, 1, 8, 4, 1, 3),  TAI_S16(128, 1, 4, 4, 1, 2),
-    TAI_S16(128, 1, 4, 3, 1, 3),  TAI_S16(128, 1, 8, 2, 2, 3),  TAI_S16(128, 1, 4, 2, 2, 3),
+    TAI_S16(128, 1, 4, 3, 1, 3),  TAI_S16(128, 1, 8, 2, 2, 3),  TAI_S16(128, 1, 4, 2, 1, 3),
     TAI_S16(160, 0, 8, 2, 2, 3),  TAI_S16(160, 0, 8, 1, 2, 3),
     TAI_S16(160, 1, 8, 2, 2, 3),  TAI_S16(160, 1, 8, 3, 1, 3),
     TAI_S16(192, 0, 8, 2, 2, 2),  TAI_S16(192, 0, 8, 1, 2, 3),
@@ -462,20 +463,15 @@ int asm16_shapes(int kc, int q, Asm16Shape* out, int cap) {
   return n;
 }
 
-Asm16Shape asm16_shape(int kc, int q) {
-  Asm16Shape c[8];
-  const int n = asm16_shapes(kc, q, c, 8);
+Asm16Shape asm16_shape(int kc, int q, int pick) {
+  Asm16Shape c[16];
+  const int n = asm16_shapes(kc, q, c, 16);
   if (n == 0) {
     Asm16Shape none{};
     none.id = -1;
     return none;
   }
-  int pick = 0;
-  if (const char* v = std::getenv("TAI_ASM16_SHAPE")) {
-    const int want = std::atoi(v);
-    if (want >= 0 && want < n && want < 8) pick = want;
-  }
-  Asm16Shape sh = c[pick];
+  Asm16Shape sh = c[(pick >= 0 && pick < n && pick < 16) ? pick : 0];
   sh.wgs_per_cu = kShapes[sh.id].occupancy();
   return sh;
 }

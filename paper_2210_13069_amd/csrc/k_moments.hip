@@ -37,8 +37,8 @@ __device__ inline double ipow(double x, int l) {
 }
 
 template <int NMAX>
-__global__ void __launch_bounds__(128)
-moments_kernel(DevBasis bs, int n, double L, NodeTables tb, double* __restrict__ M, int64_t npair) {
+__device__ inline void moments_body(const DevBasis& bs, int n, double L, const NodeTables& tb,
+                                    double* __restrict__ M, int64_t npair) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= 3 * npair) return;
   const int d = (int)(g / npair);
@@ -100,7 +100,31 @@ moments_kernel(DevBasis bs, int n, double L, NodeTables tb, double* __restrict__
   }
 }
 
+template <int NMAX>
+__global__ void __launch_bounds__(128)
+moments_kernel(DevBasis bs, int n, double L, NodeTables tb, double* __restrict__ M, int64_t npair) {
+  moments_body<NMAX>(bs, n, L, tb, M, npair);
+}
+
+// blockIdx.y = molecule; blocks past a molecule's 3*npair threads return
+template <int NMAX>
+__global__ void __launch_bounds__(128)
+moments_batch_kernel(const PrepMol* __restrict__ mols, int n) {
+  const PrepMol& m = mols[blockIdx.y];
+  moments_body<NMAX>(m.basis, n, m.L, m.tb, m.M, m.npair);
+}
+
 }  // namespace
+
+hipError_t launch_moments_batch(const PrepMol* mols, int nmol, int64_t max_npair, int n, hipStream_t s) {
+  const unsigned blocks = (unsigned)((3 * max_npair + 127) / 128);
+  const dim3 grid(blocks, nmol);
+  if (n <= 16) hipLaunchKernelGGL(moments_batch_kernel<16>, grid, dim3(128), 0, s, mols, n);
+  else if (n <= 32) hipLaunchKernelGGL(moments_batch_kernel<32>, grid, dim3(128), 0, s, mols, n);
+  else if (n <= 48) hipLaunchKernelGGL(moments_batch_kernel<48>, grid, dim3(128), 0, s, mols, n);
+  else hipLaunchKernelGGL(moments_batch_kernel<64>, grid, dim3(128), 0, s, mols, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_moments(const DevBasis& b, int n, double L, const NodeTables& tb,
                           double* M, hipStream_t s) {

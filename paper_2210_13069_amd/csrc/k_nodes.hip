@@ -49,8 +49,7 @@ __device__ inline void gauss_root(int m, int i, double& x, double& wt) {
   wt = 2.0 / ((1.0 - x * x) * dp * dp);
 }
 
-__global__ void __launch_bounds__(kNodeThreads)
-nodes_kernel(double omega, int nq, int n, double L, int kind, NodeTables tb) {
+__device__ inline void nodes_body(double omega, int nq, int n, double L, int kind, const NodeTables& tb) {
   const int tid = threadIdx.x;
   if (tid < nq) {
     double z, zw;
@@ -71,9 +70,20 @@ nodes_kernel(double omega, int nq, int n, double L, int kind, NodeTables tb) {
   }
 }
 
+__global__ void __launch_bounds__(kNodeThreads)
+nodes_kernel(double omega, int nq, int n, double L, int kind, NodeTables tb) {
+  nodes_body(omega, nq, n, L, kind, tb);
+}
+
+// one work group per molecule (blockIdx.y)
+__global__ void __launch_bounds__(kNodeThreads)
+nodes_batch_kernel(const PrepMol* __restrict__ mols, int nq, int n, int kind) {
+  const PrepMol& m = mols[blockIdx.y];
+  nodes_body(m.omega, nq, n, m.L, kind, m.tb);
+}
+
 // K tables (nq*n*n entries) followed by the n*n Chebyshev-to-Lagrange map.
-__global__ void __launch_bounds__(256)
-ktables_kernel(int nq, int n, int kind, NodeTables tb) {
+__device__ inline void ktables_body(int nq, int n, int kind, const NodeTables& tb) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nk = (int64_t)nq * n * n;
   if (g < nk) {
@@ -102,6 +112,16 @@ ktables_kernel(int nq, int n, int kind, NodeTables tb) {
     }
     tb.gam[ak] = v;
   }
+}
+
+__global__ void __launch_bounds__(256)
+ktables_kernel(int nq, int n, int kind, NodeTables tb) {
+  ktables_body(nq, n, kind, tb);
+}
+
+__global__ void __launch_bounds__(256)
+ktables_batch_kernel(const PrepMol* __restrict__ mols, int nq, int n, int kind) {
+  ktables_body(nq, n, kind, mols[blockIdx.y].tb);
 }
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -135,6 +155,16 @@ hipError_t launch_nodes(double omega, int nq, int n, double L, int kind,
   const int64_t total = (int64_t)nq * n * n + (int64_t)n * n;
   const int blocks = (int)((total + 255) / 256);
   hipLaunchKernelGGL(ktables_kernel, dim3(blocks), dim3(256), 0, s, nq, n, kind, tb);
+  return hipGetLastError();
+}
+
+hipError_t launch_nodes_batch(const PrepMol* mols, int nmol, int nq, int n, int kind, hipStream_t s) {
+  hipLaunchKernelGGL(nodes_batch_kernel, dim3(1, nmol), dim3(kNodeThreads), 0, s, mols, nq, n, kind);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)nq * n * n + (int64_t)n * n;
+  const int blocks = (int)((total + 255) / 256);
+  hipLaunchKernelGGL(ktables_batch_kernel, dim3(blocks, nmol), dim3(256), 0, s, mols, nq, n, kind);
   return hipGetLastError();
 }
 

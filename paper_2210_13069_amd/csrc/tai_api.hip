@@ -37,7 +37,14 @@ struct tai_ctx {
   Buf asm_host;           // pinned staging of the table
   hipEvent_t asm_host_done = nullptr;
   int cus = 0;            // compute units of the device
-  std::vector<tai::Asm16Shape> shapes16;  // 16-bit kernel shape per (kc, q), chosen once
+  // 16-bit kernel shapes: runtime facts per table entry, the tuned choice
+  // (candidate index) per call signature, and the tuning state
+  std::vector<tai::Asm16Shape> shapes16;
+  struct Tuned { int prec, n, nq; uint64_t key; int pick; };
+  std::vector<Tuned> tuned;
+  int tune_mode = 1;      // 0: table defaults, 1: tune each new signature once
+  int force_pick = -1;    // candidate forced while tuning
+  uint64_t size_key = 0;  // size class of the call in progress
   Buf jwork;              // apply_J intermediates
   // batched path
   Buf b_nodes, b_basis, b_opA, b_opEx, b_opY, b_mols, b_counter;
@@ -237,20 +244,33 @@ tai::DevBasis dev_basis_view(const tai_basis* b, char* dev) {
   return d;
 }
 
-// True when the 16-bit A-stationary kernel assembles this (prec, n).
+// Index of the 16-bit kernel shape used for (prec, n, nq) at the current
+// call's size class: TAI_ASM16_SHAPE if set, else the candidate being timed
+// while tuning, else the tuned choice, else the table default (0).
+int shape_pick(tai_ctx* c, int prec, int n, int nq) {
+  if (const char* v = std::getenv("TAI_ASM16_SHAPE")) return std::atoi(v);
+  if (c->force_pick >= 0) return c->force_pick;
+  for (const auto& t : c->tuned)
+    if (t.prec == prec && t.n == n && t.nq == nq && t.key == c->size_key) return t.pick;
+  return 0;
+}
 
-// Padded operand row count: a multiple of the generic kernel's tile (64),
-// of the projection kernel's 256-row blocks and of the 16-bit kernel's
-// row panel.
-// Shape of the 16-bit kernel for this arithmetic and degree (cached; the
-// device must be current).
-tai::Asm16Shape shape16(tai_ctx* c, int prec, int n) {
+// Shape of the 16-bit kernel for this call (runtime facts cached per table
+// entry; the device must be current).
+tai::Asm16Shape shape16(tai_ctx* c, int prec, int n, int nq) {
   const int kc = tai::operand_kc(prec, n), q = tai::operand_dup_chunks(prec, n);
+  tai::Asm16Shape list[16];
+  const int cnt = tai::asm16_shapes(kc, q, list, 16);
+  if (cnt == 0) {
+    tai::Asm16Shape none{};
+    none.id = -1;
+    return none;
+  }
+  int pick = shape_pick(c, prec, n, nq);
+  if (pick < 0 || pick >= cnt || pick >= 16) pick = 0;
   for (const auto& sh : c->shapes16)
-    if (sh.id >= 0 && sh.rb > 0 && sh.kc_key == kc && sh.q_key == q) return sh;
-  tai::Asm16Shape sh = tai::asm16_shape(kc, q);
-  sh.kc_key = kc;
-  sh.q_key = q;
+    if (sh.id == list[pick].id) return sh;
+  tai::Asm16Shape sh = tai::asm16_shape(kc, q, pick);
   c->shapes16.push_back(sh);
   return sh;
 }
@@ -261,14 +281,14 @@ tai::Asm16Shape shape16(tai_ctx* c, int prec, int n) {
 bool use16(tai_ctx* c, int prec, int n, int nq) {
   if (!tai::is_split16(prec) || tai::operand_kc(prec, n) > tai::asm16_max_kc() || std::getenv("TAI_ASM16_GENERIC"))
     return false;
-  const tai::Asm16Shape sh = shape16(c, prec, n);
+  const tai::Asm16Shape sh = shape16(c, prec, n, nq);
   return sh.id >= 0 && nq >= sh.nbuf;
 }
 
 int prow_of(tai_ctx* c, int prec, int n, int nq, int64_t npair) {
   int64_t t = 256;
   if (use16(c, prec, n, nq)) {
-    const int64_t r = shape16(c, prec, n).rows;
+    const int64_t r = shape16(c, prec, n, nq).rows;
     int64_t a = r, b = 256;
     while (b) {
       const int64_t tmp = a % b;
@@ -305,6 +325,70 @@ void build_items16(std::vector<int4>& out, int mol, int64_t npair, int64_t R, in
       const int64_t hi = std::min((j + 1) * chunk, ncb);
       if (lo < hi) out.push_back(int4{mol, (int)rp, (int)lo, (int)hi});
     }
+}
+
+// Whether calls of this arithmetic and degree have 16-bit kernel shapes to
+// choose between (and nobody forced one).
+bool tunable(int prec, int n) {
+  if (!tai::is_split16(prec) || tai::operand_kc(prec, n) > tai::asm16_max_kc()) return false;
+  if (std::getenv("TAI_ASM16_GENERIC") || std::getenv("TAI_ASM16_SHAPE")) return false;
+  tai::Asm16Shape list[16];
+  return tai::asm16_shapes(tai::operand_kc(prec, n), tai::operand_dup_chunks(prec, n), list, 16) > 1;
+}
+
+// Autotuner of the 16-bit kernel shape: on the first call of a signature
+// (arithmetic, degree, nodes, size class) every candidate shape runs the
+// whole call once to warm up and once timed on the caller's stream; the
+// fastest is kept for the signature.  All candidates compute every entry
+// with the same arithmetic in the same order, so the choice never changes
+// results.  `run` performs the call without a graph.
+template <class Run>
+int tune16(tai_ctx* c, int prec, int n, int nq, hipStream_t s, Run run) {
+  for (const auto& t : c->tuned)
+    if (t.prec == prec && t.n == n && t.nq == nq && t.key == c->size_key) return TAI_OK;
+  tai::Asm16Shape list[16];
+  const int cnt = tai::asm16_shapes(tai::operand_kc(prec, n), tai::operand_dup_chunks(prec, n), list, 16);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) hipEventDestroy(a);
+    return hip_fail(c, hipErrorUnknown, "hipEventCreate");
+  }
+  const bool prof = c->prof_on;
+  c->prof_on = false;
+  int best = 0, r = TAI_OK;
+  float best_ms = 0.f;
+  for (int i = 0; i < cnt && i < 16; ++i) {
+    if (nq < list[i].nbuf) continue;  // such a call takes the generic kernel
+    c->force_pick = i;
+    if ((r = run())) break;
+    hipError_t e = hipEventRecord(a, s);
+    if (e == hipSuccess && (r = run())) break;
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e != hipSuccess) {
+      r = hip_fail(c, e, "autotune timing");
+      break;
+    }
+    if (i == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = i;
+    }
+  }
+  c->force_pick = -1;
+  c->prof_on = prof;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (r) return r;
+  c->tuned.push_back({prec, n, nq, c->size_key, best});
+  return TAI_OK;
+}
+
+uint64_t pow2_at_least(int64_t v) {
+  uint64_t k = 1;
+  while ((int64_t)k < v) k <<= 1;
+  return k;
 }
 
 }  // namespace
@@ -436,16 +520,9 @@ int tai_moments(tai_ctx* c, const tai_basis* b, const tai_params* p, double* M, 
   return TAI_OK;
 }
 
-int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params* p, void* B, int64_t ldb,
-                   void* stream) {
-  int r = check_ctx(c);
-  if (r) return r;
-  if ((r = validate_params(c, p))) return r;
-  if (!M || !B) return fail(c, TAI_ERR_INVALID_ARG, "M or B is NULL");
-  if (npair < 1) return fail(c, TAI_ERR_INVALID_ARG, "npair must be >= 1");
-  if (ldb < npair) return fail(c, TAI_ERR_INVALID_ARG, "ldb must be >= npair");
-  if ((r = need_device(c))) return r;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_params* p, void* B, int64_t ldb,
+                         hipStream_t s) {
+  int r;
   const int prec = p->prec, n = p->n, nq = p->nq;
   const int prow = prow_of(c, prec, n, nq, npair);
   if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
@@ -484,7 +561,7 @@ int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params*
   m.tile0 = 0;
   if (use16(c, prec, n, nq)) {
     std::vector<int4> items;
-    const tai::Asm16Shape sh = shape16(c, prec, n);
+    const tai::Asm16Shape sh = shape16(c, prec, n, nq);
     build_items16(items, 0, npair, sh.rows, sh.cols);
     const size_t tab_bytes = align256(sizeof(tai::AsmMol)) + sizeof(int4) * items.size();
     if ((r = ensure(c, c->asm_tab, tab_bytes))) return r;
@@ -515,10 +592,31 @@ int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params*
   return TAI_OK;
 }
 
+int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params* p, void* B, int64_t ldb,
+                   void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !B) return fail(c, TAI_ERR_INVALID_ARG, "M or B is NULL");
+  if (npair < 1) return fail(c, TAI_ERR_INVALID_ARG, "npair must be >= 1");
+  if (ldb < npair) return fail(c, TAI_ERR_INVALID_ARG, "ldb must be >= npair");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  c->size_key = pow2_at_least(npair);
+  if (c->tune_mode == 1 && tunable(p->prec, p->n)) {
+    r = tune16(c, p->prec, p->n, p->nq, s, [&]() { return assemble_impl(c, M, npair, p, B, ldb, s); });
+    if (r) return r;
+  }
+  return assemble_impl(c, M, npair, p, B, ldb, s);
+}
+
+static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream_t s, bool allow_graph);
+
 int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* stream) {
   int r = check_ctx(c);
   if (r) return r;
-  if (nmol < 1 || !mols) return fail(c, TAI_ERR_INVALID_ARG, "nmol must be >= 1 and mols non-NULL");
+  if (nmol < 1 || nmol > 65535 || !mols)
+    return fail(c, TAI_ERR_INVALID_ARG, "nmol must be in 1..65535 and mols non-NULL");
   for (int i = 0; i < nmol; ++i) {
     if ((r = validate_basis(c, &mols[i].basis))) return fail(c, r, "molecule " + std::to_string(i) + ": " + c->err);
     if ((r = validate_params(c, &mols[i].params))) return fail(c, r, "molecule " + std::to_string(i) + ": " + c->err);
@@ -532,6 +630,20 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
   }
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // size class of a batch: a hash of its molecule sizes
+  uint64_t h = 1469598103934665603ull ^ (uint64_t)nmol;
+  for (int i = 0; i < nmol; ++i) h = (h ^ (uint64_t)mols[i].basis.nb) * 1099511628211ull;
+  c->size_key = h | (1ull << 63);
+  const tai_params& p0 = mols[0].params;
+  if (c->tune_mode == 1 && tunable(p0.prec, p0.n)) {
+    r = tune16(c, p0.prec, p0.n, p0.nq, s, [&]() { return batched_impl(c, nmol, mols, s, false); });
+    if (r) return r;
+  }
+  return batched_impl(c, nmol, mols, s, true);
+}
+
+static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream_t s, bool allow_graph) {
+  int r;
   const int prec = mols[0].params.prec, n = mols[0].params.n, nq = mols[0].params.nq;
   const int tile = tai::assemble_tile(prec);
 
@@ -575,15 +687,36 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
   // largest molecules first so the tail of the queue holds small items
   const bool split16 = use16(c, prec, n, nq);
   std::vector<int4> items16;
-  const tai::Asm16Shape sh16 = split16 ? shape16(c, prec, n) : tai::Asm16Shape{};
+  const tai::Asm16Shape sh16 = split16 ? shape16(c, prec, n, nq) : tai::Asm16Shape{};
   if (split16) {
     std::vector<int> order(nmol);
     for (int i = 0; i < nmol; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return am[a].npair > am[b].npair; });
     for (int i : order) build_items16(items16, i, am[i].npair, sh16.rows, sh16.cols);
   }
-  const size_t tab_bytes = align256(sizeof(tai::AsmMol) * nmol) + sizeof(int4) * items16.size();
+  // device tables: [AsmMol x nmol | PrepMol x nmol | items]
+  const size_t off_prep = align256(sizeof(tai::AsmMol) * nmol);
+  const size_t off_items = off_prep + align256(sizeof(tai::PrepMol) * nmol);
+  const size_t tab_bytes = off_items + sizeof(int4) * items16.size();
   if ((r = ensure(c, c->b_mols, tab_bytes))) return r;
+  std::vector<tai::PrepMol> prep(nmol);
+  int64_t max_npair = 0;
+  int max_prow = 0;
+  for (int i = 0; i < nmol; ++i) {
+    tai::PrepMol& q = prep[i];
+    q.omega = mols[i].params.omega;
+    q.L = mols[i].params.L;
+    q.tb = tai::carve_node_tables(static_cast<char*>(c->b_nodes.p) + off_nodes[i], nq, n);
+    q.basis = dev_basis_view(&mols[i].basis, static_cast<char*>(c->b_basis.p) + off_basis[i]);
+    q.M = mols[i].M;
+    q.npair = am[i].npair;
+    q.prow = prow[i];
+    q.A = const_cast<void*>(am[i].A);
+    q.ex = const_cast<int32_t*>(am[i].ex);
+    q.Y = const_cast<void*>(am[i].Y);
+    max_npair = std::max<int64_t>(max_npair, am[i].npair);
+    max_prow = std::max(max_prow, prow[i]);
+  }
 
   // upload bases, the molecule table and the items (outside any graph)
   const size_t host_bytes = sz_basis + tab_bytes;
@@ -591,8 +724,8 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
   char* hb = static_cast<char*>(c->b_host.p);
   for (int i = 0; i < nmol; ++i) pack_basis_host(&mols[i].basis, hb + off_basis[i]);
   std::memcpy(hb + sz_basis, am.data(), sizeof(tai::AsmMol) * nmol);
-  if (!items16.empty())
-    std::memcpy(hb + sz_basis + align256(sizeof(tai::AsmMol) * nmol), items16.data(), sizeof(int4) * items16.size());
+  std::memcpy(hb + sz_basis + off_prep, prep.data(), sizeof(tai::PrepMol) * nmol);
+  if (!items16.empty()) std::memcpy(hb + sz_basis + off_items, items16.data(), sizeof(int4) * items16.size());
   hipError_t e = hipMemcpyAsync(c->b_basis.p, hb, sz_basis, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->b_mols.p, hb + sz_basis, tab_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(c->b_host_done, s);
@@ -600,28 +733,19 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
 
   // the kernel sequence; recorded into a graph when a stream is given
   auto enqueue = [&](hipStream_t st) -> hipError_t {
-    hipError_t err = hipSuccess;
-    for (int i = 0; i < nmol && err == hipSuccess; ++i) {
-      const tai_params& pi = mols[i].params;
-      NodeTables tb = tai::carve_node_tables(static_cast<char*>(c->b_nodes.p) + off_nodes[i], nq, n);
-      err = tai::launch_nodes(pi.omega, nq, n, pi.L, pi.nodes, tb, st);
-      if (err != hipSuccess) break;
-      tai::DevBasis db = dev_basis_view(&mols[i].basis, static_cast<char*>(c->b_basis.p) + off_basis[i]);
-      err = tai::launch_moments(db, n, pi.L, tb, mols[i].M, st);
-      if (err != hipSuccess) break;
-      int32_t* ex = const_cast<int32_t*>(am[i].ex);
-      err = tai::launch_pack(prec, mols[i].M, n, am[i].npair, prow[i], const_cast<void*>(am[i].A), ex, st);
-      if (err != hipSuccess) break;
-      err = tai::launch_project(prec, mols[i].M, n, am[i].npair, prow[i], nq, tb, ex, const_cast<void*>(am[i].Y), st);
-    }
+    // preparation of every molecule, one launch per stage
+    const auto* prep_dev = reinterpret_cast<const tai::PrepMol*>(static_cast<char*>(c->b_mols.p) + off_prep);
+    hipError_t err = tai::launch_nodes_batch(prep_dev, nmol, nq, n, mols[0].params.nodes, st);
+    if (err == hipSuccess) err = tai::launch_moments_batch(prep_dev, nmol, max_npair, n, st);
+    if (err == hipSuccess) err = tai::launch_pack_batch(prec, prep_dev, nmol, max_prow, n, st);
+    if (err == hipSuccess) err = tai::launch_project_batch(prec, prep_dev, nmol, max_prow, n, nq, st);
     if (err != hipSuccess) return err;
     unsigned* counter = static_cast<unsigned*>(c->b_counter.p);
     err = tai::launch_reset_counter(counter, st);
     if (err != hipSuccess) return err;
     const auto* mols_dev = static_cast<const tai::AsmMol*>(c->b_mols.p);
     if (split16) {
-      const auto* items_dev = reinterpret_cast<const int4*>(static_cast<char*>(c->b_mols.p) +
-                                                            align256(sizeof(tai::AsmMol) * nmol));
+      const auto* items_dev = reinterpret_cast<const int4*>(static_cast<char*>(c->b_mols.p) + off_items);
       const int ni = (int)items16.size();
       const int blocks = std::min(ni, (c->cus > 0 ? c->cus : 256) * sh16.wgs_per_cu);
       return tai::launch_assemble16(prec, am[0].kc, tai::operand_dup_chunks(prec, n), sh16, mols_dev, items_dev, ni,
@@ -632,7 +756,7 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
     return tai::launch_assemble_queue(prec, mols_dev, nmol, nitems, counter, blocks, st);
   };
 
-  const bool use_graph = s != nullptr && !std::getenv("TAI_NO_GRAPH");
+  const bool use_graph = allow_graph && s != nullptr && !std::getenv("TAI_NO_GRAPH");
   if (!use_graph) {
     {
       Timed tm(c, kStBatched, s);
@@ -659,6 +783,7 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
   }
   void* bases[] = {c->b_nodes.p, c->b_basis.p, c->b_opA.p, c->b_opEx.p, c->b_opY.p, c->b_mols.p, c->b_counter.p};
   put(bases, sizeof bases);
+  put(&sh16.id, sizeof sh16.id);
   if (!c->graph || key != c->graph_key) {
     if (c->graph) {
       hipGraphExecDestroy(c->graph);
@@ -718,6 +843,15 @@ int tai_apply_J(tai_ctx* c, const double* M, int32_t nb, const tai_params* p, co
     e = tai::launch_apply_j(p->prec, M, nb, (int)npair, n, nq, tb, D, J, w, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "apply_J kernels");
+  return TAI_OK;
+}
+
+int tai_tune(tai_ctx* c, int mode) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if (mode < 0 || mode > 2) return fail(c, TAI_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
+  if (mode == 2) c->tuned.clear();
+  else c->tune_mode = mode;
   return TAI_OK;
 }
 

@@ -90,6 +90,26 @@ struct AsmMol {
   int64_t tile0;         // first linear work item of this molecule
 };
 
+// Per-molecule arguments of the preparation stages of a batch (nodes,
+// moments, operand packing and projection), read by the batch kernels at
+// blockIdx.y (nodes, moments) or blockIdx.z (pack, project).
+struct PrepMol {
+  double omega, L;
+  NodeTables tb;
+  DevBasis basis;
+  double* M;
+  int64_t npair;
+  int32_t prow;
+  void* A;
+  int32_t* ex;
+  void* Y;
+};
+hipError_t launch_nodes_batch(const PrepMol* mols, int nmol, int nq, int n, int kind, hipStream_t s);
+hipError_t launch_moments_batch(const PrepMol* mols, int nmol, int64_t max_npair, int n, hipStream_t s);
+hipError_t launch_pack_batch(int prec, const PrepMol* mols, int nmol, int max_prow, int n, hipStream_t s);
+hipError_t launch_project_batch(int prec, const PrepMol* mols, int nmol, int max_prow, int n, int nq,
+                                hipStream_t s);
+
 hipError_t launch_pack(int prec, const double* M, int n, int npair, int prow,
                        void* A, int32_t* ex, hipStream_t s);
 hipError_t launch_project(int prec, const double* M, int n, int npair, int prow, int nq,
@@ -116,10 +136,11 @@ struct Asm16Shape {
   int kc_key, q_key;  // the (kc, q) the shape was chosen for
 };
 int asm16_max_kc();
-// Shapes that compile for (kc, q), best first; `asm16_shape` picks the first
-// unless TAI_ASM16_SHAPE names another table index.
+// Shapes that compile for (kc, q), the table default first; asm16_shape
+// returns candidate `pick` (0 if out of range) with its resident work
+// groups per CU filled in from the runtime (device must be current).
 int asm16_shapes(int kc, int q, Asm16Shape* out, int cap);
-Asm16Shape asm16_shape(int kc, int q);
+Asm16Shape asm16_shape(int kc, int q, int pick);
 hipError_t launch_assemble16(int prec, int kc, int q, const Asm16Shape& shape, const AsmMol* mols_dev,
                              const int4* items_dev, int nitems, unsigned* counter, int nblocks, hipStream_t s);
 inline bool is_split16(int prec) { return prec == kBF16X3 || prec == kBF16X6 || prec == kF16X3; }

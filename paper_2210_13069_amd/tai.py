@@ -29,7 +29,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 # exported symbols declared in include/tai.h
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
            "tai_quadrature", "tai_moments", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
-           "tai_profile_enable", "tai_profile_read"]
+           "tai_tune", "tai_profile_enable", "tai_profile_read"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched"]
 
 
@@ -182,6 +182,10 @@ class Context:
         arr = (tai_mol * len(mols))(*mols)
         self.check(self.lib.tai_assemble_B_batched(self.h, len(mols), arr, _stream(stream)),
                    "tai_assemble_B_batched")
+
+    def tune(self, mode):
+        """0: table default shapes, 1: tune each new signature once, 2: forget choices."""
+        self.check(self.lib.tai_tune(self.h, int(mode)), "tai_tune")
 
     def profile_enable(self, enable=True):
         self.check(self.lib.tai_profile_enable(self.h, int(bool(enable))), "tai_profile_enable")

@@ -40,6 +40,14 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, name), name
 
 
+def test_tune_modes(lib, hctx):
+    for mode in (0, 1, 2):
+        assert lib.tai_tune(hctx.h, mode) == tai.TAI_OK
+    for mode in (-1, 3):
+        assert lib.tai_tune(hctx.h, mode) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_tune(None, 1) == tai.TAI_ERR_INVALID_ARG
+
+
 def test_status_strings(lib):
     for st in (0, -1, -2, -3, -4, -5, 7):
         s = lib.tai_status_string(st)

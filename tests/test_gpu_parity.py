@@ -150,6 +150,49 @@ def test_assemble_matches_stored_tiny_s(tai):
         assert _normwise(Bg, ref) <= (1e-10 if prec == 0 else LOWP_TOL[prec]), prec
 
 
+@pytest.mark.parametrize("case", ["sp16", "spd_small"])
+def test_assemble_shapes_agree_bitwise(tai, case):
+    """Every compiled 16-bit kernel shape (forced through TAI_ASM16_SHAPE)
+    gives the same bits, so the autotuner's choice never changes results."""
+    import os
+    if case == "sp16":
+        b, P = I.sp16()                                   # n = 32: kc 96
+    else:
+        b = I.small_random(45, natoms=8, shells=("s", "p", "d"), box=3.0)
+        P = I.Params(omega=0.4, nq=7, n=40, L=8.0)        # n = 40: kc 128
+    Mg = tai.moments(b, P)
+    old = os.environ.get("TAI_ASM16_SHAPE")
+    try:
+        outs = []
+        for pick in range(8):
+            os.environ["TAI_ASM16_SHAPE"] = str(pick)
+            outs.append(tai.assemble_B(Mg, P, prec=4).cpu().numpy())
+    finally:
+        if old is None:
+            os.environ.pop("TAI_ASM16_SHAPE", None)
+        else:
+            os.environ["TAI_ASM16_SHAPE"] = old
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_autotune_keeps_results(tai):
+    """A tuned call (first call of its signature) and later calls agree
+    bitwise with the table default shape."""
+    import torch
+    b, P = I.sp16()
+    ctx = tai.Context(0)
+    Mg = tai.moments(b, P)
+    params = tai.make_params(P, tai.F16X3)
+    outs = []
+    for mode in (0, 1, 1):
+        ctx.tune(mode)
+        B = torch.empty((b.npair, b.npair), dtype=torch.float32, device=Mg.device)
+        ctx.assemble_B(Mg, b.npair, params, B)
+        outs.append(B.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+
+
 def test_assemble_deterministic(tai):
     b, P = I.sp16()
     Mg = tai.moments(b, P)
@@ -226,7 +269,11 @@ def test_apply_J_equals_B_times_density(tai):
     assert np.max(np.abs(Jg.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-def test_batched_equals_per_molecule(tai):
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_equals_per_molecule(tai, graph):
+    """Direct launches (default stream) and hipGraph replays (a side stream):
+    every replay, with eager work and synchronization in between, equals the
+    per-molecule calls bit for bit."""
     import torch
     mols = I.batch64(nmol=6)
     ctx = tai.context(0)
@@ -240,10 +287,12 @@ def test_batched_equals_per_molecule(tai):
         Ms.append(M)
         outs.append(B)
         structs.append(tai.tai_mol(ba.struct, tai.make_params(P, tai.F16X3), M.data_ptr(), B.data_ptr(), b.npair))
+    stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
     for rep in range(3):
         for B in outs:
             B.fill_(float("nan"))
-        ctx.assemble_B_batched(structs)
+        torch.cuda.synchronize()
+        ctx.assemble_B_batched(structs, stream=stream)
         torch.cuda.synchronize()
         for (b, P), M, B in zip(mols, Ms, outs):
             Mref = tai.moments(b, P)
