@@ -161,152 +161,93 @@ __device__ inline void pack_body(int prec, const double* __restrict__ M, int n, 
   tile_store(prec, kc, tile, sw, reinterpret_cast<uint32_t*>(A + (((int64_t)d * prow + row0) * kc) * es));
 }
 
-// grid (prow / kRowsPerTile, 3 nq): Y_{k,d} rows = (K_k M_d)(:, q) scaled by
-// 2^-e(q,d), and by w_k for d = 2; FP64 arithmetic.  K_k is staged in LDS,
-// zero padded to NMAX x NMAX, and read at wave-uniform addresses.
-template <int NMAX>
-__device__ inline void project_body(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
-                                    int kc, const double* __restrict__ K, const double* __restrict__ w,
-                                    const int32_t* __restrict__ ex, char* __restrict__ Y) {
-  extern __shared__ uint32_t tile[];
-  const int sl = blockIdx.y;
-  const int k = sl / 3, d = sl - 3 * (sl / 3);
+// Y_{k,d} rows, (K_k M_d)(:, q) scaled by 2^-e(q,d) (and by w_k for d = 2),
+// in the operand format of prec, for 64 rows q and one direction d over all
+// nodes k.  The product runs on the FP64 matrix cores (v_mfma_f64_16x16x4):
+// wave w holds the A fragments M_d(b, q) of rows q0 + 16 w .. +16 for the
+// whole kernel; per node, K_k is staged in LDS (zero padded to NP x NP, the
+// next node's values in registers during the MFMAs), the 16 x NP output of
+// each wave is split into slices into an LDS tile of 64 rows, and the tile
+// leaves as one contiguous block of Y.
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+template <int NT, int PREC>
+__device__ inline void project_mfma_body(const double* __restrict__ M, int n, int64_t npair, int prow,
+                                         int nq, int kc, const double* __restrict__ K,
+                                         const double* __restrict__ w, const int32_t* __restrict__ ex,
+                                         char* __restrict__ Y) {
+  constexpr int prec = PREC;
+  constexpr int NP = 16 * NT, NK = NP / 4, PS = NP + 1;
+  constexpr int KPER = (NP * NP + 255) / 256;  // staged K values per thread
+  extern __shared__ double smem[];
+  double* Ks = smem;                                            // [NP][PS]
+  uint32_t* tile = reinterpret_cast<uint32_t*>(smem + NP * PS);  // [64][sw]
+  const int d = blockIdx.y;
   const int64_t row0 = (int64_t)blockIdx.x * kRowsPerTile;
-  const int64_t q = row0 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, kg = lane >> 4;
   const int sw = tile_stride_words(prec, kc);
-  uint32_t* row = tile + threadIdx.x * sw;
-  double* Ks = reinterpret_cast<double*>(tile + ((kRowsPerTile * sw + 1) & ~1));
-  const double* Kk = K + (int64_t)k * n * n;
-  for (int i = threadIdx.x; i < NMAX * NMAX; i += kRowsPerTile) {
-    const int a = i / NMAX, b = i - a * NMAX;
-    Ks[i] = (a < n && b < n) ? Kk[a * n + b] : 0.0;
-  }
-  double m[NMAX];
-#pragma unroll
-  for (int b = 0; b < NMAX; ++b) m[b] = 0.0;
-  double scale = 0.0;
-  if (q < npair) {
-#pragma unroll
-    for (int b = 0; b < NMAX; ++b)
-      if (b < n) m[b] = M[((int64_t)d * n + b) * npair + q];
-    scale = ldexp(1.0, -ex[(int64_t)d * prow + q]);
-    if (d == 2) scale *= w[k];
-  }
-  __syncthreads();
-  for (int a = 0; a < n; ++a) {
-    const double* kr = Ks + a * NMAX;
-    double s = 0.0;
-#pragma unroll
-    for (int b = 0; b < NMAX; ++b) s += kr[b] * m[b];
-    tile_elem(prec, 1, s * scale, n, a, row);
-  }
-  tile_pad(prec, n, kc, row);
-  __syncthreads();
   const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
-  tile_store(prec, kc, tile, sw, reinterpret_cast<uint32_t*>(Y + ((((int64_t)k * 3 + d) * prow + row0) * kc) * es));
-}
 
-// Same contraction for n % 8 == 0 with direct 16-byte stores: 256 rows per
-// work group (one per thread), eight outputs at a time, each slice segment
-// written as aligned 16-byte vectors; full rows are merged in L2 before they
-// reach HBM.  K_k is staged once per work group in LDS, zero padded.
-template <typename T>
-__device__ inline void store8(char* rowp, int pos, const T (&v)[8]) {
-  if constexpr (sizeof(T) == 2) {
-    uint4 u;
-    unsigned short h[8];
+  // A fragments: row q = row0 + 16 w + l%16, inner index b = 4 s + l/16
+  double am[NK];
+  {
+    const int64_t q = row0 + 16 * wave + r16;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) h[i] = __builtin_bit_cast(unsigned short, v[i]);
-    u.x = h[0] | ((uint32_t)h[1] << 16);
-    u.y = h[2] | ((uint32_t)h[3] << 16);
-    u.z = h[4] | ((uint32_t)h[5] << 16);
-    u.w = h[6] | ((uint32_t)h[7] << 16);
-    *reinterpret_cast<uint4*>(rowp + 2 * pos) = u;
-  } else {
-#pragma unroll
-    for (int i = 0; i < 8; i += 16 / (int)sizeof(T))
-      *reinterpret_cast<uint4*>(rowp + sizeof(T) * (pos + i)) = *reinterpret_cast<const uint4*>(&v[i]);
-  }
-}
-
-template <int NMAX>
-__device__ inline void project8_body(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
-                                     int kc, const double* __restrict__ K, const double* __restrict__ w,
-                                     const int32_t* __restrict__ ex, char* __restrict__ Y) {
-  __shared__ double Ks[NMAX * NMAX];
-  const int sl = blockIdx.y;
-  const int k = sl / 3, d = sl - 3 * (sl / 3);
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const double* Kk = K + (int64_t)k * n * n;
-  for (int i = threadIdx.x; i < NMAX * NMAX; i += 256) {
-    const int a = i / NMAX, b = i - a * NMAX;
-    Ks[i] = (a < n && b < n) ? Kk[a * n + b] : 0.0;
-  }
-  double m[NMAX];
-#pragma unroll
-  for (int b = 0; b < NMAX; ++b) m[b] = 0.0;
-  double scale = 0.0;
-  if (q < npair) {
-#pragma unroll
-    for (int b = 0; b < NMAX; ++b)
-      if (b < n) m[b] = M[((int64_t)d * n + b) * npair + q];
-    scale = ldexp(1.0, -ex[(int64_t)d * prow + q]);
-    if (d == 2) scale *= w[k];
-  }
-  __syncthreads();
-  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
-  char* rowp = Y + ((((int64_t)k * 3 + d) * prow + q) * kc) * es;
-  for (int a0 = 0; a0 < n; a0 += 8) {
-    double y[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const double* kr = Ks + (a0 + i) * NMAX;
-      double s = 0.0;
-#pragma unroll
-      for (int b = 0; b < NMAX; ++b) s += kr[b] * m[b];
-      y[i] = s * scale;
-    }
-    if (prec == kFP64) {
-      store8<double>(rowp, a0, y);
-    } else if (prec == kFP32) {
-      float f[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) f[i] = (float)y[i];
-      store8<float>(rowp, a0, f);
-    } else if (prec == kF16X3) {
-      _Float16 h0[8], h1[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        h0[i] = to_slice<_Float16>(y[i]);
-        h1[i] = to_slice<_Float16>(y[i] - (double)h0[i]);
-      }
-      // Y = [h0 | h1 | h0]
-      store8<_Float16>(rowp, seg_pos(prec, n, 0, a0), h0);
-      store8<_Float16>(rowp, seg_pos(prec, n, 1, a0), h1);
-      store8<_Float16>(rowp, seg_pos(prec, n, 2, a0), h0);
-    } else {
-      __bf16 s0[8], s1[8], s2[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        s0[i] = to_slice<__bf16>(y[i]);
-        const double r1 = y[i] - (double)(float)s0[i];
-        s1[i] = to_slice<__bf16>(r1);
-        s2[i] = to_slice<__bf16>(r1 - (double)(float)s1[i]);
-      }
-      // BF16X3: Y = [s0 | s1 | s0];  BF16X6: Y = [s0|s1|s0|s2|s1|s0]
-      store8<__bf16>(rowp, seg_pos(prec, n, 0, a0), s0);
-      store8<__bf16>(rowp, seg_pos(prec, n, 1, a0), s1);
-      store8<__bf16>(rowp, seg_pos(prec, n, 2, a0), s0);
-      if (prec == kBF16X6) {
-        store8<__bf16>(rowp, 3 * n + a0, s2);
-        store8<__bf16>(rowp, 4 * n + a0, s1);
-        store8<__bf16>(rowp, 5 * n + a0, s0);
-      }
+    for (int st = 0; st < NK; ++st) {
+      const int bb = 4 * st + kg;
+      am[st] = (q < npair && bb < n) ? M[((int64_t)d * n + bb) * npair + q] : 0.0;
     }
   }
-  // zero tail [nseg*n, kc): a multiple of 8 elements, 16-byte aligned
-  const int nseg = (prec == kFP64 || prec == kFP32) ? 1 : (prec == kBF16X6 ? 6 : 3);
-  for (int c = nseg * n * es; c < kc * es; c += 16) *reinterpret_cast<uint4*>(rowp + c) = uint4{0u, 0u, 0u, 0u};
+  // the scale 2^-e of this lane's output rows 16 w + l/16 + 4 r
+  double rs[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t q = row0 + 16 * wave + kg + 4 * r;
+    rs[r] = q < npair ? ldexp(1.0, -ex[(int64_t)d * prow + q]) : 0.0;
+  }
+  // padding columns of the tile are zero for every node
+  for (int r = threadIdx.x; r < kRowsPerTile; r += 256) tile_pad(prec, n, kc, tile + r * sw);
+
+  double kp[KPER];
+  auto load_k = [&](int k) {
+    const double* Kk = K + (int64_t)k * n * n;
+#pragma unroll
+    for (int i = 0; i < KPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int a = e / NP, bb = e % NP;
+      kp[i] = (e < NP * NP && a < n && bb < n) ? Kk[a * n + bb] : 0.0;
+    }
+  };
+  load_k(0);
+  for (int k = 0; k < nq; ++k) {
+    __syncthreads();  // previous node: Ks read and the tile copied out
+#pragma unroll
+    for (int i = 0; i < KPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < NP * NP) Ks[(e / NP) * PS + e % NP] = kp[i];
+    }
+    __syncthreads();
+    if (k + 1 < nq) load_k(k + 1);
+    const double wk = (d == 2) ? w[k] : 1.0;
+    // one column tile at a time: its fragments, MFMAs and slices
+#pragma unroll 1
+    for (int j = 0; j < NT; ++j) {
+      v4d_t acc = v4d_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < NK; ++st)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(am[st], Ks[(16 * j + r16) * PS + 4 * st + kg], acc, 0, 0, 0);
+      // lane l holds column a = 16 j + l%16, rows l/16 + 4 r
+      const int a = 16 * j + r16;
+      if (a < n) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          tile_elem(prec, 1, acc[r] * (rs[r] * wk), n, a, tile + (16 * wave + kg + 4 * r) * sw);
+      }
+    }
+    __syncthreads();
+    tile_store(prec, kc, tile, sw, reinterpret_cast<uint32_t*>(Y + ((((int64_t)k * 3 + d) * prow + row0) * kc) * es));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -542,36 +483,27 @@ pack_batch_kernel(int prec, const PrepMol* __restrict__ mols, int n, int kc) {
   pack_body<NMAX>(prec, m.M, n, m.npair, m.prow, kc, static_cast<char*>(m.A), m.ex);
 }
 
-template <int NMAX>
-__global__ void __launch_bounds__(kRowsPerTile)
-project_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
+template <int NT, int PREC>
+__global__ void __launch_bounds__(256, 3)
+project_kernel(const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
                int kc, const double* __restrict__ K, const double* __restrict__ w,
                const int32_t* __restrict__ ex, char* __restrict__ Y) {
-  project_body<NMAX>(prec, M, n, npair, prow, nq, kc, K, w, ex, Y);
+  project_mfma_body<NT, PREC>(M, n, npair, prow, nq, kc, K, w, ex, Y);
 }
 
-template <int NMAX>
-__global__ void __launch_bounds__(kRowsPerTile)
-project_batch_kernel(int prec, const PrepMol* __restrict__ mols, int n, int nq, int kc) {
+template <int NT, int PREC>
+__global__ void __launch_bounds__(256, 3)
+project_batch_kernel(const PrepMol* __restrict__ mols, int n, int nq, int kc) {
   const PrepMol& m = mols[blockIdx.z];
   if ((int64_t)blockIdx.x * kRowsPerTile >= m.prow) return;
-  project_body<NMAX>(prec, m.M, n, m.npair, m.prow, nq, kc, m.tb.K, m.tb.w, m.ex, static_cast<char*>(m.Y));
+  project_mfma_body<NT, PREC>(m.M, n, m.npair, m.prow, nq, kc, m.tb.K, m.tb.w, m.ex, static_cast<char*>(m.Y));
 }
 
-template <int NMAX>
-__global__ void __launch_bounds__(256)
-project8_kernel(int prec, const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
-                int kc, const double* __restrict__ K, const double* __restrict__ w,
-                const int32_t* __restrict__ ex, char* __restrict__ Y) {
-  project8_body<NMAX>(prec, M, n, npair, prow, nq, kc, K, w, ex, Y);
-}
-
-template <int NMAX>
-__global__ void __launch_bounds__(256)
-project8_batch_kernel(int prec, const PrepMol* __restrict__ mols, int n, int nq, int kc) {
-  const PrepMol& m = mols[blockIdx.z];
-  if ((int64_t)blockIdx.x * 256 >= m.prow) return;
-  project8_body<NMAX>(prec, m.M, n, m.npair, m.prow, nq, kc, m.tb.K, m.tb.w, m.ex, static_cast<char*>(m.Y));
+size_t project_lds(int prec, int n) {
+  const int NP = (n + 15) / 16 * 16;
+  const int kc = operand_kc(prec, n);
+  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
+  return sizeof(double) * NP * (NP + 1) + sizeof(uint32_t) * kRowsPerTile * (kc * es / 4 + 1);
 }
 
 template <int NMAX>
@@ -585,21 +517,24 @@ hipError_t launch_pack_t(int prec, const double* M, int n, int npair, int prow, 
   return hipGetLastError();
 }
 
-template <int NMAX>
+template <int NT, int PREC>
+hipError_t launch_project_p(const double* M, int n, int npair, int prow, int nq, const NodeTables& tb,
+                            const int32_t* ex, void* Y, hipStream_t s) {
+  hipLaunchKernelGGL((project_kernel<NT, PREC>), dim3(prow / kRowsPerTile, 3), dim3(256), project_lds(PREC, n), s,
+                     M, n, (int64_t)npair, prow, nq, operand_kc(PREC, n), tb.K, tb.w, ex, static_cast<char*>(Y));
+  return hipGetLastError();
+}
+
+template <int NT>
 hipError_t launch_project_t(int prec, const double* M, int n, int npair, int prow, int nq,
                             const NodeTables& tb, const int32_t* ex, void* Y, hipStream_t s) {
-  const int kc = operand_kc(prec, n);
-  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
-  if (n % 8 == 0 && prow % 256 == 0) {
-    hipLaunchKernelGGL(project8_kernel<NMAX>, dim3(prow / 256, 3 * nq), dim3(256), 0, s,
-                       prec, M, n, (int64_t)npair, prow, nq, kc, tb.K, tb.w, ex, static_cast<char*>(Y));
-    return hipGetLastError();
+  switch (prec) {
+    case kFP64: return launch_project_p<NT, kFP64>(M, n, npair, prow, nq, tb, ex, Y, s);
+    case kFP32: return launch_project_p<NT, kFP32>(M, n, npair, prow, nq, tb, ex, Y, s);
+    case kF16X3: return launch_project_p<NT, kF16X3>(M, n, npair, prow, nq, tb, ex, Y, s);
+    case kBF16X3: return launch_project_p<NT, kBF16X3>(M, n, npair, prow, nq, tb, ex, Y, s);
+    default: return launch_project_p<NT, kBF16X6>(M, n, npair, prow, nq, tb, ex, Y, s);
   }
-  const size_t tile_words = ((size_t)kRowsPerTile * (kc * es / 4 + 1) + 1) & ~size_t(1);
-  const size_t lds = sizeof(uint32_t) * tile_words + sizeof(double) * NMAX * NMAX;
-  hipLaunchKernelGGL(project_kernel<NMAX>, dim3(prow / kRowsPerTile, 3 * nq), dim3(kRowsPerTile), lds, s,
-                     prec, M, n, (int64_t)npair, prow, nq, kc, tb.K, tb.w, ex, static_cast<char*>(Y));
-  return hipGetLastError();
 }
 
 template <int NMAX>
@@ -612,22 +547,23 @@ hipError_t launch_pack_batch_t(int prec, const PrepMol* mols, int nmol, int max_
   return hipGetLastError();
 }
 
-// every prow of a batch is a multiple of 256 (the host pads rows to it)
-template <int NMAX>
+template <int NT, int PREC>
+hipError_t launch_project_batch_p(const PrepMol* mols, int nmol, int max_prow, int n, int nq, hipStream_t s) {
+  hipLaunchKernelGGL((project_batch_kernel<NT, PREC>), dim3(max_prow / kRowsPerTile, 3, nmol), dim3(256),
+                     project_lds(PREC, n), s, mols, n, nq, operand_kc(PREC, n));
+  return hipGetLastError();
+}
+
+template <int NT>
 hipError_t launch_project_batch_t(int prec, const PrepMol* mols, int nmol, int max_prow, int n, int nq,
                                   hipStream_t s) {
-  const int kc = operand_kc(prec, n);
-  const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
-  if (n % 8 == 0) {
-    hipLaunchKernelGGL(project8_batch_kernel<NMAX>, dim3(max_prow / 256, 3 * nq, nmol), dim3(256), 0, s,
-                       prec, mols, n, nq, kc);
-    return hipGetLastError();
+  switch (prec) {
+    case kFP64: return launch_project_batch_p<NT, kFP64>(mols, nmol, max_prow, n, nq, s);
+    case kFP32: return launch_project_batch_p<NT, kFP32>(mols, nmol, max_prow, n, nq, s);
+    case kF16X3: return launch_project_batch_p<NT, kF16X3>(mols, nmol, max_prow, n, nq, s);
+    case kBF16X3: return launch_project_batch_p<NT, kBF16X3>(mols, nmol, max_prow, n, nq, s);
+    default: return launch_project_batch_p<NT, kBF16X6>(mols, nmol, max_prow, n, nq, s);
   }
-  const size_t tile_words = ((size_t)kRowsPerTile * (kc * es / 4 + 1) + 1) & ~size_t(1);
-  const size_t lds = sizeof(uint32_t) * tile_words + sizeof(double) * NMAX * NMAX;
-  hipLaunchKernelGGL(project_batch_kernel<NMAX>, dim3(max_prow / kRowsPerTile, 3 * nq, nmol), dim3(kRowsPerTile),
-                     lds, s, prec, mols, n, nq, kc);
-  return hipGetLastError();
 }
 
 }  // namespace
@@ -641,10 +577,10 @@ hipError_t launch_pack_batch(int prec, const PrepMol* mols, int nmol, int max_pr
 
 hipError_t launch_project_batch(int prec, const PrepMol* mols, int nmol, int max_prow, int n, int nq,
                                 hipStream_t s) {
-  if (n <= 16) return launch_project_batch_t<16>(prec, mols, nmol, max_prow, n, nq, s);
-  if (n <= 32) return launch_project_batch_t<32>(prec, mols, nmol, max_prow, n, nq, s);
-  if (n <= 48) return launch_project_batch_t<48>(prec, mols, nmol, max_prow, n, nq, s);
-  return launch_project_batch_t<64>(prec, mols, nmol, max_prow, n, nq, s);
+  if (n <= 16) return launch_project_batch_t<1>(prec, mols, nmol, max_prow, n, nq, s);
+  if (n <= 32) return launch_project_batch_t<2>(prec, mols, nmol, max_prow, n, nq, s);
+  if (n <= 48) return launch_project_batch_t<3>(prec, mols, nmol, max_prow, n, nq, s);
+  return launch_project_batch_t<4>(prec, mols, nmol, max_prow, n, nq, s);
 }
 
 int operand_esize(int prec) {
@@ -675,10 +611,10 @@ hipError_t launch_pack(int prec, const double* M, int n, int npair, int prow, vo
 
 hipError_t launch_project(int prec, const double* M, int n, int npair, int prow, int nq,
                           const NodeTables& tb, const int32_t* ex, void* Y, hipStream_t s) {
-  if (n <= 16) return launch_project_t<16>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
-  if (n <= 32) return launch_project_t<32>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
-  if (n <= 48) return launch_project_t<48>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
-  return launch_project_t<64>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
+  if (n <= 16) return launch_project_t<1>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
+  if (n <= 32) return launch_project_t<2>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
+  if (n <= 48) return launch_project_t<3>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
+  return launch_project_t<4>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
 }
 
 hipError_t launch_assemble(int prec, const AsmMol& m, hipStream_t s) {
