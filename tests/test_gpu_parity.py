@@ -299,3 +299,40 @@ def test_batched_equals_per_molecule(tai, graph):
             assert torch.equal(M, Mref)
             Bref = tai.assemble_B(Mref, P, prec=tai.F16X3)
             assert torch.equal(B, Bref), f"replay {rep}"
+
+
+@pytest.mark.parametrize("case", ["one_function", "n2_nq1", "n64_nq128", "gauss_nodes_d"])
+def test_assemble_and_J_edge_cases(tai, case):
+    """Degenerate and extreme sizes for every arithmetic: a single basis
+    function (one pair), the smallest degree and node count, the largest
+    degree with the largest node count (BF16X6 then exceeds the persistent
+    kernel's inner length and takes the generic kernel), and Gauss-Chebyshev
+    nodes with d functions; J in FP64 and FP32 for the same inputs."""
+    import torch
+    rng = np.random.default_rng(77)
+    if case == "one_function":
+        b = I.random_molecule(rng, 1, 1.0, ["s"], 0.5, 2.0)
+        P = I.Params(omega=0.5, nq=8, n=16, L=6.0)
+    elif case == "n2_nq1":
+        b = I.small_random(51, natoms=2, shells=("s",), box=1.0)
+        P = I.Params(omega=0.3, nq=1, n=2, L=4.0)
+    elif case == "n64_nq128":
+        b = I.small_random(52, natoms=2, shells=("s", "p"), box=2.0)
+        P = I.Params(omega=1.0, nq=128, n=64, L=6.0)
+    else:
+        b = I.small_random(53, natoms=3, shells=("s", "d"), box=2.0)
+        P = I.Params(omega=0.5, nq=10, n=30, L=7.0, nodes=1)
+    Mr, K, w = _oracle(b, P)
+    Br = T.B_full(Mr, K, w)
+    Mg = tai.moments(b, P)
+    for prec in (0, 1, 2, 3, 4):
+        Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+        assert Bg.shape == (b.npair, b.npair)
+        tol = 1e-10 if prec == 0 else LOWP_TOL[prec]
+        assert _normwise(Bg, Br) <= tol, (case, prec, _normwise(Bg, Br))
+    D = I.random_density(np.random.default_rng(4), b)
+    Jr = T.J_grid(Mr, K, w, D)
+    for prec, tol in ((0, 1e-10), (1, 1e-6)):
+        Jg = tai.apply_J(Mg, torch.as_tensor(D, device=Mg.device), P, prec=prec).cpu().numpy()
+        err = np.linalg.norm(Jg - Jr) / np.linalg.norm(Jr)
+        assert err <= tol, (case, prec, err)
