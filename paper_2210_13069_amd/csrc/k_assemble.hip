@@ -463,7 +463,9 @@ assemble_queue_kernel(const AsmMol* __restrict__ mols, int nmol, int64_t nitems,
   }
 }
 
-__global__ void reset_counter_kernel(unsigned* c) { *c = 0u; }
+__global__ void reset_counter_kernel(unsigned* c) {
+  if (threadIdx.x < kAsm16Queues) c[threadIdx.x] = 0u;
+}
 
 // Single-molecule kernels and their batch forms: blockIdx.z = molecule of
 // the batch; blocks beyond a molecule's padded rows return at once (the
@@ -630,7 +632,7 @@ hipError_t launch_assemble(int prec, const AsmMol& m, hipStream_t s) {
 }
 
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 constexpr double kTwoOverSqrtPi = 1.1283791670955126;
 constexpr int kGroup16 = 8;  // FP32 accumulation group of quadrature nodes
+constexpr int kQueues = kAsm16Queues;
 
 // Compile-time shape: NW waves per work group, RB row blocks of 16 per wave,
 // CB column blocks of 16 per item block, an LDS ring of NBUF nodes.
@@ -357,10 +358,14 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
 }
 
 // Two waves per SIMD: one work group of 8 (or 12) waves, or two of 4.
+// Work groups are dealt to the 8 XCDs round-robin by index, so work group b
+// drains queue b % 8 first: queue x holds the column runs x, x + 8, ... of
+// every molecule, and the work groups sharing an XCD's L2 share their Y
+// blocks.  A drained queue sends the work group on to the next one.
 template <class C, bool BF>
 __global__ void __launch_bounds__(C::NT, C::NW_ >= 8 ? 1 : 8 / C::NW_)
-assemble16_kernel(const AsmMol* __restrict__ mols, const int4* __restrict__ items, int nitems,
-                  unsigned* __restrict__ counter) {
+assemble16_kernel(const AsmMol* __restrict__ mols, const int4* __restrict__ items, const int* __restrict__ seg,
+                  unsigned* __restrict__ counters) {
   __shared__ uint4 yb0[C::NFRAG * 64];
   __shared__ uint4 yb1[C::NFRAG * 64];
   __shared__ uint4 yb2[C::NBUF_ == 3 ? C::NFRAG * 64 : 1];
@@ -368,12 +373,20 @@ assemble16_kernel(const AsmMol* __restrict__ mols, const int4* __restrict__ item
   __shared__ int erow_s[C::ROWS];
   __shared__ int ecol_s[C::ITEM_COLS];
   __shared__ int item_s;
-  for (;;) {
+  const int home = blockIdx.x % kQueues;
+  for (int probe = 0; probe < kQueues;) {
+    const int qi = (home + probe) % kQueues;
     __syncthreads();  // the previous item is done with every LDS buffer
-    if (threadIdx.x == 0) item_s = (int)atomicAdd(counter, 1u);
+    if (threadIdx.x == 0) {
+      const int i = (int)atomicAdd(counters + qi, 1u);
+      item_s = (i < seg[qi + 1] - seg[qi]) ? seg[qi] + i : -1;
+    }
     __syncthreads();
     const int it = item_s;
-    if (it >= nitems) break;
+    if (it < 0) {
+      ++probe;
+      continue;
+    }
     const int4 item = items[it];
     const AsmMol m = mols[item.x];
     run_item<C, BF>(m, item.y, item.z, item.w, yb0, yb1, yb2, sums, erow_s, ecol_s);
@@ -381,12 +394,12 @@ assemble16_kernel(const AsmMol* __restrict__ mols, const int4* __restrict__ item
 }
 
 template <class C>
-hipError_t launch_shape(bool bf, const AsmMol* mols, const int4* items, int nitems, unsigned* counter, int nblocks,
-                        hipStream_t s) {
+hipError_t launch_shape(bool bf, const AsmMol* mols, const int4* items, const int* seg, unsigned* counters,
+                        int nblocks, hipStream_t s) {
   if (bf)
-    hipLaunchKernelGGL((assemble16_kernel<C, true>), dim3(nblocks), dim3(C::NT), 0, s, mols, items, nitems, counter);
+    hipLaunchKernelGGL((assemble16_kernel<C, true>), dim3(nblocks), dim3(C::NT), 0, s, mols, items, seg, counters);
   else
-    hipLaunchKernelGGL((assemble16_kernel<C, false>), dim3(nblocks), dim3(C::NT), 0, s, mols, items, nitems, counter);
+    hipLaunchKernelGGL((assemble16_kernel<C, false>), dim3(nblocks), dim3(C::NT), 0, s, mols, items, seg, counters);
   return hipGetLastError();
 }
 
@@ -401,7 +414,7 @@ int resident_wgs() {
   return n > 0 ? n : 1;
 }
 
-using LaunchFn = hipError_t (*)(bool, const AsmMol*, const int4*, int, unsigned*, int, hipStream_t);
+using LaunchFn = hipError_t (*)(bool, const AsmMol*, const int4*, const int*, unsigned*, int, hipStream_t);
 struct ShapeEntry {
   int kc, q, nw, rb, cb, nbuf;
   LaunchFn launch;
@@ -477,11 +490,12 @@ Asm16Shape asm16_shape(int kc, int q, int pick) {
 }
 
 hipError_t launch_assemble16(int prec, int kc, int q, const Asm16Shape& shape, const AsmMol* mols_dev,
-                             const int4* items_dev, int nitems, unsigned* counter, int nblocks, hipStream_t s) {
+                             const int4* items_dev, const int* seg_dev, unsigned* counters, int nblocks,
+                             hipStream_t s) {
   if (shape.id < 0 || shape.id >= (int)(sizeof(kShapes) / sizeof(kShapes[0])) || kShapes[shape.id].kc != kc ||
       kShapes[shape.id].q != q)
     return hipErrorInvalidValue;
-  return kShapes[shape.id].launch(prec != kF16X3, mols_dev, items_dev, nitems, counter, nblocks, s);
+  return kShapes[shape.id].launch(prec != kF16X3, mols_dev, items_dev, seg_dev, counters, nblocks, s);
 }
 
 }  // namespace tai

@@ -309,23 +309,47 @@ size_t opY_bytes(int prec, int n, int nq, int prow) {
 size_t opEx_bytes(int prow) { return align256(sizeof(int32_t) * 3 * (size_t)prow); }
 
 // Work items of the 16-bit assembly kernel for one molecule: row panels of
-// R rows x ranges of up to kChunk 32-column blocks, restricted to blocks that
-// hold entries with col >= row; column-chunk-major so that concurrently
-// running work groups share the Y blocks.
-// Work items of one molecule: (row panel of R rows) x (runs of up to 512
-// columns in blocks of C), upper triangle only, ordered column-run-major so
-// that work groups running together share the Y blocks in L2.
-void build_items16(std::vector<int4>& out, int mol, int64_t npair, int64_t R, int64_t C) {
-  const int64_t chunk = std::max<int64_t>(1, 512 / C);
-  const int64_t ncb = (npair + C - 1) / C;
-  const int64_t nrp = (npair + R - 1) / R;
-  for (int64_t j = 0; j * chunk < ncb; ++j)
-    for (int64_t rp = 0; rp < nrp; ++rp) {
-      const int64_t lo = std::max(j * chunk, rp * R / C);
-      const int64_t hi = std::min((j + 1) * chunk, ncb);
-      if (lo < hi) out.push_back(int4{mol, (int)rp, (int)lo, (int)hi});
+// Work items of the 16-bit kernel: (molecule, row panel of R rows, run of up
+// to 512 columns in blocks of C), upper triangle only.  Column runs are
+// dealt round-robin to the kAsm16Queues queues (one per XCD; `rr` carries
+// the deal across molecules), each queue ordered column-run-major so that
+// the work groups of an XCD share the Y blocks of a run in its L2.
+struct Items16 {
+  std::vector<int4> q[tai::kAsm16Queues];
+  int rr = 0;
+  void add(int mol, int64_t npair, int64_t R, int64_t C) {
+    const int64_t chunk = std::max<int64_t>(1, 512 / C);
+    const int64_t ncb = (npair + C - 1) / C;
+    const int64_t nrp = (npair + R - 1) / R;
+    for (int64_t j = 0; j * chunk < ncb; ++j) {
+      std::vector<int4>& out = q[rr++ % tai::kAsm16Queues];
+      for (int64_t rp = 0; rp < nrp; ++rp) {
+        const int64_t lo = std::max(j * chunk, rp * R / C);
+        const int64_t hi = std::min((j + 1) * chunk, ncb);
+        if (lo < hi) out.push_back(int4{mol, (int)rp, (int)lo, (int)hi});
+      }
     }
-}
+  }
+  size_t count() const {
+    size_t n = 0;
+    for (const auto& v : q) n += v.size();
+    return n;
+  }
+  // seg[kAsm16Queues + 1] offsets followed (at 256 bytes) by the items
+  static size_t seg_bytes() { return align256(sizeof(int) * (tai::kAsm16Queues + 1)); }
+  size_t bytes() const { return seg_bytes() + sizeof(int4) * count(); }
+  void write(char* dst) const {
+    int* seg = reinterpret_cast<int*>(dst);
+    int4* it = reinterpret_cast<int4*>(dst + seg_bytes());
+    int off = 0;
+    for (int x = 0; x < tai::kAsm16Queues; ++x) {
+      seg[x] = off;
+      std::memcpy(it + off, q[x].data(), sizeof(int4) * q[x].size());
+      off += (int)q[x].size();
+    }
+    seg[tai::kAsm16Queues] = off;
+  }
+};
 
 // Whether calls of this arithmetic and degree have 16-bit kernel shapes to
 // choose between (and nobody forced one).
@@ -560,28 +584,30 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
   m.tiles = prow / tai::assemble_tile(prec);
   m.tile0 = 0;
   if (use16(c, prec, n, nq)) {
-    std::vector<int4> items;
+    Items16 items;
     const tai::Asm16Shape sh = shape16(c, prec, n, nq);
-    build_items16(items, 0, npair, sh.rows, sh.cols);
-    const size_t tab_bytes = align256(sizeof(tai::AsmMol)) + sizeof(int4) * items.size();
+    items.add(0, npair, sh.rows, sh.cols);
+    const size_t tab_bytes = align256(sizeof(tai::AsmMol)) + items.bytes();
     if ((r = ensure(c, c->asm_tab, tab_bytes))) return r;
     if ((r = ensure(c, c->asm_counter, 256))) return r;
     if ((r = ensure_host(c, c->asm_host, c->asm_host_done, tab_bytes))) return r;
     char* hb = static_cast<char*>(c->asm_host.p);
     std::memcpy(hb, &m, sizeof m);
-    std::memcpy(hb + align256(sizeof(tai::AsmMol)), items.data(), sizeof(int4) * items.size());
+    items.write(hb + align256(sizeof(tai::AsmMol)));
     if ((e = hipMemcpyAsync(c->asm_tab.p, hb, tab_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
       return hip_fail(c, e, "table upload");
     if ((e = hipEventRecord(c->asm_host_done, s)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
     unsigned* counter = static_cast<unsigned*>(c->asm_counter.p);
     if ((e = tai::launch_reset_counter(counter, s)) != hipSuccess) return hip_fail(c, e, "reset kernel");
-    const int nitems = (int)items.size();
+    const int nitems = (int)items.count();
     const int nblocks = std::min(nitems, (c->cus > 0 ? c->cus : 256) * sh.wgs_per_cu);
     const auto* mols_dev = static_cast<const tai::AsmMol*>(c->asm_tab.p);
-    const auto* items_dev = reinterpret_cast<const int4*>(static_cast<char*>(c->asm_tab.p) + align256(sizeof(tai::AsmMol)));
+    const char* tab = static_cast<const char*>(c->asm_tab.p) + align256(sizeof(tai::AsmMol));
+    const auto* seg_dev = reinterpret_cast<const int*>(tab);
+    const auto* items_dev = reinterpret_cast<const int4*>(tab + Items16::seg_bytes());
     {
       Timed tm(c, kStAssemble, s);
-      e = tai::launch_assemble16(prec, m.kc, tai::operand_dup_chunks(prec, n), sh, mols_dev, items_dev, nitems,
+      e = tai::launch_assemble16(prec, m.kc, tai::operand_dup_chunks(prec, n), sh, mols_dev, items_dev, seg_dev,
                                  counter, nblocks, s);
     }
   } else {
@@ -686,18 +712,18 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   // the 16-bit kernel drains (molecule, row panel, column range) items,
   // largest molecules first so the tail of the queue holds small items
   const bool split16 = use16(c, prec, n, nq);
-  std::vector<int4> items16;
+  Items16 items16;
   const tai::Asm16Shape sh16 = split16 ? shape16(c, prec, n, nq) : tai::Asm16Shape{};
   if (split16) {
     std::vector<int> order(nmol);
     for (int i = 0; i < nmol; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return am[a].npair > am[b].npair; });
-    for (int i : order) build_items16(items16, i, am[i].npair, sh16.rows, sh16.cols);
+    for (int i : order) items16.add(i, am[i].npair, sh16.rows, sh16.cols);
   }
   // device tables: [AsmMol x nmol | PrepMol x nmol | items]
   const size_t off_prep = align256(sizeof(tai::AsmMol) * nmol);
   const size_t off_items = off_prep + align256(sizeof(tai::PrepMol) * nmol);
-  const size_t tab_bytes = off_items + sizeof(int4) * items16.size();
+  const size_t tab_bytes = off_items + (split16 ? items16.bytes() : 0);
   if ((r = ensure(c, c->b_mols, tab_bytes))) return r;
   std::vector<tai::PrepMol> prep(nmol);
   int64_t max_npair = 0;
@@ -725,7 +751,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   for (int i = 0; i < nmol; ++i) pack_basis_host(&mols[i].basis, hb + off_basis[i]);
   std::memcpy(hb + sz_basis, am.data(), sizeof(tai::AsmMol) * nmol);
   std::memcpy(hb + sz_basis + off_prep, prep.data(), sizeof(tai::PrepMol) * nmol);
-  if (!items16.empty()) std::memcpy(hb + sz_basis + off_items, items16.data(), sizeof(int4) * items16.size());
+  if (split16) items16.write(hb + sz_basis + off_items);
   hipError_t e = hipMemcpyAsync(c->b_basis.p, hb, sz_basis, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->b_mols.p, hb + sz_basis, tab_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(c->b_host_done, s);
@@ -745,11 +771,13 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     if (err != hipSuccess) return err;
     const auto* mols_dev = static_cast<const tai::AsmMol*>(c->b_mols.p);
     if (split16) {
-      const auto* items_dev = reinterpret_cast<const int4*>(static_cast<char*>(c->b_mols.p) + off_items);
-      const int ni = (int)items16.size();
+      const char* tab = static_cast<const char*>(c->b_mols.p) + off_items;
+      const auto* seg_dev = reinterpret_cast<const int*>(tab);
+      const auto* items_dev = reinterpret_cast<const int4*>(tab + Items16::seg_bytes());
+      const int ni = (int)items16.count();
       const int blocks = std::min(ni, (c->cus > 0 ? c->cus : 256) * sh16.wgs_per_cu);
-      return tai::launch_assemble16(prec, am[0].kc, tai::operand_dup_chunks(prec, n), sh16, mols_dev, items_dev, ni,
-                                    counter, blocks, st);
+      return tai::launch_assemble16(prec, am[0].kc, tai::operand_dup_chunks(prec, n), sh16, mols_dev, items_dev,
+                                    seg_dev, counter, blocks, st);
     }
     int blocks = tai::assemble_queue_blocks(prec, c->device);
     if (blocks > nitems) blocks = (int)nitems;

@@ -117,7 +117,8 @@ hipError_t launch_project(int prec, const double* M, int n, int npair, int prow,
 // Single molecule, one work group per tile.
 hipError_t launch_assemble(int prec, const AsmMol& m, hipStream_t s);
 // Persistent launch over a device work list of molecules; `counter` is a
-// device int zeroed by launch_reset_counter before each launch.
+// device int zeroed by launch_reset_counter before each launch (which
+// zeroes the kAsm16Queues counters starting there).
 hipError_t launch_assemble_queue(int prec, const AsmMol* mols_dev, int nmol, int64_t nitems,
                                  unsigned* counter, int nblocks, hipStream_t s);
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t s);
@@ -141,8 +142,12 @@ int asm16_max_kc();
 // groups per CU filled in from the runtime (device must be current).
 int asm16_shapes(int kc, int q, Asm16Shape* out, int cap);
 Asm16Shape asm16_shape(int kc, int q, int pick);
+// The items are split into kAsm16Queues queues (one per XCD): queue x is
+// items[seg[x] .. seg[x+1]); counters[x] are zeroed by launch_reset_counter.
+constexpr int kAsm16Queues = 8;
 hipError_t launch_assemble16(int prec, int kc, int q, const Asm16Shape& shape, const AsmMol* mols_dev,
-                             const int4* items_dev, int nitems, unsigned* counter, int nblocks, hipStream_t s);
+                             const int4* items_dev, const int* seg_dev, unsigned* counters, int nblocks,
+                             hipStream_t s);
 inline bool is_split16(int prec) { return prec == kBF16X3 || prec == kBF16X6 || prec == kF16X3; }
 
 // ---- Coulomb matrix through the grid tensor --------------------------------
