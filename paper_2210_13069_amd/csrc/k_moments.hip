@@ -39,6 +39,19 @@ __device__ inline double ipow(double x, int l) {
 template <int NMAX>
 __device__ inline void moments_body(const DevBasis& bs, int n, double L, const NodeTables& tb,
                                     double* __restrict__ M, int64_t npair) {
+  // the GL panel rule and the Chebyshev-to-node map, read at uniform
+  // addresses by every thread, come from LDS
+  __shared__ double s_pz[kMomOrder], s_pw[kMomOrder];
+  __shared__ double s_gam[NMAX * NMAX];
+  for (int i = threadIdx.x; i < NMAX * NMAX; i += blockDim.x) {
+    const int ai = i / NMAX, k = i - ai * NMAX;
+    s_gam[i] = (ai < n && k < n) ? tb.gam[ai * n + k] : 0.0;
+  }
+  for (int i = threadIdx.x; i < kMomOrder; i += blockDim.x) {
+    s_pz[i] = tb.pz[i];
+    s_pw[i] = tb.pw[i];
+  }
+  __syncthreads();
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= 3 * npair) return;
   const int d = (int)(g / npair);
@@ -72,9 +85,9 @@ __device__ inline void moments_body(const DevBasis& bs, int n, double L, const N
   for (int s = 0; s < kMomPanels; ++s) {
     const double mid = lo + (s + 0.5) * h;
     for (int j = 0; j < kMomOrder; ++j) {
-      const double x = mid + 0.5 * h * tb.pz[j];
+      const double x = mid + 0.5 * h * s_pz[j];
       const double dxp = x - P;
-      const double f = pref * (0.5 * h * tb.pw[j]) * ipow(x - A, la) * ipow(x - B, lb) * exp(-pp * dxp * dxp);
+      const double f = pref * (0.5 * h * s_pw[j]) * ipow(x - A, la) * ipow(x - B, lb) * exp(-pp * dxp * dxp);
       const double u = x * invL;
       double t0 = 1.0, t1 = u;
       mom[0] += f;
@@ -91,11 +104,10 @@ __device__ inline void moments_body(const DevBasis& bs, int n, double L, const N
 
   double* out = M + (int64_t)d * n * npair + p;
   for (int ai = 0; ai < n; ++ai) {
-    const double* gr = tb.gam + ai * n;
+    const double* gr = s_gam + ai * NMAX;  // zero beyond n
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k)
-      if (k < n) s += gr[k] * mom[k];
+    for (int k = 0; k < NMAX; ++k) s += gr[k] * mom[k];
     out[(int64_t)ai * npair] = s;
   }
 }
