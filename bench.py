@@ -257,6 +257,16 @@ def main():
         del Mj, Jj
         torch.cuda.empty_cache()
 
+    # ---------------- the device's own sustained peaks ------------------------
+    if not args.only_headline:
+        log("peak probes")
+        ach = {"mfma_f16_tflops": round(ctx.peak_probe(0), 1), "mfma_f64_tflops": round(ctx.peak_probe(1), 2),
+               "hbm_copy_gbs": round(ctx.peak_probe(2), 0)}
+        roofline["achievable"] = ach
+        key = {"fp64": "mfma_f64_tflops", "fp32": None}.get(args.prec, "mfma_f16_tflops")
+        if key:
+            roofline["frac_of_achievable"] = round(achieved / ach[key], 5)
+
     # ---------------- oracle on the host (bounded sample) ---------------------
     cpu = None
     rel_error = None

@@ -227,6 +227,17 @@ int tai_tune(tai_ctx* ctx, int mode);
 int tai_profile_enable(tai_ctx* ctx, int enable);
 int tai_profile_read(tai_ctx* ctx, const char* stage, double* total_ms, int64_t* count);
 
+/* What this device sustains, for reporting measured kernels against the
+   device's own ceiling beside the published one: what 0 = dense FP16 matrix
+   throughput (back-to-back independent v_mfma_f32_16x16x32_f16 on every
+   SIMD), 1 = FP64 matrix throughput (v_mfma_f64_16x16x4_f64), both in
+   TFLOP/s; 2 = HBM streaming copy, bytes read plus written, in GB/s.  The
+   best of three timed launches after one warm-up, on `stream`.  The call
+   allocates its own buffers (2 GiB for what 2), synchronizes the stream and
+   takes a few milliseconds.  TAI_ERR_INVALID_ARG for another `what` or a NULL
+   `value`, TAI_ERR_NOMEM if the buffers cannot be allocated. */
+int tai_peak_probe(tai_ctx* ctx, int what, double* value, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtai.so")
-SOURCES = ["tai_api.hip", "k_nodes.hip", "k_moments.hip", "k_assemble.hip", "k_assemble16.hip", "k_apply_j.hip"]
+SOURCES = ["tai_api.hip", "k_nodes.hip", "k_moments.hip", "k_assemble.hip", "k_assemble16.hip", "k_apply_j.hip", "k_probe.hip"]
 ARCH = os.environ.get("TAI_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -23,6 +23,10 @@ CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in architectural VGPRs: with the AGPR form the
+    # register allocator rotated loop-carried accumulator tuples through
+    # v_accvgpr moves (up to eight per MFMA in the tile kernels)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wno-unused-command-line-argument",
 ]

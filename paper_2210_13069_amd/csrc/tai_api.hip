@@ -883,6 +883,53 @@ int tai_tune(tai_ctx* c, int mode) {
   return TAI_OK;
 }
 
+int tai_peak_probe(tai_ctx* c, int what, double* value, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if (what < 0 || what > 2) return fail(c, TAI_ERR_INVALID_ARG, "what must be 0, 1 or 2");
+  if (!value) return fail(c, TAI_ERR_INVALID_ARG, "value is NULL");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e != hipSuccess || cus < 1) return hip_fail(c, e == hipSuccess ? hipErrorUnknown : e, "CU count");
+  const int iters = what == 0 ? 20000 : 4000;
+  const int64_t n16 = what == 2 ? (int64_t{1} << 26) : 0;  // 1 GiB each way
+  float* out = nullptr;
+  void* src = nullptr;
+  void* dst = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double best = 0.0;
+  auto done = [&](int code) {
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (out) hipFree(out);
+    if (src) hipFree(src);
+    if (dst) hipFree(dst);
+    return code;
+  };
+  if (hipMalloc(&out, sizeof(float) * 2 * cus * 256) != hipSuccess ||
+      (n16 && (hipMalloc(&src, 16 * n16) != hipSuccess || hipMalloc(&dst, 16 * n16) != hipSuccess))) {
+    (void)hipGetLastError();
+    return done(fail(c, TAI_ERR_NOMEM, "probe buffers"));
+  }
+  if (n16 && (e = hipMemsetAsync(src, 0, 16 * n16, s)) != hipSuccess) return done(hip_fail(c, e, "probe fill"));
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+    return done(hip_fail(c, e, "hipEventCreate"));
+  for (int rep = 0; rep < 4; ++rep) {  // the first launch warms up and is not counted
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) return done(hip_fail(c, e, "hipEventRecord"));
+    if ((e = tai::launch_probe(what, cus, out, src, dst, n16, iters, s)) != hipSuccess)
+      return done(hip_fail(c, e, "probe launch"));
+    if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+      return done(hip_fail(c, e, "probe timing"));
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return done(hip_fail(c, e, "hipEventElapsedTime"));
+    if (rep > 0 && ms > 0.f) best = std::max(best, tai::probe_work(what, cus, n16, iters) / (ms * 1e-3));
+  }
+  *value = what == 2 ? best / 1e9 : best / 1e12;
+  return done(TAI_OK);
+}
+
 int tai_profile_enable(tai_ctx* c, int enable) {
   int r = check_ctx(c);
   if (r) return r;

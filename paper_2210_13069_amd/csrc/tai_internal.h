@@ -165,6 +165,12 @@ struct JWork {
 int j_nchunk(int prec, int n, int npair);
 size_t j_work_bytes(int prec, int nq, int n, int npair);
 JWork carve_j_work(void* base, int prec, int nq, int n, int npair);
+// Achievable-peak probes (k_probe.hip): what 0 = FP16 MFMA, 1 = FP64 MFMA,
+// 2 = HBM copy.  probe_work is the flops (0, 1) or bytes (2) of one launch.
+hipError_t launch_probe(int what, int cus, float* out, const void* src, void* dst, int64_t n16, int iters,
+                        hipStream_t s);
+double probe_work(int what, int cus, int64_t n16, int iters);
+
 hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, int n, int nq,
                           const NodeTables& tb, const double* D, double* J,
                           const JWork& w, hipStream_t s);

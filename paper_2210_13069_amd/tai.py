@@ -29,7 +29,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 # exported symbols declared in include/tai.h
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
            "tai_quadrature", "tai_moments", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
-           "tai_tune", "tai_profile_enable", "tai_profile_read"]
+           "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched"]
 
 
@@ -88,6 +88,7 @@ def load_library(path=LIB_PATH):
     lib.tai_assemble_B.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, ctypes.c_int64, vp]
     lib.tai_assemble_B_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(tai_mol), vp]
     lib.tai_apply_J.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, vp, vp]
+    lib.tai_peak_probe.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
     lib.tai_profile_enable.argtypes = [vp, ctypes.c_int]
     lib.tai_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64)]
@@ -186,6 +187,12 @@ class Context:
     def tune(self, mode):
         """0: table default shapes, 1: tune each new signature once, 2: forget choices."""
         self.check(self.lib.tai_tune(self.h, int(mode)), "tai_tune")
+
+    def peak_probe(self, what, stream=None):
+        """Sustained device peak: 0 FP16 MFMA, 1 FP64 MFMA (TFLOP/s), 2 HBM copy (GB/s)."""
+        v = ctypes.c_double()
+        self.check(self.lib.tai_peak_probe(self.h, int(what), ctypes.byref(v), _stream(stream)), "tai_peak_probe")
+        return v.value
 
     def profile_enable(self, enable=True):
         self.check(self.lib.tai_profile_enable(self.h, int(bool(enable))), "tai_profile_enable")

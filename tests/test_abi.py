@@ -48,6 +48,15 @@ def test_tune_modes(lib, hctx):
     assert lib.tai_tune(None, 1) == tai.TAI_ERR_INVALID_ARG
 
 
+def test_peak_probe_argument_checks(lib, hctx):
+    v = ctypes.c_double()
+    assert lib.tai_peak_probe(None, 0, ctypes.byref(v), None) == tai.TAI_ERR_INVALID_ARG
+    for what in (-1, 3):
+        assert lib.tai_peak_probe(hctx.h, what, ctypes.byref(v), None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_peak_probe(hctx.h, 0, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_peak_probe(hctx.h, 0, ctypes.byref(v), None) == tai.TAI_ERR_NOT_READY
+
+
 def test_status_strings(lib):
     for st in (0, -1, -2, -3, -4, -5, 7):
         s = lib.tai_status_string(st)
