@@ -431,6 +431,132 @@ __device__ inline void assemble_tile(const AsmMol& m, int I, int J) {
   }
 }
 
+// FP64 / FP32 tile with the k-invariant A operand held in registers: the
+// same arithmetic in the same order as assemble_tile (identical results),
+// but A is loaded once per tile instead of once per node, and the Y
+// fragments of the next (node, direction, chunk) step are loaded while the
+// MFMAs of the current one run.  KC is the inner length (n rounded up to 8).
+template <class Op, int KC>
+__device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
+  using T = typename ElemOf<Op>::T;
+  using Acc = typename Op::Acc;
+  using Frag = typename Op::Frag;
+  constexpr int WM = 2, WN = 2, TILE = 64, NCK = KC / Op::kChunk, NSTEP = 3 * NCK;
+  static_assert(KC % Op::kChunk == 0, "inner length");
+  constexpr bool kF64 = sizeof(T) == 8;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int64_t row0 = (int64_t)I * TILE + wr * 16 * WM;
+  const int64_t col0 = (int64_t)J * TILE + wc * 16 * WN;
+  const int64_t prow = m.prow;
+  const T* __restrict__ Abase = static_cast<const T*>(m.A);
+  // Y addressing: a wave-uniform base per step plus one 32-bit lane offset
+  typedef __attribute__((address_space(1))) const Frag gFrag;
+  const char* __restrict__ Yw = static_cast<const char*>(m.Y) + col0 * KC * (int64_t)sizeof(T);
+  const uint32_t ylane = (uint32_t)((r16 * KC + kg * Op::kPerLane) * sizeof(T));
+
+  Frag fa[3][NCK][WM];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int c = 0; c < NCK; ++c)
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+        fa[d][c][i] = *reinterpret_cast<const Frag*>(Abase + ((int64_t)d * prow + row0 + 16 * i + r16) * KC +
+                                                     kg * Op::kPerLane + c * Op::kChunk);
+  // Y fragments of step s = (k, d, c): Y[k][d][col0 + 16 j + r16][c * chunk + ...]
+  auto loadY = [&](int k, int st, Frag (&dst)[WN]) {
+    const int d = st / NCK, c = st % NCK;
+    const char* y = Yw + (((int64_t)k * 3 + d) * prow * KC + c * Op::kChunk) * (int64_t)sizeof(T);
+#pragma unroll
+    for (int j = 0; j < WN; ++j) dst[j] = *(gFrag*)(y + ylane + j * 16 * KC * (int)sizeof(T));
+  };
+
+  Acc acc[WM][WN];
+  v4d acc64[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) { acc[i][j] = Op::zero(); acc64[i][j] = v4d{0.0, 0.0, 0.0, 0.0}; }
+
+  const int nq = m.nq;
+  Frag cur[WN], nxt[WN];
+  loadY(0, 0, cur);
+  for (int k = 0; k < nq; ++k) {
+    Acc H[WM][WN], G[WM][WN];
+#pragma unroll
+    for (int st = 0; st < NSTEP; ++st) {
+      const int d = st / NCK, c = st % NCK;
+      if (st + 1 < NSTEP) loadY(k, st + 1, nxt);
+      else if (k + 1 < nq) loadY(k + 1, 0, nxt);
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) G[i][j] = Op::mma(fa[d][c][i], cur[j], c == 0 ? Op::zero() : G[i][j]);
+      if (c == NCK - 1) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+            if (d == 0) H[i][j] = G[i][j];
+            else if (d == 1) H[i][j] = H[i][j] * G[i][j];
+            else acc[i][j] += H[i][j] * G[i][j];
+          }
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) cur[j] = nxt[j];
+    }
+    if (!kF64 && ((k + 1) % kGroup == 0 || k + 1 == nq)) {
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+          acc[i][j] = Op::zero();
+        }
+    }
+  }
+
+  const int64_t npair = m.npair;
+  const int64_t ldb = m.ldb;
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int64_t col = col0 + j * 16 + r16;
+      const int ecol = kF64 ? 0 : m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + i * 16 + Op::row_of(kg, r);
+        if (row >= npair || col >= npair) continue;
+        if (kF64) {
+          const double v = (double)acc[i][j][r] * kTwoOverSqrtPi;
+          double* B = static_cast<double*>(m.B);
+          B[row * ldb + col] = v;
+          if (I != J) B[col * ldb + row] = v;
+        } else {
+          const int erow = m.ex[row] + m.ex[prow + row] + m.ex[2 * prow + row];
+          const float v = (float)ldexp(acc64[i][j][r] * kTwoOverSqrtPi, erow + ecol);
+          float* B = static_cast<float*>(m.B);
+          B[row * ldb + col] = v;
+          if (I != J) B[col * ldb + row] = v;
+        }
+      }
+    }
+  }
+}
+
+template <class Op, int KC>
+__global__ void __launch_bounds__(256, 2)
+assemble_as_kernel(AsmMol m) {
+  int I, J;
+  decode_tile(m.tiles, blockIdx.x, I, J);
+  assemble_tile_as<Op, KC>(m, I, J);
+}
+
 template <class Op, int WM, int WN>
 __global__ void __launch_bounds__(256)
 assemble_kernel(AsmMol m) {
@@ -619,9 +745,24 @@ hipError_t launch_project(int prec, const double* M, int n, int npair, int prow,
   return launch_project_t<4>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
 }
 
+template <class Op>
+bool launch_as(int kc, const dim3& grid, const AsmMol& m, hipStream_t s) {
+  switch (kc) {
+    case 8: hipLaunchKernelGGL((assemble_as_kernel<Op, 8>), grid, dim3(256), 0, s, m); return true;
+    case 16: hipLaunchKernelGGL((assemble_as_kernel<Op, 16>), grid, dim3(256), 0, s, m); return true;
+    case 24: hipLaunchKernelGGL((assemble_as_kernel<Op, 24>), grid, dim3(256), 0, s, m); return true;
+    case 32: hipLaunchKernelGGL((assemble_as_kernel<Op, 32>), grid, dim3(256), 0, s, m); return true;
+    case 40: hipLaunchKernelGGL((assemble_as_kernel<Op, 40>), grid, dim3(256), 0, s, m); return true;
+    default: return false;
+  }
+}
+
 hipError_t launch_assemble(int prec, const AsmMol& m, hipStream_t s) {
   const int64_t ntiles = (int64_t)m.tiles * (m.tiles + 1) / 2;
   const dim3 grid((unsigned)ntiles), block(256);
+  // inner lengths up to 40: A-stationary tiles (the A operand fits the registers)
+  if (prec == kFP64 && launch_as<OpF64>(m.kc, grid, m, s)) return hipGetLastError();
+  if (prec == kFP32 && launch_as<OpF32>(m.kc, grid, m, s)) return hipGetLastError();
   switch (prec) {
     case kFP64: hipLaunchKernelGGL((assemble_kernel<OpF64, 2, 2>), grid, block, 0, s, m); break;
     case kFP32: hipLaunchKernelGGL((assemble_kernel<OpF32, 2, 2>), grid, block, 0, s, m); break;
