@@ -434,19 +434,21 @@ __device__ inline void assemble_tile(const AsmMol& m, int I, int J) {
 // FP64 / FP32 tile with the k-invariant A operand held in registers: the
 // same arithmetic in the same order as assemble_tile (identical results),
 // but A is loaded once per tile instead of once per node, and the Y
-// fragments of the next (node, direction, chunk) step are loaded while the
-// MFMAs of the current one run.  KC is the inner length (n rounded up to 8).
-template <class Op, int KC>
+// fragments of the next PD (node, direction, chunk) steps are loaded while
+// the MFMAs of the current one run.  KC is the inner length (n rounded up
+// to 8).
+template <class Op, int KC, int WN, int PD>
 __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
   using T = typename ElemOf<Op>::T;
   using Acc = typename Op::Acc;
   using Frag = typename Op::Frag;
-  constexpr int WM = 2, WN = 2, TILE = 64, NCK = KC / Op::kChunk, NSTEP = 3 * NCK;
+  // 64 x 64 tile; waves 2 x (4 / WN), each 32 rows x 16*WN columns
+  constexpr int WM = 2, TILE = 64, WC = 4 / WN, NCK = KC / Op::kChunk, NSTEP = 3 * NCK;
   static_assert(KC % Op::kChunk == 0, "inner length");
   constexpr bool kF64 = sizeof(T) == 8;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WC, wc = wave % WC;
   const int r16 = lane & 15, kg = lane >> 4;
   const int64_t row0 = (int64_t)I * TILE + wr * 16 * WM;
   const int64_t col0 = (int64_t)J * TILE + wc * 16 * WN;
@@ -482,19 +484,25 @@ __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
     for (int j = 0; j < WN; ++j) { acc[i][j] = Op::zero(); acc64[i][j] = v4d{0.0, 0.0, 0.0, 0.0}; }
 
   const int nq = m.nq;
-  Frag cur[WN], nxt[WN];
-  loadY(0, 0, cur);
+  // ring[0] holds the current step's Y fragments, ring[1..PD] the next PD
+  // steps' (loads in flight)
+  Frag ring[PD + 1][WN];
+#pragma unroll
+  for (int a = 0; a < PD; ++a)
+    if (a / NSTEP < nq) loadY(a / NSTEP, a % NSTEP, ring[a]);
   for (int k = 0; k < nq; ++k) {
     Acc H[WM][WN], G[WM][WN];
 #pragma unroll
     for (int st = 0; st < NSTEP; ++st) {
       const int d = st / NCK, c = st % NCK;
-      if (st + 1 < NSTEP) loadY(k, st + 1, nxt);
-      else if (k + 1 < nq) loadY(k + 1, 0, nxt);
+      {
+        const int k2 = k + (st + PD) / NSTEP, st2 = (st + PD) % NSTEP;
+        if (k2 < nq) loadY(k2, st2, ring[PD]);
+      }
 #pragma unroll
       for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) G[i][j] = Op::mma(fa[d][c][i], cur[j], c == 0 ? Op::zero() : G[i][j]);
+        for (int j = 0; j < WN; ++j) G[i][j] = Op::mma(fa[d][c][i], ring[0][j], c == 0 ? Op::zero() : G[i][j]);
       if (c == NCK - 1) {
 #pragma unroll
         for (int i = 0; i < WM; ++i)
@@ -506,7 +514,9 @@ __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
           }
       }
 #pragma unroll
-      for (int j = 0; j < WN; ++j) cur[j] = nxt[j];
+      for (int a = 0; a < PD; ++a)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) ring[a][j] = ring[a + 1][j];
     }
     if (!kF64 && ((k + 1) % kGroup == 0 || k + 1 == nq)) {
 #pragma unroll
@@ -549,12 +559,16 @@ __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
   }
 }
 
-template <class Op, int KC>
-__global__ void __launch_bounds__(256, 2)
+// WN = 2: four waves of 32 x 32; WN = 1: eight waves of 32 x 16 (half the
+// accumulator registers per wave, for the FP64 operands of the longer inner
+// lengths).  Two waves per SIMD either way.
+template <class Op, int KC, int WN>
+__global__ void __launch_bounds__(512 / WN, WN)
 assemble_as_kernel(AsmMol m) {
   int I, J;
   decode_tile(m.tiles, blockIdx.x, I, J);
-  assemble_tile_as<Op, KC>(m, I, J);
+  // FP32 MFMAs take half the cycles of FP64 ones: look two steps ahead
+  assemble_tile_as<Op, KC, WN, sizeof(typename ElemOf<Op>::T) == 8 ? 1 : 2>(m, I, J);
 }
 
 template <class Op, int WM, int WN>
@@ -745,14 +759,24 @@ hipError_t launch_project(int prec, const double* M, int n, int npair, int prow,
   return launch_project_t<4>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
 }
 
+// FP64 uses the eight-wave form from inner length 32 on (the four-wave form
+// spills there), FP32 the four-wave form throughout.
 template <class Op>
 bool launch_as(int kc, const dim3& grid, const AsmMol& m, hipStream_t s) {
+  constexpr bool f64 = sizeof(typename ElemOf<Op>::T) == 8;
+  const dim3 b4(256), b8(512);
   switch (kc) {
-    case 8: hipLaunchKernelGGL((assemble_as_kernel<Op, 8>), grid, dim3(256), 0, s, m); return true;
-    case 16: hipLaunchKernelGGL((assemble_as_kernel<Op, 16>), grid, dim3(256), 0, s, m); return true;
-    case 24: hipLaunchKernelGGL((assemble_as_kernel<Op, 24>), grid, dim3(256), 0, s, m); return true;
-    case 32: hipLaunchKernelGGL((assemble_as_kernel<Op, 32>), grid, dim3(256), 0, s, m); return true;
-    case 40: hipLaunchKernelGGL((assemble_as_kernel<Op, 40>), grid, dim3(256), 0, s, m); return true;
+    case 8: hipLaunchKernelGGL((assemble_as_kernel<Op, 8, 2>), grid, b4, 0, s, m); return true;
+    case 16: hipLaunchKernelGGL((assemble_as_kernel<Op, 16, 2>), grid, b4, 0, s, m); return true;
+    case 24: hipLaunchKernelGGL((assemble_as_kernel<Op, 24, 2>), grid, b4, 0, s, m); return true;
+    case 32:
+      if constexpr (f64) hipLaunchKernelGGL((assemble_as_kernel<Op, 32, 1>), grid, b8, 0, s, m);
+      else hipLaunchKernelGGL((assemble_as_kernel<Op, 32, 2>), grid, b4, 0, s, m);
+      return true;
+    case 40:
+      if constexpr (f64) hipLaunchKernelGGL((assemble_as_kernel<Op, 40, 1>), grid, b8, 0, s, m);
+      else hipLaunchKernelGGL((assemble_as_kernel<Op, 40, 2>), grid, b4, 0, s, m);
+      return true;
     default: return false;
   }
 }
