@@ -174,6 +174,11 @@ def main():
         if "fp64" in paths:
             for name in paths:
                 paths[name]["speedup_vs_fp64"] = round(paths[name]["entries_per_s"] / paths["fp64"]["entries_per_s"], 3)
+        # the assembly kernel of every path against its own arithmetic's peak
+        for name, pv in paths.items():
+            tf = flops / (pv["stage_ms"]["assemble"] / 1e3) / 1e12
+            pv["assemble_tflops_algorithmic"] = round(tf, 2)
+            pv["assemble_frac_of_peak"] = round(tf / PEAK_TFLOPS[name], 4)
     del B32
     torch.cuda.empty_cache()
 

@@ -579,10 +579,11 @@ assemble_kernel(AsmMol m) {
   assemble_tile<Op, WM, WN>(m, I, J);
 }
 
-// Persistent variant: work groups take (molecule, tile) items from a queue.
-template <class Op, int WM, int WN>
-__global__ void __launch_bounds__(256)
-assemble_queue_kernel(const AsmMol* __restrict__ mols, int nmol, int64_t nitems, unsigned* counter) {
+// Persistent variants: work groups take (molecule, tile) items from a queue
+// and hand each to `tile(m, I, J)`.
+template <class F>
+__device__ inline void drain_tile_queue(const AsmMol* __restrict__ mols, int nmol, int64_t nitems, unsigned* counter,
+                                        F&& tile) {
   __shared__ int64_t item_s;
   for (;;) {
     __syncthreads();
@@ -599,8 +600,23 @@ assemble_queue_kernel(const AsmMol* __restrict__ mols, int nmol, int64_t nitems,
     const AsmMol m = mols[lo];
     int I, J;
     decode_tile(m.tiles, item - m.tile0, I, J);
-    assemble_tile<Op, WM, WN>(m, I, J);
+    tile(m, I, J);
   }
+}
+
+template <class Op, int WM, int WN>
+__global__ void __launch_bounds__(256)
+assemble_queue_kernel(const AsmMol* __restrict__ mols, int nmol, int64_t nitems, unsigned* counter) {
+  drain_tile_queue(mols, nmol, nitems, counter,
+                   [](const AsmMol& m, int I, int J) { assemble_tile<Op, WM, WN>(m, I, J); });
+}
+
+template <class Op, int KC, int WN>
+__global__ void __launch_bounds__(512 / WN, WN)
+assemble_as_queue_kernel(const AsmMol* __restrict__ mols, int nmol, int64_t nitems, unsigned* counter) {
+  drain_tile_queue(mols, nmol, nitems, counter, [](const AsmMol& m, int I, int J) {
+    assemble_tile_as<Op, KC, WN, sizeof(typename ElemOf<Op>::T) == 8 ? 1 : 2>(m, I, J);
+  });
 }
 
 __global__ void reset_counter_kernel(unsigned* c) {
@@ -761,22 +777,35 @@ hipError_t launch_project(int prec, const double* M, int n, int npair, int prow,
 
 // FP64 uses the eight-wave form from inner length 32 on (the four-wave form
 // spills there), FP32 the four-wave form throughout.
+template <class Op, int KC>
+constexpr int as_wn() {
+  return (sizeof(typename ElemOf<Op>::T) == 8 && KC >= 32) ? 1 : 2;
+}
+
+// grid: tiles (one work group each), or, for the queue form, work groups
+// of four waves' worth of threads (halved for the eight-wave form).
+template <class Op, int KC>
+void launch_as_kc(const dim3& grid, const AsmMol* mols, int nmol, int64_t nitems, unsigned* counter,
+                  const AsmMol& m, bool queue, hipStream_t s) {
+  constexpr int WN = as_wn<Op, KC>();
+  const dim3 block(512 / WN);
+  if (queue) {
+    const dim3 g(WN == 1 ? (grid.x + 1) / 2 : grid.x);
+    hipLaunchKernelGGL((assemble_as_queue_kernel<Op, KC, WN>), g, block, 0, s, mols, nmol, nitems, counter);
+  } else {
+    hipLaunchKernelGGL((assemble_as_kernel<Op, KC, WN>), grid, block, 0, s, m);
+  }
+}
+
 template <class Op>
-bool launch_as(int kc, const dim3& grid, const AsmMol& m, hipStream_t s) {
-  constexpr bool f64 = sizeof(typename ElemOf<Op>::T) == 8;
-  const dim3 b4(256), b8(512);
+bool launch_as(int kc, const dim3& grid, const AsmMol* mols, int nmol, int64_t nitems, unsigned* counter,
+               const AsmMol& m, bool queue, hipStream_t s) {
   switch (kc) {
-    case 8: hipLaunchKernelGGL((assemble_as_kernel<Op, 8, 2>), grid, b4, 0, s, m); return true;
-    case 16: hipLaunchKernelGGL((assemble_as_kernel<Op, 16, 2>), grid, b4, 0, s, m); return true;
-    case 24: hipLaunchKernelGGL((assemble_as_kernel<Op, 24, 2>), grid, b4, 0, s, m); return true;
-    case 32:
-      if constexpr (f64) hipLaunchKernelGGL((assemble_as_kernel<Op, 32, 1>), grid, b8, 0, s, m);
-      else hipLaunchKernelGGL((assemble_as_kernel<Op, 32, 2>), grid, b4, 0, s, m);
-      return true;
-    case 40:
-      if constexpr (f64) hipLaunchKernelGGL((assemble_as_kernel<Op, 40, 1>), grid, b8, 0, s, m);
-      else hipLaunchKernelGGL((assemble_as_kernel<Op, 40, 2>), grid, b4, 0, s, m);
-      return true;
+    case 8: launch_as_kc<Op, 8>(grid, mols, nmol, nitems, counter, m, queue, s); return true;
+    case 16: launch_as_kc<Op, 16>(grid, mols, nmol, nitems, counter, m, queue, s); return true;
+    case 24: launch_as_kc<Op, 24>(grid, mols, nmol, nitems, counter, m, queue, s); return true;
+    case 32: launch_as_kc<Op, 32>(grid, mols, nmol, nitems, counter, m, queue, s); return true;
+    case 40: launch_as_kc<Op, 40>(grid, mols, nmol, nitems, counter, m, queue, s); return true;
     default: return false;
   }
 }
@@ -785,8 +814,8 @@ hipError_t launch_assemble(int prec, const AsmMol& m, hipStream_t s) {
   const int64_t ntiles = (int64_t)m.tiles * (m.tiles + 1) / 2;
   const dim3 grid((unsigned)ntiles), block(256);
   // inner lengths up to 40: A-stationary tiles (the A operand fits the registers)
-  if (prec == kFP64 && launch_as<OpF64>(m.kc, grid, m, s)) return hipGetLastError();
-  if (prec == kFP32 && launch_as<OpF32>(m.kc, grid, m, s)) return hipGetLastError();
+  if (prec == kFP64 && launch_as<OpF64>(m.kc, grid, nullptr, 0, 0, nullptr, m, false, s)) return hipGetLastError();
+  if (prec == kFP32 && launch_as<OpF32>(m.kc, grid, nullptr, 0, 0, nullptr, m, false, s)) return hipGetLastError();
   switch (prec) {
     case kFP64: hipLaunchKernelGGL((assemble_kernel<OpF64, 2, 2>), grid, block, 0, s, m); break;
     case kFP32: hipLaunchKernelGGL((assemble_kernel<OpF32, 2, 2>), grid, block, 0, s, m); break;
@@ -807,9 +836,14 @@ int assemble_queue_blocks(int /*prec*/, int device) {
   return cus * 4;
 }
 
-hipError_t launch_assemble_queue(int prec, const AsmMol* mols_dev, int nmol, int64_t nitems,
+hipError_t launch_assemble_queue(int prec, int kc, const AsmMol* mols_dev, int nmol, int64_t nitems,
                                  unsigned* counter, int nblocks, hipStream_t s) {
   const dim3 grid((unsigned)nblocks), block(256);
+  const AsmMol none{};
+  if (prec == kFP64 && launch_as<OpF64>(kc, grid, mols_dev, nmol, nitems, counter, none, true, s))
+    return hipGetLastError();
+  if (prec == kFP32 && launch_as<OpF32>(kc, grid, mols_dev, nmol, nitems, counter, none, true, s))
+    return hipGetLastError();
   switch (prec) {
     case kFP64: hipLaunchKernelGGL((assemble_queue_kernel<OpF64, 2, 2>), grid, block, 0, s, mols_dev, nmol, nitems, counter); break;
     case kFP32: hipLaunchKernelGGL((assemble_queue_kernel<OpF32, 2, 2>), grid, block, 0, s, mols_dev, nmol, nitems, counter); break;

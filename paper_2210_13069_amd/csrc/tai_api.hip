@@ -781,7 +781,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     }
     int blocks = tai::assemble_queue_blocks(prec, c->device);
     if (blocks > nitems) blocks = (int)nitems;
-    return tai::launch_assemble_queue(prec, mols_dev, nmol, nitems, counter, blocks, st);
+    return tai::launch_assemble_queue(prec, am[0].kc, mols_dev, nmol, nitems, counter, blocks, st);
   };
 
   const bool use_graph = allow_graph && s != nullptr && !std::getenv("TAI_NO_GRAPH");

@@ -119,7 +119,7 @@ hipError_t launch_assemble(int prec, const AsmMol& m, hipStream_t s);
 // Persistent launch over a device work list of molecules; `counter` is a
 // device int zeroed by launch_reset_counter before each launch (which
 // zeroes the kAsm16Queues counters starting there).
-hipError_t launch_assemble_queue(int prec, const AsmMol* mols_dev, int nmol, int64_t nitems,
+hipError_t launch_assemble_queue(int prec, int kc, const AsmMol* mols_dev, int nmol, int64_t nitems,
                                  unsigned* counter, int nblocks, hipStream_t s);
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t s);
 int assemble_queue_blocks(int prec, int device);

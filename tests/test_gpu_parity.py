@@ -102,6 +102,24 @@ def test_assemble_B_small(tai, prec, case):
     assert _normwise(Bg, Bg.T) <= (1e-14 if prec == 0 else tol)
 
 
+@pytest.mark.parametrize("n", [5, 12, 16, 29, 40, 41, 56])
+def test_assemble_fp64_fp32_inner_lengths(tai, n):
+    """FP64 and FP32 at every inner length of the register-resident-A tile
+    kernel (n rounded up to 8: 8, 16, 32, 40; FP64 switches to eight waves
+    from 32 on) and beyond it (48, 56: the generic tile kernel), on a ragged
+    pair count (npair = 465, not a multiple of the 64-pair tile)."""
+    b = I.small_random(51, natoms=3, shells=("s", "p", "d"), box=2.0, alpha_lo=0.2, alpha_hi=8.0)
+    P = I.Params(omega=0.5, nq=6, n=n, L=7.0)
+    Mr, K, w = _oracle(b, P)
+    Br = T.B_full(Mr, K, w)
+    Mg = tai.moments(b, P)
+    for prec in (0, 1):
+        Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+        tol = 1e-10 if prec == 0 else LOWP_TOL[prec]
+        assert _normwise(Bg, Br) <= tol, (n, prec, _normwise(Bg, Br))
+        assert _normwise(Bg, Bg.T) <= (1e-14 if prec == 0 else tol)
+
+
 @pytest.mark.parametrize("nq", [1, 2, 3, 4, 5, 7, 8, 9, 17])
 def test_assemble_16bit_node_counts(tai, nq):
     """Split 16-bit forms at node counts around the LDS ring depth (fewer
@@ -270,23 +288,26 @@ def test_apply_J_equals_B_times_density(tai):
 
 
 @pytest.mark.parametrize("graph", [False, True])
-def test_batched_equals_per_molecule(tai, graph):
+@pytest.mark.parametrize("prec", [4, 0, 1])
+def test_batched_equals_per_molecule(tai, graph, prec):
     """Direct launches (default stream) and hipGraph replays (a side stream):
     every replay, with eager work and synchronization in between, equals the
-    per-molecule calls bit for bit."""
+    per-molecule calls bit for bit (split 16-bit persistent kernel; FP64 and
+    FP32 tile queue)."""
     import torch
     mols = I.batch64(nmol=6)
     ctx = tai.context(0)
     outs, Ms, keep = [], [], []
     structs = []
+    dt = torch.float64 if prec == tai.FP64 else torch.float32
     for b, P in mols:
         ba = tai.BasisArrays(b)
         keep.append(ba)
         M = torch.empty((3, P.n, b.npair), dtype=torch.float64, device="cuda")
-        B = torch.full((b.npair, b.npair), float("nan"), dtype=torch.float32, device="cuda")
+        B = torch.full((b.npair, b.npair), float("nan"), dtype=dt, device="cuda")
         Ms.append(M)
         outs.append(B)
-        structs.append(tai.tai_mol(ba.struct, tai.make_params(P, tai.F16X3), M.data_ptr(), B.data_ptr(), b.npair))
+        structs.append(tai.tai_mol(ba.struct, tai.make_params(P, prec), M.data_ptr(), B.data_ptr(), b.npair))
     stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
     for rep in range(3):
         for B in outs:
@@ -297,7 +318,7 @@ def test_batched_equals_per_molecule(tai, graph):
         for (b, P), M, B in zip(mols, Ms, outs):
             Mref = tai.moments(b, P)
             assert torch.equal(M, Mref)
-            Bref = tai.assemble_B(Mref, P, prec=tai.F16X3)
+            Bref = tai.assemble_B(Mref, P, prec=prec)
             assert torch.equal(B, Bref), f"replay {rep}"
 
 
