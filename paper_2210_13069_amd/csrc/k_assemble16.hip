@@ -41,16 +41,19 @@ constexpr int kGroup16 = 8;  // FP32 accumulation group of quadrature nodes
 constexpr int kQueues = kAsm16Queues;
 
 // Compile-time shape: NW waves per work group, RB row blocks of 16 per wave,
-// CB column blocks of 16 per item block, an LDS ring of NBUF nodes.
-template <int KC, int Q, int NW, int RB, int CB, int NBUF>
+// CB column blocks of 16 per item block, an LDS ring of NBUF steps of NPS
+// quadrature nodes each (two nodes per step halve the waits, barriers and
+// load issues per node; the ring slot doubles).
+template <int KC, int Q, int NW, int RB, int CB, int NBUF, int NPS = 1>
 struct Cfg16 {
-  static constexpr int KC_ = KC, Q_ = Q, NW_ = NW, RB_ = RB, CB_ = CB, NBUF_ = NBUF;
+  static constexpr int KC_ = KC, Q_ = Q, NW_ = NW, RB_ = RB, CB_ = CB, NBUF_ = NBUF, NPS_ = NPS;
   static constexpr int NCH = KC / 32;                    // 32-wide inner chunks
   static constexpr int U = NCH - Q;                      // distinct A fragments
   static constexpr int NT = 64 * NW;                     // threads per work group
   static constexpr int ROWS = 16 * RB * NW;              // rows per panel
   static constexpr int COLS = 16 * CB;                   // columns per block
-  static constexpr int NFRAG = 3 * CB * NCH;             // 1 KB fragments per node
+  static constexpr int NFRAG_NODE = 3 * CB * NCH;        // 1 KB fragments per node
+  static constexpr int NFRAG = NFRAG_NODE * NPS;         // per step
   static constexpr int LPW_HI = (NFRAG + NW - 1) / NW;   // loads of waves < N_HI
   static constexpr int LPW_LO = NFRAG / NW;              // loads of the others
   static constexpr int N_HI = NFRAG % NW == 0 ? NW : NFRAG % NW;
@@ -85,16 +88,17 @@ __device__ inline v4f mma(v8bf a, v8bf b, v4f c) { return __builtin_amdgcn_mfma_
 template <class C>
 struct YLoads {
   uint32_t off[C::LPW_HI];
-  __device__ void init(int64_t prow, int64_t col0, int wave, int lane) {
+  __device__ void init(int64_t prow, int64_t col0, int64_t node_bytes, int wave, int lane) {
     const int r16 = lane & 15, kg = lane >> 4;
 #pragma unroll
     for (int i = 0; i < C::LPW_HI; ++i) {
       int f = wave + C::NW_ * i;
       f = f < C::NFRAG ? f : 0;
-      const int ch = f % C::NCH;
-      const int c = (f / C::NCH) % C::CB_;
-      const int d = f / (C::NCH * C::CB_);
-      off[i] = (uint32_t)((((int64_t)d * prow + col0 + 16 * c + r16) * C::KC_ + 32 * ch + 8 * kg) * 2);
+      const int j = f / C::NFRAG_NODE, g = f % C::NFRAG_NODE;
+      const int ch = g % C::NCH;
+      const int c = (g / C::NCH) % C::CB_;
+      const int d = g / (C::NCH * C::CB_);
+      off[i] = (uint32_t)(j * node_bytes + (((int64_t)d * prow + col0 + 16 * c + r16) * C::KC_ + 32 * ch + 8 * kg) * 2);
     }
   }
   __device__ void issue(const char* base, uint4* buf, int wave) const {
@@ -223,13 +227,14 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
   // step t = (block t / nq, node t % nq); its Y base pointer
   const int64_t node_bytes = 3 * prow * C::KC_ * 2;
   const int64_t block_bytes = (int64_t)COLS * C::KC_ * 2;
-  const int T = nblk * nq;
+  const int T = nblk * (nq / C::NPS_);
   YLoads<C> yl;
-  yl.init(prow, col_first, wave, lane);
+  yl.init(prow, col_first, node_bytes, wave, lane);
   int ib = 0, ik = 0;  // (block, node) of the next step to load
   auto issue_next = [&](uint4* buf) {
     yl.issue(Yb + ik * node_bytes + ib * block_bytes, buf, wave);
-    if (++ik == nq) {
+    ik += C::NPS_;
+    if (ik == nq) {
       ik = 0;
       ++ib;
     }
@@ -312,10 +317,11 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
       for (int c = 0; c < CB; ++c) acc[rb][c] = v4f{0.f, 0.f, 0.f, 0.f};
   };
 
-  // With nq >= NBUF (the host routes smaller nq to the generic kernel) a
-  // block ends at most once per group of NBUF steps, and the next block's
-  // first flush comes more than NBUF-1 steps later, so the finished block's
-  // sums can wait for the end of the group.
+  // With nq a multiple of NPS and at least NBUF * NPS (the host routes other
+  // node counts to another shape or the generic kernel) a block ends at most
+  // once per group of NBUF steps, and the next block's first flush comes more
+  // than NBUF-1 steps later, so the finished block's sums can wait for the
+  // end of the group.
   int done = -1;  // block finished within the current group
   auto step = [&](int t, const uint4* cur, uint4* nxt) {
     // Every wave waits for its own loads of step t, then all waves meet:
@@ -326,12 +332,15 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
     wait_step<C>(t + 1 < T, wave);
     __asm__ volatile("s_barrier" ::: "memory");
     if (t + NBUF - 1 < T) issue_next(nxt);
-    node_mfma<C, BF>(cur, af, acc, lane);
-    if ((k + 1) % kGroup16 == 0 || k + 1 == nq) flush();
-    if (++k == nq) {
-      done = blk;
-      k = 0;
-      ++blk;
+#pragma unroll
+    for (int j = 0; j < C::NPS_; ++j) {
+      node_mfma<C, BF>(cur + j * C::NFRAG_NODE * 64, af, acc, lane);
+      if ((k + 1) % kGroup16 == 0 || k + 1 == nq) flush();
+      if (++k == nq) {
+        done = blk;
+        k = 0;
+        ++blk;
+      }
     }
   };
 
@@ -416,13 +425,16 @@ int resident_wgs() {
 
 using LaunchFn = hipError_t (*)(bool, const AsmMol*, const int4*, const int*, unsigned*, int, hipStream_t);
 struct ShapeEntry {
-  int kc, q, nw, rb, cb, nbuf;
+  int kc, q, nw, rb, cb, nbuf, nps;
   LaunchFn launch;
   int (*occupancy)();
 };
 
 #define TAI_S16(KC, Q, NW, RB, CB, NBUF) \
-  {KC, Q, NW, RB, CB, NBUF, &launch_shape<Cfg16<KC, Q, NW, RB, CB, NBUF>>, &resident_wgs<Cfg16<KC, Q, NW, RB, CB, NBUF>>}
+  {KC, Q, NW, RB, CB, NBUF, 1, &launch_shape<Cfg16<KC, Q, NW, RB, CB, NBUF>>, &resident_wgs<Cfg16<KC, Q, NW, RB, CB, NBUF>>}
+#define TAI_S16P(KC, Q, NW, RB, CB, NBUF, NPS)                                   \
+  {KC, Q, NW, RB, CB, NBUF, NPS, &launch_shape<Cfg16<KC, Q, NW, RB, CB, NBUF, NPS>>, \
+   &resident_wgs<Cfg16<KC, Q, NW, RB, CB, NBUF, NPS>>}
 
 // Per inner length (kc) and duplicated chunk count (q): the shapes that fit
 // the register file (A operand 12*RB*U VGPRs plus 12*RB*CB for the
@@ -431,9 +443,11 @@ const ShapeEntry kShapes[] = {
     TAI_S16(32, 0, 8, 4, 2, 3),   TAI_S16(32, 0, 8, 4, 1, 3),
     TAI_S16(64, 0, 8, 4, 1, 3),   TAI_S16(64, 0, 8, 3, 2, 2),
     TAI_S16(96, 0, 8, 4, 1, 3),   TAI_S16(96, 0, 8, 3, 2, 2),
+    TAI_S16P(96, 1, 8, 4, 1, 2, 2),
     TAI_S16(96, 1, 8, 4, 1, 3),   TAI_S16(96, 1, 8, 3, 2, 2),   TAI_S16(96, 1, 4, 4, 1, 3),
     TAI_S16(96, 1, 4, 2, 1, 3),   TAI_S16(96, 1, 4, 2, 2, 2),
     TAI_S16(128, 0, 8, 2, 2, 3),  TAI_S16(128, 0, 8, 3, 1, 3),
+    TAI_S16P(128, 1, 8, 4, 1, 2, 2), TAI_S16P(128, 1, 8, 4, 1, 3, 2),
     TAI_S16(128, 1, 4, 4, 1, 3),  TAI_S16(128, 1, 8, 4, 1, 3),  TAI_S16(128, 1, 4, 4, 1, 2),
     TAI_S16(128, 1, 4, 3, 1, 3),  TAI_S16(128, 1, 8, 2, 2, 3),  TAI_S16(128, 1, 4, 2, 1, 3),
     TAI_S16(160, 0, 8, 2, 2, 3),  TAI_S16(160, 0, 8, 1, 2, 3),
@@ -445,6 +459,7 @@ const ShapeEntry kShapes[] = {
     TAI_S16(352, 0, 8, 1, 1, 2),
 };
 #undef TAI_S16
+#undef TAI_S16P
 
 Asm16Shape to_shape(int id) {
   const ShapeEntry& e = kShapes[id];
@@ -454,6 +469,7 @@ Asm16Shape to_shape(int id) {
   sh.rb = e.rb;
   sh.cb = e.cb;
   sh.nbuf = e.nbuf;
+  sh.nps = e.nps;
   sh.rows = 16 * e.rb * e.nw;
   sh.cols = 16 * e.cb;
   sh.wgs_per_cu = 1;  // asm16_shape asks the runtime

@@ -255,19 +255,28 @@ int shape_pick(tai_ctx* c, int prec, int n, int nq) {
   return 0;
 }
 
+// Whether a shape can stream nq nodes: its ring steps hold nps nodes each,
+// and the deferred end-of-block epilogue needs at least nbuf steps per block.
+bool shape_fits(const tai::Asm16Shape& sh, int nq) { return nq % sh.nps == 0 && nq >= sh.nbuf * sh.nps; }
+
 // Shape of the 16-bit kernel for this call (runtime facts cached per table
-// entry; the device must be current).
+// entry; the device must be current): the picked candidate if it fits nq,
+// else the first one in table order that does; id -1 if none does.
 tai::Asm16Shape shape16(tai_ctx* c, int prec, int n, int nq) {
   const int kc = tai::operand_kc(prec, n), q = tai::operand_dup_chunks(prec, n);
   tai::Asm16Shape list[16];
-  const int cnt = tai::asm16_shapes(kc, q, list, 16);
-  if (cnt == 0) {
+  const int cnt = std::min(tai::asm16_shapes(kc, q, list, 16), 16);
+  int pick = shape_pick(c, prec, n, nq);
+  if (pick < 0 || pick >= cnt || !shape_fits(list[pick], nq)) {
+    pick = -1;
+    for (int i = 0; i < cnt && pick < 0; ++i)
+      if (shape_fits(list[i], nq)) pick = i;
+  }
+  if (pick < 0) {
     tai::Asm16Shape none{};
     none.id = -1;
     return none;
   }
-  int pick = shape_pick(c, prec, n, nq);
-  if (pick < 0 || pick >= cnt || pick >= 16) pick = 0;
   for (const auto& sh : c->shapes16)
     if (sh.id == list[pick].id) return sh;
   tai::Asm16Shape sh = tai::asm16_shape(kc, q, pick);
@@ -276,13 +285,12 @@ tai::Asm16Shape shape16(tai_ctx* c, int prec, int n, int nq) {
 }
 
 // Whether the 16-bit persistent kernel takes this call: a split 16-bit
-// arithmetic whose inner length it supports, and at least as many nodes as
-// the depth of its LDS ring (fewer go to the generic kernel).
+// arithmetic whose inner length it supports, and a shape that fits the node
+// count (too few nodes for any ring go to the generic kernel).
 bool use16(tai_ctx* c, int prec, int n, int nq) {
   if (!tai::is_split16(prec) || tai::operand_kc(prec, n) > tai::asm16_max_kc() || std::getenv("TAI_ASM16_GENERIC"))
     return false;
-  const tai::Asm16Shape sh = shape16(c, prec, n, nq);
-  return sh.id >= 0 && nq >= sh.nbuf;
+  return shape16(c, prec, n, nq).id >= 0;
 }
 
 int prow_of(tai_ctx* c, int prec, int n, int nq, int64_t npair) {
@@ -382,7 +390,7 @@ int tune16(tai_ctx* c, int prec, int n, int nq, hipStream_t s, Run run) {
   int best = 0, r = TAI_OK;
   float best_ms = 0.f;
   for (int i = 0; i < cnt && i < 16; ++i) {
-    if (nq < list[i].nbuf) continue;  // such a call takes the generic kernel
+    if (!shape_fits(list[i], nq)) continue;  // shape16 would not take it
     c->force_pick = i;
     if ((r = run())) break;
     hipError_t e = hipEventRecord(a, s);

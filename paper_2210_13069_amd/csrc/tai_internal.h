@@ -132,6 +132,7 @@ int assemble_queue_blocks(int prec, int device);
 struct Asm16Shape {
   int id;          // index into the shape table (-1: none fits)
   int waves, rb, cb, nbuf;
+  int nps;         // quadrature nodes per LDS ring step (nq must be a multiple, >= nbuf * nps)
   int rows, cols;  // panel rows, block columns
   int wgs_per_cu;  // resident work groups per CU (register / LDS bound)
   int kc_key, q_key;  // the (kc, q) the shape was chosen for

@@ -168,7 +168,7 @@ def test_assemble_matches_stored_tiny_s(tai):
         assert _normwise(Bg, ref) <= (1e-10 if prec == 0 else LOWP_TOL[prec]), prec
 
 
-@pytest.mark.parametrize("case", ["sp16", "spd_small"])
+@pytest.mark.parametrize("case", ["sp16", "spd_small", "spd_small_odd"])
 def test_assemble_shapes_agree_bitwise(tai, case):
     """Every compiled 16-bit kernel shape (forced through TAI_ASM16_SHAPE)
     gives the same bits, so the autotuner's choice never changes results."""
@@ -176,8 +176,10 @@ def test_assemble_shapes_agree_bitwise(tai, case):
     if case == "sp16":
         b, P = I.sp16()                                   # n = 32: kc 96
     else:
+        # n = 40: kc 128; an odd node count leaves out the two-node-step
+        # shapes (the host falls back to the first shape that fits)
         b = I.small_random(45, natoms=8, shells=("s", "p", "d"), box=3.0)
-        P = I.Params(omega=0.4, nq=7, n=40, L=8.0)        # n = 40: kc 128
+        P = I.Params(omega=0.4, nq=7 if case == "spd_small_odd" else 8, n=40, L=8.0)
     Mg = tai.moments(b, P)
     old = os.environ.get("TAI_ASM16_SHAPE")
     try:
