@@ -206,7 +206,8 @@ int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* par
    class (npair rounded up to a power of two; for a batch, its list of basis
    sizes) -- runs every candidate twice on the call's stream, times the second
    run with HIP events and keeps the fastest for later calls of the
-   signature.  That first call therefore takes about twice the number of
+   signature (the table default stays unless another candidate is more than
+   2% faster).  That first call therefore takes about twice the number of
    candidates times longer and synchronizes the stream.  Candidates compute
    every entry with the same arithmetic in the same order: results do not
    depend on the choice.  mode 0 uses the table default shape without

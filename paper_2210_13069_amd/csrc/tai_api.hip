@@ -371,7 +371,8 @@ bool tunable(int prec, int n) {
 // Autotuner of the 16-bit kernel shape: on the first call of a signature
 // (arithmetic, degree, nodes, size class) every candidate shape runs the
 // whole call once to warm up and once timed on the caller's stream; the
-// fastest is kept for the signature.  All candidates compute every entry
+// fastest is kept for the signature (the table's first fitting shape unless
+// another is more than 2% faster).  All candidates compute every entry
 // with the same arithmetic in the same order, so the choice never changes
 // results.  `run` performs the call without a graph.
 template <class Run>
@@ -387,7 +388,7 @@ int tune16(tai_ctx* c, int prec, int n, int nq, hipStream_t s, Run run) {
   }
   const bool prof = c->prof_on;
   c->prof_on = false;
-  int best = 0, r = TAI_OK;
+  int best = -1, r = TAI_OK;
   float best_ms = 0.f;
   for (int i = 0; i < cnt && i < 16; ++i) {
     if (!shape_fits(list[i], nq)) continue;  // shape16 would not take it
@@ -403,7 +404,10 @@ int tune16(tai_ctx* c, int prec, int n, int nq, hipStream_t s, Run run) {
       r = hip_fail(c, e, "autotune timing");
       break;
     }
-    if (i == 0 || ms < best_ms) {
+    // the first candidate that fits (table order) holds unless another one
+    // is more than 2% faster, so that run-to-run noise does not flip the
+    // choice between shapes that are within it
+    if (best < 0 || ms < best_ms * 0.98f) {
       best_ms = ms;
       best = i;
     }
@@ -413,7 +417,7 @@ int tune16(tai_ctx* c, int prec, int n, int nq, hipStream_t s, Run run) {
   hipEventDestroy(a);
   hipEventDestroy(b);
   if (r) return r;
-  c->tuned.push_back({prec, n, nq, c->size_key, best});
+  c->tuned.push_back({prec, n, nq, c->size_key, best < 0 ? 0 : best});
   return TAI_OK;
 }
 
