@@ -127,30 +127,35 @@ __device__ inline void wait_step(bool next_issued, int wave) {
   wait_vmcnt<0>();
 }
 
-// The MFMA work of one node on one column block: the three G_d tiles from
-// the A fragments in registers and the Y fragments in buffer cur, then
-// acc += G_0 o G_1 o G_2 (w_k is folded into Y of direction 2).
-template <class C, bool BF>
-__device__ inline void node_mfma(const uint4* cur,
+// The MFMA work of the NPS nodes of one step on one column block: for each
+// node, the three G_d tiles from the A fragments in registers and the Y
+// fragments in buffer cur, then acc += G_0 o G_1 o G_2 (w_k is folded into
+// Y of direction 2), then node_end(j).  The Y fragments are read one chunk
+// ahead of the MFMAs that use them (two register sets), across the node
+// boundary too, so the LDS latency hides behind the RB*CB MFMAs of the
+// current chunk and the next node's first reads overlap this node's
+// Hadamard products and sum flushes.
+template <class C, bool BF, class NodeEnd>
+__device__ inline void step_mfma(const uint4* cur,
                                  const typename std::conditional<BF, v8bf, v8h>::type (&af)[3][C::RB_][C::U],
-                                 v4f (&acc)[C::RB_][C::CB_], int lane) {
+                                 v4f (&acc)[C::RB_][C::CB_], int lane, NodeEnd&& node_end) {
   using Frag = typename std::conditional<BF, v8bf, v8h>::type;
-  constexpr int RB = C::RB_, CB = C::CB_, NCH = C::NCH, NF = 3 * NCH;
-  // The Y fragments are read one chunk ahead of the MFMAs that use them
-  // (two register sets), so the LDS latency hides behind the RB*CB MFMAs
-  // of the current chunk.
+  constexpr int RB = C::RB_, CB = C::CB_, NCH = C::NCH, NF = 3 * NCH, NFS = NF * C::NPS_;
+  // fragment f of the step: node f / NF, then ((d * CB + c) * NCH + ch) within the node
+  auto frag = [&](int f, int c) {
+    const int j = f / NF, g = f % NF;
+    return *reinterpret_cast<const Frag*>(cur + (j * C::NFRAG_NODE + ((g / NCH) * CB + c) * NCH + g % NCH) * 64 + lane);
+  };
   Frag bf[2][CB];
 #pragma unroll
-  for (int c = 0; c < CB; ++c) bf[0][c] = *reinterpret_cast<const Frag*>(cur + (c * NCH) * 64 + lane);
+  for (int c = 0; c < CB; ++c) bf[0][c] = frag(0, c);
   v4f H[RB][CB], G[RB][CB];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    const int d = f / NCH, ch = f % NCH;
-    if (f + 1 < NF) {
-      const int d1 = (f + 1) / NCH, ch1 = (f + 1) % NCH;
+  for (int f = 0; f < NFS; ++f) {
+    const int g = f % NF, d = g / NCH, ch = g % NCH;
+    if (f + 1 < NFS) {
 #pragma unroll
-      for (int c = 0; c < CB; ++c)
-        bf[(f + 1) & 1][c] = *reinterpret_cast<const Frag*>(cur + ((d1 * CB + c) * NCH + ch1) * 64 + lane);
+      for (int c = 0; c < CB; ++c) bf[(f + 1) & 1][c] = frag(f + 1, c);
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -166,6 +171,7 @@ __device__ inline void node_mfma(const uint4* cur,
           else if (d == 1) H[rb][c] *= G[rb][c];
           else acc[rb][c] += H[rb][c] * G[rb][c];
         }
+      if (d == 2) node_end(f / NF);
     }
   }
 }
@@ -304,17 +310,32 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
     }
   };
 
-  auto flush = [&]() {
+  // FP32 group sums into the FP64 partial sums.  With a two-deep ring a
+  // wave has no loads in flight between its barrier and its next load issue,
+  // so the flush of a group that ends a step waits for that point and uses
+  // LDS atomic adds (ds_add_f64, no return value): no read-modify-write
+  // round trip, and the wait the compiler puts before an LDS atomic (for
+  // loads into LDS) finds nothing outstanding.  Elsewhere the flush is a
+  // plain read-modify-write.  Each lane owns its addresses, so the additions
+  // keep their node order either way.
+  constexpr bool kDeferFlush = NBUF == 2;
+  bool flush_pending = false;
+  auto flush = [&](auto atomic) {
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int c = 0; c < CB; ++c)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) mysum[((rb * CB + c) * 4 + r) * 64] += (double)acc[rb][c][r];
+        for (int r = 0; r < 4; ++r) {
+          double* sp = mysum + ((rb * CB + c) * 4 + r) * 64;
+          if constexpr (decltype(atomic)::value) atomicAdd(sp, (double)acc[rb][c][r]);
+          else *sp += (double)acc[rb][c][r];
+        }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int c = 0; c < CB; ++c) acc[rb][c] = v4f{0.f, 0.f, 0.f, 0.f};
+    flush_pending = false;
   };
 
   // With nq a multiple of NPS and at least NBUF * NPS (the host routes other
@@ -331,17 +352,20 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
     // drain the loads still in flight.
     wait_step<C>(t + 1 < T, wave);
     __asm__ volatile("s_barrier" ::: "memory");
+    if (flush_pending) flush(std::true_type{});
     if (t + NBUF - 1 < T) issue_next(nxt);
-#pragma unroll
-    for (int j = 0; j < C::NPS_; ++j) {
-      node_mfma<C, BF>(cur + j * C::NFRAG_NODE * 64, af, acc, lane);
-      if ((k + 1) % kGroup16 == 0 || k + 1 == nq) flush();
+    step_mfma<C, BF>(cur, af, acc, lane, [&](int j) {
+      if ((k + 1) % kGroup16 == 0 || k + 1 == nq) {
+        // a group that ends the step waits for the next step's start
+        if (kDeferFlush && j == C::NPS_ - 1) flush_pending = true;
+        else flush(std::false_type{});
+      }
       if (++k == nq) {
         done = blk;
         k = 0;
         ++blk;
       }
-    }
+    });
   };
 
   if constexpr (NBUF == 3) {
@@ -350,6 +374,7 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
       if (t + 1 < T) step(t + 1, yb1, yb0);
       if (t + 2 < T) step(t + 2, yb2, yb1);
       if (done >= 0) {
+        if (flush_pending) flush(std::false_type{});
         finish_block(done);
         done = -1;
       }
@@ -359,6 +384,7 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
       step(t, yb0, yb1);
       if (t + 1 < T) step(t + 1, yb1, yb0);
       if (done >= 0) {
+        if (flush_pending) flush(std::false_type{});
         finish_block(done);
         done = -1;
       }
