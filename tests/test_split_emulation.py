@@ -8,7 +8,7 @@ s0 = r(fl32(x)), s1 = r(fl32(x - s0)), s2 = r(fl32(x - s0 - s1)) with r the
 FP16 or BF16 rounding; the products of slices are exact in FP32; the slice
 products kept per direction are (0,0), (0,1), (1,0) for the X3 forms and also
 (0,2), (1,1), (2,0) for BF16X6; per node the direction results are rounded to
-FP32, multiplied (Hadamard) and summed over groups of eight nodes in FP32,
+FP32, multiplied (Hadamard) and summed over groups of sixteen nodes in FP32,
 and the groups in FP64.  Against the FP64 tensorized approximation on the
 same inputs the normwise error must be <= 1e-6 for F16X3 and BF16X6; BF16X3
 lands near 1e-5 (it is reported, and held to 3e-5).  Without the per-column
@@ -68,7 +68,7 @@ def _emulate(M, K, w, rows, kind, form, scale=True):
             g = sum(A[d][i].T @ Ys[j] for i, j in PAIRS[form])
             G.append(g.astype(np.float32))
         acc32 = acc32 + (G[0] * G[1]) * G[2]
-        if (k + 1) % 8 == 0 or k + 1 == len(w):
+        if (k + 1) % 16 == 0 or k + 1 == len(w):
             acc64 += acc32.astype(np.float64)
             acc32[:] = 0
     e = ex[0] + ex[1] + ex[2]
