@@ -120,19 +120,22 @@ def test_assemble_fp64_fp32_inner_lengths(tai, n):
         assert _normwise(Bg, Bg.T) <= (1e-14 if prec == 0 else tol)
 
 
-@pytest.mark.parametrize("nq", [1, 2, 3, 4, 5, 7, 8, 9, 17])
-def test_assemble_16bit_node_counts(tai, nq):
-    """Split 16-bit forms at node counts around the LDS ring depth (fewer
-    than three nodes take the generic kernel) and around the FP32 group of
-    eight, with column blocks ending anywhere within a group of steps."""
+@pytest.mark.parametrize("n", [24, 40])
+@pytest.mark.parametrize("nq", [1, 2, 3, 4, 5, 6, 7, 8, 9, 17, 18, 33])
+def test_assemble_16bit_node_counts(tai, nq, n):
+    """Split 16-bit forms at node counts around the LDS ring depth (too few
+    nodes take the generic kernel), around the two-node steps (odd counts
+    and counts below twice the ring depth fall back to single-node shapes;
+    n = 40 has two-node shapes, n = 24 none) and around the FP32 group of
+    sixteen nodes, with column blocks ending anywhere within a group of steps."""
     b = I.small_random(41, natoms=6, shells=("s", "p"), box=3.0)   # nb = 24, npair = 300
-    P = I.Params(omega=0.6, nq=nq, n=24, L=8.0)
+    P = I.Params(omega=0.6, nq=nq, n=n, L=8.0)
     Mr, K, w = _oracle(b, P)
     Br = T.B_full(Mr, K, w)
     Mg = tai.moments(b, P)
     for prec in (4, 2):
         Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
-        assert _normwise(Bg, Br) <= LOWP_TOL[prec], (nq, prec)
+        assert _normwise(Bg, Br) <= LOWP_TOL[prec], (nq, n, prec)
         assert np.array_equal(Bg, Bg.T) or _normwise(Bg, Bg.T) <= LOWP_TOL[prec]
 
 
