@@ -73,9 +73,11 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
   constexpr int CS = A0G + 1, MS = NP + 1;     // LDS row strides (doubles)
   using T = typename Op::T;
   using Acc = typename Op::Acc;
-  __shared__ T s_c[kKB * CS];
-  __shared__ T s_m1[kKB * MS];
-  __shared__ T s_m2[kKB * MS];
+  // two LDS buffers: batch b is read from buffer b & 1 while batch b + 1 is
+  // stored into the other after the MFMAs, one barrier per batch
+  __shared__ T s_c2[2][kKB * CS];
+  __shared__ T s_m12[2][kKB * MS];
+  __shared__ T s_m22[2][kKB * MS];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
@@ -110,14 +112,14 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
       pre[i] = (T)v;
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + 512 * i;
       const int row = e / kKB, qq = e % kKB;
-      if (row < A0G) s_c[qq * CS + row] = pre[i];
-      else if (row < A0G + NP) s_m1[qq * MS + row - A0G] = pre[i];
-      else s_m2[qq * MS + row - A0G - NP] = pre[i];
+      if (row < A0G) s_c2[buf][qq * CS + row] = pre[i];
+      else if (row < A0G + NP) s_m12[buf][qq * MS + row - A0G] = pre[i];
+      else s_m22[buf][qq * MS + row - A0G - NP] = pre[i];
     }
   };
 
@@ -134,11 +136,15 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
       }
 
   load(q0);
-  for (int64_t qb = q0; qb < q1; qb += kKB) {
-    __syncthreads();  // the previous batch is consumed
-    store();
-    __syncthreads();
-    if (qb + kKB < q1) load(qb + kKB);  // next batch in flight during the MFMAs
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t qb = q0; qb < q1; qb += kKB, buf ^= 1) {
+    const bool more = qb + kKB < q1;
+    if (more) load(qb + kKB);  // next batch in flight during the MFMAs
+    const T* s_c = s_c2[buf];
+    const T* s_m1 = s_m12[buf];
+    const T* s_m2 = s_m22[buf];
 #pragma unroll 2
     for (int st = 0; st < kKB / 4; ++st) {
       const int kk = 4 * st + kg;  // this lane's pair within the batch
@@ -170,6 +176,10 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
             acc[a][i][j] = Acc{0, 0, 0, 0};
           }
     }
+    // the other buffer was last read in the previous batch, which every wave
+    // finished before the barrier that ended it
+    if (more) store(buf ^ 1);
+    __syncthreads();
   }
 
   // lane l holds column a2 = 16 j + l%16 and rows a1 = 16 i + row_of(l/16, r)
