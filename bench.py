@@ -79,8 +79,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU layout is described in "
-              "DESIGN.md (shard tiles / pairs, one all-reduce of the grid density). Use --gpus 1.",
+        print("bench.py: runs on one GPU only (across GPUs the assembly tiles and the J pairs would be "
+              "sharded, with one all-reduce of the n^3 grid density for J). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
