@@ -59,9 +59,11 @@ def traffic_from_profiles(kernel_src_sha, workload):
 
 
 def src_sha():
+    """Hash of what the dominant kernel is built from: its source, the shared
+    header and the build flags."""
     h = hashlib.sha256()
-    for f in ("k_assemble.hip", "k_assemble16.hip", "tai_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2210_13069_amd", "csrc", f), "rb").read())
+    for f in ("csrc/k_assemble16.hip", "csrc/tai_internal.h", "build.py"):
+        h.update(open(os.path.join(ROOT, "paper_2210_13069_amd", f), "rb").read())
     return h.hexdigest()[:16]
 
 

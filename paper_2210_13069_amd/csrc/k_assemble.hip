@@ -44,8 +44,16 @@ template <typename T>
 __device__ inline T to_slice(double x);
 template <>
 __device__ inline __bf16 to_slice<__bf16>(double x) { return (__bf16)(float)x; }
+// FP64 -> FP32 -> FP16 rounds exactly as FP64 -> FP16 does (24 >= 2*11 + 2
+// bits), so the compiler folds the two conversions into one, which has no
+// instruction and is expanded into ~35 integer operations.  The empty asm
+// keeps the two hardware conversions.
 template <>
-__device__ inline _Float16 to_slice<_Float16>(double x) { return (_Float16)(float)x; }
+__device__ inline _Float16 to_slice<_Float16>(double x) {
+  float f = (float)x;
+  __asm__("" : "+v"(f));
+  return (_Float16)f;
+}
 
 // Operand rows are staged through LDS so that the global writes coalesce: a
 // work group of kRowsPerTile threads builds that many consecutive rows (one
