@@ -25,6 +25,11 @@ gives Theorem 3.1 in node form:
 
   B(p,q) = (2/sqrt(pi)) sum_k w_k prod_{d=1..3} m_{p,d}^T K_k m_{q,d}
 
+With a degree per quadrature node (the paper's N_i, eq. chebcheb and the
+nested coefficient moments of section 3.2) node k keeps only the Chebyshev
+coefficients of its factor below N_k; `truncated_tables` gives both that
+coefficient form and its node-value form.
+
 Every function below cites the passage it follows.  All arithmetic is FP64.
 Notation: nb basis functions, pairs p=(mu,nu) with mu<=nu in row-major upper
 triangle order, npair = nb(nb+1)/2; n Chebyshev nodes per direction; nq
@@ -145,6 +150,99 @@ def ktables(t, xi):
     """
     d2 = (xi[:, None] - xi[None, :]) ** 2
     return np.exp(-(np.asarray(t)[:, None, None] ** 2) * d2[None, :, :])
+
+
+# ---------------------------------------------------------------------------
+# Per-node degree N_i (eq. chebcheb with N_i interpolation points for node i;
+# the nested coefficient moments of section 3.2, fast evaluation of tensor
+# products: the moments of node i are the leading N_i of those at N = max N_i)
+# ---------------------------------------------------------------------------
+def cheb_vandermonde(xi, L):
+    """V[a, j] = T_j(xi_a / L) for j < n: the Chebyshev polynomials (Def. 2.2)
+    of the box variable on the grid, T_j(u) = cos(j arccos u)."""
+    u = np.clip(np.asarray(xi, dtype=np.float64) / L, -1.0, 1.0)
+    return np.cos(np.outer(np.arccos(u), np.arange(len(u))))
+
+
+def cheb_coefficients(F, V):
+    """Coefficients alpha of the tensor Chebyshev interpolant of node values F
+    (n x n), eq. chebcheb: the polynomial sum_ij alpha_ij T_i(x/L) T_j(y/L)
+    equal to F at every grid point, i.e. V alpha V^T = F (two linear solves)."""
+    X = np.linalg.solve(V, F)            # V X = F, X = alpha V^T
+    return np.linalg.solve(V, X.T).T     # V alpha^T = X^T
+
+
+def tail_sums(alpha):
+    """tail[m] = sum of |alpha_ij| over max(i, j) >= m (m = 0..n, tail[n] = 0),
+    summed shell by shell from the outside in.  Dropping those coefficients
+    moves the polynomial by at most tail[m] anywhere on the box, |T_j| <= 1."""
+    a = np.abs(np.asarray(alpha, dtype=np.float64))
+    n = a.shape[0]
+    tail = np.zeros(n + 1)
+    for s in range(n - 1, -1, -1):
+        shell = a[s, :s + 1].sum() + a[:s, s].sum()
+        tail[s] = tail[s + 1] + shell
+    return tail
+
+
+def node_degrees(alphas, tol):
+    """N_k for each node: the smallest m >= 1 with tail(m) <= tol, the reading
+    taken here of the paper's adaptive choice of N_i (which it delegates to
+    chebfun2).  tol <= 0 keeps every node at n."""
+    n = alphas.shape[1]
+    if tol <= 0:
+        return np.full(alphas.shape[0], n, dtype=np.int64)
+    out = []
+    for a in alphas:
+        tail = tail_sums(a)
+        out.append(next(m for m in range(1, n + 1) if tail[m] <= tol))
+    return np.asarray(out, dtype=np.int64)
+
+
+def truncated_tables(t, xi, L, tol):
+    """Per-node degree form of the interpolation tables.
+
+    For node k the coefficients alpha_k of its factor exp(-t_k^2 (x-y)^2)
+    (eq. chebcheb on the n x n grid) are kept for i, j < N_k and dropped
+    elsewhere (alpha_hat_k).  Returns (N, alpha_hat, Kt): N[k], the kept
+    coefficients [nq][n][n] and Kt_k = V alpha_hat_k V^T, the node values of
+    the truncated polynomial, which every node-form route (Theorem 3.1, the
+    grid route of J) takes in place of K_k.  tol <= 0 returns the full tables.
+    """
+    K = ktables(t, xi)
+    V = cheb_vandermonde(xi, L)
+    alphas = np.array([cheb_coefficients(Kk, V) for Kk in K])
+    N = node_degrees(alphas, tol)
+    ahat = np.zeros_like(alphas)
+    for k, m in enumerate(N):
+        ahat[k, :m, :m] = alphas[k, :m, :m]
+    Kt = np.einsum("ai,kij,bj->kab", V, ahat, V) if tol > 0 else K
+    return N, ahat, Kt
+
+
+def coefficient_moments(M, V):
+    """mu_d = V^T M_d: the moments against T_j(x/L), j < n (eq. defV in the
+    coefficient basis).  Exact counterpart of the Lagrange moments, since
+    T_j = sum_a T_j(xi_a) l_a for every j < n."""
+    return np.einsum("aj,dap->djp", V, M)
+
+
+def B_full_degrees(mu, ahat, N, w, rows=None):
+    """B by eq. tensors with a degree per node: node k contracts only the
+    leading N_k coefficient moments of every pair with the N_k x N_k block of
+    its coefficient matrix,
+    B = (2/sqrt(pi)) sum_k w_k prod_d mu_d[:N_k]^T alpha_hat_k mu_d[:N_k]."""
+    npair = mu.shape[2]
+    r = np.arange(npair) if rows is None else np.asarray(rows, dtype=np.int64)
+    B = np.zeros((len(r), npair))
+    for k in range(len(N)):
+        m = int(N[k])
+        A = ahat[k, :m, :m]
+        F = np.ones((len(r), npair))
+        for d in range(3):
+            F *= mu[d][:m, r].T @ (A @ mu[d][:m])
+        B += w[k] * F
+    return (2.0 / SQRT_PI) * B
 
 
 # ---------------------------------------------------------------------------
