@@ -90,7 +90,13 @@ typedef struct {
 
 /* Method parameters.  omega > 0; 1 <= nq <= 128 Gauss-Legendre nodes in t;
    2 <= n <= 64 Chebyshev nodes per direction; L > 0 the half-width of the box
-   [-L,L]^3 (the paper's b, eq. compact); nodes and prec from the enums. */
+   [-L,L]^3 (the paper's b, eq. compact); nodes and prec from the enums.
+   degree_tol >= 0 (finite) selects a degree per quadrature node (the
+   paper's N_i, eq. chebcheb): 0 keeps every node at n; with degree_tol > 0
+   node k keeps the Chebyshev coefficients of its factor below N_k, the
+   smallest degree whose dropped coefficients sum in absolute value to at
+   most degree_tol, so each factor moves by at most degree_tol on the box
+   (tai_degrees).  Every entry point then uses the truncated factors. */
 typedef struct {
   double  omega;
   int32_t nq;
@@ -98,6 +104,7 @@ typedef struct {
   double  L;
   int32_t nodes;
   int32_t prec;
+  double  degree_tol;
 } tai_params;
 
 /* ---- context ------------------------------------------------------------ */
@@ -129,10 +136,23 @@ int tai_sync(tai_ctx* ctx, void* stream);
 /* Quadrature nodes and interpolation tables, computed on the device in FP64.
    t[k], w[k] (k < nq): Gauss-Legendre nodes/weights of int_0^omega (eq. TEI2,
    Prop. 2.4); xi[a] (a < n): Chebyshev nodes on [-L,L] (Def. 2.2);
-   K[k][a][b] = exp(-t_k^2 (xi_a - xi_b)^2) (eq. chebcheb, node form).
+   K[k][a][b] = exp(-t_k^2 (xi_a - xi_b)^2) (eq. chebcheb, node form), or
+   with degree_tol > 0 the values at the grid of node k's polynomial cut to
+   degree N_k (tai_degrees).
    All DEVICE double; any of the four pointers may be NULL to skip it. */
 int tai_quadrature(tai_ctx* ctx, const tai_params* params,
                    double* t, double* w, double* xi, double* K, void* stream);
+
+/* Per-node degrees (eq. chebcheb with N_k interpolation points for node k,
+   and the nested coefficient moments of section 3.2).  For each node the
+   Chebyshev coefficients C_k[i][j] of the n x n interpolant of
+   exp(-t_k^2 (x-y)^2) in T_i(x/L) T_j(y/L) are computed in FP64; N_k is the
+   smallest m >= 1 with sum_{max(i,j) >= m} |C_k[i][j]| <= degree_tol (n when
+   degree_tol == 0), and entries with i or j >= N_k are set to zero.
+   nk: DEVICE int32 [nq] or NULL; C: DEVICE double [nq][n][n] or NULL (not
+   both NULL).  With degree_tol > 0, tai_quadrature's K holds the node values
+   of the kept polynomials. */
+int tai_degrees(tai_ctx* ctx, const tai_params* params, int32_t* nk, double* C, void* stream);
 
 /* 1D moments (eq. defV, Lagrange basis), FP64 on the device:
      M[d][a][p] = int_{-L}^{L} g_{mu,d}(x) g_{nu,d}(x) l_a(x) dx

@@ -83,6 +83,8 @@ int validate_params(tai_ctx* c, const tai_params* p) {
   if (p->nodes != TAI_NODES_LOBATTO && p->nodes != TAI_NODES_GAUSS)
     return fail(c, TAI_ERR_INVALID_ARG, "nodes must be TAI_NODES_LOBATTO or TAI_NODES_GAUSS");
   if (p->prec < TAI_FP64 || p->prec > TAI_F16X3) return fail(c, TAI_ERR_INVALID_ARG, "unknown prec");
+  if (!finite(p->degree_tol) || p->degree_tol < 0)
+    return fail(c, TAI_ERR_INVALID_ARG, "degree_tol must be finite and >= 0");
   return TAI_OK;
 }
 
@@ -514,7 +516,7 @@ int tai_quadrature(tai_ctx* c, const tai_params* p, double* t, double* w, double
   hipError_t e;
   {
     Timed tm(c, kStNodes, s);
-    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, tb, s);
+    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, p->degree_tol, tb, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
   const size_t nq = p->nq, n = p->n;
@@ -522,6 +524,28 @@ int tai_quadrature(tai_ctx* c, const tai_params* p, double* t, double* w, double
   if (w && (e = hipMemcpyAsync(w, tb.w, 8 * nq, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(c, e, "copy w");
   if (xi && (e = hipMemcpyAsync(xi, tb.xi, 8 * n, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(c, e, "copy xi");
   if (K && (e = hipMemcpyAsync(K, tb.K, 8 * nq * n * n, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(c, e, "copy K");
+  return TAI_OK;
+}
+
+int tai_degrees(tai_ctx* c, const tai_params* p, int32_t* nk, double* C, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!nk && !C) return fail(c, TAI_ERR_INVALID_ARG, "nk and C are both NULL");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(p->nq, p->n)))) return r;
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, p->nq, p->n);
+  hipError_t e;
+  {
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, 0.0, tb, s);
+    if (e == hipSuccess) e = tai::launch_degrees(p->nq, p->n, p->nodes, p->degree_tol, tb, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "degrees kernel");
+  const size_t nq = p->nq, n = p->n;
+  if (nk && (e = hipMemcpyAsync(nk, tb.nk, 4 * nq, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(c, e, "copy nk");
+  if (C && (e = hipMemcpyAsync(C, tb.C, 8 * nq * n * n, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(c, e, "copy C");
   return TAI_OK;
 }
 
@@ -544,7 +568,7 @@ int tai_moments(tai_ctx* c, const tai_basis* b, const tai_params* p, double* M, 
   NodeTables tb = tai::carve_node_tables(c->nodes.p, p->nq, p->n);
   {
     Timed tm(c, kStNodes, s);
-    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, tb, s);
+    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, p->degree_tol, tb, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
   tai::DevBasis db = dev_basis_view(b, static_cast<char*>(c->basis.p));
@@ -569,7 +593,7 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
   hipError_t e;
   {
     Timed tm(c, kStNodes, s);
-    e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, tb, s);
+    e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, p->degree_tol, tb, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
   int32_t* ex = static_cast<int32_t*>(c->opEx.p);
@@ -738,12 +762,15 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   const size_t tab_bytes = off_items + (split16 ? items16.bytes() : 0);
   if ((r = ensure(c, c->b_mols, tab_bytes))) return r;
   std::vector<tai::PrepMol> prep(nmol);
+  bool any_degree = false;
   int64_t max_npair = 0;
   int max_prow = 0;
   for (int i = 0; i < nmol; ++i) {
     tai::PrepMol& q = prep[i];
     q.omega = mols[i].params.omega;
     q.L = mols[i].params.L;
+    q.degree_tol = mols[i].params.degree_tol;
+    any_degree = any_degree || mols[i].params.degree_tol > 0;
     q.tb = tai::carve_node_tables(static_cast<char*>(c->b_nodes.p) + off_nodes[i], nq, n);
     q.basis = dev_basis_view(&mols[i].basis, static_cast<char*>(c->b_basis.p) + off_basis[i]);
     q.M = mols[i].M;
@@ -773,7 +800,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   auto enqueue = [&](hipStream_t st) -> hipError_t {
     // preparation of every molecule, one launch per stage
     const auto* prep_dev = reinterpret_cast<const tai::PrepMol*>(static_cast<char*>(c->b_mols.p) + off_prep);
-    hipError_t err = tai::launch_nodes_batch(prep_dev, nmol, nq, n, mols[0].params.nodes, st);
+    hipError_t err = tai::launch_nodes_batch(prep_dev, nmol, nq, n, mols[0].params.nodes, any_degree, st);
     if (err == hipSuccess) err = tai::launch_moments_batch(prep_dev, nmol, max_npair, n, st);
     if (err == hipSuccess) err = tai::launch_pack_batch(prec, prep_dev, nmol, max_prow, n, st);
     if (err == hipSuccess) err = tai::launch_project_batch(prec, prep_dev, nmol, max_prow, n, nq, st);
@@ -874,7 +901,7 @@ int tai_apply_J(tai_ctx* c, const double* M, int32_t nb, const tai_params* p, co
   hipError_t e;
   {
     Timed tm(c, kStNodes, s);
-    e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, tb, s);
+    e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, p->degree_tol, tb, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
   tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, n, (int)npair);

@@ -23,14 +23,23 @@ struct NodeTables {
   double* gam;   // [n][n]    Chebyshev-to-Lagrange map: l_a(x) = sum_k gam[a][k] T_k(x/L)
   double* pz;    // [kMomOrder] panel rule nodes on [-1, 1]
   double* pw;    // [kMomOrder] panel rule weights
+  double* C;     // [nq][n][n] Chebyshev coefficients of each node's factor,
+                 //            zero beyond its degree (launch_degrees)
+  int32_t* nk;   // [nq]      per-node degree N_k (launch_degrees)
 };
 
 // Bytes needed by the node tables (each array 256-byte aligned).
 size_t node_tables_bytes(int nq, int n);
 NodeTables carve_node_tables(void* base, int nq, int n);
 
-hipError_t launch_nodes(double omega, int nq, int n, double L, int kind,
+// Nodes, weights, Chebyshev nodes and K tables; with degree_tol > 0 also the
+// per-node degrees, after which K holds the truncated tables (launch_degrees).
+hipError_t launch_nodes(double omega, int nq, int n, double L, int kind, double degree_tol,
                         const NodeTables& tb, hipStream_t s);
+// Per-node degree (eq. chebcheb with N_k points for node k): C_k, N_k, and,
+// for degree_tol > 0, K_k replaced by the node values of the kept part.
+// Needs the tables of launch_nodes.
+hipError_t launch_degrees(int nq, int n, int kind, double degree_tol, const NodeTables& tb, hipStream_t s);
 
 // Device copy of one molecule's basis.
 struct DevBasis {
@@ -94,7 +103,7 @@ struct AsmMol {
 // moments, operand packing and projection), read by the batch kernels at
 // blockIdx.y (nodes, moments) or blockIdx.z (pack, project).
 struct PrepMol {
-  double omega, L;
+  double omega, L, degree_tol;
   NodeTables tb;
   DevBasis basis;
   double* M;
@@ -104,7 +113,10 @@ struct PrepMol {
   int32_t* ex;
   void* Y;
 };
-hipError_t launch_nodes_batch(const PrepMol* mols, int nmol, int nq, int n, int kind, hipStream_t s);
+// any_degree: some molecule has degree_tol > 0 (then the degree stage runs
+// for the batch; molecules with degree_tol <= 0 keep their tables).
+hipError_t launch_nodes_batch(const PrepMol* mols, int nmol, int nq, int n, int kind, bool any_degree,
+                              hipStream_t s);
 hipError_t launch_moments_batch(const PrepMol* mols, int nmol, int64_t max_npair, int n, hipStream_t s);
 hipError_t launch_pack_batch(int prec, const PrepMol* mols, int nmol, int max_prow, int n, hipStream_t s);
 hipError_t launch_project_batch(int prec, const PrepMol* mols, int nmol, int max_prow, int n, int nq,

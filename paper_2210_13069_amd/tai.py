@@ -28,7 +28,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 
 # exported symbols declared in include/tai.h
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
-           "tai_quadrature", "tai_moments", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
+           "tai_quadrature", "tai_degrees", "tai_moments", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
            "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched"]
 
@@ -53,7 +53,8 @@ class tai_params(ctypes.Structure):
                 ("n", ctypes.c_int32),
                 ("L", ctypes.c_double),
                 ("nodes", ctypes.c_int32),
-                ("prec", ctypes.c_int32)]
+                ("prec", ctypes.c_int32),
+                ("degree_tol", ctypes.c_double)]
 
 
 class tai_mol(ctypes.Structure):
@@ -84,6 +85,7 @@ def load_library(path=LIB_PATH):
     lib.tai_last_error.restype = ctypes.c_char_p
     lib.tai_sync.argtypes = [vp, vp]
     lib.tai_quadrature.argtypes = [vp, ctypes.POINTER(tai_params), vp, vp, vp, vp, vp]
+    lib.tai_degrees.argtypes = [vp, ctypes.POINTER(tai_params), vp, vp, vp]
     lib.tai_moments.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.POINTER(tai_params), vp, vp]
     lib.tai_assemble_B.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, ctypes.c_int64, vp]
     lib.tai_assemble_B_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(tai_mol), vp]
@@ -110,9 +112,11 @@ def _stream(stream):
 
 
 def make_params(p, prec=None):
-    """tai_params from an object with omega, nq, n, L, nodes (and prec)."""
+    """tai_params from an object with omega, nq, n, L, nodes (and prec,
+    degree_tol)."""
     return tai_params(float(p.omega), int(p.nq), int(p.n), float(p.L), int(getattr(p, "nodes", 0)),
-                      int(prec if prec is not None else getattr(p, "prec", FP64)))
+                      int(prec if prec is not None else getattr(p, "prec", FP64)),
+                      float(getattr(p, "degree_tol", 0.0)))
 
 
 class BasisArrays:
@@ -167,6 +171,11 @@ class Context:
         p = params if isinstance(params, tai_params) else make_params(params)
         self.check(self.lib.tai_quadrature(self.h, ctypes.byref(p), _ptr(t), _ptr(w), _ptr(xi), _ptr(K),
                                            _stream(stream)), "tai_quadrature")
+
+    def degrees(self, params, nk=None, C=None, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        self.check(self.lib.tai_degrees(self.h, ctypes.byref(p), _ptr(nk), _ptr(C), _stream(stream)),
+                   "tai_degrees")
 
     def moments(self, basis_arrays, params, M, stream=None):
         p = params if isinstance(params, tai_params) else make_params(params)
@@ -230,6 +239,17 @@ def quadrature(params, device=0):
     K = torch.empty((nq, n, n), dtype=torch.float64, device=dev)
     context(device).quadrature(params, t, w, xi, K)
     return t, w, xi, K
+
+
+def degrees(params, device=0):
+    """Per-node degrees N_k [nq] (int32) and kept coefficients C [nq][n][n]."""
+    import torch
+    nq, n = int(params.nq), int(params.n)
+    dev = torch.device("cuda", device)
+    nk = torch.empty(nq, dtype=torch.int32, device=dev)
+    C = torch.empty((nq, n, n), dtype=torch.float64, device=dev)
+    context(device).degrees(params, nk, C)
+    return nk, C
 
 
 def moments(basis, params, coef=None, device=0):

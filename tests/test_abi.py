@@ -64,7 +64,7 @@ def test_status_strings(lib):
 
 
 def test_null_context_rejected(lib):
-    p = tai.tai_params(0.5, 8, 8, 4.0, 0, 0)
+    p = tai.tai_params(0.5, 8, 8, 4.0, 0, 0, 0.0)
     assert lib.tai_quadrature(None, ctypes.byref(p), None, None, None, None, None) == tai.TAI_ERR_INVALID_ARG
     assert lib.tai_sync(None, None) == tai.TAI_ERR_INVALID_ARG
     assert lib.tai_destroy(None) == tai.TAI_OK
@@ -73,15 +73,17 @@ def test_null_context_rejected(lib):
 
 
 def _params(**kw):
-    base = dict(omega=0.5, nq=8, n=16, L=8.0, nodes=0, prec=0)
+    base = dict(omega=0.5, nq=8, n=16, L=8.0, nodes=0, prec=0, degree_tol=0.0)
     base.update(kw)
-    return tai.tai_params(base["omega"], base["nq"], base["n"], base["L"], base["nodes"], base["prec"])
+    return tai.tai_params(base["omega"], base["nq"], base["n"], base["L"], base["nodes"], base["prec"],
+                          base["degree_tol"])
 
 
 @pytest.mark.parametrize("bad", [dict(omega=0.0), dict(omega=-1.0), dict(omega=float("nan")),
                                  dict(omega=float("inf")), dict(nq=0), dict(nq=129), dict(n=1),
                                  dict(n=65), dict(L=0.0), dict(L=float("nan")), dict(nodes=2),
-                                 dict(prec=5), dict(prec=-1)])
+                                 dict(prec=5), dict(prec=-1), dict(degree_tol=-1e-9),
+                                 dict(degree_tol=float("nan")), dict(degree_tol=float("inf"))])
 def test_invalid_params(hctx, bad):
     p = _params(**bad)
     st = hctx.lib.tai_quadrature(hctx.h, ctypes.byref(p), None, None, None, None, None)
@@ -92,6 +94,19 @@ def test_invalid_params(hctx, bad):
 def test_valid_params_host_only_not_ready(hctx):
     p = _params()
     assert hctx.lib.tai_quadrature(hctx.h, ctypes.byref(p), None, None, None, None, None) == tai.TAI_ERR_NOT_READY
+    p = _params(degree_tol=1e-8)
+    assert hctx.lib.tai_quadrature(hctx.h, ctypes.byref(p), None, None, None, None, None) == tai.TAI_ERR_NOT_READY
+
+
+def test_degrees_argument_checks(hctx):
+    dummy = ctypes.c_void_p(16)
+    p = _params(degree_tol=1e-8)
+    assert hctx.lib.tai_degrees(hctx.h, ctypes.byref(p), None, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert hctx.lib.tai_degrees(hctx.h, None, dummy, None, None) == tai.TAI_ERR_INVALID_ARG
+    bad = _params(degree_tol=-1.0)
+    assert hctx.lib.tai_degrees(hctx.h, ctypes.byref(bad), dummy, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert hctx.lib.tai_degrees(hctx.h, ctypes.byref(p), dummy, None, None) == tai.TAI_ERR_NOT_READY
+    assert hctx.lib.tai_degrees(hctx.h, ctypes.byref(p), None, dummy, None) == tai.TAI_ERR_NOT_READY
 
 
 def _basis(**mut):

@@ -1,0 +1,137 @@
+"""GPU parity of the per-node degree form (eq. chebcheb with N_k points for
+node k): the degrees exactly, the kept coefficients and truncated K tables,
+then B in every arithmetic, the batched path and J, all through the C ABI
+against the oracle's truncated tables on the same seeded inputs.
+
+Tolerances are those of the fixed-degree paths (test_gpu_parity)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import tairef as T
+from paper_2210_13069_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+LOWP_TOL = {1: 1e-6, 2: 3e-5, 3: 1e-6, 4: 1e-6}
+
+
+def _normwise(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _oracle_tables(P):
+    t, w = T.time_nodes(P.omega, P.nq)
+    xi, _ = T.cheb_nodes(P.n, P.L, P.nodes)
+    N, ahat, Kt = T.truncated_tables(t, xi, P.L, P.degree_tol)
+    return N, ahat, Kt, w
+
+
+def _not_a_tie(P, N):
+    # the degree is an FP64 decision on both sides; it is compared exactly
+    # only where the tail sums are not within rounding of the tolerance
+    t, _ = T.time_nodes(P.omega, P.nq)
+    xi, _ = T.cheb_nodes(P.n, P.L, P.nodes)
+    V = T.cheb_vandermonde(xi, P.L)
+    K = T.ktables(t, xi)
+    for k in range(P.nq):
+        tail = T.tail_sums(T.cheb_coefficients(K[k], V))
+        for m in (N[k] - 1, N[k]):
+            if 1 <= m <= P.n - 1:
+                assert abs(tail[m] - P.degree_tol) > 1e-9 * P.degree_tol, (k, m)
+
+
+CASES = {
+    "spd400_tables": I.Params(omega=0.3, nq=32, n=40, L=16.0, degree_tol=1e-8),
+    "omega1": I.Params(omega=1.0, nq=32, n=40, L=16.0, degree_tol=1e-6),
+    "sp16_tables": I.Params(omega=0.5, nq=24, n=32, L=12.0, degree_tol=1e-10),
+    "gauss_nodes": I.Params(omega=0.7, nq=16, n=24, L=8.0, nodes=1, degree_tol=1e-7),
+    "n64": I.Params(omega=0.5, nq=8, n=64, L=12.0, degree_tol=1e-9),
+    "off": I.Params(omega=0.5, nq=8, n=24, L=8.0, degree_tol=0.0),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_degrees_and_tables(tai, case):
+    P = CASES[case]
+    N, ahat, Kt, _ = _oracle_tables(P)
+    if P.degree_tol > 0:
+        _not_a_tie(P, N)
+    nk, C = tai.degrees(P)
+    np.testing.assert_array_equal(nk.cpu().numpy(), N)
+    # kept coefficients (all of them when degree_tol == 0)
+    assert np.max(np.abs(C.cpu().numpy() - ahat)) <= 1e-13
+    _, _, _, K = (x.cpu().numpy() for x in tai.quadrature(P))
+    np.testing.assert_allclose(K, Kt, rtol=0, atol=1e-13)
+
+
+def _small_spd():
+    b = I.small_random(61, natoms=8, shells=("s", "p", "d"), box=4.0, alpha_lo=0.1, alpha_hi=30.0)
+    return b, I.Params(omega=0.4, nq=24, n=40, L=10.0, degree_tol=1e-8)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("case", ["sp16", "spd_small"])
+def test_assemble_B_with_degrees(tai, prec, case):
+    if case == "sp16":
+        b, P = I.sp16()
+        P = dataclasses.replace(P, degree_tol=1e-8)
+    else:
+        b, P = _small_spd()
+    N, _, Kt, w = _oracle_tables(P)
+    assert N.min() < P.n
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, kind=P.nodes)
+    Br = T.B_full(Mr, Kt, w)
+    Mg = tai.moments(b, P)
+    Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+    tol = 1e-10 if prec == 0 else LOWP_TOL[prec]
+    err = _normwise(Bg, Br)
+    assert err <= tol, f"prec {prec}: normwise {err:.3e} > {tol}"
+    assert _normwise(Bg, Bg.T) <= (1e-14 if prec == 0 else tol)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_J_with_degrees(tai, prec):
+    import torch
+    b, P = _small_spd()
+    D = I.random_density(np.random.default_rng(8), b)
+    _, _, Kt, w = _oracle_tables(P)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
+    Jr = T.J_grid(Mr, Kt, w, D)
+    Mg = tai.moments(b, P)
+    Jg = tai.apply_J(Mg, torch.as_tensor(D, device=Mg.device), P, prec=prec).cpu().numpy()
+    err = np.linalg.norm(Jg - Jr, 2) / np.linalg.norm(Jr, 2)
+    assert err <= (1e-10 if prec == 0 else 1e-6), err
+
+
+@pytest.mark.parametrize("prec", [4, 0])
+def test_batched_with_mixed_degrees(tai, prec):
+    """Molecules of one batch with and without per-node degrees, each equal
+    bit for bit to its own single-molecule call."""
+    import torch
+    mols = I.batch64(nmol=5)
+    mols = [(b, dataclasses.replace(P, degree_tol=(1e-8 if i % 2 == 0 else 0.0))) for i, (b, P) in enumerate(mols)]
+    ctx = tai.context(0)
+    outs, Ms, keep, structs = [], [], [], []
+    dt = torch.float64 if prec == tai.FP64 else torch.float32
+    for b, P in mols:
+        ba = tai.BasisArrays(b)
+        keep.append(ba)
+        M = torch.empty((3, P.n, b.npair), dtype=torch.float64, device="cuda")
+        B = torch.full((b.npair, b.npair), float("nan"), dtype=dt, device="cuda")
+        Ms.append(M)
+        outs.append(B)
+        structs.append(tai.tai_mol(ba.struct, tai.make_params(P, prec), M.data_ptr(), B.data_ptr(), b.npair))
+    ctx.assemble_B_batched(structs)
+    torch.cuda.synchronize()
+    for (b, P), M, B in zip(mols, Ms, outs):
+        Bref = tai.assemble_B(tai.moments(b, P), P, prec=prec)
+        assert torch.equal(B, Bref)
+    # one molecule against the oracle
+    b, P = mols[0]
+    _, _, Kt, w = _oracle_tables(P)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
+    Br = T.B_full(Mr, Kt, w)
+    tol = 1e-10 if prec == 0 else LOWP_TOL[prec]
+    assert _normwise(outs[0].cpu().numpy().astype(np.float64), Br) <= tol
