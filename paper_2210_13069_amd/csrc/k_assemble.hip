@@ -23,6 +23,7 @@
 #include "tai_internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace tai {
 namespace {
@@ -445,7 +446,21 @@ __device__ inline void assemble_tile(const AsmMol& m, int I, int J) {
 // fragments of the next PD (node, direction, chunk) steps are loaded while
 // the MFMAs of the current one run.  KC is the inner length (n rounded up
 // to 8).
-template <class Op, int KC, int WN, int PD>
+// Call f(integral_constant<int, c>) for the compile-time count c == v
+// (1 <= v <= N).
+template <int N, class F>
+__device__ inline void with_count(int v, F&& f) {
+  if constexpr (N == 1) {
+    f(std::integral_constant<int, 1>{});
+  } else {
+    if (v >= N) f(std::integral_constant<int, N>{});
+    else with_count<N - 1>(v, f);
+  }
+}
+
+// DEG: the operands are in coefficient form and node k contracts only its
+// first ceil(N_k / chunk) inner chunks (the Y rows beyond N_k are zero).
+template <class Op, int KC, int WN, int PD, bool DEG = false>
 __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
   using T = typename ElemOf<Op>::T;
   using Acc = typename Op::Acc;
@@ -495,6 +510,66 @@ __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
   // ring[0] holds the current step's Y fragments, ring[1..PD] the next PD
   // steps' (loads in flight)
   Frag ring[PD + 1][WN];
+  const int32_t* __restrict__ nkp = DEG ? m.nk : nullptr;
+  if (DEG && nkp != nullptr) {
+    // Per-node chunk counts: node k runs 3 * nck(k) steps; the ring still
+    // runs PD steps ahead, into the next node's first steps.
+    auto nck_of = [&](int k) { return (nkp[k] + Op::kChunk - 1) / Op::kChunk; };
+    auto loadY3 = [&](int k, int d, int c, Frag (&dst)[WN]) {
+      const char* y = Yw + (((int64_t)k * 3 + d) * prow * KC + c * Op::kChunk) * (int64_t)sizeof(T);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) dst[j] = *(gFrag*)(y + ylane + j * 16 * KC * (int)sizeof(T));
+    };
+    int nck_cur = nck_of(0);
+#pragma unroll
+    for (int a = 0; a < PD; ++a) loadY3(0, a / nck_cur, a % nck_cur, ring[a]);  // 3 * nck >= 3 > PD
+    for (int k = 0; k < nq; ++k) {
+      const int nck_next = k + 1 < nq ? nck_of(k + 1) : 1;
+      with_count<NCK>(nck_cur, [&](auto nc) {
+        constexpr int NC = decltype(nc)::value, NS = 3 * NC;
+        Acc H[WM][WN], G[WM][WN];
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+          const int d = st / NC, c = st % NC;
+          if (st + PD < NS) {
+            loadY3(k, (st + PD) / NC, (st + PD) % NC, ring[PD]);
+          } else if (k + 1 < nq) {
+            const int s2 = st + PD - NS;  // step of the next node, < PD
+            loadY3(k + 1, s2 / nck_next, s2 % nck_next, ring[PD]);
+          }
+#pragma unroll
+          for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int j = 0; j < WN; ++j) G[i][j] = Op::mma(fa[d][c][i], ring[0][j], c == 0 ? Op::zero() : G[i][j]);
+          if (c == NC - 1) {
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+              for (int j = 0; j < WN; ++j) {
+                if (d == 0) H[i][j] = G[i][j];
+                else if (d == 1) H[i][j] = H[i][j] * G[i][j];
+                else acc[i][j] += H[i][j] * G[i][j];
+              }
+          }
+#pragma unroll
+          for (int a = 0; a < PD; ++a)
+#pragma unroll
+            for (int j = 0; j < WN; ++j) ring[a][j] = ring[a + 1][j];
+        }
+      });
+      nck_cur = nck_next;
+      if (!kF64 && ((k + 1) % kGroup == 0 || k + 1 == nq)) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+            acc[i][j] = Op::zero();
+          }
+      }
+    }
+  } else {
 #pragma unroll
   for (int a = 0; a < PD; ++a)
     if (a / NSTEP < nq) loadY(a / NSTEP, a % NSTEP, ring[a]);
@@ -537,6 +612,7 @@ __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
         }
     }
   }
+  }
 
   const int64_t npair = m.npair;
   const int64_t ldb = m.ldb;
@@ -570,13 +646,13 @@ __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
 // WN = 2: four waves of 32 x 32; WN = 1: eight waves of 32 x 16 (half the
 // accumulator registers per wave, for the FP64 operands of the longer inner
 // lengths).  Two waves per SIMD either way.
-template <class Op, int KC, int WN>
+template <class Op, int KC, int WN, bool DEG>
 __global__ void __launch_bounds__(512 / WN, WN)
 assemble_as_kernel(AsmMol m) {
   int I, J;
   decode_tile(m.tiles, blockIdx.x, I, J);
   // FP32 MFMAs take half the cycles of FP64 ones: look two steps ahead
-  assemble_tile_as<Op, KC, WN, sizeof(typename ElemOf<Op>::T) == 8 ? 1 : 2>(m, I, J);
+  assemble_tile_as<Op, KC, WN, sizeof(typename ElemOf<Op>::T) == 8 ? 1 : 2, DEG>(m, I, J);
 }
 
 template <class Op, int WM, int WN>
@@ -619,11 +695,11 @@ assemble_queue_kernel(const AsmMol* __restrict__ mols, int nmol, int64_t nitems,
                    [](const AsmMol& m, int I, int J) { assemble_tile<Op, WM, WN>(m, I, J); });
 }
 
-template <class Op, int KC, int WN>
+template <class Op, int KC, int WN, bool DEG>
 __global__ void __launch_bounds__(512 / WN, WN)
 assemble_as_queue_kernel(const AsmMol* __restrict__ mols, int nmol, int64_t nitems, unsigned* counter) {
   drain_tile_queue(mols, nmol, nitems, counter, [](const AsmMol& m, int I, int J) {
-    assemble_tile_as<Op, KC, WN, sizeof(typename ElemOf<Op>::T) == 8 ? 1 : 2>(m, I, J);
+    assemble_tile_as<Op, KC, WN, sizeof(typename ElemOf<Op>::T) == 8 ? 1 : 2, DEG>(m, I, J);
   });
 }
 
@@ -646,7 +722,7 @@ __global__ void __launch_bounds__(kRowsPerTile)
 pack_batch_kernel(int prec, const PrepMol* __restrict__ mols, int n, int kc) {
   const PrepMol& m = mols[blockIdx.z];
   if ((int64_t)blockIdx.x * kRowsPerTile >= m.prow) return;
-  pack_body<NMAX>(prec, m.M, n, m.npair, m.prow, kc, static_cast<char*>(m.A), m.ex);
+  pack_body<NMAX>(prec, m.Mu ? m.Mu : m.M, n, m.npair, m.prow, kc, static_cast<char*>(m.A), m.ex);
 }
 
 template <int NT, int PREC>
@@ -662,7 +738,9 @@ __global__ void __launch_bounds__(256, 3)
 project_batch_kernel(const PrepMol* __restrict__ mols, int n, int nq, int kc) {
   const PrepMol& m = mols[blockIdx.z];
   if ((int64_t)blockIdx.x * kRowsPerTile >= m.prow) return;
-  project_mfma_body<NT, PREC>(m.M, n, m.npair, m.prow, nq, kc, m.tb.K, m.tb.w, m.ex, static_cast<char*>(m.Y));
+  // coefficient form (per-node degrees): moments against T_j, kept coefficients
+  project_mfma_body<NT, PREC>(m.Mu ? m.Mu : m.M, n, m.npair, m.prow, nq, kc, m.Mu ? m.tb.C : m.tb.K, m.tb.w, m.ex,
+                              static_cast<char*>(m.Y));
 }
 
 size_t project_lds(int prec, int n) {
@@ -792,28 +870,36 @@ constexpr int as_wn() {
 
 // grid: tiles (one work group each), or, for the queue form, work groups
 // of four waves' worth of threads (halved for the eight-wave form).
-template <class Op, int KC>
+template <class Op, int KC, bool DEG>
 void launch_as_kc(const dim3& grid, const AsmMol* mols, int nmol, int64_t nitems, unsigned* counter,
                   const AsmMol& m, bool queue, hipStream_t s) {
   constexpr int WN = as_wn<Op, KC>();
   const dim3 block(512 / WN);
   if (queue) {
     const dim3 g(WN == 1 ? (grid.x + 1) / 2 : grid.x);
-    hipLaunchKernelGGL((assemble_as_queue_kernel<Op, KC, WN>), g, block, 0, s, mols, nmol, nitems, counter);
+    hipLaunchKernelGGL((assemble_as_queue_kernel<Op, KC, WN, DEG>), g, block, 0, s, mols, nmol, nitems, counter);
   } else {
-    hipLaunchKernelGGL((assemble_as_kernel<Op, KC, WN>), grid, block, 0, s, m);
+    hipLaunchKernelGGL((assemble_as_kernel<Op, KC, WN, DEG>), grid, block, 0, s, m);
   }
 }
 
+template <class Op, int KC>
+void launch_as_kc(bool deg, const dim3& grid, const AsmMol* mols, int nmol, int64_t nitems, unsigned* counter,
+                  const AsmMol& m, bool queue, hipStream_t s) {
+  if (deg) launch_as_kc<Op, KC, true>(grid, mols, nmol, nitems, counter, m, queue, s);
+  else launch_as_kc<Op, KC, false>(grid, mols, nmol, nitems, counter, m, queue, s);
+}
+
+// deg: molecules may carry per-node degrees (AsmMol::nk).
 template <class Op>
-bool launch_as(int kc, const dim3& grid, const AsmMol* mols, int nmol, int64_t nitems, unsigned* counter,
+bool launch_as(int kc, bool deg, const dim3& grid, const AsmMol* mols, int nmol, int64_t nitems, unsigned* counter,
                const AsmMol& m, bool queue, hipStream_t s) {
   switch (kc) {
-    case 8: launch_as_kc<Op, 8>(grid, mols, nmol, nitems, counter, m, queue, s); return true;
-    case 16: launch_as_kc<Op, 16>(grid, mols, nmol, nitems, counter, m, queue, s); return true;
-    case 24: launch_as_kc<Op, 24>(grid, mols, nmol, nitems, counter, m, queue, s); return true;
-    case 32: launch_as_kc<Op, 32>(grid, mols, nmol, nitems, counter, m, queue, s); return true;
-    case 40: launch_as_kc<Op, 40>(grid, mols, nmol, nitems, counter, m, queue, s); return true;
+    case 8: launch_as_kc<Op, 8>(deg, grid, mols, nmol, nitems, counter, m, queue, s); return true;
+    case 16: launch_as_kc<Op, 16>(deg, grid, mols, nmol, nitems, counter, m, queue, s); return true;
+    case 24: launch_as_kc<Op, 24>(deg, grid, mols, nmol, nitems, counter, m, queue, s); return true;
+    case 32: launch_as_kc<Op, 32>(deg, grid, mols, nmol, nitems, counter, m, queue, s); return true;
+    case 40: launch_as_kc<Op, 40>(deg, grid, mols, nmol, nitems, counter, m, queue, s); return true;
     default: return false;
   }
 }
@@ -822,8 +908,9 @@ hipError_t launch_assemble(int prec, const AsmMol& m, hipStream_t s) {
   const int64_t ntiles = (int64_t)m.tiles * (m.tiles + 1) / 2;
   const dim3 grid((unsigned)ntiles), block(256);
   // inner lengths up to 40: A-stationary tiles (the A operand fits the registers)
-  if (prec == kFP64 && launch_as<OpF64>(m.kc, grid, nullptr, 0, 0, nullptr, m, false, s)) return hipGetLastError();
-  if (prec == kFP32 && launch_as<OpF32>(m.kc, grid, nullptr, 0, 0, nullptr, m, false, s)) return hipGetLastError();
+  const bool deg = m.nk != nullptr;
+  if (prec == kFP64 && launch_as<OpF64>(m.kc, deg, grid, nullptr, 0, 0, nullptr, m, false, s)) return hipGetLastError();
+  if (prec == kFP32 && launch_as<OpF32>(m.kc, deg, grid, nullptr, 0, 0, nullptr, m, false, s)) return hipGetLastError();
   switch (prec) {
     case kFP64: hipLaunchKernelGGL((assemble_kernel<OpF64, 2, 2>), grid, block, 0, s, m); break;
     case kFP32: hipLaunchKernelGGL((assemble_kernel<OpF32, 2, 2>), grid, block, 0, s, m); break;
@@ -844,13 +931,13 @@ int assemble_queue_blocks(int /*prec*/, int device) {
   return cus * 4;
 }
 
-hipError_t launch_assemble_queue(int prec, int kc, const AsmMol* mols_dev, int nmol, int64_t nitems,
+hipError_t launch_assemble_queue(int prec, int kc, bool deg, const AsmMol* mols_dev, int nmol, int64_t nitems,
                                  unsigned* counter, int nblocks, hipStream_t s) {
   const dim3 grid((unsigned)nblocks), block(256);
   const AsmMol none{};
-  if (prec == kFP64 && launch_as<OpF64>(kc, grid, mols_dev, nmol, nitems, counter, none, true, s))
+  if (prec == kFP64 && launch_as<OpF64>(kc, deg, grid, mols_dev, nmol, nitems, counter, none, true, s))
     return hipGetLastError();
-  if (prec == kFP32 && launch_as<OpF32>(kc, grid, mols_dev, nmol, nitems, counter, none, true, s))
+  if (prec == kFP32 && launch_as<OpF32>(kc, deg, grid, mols_dev, nmol, nitems, counter, none, true, s))
     return hipGetLastError();
   switch (prec) {
     case kFP64: hipLaunchKernelGGL((assemble_queue_kernel<OpF64, 2, 2>), grid, block, 0, s, mols_dev, nmol, nitems, counter); break;

@@ -126,7 +126,69 @@ moments_batch_kernel(const PrepMol* __restrict__ mols, int n) {
   moments_body<NMAX>(m.basis, n, m.L, m.tb, m.M, m.npair);
 }
 
+// Coefficient moments mu_d[j][p] = sum_a T_j(xi_a / L) M_d[a][p], the
+// moments against T_j (j < n) that the per-node degree form contracts (eq.
+// tensors with the nested moments of section 3.2): T_j = sum_a T_j(xi_a) l_a
+// for every j < n.  One thread per (pair, direction); the n x n table of
+// T_j(xi_a/L) in LDS.
+constexpr int kCoefThreads = 256;
+
+template <int NMAX>
+__device__ inline void coef_moments_body(const double* __restrict__ M, int n, int64_t npair, int kind,
+                                         double* __restrict__ mu) {
+  __shared__ double V[NMAX * NMAX];
+  for (int e = threadIdx.x; e < n * n; e += kCoefThreads) V[e] = cheb_at_node(kind, n, e / n, e % n);
+  __syncthreads();
+  const int d = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * kCoefThreads + threadIdx.x;
+  if (p >= npair) return;
+  double m[NMAX];
+#pragma unroll
+  for (int a = 0; a < NMAX; ++a) m[a] = a < n ? M[((int64_t)d * n + a) * npair + p] : 0.0;
+  for (int j = 0; j < n; ++j) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < NMAX; ++a)
+      if (a < n) s += V[a * n + j] * m[a];
+    mu[((int64_t)d * n + j) * npair + p] = s;
+  }
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(kCoefThreads)
+coef_moments_kernel(const double* __restrict__ M, int n, int64_t npair, int kind, double* __restrict__ mu) {
+  coef_moments_body<NMAX>(M, n, npair, kind, mu);
+}
+
+// blockIdx.z = molecule; molecules without coefficient moments are skipped
+template <int NMAX>
+__global__ void __launch_bounds__(kCoefThreads)
+coef_moments_batch_kernel(const PrepMol* __restrict__ mols, int n, int kind) {
+  const PrepMol& m = mols[blockIdx.z];
+  if (m.Mu == nullptr || (int64_t)blockIdx.x * kCoefThreads >= m.npair) return;
+  coef_moments_body<NMAX>(m.M, n, m.npair, kind, m.Mu);
+}
+
 }  // namespace
+
+hipError_t launch_coef_moments(const double* M, int n, int64_t npair, int kind, double* mu, hipStream_t s) {
+  const dim3 grid((unsigned)((npair + kCoefThreads - 1) / kCoefThreads), 3);
+  if (n <= 16) hipLaunchKernelGGL(coef_moments_kernel<16>, grid, dim3(kCoefThreads), 0, s, M, n, npair, kind, mu);
+  else if (n <= 32) hipLaunchKernelGGL(coef_moments_kernel<32>, grid, dim3(kCoefThreads), 0, s, M, n, npair, kind, mu);
+  else if (n <= 48) hipLaunchKernelGGL(coef_moments_kernel<48>, grid, dim3(kCoefThreads), 0, s, M, n, npair, kind, mu);
+  else hipLaunchKernelGGL(coef_moments_kernel<64>, grid, dim3(kCoefThreads), 0, s, M, n, npair, kind, mu);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_moments_batch(const PrepMol* mols, int nmol, int64_t max_npair, int n, int kind,
+                                     hipStream_t s) {
+  const dim3 grid((unsigned)((max_npair + kCoefThreads - 1) / kCoefThreads), 3, nmol);
+  if (n <= 16) hipLaunchKernelGGL(coef_moments_batch_kernel<16>, grid, dim3(kCoefThreads), 0, s, mols, n, kind);
+  else if (n <= 32) hipLaunchKernelGGL(coef_moments_batch_kernel<32>, grid, dim3(kCoefThreads), 0, s, mols, n, kind);
+  else if (n <= 48) hipLaunchKernelGGL(coef_moments_batch_kernel<48>, grid, dim3(kCoefThreads), 0, s, mols, n, kind);
+  else hipLaunchKernelGGL(coef_moments_batch_kernel<64>, grid, dim3(kCoefThreads), 0, s, mols, n, kind);
+  return hipGetLastError();
+}
 
 hipError_t launch_moments_batch(const PrepMol* mols, int nmol, int64_t max_npair, int n, hipStream_t s) {
   const unsigned blocks = (unsigned)((3 * max_npair + 127) / 128);

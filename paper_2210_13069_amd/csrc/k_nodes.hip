@@ -13,6 +13,7 @@
 //   coefficients of each node's factor, the smallest degree whose dropped
 //   coefficients sum to at most a tolerance, and the truncated K tables.
 #include "tai_internal.h"
+#include "tai_device.h"
 
 #include <cmath>
 
@@ -125,16 +126,6 @@ ktables_kernel(int nq, int n, int kind, NodeTables tb) {
 __global__ void __launch_bounds__(256)
 ktables_batch_kernel(const PrepMol* __restrict__ mols, int nq, int n, int kind) {
   ktables_body(nq, n, kind, mols[blockIdx.y].tb);
-}
-
-// T_j(xi_a / L), with the angle reduced exactly in integers: Lobatto
-// xi_a = L cos(pi a / (n-1)), first kind xi_a = L cos((2a+1) pi / (2n)).
-__device__ inline double cheb_at_node(int kind, int n, int a, int j) {
-  if (kind == 0) {
-    const int N = n - 1;
-    return cos(M_PI * (double)((int64_t)a * j % (2 * N)) / N);
-  }
-  return cos(M_PI * (double)((int64_t)j * (2 * a + 1) % (4 * n)) / (2.0 * n));
 }
 
 constexpr int kDegThreads = 256;

@@ -33,6 +33,7 @@ struct tai_ctx {
   Buf host_basis;         // pinned staging of a basis
   hipEvent_t host_basis_done = nullptr;
   Buf opA, opEx, opY;     // assembly operands
+  Buf opMu;               // coefficient moments (per-node degrees)
   Buf asm_tab, asm_counter;  // 16-bit kernel: device molecule table + items, queue counter
   Buf asm_host;           // pinned staging of the table
   hipEvent_t asm_host_done = nullptr;
@@ -47,7 +48,7 @@ struct tai_ctx {
   uint64_t size_key = 0;  // size class of the call in progress
   Buf jwork;              // apply_J intermediates
   // batched path
-  Buf b_nodes, b_basis, b_opA, b_opEx, b_opY, b_mols, b_counter;
+  Buf b_nodes, b_basis, b_opA, b_opEx, b_opY, b_opMu, b_mols, b_counter;
   Buf b_host;             // pinned staging of all bases of a batch
   hipEvent_t b_host_done = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -460,8 +461,8 @@ int tai_destroy(tai_ctx* c) {
   if (c->device >= 0) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->asm_tab, &c->asm_counter, &c->jwork, &c->b_nodes, &c->b_basis,
-                   &c->b_opA, &c->b_opEx, &c->b_opY, &c->b_mols, &c->b_counter})
+    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->asm_tab, &c->asm_counter, &c->jwork,
+                   &c->b_nodes, &c->b_basis, &c->b_opA, &c->b_opEx, &c->b_opY, &c->b_opMu, &c->b_mols, &c->b_counter})
       free_buf(c, *b);
     if (c->host_basis.p) hipHostFree(c->host_basis.p);
     if (c->b_host.p) hipHostFree(c->b_host.p);
@@ -584,11 +585,19 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
                          hipStream_t s) {
   int r;
   const int prec = p->prec, n = p->n, nq = p->nq;
+  // per-node degrees in FP64 / FP32: operands in coefficient form (moments
+  // against T_j and the kept coefficients), each node contracting its
+  // leading N_k indices.  The split 16-bit arithmetics keep the node form
+  // with the truncated K tables: in coefficient form the moments of narrow
+  // pairs cancel across indices and the slices lose about a factor of three
+  // in accuracy.
+  const bool deg = p->degree_tol > 0 && !tai::is_split16(prec);
   const int prow = prow_of(c, prec, n, nq, npair);
   if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
   if ((r = ensure(c, c->opA, opA_bytes(prec, n, prow)))) return r;
   if ((r = ensure(c, c->opEx, opEx_bytes(prow)))) return r;
   if ((r = ensure(c, c->opY, opY_bytes(prec, n, nq, prow)))) return r;
+  if (deg && (r = ensure(c, c->opMu, sizeof(double) * 3 * (size_t)n * npair))) return r;
   NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
   hipError_t e;
   {
@@ -597,14 +606,26 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
   }
   if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
   int32_t* ex = static_cast<int32_t*>(c->opEx.p);
+  const double* Mop = M;
+  NodeTables tbp = tb;
+  if (deg) {
+    double* mu = static_cast<double*>(c->opMu.p);
+    {
+      Timed tm(c, kStPack, s);
+      e = tai::launch_coef_moments(M, n, npair, p->nodes, mu, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "coefficient moments kernel");
+    Mop = mu;
+    tbp.K = tb.C;
+  }
   {
     Timed tm(c, kStPack, s);
-    e = tai::launch_pack(prec, M, n, npair, prow, c->opA.p, ex, s);
+    e = tai::launch_pack(prec, Mop, n, npair, prow, c->opA.p, ex, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "pack kernel");
   {
     Timed tm(c, kStProject, s);
-    e = tai::launch_project(prec, M, n, npair, prow, nq, tb, ex, c->opY.p, s);
+    e = tai::launch_project(prec, Mop, n, npair, prow, nq, tbp, ex, c->opY.p, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "project kernel");
   tai::AsmMol m;
@@ -619,6 +640,7 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
   m.kc = tai::operand_kc(prec, n);
   m.tiles = prow / tai::assemble_tile(prec);
   m.tile0 = 0;
+  m.nk = deg ? tb.nk : nullptr;
   if (use16(c, prec, n, nq)) {
     Items16 items;
     const tai::Asm16Shape sh = shape16(c, prec, n, nq);
@@ -708,11 +730,19 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   int r;
   const int prec = mols[0].params.prec, n = mols[0].params.n, nq = mols[0].params.nq;
   const int tile = tai::assemble_tile(prec);
+  // molecules with per-node degrees take their operands in coefficient form
+  // in FP64 / FP32 (the split arithmetics keep the node form, see assemble_impl)
+  auto coef_form = [&](int i) { return mols[i].params.degree_tol > 0 && !tai::is_split16(prec); };
+  bool any_degree = false, any_tol = false;
+  for (int i = 0; i < nmol; ++i) {
+    any_degree = any_degree || coef_form(i);
+    any_tol = any_tol || mols[i].params.degree_tol > 0;
+  }
 
   // layout of the batch workspace
-  std::vector<size_t> off_nodes(nmol), off_basis(nmol), off_A(nmol), off_Ex(nmol), off_Y(nmol);
+  std::vector<size_t> off_nodes(nmol), off_basis(nmol), off_A(nmol), off_Ex(nmol), off_Y(nmol), off_Mu(nmol);
   std::vector<int> prow(nmol);
-  size_t sz_nodes = 0, sz_basis = 0, sz_A = 0, sz_Ex = 0, sz_Y = 0;
+  size_t sz_nodes = 0, sz_basis = 0, sz_A = 0, sz_Ex = 0, sz_Y = 0, sz_Mu = 0;
   int64_t nitems = 0;
   std::vector<tai::AsmMol> am(nmol);
   for (int i = 0; i < nmol; ++i) {
@@ -723,12 +753,15 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     off_A[i] = sz_A; sz_A += opA_bytes(prec, n, prow[i]);
     off_Ex[i] = sz_Ex; sz_Ex += opEx_bytes(prow[i]);
     off_Y[i] = sz_Y; sz_Y += opY_bytes(prec, n, nq, prow[i]);
+    off_Mu[i] = sz_Mu;
+    if (coef_form(i)) sz_Mu += align256(sizeof(double) * 3 * (size_t)n * np);
   }
   if ((r = ensure(c, c->b_nodes, sz_nodes))) return r;
   if ((r = ensure(c, c->b_basis, sz_basis))) return r;
   if ((r = ensure(c, c->b_opA, sz_A))) return r;
   if ((r = ensure(c, c->b_opEx, sz_Ex))) return r;
   if ((r = ensure(c, c->b_opY, sz_Y))) return r;
+  if (sz_Mu > 0 && (r = ensure(c, c->b_opMu, sz_Mu))) return r;
   if ((r = ensure(c, c->b_counter, 256))) return r;
   for (int i = 0; i < nmol; ++i) {
     tai::AsmMol& m = am[i];
@@ -744,6 +777,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     m.tiles = prow[i] / tile;
     m.tile0 = nitems;
     nitems += (int64_t)m.tiles * (m.tiles + 1) / 2;
+    m.nk = nullptr;  // set below from the molecule's node tables
   }
   // the 16-bit kernel drains (molecule, row panel, column range) items,
   // largest molecules first so the tail of the queue holds small items
@@ -762,7 +796,6 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   const size_t tab_bytes = off_items + (split16 ? items16.bytes() : 0);
   if ((r = ensure(c, c->b_mols, tab_bytes))) return r;
   std::vector<tai::PrepMol> prep(nmol);
-  bool any_degree = false;
   int64_t max_npair = 0;
   int max_prow = 0;
   for (int i = 0; i < nmol; ++i) {
@@ -770,8 +803,9 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     q.omega = mols[i].params.omega;
     q.L = mols[i].params.L;
     q.degree_tol = mols[i].params.degree_tol;
-    any_degree = any_degree || mols[i].params.degree_tol > 0;
     q.tb = tai::carve_node_tables(static_cast<char*>(c->b_nodes.p) + off_nodes[i], nq, n);
+    q.Mu = coef_form(i) ? reinterpret_cast<double*>(static_cast<char*>(c->b_opMu.p) + off_Mu[i]) : nullptr;
+    am[i].nk = q.Mu ? q.tb.nk : nullptr;
     q.basis = dev_basis_view(&mols[i].basis, static_cast<char*>(c->b_basis.p) + off_basis[i]);
     q.M = mols[i].M;
     q.npair = am[i].npair;
@@ -800,8 +834,10 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   auto enqueue = [&](hipStream_t st) -> hipError_t {
     // preparation of every molecule, one launch per stage
     const auto* prep_dev = reinterpret_cast<const tai::PrepMol*>(static_cast<char*>(c->b_mols.p) + off_prep);
-    hipError_t err = tai::launch_nodes_batch(prep_dev, nmol, nq, n, mols[0].params.nodes, any_degree, st);
+    hipError_t err = tai::launch_nodes_batch(prep_dev, nmol, nq, n, mols[0].params.nodes, any_tol, st);
     if (err == hipSuccess) err = tai::launch_moments_batch(prep_dev, nmol, max_npair, n, st);
+    if (err == hipSuccess && any_degree)
+      err = tai::launch_coef_moments_batch(prep_dev, nmol, max_npair, n, mols[0].params.nodes, st);
     if (err == hipSuccess) err = tai::launch_pack_batch(prec, prep_dev, nmol, max_prow, n, st);
     if (err == hipSuccess) err = tai::launch_project_batch(prec, prep_dev, nmol, max_prow, n, nq, st);
     if (err != hipSuccess) return err;
@@ -820,7 +856,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     }
     int blocks = tai::assemble_queue_blocks(prec, c->device);
     if (blocks > nitems) blocks = (int)nitems;
-    return tai::launch_assemble_queue(prec, am[0].kc, mols_dev, nmol, nitems, counter, blocks, st);
+    return tai::launch_assemble_queue(prec, am[0].kc, any_degree, mols_dev, nmol, nitems, counter, blocks, st);
   };
 
   const bool use_graph = allow_graph && s != nullptr && !std::getenv("TAI_NO_GRAPH");
@@ -848,7 +884,8 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     put(&mols[i].B, sizeof(void*));
     put(&mols[i].ldb, sizeof(int64_t));
   }
-  void* bases[] = {c->b_nodes.p, c->b_basis.p, c->b_opA.p, c->b_opEx.p, c->b_opY.p, c->b_mols.p, c->b_counter.p};
+  void* bases[] = {c->b_nodes.p, c->b_basis.p, c->b_opA.p, c->b_opEx.p, c->b_opY.p, c->b_opMu.p, c->b_mols.p,
+                   c->b_counter.p};
   put(bases, sizeof bases);
   put(&sh16.id, sizeof sh16.id);
   if (!c->graph || key != c->graph_key) {

@@ -22,4 +22,15 @@ __device__ inline void decode_pair(int64_t nb, int64_t p, int& mu, int& nu) {
   nu = (int)(m + (p - pair_row_start(nb, m)));
 }
 
+// T_j(xi_a / L) on the Chebyshev grid, the angle reduced exactly in
+// integers: Lobatto (kind 0) xi_a = L cos(pi a / (n-1)), first kind
+// xi_a = L cos((2a+1) pi / (2n)).
+__device__ inline double cheb_at_node(int kind, int n, int a, int j) {
+  if (kind == 0) {
+    const int N = n - 1;
+    return cos(M_PI * (double)((int64_t)a * j % (2 * N)) / N);
+  }
+  return cos(M_PI * (double)((int64_t)j * (2 * a + 1) % (4 * n)) / (2.0 * n));
+}
+
 }  // namespace tai

@@ -52,6 +52,9 @@ struct DevBasis {
 
 hipError_t launch_moments(const DevBasis& b, int n, double L, const NodeTables& tb,
                           double* M, hipStream_t s);
+// Coefficient moments mu_d[j][p] = sum_a T_j(xi_a / L) M_d[a][p] (the
+// moments against T_j, j < n), FP64.
+hipError_t launch_coef_moments(const double* M, int n, int64_t npair, int kind, double* mu, hipStream_t s);
 
 // ---- assembly -------------------------------------------------------------
 
@@ -97,6 +100,9 @@ struct AsmMol {
   int32_t kc;
   int32_t tiles;         // tiles per side
   int64_t tile0;         // first linear work item of this molecule
+  // per-node degrees N_k [nq] when the operands are in coefficient form
+  // (FP64 and FP32 only; nullptr: every node runs the full inner length)
+  const int32_t* nk;
 };
 
 // Per-molecule arguments of the preparation stages of a batch (nodes,
@@ -107,6 +113,7 @@ struct PrepMol {
   NodeTables tb;
   DevBasis basis;
   double* M;
+  double* Mu;            // coefficient moments (per-node degrees, FP64 and FP32), else nullptr
   int64_t npair;
   int32_t prow;
   void* A;
@@ -118,6 +125,9 @@ struct PrepMol {
 hipError_t launch_nodes_batch(const PrepMol* mols, int nmol, int nq, int n, int kind, bool any_degree,
                               hipStream_t s);
 hipError_t launch_moments_batch(const PrepMol* mols, int nmol, int64_t max_npair, int n, hipStream_t s);
+// launch_coef_moments for the molecules with PrepMol::Mu set.
+hipError_t launch_coef_moments_batch(const PrepMol* mols, int nmol, int64_t max_npair, int n, int kind,
+                                     hipStream_t s);
 hipError_t launch_pack_batch(int prec, const PrepMol* mols, int nmol, int max_prow, int n, hipStream_t s);
 hipError_t launch_project_batch(int prec, const PrepMol* mols, int nmol, int max_prow, int n, int nq,
                                 hipStream_t s);
@@ -131,7 +141,7 @@ hipError_t launch_assemble(int prec, const AsmMol& m, hipStream_t s);
 // Persistent launch over a device work list of molecules; `counter` is a
 // device int zeroed by launch_reset_counter before each launch (which
 // zeroes the kAsm16Queues counters starting there).
-hipError_t launch_assemble_queue(int prec, int kc, const AsmMol* mols_dev, int nmol, int64_t nitems,
+hipError_t launch_assemble_queue(int prec, int kc, bool deg, const AsmMol* mols_dev, int nmol, int64_t nitems,
                                  unsigned* counter, int nblocks, hipStream_t s);
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t s);
 int assemble_queue_blocks(int prec, int device);

@@ -135,3 +135,23 @@ def test_batched_with_mixed_degrees(tai, prec):
     Br = T.B_full(Mr, Kt, w)
     tol = 1e-10 if prec == 0 else LOWP_TOL[prec]
     assert _normwise(outs[0].cpu().numpy().astype(np.float64), Br) <= tol
+
+
+@pytest.mark.parametrize("n,nq", [(24, 12), (29, 7), (41, 12), (48, 9), (64, 8), (16, 5)])
+def test_assemble_with_degrees_inner_lengths(tai, n, nq):
+    """Per-node degrees at inner lengths with partial and whole chunks: FP64
+    and FP32 contract N_k coefficient indices per node in the register-A
+    tile kernel (inner lengths 16..40) or all of them in the generic one
+    (48, 64); the split arithmetics take the truncated node-form tables with
+    every ring shape (odd node counts included); npair = 465 is ragged."""
+    b = I.small_random(52, natoms=3, shells=("s", "p", "d"), box=2.5, alpha_lo=0.2, alpha_hi=8.0)
+    P = I.Params(omega=0.6, nq=nq, n=n, L=7.0, degree_tol=1e-9)
+    N, _, Kt, w = _oracle_tables(P)
+    assert N.min() < n
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
+    Br = T.B_full(Mr, Kt, w)
+    Mg = tai.moments(b, P)
+    for prec in (0, 1, 2, 3, 4):
+        Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+        tol = 1e-10 if prec == 0 else LOWP_TOL[prec]
+        assert _normwise(Bg, Br) <= tol, (n, nq, prec, _normwise(Bg, Br))
