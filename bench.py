@@ -8,7 +8,8 @@ quadrature tables and moments, operand preparation, and the fused assembly of
 the full 80200 x 80200 B, in the headline arithmetic (split FP16, 3 products).
 `value` = stored B entries per second of that step, inputs resident on the
 device.  The same line reports the FP64 / FP32 / BF16 forms of the same step,
-the batched persistent assembly of 64 molecules (graph replay vs one launch
+FP64 and FP32 with a degree per quadrature node (the paper's N_i, each
+factor within 1e-8 on the box), the batched persistent assembly of 64 molecules (graph replay vs one launch
 sequence per molecule), the J-build through the grid tensor (Nb = 1000), the
 error of every form against the FP64 oracle on sampled entries, the roofline
 of the dominant kernel, and the oracle timed on the host cores.
@@ -16,6 +17,7 @@ of the dominant kernel, and the oracle timed on the host cores.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-headline] [--no-cpu]
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -30,6 +32,9 @@ METRIC = "long-range TEI entries/s: split-BF16/FP32 vs FP64 GPU, at stated rel. 
 # MI355X published dense peaks, TFLOP/s
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0, "f16x3": 2500.0}
 HBM_PEAK_GBS = 8000.0
+# tolerance of the per-node degree leg: each node's factor moves by at most
+# this much on the box (below the degree-40 interpolation error at omega 0.3)
+DEGREE_TOL = 1e-8
 
 
 def log(msg):
@@ -40,6 +45,12 @@ def algorithmic_flops(npair, nq, n):
     """Unique entries x nodes x (three length-n dot products + two Hadamard
     products + the weighted accumulation) = npair(npair+1)/2 * nq * (6n + 4)."""
     return npair * (npair + 1) / 2 * nq * (6 * n + 4)
+
+
+def algorithmic_flops_degrees(npair, nk):
+    """As algorithmic_flops with node k contracting N_k indices:
+    npair(npair+1)/2 * sum_k (6 N_k + 4)."""
+    return npair * (npair + 1) / 2 * float(sum(6 * int(x) + 4 for x in nk))
 
 
 def traffic_from_profiles(kernel_src_sha, workload):
@@ -120,16 +131,16 @@ def main():
     spt = torch.as_tensor(sp, device=dev)
     sqt = torch.as_tensor(sq, device=dev)
 
-    def run_steps(prec, Bbuf, steps, warmup):
-        params = tai.make_params(P, prec)
+    def run_steps(prec, Bbuf, steps, warmup, Pw=P):
+        params = tai.make_params(Pw, prec)
         for _ in range(warmup):
-            ctx.moments(ba, P, M)
+            ctx.moments(ba, Pw, M)
             ctx.assemble_B(M, npair, params, Bbuf)
         torch.cuda.synchronize()
         ctx.profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            ctx.moments(ba, P, M)
+            ctx.moments(ba, Pw, M)
             ctx.assemble_B(M, npair, params, Bbuf)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -158,6 +169,7 @@ def main():
     paths = {args.prec: {"ms_per_step": round(ms_head, 3), "entries_per_s": value,
                          "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st_head.items()}}}
     samples = {args.prec: samp_head}
+    degrees = None
 
     if not args.only_headline:
         B64 = torch.empty((npair, npair), dtype=torch.float64, device=dev)
@@ -171,11 +183,30 @@ def main():
             paths[name] = {"ms_per_step": round(ms, 3), "entries_per_s": entries / (ms / 1e3),
                            "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()}}
             samples[name] = samp
+        # per-node degrees N_k (the paper's N_i): FP64 and FP32 contract only
+        # each node's leading coefficient indices
+        Pd = dataclasses.replace(P, degree_tol=DEGREE_TOL)
+        nk = tai.degrees(Pd)[0].cpu().numpy()
+        deg_flops = algorithmic_flops_degrees(npair, nk)
+        degrees = {"degree_tol": DEGREE_TOL, "N_k": nk.tolist(), "flops_per_launch": deg_flops}
+        for name in ("fp64", "fp32"):
+            prec = tai.PREC_BY_NAME[name]
+            steps = max(1, K // 2)
+            log(f"per-node degrees {name}: steps={steps}")
+            ms, st, samp = run_steps(prec, B64 if prec == tai.FP64 else B32, steps, 1, Pd)
+            a_ms = st["assemble"][0] / max(1, st["assemble"][1])
+            degrees[name] = {"ms_per_step": round(ms, 3), "entries_per_s": entries / (ms / 1e3),
+                             "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()},
+                             "assemble_tflops_algorithmic": round(deg_flops / (a_ms / 1e3) / 1e12, 2)}
+            samples[name + "_degrees"] = samp
         del B64
         torch.cuda.empty_cache()
         if "fp64" in paths:
             for name in paths:
                 paths[name]["speedup_vs_fp64"] = round(paths[name]["entries_per_s"] / paths["fp64"]["entries_per_s"], 3)
+        for name in ("fp64", "fp32"):
+            if name in paths and name in degrees:
+                degrees[name]["speedup_vs_fixed_degree"] = round(paths[name]["ms_per_step"] / degrees[name]["ms_per_step"], 3)
         # the assembly kernel of every path against its own arithmetic's peak
         for name, pv in paths.items():
             tf = flops / (pv["stage_ms"]["assemble"] / 1e3) / 1e12
@@ -317,11 +348,17 @@ def main():
         scale = float(np.max(np.abs(dref)))
         rel_error = {}
         big = np.abs(ref) >= 1e-8 * scale
+        ref_deg = None
+        if degrees is not None:
+            Ktr = T.truncated_tables(t, xi, P.L, DEGREE_TOL)[2]
+            ref_deg = T.B_entries(Mr, Ktr, w, np.searchsorted(allp, sp), np.searchsorted(allp, sq))
+            degrees["oracle_change_vs_fixed_degree"] = float(np.max(np.abs(ref_deg - ref)) / scale)
         for name, sv in samples.items():
-            err = np.abs(sv - ref)
+            r = ref_deg if name.endswith("_degrees") else ref
+            err = np.abs(sv - r)
             rel_error[name] = {"normwise": float(np.max(err) / scale),
-                               "elementwise_mean": float(np.mean(err[big] / np.abs(ref[big]))),
-                               "elementwise_max": float(np.max(err[big] / np.abs(ref[big])))}
+                               "elementwise_mean": float(np.mean(err[big] / np.abs(r[big]))),
+                               "elementwise_max": float(np.max(err[big] / np.abs(r[big])))}
 
     out = {
         "metric": METRIC,
@@ -344,6 +381,7 @@ def main():
         "cpu_baseline": cpu,
         "rel_error_vs_oracle": rel_error,
         "paths": paths,
+        "degrees": degrees,
         "batched": batched,
         "japply": japply,
     }
