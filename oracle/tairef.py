@@ -282,6 +282,23 @@ def pair_index(nb, mu, nu):
     return mu * nb - (mu * (mu - 1)) // 2 + (nu - mu)
 
 
+def screened_pairs(center, alpha, tau):
+    """Pair indices p(mu, nu), mu <= nu, ascending, that survive screening
+    (section 5, compression by screening): a pair is dropped when its
+    Gaussian product prefactor exp(-ab/(a+b) |A - B|^2) is at most tau.
+    tau <= 0 keeps every pair; diagonal pairs (prefactor 1) are always kept
+    for tau < 1."""
+    center = np.asarray(center, dtype=np.float64).reshape(-1, 3)
+    alpha = np.asarray(alpha, dtype=np.float64).reshape(-1)
+    mu, nu = pair_list(len(alpha))
+    if tau <= 0:
+        return np.arange(len(mu), dtype=np.int64)
+    a, b = alpha[mu], alpha[nu]
+    r2 = np.sum((center[mu] - center[nu]) ** 2, axis=1)
+    pref = np.exp(-a * b / (a + b) * r2)
+    return np.nonzero(pref > tau)[0].astype(np.int64)
+
+
 def basis_scale(alpha, lxyz, coef):
     """Per-function scale s_mu and per-direction unit-norm factors.
 
@@ -466,6 +483,26 @@ def J_grid(M, K, w, D):
         Phi += w[k] * T
     Phi *= 2.0 / SQRT_PI
     Jp = np.einsum("ap,bp,cp,abc->p", M[0], M[1], M[2], Phi, optimize=True)
+    return unpack_pairs(Jp, nb)
+
+
+def J_grid_pairs(M, K, w, D, pairs):
+    """J through the grid with the pair sums restricted to the kept pairs of
+    screening (M holds their moments, columns in the order of `pairs`);
+    entries of dropped pairs are zero."""
+    nb = D.shape[0]
+    Dt = density_pairs(D)[pairs]
+    rho = np.einsum("q,aq,bq,cq->abc", Dt, M[0], M[1], M[2], optimize=True)
+    Phi = np.zeros_like(rho)
+    for k in range(K.shape[0]):
+        Kk = K[k]
+        T = np.einsum("ia,abc->ibc", Kk, rho, optimize=True)
+        T = np.einsum("jb,ibc->ijc", Kk, T, optimize=True)
+        T = np.einsum("kc,ijc->ijk", Kk, T, optimize=True)
+        Phi += w[k] * T
+    Phi *= 2.0 / SQRT_PI
+    Jp = np.zeros(nb * (nb + 1) // 2)
+    Jp[pairs] = np.einsum("ap,bp,cp,abc->p", M[0], M[1], M[2], Phi, optimize=True)
     return unpack_pairs(Jp, nb)
 
 
