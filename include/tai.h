@@ -216,6 +216,34 @@ int tai_assemble_B_batched(tai_ctx* ctx, int32_t nmol, const tai_mol* mols, void
 int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* params,
                 const double* D, double* J, void* stream);
 
+/* ---- screening (section 5, compression by screening) --------------------- */
+
+/* Pairs that survive screening: pair p(mu,nu), mu <= nu, is dropped when its
+   Gaussian product prefactor exp(-a_mu a_nu/(a_mu + a_nu) |A_mu - A_nu|^2)
+   is at most tau (every pair is kept when tau <= 0; 0 < tau < 1 keeps at
+   least the diagonal pairs).  pairs: DEVICE int32 with room for npair
+   entries; the kept pair indices are written in ascending order.  nkept:
+   HOST, set to their count.  The call waits for `stream` to read the count.
+   tau must be finite and < 1. */
+int tai_screen_pairs(tai_ctx* ctx, const tai_basis* basis, double tau, int32_t* pairs, int32_t* nkept,
+                     void* stream);
+
+/* tai_moments for a list of pairs: M[d][a][i] is the moment of pair pairs[i]
+   (an index into the full pair list, e.g. from tai_screen_pairs), i < npk.
+   pairs: DEVICE int32 [npk], 1 <= npk <= npair; entries outside the full
+   list give zero moments.  M: DEVICE double [3][n][npk].  tai_assemble_B with
+   npair = npk then returns B restricted to the listed pairs, in list order. */
+int tai_moments_pairs(tai_ctx* ctx, const tai_basis* basis, const tai_params* params, const int32_t* pairs,
+                      int32_t npk, double* M, void* stream);
+
+/* tai_apply_J with the pair sums restricted to a list of pairs (screening):
+   M is DEVICE double [3][n][npk] from tai_moments_pairs for the same DEVICE
+   list pairs [npk]; rho sums over the listed pairs only, J is computed for
+   them and its entries of the other pairs are written as zero.  Otherwise as
+   tai_apply_J. */
+int tai_apply_J_pairs(tai_ctx* ctx, const double* M, int32_t nb, const int32_t* pairs, int32_t npk,
+                      const tai_params* params, const double* D, double* J, void* stream);
+
 /* ---- tuning ------------------------------------------------------------- */
 
 /* Shape autotuner of the split 16-bit assembly (TAI_BF16X3, TAI_BF16X6,

@@ -26,13 +26,25 @@ namespace {
 
 constexpr double kTwoOverSqrtPi = 1.1283791670955126;
 
+// Pair p of the moments is pair pairs[p] of the full list when a screened
+// list is given (entries outside the full list contribute nothing).
+__device__ inline bool pair_of(const int32_t* pairs, int nb, int64_t p, int& mu, int& nu) {
+  int64_t g = p;
+  if (pairs) {
+    g = pairs[p];
+    if (g < 0 || g >= (int64_t)nb * (nb + 1) / 2) return false;
+  }
+  decode_pair(nb, g, mu, nu);
+  return true;
+}
+
 __global__ void __launch_bounds__(256)
-density_pairs_kernel(const double* __restrict__ D, int nb, int64_t npair, double* __restrict__ Dt) {
+density_pairs_kernel(const double* __restrict__ D, int nb, int64_t npair, const int32_t* __restrict__ pairs,
+                     double* __restrict__ Dt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npair) return;
   int mu, nu;
-  decode_pair(nb, p, mu, nu);
-  Dt[p] = D[(int64_t)mu * nb + nu] * (mu == nu ? 1.0 : 2.0);
+  Dt[p] = pair_of(pairs, nb, p, mu, nu) ? D[(int64_t)mu * nb + nu] * (mu == nu ? 1.0 : 2.0) : 0.0;
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -400,13 +412,20 @@ jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int
 }
 
 __global__ void __launch_bounds__(256)
-unpack_kernel(const double* __restrict__ Jp, int nb, int64_t npair, double* __restrict__ J) {
+unpack_kernel(const double* __restrict__ Jp, int nb, int64_t npair, const int32_t* __restrict__ pairs,
+              double* __restrict__ J) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npair) return;
   int mu, nu;
-  decode_pair(nb, p, mu, nu);
+  if (!pair_of(pairs, nb, p, mu, nu)) return;
   J[(int64_t)mu * nb + nu] = Jp[p];
   J[(int64_t)nu * nb + mu] = Jp[p];
+}
+
+// J entries of the pairs that screening dropped are zero.
+__global__ void __launch_bounds__(256) zero_kernel(double* __restrict__ x, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) x[i] = 0.0;
 }
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -468,10 +487,11 @@ void launch_pair_contraction_jp(const double* M, int n, int npair, const JWork& 
   else hipLaunchKernelGGL((jp_mfma_kernel<Op, 4>), dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
 }
 
-hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, int n, int nq, const NodeTables& tb,
-                          const double* D, double* J, const JWork& w, hipStream_t s) {
+hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
+                          const NodeTables& tb, const double* D, double* J, const JWork& w, hipStream_t s) {
   const int64_t n3 = (int64_t)n * n * n;
-  hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, D, nb, (int64_t)npair, w.Dt);
+  hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, D, nb, (int64_t)npair, pairs,
+                     w.Dt);
   if (prec == kFP32) launch_pair_contraction_rho<JF32, 1>(M, n, npair, w, s);
   else if (n <= 48) launch_pair_contraction_rho<JF64, 2>(M, n, npair, w, s);
   else launch_pair_contraction_rho<JF64, 1>(M, n, npair, w, s);
@@ -488,7 +508,11 @@ hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, int n, i
   hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.T2, tb.w, nq, n3, w.Phi);
   if (prec == kFP32) launch_pair_contraction_jp<JF32>(M, n, npair, w, s);
   else launch_pair_contraction_jp<JF64>(M, n, npair, w, s);
-  hipLaunchKernelGGL(unpack_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, w.Jp, nb, (int64_t)npair, J);
+  if (pairs) {
+    const int64_t nn = (int64_t)nb * nb;
+    hipLaunchKernelGGL(zero_kernel, dim3(nblk(nn, 256)), dim3(256), 0, s, J, nn);
+  }
+  hipLaunchKernelGGL(unpack_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, w.Jp, nb, (int64_t)npair, pairs, J);
   return hipGetLastError();
 }
 

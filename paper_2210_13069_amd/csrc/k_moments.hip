@@ -38,7 +38,7 @@ __device__ inline double ipow(double x, int l) {
 
 template <int NMAX>
 __device__ inline void moments_body(const DevBasis& bs, int n, double L, const NodeTables& tb,
-                                    double* __restrict__ M, int64_t npair) {
+                                    double* __restrict__ M, int64_t npair, const int32_t* __restrict__ pairs = nullptr) {
   // the GL panel rule and the Chebyshev-to-node map, read at uniform
   // addresses by every thread, come from LDS
   __shared__ double s_pz[kMomOrder], s_pw[kMomOrder];
@@ -56,8 +56,16 @@ __device__ inline void moments_body(const DevBasis& bs, int n, double L, const N
   if (g >= 3 * npair) return;
   const int d = (int)(g / npair);
   const int64_t p = g - d * npair;
+  // column p is pair pairs[p] of the full list when a screened list is given
+  int64_t gp = p;
+  bool valid = true;
+  if (pairs) {
+    gp = pairs[p];
+    valid = gp >= 0 && gp < (int64_t)bs.nb * (bs.nb + 1) / 2;
+    if (!valid) gp = 0;
+  }
   int mu, nu;
-  decode_pair(bs.nb, p, mu, nu);
+  decode_pair(bs.nb, gp, mu, nu);
 
   const double a = bs.alpha[mu], b = bs.alpha[nu];
   const double A = bs.center[3 * mu + d], B = bs.center[3 * nu + d];
@@ -71,7 +79,7 @@ __device__ inline void moments_body(const DevBasis& bs, int n, double L, const N
   const double pp = a + b;
   const double P = (a * A + b * B) / pp;
   const double E = exp(-a * b / pp * (A - B) * (A - B));
-  const double pref = nrm * E;
+  const double pref = valid ? nrm * E : 0.0;
   const double half = 9.0 / sqrt(pp);
   const double lo = fmax(-L, P - half);
   const double hi = fmin(L, P + half);
@@ -114,8 +122,74 @@ __device__ inline void moments_body(const DevBasis& bs, int n, double L, const N
 
 template <int NMAX>
 __global__ void __launch_bounds__(128)
-moments_kernel(DevBasis bs, int n, double L, NodeTables tb, double* __restrict__ M, int64_t npair) {
-  moments_body<NMAX>(bs, n, L, tb, M, npair);
+moments_kernel(DevBasis bs, int n, double L, NodeTables tb, double* __restrict__ M, int64_t npair,
+               const int32_t* __restrict__ pairs) {
+  moments_body<NMAX>(bs, n, L, tb, M, npair, pairs);
+}
+
+// Screening (section 5, compression by screening).  One thread per row mu
+// of the pair list counts, then writes, the pairs (mu, nu >= mu) whose
+// Gaussian product prefactor exp(-ab/(a+b) |A - B|^2) exceeds tau; a single
+// work group turns the row counts into offsets in between, so the kept
+// indices come out in ascending order.  The exponent is formed with
+// unfused, left-to-right operations.
+__device__ inline bool keep_pair(const DevBasis& bs, double tau, int mu, int nu) {
+  const double a = bs.alpha[mu], b = bs.alpha[nu];
+  double r2 = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double x = __dsub_rn(bs.center[3 * mu + d], bs.center[3 * nu + d]);
+    r2 = __dadd_rn(r2, __dmul_rn(x, x));
+  }
+  const double e = __dmul_rn(__ddiv_rn(__dmul_rn(a, b), __dadd_rn(a, b)), r2);
+  return tau <= 0.0 || exp(-e) > tau;
+}
+
+constexpr int kScreenThreads = 256;
+
+__global__ void __launch_bounds__(kScreenThreads) screen_count_kernel(DevBasis bs, double tau, int32_t* rows) {
+  const int mu = blockIdx.x * kScreenThreads + threadIdx.x;
+  if (mu >= bs.nb) return;
+  int c = 0;
+  for (int nu = mu; nu < bs.nb; ++nu) c += keep_pair(bs, tau, mu, nu) ? 1 : 0;
+  rows[mu] = c;
+}
+
+// exclusive scan of rows[0 .. nb) in place, total to rows[nb] and *count
+__global__ void __launch_bounds__(1024) screen_scan_kernel(int nb, int32_t* rows, int32_t* count) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x, per = (nb + 1023) / 1024;
+  const int lo = min(nb, t * per), hi = min(nb, lo + per);
+  int32_t sum = 0;
+  for (int i = lo; i < hi; ++i) sum += rows[i];
+  part[t] = sum;
+  __syncthreads();
+  if (t == 0) {
+    int32_t acc = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int32_t v = part[i];
+      part[i] = acc;
+      acc += v;
+    }
+    rows[nb] = acc;
+    *count = acc;
+  }
+  __syncthreads();
+  int32_t acc = part[t];
+  for (int i = lo; i < hi; ++i) {
+    const int32_t v = rows[i];
+    rows[i] = acc;
+    acc += v;
+  }
+}
+
+__global__ void __launch_bounds__(kScreenThreads)
+screen_write_kernel(DevBasis bs, double tau, const int32_t* __restrict__ rows, int32_t* __restrict__ pairs) {
+  const int mu = blockIdx.x * kScreenThreads + threadIdx.x;
+  if (mu >= bs.nb) return;
+  int32_t o = rows[mu];
+  const int64_t p0 = pair_row_start(bs.nb, mu);
+  for (int nu = mu; nu < bs.nb; ++nu)
+    if (keep_pair(bs, tau, mu, nu)) pairs[o++] = (int32_t)(p0 + (nu - mu));
 }
 
 // blockIdx.y = molecule; blocks past a molecule's 3*npair threads return
@@ -200,20 +274,33 @@ hipError_t launch_moments_batch(const PrepMol* mols, int nmol, int64_t max_npair
   return hipGetLastError();
 }
 
-hipError_t launch_moments(const DevBasis& b, int n, double L, const NodeTables& tb,
-                          double* M, hipStream_t s) {
-  const int64_t npair = (int64_t)b.nb * (b.nb + 1) / 2;
+hipError_t launch_moments_pairs(const DevBasis& b, int n, double L, const NodeTables& tb, const int32_t* pairs,
+                                int64_t npair, double* M, hipStream_t s) {
   const int64_t total = 3 * npair;
   const int threads = 128;
   const unsigned blocks = (unsigned)((total + threads - 1) / threads);
   if (n <= 16)
-    hipLaunchKernelGGL(moments_kernel<16>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair);
+    hipLaunchKernelGGL(moments_kernel<16>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair, pairs);
   else if (n <= 32)
-    hipLaunchKernelGGL(moments_kernel<32>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair);
+    hipLaunchKernelGGL(moments_kernel<32>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair, pairs);
   else if (n <= 48)
-    hipLaunchKernelGGL(moments_kernel<48>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair);
+    hipLaunchKernelGGL(moments_kernel<48>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair, pairs);
   else
-    hipLaunchKernelGGL(moments_kernel<64>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair);
+    hipLaunchKernelGGL(moments_kernel<64>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair, pairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const DevBasis& b, int n, double L, const NodeTables& tb,
+                          double* M, hipStream_t s) {
+  return launch_moments_pairs(b, n, L, tb, nullptr, (int64_t)b.nb * (b.nb + 1) / 2, M, s);
+}
+
+hipError_t launch_screen(const DevBasis& b, double tau, int32_t* rows, int32_t* pairs, int32_t* count,
+                         hipStream_t s) {
+  const unsigned blocks = (unsigned)((b.nb + kScreenThreads - 1) / kScreenThreads);
+  hipLaunchKernelGGL(screen_count_kernel, dim3(blocks), dim3(kScreenThreads), 0, s, b, tau, rows);
+  hipLaunchKernelGGL(screen_scan_kernel, dim3(1), dim3(1024), 0, s, b.nb, rows, count);
+  hipLaunchKernelGGL(screen_write_kernel, dim3(blocks), dim3(kScreenThreads), 0, s, b, tau, rows, pairs);
   return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ struct tai_ctx {
   hipEvent_t host_basis_done = nullptr;
   Buf opA, opEx, opY;     // assembly operands
   Buf opMu;               // coefficient moments (per-node degrees)
+  Buf screen;             // screening: row counts / offsets and the kept count
   Buf asm_tab, asm_counter;  // 16-bit kernel: device molecule table + items, queue counter
   Buf asm_host;           // pinned staging of the table
   hipEvent_t asm_host_done = nullptr;
@@ -461,7 +462,8 @@ int tai_destroy(tai_ctx* c) {
   if (c->device >= 0) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->asm_tab, &c->asm_counter, &c->jwork,
+    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->screen, &c->asm_tab, &c->asm_counter,
+                   &c->jwork,
                    &c->b_nodes, &c->b_basis, &c->b_opA, &c->b_opEx, &c->b_opY, &c->b_opMu, &c->b_mols, &c->b_counter})
       free_buf(c, *b);
     if (c->host_basis.p) hipHostFree(c->host_basis.p);
@@ -550,6 +552,68 @@ int tai_degrees(tai_ctx* c, const tai_params* p, int32_t* nk, double* C, void* s
   return TAI_OK;
 }
 
+// Copy a validated basis to the device (through pinned staging) on s.
+static int upload_basis(tai_ctx* c, const tai_basis* b, hipStream_t s, tai::DevBasis* db) {
+  int r;
+  const size_t bb = basis_bytes(b->nb);
+  if ((r = ensure(c, c->basis, bb))) return r;
+  if ((r = ensure_host(c, c->host_basis, c->host_basis_done, bb))) return r;
+  pack_basis_host(b, static_cast<char*>(c->host_basis.p));
+  hipError_t e = hipMemcpyAsync(c->basis.p, c->host_basis.p, bb, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "basis upload");
+  if ((e = hipEventRecord(c->host_basis_done, s)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+  *db = dev_basis_view(b, static_cast<char*>(c->basis.p));
+  return TAI_OK;
+}
+
+int tai_screen_pairs(tai_ctx* c, const tai_basis* b, double tau, int32_t* pairs, int32_t* nkept, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_basis(c, b))) return r;
+  if (!std::isfinite(tau) || !(tau < 1.0)) return fail(c, TAI_ERR_INVALID_ARG, "tau must be finite and < 1");
+  if (!pairs || !nkept) return fail(c, TAI_ERR_INVALID_ARG, "pairs or nkept is NULL");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tai::DevBasis db;
+  if ((r = upload_basis(c, b, s, &db))) return r;
+  if ((r = ensure(c, c->screen, sizeof(int32_t) * ((size_t)b->nb + 2)))) return r;
+  int32_t* rows = static_cast<int32_t*>(c->screen.p);
+  int32_t* count = rows + b->nb + 1;
+  hipError_t e;
+  {
+    Timed tm(c, kStMoments, s);
+    e = tai::launch_screen(db, tau, rows, pairs, count, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "screening kernels");
+  int32_t host = 0;
+  if ((e = hipMemcpyAsync(&host, count, sizeof host, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(c, e, "count copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  *nkept = host;
+  return TAI_OK;
+}
+
+static int moments_impl(tai_ctx* c, const tai_basis* b, const tai_params* p, const int32_t* pairs, int64_t npk,
+                        double* M, hipStream_t s) {
+  int r;
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(p->nq, p->n)))) return r;
+  tai::DevBasis db;
+  if ((r = upload_basis(c, b, s, &db))) return r;
+  hipError_t e;
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, p->nq, p->n);
+  {
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, 0.0, tb, s);  // the moments need no K tables
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  {
+    Timed tm(c, kStMoments, s);
+    e = tai::launch_moments_pairs(db, p->n, p->L, tb, pairs, npk, M, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "moments kernel");
+  return TAI_OK;
+}
+
 int tai_moments(tai_ctx* c, const tai_basis* b, const tai_params* p, double* M, void* stream) {
   int r = check_ctx(c);
   if (r) return r;
@@ -557,28 +621,19 @@ int tai_moments(tai_ctx* c, const tai_basis* b, const tai_params* p, double* M, 
   if ((r = validate_params(c, p))) return r;
   if (!M) return fail(c, TAI_ERR_INVALID_ARG, "M is NULL");
   if ((r = need_device(c))) return r;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t bb = basis_bytes(b->nb);
-  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(p->nq, p->n)))) return r;
-  if ((r = ensure(c, c->basis, bb))) return r;
-  if ((r = ensure_host(c, c->host_basis, c->host_basis_done, bb))) return r;
-  pack_basis_host(b, static_cast<char*>(c->host_basis.p));
-  hipError_t e = hipMemcpyAsync(c->basis.p, c->host_basis.p, bb, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return hip_fail(c, e, "basis upload");
-  if ((e = hipEventRecord(c->host_basis_done, s)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
-  NodeTables tb = tai::carve_node_tables(c->nodes.p, p->nq, p->n);
-  {
-    Timed tm(c, kStNodes, s);
-    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, p->degree_tol, tb, s);
-  }
-  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
-  tai::DevBasis db = dev_basis_view(b, static_cast<char*>(c->basis.p));
-  {
-    Timed tm(c, kStMoments, s);
-    e = tai::launch_moments(db, p->n, p->L, tb, M, s);
-  }
-  if (e != hipSuccess) return hip_fail(c, e, "moments kernel");
-  return TAI_OK;
+  return moments_impl(c, b, p, nullptr, npair_of(b->nb), M, static_cast<hipStream_t>(stream));
+}
+
+int tai_moments_pairs(tai_ctx* c, const tai_basis* b, const tai_params* p, const int32_t* pairs, int32_t npk,
+                      double* M, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_basis(c, b))) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !pairs) return fail(c, TAI_ERR_INVALID_ARG, "pairs or M is NULL");
+  if (npk < 1 || npk > npair_of(b->nb)) return fail(c, TAI_ERR_INVALID_ARG, "npk must be in [1, npair]");
+  if ((r = need_device(c))) return r;
+  return moments_impl(c, b, p, pairs, npk, M, static_cast<hipStream_t>(stream));
 }
 
 static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_params* p, void* B, int64_t ldb,
@@ -918,15 +973,9 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   return TAI_OK;
 }
 
-int tai_apply_J(tai_ctx* c, const double* M, int32_t nb, const tai_params* p, const double* D, double* J,
-                void* stream) {
-  int r = check_ctx(c);
-  if (r) return r;
-  if ((r = validate_params(c, p))) return r;
-  if (!M || !D || !J) return fail(c, TAI_ERR_INVALID_ARG, "M, D or J is NULL");
-  if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
-  const int64_t npair = npair_of(nb);
-  if (npair > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
+static int apply_j_impl(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs, int64_t npair,
+                        const tai_params* p, const double* D, double* J, void* stream) {
+  int r;
   if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
     return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J supports prec TAI_FP64 and TAI_FP32");
   if ((r = need_device(c))) return r;
@@ -944,10 +993,34 @@ int tai_apply_J(tai_ctx* c, const double* M, int32_t nb, const tai_params* p, co
   tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, n, (int)npair);
   {
     Timed tm(c, kStApplyJ, s);
-    e = tai::launch_apply_j(p->prec, M, nb, (int)npair, n, nq, tb, D, J, w, s);
+    e = tai::launch_apply_j(p->prec, M, nb, (int)npair, pairs, n, nq, tb, D, J, w, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "apply_J kernels");
   return TAI_OK;
+}
+
+int tai_apply_J(tai_ctx* c, const double* M, int32_t nb, const tai_params* p, const double* D, double* J,
+                void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !D || !J) return fail(c, TAI_ERR_INVALID_ARG, "M, D or J is NULL");
+  if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
+  const int64_t npair = npair_of(nb);
+  if (npair > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
+  return apply_j_impl(c, M, nb, nullptr, npair, p, D, J, stream);
+}
+
+int tai_apply_J_pairs(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs, int32_t npk,
+                      const tai_params* p, const double* D, double* J, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !D || !J || !pairs) return fail(c, TAI_ERR_INVALID_ARG, "M, pairs, D or J is NULL");
+  if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
+  if (npair_of(nb) > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
+  if (npk < 1 || npk > npair_of(nb)) return fail(c, TAI_ERR_INVALID_ARG, "npk must be in [1, npair]");
+  return apply_j_impl(c, M, nb, pairs, npk, p, D, J, stream);
 }
 
 int tai_tune(tai_ctx* c, int mode) {

@@ -52,6 +52,16 @@ struct DevBasis {
 
 hipError_t launch_moments(const DevBasis& b, int n, double L, const NodeTables& tb,
                           double* M, hipStream_t s);
+// Moments of the listed pairs (indices into the full pair list; entries
+// outside it give zero moments): M[d][a][i] for pair pairs[i], i < npk.
+hipError_t launch_moments_pairs(const DevBasis& b, int n, double L, const NodeTables& tb, const int32_t* pairs,
+                                int64_t npk, double* M, hipStream_t s);
+// Screening (section 5): pair p(mu, nu) is kept when
+// exp(-ab/(a+b) |A - B|^2) > tau (every pair when tau <= 0).  Writes the kept
+// indices in ascending order to pairs and their count to *count (device);
+// rows: device scratch of nb + 1 int32.
+hipError_t launch_screen(const DevBasis& b, double tau, int32_t* rows, int32_t* pairs, int32_t* count,
+                         hipStream_t s);
 // Coefficient moments mu_d[j][p] = sum_a T_j(xi_a / L) M_d[a][p] (the
 // moments against T_j, j < n), FP64.
 hipError_t launch_coef_moments(const double* M, int n, int64_t npair, int kind, double* mu, hipStream_t s);
@@ -194,7 +204,9 @@ hipError_t launch_probe(int what, int cus, float* out, const void* src, void* ds
                         hipStream_t s);
 double probe_work(int what, int cus, int64_t n16, int iters);
 
-hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, int n, int nq,
+// pairs: nullptr (all pairs), or the screened list: M holds the moments of
+// pairs[0 .. npair), and the J entries of the other pairs are set to zero.
+hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
                           const NodeTables& tb, const double* D, double* J,
                           const JWork& w, hipStream_t s);
 

@@ -28,7 +28,8 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 
 # exported symbols declared in include/tai.h
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
-           "tai_quadrature", "tai_degrees", "tai_moments", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
+           "tai_quadrature", "tai_degrees", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
+           "tai_apply_J_pairs", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
            "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched"]
 
@@ -86,6 +87,12 @@ def load_library(path=LIB_PATH):
     lib.tai_sync.argtypes = [vp, vp]
     lib.tai_quadrature.argtypes = [vp, ctypes.POINTER(tai_params), vp, vp, vp, vp, vp]
     lib.tai_degrees.argtypes = [vp, ctypes.POINTER(tai_params), vp, vp, vp]
+    lib.tai_screen_pairs.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.c_double, vp,
+                                     ctypes.POINTER(ctypes.c_int32), vp]
+    lib.tai_moments_pairs.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.POINTER(tai_params), vp, ctypes.c_int32,
+                                      vp, vp]
+    lib.tai_apply_J_pairs.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp,
+                                      vp, vp]
     lib.tai_moments.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.POINTER(tai_params), vp, vp]
     lib.tai_assemble_B.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, ctypes.c_int64, vp]
     lib.tai_assemble_B_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(tai_mol), vp]
@@ -176,6 +183,24 @@ class Context:
         p = params if isinstance(params, tai_params) else make_params(params)
         self.check(self.lib.tai_degrees(self.h, ctypes.byref(p), _ptr(nk), _ptr(C), _stream(stream)),
                    "tai_degrees")
+
+    def screen_pairs(self, basis_arrays, tau, pairs, stream=None):
+        """Kept pair indices into `pairs` (int32 device tensor of npair
+        entries); returns their count."""
+        cnt = ctypes.c_int32()
+        self.check(self.lib.tai_screen_pairs(self.h, ctypes.byref(basis_arrays.struct), float(tau), _ptr(pairs),
+                                             ctypes.byref(cnt), _stream(stream)), "tai_screen_pairs")
+        return cnt.value
+
+    def moments_pairs(self, basis_arrays, params, pairs, npk, M, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        self.check(self.lib.tai_moments_pairs(self.h, ctypes.byref(basis_arrays.struct), ctypes.byref(p),
+                                              _ptr(pairs), int(npk), _ptr(M), _stream(stream)), "tai_moments_pairs")
+
+    def apply_J_pairs(self, M, nb, pairs, npk, params, D, J, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        self.check(self.lib.tai_apply_J_pairs(self.h, _ptr(M), int(nb), _ptr(pairs), int(npk), ctypes.byref(p),
+                                              _ptr(D), _ptr(J), _stream(stream)), "tai_apply_J_pairs")
 
     def moments(self, basis_arrays, params, M, stream=None):
         p = params if isinstance(params, tai_params) else make_params(params)
@@ -278,4 +303,33 @@ def apply_J(M, D, params, prec=FP64, device=0):
     nb = int(D.shape[0])
     J = torch.empty((nb, nb), dtype=torch.float64, device=M.device)
     context(device).apply_J(M, nb, make_params(params, prec), D, J)
+    return J
+
+
+def screen_pairs(basis, tau, device=0):
+    """Pair indices kept by screening at tau (int32 device tensor, ascending)."""
+    import torch
+    ba = BasisArrays(basis)
+    npair = ba.alpha.shape[0] * (ba.alpha.shape[0] + 1) // 2
+    pairs = torch.empty(npair, dtype=torch.int32, device=torch.device("cuda", device))
+    cnt = context(device).screen_pairs(ba, tau, pairs)
+    return pairs[:cnt].clone()
+
+
+def moments_pairs(basis, params, pairs, coef=None, device=0):
+    """M[3][n][len(pairs)] (FP64, on the device) of the listed pairs."""
+    import torch
+    ba = BasisArrays(basis, coef)
+    npk = int(pairs.shape[0])
+    M = torch.empty((3, int(params.n), npk), dtype=torch.float64, device=torch.device("cuda", device))
+    context(device).moments_pairs(ba, params, pairs, npk, M)
+    return M
+
+
+def apply_J_pairs(M, D, pairs, params, prec=FP64, device=0):
+    """J (nb x nb FP64) with the pair sums restricted to `pairs`."""
+    import torch
+    nb = int(D.shape[0])
+    J = torch.empty((nb, nb), dtype=torch.float64, device=M.device)
+    context(device).apply_J_pairs(M, nb, pairs, int(pairs.shape[0]), make_params(params, prec), D, J)
     return J

@@ -193,3 +193,25 @@ def test_device_context_without_gpu_fails_cleanly(lib):
     h = ctypes.c_void_p()
     assert lib.tai_create(ctypes.byref(h), 0) == tai.TAI_ERR_HIP
     assert not h.value
+
+
+def test_screening_argument_checks(hctx):
+    lib, h = hctx.lib, hctx.h
+    ba = tai.BasisArrays(_basis())
+    dummy = ctypes.c_void_p(16)
+    cnt = ctypes.c_int32(-7)
+    for tau in (float("nan"), float("inf"), 1.0, 2.0):
+        assert lib.tai_screen_pairs(h, ctypes.byref(ba.struct), tau, dummy, ctypes.byref(cnt), None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_screen_pairs(h, ctypes.byref(ba.struct), 1e-8, None, ctypes.byref(cnt), None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_screen_pairs(h, ctypes.byref(ba.struct), 1e-8, dummy, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_screen_pairs(h, ctypes.byref(ba.struct), 1e-8, dummy, ctypes.byref(cnt), None) == tai.TAI_ERR_NOT_READY
+    assert cnt.value == -7  # nothing written on a host-only context
+    p = _params()
+    npair = ba.alpha.shape[0] * (ba.alpha.shape[0] + 1) // 2
+    for npk in (0, -1, npair + 1):
+        assert lib.tai_moments_pairs(h, ctypes.byref(ba.struct), ctypes.byref(p), dummy, npk, dummy, None) == tai.TAI_ERR_INVALID_ARG
+        assert lib.tai_apply_J_pairs(h, dummy, ba.alpha.shape[0], dummy, npk, ctypes.byref(p), dummy, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_moments_pairs(h, ctypes.byref(ba.struct), ctypes.byref(p), None, 3, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_apply_J_pairs(h, dummy, ba.alpha.shape[0], None, 3, ctypes.byref(p), dummy, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_moments_pairs(h, ctypes.byref(ba.struct), ctypes.byref(p), dummy, npair, dummy, None) == tai.TAI_ERR_NOT_READY
+    assert lib.tai_apply_J_pairs(h, dummy, ba.alpha.shape[0], dummy, 3, ctypes.byref(p), dummy, dummy, None) == tai.TAI_ERR_NOT_READY
