@@ -9,7 +9,8 @@ the full 80200 x 80200 B, in the headline arithmetic (split FP16, 3 products).
 `value` = stored B entries per second of that step, inputs resident on the
 device.  The same line reports the FP64 / FP32 / BF16 forms of the same step,
 FP64 and FP32 with a degree per quadrature node (the paper's N_i, each
-factor within 1e-8 on the box), the batched persistent assembly of 64 molecules (graph replay vs one launch
+factor within 1e-8 on the box), the step and the J-build over the pairs that
+screening keeps (prefactor above 1e-12), the batched persistent assembly of 64 molecules (graph replay vs one launch
 sequence per molecule), the J-build through the grid tensor (Nb = 1000), the
 error of every form against the FP64 oracle on sampled entries, the roofline
 of the dominant kernel, and the oracle timed on the host cores.
@@ -35,6 +36,9 @@ HBM_PEAK_GBS = 8000.0
 # tolerance of the per-node degree leg: each node's factor moves by at most
 # this much on the box (below the degree-40 interpolation error at omega 0.3)
 DEGREE_TOL = 1e-8
+# screening threshold of the screened legs: pairs whose Gaussian product
+# prefactor is at most this are dropped
+SCREEN_TAU = 1e-12
 
 
 def log(msg):
@@ -215,6 +219,42 @@ def main():
     del B32
     torch.cuda.empty_cache()
 
+    # ---------------- the headline step over the pairs kept by screening -------
+    screened = None
+    screened_sample = None
+    if not args.only_headline:
+        pairs = torch.empty(npair, dtype=torch.int32, device=dev)
+        params = tai.make_params(P, head)
+        Ms = Bs = None
+        log(f"screened {args.prec}: tau={SCREEN_TAU}")
+        for it in range(W + K):
+            if it == W:
+                torch.cuda.synchronize()
+                ctx.profile_enable(True)
+                t0 = time.perf_counter()
+            npk = ctx.screen_pairs(ba, SCREEN_TAU, pairs)
+            if Ms is None:
+                Ms = torch.empty((3, n, npk), dtype=torch.float64, device=dev)
+                Bs = torch.empty((npk, npk), dtype=torch.float64 if head == tai.FP64 else torch.float32, device=dev)
+            ctx.moments_pairs(ba, P, pairs, npk, Ms)
+            ctx.assemble_B(Ms, npk, params, Bs)
+        torch.cuda.synchronize()
+        ms_s = (time.perf_counter() - t0) * 1e3 / K
+        sts = {s_: ctx.profile_read(s_) for s_ in ("moments", "pack", "project", "assemble")}
+        ctx.profile_enable(False)
+        ent_s = float(npk) * npk
+        screened = {"tau": SCREEN_TAU, "kept_pairs": npk, "pairs": npair, "entries": ent_s,
+                    "ms_per_step": round(ms_s, 3), "entries_per_s": ent_s / (ms_s / 1e3),
+                    "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in sts.items()},
+                    "speedup_vs_unscreened_step": round(ms_head / ms_s, 3)}
+        ki = rng.integers(0, npk, 240)
+        kj = rng.integers(0, npk, 240)
+        kept_host = pairs[:npk].cpu().numpy().astype(np.int64)
+        screened_sample = (kept_host[ki], kept_host[kj],
+                           Bs[torch.as_tensor(ki, device=dev), torch.as_tensor(kj, device=dev)].double().cpu().numpy())
+        del Ms, Bs, pairs
+        torch.cuda.empty_cache()
+
     # ---------------- batched persistent assembly (64 molecules) --------------
     batched = None
     if not args.only_headline:
@@ -295,7 +335,34 @@ def main():
                                                         torch.linalg.matrix_norm(ref, 2))
         japply["fp32"]["normwise_vs_fp64_gpu"] = float((got - ref).abs().max() / ref.abs().max())
         japply["fp32"]["speedup_vs_fp64"] = round(japply["fp64"]["ms_per_step"] / japply["fp32"]["ms_per_step"], 3)
-        del Mj, Jj
+        # the same J-build over the pairs kept by screening
+        jpairs = torch.empty(jb.npair, dtype=torch.int32, device=dev)
+        jparams = tai.make_params(jP, tai.FP64)
+        Js = torch.empty_like(Jj["fp64"])
+        Mjs = None
+        log(f"screened J-build fp64: tau={SCREEN_TAU}")
+        for it in range(W + K):
+            if it == W:
+                torch.cuda.synchronize()
+                ctx.profile_enable(True)
+                t0 = time.perf_counter()
+            npk_j = ctx.screen_pairs(jba, SCREEN_TAU, jpairs)
+            if Mjs is None:
+                Mjs = torch.empty((3, jP.n, npk_j), dtype=torch.float64, device=dev)
+            ctx.moments_pairs(jba, jP, jpairs, npk_j, Mjs)
+            ctx.apply_J_pairs(Mjs, jb.nb, jpairs, npk_j, jparams, Dj, Js)
+        torch.cuda.synchronize()
+        ms_js = (time.perf_counter() - t0) * 1e3 / K
+        stj = {s_: ctx.profile_read(s_) for s_ in ("moments", "apply_J")}
+        ctx.profile_enable(False)
+        ref = Jj["fp64"]
+        screened_j = {"tau": SCREEN_TAU, "kept_pairs": npk_j, "pairs": jb.npair, "ms_per_step": round(ms_js, 3),
+                      "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stj.items()},
+                      "speedup_vs_unscreened": round(japply["fp64"]["ms_per_step"] / ms_js, 3),
+                      "rel_2norm_vs_unscreened_gpu": float(torch.linalg.matrix_norm(Js - ref, 2) /
+                                                           torch.linalg.matrix_norm(ref, 2))}
+        japply["screened_fp64"] = screened_j
+        del Mj, Jj, Js, Mjs
         torch.cuda.empty_cache()
 
     # ---------------- the device's own sustained peaks ------------------------
@@ -353,6 +420,13 @@ def main():
             Ktr = T.truncated_tables(t, xi, P.L, DEGREE_TOL)[2]
             ref_deg = T.B_entries(Mr, Ktr, w, np.searchsorted(allp, sp), np.searchsorted(allp, sq))
             degrees["oracle_change_vs_fixed_degree"] = float(np.max(np.abs(ref_deg - ref)) / scale)
+        if screened_sample is not None:
+            gi, gj, sv = screened_sample
+            allk = np.unique(np.concatenate([gi, gj]))
+            Mk = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, pairs=allk)
+            ref_s = T.B_entries(Mk, Kt, w, np.searchsorted(allk, gi), np.searchsorted(allk, gj))
+            err = np.abs(sv - ref_s)
+            rel_error[args.prec + "_screened"] = {"normwise": float(np.max(err) / scale)}
         for name, sv in samples.items():
             r = ref_deg if name.endswith("_degrees") else ref
             err = np.abs(sv - r)
@@ -382,6 +456,7 @@ def main():
         "rel_error_vs_oracle": rel_error,
         "paths": paths,
         "degrees": degrees,
+        "screened": screened,
         "batched": batched,
         "japply": japply,
     }
