@@ -506,6 +506,20 @@ def J_grid_pairs(M, K, w, D, pairs):
     return unpack_pairs(Jp, nb)
 
 
+def coulomb_mo(M, K, w, Q):
+    """Coulomb matrix in the molecular-orbital basis (section 5, eq. Coul):
+    J(i,j) = < q_i q_i^T, B (q_j q_j^T) >, the sum over all ordered
+    (mu, nu) and (kappa, lambda) of q_i(mu) q_i(nu) B(mu nu, kappa lambda)
+    q_j(kappa) q_j(lambda), for the orbitals Q[i] (rows, length nb).  Each
+    B (q_j q_j^T) is the AO Coulomb matrix of the density q_j q_j^T, taken by
+    the grid route."""
+    Q = np.asarray(Q, dtype=np.float64)
+    norb = Q.shape[0]
+    Dm = [np.outer(Q[i], Q[i]) for i in range(norb)]
+    Jao = [J_grid(M, K, w, Dm[j]) for j in range(norb)]
+    return np.array([[np.sum(Dm[i] * Jao[j]) for j in range(norb)] for i in range(norb)])
+
+
 def J_direct_rows(M, K, w, D, rows):
     """J_p = sum_q B(p,q) Dt_q for the given pair rows, with the rows of B
     from Theorem 3.1 (eq. Coul in the atomic-orbital basis)."""

@@ -65,3 +65,44 @@ def test_J_linear_in_density():
     J12 = T.J_grid(M, K, w, 2.0 * D1 - 0.5 * D2)
     ref = 2.0 * T.J_grid(M, K, w, D1) - 0.5 * T.J_grid(M, K, w, D2)
     assert np.max(np.abs(J12 - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_coulomb_mo_equals_B_contracted_with_orbital_densities():
+    # J(i,j) = <q_i q_i^T, B (q_j q_j^T)> against the full B written out over
+    # all ordered index pairs, on a tiny basis
+    basis = I.small_random(81, natoms=2, shells=("s", "p"), box=2.0)
+    M, K, w = _ta(basis, 0.5, 8, 12, 8.0)
+    rng = np.random.default_rng(12)
+    Q = rng.standard_normal((3, basis.nb))
+    Jmo = T.coulomb_mo(M, K, w, Q)
+    B = T.B_full(M, K, w)
+    nb = basis.nb
+    Bfull = np.zeros((nb, nb, nb, nb))
+    mu, nu = T.pair_list(nb)
+    for p in range(basis.npair):
+        for q in range(basis.npair):
+            for (a, b_) in {(mu[p], nu[p]), (nu[p], mu[p])}:
+                for (c, d) in {(mu[q], nu[q]), (nu[q], mu[q])}:
+                    Bfull[a, b_, c, d] = B[p, q]
+    ref = np.einsum("ia,ib,abcd,jc,jd->ij", Q, Q, Bfull, Q, Q)
+    assert np.max(np.abs(Jmo - ref)) <= 1e-12 * np.max(np.abs(ref))
+    np.testing.assert_allclose(Jmo, Jmo.T, rtol=1e-12, atol=1e-14 * np.max(np.abs(ref)))
+    # B is positive semidefinite, so the diagonal of the MO Coulomb matrix is >= 0
+    assert np.all(np.diag(Jmo) >= -1e-14 * np.max(np.abs(ref)))
+
+
+def test_coulomb_mo_closed_form_s():
+    # s-type basis at converged TA parameters: the MO Coulomb matrix from the
+    # exact long-range integrals
+    b, _ = I.tiny_s()
+    M, K, w = _ta(b, 0.5, 32, 64, 12.0)
+    rng = np.random.default_rng(13)
+    Q = rng.standard_normal((4, b.nb))
+    Jmo = T.coulomb_mo(M, K, w, Q)
+    Bc = X.B_closed_form_s(b.center, b.alpha, 0.5)
+    ref = np.zeros((4, 4))
+    for j in range(4):
+        Jao = T.unpack_pairs(Bc @ T.density_pairs(np.outer(Q[j], Q[j])), b.nb)
+        for i in range(4):
+            ref[i, j] = np.sum(np.outer(Q[i], Q[i]) * Jao)
+    assert np.max(np.abs(Jmo - ref)) <= 1e-11 * np.max(np.abs(ref))
