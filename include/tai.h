@@ -216,6 +216,21 @@ int tai_assemble_B_batched(tai_ctx* ctx, int32_t nmol, const tai_mol* mols, void
 int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* params,
                 const double* D, double* J, void* stream);
 
+/* Coulomb matrix in the molecular-orbital basis (section 5, eq. Coul):
+     Jmo[i][j] = sum over all ordered (mu,nu), (kappa,lambda) of
+                 q_i(mu) q_i(nu) B(mu nu, kappa lambda) q_j(kappa) q_j(lambda)
+   = < q_i q_i^T, B (q_j q_j^T) > for the orbitals q_i = Q[i][0 .. nb).
+   Through the grid, with neither B nor any AO Coulomb matrix formed: for each
+   orbital the pair density of q_i q_i^T gives rho_i and Phi_i as in
+   tai_apply_J, and Jmo[i][j] = sum_a rho_i(a) Phi_j(a) over the n^3 grid.
+   M: DEVICE double [3][n][npair], or [3][n][npk] for the DEVICE pair list
+   pairs [npk] of tai_moments_pairs (pairs NULL: all pairs, npk ignored).
+   Q: DEVICE double [norb][nb], 1 <= norb <= 1024.  Jmo: DEVICE double
+   [norb][norb].  params->prec TAI_FP64 or TAI_FP32 as for tai_apply_J (the
+   rho contraction); the grid sums are FP64.  Workspace 2 * norb * n^3 doubles. */
+int tai_coulomb_mo(tai_ctx* ctx, const double* M, int32_t nb, const int32_t* pairs, int32_t npk,
+                   const tai_params* params, const double* Q, int32_t norb, double* Jmo, void* stream);
+
 /* ---- screening (section 5, compression by screening) --------------------- */
 
 /* Pairs that survive screening: pair p(mu,nu), mu <= nu, is dropped when its

@@ -422,6 +422,37 @@ unpack_kernel(const double* __restrict__ Jp, int nb, int64_t npair, const int32_
   J[(int64_t)nu * nb + mu] = Jp[p];
 }
 
+// Pair density of one orbital, D = q q^T folded over the ordered pairs:
+// Dt_p = q(mu) q(nu) (2 - delta_mu,nu).
+__global__ void __launch_bounds__(256)
+orbital_pairs_kernel(const double* __restrict__ q, int nb, int64_t npair, const int32_t* __restrict__ pairs,
+                     double* __restrict__ Dt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npair) return;
+  int mu, nu;
+  Dt[p] = pair_of(pairs, nb, p, mu, nu) ? q[mu] * q[nu] * (mu == nu ? 1.0 : 2.0) : 0.0;
+}
+
+// J_mo(i, j) = sum_a rho_i(a) Phi_j(a) over the n^3 grid, one work group per
+// (i, j), a fixed-order tree sum.
+__global__ void __launch_bounds__(256)
+mo_dot_kernel(const double* __restrict__ R, const double* __restrict__ F, int64_t n3, int norb,
+              double* __restrict__ Jmo) {
+  __shared__ double red[256];
+  const int i = blockIdx.y, j = blockIdx.x;
+  const double* r = R + (int64_t)i * n3;
+  const double* f = F + (int64_t)j * n3;
+  double acc = 0.0;
+  for (int64_t a = threadIdx.x; a < n3; a += 256) acc += r[a] * f[a];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) Jmo[(int64_t)i * norb + j] = red[0];
+}
+
 // J entries of the pairs that screening dropped are zero.
 __global__ void __launch_bounds__(256) zero_kernel(double* __restrict__ x, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -487,11 +518,12 @@ void launch_pair_contraction_jp(const double* M, int n, int npair, const JWork& 
   else hipLaunchKernelGGL((jp_mfma_kernel<Op, 4>), dim3(jb), dim3(512), 0, s, M, w.Phi, n, (int64_t)npair, w.Jp);
 }
 
-hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
-                          const NodeTables& tb, const double* D, double* J, const JWork& w, hipStream_t s) {
+namespace {
+// rho from the pair densities in w.Dt, then Phi = (2/sqrt(pi)) sum_k w_k rho x_d K_k
+// (into w.rho and w.Phi)
+void launch_rho_phi(int prec, const double* M, int npair, int n, int nq, const NodeTables& tb, const JWork& w,
+                    hipStream_t s) {
   const int64_t n3 = (int64_t)n * n * n;
-  hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, D, nb, (int64_t)npair, pairs,
-                     w.Dt);
   if (prec == kFP32) launch_pair_contraction_rho<JF32, 1>(M, n, npair, w, s);
   else if (n <= 48) launch_pair_contraction_rho<JF64, 2>(M, n, npair, w, s);
   else launch_pair_contraction_rho<JF64, 1>(M, n, npair, w, s);
@@ -506,6 +538,14 @@ hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, const in
   else if (n <= 48) hipLaunchKernelGGL(mode0_kernel<48>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
   else hipLaunchKernelGGL(mode0_kernel<64>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
   hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.T2, tb.w, nq, n3, w.Phi);
+}
+}  // namespace
+
+hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
+                          const NodeTables& tb, const double* D, double* J, const JWork& w, hipStream_t s) {
+  hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, D, nb, (int64_t)npair, pairs,
+                     w.Dt);
+  launch_rho_phi(prec, M, npair, n, nq, tb, w, s);
   if (prec == kFP32) launch_pair_contraction_jp<JF32>(M, n, npair, w, s);
   else launch_pair_contraction_jp<JF64>(M, n, npair, w, s);
   if (pairs) {
@@ -513,6 +553,24 @@ hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, const in
     hipLaunchKernelGGL(zero_kernel, dim3(nblk(nn, 256)), dim3(256), 0, s, J, nn);
   }
   hipLaunchKernelGGL(unpack_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, w.Jp, nb, (int64_t)npair, pairs, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
+                             const NodeTables& tb, const double* Q, int norb, double* R, double* F, double* Jmo,
+                             const JWork& w, hipStream_t s) {
+  const int64_t n3 = (int64_t)n * n * n;
+  for (int i = 0; i < norb; ++i) {
+    JWork wi = w;
+    wi.rho = R + (int64_t)i * n3;
+    wi.Phi = F + (int64_t)i * n3;
+    hipLaunchKernelGGL(orbital_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, Q + (int64_t)i * nb, nb,
+                       (int64_t)npair, pairs, wi.Dt);
+    launch_rho_phi(prec, M, npair, n, nq, tb, wi, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(mo_dot_kernel, dim3(norb, norb), dim3(256), 0, s, R, F, n3, norb, Jmo);
   return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ struct tai_ctx {
   Buf opA, opEx, opY;     // assembly operands
   Buf opMu;               // coefficient moments (per-node degrees)
   Buf screen;             // screening: row counts / offsets and the kept count
+  Buf mo;                 // orbital-basis Coulomb matrix: rho and Phi of every orbital
   Buf asm_tab, asm_counter;  // 16-bit kernel: device molecule table + items, queue counter
   Buf asm_host;           // pinned staging of the table
   hipEvent_t asm_host_done = nullptr;
@@ -462,7 +463,8 @@ int tai_destroy(tai_ctx* c) {
   if (c->device >= 0) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->screen, &c->asm_tab, &c->asm_counter,
+    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->screen, &c->mo, &c->asm_tab,
+                   &c->asm_counter,
                    &c->jwork,
                    &c->b_nodes, &c->b_basis, &c->b_opA, &c->b_opEx, &c->b_opY, &c->b_opMu, &c->b_mols, &c->b_counter})
       free_buf(c, *b);
@@ -1021,6 +1023,43 @@ int tai_apply_J_pairs(tai_ctx* c, const double* M, int32_t nb, const int32_t* pa
   if (npair_of(nb) > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
   if (npk < 1 || npk > npair_of(nb)) return fail(c, TAI_ERR_INVALID_ARG, "npk must be in [1, npair]");
   return apply_j_impl(c, M, nb, pairs, npk, p, D, J, stream);
+}
+
+int tai_coulomb_mo(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs, int32_t npk,
+                   const tai_params* p, const double* Q, int32_t norb, double* Jmo, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !Q || !Jmo) return fail(c, TAI_ERR_INVALID_ARG, "M, Q or Jmo is NULL");
+  if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
+  if (npair_of(nb) > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
+  if (norb < 1 || norb > 1024) return fail(c, TAI_ERR_INVALID_ARG, "norb must be in [1, 1024]");
+  if (pairs && (npk < 1 || npk > npair_of(nb))) return fail(c, TAI_ERR_INVALID_ARG, "npk must be in [1, npair]");
+  if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_coulomb_mo supports prec TAI_FP64 and TAI_FP32");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = p->n, nq = p->nq;
+  const int64_t npair = pairs ? npk : npair_of(nb);
+  const size_t n3 = (size_t)n * n * n;
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
+  if ((r = ensure(c, c->jwork, tai::j_work_bytes(p->prec, nq, n, (int)npair)))) return r;
+  if ((r = ensure(c, c->mo, 2 * sizeof(double) * n3 * (size_t)norb))) return r;
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
+  hipError_t e;
+  {
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, p->degree_tol, tb, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, n, (int)npair);
+  double* R = static_cast<double*>(c->mo.p);
+  {
+    Timed tm(c, kStApplyJ, s);
+    e = tai::launch_coulomb_mo(p->prec, M, nb, (int)npair, pairs, n, nq, tb, Q, norb, R, R + n3 * norb, Jmo, w, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "coulomb_mo kernels");
+  return TAI_OK;
 }
 
 int tai_tune(tai_ctx* c, int mode) {

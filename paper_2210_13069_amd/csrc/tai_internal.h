@@ -198,6 +198,12 @@ struct JWork {
 int j_nchunk(int prec, int n, int npair);
 size_t j_work_bytes(int prec, int nq, int n, int npair);
 JWork carve_j_work(void* base, int prec, int nq, int n, int npair);
+// Coulomb matrix in the orbital basis: per orbital i (row i of Q, length nb)
+// the pair density of q_i q_i^T, rho_i -> R[i] and Phi_i -> F[i] (n^3 each),
+// then Jmo[i][j] = sum_a R[i][a] F[j][a].
+hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
+                             const NodeTables& tb, const double* Q, int norb, double* R, double* F, double* Jmo,
+                             const JWork& w, hipStream_t s);
 // Achievable-peak probes (k_probe.hip): what 0 = FP16 MFMA, 1 = FP64 MFMA,
 // 2 = HBM copy.  probe_work is the flops (0, 1) or bytes (2) of one launch.
 hipError_t launch_probe(int what, int cus, float* out, const void* src, void* dst, int64_t n16, int iters,

@@ -29,7 +29,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 # exported symbols declared in include/tai.h
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
            "tai_quadrature", "tai_degrees", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
-           "tai_apply_J_pairs", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
+           "tai_apply_J_pairs", "tai_coulomb_mo", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
            "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched"]
 
@@ -93,6 +93,8 @@ def load_library(path=LIB_PATH):
                                       vp, vp]
     lib.tai_apply_J_pairs.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp,
                                       vp, vp]
+    lib.tai_coulomb_mo.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp,
+                                   ctypes.c_int32, vp, vp]
     lib.tai_moments.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.POINTER(tai_params), vp, vp]
     lib.tai_assemble_B.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, ctypes.c_int64, vp]
     lib.tai_assemble_B_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(tai_mol), vp]
@@ -201,6 +203,11 @@ class Context:
         p = params if isinstance(params, tai_params) else make_params(params)
         self.check(self.lib.tai_apply_J_pairs(self.h, _ptr(M), int(nb), _ptr(pairs), int(npk), ctypes.byref(p),
                                               _ptr(D), _ptr(J), _stream(stream)), "tai_apply_J_pairs")
+
+    def coulomb_mo(self, M, nb, params, Q, norb, Jmo, pairs=None, npk=0, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        self.check(self.lib.tai_coulomb_mo(self.h, _ptr(M), int(nb), _ptr(pairs), int(npk), ctypes.byref(p), _ptr(Q),
+                                           int(norb), _ptr(Jmo), _stream(stream)), "tai_coulomb_mo")
 
     def moments(self, basis_arrays, params, M, stream=None):
         p = params if isinstance(params, tai_params) else make_params(params)
@@ -333,3 +340,13 @@ def apply_J_pairs(M, D, pairs, params, prec=FP64, device=0):
     J = torch.empty((nb, nb), dtype=torch.float64, device=M.device)
     context(device).apply_J_pairs(M, nb, pairs, int(pairs.shape[0]), make_params(params, prec), D, J)
     return J
+
+
+def coulomb_mo(M, nb, Q, params, prec=FP64, pairs=None, device=0):
+    """Orbital-basis Coulomb matrix [norb][norb] (FP64) for orbitals Q [norb][nb]."""
+    import torch
+    norb = int(Q.shape[0])
+    Jmo = torch.empty((norb, norb), dtype=torch.float64, device=M.device)
+    context(device).coulomb_mo(M, nb, make_params(params, prec), Q, norb, Jmo, pairs=pairs,
+                               npk=0 if pairs is None else int(pairs.shape[0]))
+    return Jmo

@@ -215,3 +215,21 @@ def test_screening_argument_checks(hctx):
     assert lib.tai_apply_J_pairs(h, dummy, ba.alpha.shape[0], None, 3, ctypes.byref(p), dummy, dummy, None) == tai.TAI_ERR_INVALID_ARG
     assert lib.tai_moments_pairs(h, ctypes.byref(ba.struct), ctypes.byref(p), dummy, npair, dummy, None) == tai.TAI_ERR_NOT_READY
     assert lib.tai_apply_J_pairs(h, dummy, ba.alpha.shape[0], dummy, 3, ctypes.byref(p), dummy, dummy, None) == tai.TAI_ERR_NOT_READY
+
+
+def test_coulomb_mo_argument_checks(hctx):
+    lib, h = hctx.lib, hctx.h
+    dummy = ctypes.c_void_p(16)
+    p = _params()
+    assert lib.tai_coulomb_mo(h, None, 8, None, 0, ctypes.byref(p), dummy, 2, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_coulomb_mo(h, dummy, 8, None, 0, ctypes.byref(p), None, 2, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_coulomb_mo(h, dummy, 8, None, 0, ctypes.byref(p), dummy, 2, None, None) == tai.TAI_ERR_INVALID_ARG
+    for norb in (0, -3, 1025):
+        assert lib.tai_coulomb_mo(h, dummy, 8, None, 0, ctypes.byref(p), dummy, norb, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_coulomb_mo(h, dummy, 0, None, 0, ctypes.byref(p), dummy, 2, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_coulomb_mo(h, dummy, 8, dummy, 0, ctypes.byref(p), dummy, 2, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_coulomb_mo(h, dummy, 8, dummy, 37, ctypes.byref(p), dummy, 2, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    p16 = _params(prec=4)
+    assert lib.tai_coulomb_mo(h, dummy, 8, None, 0, ctypes.byref(p16), dummy, 2, dummy, None) == tai.TAI_ERR_UNSUPPORTED
+    assert lib.tai_coulomb_mo(h, dummy, 8, None, 0, ctypes.byref(p), dummy, 2, dummy, None) == tai.TAI_ERR_NOT_READY
+    assert lib.tai_coulomb_mo(h, dummy, 8, dummy, 36, ctypes.byref(p), dummy, 2, dummy, None) == tai.TAI_ERR_NOT_READY
