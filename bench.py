@@ -10,7 +10,8 @@ the full 80200 x 80200 B, in the headline arithmetic (split FP16, 3 products).
 device.  The same line reports the FP64 / FP32 / BF16 forms of the same step,
 FP64 and FP32 with a degree per quadrature node (the paper's N_i, each
 factor within 1e-8 on the box), the step and the J-build over the pairs that
-screening keeps (prefactor above 1e-12), the batched persistent assembly of 64 molecules (graph replay vs one launch
+screening keeps (prefactor above 1e-12), the orbital-basis Coulomb matrix
+of 16 orbitals at Nb = 1000, the batched persistent assembly of 64 molecules (graph replay vs one launch
 sequence per molecule), the J-build through the grid tensor (Nb = 1000), the
 error of every form against the FP64 oracle on sampled entries, the roofline
 of the dominant kernel, and the oracle timed on the host cores.
@@ -39,6 +40,8 @@ DEGREE_TOL = 1e-8
 # screening threshold of the screened legs: pairs whose Gaussian product
 # prefactor is at most this are dropped
 SCREEN_TAU = 1e-12
+# orbitals of the orbital-basis Coulomb matrix leg
+NORB = 16
 
 
 def log(msg):
@@ -362,7 +365,22 @@ def main():
                       "rel_2norm_vs_unscreened_gpu": float(torch.linalg.matrix_norm(Js - ref, 2) /
                                                            torch.linalg.matrix_norm(ref, 2))}
         japply["screened_fp64"] = screened_j
-        del Mj, Jj, Js, Mjs
+        # the orbital-basis Coulomb matrix of NORB orbitals on the same grid
+        Qo = torch.as_tensor(np.random.default_rng(17).standard_normal((NORB, jb.nb)) / np.sqrt(jb.nb), device=dev)
+        Jmo = torch.empty((NORB, NORB), dtype=torch.float64, device=dev)
+        log(f"orbital-basis Coulomb matrix fp64: norb={NORB}")
+        ctx.moments(jba, jP, Mj)
+        for it in range(W + K):
+            if it == W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            ctx.coulomb_mo(Mj, jb.nb, jparams, Qo, NORB, Jmo)
+        torch.cuda.synchronize()
+        ms_mo = (time.perf_counter() - t0) * 1e3 / K
+        japply["coulomb_mo_fp64"] = {"norb": NORB, "ms_per_call": round(ms_mo, 3),
+                                     "ms_per_orbital": round(ms_mo / NORB, 4),
+                                     "symmetry_rel": float((Jmo - Jmo.T).abs().max() / Jmo.abs().max())}
+        del Mj, Jj, Js, Mjs, Jmo
         torch.cuda.empty_cache()
 
     # ---------------- the device's own sustained peaks ------------------------
