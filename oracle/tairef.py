@@ -299,6 +299,52 @@ def screened_pairs(center, alpha, tau):
     return np.nonzero(pref > tau)[0].astype(np.int64)
 
 
+def contraction_pairs(fmap):
+    """Contracted basis functions (eq. basis, I_mu primitives each): the
+    primitive basis is listed function by function and fmap[i] is the
+    contracted function of primitive i (non-decreasing).  For each primitive
+    pair p = (i, j), i <= j, returns the contracted pair index P = p(fmap[i],
+    fmap[j]) and the weight w_p with which it enters the contracted pair's
+    product g_mu g_nu = sum over ordered (i in mu, j in nu) of g_i g_j: 2 for
+    i != j within one function (both orders), else 1."""
+    fmap = np.asarray(fmap, dtype=np.int64)
+    nb = int(fmap[-1]) + 1
+    i, j = pair_list(len(fmap))
+    P = pair_index(nb, fmap[i], fmap[j])
+    w = np.where((fmap[i] == fmap[j]) & (i != j), 2.0, 1.0)
+    return P, w
+
+
+def contract_pairs(Bp, fmap):
+    """B over contracted pairs from B over primitive pairs:
+    B_c(P, Q) = sum_{p -> P} sum_{q -> Q} w_p w_q Bp(p, q)."""
+    P, w = contraction_pairs(fmap)
+    nb = int(np.asarray(fmap)[-1]) + 1
+    npc = nb * (nb + 1) // 2
+    rows = np.zeros((npc, Bp.shape[1]))
+    np.add.at(rows, P, w[:, None] * Bp)
+    out = np.zeros((npc, npc))
+    np.add.at(out.T, P, w[:, None] * rows.T)
+    return out
+
+
+def expand_density(D, fmap):
+    """Density over the primitives of a contracted basis: D_prim(i, j) =
+    D(fmap[i], fmap[j])."""
+    fmap = np.asarray(fmap, dtype=np.int64)
+    return np.asarray(D, dtype=np.float64)[np.ix_(fmap, fmap)]
+
+
+def contract_functions(Jp, fmap):
+    """nb x nb matrix over contracted functions from one over primitives:
+    J(mu, nu) = sum_{i in mu, j in nu} Jp(i, j)."""
+    fmap = np.asarray(fmap, dtype=np.int64)
+    nb = int(fmap[-1]) + 1
+    F = np.zeros((len(fmap), nb))
+    F[np.arange(len(fmap)), fmap] = 1.0
+    return F.T @ Jp @ F
+
+
 def basis_scale(alpha, lxyz, coef):
     """Per-function scale s_mu and per-direction unit-norm factors.
 
