@@ -231,6 +231,35 @@ int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* par
 int tai_coulomb_mo(tai_ctx* ctx, const double* M, int32_t nb, const int32_t* pairs, int32_t npk,
                    const tai_params* params, const double* Q, int32_t norb, double* Jmo, void* stream);
 
+/* ---- contracted basis functions (eq. basis, I_mu > 1 primitives) ---------- */
+
+/* A contracted basis is passed as its primitives: a tai_basis of nbp
+   primitive functions listed function by function, whose coef holds each
+   primitive's contraction coefficient (times any normalisation wanted), and
+   fmap [nbp] (HOST int32), the contracted function of each primitive:
+   fmap[0] = 0 and each step adds 0 or 1, so nb = fmap[nbp-1] + 1.  Moments
+   and B are formed over the primitive pairs (tai_moments, tai_assemble_B with
+   the primitive basis); the contracted results are segment sums of them. */
+
+/* B over contracted pairs from B over primitive pairs:
+     B[P*ldb + Q] = sum_{p -> P} sum_{q -> Q} w_p w_q Bp[p*ldbp + q],
+   where primitive pair p = (i, j), i <= j, belongs to P = (fmap[i], fmap[j])
+   and w_p = 2 when i != j are primitives of one function (the product
+   g_mu g_mu holds both orders), else 1.  Bp: DEVICE, npair(nbp) rows, ldbp
+   >= npair(nbp); B: DEVICE, npair(nb) x ldb, ldb >= npair(nb); both double
+   if prec == TAI_FP64, else float (sums in FP64).  Writes every entry of B. */
+int tai_contract_pairs(tai_ctx* ctx, const void* Bp, int64_t ldbp, int32_t nbp, const int32_t* fmap, int32_t prec,
+                       void* B, int64_t ldb, void* stream);
+
+/* tai_apply_J for a contracted basis: M is DEVICE double [3][n][npair(nbp)],
+   the moments of the primitive basis; D and J are DEVICE double [nb][nb]
+   over contracted functions.  The density is expanded to the primitives,
+   D_prim(i,j) = D(fmap[i], fmap[j]), J_prim is formed as in tai_apply_J, and
+   J(mu,nu) = sum over primitives i of mu and j of nu of J_prim(i,j).
+   Workspace 2 * nbp^2 doubles. */
+int tai_apply_J_contracted(tai_ctx* ctx, const double* M, int32_t nbp, const int32_t* fmap,
+                           const tai_params* params, const double* D, double* J, void* stream);
+
 /* ---- screening (section 5, compression by screening) --------------------- */
 
 /* Pairs that survive screening: pair p(mu,nu), mu <= nu, is dropped when its

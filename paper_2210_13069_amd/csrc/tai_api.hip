@@ -36,6 +36,9 @@ struct tai_ctx {
   Buf opMu;               // coefficient moments (per-node degrees)
   Buf screen;             // screening: row counts / offsets and the kept count
   Buf mo;                 // orbital-basis Coulomb matrix: rho and Phi of every orbital
+  Buf ct, ct_work;        // contraction: member tables; primitive-basis D and J
+  Buf ct_host;            // pinned staging of the member tables
+  hipEvent_t ct_host_done = nullptr;
   Buf asm_tab, asm_counter;  // 16-bit kernel: device molecule table + items, queue counter
   Buf asm_host;           // pinned staging of the table
   hipEvent_t asm_host_done = nullptr;
@@ -463,7 +466,8 @@ int tai_destroy(tai_ctx* c) {
   if (c->device >= 0) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->screen, &c->mo, &c->asm_tab,
+    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->screen, &c->mo, &c->ct, &c->ct_work,
+                   &c->asm_tab,
                    &c->asm_counter,
                    &c->jwork,
                    &c->b_nodes, &c->b_basis, &c->b_opA, &c->b_opEx, &c->b_opY, &c->b_opMu, &c->b_mols, &c->b_counter})
@@ -471,6 +475,8 @@ int tai_destroy(tai_ctx* c) {
     if (c->host_basis.p) hipHostFree(c->host_basis.p);
     if (c->b_host.p) hipHostFree(c->b_host.p);
     if (c->asm_host.p) hipHostFree(c->asm_host.p);
+    if (c->ct_host.p) hipHostFree(c->ct_host.p);
+    if (c->ct_host_done) hipEventDestroy(c->ct_host_done);
     if (c->asm_host_done) hipEventDestroy(c->asm_host_done);
     if (c->host_basis_done) hipEventDestroy(c->host_basis_done);
     if (c->b_host_done) hipEventDestroy(c->b_host_done);
@@ -1059,6 +1065,108 @@ int tai_coulomb_mo(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs
     e = tai::launch_coulomb_mo(p->prec, M, nb, (int)npair, pairs, n, nq, tb, Q, norb, R, R + n3 * norb, Jmo, w, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "coulomb_mo kernels");
+  return TAI_OK;
+}
+
+// A contraction map: fmap[0] = 0 and each step adds 0 or 1 (primitives listed
+// function by function, every function at least one); returns nb or 0.
+static int32_t contraction_nb(const int32_t* fmap, int32_t nbp) {
+  if (!fmap || nbp < 1 || fmap[0] != 0) return 0;
+  for (int32_t i = 1; i < nbp; ++i)
+    if (fmap[i] != fmap[i - 1] && fmap[i] != fmap[i - 1] + 1) return 0;
+  return fmap[nbp - 1] + 1;
+}
+
+int tai_contract_pairs(tai_ctx* c, const void* Bp, int64_t ldbp, int32_t nbp, const int32_t* fmap, int32_t prec,
+                       void* B, int64_t ldb, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!Bp || !B) return fail(c, TAI_ERR_INVALID_ARG, "Bp or B is NULL");
+  if (nbp < 1 || npair_of(nbp) > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "nbp out of range");
+  const int32_t nb = contraction_nb(fmap, nbp);
+  if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "fmap must start at 0 and step by 0 or 1");
+  const int64_t npp = npair_of(nbp), npc = npair_of(nb);
+  if (ldbp < npp || ldb < npc) return fail(c, TAI_ERR_INVALID_ARG, "ldbp < npair(nbp) or ldb < npair(nb)");
+  if (prec < TAI_FP64 || prec > TAI_F16X3) return fail(c, TAI_ERR_INVALID_ARG, "unknown prec");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // member lists of the contracted pairs (CSR over primitive pairs, row-major order)
+  const size_t tab = align256(sizeof(int32_t) * (npc + 1)) + align256(sizeof(int32_t) * npp) +
+                     align256(sizeof(double) * npp);
+  if ((r = ensure(c, c->ct, tab))) return r;
+  if ((r = ensure_host(c, c->ct_host, c->ct_host_done, tab))) return r;
+  char* hb = static_cast<char*>(c->ct_host.p);
+  int32_t* off = reinterpret_cast<int32_t*>(hb);
+  int32_t* idx = reinterpret_cast<int32_t*>(hb + align256(sizeof(int32_t) * (npc + 1)));
+  double* wt = reinterpret_cast<double*>(hb + align256(sizeof(int32_t) * (npc + 1)) + align256(sizeof(int32_t) * npp));
+  std::vector<int64_t> P(npp);
+  std::fill(off, off + npc + 1, 0);
+  int64_t p = 0;
+  for (int32_t i = 0; i < nbp; ++i)
+    for (int32_t j = i; j < nbp; ++j, ++p) {
+      const int64_t mu = fmap[i], nu = fmap[j];
+      P[p] = mu * nb - mu * (mu - 1) / 2 + (nu - mu);
+      ++off[P[p] + 1];
+    }
+  for (int64_t q = 0; q < npc; ++q) off[q + 1] += off[q];
+  std::vector<int32_t> fill(off, off + npc);
+  p = 0;
+  for (int32_t i = 0; i < nbp; ++i)
+    for (int32_t j = i; j < nbp; ++j, ++p) {
+      const int32_t slot = fill[P[p]]++;
+      idx[slot] = (int32_t)p;
+      wt[slot] = (fmap[i] == fmap[j] && i != j) ? 2.0 : 1.0;
+    }
+  hipError_t e = hipMemcpyAsync(c->ct.p, hb, tab, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(c->ct_host_done, s);
+  if (e != hipSuccess) return hip_fail(c, e, "contraction table upload");
+  char* db = static_cast<char*>(c->ct.p);
+  e = tai::launch_contract_pairs(prec == TAI_FP64, Bp, ldbp, reinterpret_cast<const int32_t*>(db),
+                                 reinterpret_cast<const int32_t*>(db + align256(sizeof(int32_t) * (npc + 1))),
+                                 reinterpret_cast<const double*>(db + align256(sizeof(int32_t) * (npc + 1)) +
+                                                                 align256(sizeof(int32_t) * npp)),
+                                 npc, B, ldb, s);
+  if (e != hipSuccess) return hip_fail(c, e, "contraction kernel");
+  return TAI_OK;
+}
+
+int tai_apply_J_contracted(tai_ctx* c, const double* M, int32_t nbp, const int32_t* fmap, const tai_params* p,
+                           const double* D, double* J, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !D || !J) return fail(c, TAI_ERR_INVALID_ARG, "M, D or J is NULL");
+  if (nbp < 1 || npair_of(nbp) > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "nbp out of range");
+  const int32_t nb = contraction_nb(fmap, nbp);
+  if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "fmap must start at 0 and step by 0 or 1");
+  if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_contracted supports prec TAI_FP64 and TAI_FP32");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // device tables: fmap [nbp], first primitive of each function [nb + 1]
+  const size_t tab = align256(sizeof(int32_t) * nbp) + align256(sizeof(int32_t) * (nb + 1));
+  if ((r = ensure(c, c->ct, tab))) return r;
+  if ((r = ensure_host(c, c->ct_host, c->ct_host_done, tab))) return r;
+  char* hb = static_cast<char*>(c->ct_host.p);
+  std::memcpy(hb, fmap, sizeof(int32_t) * nbp);
+  int32_t* first = reinterpret_cast<int32_t*>(hb + align256(sizeof(int32_t) * nbp));
+  first[0] = 0;
+  for (int32_t i = 1; i < nbp; ++i)
+    if (fmap[i] != fmap[i - 1]) first[fmap[i]] = i;
+  first[nb] = nbp;
+  hipError_t e = hipMemcpyAsync(c->ct.p, hb, tab, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(c->ct_host_done, s);
+  if (e != hipSuccess) return hip_fail(c, e, "contraction table upload");
+  const int32_t* fmap_d = static_cast<const int32_t*>(c->ct.p);
+  const int32_t* first_d = reinterpret_cast<const int32_t*>(static_cast<char*>(c->ct.p) + align256(sizeof(int32_t) * nbp));
+  const size_t nn = (size_t)nbp * nbp;
+  if ((r = ensure(c, c->ct_work, 2 * sizeof(double) * nn))) return r;
+  double* Dp = static_cast<double*>(c->ct_work.p);
+  double* Jp = Dp + nn;
+  if ((e = tai::launch_expand_density(D, nb, fmap_d, nbp, Dp, s)) != hipSuccess) return hip_fail(c, e, "expand density");
+  if ((r = apply_j_impl(c, M, nbp, nullptr, npair_of(nbp), p, Dp, Jp, stream))) return r;
+  if ((e = tai::launch_contract_functions(Jp, nbp, first_d, nb, J, s)) != hipSuccess)
+    return hip_fail(c, e, "contract functions");
   return TAI_OK;
 }
 

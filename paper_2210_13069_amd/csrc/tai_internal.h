@@ -198,6 +198,15 @@ struct JWork {
 int j_nchunk(int prec, int n, int npair);
 size_t j_work_bytes(int prec, int nq, int n, int npair);
 JWork carve_j_work(void* base, int prec, int nq, int n, int npair);
+// Contracted basis functions (k_contract.hip).  B_c[P][Q] = sum over the
+// CSR members a of P and b of Q of wt[a] wt[b] Bp[idx[a]][idx[b]] (double or
+// float matrices, FP64 sums); D_prim[i][j] = D[fmap[i]][fmap[j]];
+// J[mu][nu] = sum of Jp over primitives first[mu] .. first[mu+1] by first[nu] .. first[nu+1].
+hipError_t launch_contract_pairs(bool fp64, const void* Bp, int64_t ldbp, const int32_t* off, const int32_t* idx,
+                                 const double* wt, int64_t npc, void* B, int64_t ldb, hipStream_t s);
+hipError_t launch_expand_density(const double* D, int nb, const int32_t* fmap, int nbp, double* Dp, hipStream_t s);
+hipError_t launch_contract_functions(const double* Jp, int nbp, const int32_t* first, int nb, double* J,
+                                     hipStream_t s);
 // Coulomb matrix in the orbital basis: per orbital i (row i of Q, length nb)
 // the pair density of q_i q_i^T, rho_i -> R[i] and Phi_i -> F[i] (n^3 each),
 // then Jmo[i][j] = sum_a R[i][a] F[j][a].

@@ -29,7 +29,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 # exported symbols declared in include/tai.h
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
            "tai_quadrature", "tai_degrees", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
-           "tai_apply_J_pairs", "tai_coulomb_mo", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
+           "tai_apply_J_pairs", "tai_coulomb_mo", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
            "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched"]
 
@@ -95,6 +95,10 @@ def load_library(path=LIB_PATH):
                                       vp, vp]
     lib.tai_coulomb_mo.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp,
                                    ctypes.c_int32, vp, vp]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.tai_contract_pairs.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, i32p, ctypes.c_int32, vp,
+                                       ctypes.c_int64, vp]
+    lib.tai_apply_J_contracted.argtypes = [vp, vp, ctypes.c_int32, i32p, ctypes.POINTER(tai_params), vp, vp, vp]
     lib.tai_moments.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.POINTER(tai_params), vp, vp]
     lib.tai_assemble_B.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, ctypes.c_int64, vp]
     lib.tai_assemble_B_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(tai_mol), vp]
@@ -208,6 +212,21 @@ class Context:
         p = params if isinstance(params, tai_params) else make_params(params)
         self.check(self.lib.tai_coulomb_mo(self.h, _ptr(M), int(nb), _ptr(pairs), int(npk), ctypes.byref(p), _ptr(Q),
                                            int(norb), _ptr(Jmo), _stream(stream)), "tai_coulomb_mo")
+
+    def contract_pairs(self, Bp, nbp, fmap, prec, B, ldbp=None, ldb=None, stream=None):
+        fm = np.ascontiguousarray(fmap, dtype=np.int32)
+        ldbp = int(Bp.shape[1]) if ldbp is None else ldbp
+        ldb = int(B.shape[1]) if ldb is None else ldb
+        self.check(self.lib.tai_contract_pairs(self.h, _ptr(Bp), int(ldbp), int(nbp),
+                                               fm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(prec), _ptr(B),
+                                               int(ldb), _stream(stream)), "tai_contract_pairs")
+
+    def apply_J_contracted(self, M, nbp, fmap, params, D, J, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        fm = np.ascontiguousarray(fmap, dtype=np.int32)
+        self.check(self.lib.tai_apply_J_contracted(self.h, _ptr(M), int(nbp),
+                                                   fm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(p),
+                                                   _ptr(D), _ptr(J), _stream(stream)), "tai_apply_J_contracted")
 
     def moments(self, basis_arrays, params, M, stream=None):
         p = params if isinstance(params, tai_params) else make_params(params)
@@ -350,3 +369,22 @@ def coulomb_mo(M, nb, Q, params, prec=FP64, pairs=None, device=0):
     context(device).coulomb_mo(M, nb, make_params(params, prec), Q, norb, Jmo, pairs=pairs,
                                npk=0 if pairs is None else int(pairs.shape[0]))
     return Jmo
+
+
+def contract_pairs(Bp, nbp, fmap, prec=FP64, device=0):
+    """B over contracted pairs from B over the primitive pairs (see tai_contract_pairs)."""
+    import torch
+    nb = int(np.asarray(fmap)[-1]) + 1
+    npc = nb * (nb + 1) // 2
+    B = torch.empty((npc, npc), dtype=Bp.dtype, device=Bp.device)
+    context(device).contract_pairs(Bp, nbp, fmap, prec, B)
+    return B
+
+
+def apply_J_contracted(M, nbp, fmap, D, params, prec=FP64, device=0):
+    """J over contracted functions from the primitive moments (see tai_apply_J_contracted)."""
+    import torch
+    nb = int(D.shape[0])
+    J = torch.empty((nb, nb), dtype=torch.float64, device=M.device)
+    context(device).apply_J_contracted(M, nbp, fmap, make_params(params, prec), D, J)
+    return J

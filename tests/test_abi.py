@@ -233,3 +233,28 @@ def test_coulomb_mo_argument_checks(hctx):
     assert lib.tai_coulomb_mo(h, dummy, 8, None, 0, ctypes.byref(p16), dummy, 2, dummy, None) == tai.TAI_ERR_UNSUPPORTED
     assert lib.tai_coulomb_mo(h, dummy, 8, None, 0, ctypes.byref(p), dummy, 2, dummy, None) == tai.TAI_ERR_NOT_READY
     assert lib.tai_coulomb_mo(h, dummy, 8, dummy, 36, ctypes.byref(p), dummy, 2, dummy, None) == tai.TAI_ERR_NOT_READY
+
+
+def test_contraction_argument_checks(hctx):
+    lib, h = hctx.lib, hctx.h
+    dummy = ctypes.c_void_p(16)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+
+    def fm(lst):
+        return (ctypes.c_int32 * len(lst))(*lst)
+
+    good = fm([0, 0, 1, 2, 2])      # nb = 3 from 5 primitives: npair 6 from 15
+    for bad in ([1, 1, 2, 3, 3], [0, 2, 2, 3, 3], [0, 1, 0, 1, 2]):
+        assert lib.tai_contract_pairs(h, dummy, 15, 5, fm(bad), 0, dummy, 6, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_contract_pairs(h, dummy, 15, 5, None, 0, dummy, 6, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_contract_pairs(h, dummy, 14, 5, good, 0, dummy, 6, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_contract_pairs(h, dummy, 15, 5, good, 0, dummy, 5, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_contract_pairs(h, None, 15, 5, good, 0, dummy, 6, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_contract_pairs(h, dummy, 15, 5, good, 9, dummy, 6, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_contract_pairs(h, dummy, 15, 5, good, 0, dummy, 6, None) == tai.TAI_ERR_NOT_READY
+    p = _params()
+    assert lib.tai_apply_J_contracted(h, dummy, 5, fm([0, 1, 1, 3, 3]), ctypes.byref(p), dummy, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_apply_J_contracted(h, None, 5, good, ctypes.byref(p), dummy, dummy, None) == tai.TAI_ERR_INVALID_ARG
+    p16 = _params(prec=4)
+    assert lib.tai_apply_J_contracted(h, dummy, 5, good, ctypes.byref(p16), dummy, dummy, None) == tai.TAI_ERR_UNSUPPORTED
+    assert lib.tai_apply_J_contracted(h, dummy, 5, good, ctypes.byref(p), dummy, dummy, None) == tai.TAI_ERR_NOT_READY

@@ -1,0 +1,85 @@
+"""GPU parity of contracted basis functions (eq. basis with I_mu > 1): B
+over contracted pairs by weighted segment sums of B over the primitive pairs
+(FP64 and a split arithmetic), and J over contracted functions, through the
+C ABI against the oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from oracle import tairef as T
+from paper_2210_13069_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _contracted(seed):
+    """Primitive basis of 6 atoms (two s primitives contracted into one
+    function, three more forming a contracted p shell) and its fmap."""
+    rng = np.random.default_rng(seed)
+    prim = I.random_molecule(rng, 6, 3.0, ["s", "s", "p", "p"], 0.2, 12.0)
+    fmap, f = [], -1
+    for a in range(6):
+        f += 1
+        fmap += [f, f]                 # s s -> one s function
+        base = f
+        for c in range(3):             # p shell 1 and p shell 2 -> one p shell
+            fmap.append(base + 1 + c)
+        for c in range(3):
+            fmap.append(base + 1 + c)
+        f = base + 3
+    # primitives must be listed function by function: reorder p primitives
+    order = []
+    idx = 0
+    for a in range(6):
+        s0 = idx
+        order += [s0, s0 + 1]
+        for c in range(3):
+            order += [s0 + 2 + c, s0 + 5 + c]
+        idx += 8
+    order = np.array(order)
+    prim = I.Basis(prim.center[order], prim.alpha[order], prim.lxyz[order])
+    fmap = np.array(sorted(fmap))
+    coef = rng.uniform(0.3, 1.0, prim.nb)
+    return prim, fmap, coef
+
+
+@pytest.mark.parametrize("prec", [0, 4, 1])
+def test_contract_pairs_matches_oracle(tai, prec):
+    prim, fmap, coef = _contracted(91)
+    P = I.Params(omega=0.4, nq=12, n=24, L=8.0)
+    Mr = T.moments(prim.center, prim.alpha, prim.lxyz, P.L, P.n, coef=coef)
+    t, w = T.time_nodes(P.omega, P.nq)
+    xi, _ = T.cheb_nodes(P.n, P.L)
+    ref = T.contract_pairs(T.B_full(Mr, T.ktables(t, xi), w), fmap)
+    Mg = tai.moments(prim, P, coef=coef)
+    Bp = tai.assemble_B(Mg, P, prec=prec)
+    Bc = tai.contract_pairs(Bp, prim.nb, fmap, prec=prec).cpu().numpy().astype(np.float64)
+    err = np.max(np.abs(Bc - ref)) / np.max(np.abs(ref))
+    assert err <= (1e-10 if prec == 0 else 1e-6), err
+
+
+def test_trivial_contraction_copies(tai):
+    import torch
+    b = I.small_random(92, natoms=2, shells=("s", "p"))
+    rng = np.random.default_rng(1)
+    Bp = torch.as_tensor(rng.standard_normal((b.npair, b.npair)), device="cuda")
+    Bc = tai.contract_pairs(Bp, b.nb, np.arange(b.nb), prec=0)
+    assert torch.equal(Bc, Bp)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_J_contracted_matches_oracle(tai, prec):
+    import torch
+    prim, fmap, coef = _contracted(93)
+    nb = int(fmap[-1]) + 1
+    P = I.Params(omega=0.4, nq=12, n=32, L=8.0)
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((nb, nb))
+    D = A + A.T
+    Mr = T.moments(prim.center, prim.alpha, prim.lxyz, P.L, P.n, coef=coef)
+    t, w = T.time_nodes(P.omega, P.nq)
+    xi, _ = T.cheb_nodes(P.n, P.L)
+    ref = T.contract_functions(T.J_grid(Mr, T.ktables(t, xi), w, T.expand_density(D, fmap)), fmap)
+    Mg = tai.moments(prim, P, coef=coef)
+    J = tai.apply_J_contracted(Mg, prim.nb, fmap, torch.as_tensor(D, device=Mg.device), P, prec=prec).cpu().numpy()
+    err = np.linalg.norm(J - ref, 2) / np.linalg.norm(ref, 2)
+    assert err <= (1e-10 if prec == 0 else 1e-6), err
