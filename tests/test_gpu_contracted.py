@@ -83,3 +83,28 @@ def test_apply_J_contracted_matches_oracle(tai, prec):
     J = tai.apply_J_contracted(Mg, prim.nb, fmap, torch.as_tensor(D, device=Mg.device), P, prec=prec).cpu().numpy()
     err = np.linalg.norm(J - ref, 2) / np.linalg.norm(ref, 2)
     assert err <= (1e-10 if prec == 0 else 1e-6), err
+
+
+def test_contract_everything_into_one_function(tai):
+    """Every primitive (all s, one centre) in one contracted function: B is
+    1 x 1, J is 1 x 1."""
+    import torch
+    rng = np.random.default_rng(94)
+    nbp = 5
+    prim = I.Basis(np.zeros((nbp, 3)) + 0.3, np.exp(rng.uniform(np.log(0.3), np.log(9.0), nbp)),
+                   np.zeros((nbp, 3), dtype=np.int32))
+    fmap = np.zeros(nbp, dtype=np.int64)
+    coef = rng.uniform(0.2, 1.0, nbp)
+    P = I.Params(omega=0.5, nq=8, n=16, L=6.0)
+    Mr = T.moments(prim.center, prim.alpha, prim.lxyz, P.L, P.n, coef=coef)
+    t, w = T.time_nodes(P.omega, P.nq)
+    xi, _ = T.cheb_nodes(P.n, P.L)
+    K = T.ktables(t, xi)
+    ref = T.contract_pairs(T.B_full(Mr, K, w), fmap)
+    Mg = tai.moments(prim, P, coef=coef)
+    Bc = tai.contract_pairs(tai.assemble_B(Mg, P, prec=0), nbp, fmap, prec=0).cpu().numpy()
+    assert Bc.shape == (1, 1) and abs(Bc[0, 0] - ref[0, 0]) <= 1e-10 * abs(ref[0, 0])
+    D = np.array([[0.7]])
+    Jref = T.contract_functions(T.J_grid(Mr, K, w, T.expand_density(D, fmap)), fmap)
+    J = tai.apply_J_contracted(Mg, nbp, fmap, torch.as_tensor(D, device=Mg.device), P).cpu().numpy()
+    assert abs(J[0, 0] - Jref[0, 0]) <= 1e-10 * abs(Jref[0, 0])

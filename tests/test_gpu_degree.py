@@ -155,3 +155,19 @@ def test_assemble_with_degrees_inner_lengths(tai, n, nq):
         Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
         tol = 1e-10 if prec == 0 else LOWP_TOL[prec]
         assert _normwise(Bg, Br) <= tol, (n, nq, prec, _normwise(Bg, Br))
+
+
+@pytest.mark.parametrize("prec", [0, 1, 4])
+def test_degrees_all_one(tai, prec):
+    """A tolerance so loose that every node keeps only the constant term:
+    N_k = 1 everywhere, one inner chunk per node in the FP64/FP32 kernels."""
+    b = I.small_random(53, natoms=3, shells=("s", "p"), box=2.0)
+    P = I.Params(omega=0.5, nq=6, n=16, L=6.0, degree_tol=1e3)
+    N, _, Kt, w = _oracle_tables(P)
+    assert np.all(N == 1)
+    nk, _ = tai.degrees(P)
+    assert np.all(nk.cpu().numpy() == 1)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
+    Br = T.B_full(Mr, Kt, w)
+    Bg = tai.assemble_B(tai.moments(b, P), P, prec=prec).cpu().numpy().astype(np.float64)
+    assert _normwise(Bg, Br) <= (1e-10 if prec == 0 else LOWP_TOL[prec])

@@ -115,3 +115,20 @@ def test_screened_J_full_size_close_to_unscreened(tai):
     Js = tai.apply_J_pairs(tai.moments_pairs(b, P, pairs), Dg, pairs, P)
     rel = float(torch.linalg.matrix_norm(Js - Jf, 2) / torch.linalg.matrix_norm(Jf, 2))
     assert rel <= 1e-9, rel
+
+
+def test_screen_keeps_only_diagonal(tai):
+    """tau just below 1 keeps exactly the nb diagonal pairs of well separated
+    functions; B over them in FP64 against the oracle."""
+    b = I.small_random(75, natoms=4, shells=("s",), box=6.0, alpha_lo=2.0, alpha_hi=8.0)
+    pairs = tai.screen_pairs(b, 0.999999)
+    kept = pairs.cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(kept, T.screened_pairs(b.center, b.alpha, 0.999999))
+    np.testing.assert_array_equal(kept, [T.pair_index(b.nb, m, m) for m in range(b.nb)])
+    P = I.Params(omega=0.5, nq=8, n=16, L=10.0)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, pairs=kept)
+    t, w = T.time_nodes(P.omega, P.nq)
+    xi, _ = T.cheb_nodes(P.n, P.L)
+    Br = T.B_full(Mr, T.ktables(t, xi), w)
+    Bg = tai.assemble_B(tai.moments_pairs(b, P, pairs), P, prec=0).cpu().numpy()
+    assert np.max(np.abs(Bg - Br)) <= 1e-10 * np.max(np.abs(Br))
