@@ -100,9 +100,9 @@ __device__ inline void tile_elem(int prec, int side, double x, int n, int a, uin
     put16(row, seg_pos(prec, n, 2, a), side ? s0 : s1);
     if (prec == kBF16X6) {
       const __bf16 s2 = to_slice<__bf16>(r1 - (double)(float)s1);
-      put16(row, 3 * n + a, side ? s2 : s0);
-      put16(row, 4 * n + a, s1);
-      put16(row, 5 * n + a, side ? s0 : s2);
+      put16(row, seg_pos(prec, n, 3, a), side ? s2 : s0);
+      put16(row, seg_pos(prec, n, 4, a), s1);
+      put16(row, seg_pos(prec, n, 5, a), side ? s0 : s2);
     }
   }
 }

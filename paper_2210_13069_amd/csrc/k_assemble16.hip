@@ -51,7 +51,7 @@ template <int KC, int Q, int NW, int RB, int CB, int NBUF, int NPS = 1>
 struct Cfg16 {
   static constexpr int KC_ = KC, Q_ = Q, NW_ = NW, RB_ = RB, CB_ = CB, NBUF_ = NBUF, NPS_ = NPS;
   static constexpr int NCH = KC / 32;                    // 32-wide inner chunks
-  static constexpr int U = NCH - Q;                      // distinct A fragments
+  static constexpr int U = Q >= kX6Key ? NCH - 3 * (Q - kX6Key) : NCH - Q;  // distinct A fragments
   static constexpr int NT = 64 * NW;                     // threads per work group
   static constexpr int ROWS = 16 * RB * NW;              // rows per panel
   static constexpr int COLS = 16 * CB;                   // columns per block
@@ -68,10 +68,27 @@ struct Cfg16 {
   static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
-// A fragment register index of MFMA chunk ch (chunks Q..2Q-1 repeat 0..Q-1),
-// and the K chunk a register fragment is loaded from.
-template <int Q> __device__ constexpr int a_slot(int ch) { return ch < Q ? ch : ch - Q; }
-template <int Q> __device__ constexpr int a_chunk(int u) { return u < Q ? u : u + Q; }
+// A fragment register index of MFMA chunk ch, and the K chunk a register
+// fragment is loaded from.  X3 layouts: chunks Q..2Q-1 repeat 0..Q-1.  BF16X6
+// layouts (Q = kX6Key + Q6): in range r < Q6 the six segment chunks 6r + s
+// use fragments 3r + {0, 0, 1, 0, 1, 2}[s]; later chunks follow.
+template <int Q> __device__ constexpr int a_slot(int ch) {
+  if constexpr (Q >= kX6Key) {
+    constexpr int Q6 = Q - kX6Key;
+    return ch < 6 * Q6 ? 3 * (ch / 6) + (ch % 6 == 5 ? 2 : (ch % 6 == 2 || ch % 6 == 4) ? 1 : 0)
+                       : 3 * Q6 + (ch - 6 * Q6);
+  } else {
+    return ch < Q ? ch : ch - Q;
+  }
+}
+template <int Q> __device__ constexpr int a_chunk(int u) {
+  if constexpr (Q >= kX6Key) {
+    constexpr int Q6 = Q - kX6Key;
+    return u < 3 * Q6 ? 6 * (u / 3) + (u % 3 == 0 ? 0 : (u % 3 == 1 ? 2 : 5)) : 6 * Q6 + (u - 3 * Q6);
+  } else {
+    return u < Q ? u : u + Q;
+  }
+}
 
 template <int N>
 __device__ inline void wait_vmcnt() {
@@ -483,7 +500,14 @@ const ShapeEntry kShapes[] = {
     TAI_S16(160, 1, 8, 2, 2, 3),  TAI_S16(160, 1, 8, 3, 1, 3),
     TAI_S16(192, 0, 8, 2, 2, 2),  TAI_S16(192, 0, 8, 1, 2, 3),
     TAI_S16(192, 1, 8, 2, 2, 2),  TAI_S16(192, 2, 8, 2, 2, 2),
+    TAI_S16P(192, kX6Key + 1, 8, 4, 1, 2, 2),
+    TAI_S16(192, kX6Key + 1, 8, 4, 1, 3), TAI_S16(192, kX6Key + 1, 8, 3, 1, 3),
     TAI_S16(224, 0, 8, 1, 2, 2),  TAI_S16(256, 0, 8, 1, 2, 2),
+    TAI_S16P(256, kX6Key + 1, 8, 2, 1, 2, 2),
+    TAI_S16(256, kX6Key + 1, 8, 2, 1, 3), TAI_S16(256, kX6Key + 1, 8, 2, 1, 2),
+    TAI_S16P(288, kX6Key + 1, 8, 2, 1, 2, 2),
+    TAI_S16(288, kX6Key + 1, 8, 2, 1, 3), TAI_S16(288, kX6Key + 1, 8, 1, 2, 2),
+    TAI_S16(352, kX6Key + 1, 8, 1, 1, 2),
     TAI_S16(288, 0, 8, 1, 2, 2),  TAI_S16(320, 0, 8, 1, 2, 2),
     TAI_S16(352, 0, 8, 1, 1, 2),
 };

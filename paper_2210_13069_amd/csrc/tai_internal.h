@@ -78,11 +78,27 @@ int operand_kc(int prec, int n);
 // operand then has Q pairs of identical MFMA fragments, which the 16-bit
 // kernel keeps in registers once.  Any such permutation of K, applied to A
 // and Y alike, leaves every inner product unchanged.
+//
+// BF16X6 (A = [s0|s0|s1|s0|s1|s2], Y = [s0|s1|s0|s2|s1|s0]) with n % 8 == 0
+// and n >= 32 takes the same idea with six segments: each of the first
+// n / 32 full 32-index ranges r comes as six chunks, segment 0 .. 5 of its
+// indices; chunks 6r, 6r+1, 6r+3 of A are then equal (s0), and 6r+2, 6r+4
+// (s1), so A has three distinct fragments per range.  The remaining indices
+// follow in groups of 8, the six segments of a group side by side.  Its
+// shape key is kX6Key + n / 32.
+constexpr int kX6Key = 100;
 __host__ __device__ inline int operand_dup_chunks(int prec, int n) {
-  return ((prec == kBF16X3 || prec == kF16X3) && n % 8 == 0) ? n / 32 : 0;
+  if ((prec == kBF16X3 || prec == kF16X3) && n % 8 == 0) return n / 32;
+  if (prec == kBF16X6 && n % 8 == 0 && n >= 32) return kX6Key + n / 32;
+  return 0;
 }
 __host__ __device__ inline int seg_pos(int prec, int n, int s, int a) {
   const int Q = operand_dup_chunks(prec, n);
+  if (Q >= kX6Key) {
+    const int Q6 = Q - kX6Key, g = a >> 3, o = a & 7;
+    const int p = g < 4 * Q6 ? 24 * (g >> 2) + 4 * s + (g & 3) : 24 * Q6 + 6 * (g - 4 * Q6) + s;
+    return 8 * p + o;
+  }
   if (Q == 0) return s * n + a;
   const int G = n / 8, g = a >> 3, o = a & 7;
   int p;

@@ -362,3 +362,33 @@ def test_assemble_and_J_edge_cases(tai, case):
         Jg = tai.apply_J(Mg, torch.as_tensor(D, device=Mg.device), P, prec=prec).cpu().numpy()
         err = np.linalg.norm(Jg - Jr) / np.linalg.norm(Jr)
         assert err <= tol, (case, prec, err)
+
+
+@pytest.mark.parametrize("n", [24, 32, 40, 48, 56])
+def test_bf16x6_layouts_and_shapes(tai, n):
+    """BF16X6 at every operand layout: segment-major (n = 24) and the
+    duplicated-chunk layout with and without index tails (32, 40, 48, 56:
+    inner lengths 192, 256, 288, 352); every compiled shape of the inner
+    length gives the same bits and matches the oracle; odd node counts take
+    the three-deep rings."""
+    import os
+    b = I.small_random(47, natoms=5, shells=("s", "p", "d"), box=3.0, alpha_lo=0.2, alpha_hi=10.0)
+    for nq in (7, 8):
+        P = I.Params(omega=0.5, nq=nq, n=n, L=8.0)
+        Mr, K, w = _oracle(b, P)
+        Br = T.B_full(Mr, K, w)
+        Mg = tai.moments(b, P)
+        old = os.environ.get("TAI_ASM16_SHAPE")
+        try:
+            outs = []
+            for pick in range(4):
+                os.environ["TAI_ASM16_SHAPE"] = str(pick)
+                outs.append(tai.assemble_B(Mg, P, prec=3).cpu().numpy())
+        finally:
+            if old is None:
+                os.environ.pop("TAI_ASM16_SHAPE", None)
+            else:
+                os.environ["TAI_ASM16_SHAPE"] = old
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+        assert _normwise(outs[0].astype(np.float64), Br) <= LOWP_TOL[3], (n, nq, _normwise(outs[0], Br))
