@@ -460,13 +460,14 @@ __device__ inline void with_count(int v, F&& f) {
 
 // DEG: the operands are in coefficient form and node k contracts only its
 // first ceil(N_k / chunk) inner chunks (the Y rows beyond N_k are zero).
-template <class Op, int KC, int WN, int PD, bool DEG = false>
+template <class Op, int KC, int WN, int PD, bool DEG = false, int WM = 2>
 __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
   using T = typename ElemOf<Op>::T;
   using Acc = typename Op::Acc;
   using Frag = typename Op::Frag;
-  // 64 x 64 tile; waves 2 x (4 / WN), each 32 rows x 16*WN columns
-  constexpr int WM = 2, TILE = 64, WC = 4 / WN, NCK = KC / Op::kChunk, NSTEP = 3 * NCK;
+  // 64 x 64 tile; waves (4 / WM) x (4 / WN), each 16*WM rows x 16*WN columns
+  constexpr int TILE = 64, WC = 4 / WN, NCK = KC / Op::kChunk, NSTEP = 3 * NCK;
+  static_assert(WM == 2 || WM == 4, "rows per wave");
   static_assert(KC % Op::kChunk == 0, "inner length");
   constexpr bool kF64 = sizeof(T) == 8;
   const int lane = threadIdx.x & 63;
@@ -643,16 +644,21 @@ __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
   }
 }
 
-// WN = 2: four waves of 32 x 32; WN = 1: eight waves of 32 x 16 (half the
-// accumulator registers per wave, for the FP64 operands of the longer inner
-// lengths).  Two waves per SIMD either way.
-template <class Op, int KC, int WN, bool DEG>
-__global__ void __launch_bounds__(512 / WN, WN)
+// Wave tiles of (16 WM) x (16 WN) in a 64 x 64 tile: WM 2, WN 2: four waves
+// of 32 x 32; WM 2, WN 1: eight waves of 32 x 16 (half the accumulator
+// registers per wave, for the FP64 operands of the longer inner lengths);
+// WM 4, WN 1: four waves of 64 x 16 (each Y fragment feeds four MFMAs).  Two
+// waves per SIMD in every form.
+template <int WM, int WN>
+constexpr int as_threads() { return 64 * (4 / WM) * (4 / WN); }
+
+template <class Op, int KC, int WN, bool DEG, int WM>
+__global__ void __launch_bounds__((as_threads<WM, WN>()), (512 / as_threads<WM, WN>()))
 assemble_as_kernel(AsmMol m) {
   int I, J;
   decode_tile(m.tiles, blockIdx.x, I, J);
   // FP32 MFMAs take half the cycles of FP64 ones: look two steps ahead
-  assemble_tile_as<Op, KC, WN, sizeof(typename ElemOf<Op>::T) == 8 ? 1 : 2, DEG>(m, I, J);
+  assemble_tile_as<Op, KC, WN, sizeof(typename ElemOf<Op>::T) == 8 ? 1 : 2, DEG, WM>(m, I, J);
 }
 
 template <class Op, int WM, int WN>
@@ -695,11 +701,11 @@ assemble_queue_kernel(const AsmMol* __restrict__ mols, int nmol, int64_t nitems,
                    [](const AsmMol& m, int I, int J) { assemble_tile<Op, WM, WN>(m, I, J); });
 }
 
-template <class Op, int KC, int WN, bool DEG>
-__global__ void __launch_bounds__(512 / WN, WN)
+template <class Op, int KC, int WN, bool DEG, int WM>
+__global__ void __launch_bounds__((as_threads<WM, WN>()), (512 / as_threads<WM, WN>()))
 assemble_as_queue_kernel(const AsmMol* __restrict__ mols, int nmol, int64_t nitems, unsigned* counter) {
   drain_tile_queue(mols, nmol, nitems, counter, [](const AsmMol& m, int I, int J) {
-    assemble_tile_as<Op, KC, WN, sizeof(typename ElemOf<Op>::T) == 8 ? 1 : 2, DEG>(m, I, J);
+    assemble_tile_as<Op, KC, WN, sizeof(typename ElemOf<Op>::T) == 8 ? 1 : 2, DEG, WM>(m, I, J);
   });
 }
 
@@ -862,10 +868,14 @@ hipError_t launch_project(int prec, const double* M, int n, int npair, int prow,
 }
 
 // FP64 uses the eight-wave form from inner length 32 on (the four-wave form
-// spills there), FP32 the four-wave form throughout.
+// spills there); FP32 the four waves of 64 x 16.
 template <class Op, int KC>
 constexpr int as_wn() {
-  return (sizeof(typename ElemOf<Op>::T) == 8 && KC >= 32) ? 1 : 2;
+  return sizeof(typename ElemOf<Op>::T) == 8 ? (KC >= 32 ? 1 : 2) : 1;
+}
+template <class Op, int KC>
+constexpr int as_wm() {
+  return sizeof(typename ElemOf<Op>::T) == 8 ? 2 : 4;
 }
 
 // grid: tiles (one work group each), or, for the queue form, work groups
@@ -873,13 +883,14 @@ constexpr int as_wn() {
 template <class Op, int KC, bool DEG>
 void launch_as_kc(const dim3& grid, const AsmMol* mols, int nmol, int64_t nitems, unsigned* counter,
                   const AsmMol& m, bool queue, hipStream_t s) {
-  constexpr int WN = as_wn<Op, KC>();
-  const dim3 block(512 / WN);
+  constexpr int WN = as_wn<Op, KC>(), WM = as_wm<Op, KC>(), NT = as_threads<WM, WN>();
+  const dim3 block(NT);
   if (queue) {
-    const dim3 g(WN == 1 ? (grid.x + 1) / 2 : grid.x);
-    hipLaunchKernelGGL((assemble_as_queue_kernel<Op, KC, WN, DEG>), g, block, 0, s, mols, nmol, nitems, counter);
+    // grid.x counts 256-thread work groups
+    const dim3 g((unsigned)(((int64_t)grid.x * 256 + NT - 1) / NT));
+    hipLaunchKernelGGL((assemble_as_queue_kernel<Op, KC, WN, DEG, WM>), g, block, 0, s, mols, nmol, nitems, counter);
   } else {
-    hipLaunchKernelGGL((assemble_as_kernel<Op, KC, WN, DEG>), grid, block, 0, s, m);
+    hipLaunchKernelGGL((assemble_as_kernel<Op, KC, WN, DEG, WM>), grid, block, 0, s, m);
   }
 }
 
