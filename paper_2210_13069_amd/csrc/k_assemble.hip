@@ -118,14 +118,19 @@ __device__ inline void tile_pad(int prec, int n, int kc, uint32_t* row) {
   }
 }
 
-// Copy the LDS tile of kRowsPerTile rows to dst (rows contiguous, kc elements each).
+// Copy the LDS tile of kRowsPerTile rows to dst (rows contiguous, kc elements
+// each) in 16-byte stores: a row is kc * es bytes, a multiple of 16 for every
+// operand format (kc is a multiple of 8, or of 32 for the 16-bit slices), and
+// dst is 16-byte aligned.
 __device__ inline void tile_store(int prec, int kc, const uint32_t* tile, int stride_w, uint32_t* __restrict__ dst) {
   const int es = prec == kFP64 ? 8 : (prec == kFP32 ? 4 : 2);
-  const int wpr = kc * es / 4;
-  const int total = kRowsPerTile * wpr;
-  for (int w = threadIdx.x; w < total; w += blockDim.x) {
-    const int r = w / wpr, j = w - r * wpr;
-    dst[w] = tile[r * stride_w + j];
+  const int qpr = kc * es / 16;  // 16-byte quads per row
+  const int total = kRowsPerTile * qpr;
+  uint4* __restrict__ dst4 = reinterpret_cast<uint4*>(dst);
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int r = e / qpr, q = e - r * qpr;
+    const uint32_t* src = tile + r * stride_w + 4 * q;
+    dst4[e] = uint4{src[0], src[1], src[2], src[3]};
   }
 }
 
