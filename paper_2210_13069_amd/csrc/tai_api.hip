@@ -301,10 +301,18 @@ bool use16(tai_ctx* c, int prec, int n, int nq) {
   return shape16(c, prec, n, nq).id >= 0;
 }
 
+// Whether FP32 assembly takes the persistent LDS-ring kernel (k_assemble32),
+// for the inner lengths it is built for (it skips each node's unused inner
+// steps with per-node degrees too).
+bool use32(int prec, int n) {
+  return prec == tai::kFP32 && tai::operand_kc(prec, n) <= tai::kAsm32MaxKc && !std::getenv("TAI_FP32_TILE");
+}
+
 int prow_of(tai_ctx* c, int prec, int n, int nq, int64_t npair) {
   int64_t t = 256;
-  if (use16(c, prec, n, nq)) {
-    const int64_t r = shape16(c, prec, n, nq).rows;
+  const bool p16 = use16(c, prec, n, nq), p32 = use32(prec, n);
+  if (p16 || p32) {
+    const int64_t r = p16 ? shape16(c, prec, n, nq).rows : tai::asm32_rows(tai::operand_kc(prec, n));
     int64_t a = r, b = 256;
     while (b) {
       const int64_t tmp = a % b;
@@ -704,10 +712,12 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
   m.tiles = prow / tai::assemble_tile(prec);
   m.tile0 = 0;
   m.nk = deg ? tb.nk : nullptr;
-  if (use16(c, prec, n, nq)) {
+  const bool p16 = use16(c, prec, n, nq), p32 = !p16 && use32(prec, n);
+  if (p16 || p32) {
     Items16 items;
-    const tai::Asm16Shape sh = shape16(c, prec, n, nq);
-    items.add(0, npair, sh.rows, sh.cols);
+    const tai::Asm16Shape sh = p16 ? shape16(c, prec, n, nq) : tai::Asm16Shape{};
+    if (p16) items.add(0, npair, sh.rows, sh.cols);
+    else items.add(0, npair, tai::asm32_rows(m.kc), tai::kAsm32Cols);
     const size_t tab_bytes = align256(sizeof(tai::AsmMol)) + items.bytes();
     if ((r = ensure(c, c->asm_tab, tab_bytes))) return r;
     if ((r = ensure(c, c->asm_counter, 256))) return r;
@@ -721,15 +731,18 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
     unsigned* counter = static_cast<unsigned*>(c->asm_counter.p);
     if ((e = tai::launch_reset_counter(counter, s)) != hipSuccess) return hip_fail(c, e, "reset kernel");
     const int nitems = (int)items.count();
-    const int nblocks = std::min(nitems, (c->cus > 0 ? c->cus : 256) * sh.wgs_per_cu);
+    const int nblocks = std::min(nitems, (c->cus > 0 ? c->cus : 256) * (p16 ? sh.wgs_per_cu : 1));
     const auto* mols_dev = static_cast<const tai::AsmMol*>(c->asm_tab.p);
     const char* tab = static_cast<const char*>(c->asm_tab.p) + align256(sizeof(tai::AsmMol));
     const auto* seg_dev = reinterpret_cast<const int*>(tab);
     const auto* items_dev = reinterpret_cast<const int4*>(tab + Items16::seg_bytes());
     {
       Timed tm(c, kStAssemble, s);
-      e = tai::launch_assemble16(prec, m.kc, tai::operand_dup_chunks(prec, n), sh, mols_dev, items_dev, seg_dev,
-                                 counter, nblocks, s);
+      if (p16)
+        e = tai::launch_assemble16(prec, m.kc, tai::operand_dup_chunks(prec, n), sh, mols_dev, items_dev, seg_dev,
+                                   counter, nblocks, s);
+      else
+        e = tai::launch_assemble32(m.kc, deg, mols_dev, items_dev, seg_dev, counter, nblocks, s);
     }
   } else {
     Timed tm(c, kStAssemble, s);
@@ -845,18 +858,21 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   // the 16-bit kernel drains (molecule, row panel, column range) items,
   // largest molecules first so the tail of the queue holds small items
   const bool split16 = use16(c, prec, n, nq);
+  const bool fp32p = !split16 && use32(prec, n);
   Items16 items16;
   const tai::Asm16Shape sh16 = split16 ? shape16(c, prec, n, nq) : tai::Asm16Shape{};
-  if (split16) {
+  if (split16 || fp32p) {
     std::vector<int> order(nmol);
     for (int i = 0; i < nmol; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return am[a].npair > am[b].npair; });
-    for (int i : order) items16.add(i, am[i].npair, sh16.rows, sh16.cols);
+    const int kc = tai::operand_kc(prec, n);
+    for (int i : order)
+      items16.add(i, am[i].npair, split16 ? sh16.rows : tai::asm32_rows(kc), split16 ? sh16.cols : tai::kAsm32Cols);
   }
   // device tables: [AsmMol x nmol | PrepMol x nmol | items]
   const size_t off_prep = align256(sizeof(tai::AsmMol) * nmol);
   const size_t off_items = off_prep + align256(sizeof(tai::PrepMol) * nmol);
-  const size_t tab_bytes = off_items + (split16 ? items16.bytes() : 0);
+  const size_t tab_bytes = off_items + (split16 || fp32p ? items16.bytes() : 0);
   if ((r = ensure(c, c->b_mols, tab_bytes))) return r;
   std::vector<tai::PrepMol> prep(nmol);
   int64_t max_npair = 0;
@@ -887,7 +903,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   for (int i = 0; i < nmol; ++i) pack_basis_host(&mols[i].basis, hb + off_basis[i]);
   std::memcpy(hb + sz_basis, am.data(), sizeof(tai::AsmMol) * nmol);
   std::memcpy(hb + sz_basis + off_prep, prep.data(), sizeof(tai::PrepMol) * nmol);
-  if (split16) items16.write(hb + sz_basis + off_items);
+  if (split16 || fp32p) items16.write(hb + sz_basis + off_items);
   hipError_t e = hipMemcpyAsync(c->b_basis.p, hb, sz_basis, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->b_mols.p, hb + sz_basis, tab_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(c->b_host_done, s);
@@ -908,12 +924,13 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     err = tai::launch_reset_counter(counter, st);
     if (err != hipSuccess) return err;
     const auto* mols_dev = static_cast<const tai::AsmMol*>(c->b_mols.p);
-    if (split16) {
+    if (split16 || fp32p) {
       const char* tab = static_cast<const char*>(c->b_mols.p) + off_items;
       const auto* seg_dev = reinterpret_cast<const int*>(tab);
       const auto* items_dev = reinterpret_cast<const int4*>(tab + Items16::seg_bytes());
       const int ni = (int)items16.count();
-      const int blocks = std::min(ni, (c->cus > 0 ? c->cus : 256) * sh16.wgs_per_cu);
+      const int blocks = std::min(ni, (c->cus > 0 ? c->cus : 256) * (split16 ? sh16.wgs_per_cu : 1));
+      if (fp32p) return tai::launch_assemble32(am[0].kc, any_degree, mols_dev, items_dev, seg_dev, counter, blocks, st);
       return tai::launch_assemble16(prec, am[0].kc, tai::operand_dup_chunks(prec, n), sh16, mols_dev, items_dev,
                                     seg_dev, counter, blocks, st);
     }

@@ -199,6 +199,16 @@ hipError_t launch_assemble16(int prec, int kc, int q, const Asm16Shape& shape, c
                              hipStream_t s);
 inline bool is_split16(int prec) { return prec == kBF16X3 || prec == kBF16X6 || prec == kF16X3; }
 
+// FP32 persistent kernel (k_assemble32.hip): the same items and queues as the
+// 16-bit kernel, panels of asm32_rows(kc) rows, column blocks of 16; one work
+// group of eight waves per CU.  kc a multiple of 8 up to 64.
+constexpr int kAsm32Cols = 16;
+constexpr int kAsm32MaxKc = 64;
+int asm32_rows(int kc);
+// deg: the molecules may carry per-node degrees (AsmMol::nk).
+hipError_t launch_assemble32(int kc, bool deg, const AsmMol* mols_dev, const int4* items_dev, const int* seg_dev,
+                             unsigned* counters, int nblocks, hipStream_t s);
+
 // ---- Coulomb matrix through the grid tensor --------------------------------
 
 struct JWork {
