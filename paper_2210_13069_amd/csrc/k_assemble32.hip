@@ -277,6 +277,205 @@ assemble32_kernel(const AsmMol* __restrict__ mols, const int4* __restrict__ item
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 form (v_mfma_f64_16x16x4f64): the same persistent design with 1 KB
+// fragments of two doubles per lane (dwordx4 loads), two MFMAs per fragment,
+// so inner lengths that are multiples of 8 run without padding.  Products
+// and sums are FP64 throughout, as in the FP64 tile kernel; the accumulators
+// stay in registers and no exponent scaling applies.
+// ---------------------------------------------------------------------------
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int KC, int RB>
+struct Cfg64 {
+  static constexpr int KC_ = KC, RB_ = RB, NW = kNW32;
+  static constexpr int NCH = KC / 8;                   // 1 KB fragments per direction (8 inner indices)
+  static constexpr int NT = 64 * NW;
+  static constexpr int ROWS = 16 * RB * NW;
+  static constexpr int COLS = 16;
+  static constexpr int NFRAG = 3 * NCH;
+  static constexpr int LPW = (NFRAG + NW - 1) / NW;
+  static_assert(KC % 8 == 0, "inner length");
+  static_assert(2 * NFRAG * 1024 <= 160 * 1024, "LDS");
+};
+
+template <class C, bool DEG>
+__device__ inline void run_item64(const AsmMol& m, int rp, int cb0, int cb1, uint4* yb0, uint4* yb1) {
+  constexpr int RB = C::RB_, NCH = C::NCH, NW = C::NW, NFRAG = C::NFRAG, LPW = C::LPW, ROWS = C::ROWS;
+  constexpr int COLS = C::COLS;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int64_t prow = m.prow;
+  const int64_t row_wg = (int64_t)rp * ROWS;
+  const int64_t row_base = row_wg + wave * 16 * RB;
+  const double* __restrict__ Ad = static_cast<const double*>(m.A);
+  const char* __restrict__ Yb = static_cast<const char*>(m.Y);
+  const int nq = m.nq;
+  const int64_t ldb = m.ldb;
+  const int npair32 = (int)m.npair;
+  const int nblk = cb1 - cb0;
+  const int64_t col_first = (int64_t)cb0 * COLS;
+
+  // k-invariant A operand: lane l holds A_d[row][8 ch + 2 (l/16) + {0, 1}]
+  v2d af[3][RB][NCH];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        af[d][rb][ch] = *(const __attribute__((address_space(1))) v2d*)(
+            Ad + ((int64_t)d * prow + row_base + 16 * rb + r16) * C::KC_ + 8 * ch + 2 * kg);
+
+  const int64_t node_bytes = 3 * prow * C::KC_ * 8;
+  const int64_t block_bytes = (int64_t)COLS * C::KC_ * 8;
+  uint32_t off[LPW];
+#pragma unroll
+  for (int i = 0; i < LPW; ++i) {
+    int f = wave + NW * i;
+    f = f < NFRAG ? f : 0;
+    const int d = f / NCH, ch = f % NCH;
+    off[i] = (uint32_t)((((int64_t)d * prow + col_first + r16) * C::KC_ + 8 * ch + 2 * kg) * 8);
+  }
+  const int T = nblk * nq;
+  const int32_t* __restrict__ nkp = DEG ? m.nk : nullptr;
+  auto steps_of = [&](int node) { return (DEG && nkp) ? (nkp[node] + 7) / 8 : NCH; };
+  int ib = 0, ik = 0;
+  auto issue_next = [&](uint4* buf) {
+    const char* base = Yb + ik * node_bytes + ib * block_bytes;
+    const int nch = steps_of(ik);
+#pragma unroll
+    for (int i = 0; i < LPW; ++i) {
+      const int f = wave + NW * i;
+      if (f < NFRAG && f % NCH < nch)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(base + off[i]), (lds_ptr_t)(buf + f * 64), 16,
+                                         0, 0);
+    }
+    if (++ik == nq) {
+      ik = 0;
+      ++ib;
+    }
+  };
+  issue_next(yb0);
+
+  v4d acc[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) acc[rb] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  typedef __attribute__((address_space(1))) double gdouble;
+  gdouble* Bd = (gdouble*)static_cast<double*>(m.B);
+  // lane l holds column col0 + l%16 and rows kg + 4 r of each 16-row block
+  auto finish_block = [&](int fb) {
+    const int64_t colu = col_first + (int64_t)fb * COLS;
+    const int col = (int)colu + r16;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int64_t rowu = row_wg + wave * 16 * RB + 16 * rb;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = (int)rowu + kg + 4 * r;
+        const double v = acc[rb][r] * kTwoOverSqrtPi;
+        if (col < npair32 && row <= col) {
+          Bd[(int64_t)row * ldb + col] = v;
+          if (row < col) Bd[(int64_t)col * ldb + row] = v;
+        }
+      }
+      acc[rb] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+  };
+
+  int k = 0, blk = 0;
+  uint4* cur = yb0;
+  uint4* nxt = yb1;
+  for (int t = 0; t < T; ++t) {
+    wait_vmcnt0();
+    __asm__ volatile("s_barrier" ::: "memory");
+    const int nch = steps_of(k);
+    if (t + 1 < T) issue_next(nxt);
+    auto node = [&](auto nc) {
+      constexpr int NC = decltype(nc)::value;
+      v4d H[RB], G[RB];
+      v2d b[2];
+      b[0] = *reinterpret_cast<const v2d*>(cur + lane);
+#pragma unroll
+      for (int g = 0; g < 3 * NC; ++g) {
+        const int d = g / NC, ch = g % NC;
+        if (g + 1 < 3 * NC)
+          b[(g + 1) & 1] = *reinterpret_cast<const v2d*>(cur + (((g + 1) / NC) * NCH + (g + 1) % NC) * 64 + lane);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          v4d x = __builtin_amdgcn_mfma_f64_16x16x4f64(af[d][rb][ch].x, b[g & 1].x,
+                                                       ch == 0 ? v4d{0.0, 0.0, 0.0, 0.0} : G[rb], 0, 0, 0);
+          G[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[d][rb][ch].y, b[g & 1].y, x, 0, 0, 0);
+        }
+        if (ch == NC - 1) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            if (d == 0) H[rb] = G[rb];
+            else if (d == 1) H[rb] *= G[rb];
+            else acc[rb] += H[rb] * G[rb];
+          }
+        }
+      }
+    };
+    if constexpr (DEG) with_steps<NCH>(nch, node);
+    else node(std::integral_constant<int, NCH>{});
+    if (++k == nq) {
+      finish_block(blk);
+      k = 0;
+      ++blk;
+    }
+    uint4* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+}
+
+template <class C, bool DEG>
+__global__ void __launch_bounds__(C::NT, 1)
+assemble64_kernel(const AsmMol* __restrict__ mols, const int4* __restrict__ items, const int* __restrict__ seg,
+                  unsigned* __restrict__ counters) {
+  __shared__ uint4 yb0[C::NFRAG * 64];
+  __shared__ uint4 yb1[C::NFRAG * 64];
+  __shared__ int item_s;
+  const int home = blockIdx.x % kQueues;
+  for (int probe = 0; probe < kQueues;) {
+    const int qi = (home + probe) % kQueues;
+    __syncthreads();  // the previous item is done with every LDS buffer
+    if (threadIdx.x == 0) {
+      const int i = (int)atomicAdd(counters + qi, 1u);
+      item_s = (i < seg[qi + 1] - seg[qi]) ? seg[qi] + i : -1;
+    }
+    __syncthreads();
+    const int it = item_s;
+    if (it < 0) {
+      ++probe;
+      continue;
+    }
+    const int4 item = items[it];
+    const AsmMol m = mols[item.x];
+    run_item64<C, DEG>(m, item.y, item.z, item.w, yb0, yb1);
+  }
+}
+
+template <int KC, int RB>
+hipError_t launch64(bool deg, const AsmMol* mols, const int4* items, const int* seg, unsigned* counters, int nblocks,
+                    hipStream_t s) {
+  if (deg)
+    hipLaunchKernelGGL((assemble64_kernel<Cfg64<KC, RB>, true>), dim3(nblocks), dim3(Cfg64<KC, RB>::NT), 0, s, mols,
+                       items, seg, counters);
+  else
+    hipLaunchKernelGGL((assemble64_kernel<Cfg64<KC, RB>, false>), dim3(nblocks), dim3(Cfg64<KC, RB>::NT), 0, s, mols,
+                       items, seg, counters);
+  return hipGetLastError();
+}
+
+// row blocks per wave: the FP64 A operand takes 24 VGPRs per row block and
+// 8 inner indices
+constexpr int rb64(int kc) { return kc <= 8 ? 4 : (kc <= 40 ? 2 : 1); }
+
 template <int KC, int RB>
 hipError_t launch32(bool deg, const AsmMol* mols, const int4* items, const int* seg, unsigned* counters, int nblocks,
                     hipStream_t s) {
@@ -296,6 +495,22 @@ constexpr int rb32(int kc) { return kc <= 40 ? 4 : 2; }
 }  // namespace
 
 int asm32_rows(int kc) { return 16 * rb32(kc) * kNW32; }
+int asm64_rows(int kc) { return 16 * rb64(kc) * kNW32; }
+
+hipError_t launch_assemble64(int kc, bool deg, const AsmMol* mols_dev, const int4* items_dev, const int* seg_dev,
+                             unsigned* counters, int nblocks, hipStream_t s) {
+  switch (kc) {
+    case 8: return launch64<8, rb64(8)>(deg, mols_dev, items_dev, seg_dev, counters, nblocks, s);
+    case 16: return launch64<16, rb64(16)>(deg, mols_dev, items_dev, seg_dev, counters, nblocks, s);
+    case 24: return launch64<24, rb64(24)>(deg, mols_dev, items_dev, seg_dev, counters, nblocks, s);
+    case 32: return launch64<32, rb64(32)>(deg, mols_dev, items_dev, seg_dev, counters, nblocks, s);
+    case 40: return launch64<40, rb64(40)>(deg, mols_dev, items_dev, seg_dev, counters, nblocks, s);
+    case 48: return launch64<48, rb64(48)>(deg, mols_dev, items_dev, seg_dev, counters, nblocks, s);
+    case 56: return launch64<56, rb64(56)>(deg, mols_dev, items_dev, seg_dev, counters, nblocks, s);
+    case 64: return launch64<64, rb64(64)>(deg, mols_dev, items_dev, seg_dev, counters, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_assemble32(int kc, bool deg, const AsmMol* mols_dev, const int4* items_dev, const int* seg_dev,
                              unsigned* counters, int nblocks, hipStream_t s) {

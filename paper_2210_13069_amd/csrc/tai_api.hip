@@ -301,18 +301,32 @@ bool use16(tai_ctx* c, int prec, int n, int nq) {
   return shape16(c, prec, n, nq).id >= 0;
 }
 
-// Whether FP32 assembly takes the persistent LDS-ring kernel (k_assemble32),
-// for the inner lengths it is built for (it skips each node's unused inner
-// steps with per-node degrees too).
+// Whether FP32 / FP64 assembly takes the persistent LDS-ring kernel
+// (k_assemble32.hip), for the inner lengths it is built for (it skips each
+// node's unused inner steps with per-node degrees too).  TAI_TILE_ASSEMBLY
+// selects the tile kernels instead.
 bool use32(int prec, int n) {
-  return prec == tai::kFP32 && tai::operand_kc(prec, n) <= tai::kAsm32MaxKc && !std::getenv("TAI_FP32_TILE");
+  return (prec == tai::kFP32 || prec == tai::kFP64) && tai::operand_kc(prec, n) <= tai::kAsm32MaxKc &&
+         !std::getenv("TAI_TILE_ASSEMBLY");
+}
+int ring_rows(int prec, int n) {
+  const int kc = tai::operand_kc(prec, n);
+  return prec == tai::kFP64 ? tai::asm64_rows(kc) : tai::asm32_rows(kc);
+}
+// Always the form that reads per-node degrees (a molecule without them runs
+// every inner step): a molecule then gives the same bits alone and in any
+// batch.
+hipError_t launch_ring(int prec, int kc, bool /*deg*/, const tai::AsmMol* mols, const int4* items, const int* seg,
+                       unsigned* counters, int nblocks, hipStream_t s) {
+  return prec == tai::kFP64 ? tai::launch_assemble64(kc, true, mols, items, seg, counters, nblocks, s)
+                            : tai::launch_assemble32(kc, true, mols, items, seg, counters, nblocks, s);
 }
 
 int prow_of(tai_ctx* c, int prec, int n, int nq, int64_t npair) {
   int64_t t = 256;
   const bool p16 = use16(c, prec, n, nq), p32 = use32(prec, n);
   if (p16 || p32) {
-    const int64_t r = p16 ? shape16(c, prec, n, nq).rows : tai::asm32_rows(tai::operand_kc(prec, n));
+    const int64_t r = p16 ? shape16(c, prec, n, nq).rows : ring_rows(prec, n);
     int64_t a = r, b = 256;
     while (b) {
       const int64_t tmp = a % b;
@@ -717,7 +731,7 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
     Items16 items;
     const tai::Asm16Shape sh = p16 ? shape16(c, prec, n, nq) : tai::Asm16Shape{};
     if (p16) items.add(0, npair, sh.rows, sh.cols);
-    else items.add(0, npair, tai::asm32_rows(m.kc), tai::kAsm32Cols);
+    else items.add(0, npair, ring_rows(prec, n), tai::kAsm32Cols);
     const size_t tab_bytes = align256(sizeof(tai::AsmMol)) + items.bytes();
     if ((r = ensure(c, c->asm_tab, tab_bytes))) return r;
     if ((r = ensure(c, c->asm_counter, 256))) return r;
@@ -742,7 +756,7 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
         e = tai::launch_assemble16(prec, m.kc, tai::operand_dup_chunks(prec, n), sh, mols_dev, items_dev, seg_dev,
                                    counter, nblocks, s);
       else
-        e = tai::launch_assemble32(m.kc, deg, mols_dev, items_dev, seg_dev, counter, nblocks, s);
+        e = launch_ring(prec, m.kc, deg, mols_dev, items_dev, seg_dev, counter, nblocks, s);
     }
   } else {
     Timed tm(c, kStAssemble, s);
@@ -867,7 +881,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return am[a].npair > am[b].npair; });
     const int kc = tai::operand_kc(prec, n);
     for (int i : order)
-      items16.add(i, am[i].npair, split16 ? sh16.rows : tai::asm32_rows(kc), split16 ? sh16.cols : tai::kAsm32Cols);
+      items16.add(i, am[i].npair, split16 ? sh16.rows : ring_rows(prec, n), split16 ? sh16.cols : tai::kAsm32Cols);
   }
   // device tables: [AsmMol x nmol | PrepMol x nmol | items]
   const size_t off_prep = align256(sizeof(tai::AsmMol) * nmol);
@@ -930,7 +944,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
       const auto* items_dev = reinterpret_cast<const int4*>(tab + Items16::seg_bytes());
       const int ni = (int)items16.count();
       const int blocks = std::min(ni, (c->cus > 0 ? c->cus : 256) * (split16 ? sh16.wgs_per_cu : 1));
-      if (fp32p) return tai::launch_assemble32(am[0].kc, any_degree, mols_dev, items_dev, seg_dev, counter, blocks, st);
+      if (fp32p) return launch_ring(prec, am[0].kc, any_degree, mols_dev, items_dev, seg_dev, counter, blocks, st);
       return tai::launch_assemble16(prec, am[0].kc, tai::operand_dup_chunks(prec, n), sh16, mols_dev, items_dev,
                                     seg_dev, counter, blocks, st);
     }

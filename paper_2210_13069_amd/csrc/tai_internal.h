@@ -205,6 +205,10 @@ inline bool is_split16(int prec) { return prec == kBF16X3 || prec == kBF16X6 || 
 constexpr int kAsm32Cols = 16;
 constexpr int kAsm32MaxKc = 64;
 int asm32_rows(int kc);
+// The FP64 form: panels of asm64_rows(kc) rows.
+int asm64_rows(int kc);
+hipError_t launch_assemble64(int kc, bool deg, const AsmMol* mols_dev, const int4* items_dev, const int* seg_dev,
+                             unsigned* counters, int nblocks, hipStream_t s);
 // deg: the molecules may carry per-node degrees (AsmMol::nk).
 hipError_t launch_assemble32(int kc, bool deg, const AsmMol* mols_dev, const int4* items_dev, const int* seg_dev,
                              unsigned* counters, int nblocks, hipStream_t s);
