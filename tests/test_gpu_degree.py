@@ -105,7 +105,7 @@ def test_apply_J_with_degrees(tai, prec):
     assert err <= (1e-10 if prec == 0 else 1e-6), err
 
 
-@pytest.mark.parametrize("prec", [4, 0])
+@pytest.mark.parametrize("prec", [4, 0, 1])
 def test_batched_with_mixed_degrees(tai, prec):
     """Molecules of one batch with and without per-node degrees, each equal
     bit for bit to its own single-molecule call."""

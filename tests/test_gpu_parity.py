@@ -104,10 +104,9 @@ def test_assemble_B_small(tai, prec, case):
 
 @pytest.mark.parametrize("n", [5, 12, 16, 29, 40, 41, 56])
 def test_assemble_fp64_fp32_inner_lengths(tai, n):
-    """FP64 and FP32 at every inner length of the register-resident-A tile
-    kernel (n rounded up to 8: 8, 16, 32, 40; FP64 switches to eight waves
-    from 32 on) and beyond it (48, 56: the generic tile kernel), on a ragged
-    pair count (npair = 465, not a multiple of the 64-pair tile)."""
+    """FP64 and FP32 at inner lengths 8 .. 56 (n rounded up to 8) of the
+    persistent ring kernels, whose row blocks per wave change with the inner
+    length, on a ragged pair count (npair = 465, not a multiple of any panel)."""
     b = I.small_random(51, natoms=3, shells=("s", "p", "d"), box=2.0, alpha_lo=0.2, alpha_hi=8.0)
     P = I.Params(omega=0.5, nq=6, n=n, L=7.0)
     Mr, K, w = _oracle(b, P)
@@ -392,3 +391,25 @@ def test_bf16x6_layouts_and_shapes(tai, n):
         for o in outs[1:]:
             assert np.array_equal(o, outs[0])
         assert _normwise(outs[0].astype(np.float64), Br) <= LOWP_TOL[3], (n, nq, _normwise(outs[0], Br))
+
+
+@pytest.mark.parametrize("n", [12, 40, 64])
+def test_ring_and_tile_kernels_agree(tai, n):
+    """FP64 and FP32: the persistent ring kernels and the tile kernels
+    (TAI_TILE_ASSEMBLY) compute the same B to their arithmetic's accuracy."""
+    import os
+    b = I.small_random(48, natoms=4, shells=("s", "p", "d"), box=2.5, alpha_lo=0.2, alpha_hi=8.0)
+    P = I.Params(omega=0.5, nq=5, n=n, L=7.0)
+    Mg = tai.moments(b, P)
+    for prec in (0, 1):
+        ring = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+        old = os.environ.get("TAI_TILE_ASSEMBLY")
+        os.environ["TAI_TILE_ASSEMBLY"] = "1"
+        try:
+            tile = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+        finally:
+            if old is None:
+                os.environ.pop("TAI_TILE_ASSEMBLY", None)
+            else:
+                os.environ["TAI_TILE_ASSEMBLY"] = old
+        assert _normwise(ring, tile) <= (1e-13 if prec == 0 else 1e-6), (n, prec)
