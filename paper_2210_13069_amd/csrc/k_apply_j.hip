@@ -74,9 +74,11 @@ struct JF32 {
 // grid (ceil(n / (8*A0W)), nchunk), 512 threads.  Wave w owns
 // a0 = blockIdx.x*8*A0W + w*A0W + {0..A0W-1} and all (a1, a2) in NT x NT
 // output tiles of 16 x 16 (n padded to 16*NT with zeros).
-template <class Op, int NT, int A0W>
+// MT: the element type the moments are read in (the FP32 form reads an FP32
+// copy, half the bytes of the staging loads that bound it).
+template <class Op, int NT, int A0W, class MT = double>
 __global__ void __launch_bounds__(512, 1)
-rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int n, int64_t npair,
+rho_mfma_kernel(const MT* __restrict__ M, const double* __restrict__ Dt, int n, int64_t npair,
                 int64_t chunk, double* __restrict__ part) {
   constexpr int NP = 16 * NT;                  // padded extent of a1 and a2
   constexpr int A0G = 8 * A0W;                 // a0 per work group
@@ -96,9 +98,9 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
   const int a0base = blockIdx.x * A0G;
   const int64_t q0 = (int64_t)blockIdx.y * chunk;
   const int64_t q1 = (q0 + chunk < npair) ? q0 + chunk : npair;
-  const double* M0 = M;
-  const double* M1 = M + (int64_t)n * npair;
-  const double* M2 = M + 2 * (int64_t)n * npair;
+  const MT* M0 = M;
+  const MT* M1 = M + (int64_t)n * npair;
+  const MT* M2 = M + 2 * (int64_t)n * npair;
 
   // staged value e = threadIdx.x + 512 i of a batch: row e / kKB, pair e % kKB
   T pre[PER];
@@ -112,13 +114,13 @@ rho_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Dt, int
       if (q < q1) {
         if (row < A0G) {
           const int a0 = a0base + row;
-          if (a0 < n) v = Dt[q] * M0[(int64_t)a0 * npair + q];
+          if (a0 < n) v = Dt[q] * (double)M0[(int64_t)a0 * npair + q];
         } else if (row < A0G + NP) {
           const int a = row - A0G;
-          if (a < n) v = M1[(int64_t)a * npair + q];
+          if (a < n) v = (double)M1[(int64_t)a * npair + q];
         } else {
           const int a = row - A0G - NP;
-          if (a < n) v = M2[(int64_t)a * npair + q];
+          if (a < n) v = (double)M2[(int64_t)a * npair + q];
         }
       }
       pre[i] = (T)v;
@@ -481,7 +483,9 @@ int j_nchunk(int prec, int n, int npair) {
 size_t j_work_bytes(int prec, int nq, int n, int npair) {
   const size_t n3 = (size_t)n * n * n;
   const int nc = j_nchunk(prec, n, npair);
-  return align256(8 * (size_t)npair) * 2 + align256(8 * n3 * nc) + align256(8 * n3) * 2 + align256(8 * n3 * nq) * 2;
+  const size_t m32 = prec == kFP32 ? align256(4 * 3 * (size_t)n * npair) : 0;
+  return align256(8 * (size_t)npair) * 2 + align256(8 * n3 * nc) + align256(8 * n3) * 2 + align256(8 * n3 * nq) * 2 +
+         m32;
 }
 
 JWork carve_j_work(void* base, int prec, int nq, int n, int npair) {
@@ -495,18 +499,24 @@ JWork carve_j_work(void* base, int prec, int nq, int n, int npair) {
   w.rho = reinterpret_cast<double*>(p); p += align256(8 * n3);
   w.Phi = reinterpret_cast<double*>(p); p += align256(8 * n3);
   w.T1 = reinterpret_cast<double*>(p); p += align256(8 * n3 * nq);
-  w.T2 = reinterpret_cast<double*>(p);
+  w.T2 = reinterpret_cast<double*>(p); p += align256(8 * n3 * nq);
+  w.M32 = prec == kFP32 ? reinterpret_cast<float*>(p) : nullptr;
   return w;
 }
 
-template <class Op, int A0W>
-void launch_pair_contraction_rho(const double* M, int n, int npair, const JWork& w, hipStream_t s) {
+template <class Op, int A0W, class MT>
+void launch_pair_contraction_rho(const MT* M, int n, int npair, const JWork& w, hipStream_t s) {
   const int64_t chunk = ((int64_t)npair + w.nchunk - 1) / w.nchunk;
   const dim3 rg((n + 8 * A0W - 1) / (8 * A0W), w.nchunk);
-  if (n <= 16) hipLaunchKernelGGL((rho_mfma_kernel<Op, 1, A0W>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
-  else if (n <= 32) hipLaunchKernelGGL((rho_mfma_kernel<Op, 2, A0W>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
-  else if (n <= 48) hipLaunchKernelGGL((rho_mfma_kernel<Op, 3, A0W>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
-  else hipLaunchKernelGGL((rho_mfma_kernel<Op, 4, 1>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  if (n <= 16) hipLaunchKernelGGL((rho_mfma_kernel<Op, 1, A0W, MT>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  else if (n <= 32) hipLaunchKernelGGL((rho_mfma_kernel<Op, 2, A0W, MT>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  else if (n <= 48) hipLaunchKernelGGL((rho_mfma_kernel<Op, 3, A0W, MT>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+  else hipLaunchKernelGGL((rho_mfma_kernel<Op, 4, 1, MT>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
+}
+
+__global__ void __launch_bounds__(256) to_fp32_kernel(const double* __restrict__ x, int64_t count, float* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) y[i] = (float)x[i];
 }
 
 template <class Op>
@@ -519,12 +529,20 @@ void launch_pair_contraction_jp(const double* M, int n, int npair, const JWork& 
 }
 
 namespace {
+// the FP32 pair contraction reads an FP32 copy of the moments (in w.M32),
+// made once per call
+void convert_moments(int prec, const double* M, int n, int npair, const JWork& w, hipStream_t s) {
+  if (prec != kFP32) return;
+  const int64_t count = 3 * (int64_t)n * npair;
+  hipLaunchKernelGGL(to_fp32_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, M, count, w.M32);
+}
+
 // rho from the pair densities in w.Dt, then Phi = (2/sqrt(pi)) sum_k w_k rho x_d K_k
 // (into w.rho and w.Phi)
 void launch_rho_phi(int prec, const double* M, int npair, int n, int nq, const NodeTables& tb, const JWork& w,
                     hipStream_t s) {
   const int64_t n3 = (int64_t)n * n * n;
-  if (prec == kFP32) launch_pair_contraction_rho<JF32, 1>(M, n, npair, w, s);
+  if (prec == kFP32) launch_pair_contraction_rho<JF32, 1>(static_cast<const float*>(w.M32), n, npair, w, s);
   else if (n <= 48) launch_pair_contraction_rho<JF64, 2>(M, n, npair, w, s);
   else launch_pair_contraction_rho<JF64, 1>(M, n, npair, w, s);
   hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.rho_part, w.nchunk, n3, w.rho);
@@ -545,6 +563,7 @@ hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, const in
                           const NodeTables& tb, const double* D, double* J, const JWork& w, hipStream_t s) {
   hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, D, nb, (int64_t)npair, pairs,
                      w.Dt);
+  convert_moments(prec, M, n, npair, w, s);
   launch_rho_phi(prec, M, npair, n, nq, tb, w, s);
   if (prec == kFP32) launch_pair_contraction_jp<JF32>(M, n, npair, w, s);
   else launch_pair_contraction_jp<JF64>(M, n, npair, w, s);
@@ -560,6 +579,7 @@ hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const
                              const NodeTables& tb, const double* Q, int norb, double* R, double* F, double* Jmo,
                              const JWork& w, hipStream_t s) {
   const int64_t n3 = (int64_t)n * n * n;
+  convert_moments(prec, M, n, npair, w, s);
   for (int i = 0; i < norb; ++i) {
     JWork wi = w;
     wi.rho = R + (int64_t)i * n3;

@@ -223,6 +223,7 @@ struct JWork {
   double* T2;      // [nq][n^3] mode-0 products, before the sum over nodes
   double* Phi;     // [n^3]
   double* Jp;      // [npair]
+  float* M32;      // [3][n][npair] FP32 copy of the moments (FP32 only, else null)
   int nchunk;
 };
 int j_nchunk(int prec, int n, int npair);
