@@ -260,7 +260,7 @@ int tai_contract_pairs(tai_ctx* ctx, const void* Bp, int64_t ldbp, int32_t nbp, 
 int tai_apply_J_contracted(tai_ctx* ctx, const double* M, int32_t nbp, const int32_t* fmap,
                            const tai_params* params, const double* D, double* J, void* stream);
 
-/* ---- screening (section 5, compression by screening) --------------------- */
+/* ---- screening (section 6.3, compression by screening) --------------------- */
 
 /* Pairs that survive screening: pair p(mu,nu), mu <= nu, is dropped when its
    Gaussian product prefactor exp(-a_mu a_nu/(a_mu + a_nu) |A_mu - A_nu|^2)

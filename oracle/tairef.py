@@ -246,7 +246,7 @@ def B_full_degrees(mu, ahat, N, w, rows=None):
 
 
 # ---------------------------------------------------------------------------
-# Basis and pairs (eqs. basis, primi; Prop. 2.1; symmetric pairs, section 5.3)
+# Basis and pairs (eqs. basis, primi; Prop. 2.1; symmetric pairs, section 6.3)
 # ---------------------------------------------------------------------------
 def _double_factorial_odd(l):
     """(2l-1)!! with (-1)!! = 1."""
@@ -271,7 +271,7 @@ def pair_list(nb):
     """(mu, nu) of every pair mu <= nu, row-major upper triangle.
 
     Pair index p(mu,nu) = mu*nb - mu(mu-1)/2 + (nu - mu) (0-based), which is the
-    order of this list.  Pair symmetry g_mu g_nu = g_nu g_mu (section 5.3).
+    order of this list.  Pair symmetry g_mu g_nu = g_nu g_mu (section 6.3).
     """
     mu, nu = np.triu_indices(nb)
     return mu.astype(np.int64), nu.astype(np.int64)
@@ -284,7 +284,7 @@ def pair_index(nb, mu, nu):
 
 def screened_pairs(center, alpha, tau):
     """Pair indices p(mu, nu), mu <= nu, ascending, that survive screening
-    (section 5, compression by screening): a pair is dropped when its
+    (section 6.3, compression by screening): a pair is dropped when its
     Gaussian product prefactor exp(-ab/(a+b) |A - B|^2) is at most tau.
     tau <= 0 keeps every pair; diagonal pairs (prefactor 1) are always kept
     for tau < 1."""
@@ -482,6 +482,34 @@ def B_kronecker(M, K, w):
         kron = np.kron(np.kron(K[k], K[k]), K[k])
         B += w[k] * (Mt @ kron @ Mt.T)
     return (2.0 / SQRT_PI) * B
+
+
+# ---------------------------------------------------------------------------
+# Low-rank compression of the moments (section 6.1, eqs. SVD and approxepsilon)
+# ---------------------------------------------------------------------------
+def compression_basis(M, tol):
+    """Truncated SVD of the moments (section 6.1, eq. SVD).  The moment
+    matrices of the three directions are stacked side by side,
+    W = [M_1 | M_2 | M_3] (n x 3 npair), one orthonormal basis V of its leading
+    left singular vectors serves the three directions and every quadrature
+    node (with one degree n the moments of all nodes coincide).  The rank is
+    R = #{r : sigma_r > tol * sigma_1}, at least 1.
+
+    Returns (V[:, :R], sigma (all n), R)."""
+    W = np.concatenate([M[0], M[1], M[2]], axis=1)
+    V, sigma, _ = np.linalg.svd(W, full_matrices=False)
+    R = max(1, int(np.sum(sigma > tol * sigma[0])))
+    return V[:, :R], sigma, R
+
+
+def compress(M, K, V):
+    """The compressed operands of eq. approxepsilon: moments U_d = V^T M_d
+    (R x npair per direction) and tables Kc_k = V^T K_k V (R x R per node),
+    so that m_p^T K_k m_q becomes u_p^T Kc_k u_q = m_p^T P K_k P m_q with the
+    projector P = V V^T."""
+    U = np.stack([V.T @ M[d] for d in range(3)])
+    Kc = np.stack([V.T @ K[k] @ V for k in range(K.shape[0])])
+    return U, Kc
 
 
 # ---------------------------------------------------------------------------

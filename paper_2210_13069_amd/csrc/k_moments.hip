@@ -127,7 +127,7 @@ moments_kernel(DevBasis bs, int n, double L, NodeTables tb, double* __restrict__
   moments_body<NMAX>(bs, n, L, tb, M, npair, pairs);
 }
 
-// Screening (section 5, compression by screening).  One thread per row mu
+// Screening (section 6.3, compression by screening).  One thread per row mu
 // of the pair list counts, then writes, the pairs (mu, nu >= mu) whose
 // Gaussian product prefactor exp(-ab/(a+b) |A - B|^2) exceeds tau; a single
 // work group turns the row counts into offsets in between, so the kept

@@ -56,7 +56,7 @@ hipError_t launch_moments(const DevBasis& b, int n, double L, const NodeTables& 
 // outside it give zero moments): M[d][a][i] for pair pairs[i], i < npk.
 hipError_t launch_moments_pairs(const DevBasis& b, int n, double L, const NodeTables& tb, const int32_t* pairs,
                                 int64_t npk, double* M, hipStream_t s);
-// Screening (section 5): pair p(mu, nu) is kept when
+// Screening (section 6.3): pair p(mu, nu) is kept when
 // exp(-ab/(a+b) |A - B|^2) > tau (every pair when tau <= 0).  Writes the kept
 // indices in ascending order to pairs and their count to *count (device);
 // rows: device scratch of nb + 1 int32.

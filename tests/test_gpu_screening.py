@@ -1,4 +1,4 @@
-"""GPU parity of pair screening (section 5, compression by screening): the
+"""GPU parity of pair screening (section 6.3, compression by screening): the
 kept list exactly, the moments of the kept pairs, B over them in every
 arithmetic and J with the pair sums restricted to them, through the C ABI
 against the oracle on the same seeded inputs.  Tolerances are those of the

@@ -1,4 +1,4 @@
-"""Pins of the oracle's pair screening (section 5, compression by screening):
+"""Pins of the oracle's pair screening (section 6.3, compression by screening):
 the kept list against a plain double loop over the criterion, its
 monotonicity, and the size of everything screening drops against bounds that
 use only the overlaps of the dropped pairs."""
