@@ -37,6 +37,12 @@ HBM_PEAK_GBS = 8000.0
 # tolerance of the per-node degree leg: each node's factor moves by at most
 # this much on the box (below the degree-40 interpolation error at omega 0.3)
 DEGREE_TOL = 1e-8
+# tolerance of the low-rank compression legs: directions of the stacked
+# moments with sigma_r <= this * sigma_1 are dropped
+RANK_TOL = 1e-7
+# the J-build legs cut at a looser tolerance: the grid kernels work in tiles
+# of 16 directions, so the compression pays there once R <= 32 of n = 48
+RANK_TOL_J = 1e-5
 # screening threshold of the screened legs: pairs whose Gaussian product
 # prefactor is at most this are dropped
 SCREEN_TAU = 1e-12
@@ -151,7 +157,7 @@ def main():
             ctx.assemble_B(M, npair, params, Bbuf)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        stages = {s: ctx.profile_read(s) for s in ("nodes", "moments", "pack", "project", "assemble")}
+        stages = {s: ctx.profile_read(s) for s in ("nodes", "moments", "compress", "pack", "project", "assemble")}
         ctx.profile_enable(False)
         ms = (t1 - t0) * 1e3 / steps
         sample = Bbuf[spt, sqt].double().cpu().numpy()
@@ -177,6 +183,7 @@ def main():
                          "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st_head.items()}}}
     samples = {args.prec: samp_head}
     degrees = None
+    compressed = None
 
     if not args.only_headline:
         B64 = torch.empty((npair, npair), dtype=torch.float64, device=dev)
@@ -206,6 +213,31 @@ def main():
                              "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()},
                              "assemble_tflops_algorithmic": round(deg_flops / (a_ms / 1e3) / 1e12, 2)}
             samples[name + "_degrees"] = samp
+        # low-rank compression of the moments (section 6.1): every path
+        # contracts R < n directions of one SVD basis
+        Pc = dataclasses.replace(P, rank_tol=RANK_TOL)
+        ctx.moments(ba, P, M)
+        rank = ctx.compress(M, npair, Pc)
+        cmp_flops = algorithmic_flops(npair, nq, rank)
+        compressed = {"rank_tol": RANK_TOL, "rank": rank, "n": n, "flops_per_launch": cmp_flops,
+                      "rel_error": "rel_error_vs_oracle[<path>_compressed] is against the oracle of the "
+                                   "uncompressed method, so it includes the truncation"}
+        for name in (args.prec, "fp64", "fp32"):
+            if name in compressed:
+                continue
+            prec = tai.PREC_BY_NAME[name]
+            steps = max(1, K // 2)
+            log(f"compressed {name}: rank={rank} steps={steps}")
+            ms, st, samp = run_steps(prec, B64 if prec == tai.FP64 else B32, steps, 1, Pc)
+            a_ms = st["assemble"][0] / max(1, st["assemble"][1])
+            compressed[name] = {"ms_per_step": round(ms, 3), "entries_per_s": entries / (ms / 1e3),
+                                "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()},
+                                "assemble_tflops_algorithmic": round(cmp_flops / (a_ms / 1e3) / 1e12, 2)}
+            if name in paths:
+                compressed[name]["speedup_vs_uncompressed_step"] = round(paths[name]["ms_per_step"] / ms, 3)
+                compressed[name]["normwise_change_vs_uncompressed_gpu_sampled"] = float(
+                    np.max(np.abs(samp - samples[name])) / np.max(np.abs(samples[name])))
+            samples[name + "_compressed"] = samp
         del B64
         torch.cuda.empty_cache()
         if "fp64" in paths:
@@ -365,6 +397,32 @@ def main():
                       "rel_2norm_vs_unscreened_gpu": float(torch.linalg.matrix_norm(Js - ref, 2) /
                                                            torch.linalg.matrix_norm(ref, 2))}
         japply["screened_fp64"] = screened_j
+        # the same J-build on the compressed grid (R^3 instead of n^3)
+        jPc = dataclasses.replace(jP, rank_tol=RANK_TOL_J)
+        ctx.moments(jba, jP, Mj)
+        jrank = ctx.compress(Mj, jb.npair, jPc)
+        Jc = torch.empty_like(Jj["fp64"])
+        for name in ("fp64", "fp32"):
+            jparams_c = tai.make_params(jPc, tai.PREC_BY_NAME[name])
+            log(f"compressed J-build {name}: rank={jrank}")
+            for it in range(W + K):
+                if it == W:
+                    torch.cuda.synchronize()
+                    ctx.profile_enable(True)
+                    t0 = time.perf_counter()
+                ctx.moments(jba, jP, Mj)
+                ctx.apply_J(Mj, jb.nb, jparams_c, Dj, Jc)
+            torch.cuda.synchronize()
+            ms_jc = (time.perf_counter() - t0) * 1e3 / K
+            stj = {s_: ctx.profile_read(s_) for s_ in ("moments", "compress", "apply_J")}
+            ctx.profile_enable(False)
+            japply["compressed_" + name] = {
+                "rank_tol": RANK_TOL_J, "rank": jrank, "n": jP.n, "ms_per_step": round(ms_jc, 3),
+                "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stj.items()},
+                "speedup_vs_uncompressed": round(japply[name]["ms_per_step"] / ms_jc, 3),
+                "rel_2norm_vs_uncompressed_fp64_gpu": float(torch.linalg.matrix_norm(Jc - Jj["fp64"], 2) /
+                                                            torch.linalg.matrix_norm(Jj["fp64"], 2))}
+        del Jc
         # the orbital-basis Coulomb matrix of NORB orbitals on the same grid
         Qo = torch.as_tensor(np.random.default_rng(17).standard_normal((NORB, jb.nb)) / np.sqrt(jb.nb), device=dev)
         Jmo = torch.empty((NORB, NORB), dtype=torch.float64, device=dev)
@@ -474,6 +532,7 @@ def main():
         "rel_error_vs_oracle": rel_error,
         "paths": paths,
         "degrees": degrees,
+        "compressed": compressed,
         "screened": screened,
         "batched": batched,
         "japply": japply,

@@ -96,7 +96,15 @@ typedef struct {
    node k keeps the Chebyshev coefficients of its factor below N_k, the
    smallest degree whose dropped coefficients sum in absolute value to at
    most degree_tol, so each factor moves by at most degree_tol on the box
-   (tai_degrees).  Every entry point then uses the truncated factors. */
+   (tai_degrees).  Every entry point then uses the truncated factors.
+   rank_tol in [0, 1) selects the low-rank compression of the moments
+   (section 6.1, eqs. SVD and approxepsilon): 0 keeps the n node values;
+   with rank_tol > 0 tai_assemble_B, tai_apply_J(_pairs), tai_apply_J_contracted
+   and tai_coulomb_mo contract U_d = V^T M_d and Kc_k = V^T K_k V instead,
+   V the R leading left singular vectors of [M_1 | M_2 | M_3] with
+   sigma_r > rank_tol * sigma_1 (tai_compress); those calls then wait on the
+   host for R.  rank_tol > 0 with degree_tol > 0 is TAI_ERR_UNSUPPORTED, and
+   so is rank_tol > 0 in tai_assemble_B_batched. */
 typedef struct {
   double  omega;
   int32_t nq;
@@ -105,6 +113,7 @@ typedef struct {
   int32_t nodes;
   int32_t prec;
   double  degree_tol;
+  double  rank_tol;
 } tai_params;
 
 /* ---- context ------------------------------------------------------------ */
@@ -153,6 +162,22 @@ int tai_quadrature(tai_ctx* ctx, const tai_params* params,
    both NULL).  With degree_tol > 0, tai_quadrature's K holds the node values
    of the kept polynomials. */
 int tai_degrees(tai_ctx* ctx, const tai_params* params, int32_t* nk, double* C, void* stream);
+
+/* Low-rank compression of the moments (section 6.1, eqs. SVD and
+   approxepsilon).  M: DEVICE double [3][n][npair] (tai_moments).  The
+   singular values and left singular vectors of W = [M_1 | M_2 | M_3]
+   (n x 3 npair) are computed in FP64 from the eigenpairs of W W^T (cyclic
+   Jacobi): sigma (DEVICE double [n] or NULL) in decreasing order, V (DEVICE
+   double [n][n] or NULL) with V[a][r] the r-th singular vector, and
+   *rank (HOST) = #{r : sigma_r > rank_tol * sigma_1} (at least 1) rounded up
+   to a multiple of 8 and capped at n (the contractions run their inner index
+   in chunks of 8, so the extra directions are free).  One basis
+   serves the three directions and every quadrature node.  Forming W W^T
+   resolves sigma_r to about 1e-16 sigma_1^2 / sigma_r, so ranks cut at
+   rank_tol >= 1e-7 rest on well-resolved values.  rank_tol must be > 0
+   (TAI_ERR_INVALID_ARG otherwise).  The call waits on the host for the rank. */
+int tai_compress(tai_ctx* ctx, const double* M, int32_t npair, const tai_params* params, int32_t* rank,
+                 double* sigma, double* V, void* stream);
 
 /* 1D moments (eq. defV, Lagrange basis), FP64 on the device:
      M[d][a][p] = int_{-L}^{L} g_{mu,d}(x) g_{nu,d}(x) l_a(x) dx
@@ -314,7 +339,7 @@ int tai_tune(tai_ctx* ctx, int mode);
    enqueues with HIP events recorded on the call's stream (outside graph
    capture).  Stages: "nodes", "moments", "pack", "project", "assemble",
    "apply_J", "batched" (a whole tai_assemble_B_batched launch or graph
-   replay).  tai_profile_enable clears the totals (enable = 0 turns timing
+   replay), "compress" (basis and compressed operands of rank_tol > 0).  tai_profile_enable clears the totals (enable = 0 turns timing
    off); tai_profile_read waits for the recorded events and returns the total
    milliseconds and the number of timed launches of one stage. */
 int tai_profile_enable(tai_ctx* ctx, int enable);

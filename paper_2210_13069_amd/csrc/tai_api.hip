@@ -34,6 +34,7 @@ struct tai_ctx {
   hipEvent_t host_basis_done = nullptr;
   Buf opA, opEx, opY;     // assembly operands
   Buf opMu;               // coefficient moments (per-node degrees)
+  Buf cmp, cmpU;          // low-rank compression: basis, Gram, tables; compressed moments
   Buf screen;             // screening: row counts / offsets and the kept count
   Buf mo;                 // orbital-basis Coulomb matrix: rho and Phi of every orbital
   Buf ct, ct_work;        // contraction: member tables; primitive-basis D and J
@@ -91,6 +92,10 @@ int validate_params(tai_ctx* c, const tai_params* p) {
   if (p->prec < TAI_FP64 || p->prec > TAI_F16X3) return fail(c, TAI_ERR_INVALID_ARG, "unknown prec");
   if (!finite(p->degree_tol) || p->degree_tol < 0)
     return fail(c, TAI_ERR_INVALID_ARG, "degree_tol must be finite and >= 0");
+  if (!finite(p->rank_tol) || p->rank_tol < 0 || !(p->rank_tol < 1))
+    return fail(c, TAI_ERR_INVALID_ARG, "rank_tol must be finite and in [0, 1)");
+  if (p->rank_tol > 0 && p->degree_tol > 0)
+    return fail(c, TAI_ERR_UNSUPPORTED, "rank_tol and degree_tol cannot both be > 0");
   return TAI_OK;
 }
 
@@ -130,9 +135,9 @@ int need_device(tai_ctx* c) {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-const char* const kStageNames[] = {"nodes", "moments", "pack", "project", "assemble", "apply_J", "batched"};
-constexpr int kNumStages = 7;
-enum { kStNodes = 0, kStMoments, kStPack, kStProject, kStAssemble, kStApplyJ, kStBatched };
+const char* const kStageNames[] = {"nodes", "moments", "pack", "project", "assemble", "apply_J", "batched", "compress"};
+constexpr int kNumStages = 8;
+enum { kStNodes = 0, kStMoments, kStPack, kStProject, kStAssemble, kStApplyJ, kStBatched, kStCompress };
 
 hipEvent_t take_event(tai_ctx* c) {
   if (!c->ev_pool.empty()) {
@@ -582,6 +587,33 @@ int tai_degrees(tai_ctx* c, const tai_params* p, int32_t* nk, double* C, void* s
   return TAI_OK;
 }
 
+static int compress_impl(tai_ctx* c, const double* M, int64_t npair, const tai_params* p, const NodeTables& tb,
+                         bool operands, hipStream_t s, tai::CompressWork* w, int* R);
+
+int tai_compress(tai_ctx* c, const double* M, int32_t npair, const tai_params* p, int32_t* rank, double* sigma,
+                 double* V, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !rank) return fail(c, TAI_ERR_INVALID_ARG, "M or rank is NULL");
+  if (npair < 1) return fail(c, TAI_ERR_INVALID_ARG, "npair must be >= 1");
+  if (!(p->rank_tol > 0)) return fail(c, TAI_ERR_INVALID_ARG, "rank_tol must be > 0");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tai::CompressWork w;
+  int R = 0;
+  NodeTables none{};
+  if ((r = compress_impl(c, M, npair, p, none, false, s, &w, &R))) return r;
+  const size_t n = p->n;
+  hipError_t e;
+  if (sigma && (e = hipMemcpyAsync(sigma, w.sigma, 8 * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(c, e, "copy sigma");
+  if (V && (e = hipMemcpyAsync(V, w.V, 8 * n * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(c, e, "copy V");
+  *rank = R;
+  return TAI_OK;
+}
+
 // Copy a validated basis to the device (through pinned staging) on s.
 static int upload_basis(tai_ctx* c, const tai_basis* b, hipStream_t s, tai::DevBasis* db) {
   int r;
@@ -666,10 +698,71 @@ int tai_moments_pairs(tai_ctx* c, const tai_basis* b, const tai_params* p, const
   return moments_impl(c, b, p, pairs, npk, M, static_cast<hipStream_t>(stream));
 }
 
+// Low-rank compression of the moments (section 6.1, eqs. SVD and
+// approxepsilon) on s: basis and rank, then the compressed moments
+// (c->cmpU, [3][R][npair]) and tables (w->Kc, [nq][R][R]) from the node tables
+// tb.  The call waits on the host for the rank.
+static int compress_impl(tai_ctx* c, const double* M, int64_t npair, const tai_params* p, const NodeTables& tb,
+                         bool operands, hipStream_t s, tai::CompressWork* w, int* R) {
+  int r;
+  const int n = p->n, nq = p->nq;
+  if ((r = ensure(c, c->cmp, tai::compress_work_bytes(n, nq, npair)))) return r;
+  if ((r = ensure(c, c->cmpU, sizeof(double) * 3 * (size_t)n * npair))) return r;
+  *w = tai::carve_compress_work(c->cmp.p, n, nq, npair);
+  hipError_t e;
+  {
+    Timed tm(c, kStCompress, s);
+    e = tai::launch_compress_basis(M, n, npair, p->rank_tol, *w, static_cast<double*>(c->cmpU.p), s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "compression basis kernels");
+  int32_t host = 0;
+  if ((e = hipMemcpyAsync(&host, w->rank, sizeof host, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(c, e, "rank copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  if (host < 2 || host > n) return fail(c, TAI_ERR_HIP, "compression rank out of range");
+  *R = host;
+  if (!operands) return TAI_OK;
+  {
+    Timed tm(c, kStCompress, s);
+    e = tai::launch_compress_operands(M, n, npair, host, nq, tb.K, *w, static_cast<double*>(c->cmpU.p), s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "compression operand kernels");
+  return TAI_OK;
+}
+
+// Node tables of p on s, then the operands a path contracts: M, n and the K
+// tables, or with p->rank_tol > 0 the compressed U, R and Kc.
+static int prepare_operands(tai_ctx* c, const double* M, int64_t npair, const tai_params* p, hipStream_t s,
+                            NodeTables* tb, const double** Mop, int* ne, NodeTables* tbp) {
+  int r;
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(p->nq, p->n)))) return r;
+  *tb = tai::carve_node_tables(c->nodes.p, p->nq, p->n);
+  hipError_t e;
+  {
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, p->degree_tol, *tb, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  *Mop = M;
+  *ne = p->n;
+  *tbp = *tb;
+  if (p->rank_tol > 0) {
+    tai::CompressWork w;
+    if ((r = compress_impl(c, M, npair, p, *tb, true, s, &w, ne))) return r;
+    *Mop = static_cast<const double*>(c->cmpU.p);
+    tbp->K = w.Kc;
+  }
+  return TAI_OK;
+}
+
 static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_params* p, void* B, int64_t ldb,
                          hipStream_t s) {
   int r;
-  const int prec = p->prec, n = p->n, nq = p->nq;
+  const int prec = p->prec, nq = p->nq;
+  NodeTables tb, tbp;
+  const double* Mop = M;
+  int n = p->n;
+  if ((r = prepare_operands(c, M, npair, p, s, &tb, &Mop, &n, &tbp))) return r;
   // per-node degrees in FP64 / FP32: operands in coefficient form (moments
   // against T_j and the kept coefficients), each node contracting its
   // leading N_k indices.  The split 16-bit arithmetics keep the node form
@@ -678,21 +771,12 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
   // in accuracy.
   const bool deg = p->degree_tol > 0 && !tai::is_split16(prec);
   const int prow = prow_of(c, prec, n, nq, npair);
-  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
   if ((r = ensure(c, c->opA, opA_bytes(prec, n, prow)))) return r;
   if ((r = ensure(c, c->opEx, opEx_bytes(prow)))) return r;
   if ((r = ensure(c, c->opY, opY_bytes(prec, n, nq, prow)))) return r;
   if (deg && (r = ensure(c, c->opMu, sizeof(double) * 3 * (size_t)n * npair))) return r;
-  NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
   hipError_t e;
-  {
-    Timed tm(c, kStNodes, s);
-    e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, p->degree_tol, tb, s);
-  }
-  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
   int32_t* ex = static_cast<int32_t*>(c->opEx.p);
-  const double* Mop = M;
-  NodeTables tbp = tb;
   if (deg) {
     double* mu = static_cast<double*>(c->opMu.p);
     {
@@ -777,7 +861,7 @@ int tai_assemble_B(tai_ctx* c, const double* M, int32_t npair, const tai_params*
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
   c->size_key = pow2_at_least(npair);
-  if (c->tune_mode == 1 && tunable(p->prec, p->n)) {
+  if (c->tune_mode == 1 && tunable(p->prec, p->n) && !(p->rank_tol > 0)) {
     r = tune16(c, p->prec, p->n, p->nq, s, [&]() { return assemble_impl(c, M, npair, p, B, ldb, s); });
     if (r) return r;
   }
@@ -801,6 +885,8 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
     const tai_params& pi = mols[i].params;
     if (pi.nq != p0.nq || pi.n != p0.n || pi.nodes != p0.nodes || pi.prec != p0.prec)
       return fail(c, TAI_ERR_INVALID_ARG, "molecules of a batch must share nq, n, nodes and prec");
+    if (pi.rank_tol > 0)
+      return fail(c, TAI_ERR_UNSUPPORTED, "molecule " + std::to_string(i) + ": rank_tol > 0 is not batched");
   }
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1019,20 +1105,17 @@ static int apply_j_impl(tai_ctx* c, const double* M, int32_t nb, const int32_t* 
     return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J supports prec TAI_FP64 and TAI_FP32");
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int n = p->n, nq = p->nq;
-  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
+  const int nq = p->nq;
+  NodeTables tb, tbp;
+  const double* Mop = M;
+  int n = p->n;
+  if ((r = prepare_operands(c, M, npair, p, s, &tb, &Mop, &n, &tbp))) return r;
   if ((r = ensure(c, c->jwork, tai::j_work_bytes(p->prec, nq, n, (int)npair)))) return r;
-  NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
   hipError_t e;
-  {
-    Timed tm(c, kStNodes, s);
-    e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, p->degree_tol, tb, s);
-  }
-  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
   tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, n, (int)npair);
   {
     Timed tm(c, kStApplyJ, s);
-    e = tai::launch_apply_j(p->prec, M, nb, (int)npair, pairs, n, nq, tb, D, J, w, s);
+    e = tai::launch_apply_j(p->prec, Mop, nb, (int)npair, pairs, n, nq, tbp, D, J, w, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "apply_J kernels");
   return TAI_OK;
@@ -1076,24 +1159,22 @@ int tai_coulomb_mo(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs
     return fail(c, TAI_ERR_UNSUPPORTED, "tai_coulomb_mo supports prec TAI_FP64 and TAI_FP32");
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int n = p->n, nq = p->nq;
+  const int nq = p->nq;
   const int64_t npair = pairs ? npk : npair_of(nb);
+  NodeTables tb, tbp;
+  const double* Mop = M;
+  int n = p->n;
+  if ((r = prepare_operands(c, M, npair, p, s, &tb, &Mop, &n, &tbp))) return r;
   const size_t n3 = (size_t)n * n * n;
-  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
   if ((r = ensure(c, c->jwork, tai::j_work_bytes(p->prec, nq, n, (int)npair)))) return r;
   if ((r = ensure(c, c->mo, 2 * sizeof(double) * n3 * (size_t)norb))) return r;
-  NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
   hipError_t e;
-  {
-    Timed tm(c, kStNodes, s);
-    e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, p->degree_tol, tb, s);
-  }
-  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
   tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, n, (int)npair);
   double* R = static_cast<double*>(c->mo.p);
   {
     Timed tm(c, kStApplyJ, s);
-    e = tai::launch_coulomb_mo(p->prec, M, nb, (int)npair, pairs, n, nq, tb, Q, norb, R, R + n3 * norb, Jmo, w, s);
+    e = tai::launch_coulomb_mo(p->prec, Mop, nb, (int)npair, pairs, n, nq, tbp, Q, norb, R, R + n3 * norb, Jmo, w,
+                               s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "coulomb_mo kernels");
   return TAI_OK;

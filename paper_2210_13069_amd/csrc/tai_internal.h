@@ -229,6 +229,30 @@ struct JWork {
 int j_nchunk(int prec, int n, int npair);
 size_t j_work_bytes(int prec, int nq, int n, int npair);
 JWork carve_j_work(void* base, int prec, int nq, int n, int npair);
+// Low-rank compression of the moments (k_compress.hip): Gram matrix of
+// W = [M_1 | M_2 | M_3], its eigenpairs by Jacobi (V[a][r], sigma[r]
+// decreasing, *rank = #{sigma_r > tol sigma_1} rounded up to a multiple of 8,
+// capped at n), then compressed
+// moments U[d][r][q] = sum_a V[a][r] M[d][a][q] and tables Kc[k] = V_R^T K[k] V_R.
+struct CompressWork {
+  double* part;    // [nchunk][n][n] partial Gram matrices
+  double* G;       // [n][n]
+  double* V;       // [n][n] the basis V1 V2
+  double* V1;      // [n][n] eigenvectors of W W^T
+  double* V2;      // [n][n] eigenvectors of Y Y^T, Y = V1^T W
+  double* sigma;   // [n]
+  double* Kc;      // [nq][R][R]
+  int32_t* rank;   // [1]
+  int nchunk;
+};
+size_t compress_work_bytes(int n, int nq, int64_t npair);
+CompressWork carve_compress_work(void* base, int n, int nq, int64_t npair);
+// Y: workspace [3][n][npair]
+hipError_t launch_compress_basis(const double* M, int n, int64_t npair, double tol, const CompressWork& w,
+                                 double* Y, hipStream_t s);
+hipError_t launch_compress_operands(const double* M, int n, int64_t npair, int R, int nq, const double* K,
+                                    const CompressWork& w, double* U, hipStream_t s);
+
 // Contracted basis functions (k_contract.hip).  B_c[P][Q] = sum over the
 // CSR members a of P and b of Q of wt[a] wt[b] Bp[idx[a]][idx[b]] (double or
 // float matrices, FP64 sums); D_prim[i][j] = D[fmap[i]][fmap[j]];

@@ -45,6 +45,7 @@ class Params:
     L: float
     nodes: int = 0              # 0 = Chebyshev-Lobatto, 1 = Chebyshev-Gauss
     degree_tol: float = 0.0     # > 0: per-node degrees N_k within this tolerance
+    rank_tol: float = 0.0       # > 0: low-rank compression of the moments at this tolerance
 
 
 def random_molecule(rng, natoms, box, shells, alpha_lo, alpha_hi):

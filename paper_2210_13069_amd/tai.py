@@ -28,10 +28,10 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 
 # exported symbols declared in include/tai.h
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
-           "tai_quadrature", "tai_degrees", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
+           "tai_quadrature", "tai_degrees", "tai_compress", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
            "tai_apply_J_pairs", "tai_coulomb_mo", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
            "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
-STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched"]
+STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched", "compress"]
 
 
 class TaiError(RuntimeError):
@@ -55,7 +55,8 @@ class tai_params(ctypes.Structure):
                 ("L", ctypes.c_double),
                 ("nodes", ctypes.c_int32),
                 ("prec", ctypes.c_int32),
-                ("degree_tol", ctypes.c_double)]
+                ("degree_tol", ctypes.c_double),
+                ("rank_tol", ctypes.c_double)]
 
 
 class tai_mol(ctypes.Structure):
@@ -87,6 +88,8 @@ def load_library(path=LIB_PATH):
     lib.tai_sync.argtypes = [vp, vp]
     lib.tai_quadrature.argtypes = [vp, ctypes.POINTER(tai_params), vp, vp, vp, vp, vp]
     lib.tai_degrees.argtypes = [vp, ctypes.POINTER(tai_params), vp, vp, vp]
+    lib.tai_compress.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), ctypes.POINTER(ctypes.c_int32),
+                                 vp, vp, vp]
     lib.tai_screen_pairs.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.c_double, vp,
                                      ctypes.POINTER(ctypes.c_int32), vp]
     lib.tai_moments_pairs.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.POINTER(tai_params), vp, ctypes.c_int32,
@@ -126,10 +129,10 @@ def _stream(stream):
 
 def make_params(p, prec=None):
     """tai_params from an object with omega, nq, n, L, nodes (and prec,
-    degree_tol)."""
+    degree_tol, rank_tol)."""
     return tai_params(float(p.omega), int(p.nq), int(p.n), float(p.L), int(getattr(p, "nodes", 0)),
                       int(prec if prec is not None else getattr(p, "prec", FP64)),
-                      float(getattr(p, "degree_tol", 0.0)))
+                      float(getattr(p, "degree_tol", 0.0)), float(getattr(p, "rank_tol", 0.0)))
 
 
 class BasisArrays:
@@ -189,6 +192,15 @@ class Context:
         p = params if isinstance(params, tai_params) else make_params(params)
         self.check(self.lib.tai_degrees(self.h, ctypes.byref(p), _ptr(nk), _ptr(C), _stream(stream)),
                    "tai_degrees")
+
+    def compress(self, M, npair, params, sigma=None, V=None, stream=None):
+        """Rank of the low-rank compression of M (params.rank_tol > 0); the
+        singular values and vectors go into sigma [n] and V [n][n] if given."""
+        p = params if isinstance(params, tai_params) else make_params(params)
+        rank = ctypes.c_int32()
+        self.check(self.lib.tai_compress(self.h, _ptr(M), int(npair), ctypes.byref(p), ctypes.byref(rank),
+                                         _ptr(sigma), _ptr(V), _stream(stream)), "tai_compress")
+        return rank.value
 
     def screen_pairs(self, basis_arrays, tau, pairs, stream=None):
         """Kept pair indices into `pairs` (int32 device tensor of npair
@@ -301,6 +313,17 @@ def degrees(params, device=0):
     C = torch.empty((nq, n, n), dtype=torch.float64, device=dev)
     context(device).degrees(params, nk, C)
     return nk, C
+
+
+def compress(M, params, device=0):
+    """(rank, sigma [n], V [n][n]) of the low-rank compression of M."""
+    import torch
+    n = int(params.n)
+    dev = torch.device("cuda", device)
+    sigma = torch.empty(n, dtype=torch.float64, device=dev)
+    V = torch.empty((n, n), dtype=torch.float64, device=dev)
+    rank = context(device).compress(M, M.shape[2], params, sigma, V)
+    return rank, sigma, V
 
 
 def moments(basis, params, coef=None, device=0):

@@ -73,17 +73,19 @@ def test_null_context_rejected(lib):
 
 
 def _params(**kw):
-    base = dict(omega=0.5, nq=8, n=16, L=8.0, nodes=0, prec=0, degree_tol=0.0)
+    base = dict(omega=0.5, nq=8, n=16, L=8.0, nodes=0, prec=0, degree_tol=0.0, rank_tol=0.0)
     base.update(kw)
     return tai.tai_params(base["omega"], base["nq"], base["n"], base["L"], base["nodes"], base["prec"],
-                          base["degree_tol"])
+                          base["degree_tol"], base["rank_tol"])
 
 
 @pytest.mark.parametrize("bad", [dict(omega=0.0), dict(omega=-1.0), dict(omega=float("nan")),
                                  dict(omega=float("inf")), dict(nq=0), dict(nq=129), dict(n=1),
                                  dict(n=65), dict(L=0.0), dict(L=float("nan")), dict(nodes=2),
                                  dict(prec=5), dict(prec=-1), dict(degree_tol=-1e-9),
-                                 dict(degree_tol=float("nan")), dict(degree_tol=float("inf"))])
+                                 dict(degree_tol=float("nan")), dict(degree_tol=float("inf")),
+                                 dict(rank_tol=-1e-9), dict(rank_tol=1.0), dict(rank_tol=float("nan")),
+                                 dict(rank_tol=float("inf"))])
 def test_invalid_params(hctx, bad):
     p = _params(**bad)
     st = hctx.lib.tai_quadrature(hctx.h, ctypes.byref(p), None, None, None, None, None)
@@ -107,6 +109,24 @@ def test_degrees_argument_checks(hctx):
     assert hctx.lib.tai_degrees(hctx.h, ctypes.byref(bad), dummy, None, None) == tai.TAI_ERR_INVALID_ARG
     assert hctx.lib.tai_degrees(hctx.h, ctypes.byref(p), dummy, None, None) == tai.TAI_ERR_NOT_READY
     assert hctx.lib.tai_degrees(hctx.h, ctypes.byref(p), None, dummy, None) == tai.TAI_ERR_NOT_READY
+
+
+def test_compress_argument_checks(hctx):
+    dummy = ctypes.c_void_p(16)
+    rank = ctypes.c_int32(-7)
+    p = _params(rank_tol=1e-6)
+    lib, h = hctx.lib, hctx.h
+    assert lib.tai_compress(h, None, 10, ctypes.byref(p), ctypes.byref(rank), None, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_compress(h, dummy, 10, ctypes.byref(p), None, None, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_compress(h, dummy, 0, ctypes.byref(p), ctypes.byref(rank), None, None, None) == tai.TAI_ERR_INVALID_ARG
+    off = _params()
+    assert lib.tai_compress(h, dummy, 10, ctypes.byref(off), ctypes.byref(rank), None, None, None) == tai.TAI_ERR_INVALID_ARG
+    both = _params(rank_tol=1e-6, degree_tol=1e-8)
+    assert lib.tai_compress(h, dummy, 10, ctypes.byref(both), ctypes.byref(rank), None, None, None) == tai.TAI_ERR_UNSUPPORTED
+    assert lib.tai_assemble_B(h, dummy, 10, ctypes.byref(both), dummy, 10, None) == tai.TAI_ERR_UNSUPPORTED
+    assert lib.tai_compress(h, dummy, 10, ctypes.byref(p), ctypes.byref(rank), None, None, None) == tai.TAI_ERR_NOT_READY
+    assert rank.value == -7
+    assert lib.tai_assemble_B(h, dummy, 10, ctypes.byref(p), dummy, 10, None) == tai.TAI_ERR_NOT_READY
 
 
 def _basis(**mut):

@@ -1,0 +1,179 @@
+"""GPU parity of the low-rank compression of the moments (section 6.1, eqs.
+SVD and approxepsilon) through the C ABI: the rank exactly and the singular
+values and kept subspace against the oracle's SVD; B in all five arithmetics,
+J, the screened J and the orbital-basis J against the oracle's compressed
+operands on the same seeded inputs; at Nb = 400 the compressed B against the
+uncompressed one (the truncation bound that holds at any size).
+
+The GPU basis comes from the eigenpairs of the Gram matrix, the oracle's from
+an SVD of the stacked moments: the two agree on the kept subspace (hence on
+every compressed product) wherever the spectrum has a gap at the cut."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import tairef as T
+from paper_2210_13069_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+LOWP_TOL = {1: 1e-6, 2: 3e-5, 3: 1e-6, 4: 1e-6}
+
+
+def _normwise(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _tables(P):
+    t, w = T.time_nodes(P.omega, P.nq)
+    xi, _ = T.cheb_nodes(P.n, P.L, P.nodes)
+    return T.ktables(t, xi), w
+
+
+def _spd():
+    b = I.small_random(91, natoms=6, shells=("s", "p", "d"), box=4.0, alpha_lo=0.1, alpha_hi=60.0)
+    return b, I.Params(omega=0.3, nq=16, n=40, L=12.0)
+
+
+CASES = {"sp16": I.sp16, "spd": _spd}
+
+
+def _check_cut(sigma, R, tol):
+    # the count of kept directions is an FP64 decision on both sides; compare
+    # ranks only where no singular value lies within rounding of the cut
+    s = sigma / sigma[0]
+    assert np.all(np.abs(s - tol) > 1e-6 * tol)
+    count = max(1, int(np.sum(s > tol)))
+    assert R == min(len(s), 8 * ((count + 7) // 8))
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-5, 1e-7])
+@pytest.mark.parametrize("case", list(CASES))
+def test_rank_sigma_and_subspace(tai, case, tol):
+    b, P = CASES[case]()
+    P = dataclasses.replace(P, rank_tol=tol)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, kind=P.nodes)
+    Vr, sr, Rr = T.compression_basis(Mr, tol)
+    _check_cut(sr, Rr, tol)
+    Mg = tai.moments(b, P)
+    R, sg, Vg = tai.compress(Mg, P)
+    assert R == Rr
+    sg, Vg = sg.cpu().numpy(), Vg.cpu().numpy()
+    assert np.all(np.diff(sg) <= 0)
+    # both sides resolve sigma_r to about 1e-16 sigma_1 / sigma_r in relative terms
+    big = sr >= 1e-6 * sr[0]
+    np.testing.assert_allclose(sg[big], sr[big], rtol=1e-8)
+    assert np.max(np.abs(sg - sr)) <= 1e-12 * sr[0]
+    # unit, orthogonal columns and the same kept subspace
+    np.testing.assert_allclose(Vg.T @ Vg, np.eye(P.n), atol=1e-12)
+    Pg, Pr = Vg[:, :R] @ Vg[:, :R].T, Vr @ Vr.T
+    assert np.max(np.abs(Pg - Pr)) <= 1e-7
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("case", list(CASES))
+def test_compressed_B(tai, case, prec):
+    b, P = CASES[case]()
+    P = dataclasses.replace(P, rank_tol=1e-6)
+    K, w = _tables(P)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, kind=P.nodes)
+    V, s, R = T.compression_basis(Mr, P.rank_tol)
+    _check_cut(s, R, P.rank_tol)
+    assert R < P.n
+    Br = T.B_full(*T.compress(Mr, K, V), w)
+    Bg = tai.assemble_B(tai.moments(b, P), P, prec=prec).cpu().numpy().astype(np.float64)
+    tol = 1e-10 if prec == 0 else LOWP_TOL[prec]
+    err = _normwise(Bg, Br)
+    assert err <= tol, f"prec {prec}: normwise {err:.3e} > {tol}"
+    assert _normwise(Bg, Bg.T) <= (1e-14 if prec == 0 else tol)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_compressed_J(tai, prec):
+    import torch
+    b, P = _spd()
+    P = dataclasses.replace(P, rank_tol=1e-7)
+    K, w = _tables(P)
+    D = I.random_density(np.random.default_rng(21), b)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
+    V, s, R = T.compression_basis(Mr, P.rank_tol)
+    _check_cut(s, R, P.rank_tol)
+    Jr = T.J_grid(*T.compress(Mr, K, V), w, D)
+    Mg = tai.moments(b, P)
+    Jg = tai.apply_J(Mg, torch.as_tensor(D, device=Mg.device), P, prec=prec).cpu().numpy()
+    err = np.linalg.norm(Jg - Jr, 2) / np.linalg.norm(Jr, 2)
+    assert err <= (1e-10 if prec == 0 else 1e-6), err
+
+
+def test_compressed_J_screened_and_orbitals(tai):
+    """The screened J and the orbital-basis J with the basis of the kept
+    pairs' moments."""
+    import torch
+    b = I.small_random(92, natoms=8, shells=("s", "p"), box=5.0, alpha_lo=0.2, alpha_hi=30.0)
+    P = I.Params(omega=0.4, nq=12, n=24, L=9.0, rank_tol=1e-6)
+    K, w = _tables(P)
+    pairs = tai.screen_pairs(b, 1e-8)
+    kept = pairs.cpu().numpy().astype(np.int64)
+    assert len(kept) < b.npair
+    Mk = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, pairs=kept)
+    V, s, R = T.compression_basis(Mk, P.rank_tol)
+    _check_cut(s, R, P.rank_tol)
+    U, Kc = T.compress(Mk, K, V)
+    D = I.random_density(np.random.default_rng(22), b)
+    Jr = T.J_grid_pairs(U, Kc, w, D, kept)
+    Mg = tai.moments_pairs(b, P, pairs)
+    Jg = tai.apply_J_pairs(Mg, torch.as_tensor(D, device=Mg.device), pairs, P).cpu().numpy()
+    assert np.linalg.norm(Jg - Jr, 2) <= 1e-10 * np.linalg.norm(Jr, 2)
+    Q = np.random.default_rng(23).standard_normal((3, b.nb))
+    ref = np.zeros((3, 3))
+    for j in range(3):
+        Jao = T.J_grid_pairs(U, Kc, w, np.outer(Q[j], Q[j]), kept)
+        for i in range(3):
+            ref[i, j] = np.sum(np.outer(Q[i], Q[i]) * Jao)
+    got = tai.coulomb_mo(Mg, b.nb, torch.as_tensor(Q, device=Mg.device), P, pairs=pairs).cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_rank_eight_at_a_loose_tolerance(tai):
+    """A tolerance just below 1 keeps one direction, rounded up to the
+    smallest rank, 8."""
+    b, P = I.sp16()
+    P = dataclasses.replace(P, rank_tol=0.999)
+    K, w = _tables(P)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
+    V, s, R = T.compression_basis(Mr, P.rank_tol)
+    assert R == 8
+    Br = T.B_full(*T.compress(Mr, K, V), w)
+    Mg = tai.moments(b, P)
+    assert tai.compress(Mg, P)[0] == 8
+    for prec in (0, 1, 4):
+        Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+        assert _normwise(Bg, Br) <= (1e-10 if prec == 0 else LOWP_TOL[prec]), prec
+
+
+@pytest.mark.parametrize("prec", [0, 4])
+def test_full_size_compressed_against_uncompressed(tai, prec):
+    """Nb = 400 (80 200 pairs): the compressed B differs from the uncompressed
+    B of the same arithmetic by about the tolerance, with fewer directions
+    than nodes."""
+    import torch
+    b, P = I.spd400()
+    Mg = tai.moments(b, P)
+    tol = 1e-6
+    Pc = dataclasses.replace(P, rank_tol=tol)
+    R, sg, _ = tai.compress(Mg, Pc)
+    assert 20 <= R < P.n
+    npair = b.npair
+    dt = torch.float64 if prec == 0 else torch.float32
+    B = torch.empty((npair, npair), dtype=dt, device=Mg.device)
+    Bc = torch.empty_like(B)
+    tai.assemble_B(Mg, P, prec=prec, out=B)
+    tai.assemble_B(Mg, Pc, prec=prec, out=Bc)
+    scale = float(torch.max(torch.abs(B)))
+    diff = 0.0
+    for r0 in range(0, npair, 8192):
+        diff = max(diff, float(torch.max(torch.abs(B[r0:r0 + 8192].double() - Bc[r0:r0 + 8192].double()))))
+    assert diff / scale <= 20 * tol, diff / scale
+    del B, Bc
+    torch.cuda.empty_cache()
