@@ -97,10 +97,12 @@ gram_sum_kernel(const double* __restrict__ part, int nchunk, int nn, double* __r
 // unit eigenvectors, and *rank.
 constexpr int kJacobiThreads = 1024;
 
-// Off-diagonal entries at most rel * sqrt(|a_pp a_qq|) are left alone.
+// Off-diagonal entries at most rel * sqrt(|a_pp a_qq|), or at most
+// floor_rel * trace(G), are left alone: below the floor an entry is rounding
+// noise of the Gram matrix itself, and rotating on it would never settle.
 __global__ void __launch_bounds__(kJacobiThreads)
-jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, double* __restrict__ sigma,
-              double* __restrict__ V, int32_t* __restrict__ rank) {
+jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, double floor_rel,
+              double* __restrict__ sigma, double* __restrict__ V, int32_t* __restrict__ rank) {
   constexpr int S = kMaxN + 1;
   __shared__ double A[kMaxN * S];
   __shared__ double Q[kMaxN * S];
@@ -108,7 +110,13 @@ jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, doubl
   __shared__ int rp[kMaxN / 2], rq[kMaxN / 2];
   __shared__ int order[kMaxN];
   __shared__ int rotated;
+  __shared__ double floor_abs;
   const int m = n + (n & 1), half = m / 2;
+  if (threadIdx.x == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += fabs(G[i * n + i]);
+    floor_abs = fmax(floor_rel * tr, 1e-290);
+  }
   for (int e = threadIdx.x; e < m * m; e += kJacobiThreads) {
     const int i = e / m, j = e % m;
     A[i * S + j] = (i < n && j < n) ? G[i * n + j] : 0.0;
@@ -134,7 +142,7 @@ jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, doubl
         // rotate unless apq is negligible against the diagonal pair (a
         // relative test, so tiny eigenvalues of a semi-definite G are still
         // resolved) or below the underflow range
-        if (fabs(apq) > rel * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-290) {
+        if (fabs(apq) > rel * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
           // the rotation that zeroes A'(p, q): tan = t, the root of
           // t^2 + 2 theta t - 1 = 0 of smaller size, theta = (aqq - app) / (2 apq)
           const double theta = (aqq - app) / (2.0 * apq);
@@ -316,22 +324,26 @@ void launch_moments_in(const double* M, int n, int64_t npair, const double* V, i
   else if (n <= 48) hipLaunchKernelGGL(compress_moments_kernel<48>, g, dim3(256), 0, s, M, n, npair, V, R, U);
   else hipLaunchKernelGGL(compress_moments_kernel<64>, g, dim3(256), 0, s, M, n, npair, V, R, U);
 }
-void launch_gram_eig(const double* M, int n, int64_t npair, double tol, double rel, const CompressWork& w,
-                     double* V, hipStream_t s) {
+void launch_gram_eig(const double* M, int n, int64_t npair, double tol, double rel, double floor_rel,
+                     const CompressWork& w, double* V, hipStream_t s) {
   const int64_t chunk = (npair + w.nchunk - 1) / w.nchunk;
   const int nchunk = (int)((npair + chunk - 1) / chunk);
   hipLaunchKernelGGL(gram_kernel, dim3(nchunk), dim3(256), 0, s, M, n, npair, chunk, w.part);
   hipLaunchKernelGGL(gram_sum_kernel, dim3(nblk(n * n, 256)), dim3(256), 0, s, w.part, nchunk, n * n, w.G);
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, s, w.G, n, tol, rel, w.sigma, V, w.rank);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, s, w.G, n, tol, rel, floor_rel, w.sigma, V,
+                     w.rank);
 }
 }  // namespace
 
 hipError_t launch_compress_basis(const double* M, int n, int64_t npair, double tol, const CompressWork& w,
                                  double* Y, hipStream_t s) {
-  // V1 from W W^T need only be close: the refinement pass corrects it
-  launch_gram_eig(M, n, npair, tol, 1e-10, w, w.V1, s);
+  // V1 from W W^T need only be close: the refinement pass corrects it, and
+  // entries below 1e-14 of the trace are the Gram matrix's own rounding
+  launch_gram_eig(M, n, npair, tol, 1e-10, 1e-14, w, w.V1, s);
   launch_moments_in(M, n, npair, w.V1, n, Y, s);      // Y = V1^T W
-  launch_gram_eig(Y, n, npair, tol, 1e-15, w, w.V2, s);  // V2, sigma, rank from Y Y^T
+  // V2, sigma, rank from Y Y^T: a relative test only (its entries are
+  // rounded relative to sigma_r sigma_s)
+  launch_gram_eig(Y, n, npair, tol, 1e-13, 0.0, w, w.V2, s);
   hipLaunchKernelGGL(basis_product_kernel, dim3(1), dim3(256), 0, s, w.V1, w.V2, n, w.V);
   return hipGetLastError();
 }

@@ -177,3 +177,17 @@ def test_full_size_compressed_against_uncompressed(tai, prec):
     assert diff / scale <= 20 * tol, diff / scale
     del B, Bc
     torch.cuda.empty_cache()
+
+
+def test_compression_is_deterministic(tai):
+    """Two calls give the same rank, singular values, basis and B bit for bit
+    (fixed-order sums everywhere, no atomics)."""
+    import torch
+    b, P = _spd()
+    P = dataclasses.replace(P, rank_tol=1e-6)
+    Mg = tai.moments(b, P)
+    r1, s1, V1 = tai.compress(Mg, P)
+    r2, s2, V2 = tai.compress(Mg, P)
+    assert r1 == r2 and torch.equal(s1, s2) and torch.equal(V1, V2)
+    for prec in (0, 4):
+        assert torch.equal(tai.assemble_B(Mg, P, prec=prec), tai.assemble_B(Mg, P, prec=prec))
