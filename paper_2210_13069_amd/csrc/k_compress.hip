@@ -82,13 +82,20 @@ gram_kernel(const double* __restrict__ M, int n, int64_t npair, int64_t chunk, d
       if (a0 + i < n && b0 + k < n) out[(a0 + i) * n + b0 + k] = acc[i][k];
 }
 
+// G[e] = sum over the chunks of part[c][e]: 64 entries per work group, four
+// groups of threads each summing every fourth chunk in order, the four group
+// sums then added in a fixed order.
 __global__ void __launch_bounds__(256)
 gram_sum_kernel(const double* __restrict__ part, int nchunk, int nn, double* __restrict__ G) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= nn) return;
+  __shared__ double s_sum[4][64];
+  const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + l;
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * nn + e];
-  G[e] = s;
+  if (e < nn)
+    for (int c = g; c < nchunk; c += 4) s += part[(int64_t)c * nn + e];
+  s_sum[g][l] = s;
+  __syncthreads();
+  if (g == 0 && e < nn) G[e] = ((s_sum[0][l] + s_sum[1][l]) + s_sum[2][l]) + s_sum[3][l];
 }
 
 // Cyclic Jacobi on the symmetric n x n matrix G (n <= 64, padded to an even
@@ -220,7 +227,7 @@ template <int NMAX>
 __global__ void __launch_bounds__(256)
 compress_moments_kernel(const double* __restrict__ M, int n, int64_t npair, const double* __restrict__ V, int R,
                         double* __restrict__ U) {
-  __shared__ double s_v[NMAX * NMAX];
+  __shared__ __align__(16) double s_v[NMAX * NMAX];
   for (int e = threadIdx.x; e < n * R; e += 256) {
     const int a = e / R, r = e % R;
     s_v[a * NMAX + r] = V[a * n + r];
@@ -234,12 +241,25 @@ compress_moments_kernel(const double* __restrict__ M, int n, int64_t npair, cons
 #pragma unroll
   for (int a = 0; a < NMAX; ++a) m[a] = a < n ? Md[(int64_t)a * npair + q] : 0.0;
   double* Ud = U + (int64_t)d * R * npair;
-  for (int r = 0; r < R; ++r) {
-    double s = 0.0;
+  int r = 0;
+  for (; r + 1 < R; r += 2) {
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int a = 0; a < NMAX; ++a)
-      if (a < n) s += s_v[a * NMAX + r] * m[a];
-    Ud[(int64_t)r * npair + q] = s;
+      if (a < n) {
+        const double2 v = *reinterpret_cast<const double2*>(&s_v[a * NMAX + r]);
+        s0 += v.x * m[a];
+        s1 += v.y * m[a];
+      }
+    Ud[(int64_t)r * npair + q] = s0;
+    Ud[(int64_t)(r + 1) * npair + q] = s1;
+  }
+  if (r < R) {
+    double s0 = 0.0;
+#pragma unroll
+    for (int a = 0; a < NMAX; ++a)
+      if (a < n) s0 += s_v[a * NMAX + r] * m[a];
+    Ud[(int64_t)r * npair + q] = s0;
   }
 }
 
@@ -291,7 +311,7 @@ compress_tables_kernel(const double* __restrict__ K, int n, const double* __rest
 
 int compress_nchunk(int64_t npair) {
   const int64_t c = (npair + kGramPairs - 1) / kGramPairs;
-  return (int)(c < 512 ? c : 512);
+  return (int)(c < 2048 ? c : 2048);
 }
 
 size_t compress_work_bytes(int n, int nq, int64_t npair) {
@@ -329,7 +349,7 @@ void launch_gram_eig(const double* M, int n, int64_t npair, double tol, double r
   const int64_t chunk = (npair + w.nchunk - 1) / w.nchunk;
   const int nchunk = (int)((npair + chunk - 1) / chunk);
   hipLaunchKernelGGL(gram_kernel, dim3(nchunk), dim3(256), 0, s, M, n, npair, chunk, w.part);
-  hipLaunchKernelGGL(gram_sum_kernel, dim3(nblk(n * n, 256)), dim3(256), 0, s, w.part, nchunk, n * n, w.G);
+  hipLaunchKernelGGL(gram_sum_kernel, dim3(nblk(n * n, 64)), dim3(256), 0, s, w.part, nchunk, n * n, w.G);
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, s, w.G, n, tol, rel, floor_rel, w.sigma, V,
                      w.rank);
 }
