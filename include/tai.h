@@ -175,9 +175,27 @@ int tai_degrees(tai_ctx* ctx, const tai_params* params, int32_t* nk, double* C, 
    serves the three directions and every quadrature node.  Forming W W^T
    resolves sigma_r to about 1e-16 sigma_1^2 / sigma_r, so ranks cut at
    rank_tol >= 1e-7 rest on well-resolved values.  rank_tol must be > 0
-   (TAI_ERR_INVALID_ARG otherwise).  The call waits on the host for the rank. */
+   (TAI_ERR_INVALID_ARG otherwise).  The call waits on the host for the rank.
+   With U (DEVICE double, room for [3][n][npair]) and/or Kc (DEVICE double,
+   room for [nq][n][n]) non-NULL the compressed operands are written too:
+   U[d][r][q] = sum_a V[a][r] M[d][a][q] for r < R, packed as [3][R][npair],
+   and Kc[k] = V_R^T K_k V_R packed as [nq][R][R] (eq. approxepsilon); they
+   serve tai_apply_J_compressed for as long as the moments do not change. */
 int tai_compress(tai_ctx* ctx, const double* M, int32_t npair, const tai_params* params, int32_t* rank,
-                 double* sigma, double* V, void* stream);
+                 double* sigma, double* V, double* U, double* Kc, void* stream);
+
+/* J from prepared compressed operands (tai_compress with U and Kc): the J of
+   tai_apply_J (or tai_apply_J_pairs when pairs != NULL, npk pairs listed) on
+   the R^3 grid, with no basis computed and no host wait, so that one
+   compression serves every J build while the moments stay fixed (a
+   self-consistent-field loop changes D only).  U: DEVICE double [3][R][npk or
+   npair]; Kc: DEVICE double [nq][R][R]; 2 <= R <= params->n; params gives
+   omega, nq, n, L, nodes (for the weights w_k) and prec (TAI_FP64 or
+   TAI_FP32); rank_tol and degree_tol are not read.  The result equals that of
+   tai_apply_J with the same rank_tol bit for bit. */
+int tai_apply_J_compressed(tai_ctx* ctx, const double* U, int32_t nb, const int32_t* pairs, int32_t npk,
+                           int32_t R, const double* Kc, const tai_params* params, const double* D, double* J,
+                           void* stream);
 
 /* 1D moments (eq. defV, Lagrange basis), FP64 on the device:
      M[d][a][p] = int_{-L}^{L} g_{mu,d}(x) g_{nu,d}(x) l_a(x) dx

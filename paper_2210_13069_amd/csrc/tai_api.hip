@@ -591,7 +591,7 @@ static int compress_impl(tai_ctx* c, const double* M, int64_t npair, const tai_p
                          bool operands, hipStream_t s, tai::CompressWork* w, int* R);
 
 int tai_compress(tai_ctx* c, const double* M, int32_t npair, const tai_params* p, int32_t* rank, double* sigma,
-                 double* V, void* stream) {
+                 double* V, double* U, double* Kc, void* stream) {
   int r = check_ctx(c);
   if (r) return r;
   if ((r = validate_params(c, p))) return r;
@@ -602,15 +602,63 @@ int tai_compress(tai_ctx* c, const double* M, int32_t npair, const tai_params* p
   hipStream_t s = static_cast<hipStream_t>(stream);
   tai::CompressWork w;
   int R = 0;
-  NodeTables none{};
-  if ((r = compress_impl(c, M, npair, p, none, false, s, &w, &R))) return r;
-  const size_t n = p->n;
   hipError_t e;
+  const bool operands = U || Kc;
+  NodeTables tb{};
+  if (operands) {
+    if ((r = ensure(c, c->nodes, tai::node_tables_bytes(p->nq, p->n)))) return r;
+    tb = tai::carve_node_tables(c->nodes.p, p->nq, p->n);
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, 0.0, tb, s);
+    if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  }
+  if ((r = compress_impl(c, M, npair, p, tb, operands, s, &w, &R))) return r;
+  const size_t n = p->n;
   if (sigma && (e = hipMemcpyAsync(sigma, w.sigma, 8 * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(c, e, "copy sigma");
   if (V && (e = hipMemcpyAsync(V, w.V, 8 * n * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(c, e, "copy V");
+  if (U && (e = hipMemcpyAsync(U, c->cmpU.p, 8 * 3 * (size_t)R * npair, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(c, e, "copy U");
+  if (Kc && (e = hipMemcpyAsync(Kc, w.Kc, 8 * (size_t)p->nq * R * R, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(c, e, "copy Kc");
   *rank = R;
+  return TAI_OK;
+}
+
+int tai_apply_J_compressed(tai_ctx* c, const double* U, int32_t nb, const int32_t* pairs, int32_t npk, int32_t R,
+                           const double* Kc, const tai_params* p, const double* D, double* J, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!U || !Kc || !D || !J) return fail(c, TAI_ERR_INVALID_ARG, "U, Kc, D or J is NULL");
+  if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
+  if (npair_of(nb) > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
+  if (pairs && (npk < 1 || npk > npair_of(nb))) return fail(c, TAI_ERR_INVALID_ARG, "npk must be in [1, npair]");
+  if (R < 2 || R > p->n) return fail(c, TAI_ERR_INVALID_ARG, "R must be in [2, n]");
+  if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_compressed supports prec TAI_FP64 and TAI_FP32");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nq = p->nq;
+  const int64_t npair = pairs ? npk : npair_of(nb);
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, p->n)))) return r;
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, p->n);
+  hipError_t e;
+  {
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, nq, p->n, p->L, p->nodes, 0.0, tb, s);  // the weights w_k
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  NodeTables tbp = tb;
+  tbp.K = const_cast<double*>(Kc);
+  if ((r = ensure(c, c->jwork, tai::j_work_bytes(p->prec, nq, R, (int)npair)))) return r;
+  tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, R, (int)npair);
+  {
+    Timed tm(c, kStApplyJ, s);
+    e = tai::launch_apply_j(p->prec, U, nb, (int)npair, pairs, R, nq, tbp, D, J, w, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "apply_J kernels");
   return TAI_OK;
 }
 

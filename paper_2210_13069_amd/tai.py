@@ -29,7 +29,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 # exported symbols declared in include/tai.h
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
            "tai_quadrature", "tai_degrees", "tai_compress", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
-           "tai_apply_J_pairs", "tai_coulomb_mo", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
+           "tai_apply_J_pairs", "tai_apply_J_compressed", "tai_coulomb_mo", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
            "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched", "compress"]
 
@@ -89,7 +89,9 @@ def load_library(path=LIB_PATH):
     lib.tai_quadrature.argtypes = [vp, ctypes.POINTER(tai_params), vp, vp, vp, vp, vp]
     lib.tai_degrees.argtypes = [vp, ctypes.POINTER(tai_params), vp, vp, vp]
     lib.tai_compress.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), ctypes.POINTER(ctypes.c_int32),
-                                 vp, vp, vp]
+                                 vp, vp, vp, vp, vp]
+    lib.tai_apply_J_compressed.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int32, vp,
+                                           ctypes.POINTER(tai_params), vp, vp, vp]
     lib.tai_screen_pairs.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.c_double, vp,
                                      ctypes.POINTER(ctypes.c_int32), vp]
     lib.tai_moments_pairs.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.POINTER(tai_params), vp, ctypes.c_int32,
@@ -193,14 +195,22 @@ class Context:
         self.check(self.lib.tai_degrees(self.h, ctypes.byref(p), _ptr(nk), _ptr(C), _stream(stream)),
                    "tai_degrees")
 
-    def compress(self, M, npair, params, sigma=None, V=None, stream=None):
+    def compress(self, M, npair, params, sigma=None, V=None, U=None, Kc=None, stream=None):
         """Rank of the low-rank compression of M (params.rank_tol > 0); the
-        singular values and vectors go into sigma [n] and V [n][n] if given."""
+        singular values and vectors go into sigma [n] and V [n][n], the
+        compressed operands into U (room for [3][n][npair]) and Kc (room for
+        [nq][n][n]) if given."""
         p = params if isinstance(params, tai_params) else make_params(params)
         rank = ctypes.c_int32()
         self.check(self.lib.tai_compress(self.h, _ptr(M), int(npair), ctypes.byref(p), ctypes.byref(rank),
-                                         _ptr(sigma), _ptr(V), _stream(stream)), "tai_compress")
+                                         _ptr(sigma), _ptr(V), _ptr(U), _ptr(Kc), _stream(stream)), "tai_compress")
         return rank.value
+
+    def apply_J_compressed(self, U, nb, R, Kc, params, D, J, pairs=None, npk=0, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        self.check(self.lib.tai_apply_J_compressed(self.h, _ptr(U), int(nb), _ptr(pairs), int(npk), int(R), _ptr(Kc),
+                                                   ctypes.byref(p), _ptr(D), _ptr(J), _stream(stream)),
+                   "tai_apply_J_compressed")
 
     def screen_pairs(self, basis_arrays, tau, pairs, stream=None):
         """Kept pair indices into `pairs` (int32 device tensor of npair
@@ -324,6 +334,27 @@ def compress(M, params, device=0):
     V = torch.empty((n, n), dtype=torch.float64, device=dev)
     rank = context(device).compress(M, M.shape[2], params, sigma, V)
     return rank, sigma, V
+
+
+def compress_operands(M, params, device=0):
+    """(rank R, U [3][R][npair], Kc [nq][R][R]): the compressed operands of M."""
+    import torch
+    n, nq, npair = int(params.n), int(params.nq), int(M.shape[2])
+    dev = torch.device("cuda", device)
+    U = torch.empty(3 * n * npair, dtype=torch.float64, device=dev)
+    Kc = torch.empty(nq * n * n, dtype=torch.float64, device=dev)
+    R = context(device).compress(M, npair, params, U=U, Kc=Kc)
+    return R, U[:3 * R * npair].view(3, R, npair), Kc[:nq * R * R].view(nq, R, R)
+
+
+def apply_J_compressed(U, Kc, D, params, prec=FP64, pairs=None, device=0):
+    """J (nb x nb FP64) from prepared compressed operands."""
+    import torch
+    nb = int(D.shape[0])
+    J = torch.empty((nb, nb), dtype=torch.float64, device=U.device)
+    npk = 0 if pairs is None else int(pairs.shape[0])
+    context(device).apply_J_compressed(U, nb, int(U.shape[1]), Kc, make_params(params, prec), D, J, pairs, npk)
+    return J
 
 
 def moments(basis, params, coef=None, device=0):

@@ -116,17 +116,34 @@ def test_compress_argument_checks(hctx):
     rank = ctypes.c_int32(-7)
     p = _params(rank_tol=1e-6)
     lib, h = hctx.lib, hctx.h
-    assert lib.tai_compress(h, None, 10, ctypes.byref(p), ctypes.byref(rank), None, None, None) == tai.TAI_ERR_INVALID_ARG
-    assert lib.tai_compress(h, dummy, 10, ctypes.byref(p), None, None, None, None) == tai.TAI_ERR_INVALID_ARG
-    assert lib.tai_compress(h, dummy, 0, ctypes.byref(p), ctypes.byref(rank), None, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_compress(h, None, 10, ctypes.byref(p), ctypes.byref(rank), None, None, None, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_compress(h, dummy, 10, ctypes.byref(p), None, None, None, None, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_compress(h, dummy, 0, ctypes.byref(p), ctypes.byref(rank), None, None, None, None, None) == tai.TAI_ERR_INVALID_ARG
     off = _params()
-    assert lib.tai_compress(h, dummy, 10, ctypes.byref(off), ctypes.byref(rank), None, None, None) == tai.TAI_ERR_INVALID_ARG
+    assert lib.tai_compress(h, dummy, 10, ctypes.byref(off), ctypes.byref(rank), None, None, None, None, None) == tai.TAI_ERR_INVALID_ARG
     both = _params(rank_tol=1e-6, degree_tol=1e-8)
-    assert lib.tai_compress(h, dummy, 10, ctypes.byref(both), ctypes.byref(rank), None, None, None) == tai.TAI_ERR_UNSUPPORTED
+    assert lib.tai_compress(h, dummy, 10, ctypes.byref(both), ctypes.byref(rank), None, None, None, None, None) == tai.TAI_ERR_UNSUPPORTED
     assert lib.tai_assemble_B(h, dummy, 10, ctypes.byref(both), dummy, 10, None) == tai.TAI_ERR_UNSUPPORTED
-    assert lib.tai_compress(h, dummy, 10, ctypes.byref(p), ctypes.byref(rank), None, None, None) == tai.TAI_ERR_NOT_READY
+    assert lib.tai_compress(h, dummy, 10, ctypes.byref(p), ctypes.byref(rank), None, None, None, None, None) == tai.TAI_ERR_NOT_READY
     assert rank.value == -7
     assert lib.tai_assemble_B(h, dummy, 10, ctypes.byref(p), dummy, 10, None) == tai.TAI_ERR_NOT_READY
+
+
+def test_apply_J_compressed_argument_checks(hctx):
+    dummy = ctypes.c_void_p(16)
+    lib, h = hctx.lib, hctx.h
+    p = _params()
+    call = lambda U=dummy, nb=4, pairs=None, npk=0, R=8, Kc=dummy, params=p, D=dummy, J=dummy: \
+        lib.tai_apply_J_compressed(h, U, nb, pairs, npk, R, Kc, ctypes.byref(params), D, J, None)
+    assert call(U=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(Kc=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(nb=0) == tai.TAI_ERR_INVALID_ARG
+    assert call(R=1) == tai.TAI_ERR_INVALID_ARG
+    assert call(R=17) == tai.TAI_ERR_INVALID_ARG           # n = 16
+    assert call(pairs=dummy, npk=0) == tai.TAI_ERR_INVALID_ARG
+    assert call(params=_params(prec=4)) == tai.TAI_ERR_UNSUPPORTED
+    assert call() == tai.TAI_ERR_NOT_READY
+    assert call(pairs=dummy, npk=5) == tai.TAI_ERR_NOT_READY
 
 
 def _basis(**mut):

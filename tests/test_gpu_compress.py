@@ -191,3 +191,27 @@ def test_compression_is_deterministic(tai):
     assert r1 == r2 and torch.equal(s1, s2) and torch.equal(V1, V2)
     for prec in (0, 4):
         assert torch.equal(tai.assemble_B(Mg, P, prec=prec), tai.assemble_B(Mg, P, prec=prec))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_J_from_prepared_operands(tai, prec):
+    """One compression serves several J builds: tai_apply_J_compressed on the
+    operands from tai_compress equals tai_apply_J with the same rank_tol bit
+    for bit, for two densities and for a screened pair list."""
+    import torch
+    b, P = _spd()
+    P = dataclasses.replace(P, rank_tol=1e-6)
+    Mg = tai.moments(b, P)
+    R, U, Kc = tai.compress_operands(Mg, P)
+    assert R < P.n and U.shape == (3, R, b.npair) and Kc.shape == (P.nq, R, R)
+    for seed in (31, 32):
+        D = torch.as_tensor(I.random_density(np.random.default_rng(seed), b), device=Mg.device)
+        Jref = tai.apply_J(Mg, D, P, prec=prec)
+        Jc = tai.apply_J_compressed(U, Kc, D, P, prec=prec)
+        assert torch.equal(Jc, Jref)
+    pairs = tai.screen_pairs(b, 1e-6)
+    assert pairs.shape[0] < b.npair
+    Mk = tai.moments_pairs(b, P, pairs)
+    Rk, Uk, Kck = tai.compress_operands(Mk, P)
+    Jref = tai.apply_J_pairs(Mk, D, pairs, P, prec=prec)
+    assert torch.equal(tai.apply_J_compressed(Uk, Kck, D, P, prec=prec, pairs=pairs), Jref)
