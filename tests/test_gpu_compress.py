@@ -215,3 +215,48 @@ def test_apply_J_from_prepared_operands(tai, prec):
     Rk, Uk, Kck = tai.compress_operands(Mk, P)
     Jref = tai.apply_J_pairs(Mk, D, pairs, P, prec=prec)
     assert torch.equal(tai.apply_J_compressed(Uk, Kck, D, P, prec=prec, pairs=pairs), Jref)
+
+
+@pytest.mark.parametrize("n,nodes", [(29, 0), (41, 0), (24, 1)])
+def test_compressed_B_odd_n_and_gauss_nodes(tai, n, nodes):
+    """Odd n (the Jacobi sweep pads to an even order with a zero row and
+    column; n = 41 is no multiple of 8, the rank's rounding step) and
+    Chebyshev-Gauss nodes, FP64 and F16X3 against the oracle's compressed
+    operands."""
+    b = I.small_random(93, natoms=4, shells=("s", "p", "d"), box=3.0, alpha_lo=0.2, alpha_hi=20.0)
+    P = I.Params(omega=0.5, nq=10, n=n, L=8.0, nodes=nodes, rank_tol=1e-6)
+    K, w = _tables(P)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, kind=P.nodes)
+    V, s, R = T.compression_basis(Mr, P.rank_tol)
+    _check_cut(s, R, P.rank_tol)
+    Br = T.B_full(*T.compress(Mr, K, V), w)
+    Mg = tai.moments(b, P)
+    Rg, sg, _ = tai.compress(Mg, P)
+    assert Rg == R
+    for prec in (0, 4):
+        Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+        assert _normwise(Bg, Br) <= (1e-10 if prec == 0 else LOWP_TOL[prec]), (n, nodes, prec, R)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_compressed_contracted_J(tai, prec):
+    """J over contracted functions with the compression of the primitive
+    moments: the contracted J of the oracle's compressed grid J."""
+    import torch
+    from test_gpu_contracted import _contracted
+    prim, fmap, coef = _contracted(95)
+    nb = int(fmap[-1]) + 1
+    P = I.Params(omega=0.4, nq=12, n=32, L=8.0, rank_tol=1e-6)
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((nb, nb))
+    D = A + A.T
+    K, w = _tables(P)
+    Mr = T.moments(prim.center, prim.alpha, prim.lxyz, P.L, P.n, coef=coef)
+    V, s, R = T.compression_basis(Mr, P.rank_tol)
+    _check_cut(s, R, P.rank_tol)
+    U, Kc = T.compress(Mr, K, V)
+    ref = T.contract_functions(T.J_grid(U, Kc, w, T.expand_density(D, fmap)), fmap)
+    Mg = tai.moments(prim, P, coef=coef)
+    J = tai.apply_J_contracted(Mg, prim.nb, fmap, torch.as_tensor(D, device=Mg.device), P, prec=prec).cpu().numpy()
+    err = np.linalg.norm(J - ref, 2) / np.linalg.norm(ref, 2)
+    assert err <= (1e-10 if prec == 0 else 1e-6), err
