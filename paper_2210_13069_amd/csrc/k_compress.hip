@@ -10,8 +10,8 @@
 //  * Eigenpairs of G (sigma_r^2 and the left singular vectors of W) by the
 //    cyclic Jacobi method in one work group: the n(n-1)/2 rotations of a
 //    sweep are applied in n-1 rounds of n/2 disjoint pairs (round-robin
-//    order), each round a parallel column pass and a parallel row pass over
-//    G in LDS, the columns of V rotated alongside.  Sweeps stop when a whole
+//    order), each round one parallel in-place pass over the 2 x 2 blocks of G
+//    in LDS, the columns of V rotated alongside.  Sweeps stop when a whole
 //    sweep finds every off-diagonal entry negligible against its diagonal
 //    pair.  Eigenvalues are sorted in decreasing order; R is the count of
 //    sigma_r > tol * sigma_1 (at least one) rounded up to a multiple of 8 and
@@ -164,29 +164,33 @@ jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, doubl
         rs[i] = s;
       }
       __syncthreads();
-      // columns: (A[:,p], A[:,q]) <- (c A[:,p] - s A[:,q], s A[:,p] + c A[:,q]); V likewise
-      for (int e = threadIdx.x; e < m * half; e += kJacobiThreads) {
-        const int r = e / half, i = e % half;
-        const int p = rp[i], q = rq[i];
-        const double c = rc[i], s = rs[i];
-        const double x = A[r * S + p], y = A[r * S + q];
-        A[r * S + p] = c * x - s * y;
-        A[r * S + q] = s * x + c * y;
-        const double u = Q[r * S + p], v = Q[r * S + q];
-        Q[r * S + p] = c * u - s * v;
-        Q[r * S + q] = s * u + c * v;
-      }
-      __syncthreads();
-      // rows: (A[p,:], A[q,:]) <- (c A[p,:] - s A[q,:], s A[p,:] + c A[q,:]);
-      // the rotated entries (p, q) and (q, p) are zero by construction of the angle
-      for (int e = threadIdx.x; e < m * half; e += kJacobiThreads) {
-        const int r = e / half, i = e % half;
-        const int p = rp[i], q = rq[i];
-        const double c = rc[i], s = rs[i];
-        const double x = A[p * S + r], y = A[q * S + r];
-        const bool hit = s != 0.0;
-        A[p * S + r] = (hit && r == q) ? 0.0 : c * x - s * y;
-        A[q * S + r] = (hit && r == p) ? 0.0 : s * x + c * y;
+      // A <- J^T A J and V <- V J for the block-diagonal J of this round's
+      // disjoint rotations: entry block (p_i, q_i) x (p_j, q_j) of A depends
+      // only on the same block, so every 2 x 2 block is updated in place by
+      // one thread (columns by rotation j, then rows by rotation i); the
+      // rotated entries (p, q), (q, p) are zero by construction of the angle
+      const int nblkA = half * half;
+      for (int e = threadIdx.x; e < nblkA + m * half; e += kJacobiThreads) {
+        if (e < nblkA) {
+          const int i = e / half, j = e % half;
+          const int p = rp[i], q = rq[i], u = rp[j], v = rq[j];
+          const double ci = rc[i], si = rs[i], cj = rc[j], sj = rs[j];
+          const double a_pu = A[p * S + u], a_pv = A[p * S + v], a_qu = A[q * S + u], a_qv = A[q * S + v];
+          const double b_pu = cj * a_pu - sj * a_pv, b_pv = sj * a_pu + cj * a_pv;
+          const double b_qu = cj * a_qu - sj * a_qv, b_qv = sj * a_qu + cj * a_qv;
+          const bool hit = i == j && si != 0.0;
+          A[p * S + u] = ci * b_pu - si * b_qu;
+          A[q * S + u] = hit ? 0.0 : si * b_pu + ci * b_qu;
+          A[p * S + v] = hit ? 0.0 : ci * b_pv - si * b_qv;
+          A[q * S + v] = si * b_pv + ci * b_qv;
+        } else {
+          const int f = e - nblkA, r = f / half, j = f % half;
+          const int u = rp[j], v = rq[j];
+          const double c = rc[j], sn = rs[j];
+          const double x = Q[r * S + u], y = Q[r * S + v];
+          Q[r * S + u] = c * x - sn * y;
+          Q[r * S + v] = sn * x + c * y;
+        }
       }
       __syncthreads();
     }
