@@ -458,6 +458,23 @@ def main():
         japply["coulomb_mo_fp64"] = {"norb": NORB, "ms_per_call": round(ms_mo, 3),
                                      "ms_per_orbital": round(ms_mo / NORB, 4),
                                      "symmetry_rel": float((Jmo - Jmo.T).abs().max() / Jmo.abs().max())}
+        # the same with the moments compressed on every call (rank_tol > 0):
+        # the compression is paid once per call for all NORB orbitals
+        jparams_mc = tai.make_params(dataclasses.replace(jP, rank_tol=RANK_TOL_J), tai.FP64)
+        Jmo_c = torch.empty_like(Jmo)
+        log(f"orbital-basis Coulomb matrix fp64, compressed: norb={NORB} rank_tol={RANK_TOL_J}")
+        for it in range(W + K):
+            if it == W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            ctx.coulomb_mo(Mj, jb.nb, jparams_mc, Qo, NORB, Jmo_c)
+        torch.cuda.synchronize()
+        ms_mc = (time.perf_counter() - t0) * 1e3 / K
+        japply["coulomb_mo_fp64_compressed"] = {
+            "norb": NORB, "rank_tol": RANK_TOL_J, "ms_per_call": round(ms_mc, 3),
+            "speedup_vs_uncompressed": round(ms_mo / ms_mc, 3),
+            "normwise_vs_uncompressed_gpu": float((Jmo_c - Jmo).abs().max() / Jmo.abs().max())}
+        del Jmo_c
         del Mj, Jj, Js, Mjs, Jmo
         torch.cuda.empty_cache()
 
