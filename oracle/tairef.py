@@ -598,6 +598,50 @@ def coulomb_mo(M, K, w, Q):
     return np.array([[np.sum(Dm[i] * Jao[j]) for j in range(norb)] for i in range(norb)])
 
 
+def pair_index_matrix(nb):
+    """P[mu][nu] = index of the unordered pair (min, max) in the pair list."""
+    mu, nu = np.meshgrid(np.arange(nb), np.arange(nb), indexing="ij")
+    lo, hi = np.minimum(mu, nu), np.maximum(mu, nu)
+    return lo * nb - lo * (lo - 1) // 2 + (hi - lo)
+
+
+def exchange_direct(B, Q):
+    """Long-range exchange matrix (appendix B, eq. exchange) written out over
+    the pair matrix: K(mu, nu) = 2 sum_j sum_{lambda, kappa} q_j(lambda)
+    q_j(kappa) B(mu lambda, kappa nu), with B over ordered index pairs read
+    from the unordered pair matrix B (npair x npair)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    nb = Q.shape[1]
+    P = pair_index_matrix(nb)
+    B4 = B[P[:, :, None, None], P[None, None, :, :]]     # [mu, lambda, kappa, nu]
+    D = Q.T @ Q                                          # sum_j q_j q_j^T
+    return 2.0 * np.einsum("mlkn,lk->mn", B4, D)
+
+
+def exchange_grid(M, K, w, Q):
+    """The exchange matrix by the factorized form of appendix B: for orbital
+    j and function mu the n^3 tensor X_{j mu} = sum_lambda q_j(lambda)
+    prod_d m_{(mu lambda), d} (the product of the orbital's coefficients with
+    the moment rows of mu), then K(mu, nu) = 2 sum_j < X_{j mu}, Phi_{j nu} >
+    with Phi = (2/sqrt(pi)) sum_k w_k X x_1 K_k x_2 K_k x_3 K_k."""
+    Q = np.asarray(Q, dtype=np.float64)
+    norb, nb = Q.shape
+    P = pair_index_matrix(nb)
+    n = M.shape[1]
+    X = np.zeros((norb, nb, n, n, n))
+    for mu in range(nb):
+        cols = P[mu]                                     # pairs (mu, lambda), lambda = 0..nb-1
+        X[:, mu] = np.einsum("jl,al,bl,cl->jabc", Q, M[0][:, cols], M[1][:, cols], M[2][:, cols], optimize=True)
+    Phi = np.zeros_like(X)
+    for k in range(K.shape[0]):
+        T = np.einsum("ia,jmabc->jmibc", K[k], X, optimize=True)
+        T = np.einsum("jb,xmibc->xmijc", K[k], T, optimize=True)
+        T = np.einsum("kc,xmijc->xmijk", K[k], T, optimize=True)
+        Phi += w[k] * T
+    Phi *= 2.0 / SQRT_PI
+    return 2.0 * np.einsum("jmabc,jnabc->mn", X, Phi, optimize=True)
+
+
 def J_direct_rows(M, K, w, D, rows):
     """J_p = sum_q B(p,q) Dt_q for the given pair rows, with the rows of B
     from Theorem 3.1 (eq. Coul in the atomic-orbital basis)."""
