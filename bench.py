@@ -477,6 +477,31 @@ def main():
         del Jmo_c
         del Mj, Jj, Js, Mjs, Jmo
         torch.cuda.empty_cache()
+        # the long-range exchange matrix (appendix B) on the Nb = 64 workload:
+        # one grid tensor X_{j mu} and its Phi per (orbital, function)
+        xb, xP = I.sp16()
+        xba = tai.BasisArrays(xb)
+        norb_x = 8
+        Mx = torch.empty((3, xP.n, xb.npair), dtype=torch.float64, device=dev)
+        ctx.moments(xba, xP, Mx)
+        Qx = torch.as_tensor(np.random.default_rng(19).standard_normal((norb_x, xb.nb)) / np.sqrt(xb.nb), device=dev)
+        Kx = torch.empty((xb.nb, xb.nb), dtype=torch.float64, device=dev)
+        exchange = {"workload": f"sp16: Nb={xb.nb}, {xb.npair} pairs, nq={xP.nq}, n={xP.n}, {norb_x} orbitals",
+                    "tensors": norb_x * xb.nb}
+        for name, Px, prec in (("fp64", xP, tai.FP64), ("fp32", xP, tai.FP32),
+                               ("fp64_compressed", dataclasses.replace(xP, rank_tol=RANK_TOL_J), tai.FP64)):
+            xparams = tai.make_params(Px, prec)
+            log(f"exchange {name}: Nb={xb.nb} norb={norb_x}")
+            for it in range(W + K):
+                if it == W:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                ctx.exchange(Mx, xb.nb, xparams, Qx, norb_x, Kx)
+            torch.cuda.synchronize()
+            exchange[name] = {"ms_per_call": round((time.perf_counter() - t0) * 1e3 / K, 3),
+                              "symmetry_rel": float((Kx - Kx.T).abs().max() / Kx.abs().max())}
+        japply["exchange"] = exchange
+        del Mx, Kx
 
     # ---------------- the device's own sustained peaks ------------------------
     if not args.only_headline:

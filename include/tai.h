@@ -274,6 +274,22 @@ int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* par
 int tai_coulomb_mo(tai_ctx* ctx, const double* M, int32_t nb, const int32_t* pairs, int32_t npk,
                    const tai_params* params, const double* Q, int32_t norb, double* Jmo, void* stream);
 
+/* Long-range exchange matrix (appendix B, eq. exchange):
+   Kx(mu, nu) = 2 sum_j sum_{lambda, kappa} q_j(lambda) q_j(kappa) B(mu lambda, kappa nu)
+   over ordered index pairs, for the orbitals Q (DEVICE double [norb][nb],
+   1 <= norb <= 1024), by the paper's factorized form: for each orbital j and
+   function mu the n^3 grid tensor X_{j mu} = sum_lambda q_j(lambda) m_(mu lambda)
+   (a rho over the pairs that hold mu) and its Phi_{j nu} as in tai_apply_J,
+   then Kx(mu, nu) = 2 sum_j <X_{j mu}, Phi_{j nu}>.  M: DEVICE double
+   [3][n][npair] (or [3][n][npk] with a pair list, as tai_apply_J_pairs);
+   Kx: DEVICE double [nb][nb], written in full.  The context keeps
+   2 norb nb n^3 doubles of grid tensors (at most 64 GiB, else
+   TAI_ERR_INVALID_ARG).  prec TAI_FP64 or TAI_FP32 (the rho contractions);
+   rank_tol > 0 runs it on the compressed grid.  Each (j, mu) costs one rho
+   over all listed pairs, so the call is meant for small bases. */
+int tai_exchange(tai_ctx* ctx, const double* M, int32_t nb, const int32_t* pairs, int32_t npk,
+                 const tai_params* params, const double* Q, int32_t norb, double* Kx, void* stream);
+
 /* ---- contracted basis functions (eq. basis, I_mu > 1 primitives) ---------- */
 
 /* A contracted basis is passed as its primitives: a tai_basis of nbp

@@ -435,6 +435,42 @@ orbital_pairs_kernel(const double* __restrict__ q, int nb, int64_t npair, const 
   Dt[p] = pair_of(pairs, nb, p, mu, nu) ? q[mu] * q[nu] * (mu == nu ? 1.0 : 2.0) : 0.0;
 }
 
+// Exchange (appendix B): the pair weights of X_{j mu} = sum_lambda q_j(lambda)
+// m_(mu lambda), over the pairs that hold mu: Dt_p = q(other index of p), and
+// q(mu) for the pair (mu, mu).
+__global__ void __launch_bounds__(256)
+exchange_pairs_kernel(const double* __restrict__ q, int nb, int row, int64_t npair, const int32_t* __restrict__ pairs,
+                      double* __restrict__ Dt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npair) return;
+  int mu, nu;
+  double v = 0.0;
+  if (pair_of(pairs, nb, p, mu, nu)) v = mu == row ? q[nu] : (nu == row ? q[mu] : 0.0);
+  Dt[p] = v;
+}
+
+// K(mu, nu) = 2 sum_j sum_a X_{j mu}(a) Phi_{j nu}(a), one work group per
+// (mu, nu), the orbitals and grid points in a fixed order, then a tree sum.
+__global__ void __launch_bounds__(256)
+exchange_dot_kernel(const double* __restrict__ R, const double* __restrict__ F, int64_t n3, int nb, int norb,
+                    double* __restrict__ Kx) {
+  __shared__ double red[256];
+  const int mu = blockIdx.y, nu = blockIdx.x;
+  double acc = 0.0;
+  for (int j = 0; j < norb; ++j) {
+    const double* r = R + ((int64_t)j * nb + mu) * n3;
+    const double* f = F + ((int64_t)j * nb + nu) * n3;
+    for (int64_t a = threadIdx.x; a < n3; a += 256) acc += r[a] * f[a];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) Kx[(int64_t)mu * nb + nu] = 2.0 * red[0];
+}
+
 // J_mo(i, j) = sum_a rho_i(a) Phi_j(a) over the n^3 grid, one work group per
 // (i, j), a fixed-order tree sum.
 __global__ void __launch_bounds__(256)
@@ -591,6 +627,27 @@ hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(mo_dot_kernel, dim3(norb, norb), dim3(256), 0, s, R, F, n3, norb, Jmo);
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
+                           const NodeTables& tb, const double* Q, int norb, double* R, double* F, double* Kx,
+                           const JWork& w, hipStream_t s) {
+  const int64_t n3 = (int64_t)n * n * n;
+  convert_moments(prec, M, n, npair, w, s);
+  for (int j = 0; j < norb; ++j)
+    for (int mu = 0; mu < nb; ++mu) {
+      JWork wi = w;
+      const int64_t slot = (int64_t)j * nb + mu;
+      wi.rho = R + slot * n3;
+      wi.Phi = F + slot * n3;
+      hipLaunchKernelGGL(exchange_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, Q + (int64_t)j * nb, nb, mu,
+                         (int64_t)npair, pairs, wi.Dt);
+      launch_rho_phi(prec, M, npair, n, nq, tb, wi, s);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  hipLaunchKernelGGL(exchange_dot_kernel, dim3(nb, nb), dim3(256), 0, s, R, F, n3, nb, norb, Kx);
   return hipGetLastError();
 }
 

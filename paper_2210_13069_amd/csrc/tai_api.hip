@@ -1228,6 +1228,43 @@ int tai_coulomb_mo(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs
   return TAI_OK;
 }
 
+int tai_exchange(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs, int32_t npk, const tai_params* p,
+                 const double* Q, int32_t norb, double* Kx, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !Q || !Kx) return fail(c, TAI_ERR_INVALID_ARG, "M, Q or Kx is NULL");
+  if (nb < 1 || nb > 65535) return fail(c, TAI_ERR_INVALID_ARG, "nb must be in [1, 65535]");
+  if (npair_of(nb) > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
+  if (norb < 1 || norb > 1024) return fail(c, TAI_ERR_INVALID_ARG, "norb must be in [1, 1024]");
+  if (pairs && (npk < 1 || npk > npair_of(nb))) return fail(c, TAI_ERR_INVALID_ARG, "npk must be in [1, npair]");
+  const double work = 16.0 * norb * (double)nb * p->n * p->n * p->n;
+  if (work > 64.0 * (1ull << 30))
+    return fail(c, TAI_ERR_INVALID_ARG, "norb * nb * n^3 too large: the X and Phi tensors exceed 64 GiB");
+  if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_exchange supports prec TAI_FP64 and TAI_FP32");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nq = p->nq;
+  const int64_t npair = pairs ? npk : npair_of(nb);
+  NodeTables tb, tbp;
+  const double* Mop = M;
+  int n = p->n;
+  if ((r = prepare_operands(c, M, npair, p, s, &tb, &Mop, &n, &tbp))) return r;
+  const size_t slots = (size_t)norb * nb * n * n * n;
+  if ((r = ensure(c, c->jwork, tai::j_work_bytes(p->prec, nq, n, (int)npair)))) return r;
+  if ((r = ensure(c, c->mo, 2 * sizeof(double) * slots))) return r;
+  hipError_t e;
+  tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, n, (int)npair);
+  double* R = static_cast<double*>(c->mo.p);
+  {
+    Timed tm(c, kStApplyJ, s);
+    e = tai::launch_exchange(p->prec, Mop, nb, (int)npair, pairs, n, nq, tbp, Q, norb, R, R + slots, Kx, w, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "exchange kernels");
+  return TAI_OK;
+}
+
 // A contraction map: fmap[0] = 0 and each step adds 0 or 1 (primitives listed
 // function by function, every function at least one); returns nb or 0.
 static int32_t contraction_nb(const int32_t* fmap, int32_t nbp) {

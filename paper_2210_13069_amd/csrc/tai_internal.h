@@ -268,6 +268,12 @@ hipError_t launch_contract_functions(const double* Jp, int nbp, const int32_t* f
 hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
                              const NodeTables& tb, const double* Q, int norb, double* R, double* F, double* Jmo,
                              const JWork& w, hipStream_t s);
+// Long-range exchange matrix (appendix B): X_{j mu} and Phi_{j nu} for every
+// orbital j and function mu into R and F ([norb][nb][n^3] each), then
+// Kx(mu, nu) = 2 sum_j <X_{j mu}, Phi_{j nu}>.
+hipError_t launch_exchange(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
+                           const NodeTables& tb, const double* Q, int norb, double* R, double* F, double* Kx,
+                           const JWork& w, hipStream_t s);
 // Achievable-peak probes (k_probe.hip): what 0 = FP16 MFMA, 1 = FP64 MFMA,
 // 2 = HBM copy.  probe_work is the flops (0, 1) or bytes (2) of one launch.
 hipError_t launch_probe(int what, int cus, float* out, const void* src, void* dst, int64_t n16, int iters,

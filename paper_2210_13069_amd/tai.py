@@ -29,7 +29,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 # exported symbols declared in include/tai.h
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
            "tai_quadrature", "tai_degrees", "tai_compress", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
-           "tai_apply_J_pairs", "tai_apply_J_compressed", "tai_coulomb_mo", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
+           "tai_apply_J_pairs", "tai_apply_J_compressed", "tai_coulomb_mo", "tai_exchange", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
            "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched", "compress"]
 
@@ -90,6 +90,8 @@ def load_library(path=LIB_PATH):
     lib.tai_degrees.argtypes = [vp, ctypes.POINTER(tai_params), vp, vp, vp]
     lib.tai_compress.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), ctypes.POINTER(ctypes.c_int32),
                                  vp, vp, vp, vp, vp]
+    lib.tai_exchange.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp,
+                                 ctypes.c_int32, vp, vp]
     lib.tai_apply_J_compressed.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int32, vp,
                                            ctypes.POINTER(tai_params), vp, vp, vp]
     lib.tai_screen_pairs.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.c_double, vp,
@@ -229,6 +231,11 @@ class Context:
         p = params if isinstance(params, tai_params) else make_params(params)
         self.check(self.lib.tai_apply_J_pairs(self.h, _ptr(M), int(nb), _ptr(pairs), int(npk), ctypes.byref(p),
                                               _ptr(D), _ptr(J), _stream(stream)), "tai_apply_J_pairs")
+
+    def exchange(self, M, nb, params, Q, norb, Kx, pairs=None, npk=0, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        self.check(self.lib.tai_exchange(self.h, _ptr(M), int(nb), _ptr(pairs), int(npk), ctypes.byref(p), _ptr(Q),
+                                         int(norb), _ptr(Kx), _stream(stream)), "tai_exchange")
 
     def coulomb_mo(self, M, nb, params, Q, norb, Jmo, pairs=None, npk=0, stream=None):
         p = params if isinstance(params, tai_params) else make_params(params)
@@ -433,6 +440,16 @@ def contract_pairs(Bp, nbp, fmap, prec=FP64, device=0):
     B = torch.empty((npc, npc), dtype=Bp.dtype, device=Bp.device)
     context(device).contract_pairs(Bp, nbp, fmap, prec, B)
     return B
+
+
+def exchange(M, nb, Q, params, prec=FP64, pairs=None, device=0):
+    """Long-range exchange matrix [nb][nb] (FP64) for orbitals Q [norb][nb]."""
+    import torch
+    norb = int(Q.shape[0])
+    Kx = torch.empty((nb, nb), dtype=torch.float64, device=M.device)
+    npk = 0 if pairs is None else int(pairs.shape[0])
+    context(device).exchange(M, nb, make_params(params, prec), Q.contiguous(), norb, Kx, pairs, npk)
+    return Kx
 
 
 def apply_J_contracted(M, nbp, fmap, D, params, prec=FP64, device=0):

@@ -295,3 +295,21 @@ def test_contraction_argument_checks(hctx):
     p16 = _params(prec=4)
     assert lib.tai_apply_J_contracted(h, dummy, 5, good, ctypes.byref(p16), dummy, dummy, None) == tai.TAI_ERR_UNSUPPORTED
     assert lib.tai_apply_J_contracted(h, dummy, 5, good, ctypes.byref(p), dummy, dummy, None) == tai.TAI_ERR_NOT_READY
+
+
+def test_exchange_argument_checks(hctx):
+    dummy = ctypes.c_void_p(16)
+    lib, h = hctx.lib, hctx.h
+    p = _params()
+    call = lambda M=dummy, nb=4, pairs=None, npk=0, params=p, Q=dummy, norb=2, Kx=dummy: \
+        lib.tai_exchange(h, M, nb, pairs, npk, ctypes.byref(params), Q, norb, Kx, None)
+    assert call(M=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(Q=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(Kx=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(nb=0) == tai.TAI_ERR_INVALID_ARG
+    assert call(norb=0) == tai.TAI_ERR_INVALID_ARG
+    assert call(norb=1025) == tai.TAI_ERR_INVALID_ARG
+    assert call(pairs=dummy, npk=0) == tai.TAI_ERR_INVALID_ARG
+    assert call(nb=60000, norb=1024, params=_params(n=64)) == tai.TAI_ERR_INVALID_ARG   # tensors > 64 GiB
+    assert call(params=_params(prec=4)) == tai.TAI_ERR_UNSUPPORTED
+    assert call() == tai.TAI_ERR_NOT_READY
