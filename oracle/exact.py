@@ -20,15 +20,28 @@ interpolation, no moments, no K tables):
 
 The integrals are over all of R^3 x R^3 (no box); tests choose the box large
 enough that truncation is far below their tolerance.
+
+Nothing here is taken from `tairef`: the Gauss-Legendre rule of the
+t-integral is scipy's, and the unit-norm constant of a Cartesian factor is
+computed from its own definition, 1 / sqrt(int (x^l exp(-alpha x^2))^2 dx),
+by a Gauss-Hermite rule that is exact for that integrand.
 """
 import math
 
 import numpy as np
-from scipy.special import erf, roots_hermite
-
-from .tairef import gauss_legendre, norm_1d
+from scipy.special import erf, roots_hermite, roots_legendre
 
 SQRT_PI = math.sqrt(math.pi)
+
+
+def norm_factor(alpha, l):
+    """Constant c with int (c x^l exp(-alpha x^2))^2 dx = 1, from that
+    integral itself: with u = sqrt(2 alpha) x it is
+    (2 alpha)^(-l-1/2) int u^(2l) exp(-u^2) du, which the (l+1)-point
+    Gauss-Hermite rule integrates exactly (degree 2l <= 2(l+1) - 1)."""
+    u, wu = roots_hermite(l + 1)
+    integral = (2.0 * alpha) ** (-l - 0.5) * float(np.sum(wu * u ** (2 * l)))
+    return 1.0 / math.sqrt(integral)
 
 
 def boys_f0(T):
@@ -149,7 +162,7 @@ def eri_lr_semi(fns, omega, gh_order=8, tol=1e-15, n0=32, nmax=1024):
     prev = None
     m = n0
     while m <= nmax:
-        z, zw = gauss_legendre(m)
+        z, zw = roots_legendre(m)
         t = 0.5 * omega * (1.0 + z)
         s = 0.5 * omega * np.sum(zw * np.array([integrand(tt) for tt in t]))
         val = 2.0 / SQRT_PI * s * nA * nB * nC * nD
@@ -165,7 +178,7 @@ def basis_function(center, alpha, lxyz, mu):
     l = [int(v) for v in lxyz[mu]]
     nrm = 1.0
     for d in range(3):
-        nrm *= norm_1d(float(alpha[mu]), l[d])
+        nrm *= norm_factor(float(alpha[mu]), l[d])
     return (np.asarray(center[mu], dtype=np.float64), float(alpha[mu]), l, nrm)
 
 

@@ -492,17 +492,14 @@ def compression_basis(M, tol):
     matrices of the three directions are stacked side by side,
     W = [M_1 | M_2 | M_3] (n x 3 npair), one orthonormal basis V of its leading
     left singular vectors serves the three directions and every quadrature
-    node (with one degree n the moments of all nodes coincide).  The
-    directions kept are those with sigma_r > tol * sigma_1 (at least one),
-    their count rounded up to a multiple of 8 and capped at n: the rank R is
-    the inner length of every later contraction, which runs in chunks of 8,
-    so the rounded-up directions cost nothing and only shrink the truncation.
+    node (with one degree n the moments of all nodes coincide).  The rank is
+    the number of singular values above the relative cut of section 6.1,
+    R = #{r : sigma_r > tol * sigma_1}, and at least 1.
 
     Returns (V[:, :R], sigma (all n), R)."""
     W = np.concatenate([M[0], M[1], M[2]], axis=1)
     V, sigma, _ = np.linalg.svd(W, full_matrices=False)
-    count = max(1, int(np.sum(sigma > tol * sigma[0])))
-    R = min(len(sigma), 8 * ((count + 7) // 8))
+    R = max(1, int(np.sum(sigma > tol * sigma[0])))
     return V[:, :R], sigma, R
 
 

@@ -7,6 +7,7 @@ import pytest
 from scipy import integrate
 from scipy.special import erf
 
+from oracle import exact as X
 from oracle import tairef as T
 from paper_2210_13069_amd import inputs as I
 
@@ -16,7 +17,28 @@ pytestmark = pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarn
 def _factor(center, alpha, lxyz, mu, d, x):
     """One unit-normalised Cartesian factor of g_mu in direction d."""
     l = int(lxyz[mu, d])
-    return T.norm_1d(alpha[mu], l) * (x - center[mu, d]) ** l * np.exp(-alpha[mu] * (x - center[mu, d]) ** 2)
+    return X.norm_factor(alpha[mu], l) * (x - center[mu, d]) ** l * np.exp(-alpha[mu] * (x - center[mu, d]) ** 2)
+
+
+@pytest.mark.parametrize("l", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("alpha", [0.07, 1.3, 45.0])
+def test_unit_norm_constant(alpha, l):
+    """The oracle's constant (2l-1)!! formula against its definition: the
+    squared factor integrates to one by adaptive quadrature, and it equals
+    the Gauss-Hermite value of the independent checker."""
+    c = T.norm_1d(alpha, l)
+    val, err = integrate.quad(lambda x: (c * x ** l * math.exp(-alpha * x * x)) ** 2, -np.inf, np.inf,
+                              epsabs=0.0, epsrel=1e-13, limit=200)
+    assert abs(val - 1.0) <= 1e-11
+    assert abs(c - X.norm_factor(alpha, l)) <= 1e-13 * c
+
+
+def test_unit_norm_constant_catches_a_wrong_double_factorial():
+    """A plausible slip, (2l-1)! in place of (2l-1)!!, moves the constant for
+    l >= 2 far outside the tolerance above."""
+    for l in (2, 3):
+        wrong = math.sqrt(math.sqrt(2.0 * 1.3 / math.pi) * (4.0 * 1.3) ** l / math.factorial(2 * l - 1))
+        assert abs(wrong - X.norm_factor(1.3, l)) > 1e-3 * wrong
 
 
 def test_sum_of_moments_is_truncated_overlap_s_type():
