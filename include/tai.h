@@ -169,30 +169,36 @@ int tai_degrees(tai_ctx* ctx, const tai_params* params, int32_t* nk, double* C, 
    (n x 3 npair) are computed in FP64 from the eigenpairs of W W^T (cyclic
    Jacobi): sigma (DEVICE double [n] or NULL) in decreasing order, V (DEVICE
    double [n][n] or NULL) with V[a][r] the r-th singular vector, and
-   *rank (HOST) = #{r : sigma_r > rank_tol * sigma_1} (at least 1) rounded up
-   to a multiple of 8 and capped at n (the contractions run their inner index
-   in chunks of 8, so the extra directions are free).  One basis
-   serves the three directions and every quadrature node.  Forming W W^T
-   resolves sigma_r to about 1e-16 sigma_1^2 / sigma_r, so ranks cut at
-   rank_tol >= 1e-7 rest on well-resolved values.  rank_tol must be > 0
-   (TAI_ERR_INVALID_ARG otherwise).  The call waits on the host for the rank.
+   *rank (HOST) R = #{r : sigma_r > rank_tol * sigma_1}, at least 1 (the cut
+   of section 6.1).  One basis serves the three directions and every
+   quadrature node.  Forming W W^T resolves sigma_r to about
+   1e-16 sigma_1^2 / sigma_r, so ranks cut at rank_tol >= 1e-7 rest on
+   well-resolved values.  rank_tol must be > 0 (TAI_ERR_INVALID_ARG
+   otherwise).  The call waits on the host for the rank.
    With U (DEVICE double, room for [3][n][npair]) and/or Kc (DEVICE double,
-   room for [nq][n][n]) non-NULL the compressed operands are written too:
-   U[d][r][q] = sum_a V[a][r] M[d][a][q] for r < R, packed as [3][R][npair],
-   and Kc[k] = V_R^T K_k V_R packed as [nq][R][R] (eq. approxepsilon); they
-   serve tai_apply_J_compressed for as long as the moments do not change. */
+   room for [nq][n][n]) non-NULL the compressed operands are written too, at
+   the padded inner length Rp = min(n, 8 ceil(R / 8)) that the contractions
+   run at (their inner index goes in chunks of 8):
+   U[d][r][q] = sum_a V[a][r] M[d][a][q] for r < R and 0 for R <= r < Rp,
+   packed as [3][Rp][npair], and Kc[k] = V_R^T K_k V_R (eq. approxepsilon)
+   bordered by zero rows and columns up to Rp, packed as [nq][Rp][Rp].  The
+   zero padding adds nothing to any product: results are those of rank R.
+   They serve tai_apply_J_compressed for as long as the moments do not
+   change. */
 int tai_compress(tai_ctx* ctx, const double* M, int32_t npair, const tai_params* params, int32_t* rank,
                  double* sigma, double* V, double* U, double* Kc, void* stream);
 
 /* J from prepared compressed operands (tai_compress with U and Kc): the J of
    tai_apply_J (or tai_apply_J_pairs when pairs != NULL, npk pairs listed) on
-   the R^3 grid, with no basis computed and no host wait, so that one
-   compression serves every J build while the moments stay fixed (a
-   self-consistent-field loop changes D only).  U: DEVICE double [3][R][npk or
-   npair]; Kc: DEVICE double [nq][R][R]; 2 <= R <= params->n; params gives
-   omega, nq, n, L, nodes (for the weights w_k) and prec (TAI_FP64 or
-   TAI_FP32); rank_tol and degree_tol are not read.  The result equals that of
-   tai_apply_J with the same rank_tol bit for bit. */
+   the grid of the compressed directions, with no basis computed and no host
+   wait, so that one compression serves every J build while the moments stay
+   fixed (a self-consistent-field loop changes D only).  R is the rank
+   tai_compress returned (1 <= R <= params->n); U: DEVICE double
+   [3][Rp][npk or npair] and Kc: DEVICE double [nq][Rp][Rp] as tai_compress
+   wrote them, Rp = min(n, 8 ceil(R / 8)); params gives omega, nq, n, L, nodes
+   (for the weights w_k) and prec (TAI_FP64 or TAI_FP32); rank_tol and
+   degree_tol are not read.  The result equals that of tai_apply_J with the
+   same rank_tol bit for bit. */
 int tai_apply_J_compressed(tai_ctx* ctx, const double* U, int32_t nb, const int32_t* pairs, int32_t npk,
                            int32_t R, const double* Kc, const tai_params* params, const double* D, double* J,
                            void* stream);

@@ -175,7 +175,7 @@ __device__ inline void pack_body(int prec, const double* __restrict__ M, int n, 
   tile_store(prec, kc, tile, sw, reinterpret_cast<uint32_t*>(A + (((int64_t)d * prow + row0) * kc) * es));
 }
 
-// Y_{k,d} rows, (K_k M_d)(:, q) scaled by 2^-e(q,d) (and by w_k for d = 2),
+// Y_{k,d} rows, (K_k M_d)(:, q) scaled by 2^-e(q,d) (and by w_k 2^ysh for d = 2),
 // in the operand format of prec, for 64 rows q and one direction d over all
 // nodes k.  The product runs on the FP64 matrix cores (v_mfma_f64_16x16x4):
 // wave w holds the A fragments M_d(b, q) of rows q0 + 16 w .. +16 for the
@@ -189,7 +189,7 @@ template <int NT, int PREC>
 __device__ inline void project_mfma_body(const double* __restrict__ M, int n, int64_t npair, int prow,
                                          int nq, int kc, const double* __restrict__ K,
                                          const double* __restrict__ w, const int32_t* __restrict__ ex,
-                                         char* __restrict__ Y) {
+                                         int ysh, char* __restrict__ Y) {
   constexpr int prec = PREC;
   constexpr int NP = 16 * NT, NK = NP / 4, PS = NP + 1;
   constexpr int KPER = (NP * NP + 255) / 256;  // staged K values per thread
@@ -243,7 +243,7 @@ __device__ inline void project_mfma_body(const double* __restrict__ M, int n, in
     }
     __syncthreads();
     if (k + 1 < nq) load_k(k + 1);
-    const double wk = (d == 2) ? w[k] : 1.0;
+    const double wk = (d == 2) ? ldexp(w[k], ysh) : 1.0;
     // one column tile at a time: its fragments, MFMAs and slices
 #pragma unroll 1
     for (int j = 0; j < NT; ++j) {
@@ -419,7 +419,7 @@ __device__ inline void assemble_tile(const AsmMol& m, int I, int J) {
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
       const int64_t col = col0 + j * 16 + r16;
-      const int ecol = kF64 ? 0 : m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col];
+      const int ecol = kF64 ? 0 : m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col] - m.ysh;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = row0 + i * 16 + Op::row_of(kg, r);
@@ -627,7 +627,7 @@ __device__ inline void assemble_tile_as(const AsmMol& m, int I, int J) {
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
       const int64_t col = col0 + j * 16 + r16;
-      const int ecol = kF64 ? 0 : m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col];
+      const int ecol = kF64 ? 0 : m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col] - m.ysh;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = row0 + i * 16 + Op::row_of(kg, r);
@@ -740,8 +740,8 @@ template <int NT, int PREC>
 __global__ void __launch_bounds__(256, 3)
 project_kernel(const double* __restrict__ M, int n, int64_t npair, int prow, int nq,
                int kc, const double* __restrict__ K, const double* __restrict__ w,
-               const int32_t* __restrict__ ex, char* __restrict__ Y) {
-  project_mfma_body<NT, PREC>(M, n, npair, prow, nq, kc, K, w, ex, Y);
+               const int32_t* __restrict__ ex, int ysh, char* __restrict__ Y) {
+  project_mfma_body<NT, PREC>(M, n, npair, prow, nq, kc, K, w, ex, ysh, Y);
 }
 
 template <int NT, int PREC>
@@ -751,7 +751,7 @@ project_batch_kernel(const PrepMol* __restrict__ mols, int n, int nq, int kc) {
   if ((int64_t)blockIdx.x * kRowsPerTile >= m.prow) return;
   // coefficient form (per-node degrees): moments against T_j, kept coefficients
   project_mfma_body<NT, PREC>(m.Mu ? m.Mu : m.M, n, m.npair, m.prow, nq, kc, m.Mu ? m.tb.C : m.tb.K, m.tb.w, m.ex,
-                              static_cast<char*>(m.Y));
+                              m.ysh, static_cast<char*>(m.Y));
 }
 
 size_t project_lds(int prec, int n) {
@@ -774,21 +774,21 @@ hipError_t launch_pack_t(int prec, const double* M, int n, int npair, int prow, 
 
 template <int NT, int PREC>
 hipError_t launch_project_p(const double* M, int n, int npair, int prow, int nq, const NodeTables& tb,
-                            const int32_t* ex, void* Y, hipStream_t s) {
+                            const int32_t* ex, int ysh, void* Y, hipStream_t s) {
   hipLaunchKernelGGL((project_kernel<NT, PREC>), dim3(prow / kRowsPerTile, 3), dim3(256), project_lds(PREC, n), s,
-                     M, n, (int64_t)npair, prow, nq, operand_kc(PREC, n), tb.K, tb.w, ex, static_cast<char*>(Y));
+                     M, n, (int64_t)npair, prow, nq, operand_kc(PREC, n), tb.K, tb.w, ex, ysh, static_cast<char*>(Y));
   return hipGetLastError();
 }
 
 template <int NT>
 hipError_t launch_project_t(int prec, const double* M, int n, int npair, int prow, int nq,
-                            const NodeTables& tb, const int32_t* ex, void* Y, hipStream_t s) {
+                            const NodeTables& tb, const int32_t* ex, int ysh, void* Y, hipStream_t s) {
   switch (prec) {
-    case kFP64: return launch_project_p<NT, kFP64>(M, n, npair, prow, nq, tb, ex, Y, s);
-    case kFP32: return launch_project_p<NT, kFP32>(M, n, npair, prow, nq, tb, ex, Y, s);
-    case kF16X3: return launch_project_p<NT, kF16X3>(M, n, npair, prow, nq, tb, ex, Y, s);
-    case kBF16X3: return launch_project_p<NT, kBF16X3>(M, n, npair, prow, nq, tb, ex, Y, s);
-    default: return launch_project_p<NT, kBF16X6>(M, n, npair, prow, nq, tb, ex, Y, s);
+    case kFP64: return launch_project_p<NT, kFP64>(M, n, npair, prow, nq, tb, ex, ysh, Y, s);
+    case kFP32: return launch_project_p<NT, kFP32>(M, n, npair, prow, nq, tb, ex, ysh, Y, s);
+    case kF16X3: return launch_project_p<NT, kF16X3>(M, n, npair, prow, nq, tb, ex, ysh, Y, s);
+    case kBF16X3: return launch_project_p<NT, kBF16X3>(M, n, npair, prow, nq, tb, ex, ysh, Y, s);
+    default: return launch_project_p<NT, kBF16X6>(M, n, npair, prow, nq, tb, ex, ysh, Y, s);
   }
 }
 
@@ -865,11 +865,11 @@ hipError_t launch_pack(int prec, const double* M, int n, int npair, int prow, vo
 }
 
 hipError_t launch_project(int prec, const double* M, int n, int npair, int prow, int nq,
-                          const NodeTables& tb, const int32_t* ex, void* Y, hipStream_t s) {
-  if (n <= 16) return launch_project_t<1>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
-  if (n <= 32) return launch_project_t<2>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
-  if (n <= 48) return launch_project_t<3>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
-  return launch_project_t<4>(prec, M, n, npair, prow, nq, tb, ex, Y, s);
+                          const NodeTables& tb, const int32_t* ex, int ysh, void* Y, hipStream_t s) {
+  if (n <= 16) return launch_project_t<1>(prec, M, n, npair, prow, nq, tb, ex, ysh, Y, s);
+  if (n <= 32) return launch_project_t<2>(prec, M, n, npair, prow, nq, tb, ex, ysh, Y, s);
+  if (n <= 48) return launch_project_t<3>(prec, M, n, npair, prow, nq, tb, ex, ysh, Y, s);
+  return launch_project_t<4>(prec, M, n, npair, prow, nq, tb, ex, ysh, Y, s);
 }
 
 // FP64 uses the eight-wave form from inner length 32 on (the four-wave form

@@ -95,7 +95,7 @@ __device__ inline void run_item32(const AsmMol& m, int rp, int cb0, int cb1, flo
   }
   for (int i = threadIdx.x; i < nblk * COLS; i += NT) {
     const int64_t col = col_first + i;
-    ecol_s[i] = m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col];
+    ecol_s[i] = m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col] - m.ysh;
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) mysum[v * 64] = 0.0;

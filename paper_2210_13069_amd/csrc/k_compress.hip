@@ -13,10 +13,13 @@
 //    order), each round one parallel in-place pass over the 2 x 2 blocks of G
 //    in LDS, the columns of V rotated alongside.  Sweeps stop when a whole
 //    sweep finds every off-diagonal entry negligible against its diagonal
-//    pair.  Eigenvalues are sorted in decreasing order; R is the count of
-//    sigma_r > tol * sigma_1 (at least one) rounded up to a multiple of 8 and
-//    capped at n: every later contraction runs its inner index in chunks of
-//    8, so the extra directions are free and only shrink the truncation.
+//    pair.  Eigenvalues are sorted in decreasing order; the rank R is the
+//    count of sigma_r > tol * sigma_1 (at least one), the cut of section 6.1.
+//    The contractions run their inner index in chunks of 8, so the operands
+//    are written at the padded length min(n, 8 ceil(R / 8)) with the basis
+//    columns from R on taken as zero: zero rows of U and zero rows and
+//    columns of Kc add nothing to any product, and the result is that of
+//    rank R.
 //  * One refinement pass: Y = V1^T W in the first basis V1, then the Gram
 //    matrix of Y (nearly diagonal, its entries (r, s) rounded relative to
 //    sigma_r sigma_s rather than sigma_1^2) and its Jacobi eigenvectors V2;
@@ -213,9 +216,7 @@ jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, doubl
     int r = 0;
     for (int i = 0; i < n; ++i)
       if (sqrt(fmax(A[order[i] * S + order[i]], 0.0)) > tol * s0) ++r;
-    r = r < 1 ? 1 : r;
-    r = (r + 7) / 8 * 8;
-    *rank = r < n ? r : n;
+    *rank = r < 1 ? 1 : r;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < n * n; e += kJacobiThreads) {
@@ -226,15 +227,18 @@ jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, doubl
 }
 
 // U[d][r][q] = sum_a V[a][r] M[d][a][q] for r < R (V is n x n, its first R
-// columns used); one thread per pair with the moment column in registers.
+// columns used), with the columns from `keep` on taken as zero: rows
+// keep..R-1 of U are the zero padding of the kept rank up to the inner
+// length the contractions run at.  One thread per pair with the moment
+// column in registers.
 template <int NMAX>
 __global__ void __launch_bounds__(256)
 compress_moments_kernel(const double* __restrict__ M, int n, int64_t npair, const double* __restrict__ V, int R,
-                        double* __restrict__ U) {
+                        int keep, double* __restrict__ U) {
   __shared__ __align__(16) double s_v[NMAX * NMAX];
   for (int e = threadIdx.x; e < n * R; e += 256) {
     const int a = e / R, r = e % R;
-    s_v[a * NMAX + r] = V[a * n + r];
+    s_v[a * NMAX + r] = r < keep ? V[a * n + r] : 0.0;
   }
   __syncthreads();
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -278,9 +282,10 @@ basis_product_kernel(const double* __restrict__ V1, const double* __restrict__ V
   }
 }
 
-// Kc[k] = V_R^T K[k] V_R (R x R), one work group per node.
+// Kc[k] = V_R^T K[k] V_R (R x R), one work group per node; the columns of V
+// from `keep` on are taken as zero (zero rows and columns of Kc).
 __global__ void __launch_bounds__(256)
-compress_tables_kernel(const double* __restrict__ K, int n, const double* __restrict__ V, int R,
+compress_tables_kernel(const double* __restrict__ K, int n, const double* __restrict__ V, int R, int keep,
                        double* __restrict__ Kc) {
   constexpr int S = kMaxN + 1;
   __shared__ double s_k[kMaxN * S];
@@ -291,7 +296,7 @@ compress_tables_kernel(const double* __restrict__ K, int n, const double* __rest
   for (int e = threadIdx.x; e < n * n; e += 256) {
     const int a = e / n, b = e % n;
     s_k[a * S + b] = Kk[e];
-    s_v[a * S + b] = V[e];
+    s_v[a * S + b] = b < keep ? V[e] : 0.0;
   }
   __syncthreads();
   // T = K V_R  (n x R)
@@ -341,12 +346,13 @@ CompressWork carve_compress_work(void* base, int n, int nq, int64_t npair) {
 }
 
 namespace {
-void launch_moments_in(const double* M, int n, int64_t npair, const double* V, int R, double* U, hipStream_t s) {
+void launch_moments_in(const double* M, int n, int64_t npair, const double* V, int R, int keep, double* U,
+                       hipStream_t s) {
   const dim3 g(nblk(npair, 256), 3);
-  if (n <= 16) hipLaunchKernelGGL(compress_moments_kernel<16>, g, dim3(256), 0, s, M, n, npair, V, R, U);
-  else if (n <= 32) hipLaunchKernelGGL(compress_moments_kernel<32>, g, dim3(256), 0, s, M, n, npair, V, R, U);
-  else if (n <= 48) hipLaunchKernelGGL(compress_moments_kernel<48>, g, dim3(256), 0, s, M, n, npair, V, R, U);
-  else hipLaunchKernelGGL(compress_moments_kernel<64>, g, dim3(256), 0, s, M, n, npair, V, R, U);
+  if (n <= 16) hipLaunchKernelGGL(compress_moments_kernel<16>, g, dim3(256), 0, s, M, n, npair, V, R, keep, U);
+  else if (n <= 32) hipLaunchKernelGGL(compress_moments_kernel<32>, g, dim3(256), 0, s, M, n, npair, V, R, keep, U);
+  else if (n <= 48) hipLaunchKernelGGL(compress_moments_kernel<48>, g, dim3(256), 0, s, M, n, npair, V, R, keep, U);
+  else hipLaunchKernelGGL(compress_moments_kernel<64>, g, dim3(256), 0, s, M, n, npair, V, R, keep, U);
 }
 void launch_gram_eig(const double* M, int n, int64_t npair, double tol, double rel, double floor_rel,
                      const CompressWork& w, double* V, hipStream_t s) {
@@ -364,7 +370,7 @@ hipError_t launch_compress_basis(const double* M, int n, int64_t npair, double t
   // V1 from W W^T need only be close: the refinement pass corrects it, and
   // entries below 1e-14 of the trace are the Gram matrix's own rounding
   launch_gram_eig(M, n, npair, tol, 1e-10, 1e-14, w, w.V1, s);
-  launch_moments_in(M, n, npair, w.V1, n, Y, s);      // Y = V1^T W
+  launch_moments_in(M, n, npair, w.V1, n, n, Y, s);   // Y = V1^T W
   // V2, sigma, rank from Y Y^T: a relative test only (its entries are
   // rounded relative to sigma_r sigma_s)
   launch_gram_eig(Y, n, npair, tol, 1e-13, 0.0, w, w.V2, s);
@@ -372,10 +378,10 @@ hipError_t launch_compress_basis(const double* M, int n, int64_t npair, double t
   return hipGetLastError();
 }
 
-hipError_t launch_compress_operands(const double* M, int n, int64_t npair, int R, int nq, const double* K,
-                                    const CompressWork& w, double* U, hipStream_t s) {
-  launch_moments_in(M, n, npair, w.V, R, U, s);
-  hipLaunchKernelGGL(compress_tables_kernel, dim3(nq), dim3(256), 0, s, K, n, w.V, R, w.Kc);
+hipError_t launch_compress_operands(const double* M, int n, int64_t npair, int R, int keep, int nq,
+                                    const double* K, const CompressWork& w, double* U, hipStream_t s) {
+  launch_moments_in(M, n, npair, w.V, R, keep, U, s);
+  hipLaunchKernelGGL(compress_tables_kernel, dim3(nq), dim3(256), 0, s, K, n, w.V, R, keep, w.Kc);
   return hipGetLastError();
 }
 

@@ -614,13 +614,14 @@ int tai_compress(tai_ctx* c, const double* M, int32_t npair, const tai_params* p
   }
   if ((r = compress_impl(c, M, npair, p, tb, operands, s, &w, &R))) return r;
   const size_t n = p->n;
+  const size_t Rp = tai::padded_rank(R, p->n);
   if (sigma && (e = hipMemcpyAsync(sigma, w.sigma, 8 * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(c, e, "copy sigma");
   if (V && (e = hipMemcpyAsync(V, w.V, 8 * n * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(c, e, "copy V");
-  if (U && (e = hipMemcpyAsync(U, c->cmpU.p, 8 * 3 * (size_t)R * npair, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+  if (U && (e = hipMemcpyAsync(U, c->cmpU.p, 8 * 3 * Rp * npair, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(c, e, "copy U");
-  if (Kc && (e = hipMemcpyAsync(Kc, w.Kc, 8 * (size_t)p->nq * R * R, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+  if (Kc && (e = hipMemcpyAsync(Kc, w.Kc, 8 * (size_t)p->nq * Rp * Rp, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(c, e, "copy Kc");
   *rank = R;
   return TAI_OK;
@@ -635,7 +636,7 @@ int tai_apply_J_compressed(tai_ctx* c, const double* U, int32_t nb, const int32_
   if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
   if (npair_of(nb) > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
   if (pairs && (npk < 1 || npk > npair_of(nb))) return fail(c, TAI_ERR_INVALID_ARG, "npk must be in [1, npair]");
-  if (R < 2 || R > p->n) return fail(c, TAI_ERR_INVALID_ARG, "R must be in [2, n]");
+  if (R < 1 || R > p->n) return fail(c, TAI_ERR_INVALID_ARG, "R must be in [1, n]");
   if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
     return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_compressed supports prec TAI_FP64 and TAI_FP32");
   if ((r = need_device(c))) return r;
@@ -652,11 +653,12 @@ int tai_apply_J_compressed(tai_ctx* c, const double* U, int32_t nb, const int32_
   if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
   NodeTables tbp = tb;
   tbp.K = const_cast<double*>(Kc);
-  if ((r = ensure(c, c->jwork, tai::j_work_bytes(p->prec, nq, R, (int)npair)))) return r;
-  tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, R, (int)npair);
+  const int Rp = tai::padded_rank(R, p->n);   // U and Kc are laid out at the padded length
+  if ((r = ensure(c, c->jwork, tai::j_work_bytes(p->prec, nq, Rp, (int)npair)))) return r;
+  tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, Rp, (int)npair);
   {
     Timed tm(c, kStApplyJ, s);
-    e = tai::launch_apply_j(p->prec, U, nb, (int)npair, pairs, R, nq, tbp, D, J, w, s);
+    e = tai::launch_apply_j(p->prec, U, nb, (int)npair, pairs, Rp, nq, tbp, D, J, w, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "apply_J kernels");
   return TAI_OK;
@@ -767,12 +769,13 @@ static int compress_impl(tai_ctx* c, const double* M, int64_t npair, const tai_p
   if ((e = hipMemcpyAsync(&host, w->rank, sizeof host, hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(c, e, "rank copy");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
-  if (host < 2 || host > n) return fail(c, TAI_ERR_HIP, "compression rank out of range");
+  if (host < 1 || host > n) return fail(c, TAI_ERR_HIP, "compression rank out of range");
   *R = host;
   if (!operands) return TAI_OK;
   {
     Timed tm(c, kStCompress, s);
-    e = tai::launch_compress_operands(M, n, npair, host, nq, tb.K, *w, static_cast<double*>(c->cmpU.p), s);
+    e = tai::launch_compress_operands(M, n, npair, tai::padded_rank(host, n), host, nq, tb.K, *w,
+                                      static_cast<double*>(c->cmpU.p), s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "compression operand kernels");
   return TAI_OK;
@@ -797,6 +800,7 @@ static int prepare_operands(tai_ctx* c, const double* M, int64_t npair, const ta
   if (p->rank_tol > 0) {
     tai::CompressWork w;
     if ((r = compress_impl(c, M, npair, p, *tb, true, s, &w, ne))) return r;
+    *ne = tai::padded_rank(*ne, p->n);   // the zero-padded inner length of U and Kc
     *Mop = static_cast<const double*>(c->cmpU.p);
     tbp->K = w.Kc;
   }
@@ -842,7 +846,7 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
   if (e != hipSuccess) return hip_fail(c, e, "pack kernel");
   {
     Timed tm(c, kStProject, s);
-    e = tai::launch_project(prec, Mop, n, npair, prow, nq, tbp, ex, c->opY.p, s);
+    e = tai::launch_project(prec, Mop, n, npair, prow, nq, tbp, ex, tai::y_shift(prec, p->omega, nq), c->opY.p, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "project kernel");
   tai::AsmMol m;
@@ -858,6 +862,7 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
   m.tiles = prow / tai::assemble_tile(prec);
   m.tile0 = 0;
   m.nk = deg ? tb.nk : nullptr;
+  m.ysh = tai::y_shift(prec, p->omega, nq);
   const bool p16 = use16(c, prec, n, nq), p32 = !p16 && use32(prec, n);
   if (p16 || p32) {
     Items16 items;
@@ -1002,6 +1007,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     m.tile0 = nitems;
     nitems += (int64_t)m.tiles * (m.tiles + 1) / 2;
     m.nk = nullptr;  // set below from the molecule's node tables
+    m.ysh = tai::y_shift(prec, mols[i].params.omega, nq);
   }
   // the 16-bit kernel drains (molecule, row panel, column range) items,
   // largest molecules first so the tail of the queue holds small items
@@ -1040,6 +1046,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     q.A = const_cast<void*>(am[i].A);
     q.ex = const_cast<int32_t*>(am[i].ex);
     q.Y = const_cast<void*>(am[i].Y);
+    q.ysh = am[i].ysh;
     max_npair = std::max<int64_t>(max_npair, am[i].npair);
     max_prow = std::max(max_prow, prow[i]);
   }

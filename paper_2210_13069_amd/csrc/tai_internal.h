@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <cmath>
 #include <cstdint>
 
 namespace tai {
@@ -129,6 +130,9 @@ struct AsmMol {
   // per-node degrees N_k [nq] when the operands are in coefficient form
   // (FP64 and FP32 only; nullptr: every node runs the full inner length)
   const int32_t* nk;
+  // power of two folded into Y_{k,2} with w_k (y_shift); the column
+  // exponents are lowered by it when B is scaled back
+  int32_t ysh;
 };
 
 // Per-molecule arguments of the preparation stages of a batch (nodes,
@@ -145,6 +149,7 @@ struct PrepMol {
   void* A;
   int32_t* ex;
   void* Y;
+  int32_t ysh;           // y_shift of the molecule
 };
 // any_degree: some molecule has degree_tol > 0 (then the degree stage runs
 // for the batch; molecules with degree_tol <= 0 keep their tables).
@@ -161,7 +166,7 @@ hipError_t launch_project_batch(int prec, const PrepMol* mols, int nmol, int max
 hipError_t launch_pack(int prec, const double* M, int n, int npair, int prow,
                        void* A, int32_t* ex, hipStream_t s);
 hipError_t launch_project(int prec, const double* M, int n, int npair, int prow, int nq,
-                          const NodeTables& tb, const int32_t* ex, void* Y, hipStream_t s);
+                          const NodeTables& tb, const int32_t* ex, int ysh, void* Y, hipStream_t s);
 // Single molecule, one work group per tile.
 hipError_t launch_assemble(int prec, const AsmMol& m, hipStream_t s);
 // Persistent launch over a device work list of molecules; `counter` is a
@@ -250,8 +255,29 @@ CompressWork carve_compress_work(void* base, int n, int nq, int64_t npair);
 // Y: workspace [3][n][npair]
 hipError_t launch_compress_basis(const double* M, int n, int64_t npair, double tol, const CompressWork& w,
                                  double* Y, hipStream_t s);
-hipError_t launch_compress_operands(const double* M, int n, int64_t npair, int R, int nq, const double* K,
-                                    const CompressWork& w, double* U, hipStream_t s);
+// U [3][R][npair] and Kc [nq][R][R] at inner length R with the basis columns
+// from `keep` on taken as zero (keep <= R: the kept rank, R its padding).
+hipError_t launch_compress_operands(const double* M, int n, int64_t npair, int R, int keep, int nq,
+                                    const double* K, const CompressWork& w, double* U, hipStream_t s);
+// Power of two 2^ysh that the projection folds into Y_{k,2} together with
+// the quadrature weight w_k, so that the split 16-bit operands stay clear of
+// the FP16 subnormals: without it w_k (about omega pi / (2 nq), 1e-3 .. 3e-2)
+// pushes the low slice of every Y_{k,2} entry below FP16's smallest normal.
+// ysh puts the largest weight near [8, 16); products of a B entry stay far
+// below FP32 and FP16 overflow (|Y| <= 16 n).  Zero for FP64 and FP32.  The
+// value is any power of two of that size: the assembly lowers every column
+// exponent by ysh, which is exact.
+inline int y_shift(int prec, double omega, int nq) {
+  if (prec == 0 || prec == 1) return 0;
+  const double west = 0.5 * omega * 3.141592653589793 / (nq + 0.5);
+  return 3 - ilogb(west);
+}
+
+// Inner length the compressed operands of kept rank R are written at.
+inline int padded_rank(int R, int n) {
+  const int r8 = (R + 7) / 8 * 8;
+  return r8 < n ? r8 : n;
+}
 
 // Contracted basis functions (k_contract.hip).  B_c[P][Q] = sum over the
 // CSR members a of P and b of Q of wt[a] wt[b] Bp[idx[a]][idx[b]] (double or

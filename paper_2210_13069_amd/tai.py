@@ -343,24 +343,32 @@ def compress(M, params, device=0):
     return rank, sigma, V
 
 
+def padded_rank(R, n):
+    """Inner length min(n, 8 ceil(R / 8)) the compressed operands of rank R
+    are laid out at (the rows and columns from R on are zero)."""
+    return min(int(n), (int(R) + 7) // 8 * 8)
+
+
 def compress_operands(M, params, device=0):
-    """(rank R, U [3][R][npair], Kc [nq][R][R]): the compressed operands of M."""
+    """(rank R, U [3][Rp][npair], Kc [nq][Rp][Rp]): the compressed operands of
+    M at the padded length Rp = padded_rank(R, n)."""
     import torch
     n, nq, npair = int(params.n), int(params.nq), int(M.shape[2])
     dev = torch.device("cuda", device)
     U = torch.empty(3 * n * npair, dtype=torch.float64, device=dev)
     Kc = torch.empty(nq * n * n, dtype=torch.float64, device=dev)
     R = context(device).compress(M, npair, params, U=U, Kc=Kc)
-    return R, U[:3 * R * npair].view(3, R, npair), Kc[:nq * R * R].view(nq, R, R)
+    Rp = padded_rank(R, n)
+    return R, U[:3 * Rp * npair].view(3, Rp, npair), Kc[:nq * Rp * Rp].view(nq, Rp, Rp)
 
 
-def apply_J_compressed(U, Kc, D, params, prec=FP64, pairs=None, device=0):
-    """J (nb x nb FP64) from prepared compressed operands."""
+def apply_J_compressed(U, Kc, D, params, R, prec=FP64, pairs=None, device=0):
+    """J (nb x nb FP64) from prepared compressed operands of rank R."""
     import torch
     nb = int(D.shape[0])
     J = torch.empty((nb, nb), dtype=torch.float64, device=U.device)
     npk = 0 if pairs is None else int(pairs.shape[0])
-    context(device).apply_J_compressed(U, nb, int(U.shape[1]), Kc, make_params(params, prec), D, J, pairs, npk)
+    context(device).apply_J_compressed(U, nb, int(R), Kc, make_params(params, prec), D, J, pairs, npk)
     return J
 
 

@@ -138,7 +138,8 @@ def test_apply_J_compressed_argument_checks(hctx):
     assert call(U=None) == tai.TAI_ERR_INVALID_ARG
     assert call(Kc=None) == tai.TAI_ERR_INVALID_ARG
     assert call(nb=0) == tai.TAI_ERR_INVALID_ARG
-    assert call(R=1) == tai.TAI_ERR_INVALID_ARG
+    assert call(R=0) == tai.TAI_ERR_INVALID_ARG
+    assert call(R=1) == tai.TAI_ERR_NOT_READY               # rank 1 is valid (padded to 8)
     assert call(R=17) == tai.TAI_ERR_INVALID_ARG           # n = 16
     assert call(pairs=dummy, npk=0) == tai.TAI_ERR_INVALID_ARG
     assert call(params=_params(prec=4)) == tai.TAI_ERR_UNSUPPORTED

@@ -44,8 +44,7 @@ def _check_cut(sigma, R, tol):
     # ranks only where no singular value lies within rounding of the cut
     s = sigma / sigma[0]
     assert np.all(np.abs(s - tol) > 1e-6 * tol)
-    count = max(1, int(np.sum(s > tol)))
-    assert R == min(len(s), 8 * ((count + 7) // 8))
+    assert R == max(1, int(np.sum(s > tol)))
 
 
 @pytest.mark.parametrize("tol", [1e-3, 1e-5, 1e-7])
@@ -135,21 +134,46 @@ def test_compressed_J_screened_and_orbitals(tai):
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
 
 
-def test_rank_eight_at_a_loose_tolerance(tai):
-    """A tolerance just below 1 keeps one direction, rounded up to the
-    smallest rank, 8."""
+def test_rank_one_at_a_loose_tolerance(tai):
+    """A tolerance just below 1 keeps one direction: the kernels run at the
+    padded length 8 with seven zero directions and give the rank-1 result."""
     b, P = I.sp16()
     P = dataclasses.replace(P, rank_tol=0.999)
     K, w = _tables(P)
     Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
     V, s, R = T.compression_basis(Mr, P.rank_tol)
-    assert R == 8
+    assert R == 1
     Br = T.B_full(*T.compress(Mr, K, V), w)
     Mg = tai.moments(b, P)
-    assert tai.compress(Mg, P)[0] == 8
+    assert tai.compress(Mg, P)[0] == 1
     for prec in (0, 1, 4):
         Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
         assert _normwise(Bg, Br) <= (1e-10 if prec == 0 else LOWP_TOL[prec]), prec
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-5])
+def test_operands_are_zero_padded(tai, tol):
+    """U and Kc come at the padded length min(n, 8 ceil(R / 8)): the first R
+    rows equal the oracle's compressed operands up to the sign of each basis
+    vector, the rest are exactly zero."""
+    b, P = _spd()
+    P = dataclasses.replace(P, rank_tol=tol)
+    K, _ = _tables(P)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
+    V, s, R = T.compression_basis(Mr, tol)
+    _check_cut(s, R, tol)
+    Ur, Kcr = T.compress(Mr, K, V)
+    Mg = tai.moments(b, P)
+    Rg, U, Kc = tai.compress_operands(Mg, P)
+    Rp = tai.padded_rank(Rg, P.n)
+    assert Rg == R and U.shape == (3, Rp, b.npair) and Kc.shape == (P.nq, Rp, Rp)
+    U, Kc = U.cpu().numpy(), Kc.cpu().numpy()
+    if Rp > R:
+        assert np.all(U[:, R:] == 0.0) and np.all(Kc[:, R:, :] == 0.0) and np.all(Kc[:, :, R:] == 0.0)
+    # the basis vectors agree up to sign where the spectrum has a gap
+    sgn = np.sign(np.sum(U[0, :R] * Ur[0], axis=1))
+    assert np.max(np.abs(U[:, :R] * sgn[None, :, None] - Ur)) <= 1e-7 * np.max(np.abs(Ur))
+    assert np.max(np.abs(Kc[:, :R, :R] * sgn[None, :, None] * sgn[None, None, :] - Kcr)) <= 1e-7 * np.max(np.abs(Kcr))
 
 
 @pytest.mark.parametrize("prec", [0, 4])
@@ -203,24 +227,25 @@ def test_apply_J_from_prepared_operands(tai, prec):
     P = dataclasses.replace(P, rank_tol=1e-6)
     Mg = tai.moments(b, P)
     R, U, Kc = tai.compress_operands(Mg, P)
-    assert R < P.n and U.shape == (3, R, b.npair) and Kc.shape == (P.nq, R, R)
+    Rp = tai.padded_rank(R, P.n)
+    assert R < P.n and U.shape == (3, Rp, b.npair) and Kc.shape == (P.nq, Rp, Rp)
     for seed in (31, 32):
         D = torch.as_tensor(I.random_density(np.random.default_rng(seed), b), device=Mg.device)
         Jref = tai.apply_J(Mg, D, P, prec=prec)
-        Jc = tai.apply_J_compressed(U, Kc, D, P, prec=prec)
+        Jc = tai.apply_J_compressed(U, Kc, D, P, R, prec=prec)
         assert torch.equal(Jc, Jref)
     pairs = tai.screen_pairs(b, 1e-6)
     assert pairs.shape[0] < b.npair
     Mk = tai.moments_pairs(b, P, pairs)
     Rk, Uk, Kck = tai.compress_operands(Mk, P)
     Jref = tai.apply_J_pairs(Mk, D, pairs, P, prec=prec)
-    assert torch.equal(tai.apply_J_compressed(Uk, Kck, D, P, prec=prec, pairs=pairs), Jref)
+    assert torch.equal(tai.apply_J_compressed(Uk, Kck, D, P, Rk, prec=prec, pairs=pairs), Jref)
 
 
 @pytest.mark.parametrize("n,nodes", [(29, 0), (41, 0), (24, 1)])
 def test_compressed_B_odd_n_and_gauss_nodes(tai, n, nodes):
     """Odd n (the Jacobi sweep pads to an even order with a zero row and
-    column; n = 41 is no multiple of 8, the rank's rounding step) and
+    column; n = 41 is no multiple of 8, the operands' padding step) and
     Chebyshev-Gauss nodes, FP64 and F16X3 against the oracle's compressed
     operands."""
     b = I.small_random(93, natoms=4, shells=("s", "p", "d"), box=3.0, alpha_lo=0.2, alpha_hi=20.0)

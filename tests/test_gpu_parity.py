@@ -8,6 +8,12 @@ Tolerances (relative, normwise = max|diff| / max|oracle|):
   B, FP32 / BF16X6 / F16X3               1e-6   (the low-precision target)
   B, BF16X3                              3e-5   (reported; misses 1e-6 by design)
   J, FP64                                1e-10 relative 2-norm
+Element-wise (|diff| / |oracle| over entries with |oracle| >= 1e-8 max|oracle|,
+the paper's element-wise measure), F16X3: mean <= 8e-6, and max <= 2e-5 over
+entries >= 1e-3 max (smaller entries carry the absolute error of the form as
+relative error).  The host emulation of the form gives 5.2e-6 and 1.2e-5 on
+the whole Nb = 64 matrix (1.4e-5 and 3.3e-5 without the power of two that
+keeps the weighted low slices out of the FP16 subnormals).
 """
 import numpy as np
 import pytest
@@ -29,6 +35,18 @@ def _oracle(basis, P, pairs=None):
 
 def _normwise(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _check_elementwise_f16x3(got, ref, scale=None):
+    scale = np.max(np.abs(ref)) if scale is None else scale
+    rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
+    big = np.abs(ref) >= 1e-8 * scale
+    mean = float(np.mean(rel[big]))
+    assert mean <= 8e-6, f"F16X3 mean element-wise {mean:.3e}"
+    big3 = np.abs(ref) >= 1e-3 * scale
+    if np.any(big3):
+        mx = float(np.max(rel[big3]))
+        assert mx <= 2e-5, f"F16X3 max element-wise (>= 1e-3 max) {mx:.3e}"
 
 
 @pytest.mark.parametrize("kind", [0, 1])
@@ -97,6 +115,8 @@ def test_assemble_B_small(tai, prec, case):
     assert err <= tol, f"prec {prec}: normwise {err:.3e} > {tol}"
     # every entry written, both triangles
     assert np.all(np.isfinite(Bg))
+    if prec == 4:
+        _check_elementwise_f16x3(Bg, Br)
     # mirrored tiles are exact copies; diagonal tiles are symmetric to the
     # arithmetic's own accuracy
     assert _normwise(Bg, Bg.T) <= (1e-14 if prec == 0 else tol)
@@ -247,6 +267,8 @@ def test_assemble_B_full_size_sampled(tai, omega):
         tol = 1e-10 if prec == 0 else 1e-6
         err = np.max(np.abs(got - ref)) / scale
         assert err <= tol, f"prec {prec}: {err:.3e}"
+        if prec == 4:
+            _check_elementwise_f16x3(got, ref, scale)
         del B
         torch.cuda.empty_cache()
 

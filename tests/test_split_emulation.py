@@ -14,8 +14,13 @@ same inputs the normwise error must be <= 1e-6 for F16X3 and BF16X6; BF16X3
 lands near 1e-5 (it is reported, and held to 3e-5).  Without the per-column
 power-of-two scaling, FP16 slices underflow on the small moments: the
 element-wise error on the small entries grows, which is why the scaling is
-part of the form.
+part of the form.  The quadrature weight w_k goes into the direction-2
+operand of each node together with a power of two that brings the largest
+weight near [8, 16): w_k alone (1e-3 .. 3e-2) pushes the low FP16 slices into
+the subnormals, which costs F16X3 several times its element-wise accuracy.
 """
+import math
+
 import numpy as np
 
 from oracle import tairef as T
@@ -46,9 +51,15 @@ def _slices(x, kind, ns):
 PAIRS = {"x3": [(0, 0), (0, 1), (1, 0)], "x6": [(0, 0), (0, 1), (1, 0), (0, 2), (1, 1), (2, 0)]}
 
 
-def _emulate(M, K, w, rows, kind, form, scale=True):
+def _weight_shift(w):
+    """Exponent s with max_k w_k 2^s in [8, 16)."""
+    return 3 - (math.frexp(float(np.max(w)))[1] - 1)
+
+
+def _emulate(M, K, w, rows, kind, form, scale=True, wshift=True):
     """B[rows, :] in the emulated split arithmetic."""
     n, npair = M.shape[1], M.shape[2]
+    sh = _weight_shift(w) if wshift else 0
     ns = 3 if form == "x6" else 2
     ex = np.zeros((3, npair))
     if scale:
@@ -63,7 +74,7 @@ def _emulate(M, K, w, rows, kind, form, scale=True):
         for d in range(3):
             Y = (K[k] @ M[d]) * 2.0 ** -ex[d]
             if d == 2:
-                Y = Y * w[k]
+                Y = Y * (w[k] * 2.0 ** sh)
             Ys = _slices(Y, kind, ns)
             g = sum(A[d][i].T @ Ys[j] for i, j in PAIRS[form])
             G.append(g.astype(np.float32))
@@ -72,7 +83,7 @@ def _emulate(M, K, w, rows, kind, form, scale=True):
             acc64 += acc32.astype(np.float64)
             acc32[:] = 0
     e = ex[0] + ex[1] + ex[2]
-    return acc64 * (2.0 / np.sqrt(np.pi)) * 2.0 ** (e[rows][:, None] + e[None, :])
+    return acc64 * (2.0 / np.sqrt(np.pi)) * 2.0 ** (e[rows][:, None] + e[None, :] - sh)
 
 
 def _setup():
@@ -116,3 +127,28 @@ def test_f16_slices_need_the_power_of_two_scaling():
         assert _normwise(B, ref) <= 1e-6
     print(f"f16x3 mean element-wise error: scaled {mean_rel[True]:.2e}, unscaled {mean_rel[False]:.2e}")
     assert mean_rel[True] * 10 < mean_rel[False]
+
+
+def _mean_rel(B, ref):
+    big = np.abs(ref) >= 1e-8 * np.max(np.abs(ref))
+    return float(np.mean(np.abs(B - ref)[big] / np.abs(ref[big])))
+
+
+def test_f16_weight_shift_keeps_the_low_slices_normal():
+    """With w_k folded in unshifted, the low FP16 slices of the direction-2
+    operand are subnormal and the mean element-wise error is several times
+    that of the shifted form; the shifted form stays within 2e-6 mean, with
+    the normwise bar met either way.  BF16 has FP32's exponent range: the
+    shift changes its results only where FP32 products underflow."""
+    M, K, w, rows, ref = _setup()
+    B1 = _emulate(M, K, w, rows, "f16", "x3", wshift=True)
+    B0 = _emulate(M, K, w, rows, "f16", "x3", wshift=False)
+    m1, m0 = _mean_rel(B1, ref), _mean_rel(B0, ref)
+    print(f"f16x3 mean element-wise error: weight shift {m1:.2e}, none {m0:.2e}")
+    assert _normwise(B1, ref) <= 1e-6 and _normwise(B0, ref) <= 1e-6
+    assert m1 <= 2e-6
+    assert 3 * m1 < m0
+    Bb1 = _emulate(M, K, w, rows, "bf16", "x3", wshift=True)
+    Bb0 = _emulate(M, K, w, rows, "bf16", "x3", wshift=False)
+    assert _normwise(Bb1, Bb0) <= 1e-12
+    assert abs(_mean_rel(Bb1, ref) - _mean_rel(Bb0, ref)) <= 0.05 * _mean_rel(Bb0, ref)
