@@ -91,6 +91,17 @@ def src_sha():
     return h.hexdigest()[:16]
 
 
+def load_j_fixture():
+    """(pairs [m][2], J [m]) of the Nb = 1000 J workload from the oracle's
+    stored entries, or None if the file is absent."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "jbuild1000_J.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    return np.asarray(g["pairs"], dtype=np.int64), np.asarray(g["J"], dtype=np.float64)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,6 +376,20 @@ def main():
             japply[name] = {"ms_per_step": round(ms_j, 3),
                             "effective_entries_per_s": float(jb.npair) ** 2 / (ms_j / 1e3),
                             "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stj.items()}}
+        # against the oracle: J at 64 sampled pairs by the direct route
+        # (J_p = sum_q B(p,q) Dt_q over all 500500 pairs, rows of B from
+        # Theorem 3.1), written once by tests/golden/make_jbuild1000.py
+        gold = load_j_fixture()
+        if gold is not None:
+            gp, gj = gold
+            gmu = torch.as_tensor(gp[:, 0], device=dev)
+            gnu = torch.as_tensor(gp[:, 1], device=dev)
+            for name in ("fp64", "fp32"):
+                v = Jj[name][gmu, gnu].cpu().numpy()
+                japply[name]["rel_2norm_vs_oracle"] = float(np.linalg.norm(v - gj) / np.linalg.norm(gj))
+                japply[name]["normwise_vs_oracle"] = float(np.max(np.abs(v - gj)) / np.max(np.abs(gj)))
+            japply["oracle_sample"] = (f"{len(gj)} entries J(mu,nu) by the oracle's direct route "
+                                       "(tests/golden/jbuild1000_J.json)")
         ref, got = Jj["fp64"], Jj["fp32"]
         japply["fp32"]["rel_2norm_vs_fp64_gpu"] = float(torch.linalg.matrix_norm(got - ref, 2) /
                                                         torch.linalg.matrix_norm(ref, 2))
