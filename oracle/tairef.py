@@ -644,3 +644,120 @@ def J_direct_rows(M, K, w, D, rows):
     from Theorem 3.1 (eq. Coul in the atomic-orbital basis)."""
     Dt = density_pairs(D)
     return B_full(M, K, w, rows=rows) @ Dt
+
+
+# ---------------------------------------------------------------------------
+# Adaptive integration boxes (section 6.2): a box [-b_s, b_s] per cluster of
+# pairs, with the J of eq. coulapprox summed over the pairs of clusters
+# ---------------------------------------------------------------------------
+def pair_supports(center, alpha, tau):
+    """Half-width b_p of the centred box [-b_p, b_p]^3 that holds the numerical
+    support of pair p = (mu, nu), mu <= nu (section 6.2).  By the Gaussian
+    product rule the pair's exponential factor in direction d is
+    sigma(x) = exp(-p (x - P_d)^2), p = a + b, P = (a A + b B) / p, and
+    sigma(x) <= tau exactly when |x - P_d| >= r = sqrt(ln(1/tau) / p); the box
+    must reach P_d +- r in every direction, so b_p = max_d |P_d| + r."""
+    center = np.asarray(center, dtype=np.float64).reshape(-1, 3)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    mu, nu = pair_list(len(alpha))
+    a, b = alpha[mu], alpha[nu]
+    p = a + b
+    P = (a[:, None] * center[mu] + b[:, None] * center[nu]) / p[:, None]
+    r = np.sqrt(math.log(1.0 / tau) / p)
+    return np.max(np.abs(P), axis=1) + r
+
+
+def adaptive_partitions(supports, nparts):
+    """Clusters the pair supports into nparts boxes (section 6.2, which leaves
+    the clustering rule open).  Reading: equal-count quantiles of the sorted
+    supports.  With v_s the ceil(s npair / nparts)-th smallest support
+    (s = 1..nparts), partition s holds the pairs with v_{s-1} < b_p <= v_s
+    (v_0 = 0) and its box is [-v_s, v_s]: the smallest of the boxes that holds
+    the pair's support.  Equal supports stay together, so a partition can be
+    empty.  Returns (part [npair] int64, boxes [nparts])."""
+    b = np.asarray(supports, dtype=np.float64)
+    npair = len(b)
+    srt = np.sort(b)
+    ranks = [-(-s * npair // nparts) for s in range(1, nparts + 1)]   # ceil(s npair / nparts)
+    boxes = np.array([srt[k - 1] for k in ranks])
+    part = np.searchsorted(boxes, b, side="left").astype(np.int64)    # first s with b_p <= v_s
+    return part, boxes
+
+
+def cross_tables(t, xi_out, xi_in):
+    """K_k(a, b) = exp(-t_k^2 (xi_out[a] - xi_in[b])^2): node values of the
+    tensor Chebyshev interpolant of exp(-t_k^2 (x - y)^2) with x on the grid of
+    one box and y on the grid of another (eq. chebcheb on the rectangle
+    [-b_s, b_s] x [-b_s', b_s'])."""
+    d = xi_out[:, None] - xi_in[None, :]
+    return np.exp(-(t[:, None, None] ** 2) * d[None, :, :] ** 2)
+
+
+def partition_moments(center, alpha, lxyz, part, boxes, n, kind=NODES_LOBATTO, coef=None):
+    """Moments of each partition's pairs on the Chebyshev grid of its own box
+    (eq. defV with [-b, b] = [-b_s, b_s]): list of (pairs_s ascending,
+    M_s [3][n][len(pairs_s)])."""
+    out = []
+    for s in range(len(boxes)):
+        sel = np.flatnonzero(part == s)
+        M = moments(center, alpha, lxyz, boxes[s], n, kind=kind, coef=coef, pairs=sel) if len(sel) else \
+            np.zeros((3, n, 0))
+        out.append((sel, M))
+    return out
+
+
+def J_partitioned(pm, boxes, t, w, n, D, kind=NODES_LOBATTO):
+    """J of eq. coulapprox with adaptive boxes (section 6.2).  Every pair p of
+    partition s carries its moments on the grid of box s; the interaction of
+    pairs in partitions s and s' interpolates exp(-t_k^2 (x - y)^2) on
+    [-b_s, b_s] x [-b_s', b_s'], so with rho_s' = sum_{q in s'} Dt_q
+    (x)_d m_{q,d} on grid s',
+        Phi_s = (2/sqrt(pi)) sum_k w_k sum_s' rho_s' x_1 K_k^(s,s') x_2 K_k^(s,s') x_3 K_k^(s,s'),
+        J_p   = < (x)_d m_{p,d}, Phi_s >,   p in s,
+    the partition-wise form of the grid route (eq. ig1)."""
+    nb = D.shape[0]
+    Dt = density_pairs(D)
+    grids = [cheb_nodes(n, boxes[s], kind)[0] for s in range(len(boxes))]
+    rho = []
+    for sel, M in pm:
+        rho.append(np.einsum("q,aq,bq,cq->abc", Dt[sel], M[0], M[1], M[2], optimize=True))
+    Jp = np.zeros(len(Dt))
+    for s, (sel, M) in enumerate(pm):
+        if len(sel) == 0:
+            continue
+        Phi = np.zeros((n, n, n))
+        for s2 in range(len(pm)):
+            Kx = cross_tables(t, grids[s], grids[s2])
+            for k in range(len(t)):
+                Kk = Kx[k]
+                T = np.einsum("ia,abc->ibc", Kk, rho[s2], optimize=True)
+                T = np.einsum("jb,ibc->ijc", Kk, T, optimize=True)
+                T = np.einsum("kc,ijc->ijk", Kk, T, optimize=True)
+                Phi += w[k] * T
+        Phi *= 2.0 / SQRT_PI
+        Jp[sel] = np.einsum("ap,bp,cp,abc->p", M[0], M[1], M[2], Phi, optimize=True)
+    return unpack_pairs(Jp, nb)
+
+
+def B_partitioned_entries(pm, boxes, t, w, n, p_idx, q_idx, kind=NODES_LOBATTO):
+    """Entries B(p, q) of the adaptive-box approximation by Algorithm 1:
+    B(p,q) = (2/sqrt(pi)) sum_k w_k prod_d m_{p,d}^T K_k^(s,s') m_{q,d}, p in
+    partition s, q in s' (pair indices into the full list)."""
+    where = {}
+    for s, (sel, _) in enumerate(pm):
+        for i, p in enumerate(sel):
+            where[int(p)] = (s, i)
+    grids = [cheb_nodes(n, boxes[s], kind)[0] for s in range(len(boxes))]
+    out = np.zeros(len(p_idx))
+    for e, (p, q) in enumerate(zip(p_idx, q_idx)):
+        s, i = where[int(p)]
+        s2, i2 = where[int(q)]
+        Kx = cross_tables(t, grids[s], grids[s2])
+        acc = 0.0
+        for k in range(len(t)):
+            f = 1.0
+            for d in range(3):
+                f *= pm[s][1][d][:, i] @ Kx[k] @ pm[s2][1][d][:, i2]
+            acc += w[k] * f
+        out[e] = (2.0 / SQRT_PI) * acc
+    return out
