@@ -761,3 +761,33 @@ def B_partitioned_entries(pm, boxes, t, w, n, p_idx, q_idx, kind=NODES_LOBATTO):
             acc += w[k] * f
         out[e] = (2.0 / SQRT_PI) * acc
     return out
+
+
+def J_partitioned_rows(pm, boxes, t, w, n, D, rows, kind=NODES_LOBATTO):
+    """J_p = sum_q B(p, q) Dt_q for the given pairs p (indices into the full
+    list) with adaptive boxes: the direct route, rows of B from Theorem 3.1
+    on the pairs' boxes (the same entries as B_partitioned_entries, a pair p
+    against every pair of one partition at a time)."""
+    Dt = density_pairs(D)
+    where = {}
+    for s, (sel, _) in enumerate(pm):
+        for i, p in enumerate(sel):
+            where[int(p)] = (s, i)
+    grids = [cheb_nodes(n, boxes[s], kind)[0] for s in range(len(boxes))]
+    out = np.zeros(len(rows))
+    for e, p in enumerate(rows):
+        s, i = where[int(p)]
+        acc = 0.0
+        for s2, (sel2, M2) in enumerate(pm):
+            if len(sel2) == 0:
+                continue
+            Kx = cross_tables(t, grids[s], grids[s2])
+            F = np.zeros(len(sel2))
+            for k in range(len(t)):
+                f = np.ones(len(sel2))
+                for d in range(3):
+                    f *= (pm[s][1][d][:, i] @ Kx[k]) @ M2[d]
+                F += w[k] * f
+            acc += F @ Dt[sel2]
+        out[e] = (2.0 / SQRT_PI) * acc
+    return out

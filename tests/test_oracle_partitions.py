@@ -97,6 +97,11 @@ def test_grid_route_equals_algorithm_1_over_partition_pairs():
     assert np.max(np.abs(B - B.T)) <= 1e-13 * np.max(np.abs(B))
     ref = T.unpack_pairs(B @ T.density_pairs(D), b.nb)
     assert np.max(np.abs(J - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # the row form of the direct route (the full-size fixture's writer)
+    rows = np.arange(0, npair, 3)
+    mu, nu = T.pair_list(b.nb)
+    jr = T.J_partitioned_rows(pm, boxes, t, w, n, D, rows)
+    assert np.max(np.abs(jr - ref[mu[rows], nu[rows]])) <= 1e-12 * np.max(np.abs(ref))
 
 
 def test_converges_to_the_closed_form_and_fixed_boxes_truncate():
