@@ -48,6 +48,10 @@ RANK_TOL_J = 1e-5
 SCREEN_TAU = 1e-12
 # orbitals of the orbital-basis Coulomb matrix leg
 NORB = 16
+# adaptive integration boxes: support cut and number of boxes (the paper's
+# figure of the support distribution uses 1e-20)
+PARTS_TAU = 1e-20
+PARTS_N = 4
 
 
 def log(msg):
@@ -91,11 +95,11 @@ def src_sha():
     return h.hexdigest()[:16]
 
 
-def load_j_fixture():
+def load_j_fixture(name="jbuild1000_J.json"):
     """(pairs [m][2], J [m]) of the Nb = 1000 J workload from the oracle's
     stored entries, or None if the file is absent."""
     import numpy as np
-    path = os.path.join(ROOT, "tests", "golden", "jbuild1000_J.json")
+    path = os.path.join(ROOT, "tests", "golden", name)
     if not os.path.exists(path):
         return None
     g = json.load(open(path))
@@ -354,10 +358,11 @@ def main():
         jba = tai.BasisArrays(jb)
         Mj = torch.empty((3, jP.n, jb.npair), dtype=torch.float64, device=dev)
         Dj = torch.as_tensor(D, device=dev)
-        Jj = {name: torch.empty((jb.nb, jb.nb), dtype=torch.float64, device=dev) for name in ("fp64", "fp32")}
+        JNAMES = ("fp64", "fp32", "bf16x6", "bf16x3")
+        Jj = {name: torch.empty((jb.nb, jb.nb), dtype=torch.float64, device=dev) for name in JNAMES}
         japply = {"workload": "Nb=1000 (100 atoms s,p,d), 500500 pairs, omega=0.4, nq=32, n=48, L=24; "
                               "step = moments + J (B never stored)"}
-        for name in ("fp64", "fp32"):
+        for name in JNAMES:
             jparams = tai.make_params(jP, tai.PREC_BY_NAME[name])
             log(f"J-build {name}: Nb=1000")
             for _ in range(W):
@@ -384,7 +389,7 @@ def main():
             gp, gj = gold
             gmu = torch.as_tensor(gp[:, 0], device=dev)
             gnu = torch.as_tensor(gp[:, 1], device=dev)
-            for name in ("fp64", "fp32"):
+            for name in JNAMES:
                 v = Jj[name][gmu, gnu].cpu().numpy()
                 japply[name]["rel_2norm_vs_oracle"] = float(np.linalg.norm(v - gj) / np.linalg.norm(gj))
                 japply[name]["normwise_vs_oracle"] = float(np.max(np.abs(v - gj)) / np.max(np.abs(gj)))
@@ -394,7 +399,14 @@ def main():
         japply["fp32"]["rel_2norm_vs_fp64_gpu"] = float(torch.linalg.matrix_norm(got - ref, 2) /
                                                         torch.linalg.matrix_norm(ref, 2))
         japply["fp32"]["normwise_vs_fp64_gpu"] = float((got - ref).abs().max() / ref.abs().max())
-        japply["fp32"]["speedup_vs_fp64"] = round(japply["fp64"]["ms_per_step"] / japply["fp32"]["ms_per_step"], 3)
+        for name in JNAMES[1:]:
+            japply[name]["speedup_vs_fp64"] = round(japply["fp64"]["ms_per_step"] / japply[name]["ms_per_step"], 3)
+            japply[name]["apply_J_speedup_vs_fp64"] = round(japply["fp64"]["stage_ms"]["apply_J"] /
+                                                            japply[name]["stage_ms"]["apply_J"], 3)
+        for name in ("bf16x6", "bf16x3"):
+            got = Jj[name]
+            japply[name]["rel_2norm_vs_fp64_gpu"] = float(torch.linalg.matrix_norm(got - ref, 2) /
+                                                          torch.linalg.matrix_norm(ref, 2))
         # the same J-build over the pairs kept by screening
         jpairs = torch.empty(jb.npair, dtype=torch.int32, device=dev)
         jparams = tai.make_params(jP, tai.FP64)
@@ -422,6 +434,46 @@ def main():
                       "rel_2norm_vs_unscreened_gpu": float(torch.linalg.matrix_norm(Js - ref, 2) /
                                                            torch.linalg.matrix_norm(ref, 2))}
         japply["screened_fp64"] = screened_j
+        # adaptive integration boxes (section 6.2): supports at tau = 1e-20,
+        # four equal-count quantile boxes; a step = partitions + moments of
+        # every partition on its box + J over the box pairs
+        gparts = load_j_fixture("jbuild1000_Jparts.json")
+        adaptive = {"tau": PARTS_TAU, "nparts": PARTS_N}
+        lst = torch.empty(jb.npair, dtype=torch.int32, device=dev)
+        Mpt = torch.empty(3 * jP.n * jb.npair, dtype=torch.float64, device=dev)
+        Jpt = torch.empty_like(Jj["fp64"])
+        for name in ("fp64", "bf16x6"):
+            jparams = tai.make_params(jP, tai.PREC_BY_NAME[name])
+            log(f"adaptive-box J-build {name}: nparts={PARTS_N}")
+            for it in range(W + K):
+                if it == W:
+                    torch.cuda.synchronize()
+                    ctx.profile_enable(True)
+                    t0 = time.perf_counter()
+                counts, boxes = ctx.partition_pairs(jba, PARTS_TAU, PARTS_N, lst)
+                off = 0
+                for c_, bx_ in zip(counts, boxes):
+                    if c_:
+                        ctx.moments_pairs(jba, dataclasses.replace(jP, L=bx_), lst[off:], c_,
+                                          Mpt[3 * jP.n * off:3 * jP.n * (off + c_)])
+                    off += c_
+                ctx.apply_J_partitioned(Mpt, jb.nb, lst, counts, boxes, jparams, Dj, Jpt)
+            torch.cuda.synchronize()
+            ms_pt = (time.perf_counter() - t0) * 1e3 / K
+            stp = {s_: ctx.profile_read(s_) for s_ in ("nodes", "moments", "apply_J")}
+            ctx.profile_enable(False)
+            rec = {"ms_per_step": round(ms_pt, 3), "boxes": [round(x, 4) for x in boxes], "counts": counts,
+                   "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stp.items()},
+                   "step_ratio_vs_fixed_box": round(ms_pt / japply[name]["ms_per_step"], 3),
+                   "rel_2norm_vs_fixed_box_L24_gpu": float(torch.linalg.matrix_norm(Jpt - Jj["fp64"], 2) /
+                                                           torch.linalg.matrix_norm(Jj["fp64"], 2))}
+            if gparts is not None:
+                gp, gj = gparts
+                v = Jpt[torch.as_tensor(gp[:, 0], device=dev), torch.as_tensor(gp[:, 1], device=dev)].cpu().numpy()
+                rec["rel_2norm_vs_oracle"] = float(np.linalg.norm(v - gj) / np.linalg.norm(gj))
+            adaptive[name] = rec
+        japply["adaptive_boxes"] = adaptive
+        del lst, Mpt, Jpt
         # the same J-build on the compressed grid (R^3 instead of n^3)
         jPc = dataclasses.replace(jP, rank_tol=RANK_TOL_J)
         ctx.moments(jba, jP, Mj)
@@ -471,13 +523,14 @@ def main():
         # the orbital-basis Coulomb matrix of NORB orbitals on the same grid
         Qo = torch.as_tensor(np.random.default_rng(17).standard_normal((NORB, jb.nb)) / np.sqrt(jb.nb), device=dev)
         Jmo = torch.empty((NORB, NORB), dtype=torch.float64, device=dev)
+        jparams_mo = tai.make_params(jP, tai.FP64)
         log(f"orbital-basis Coulomb matrix fp64: norb={NORB}")
         ctx.moments(jba, jP, Mj)
         for it in range(W + K):
             if it == W:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-            ctx.coulomb_mo(Mj, jb.nb, jparams, Qo, NORB, Jmo)
+            ctx.coulomb_mo(Mj, jb.nb, jparams_mo, Qo, NORB, Jmo)
         torch.cuda.synchronize()
         ms_mo = (time.perf_counter() - t0) * 1e3 / K
         japply["coulomb_mo_fp64"] = {"norb": NORB, "ms_per_call": round(ms_mo, 3),
@@ -502,31 +555,52 @@ def main():
         del Jmo_c
         del Mj, Jj, Js, Mjs, Jmo
         torch.cuda.empty_cache()
-        # the long-range exchange matrix (appendix B) on the Nb = 64 workload:
-        # one grid tensor X_{j mu} and its Phi per (orbital, function)
-        xb, xP = I.sp16()
-        xba = tai.BasisArrays(xb)
+        # the long-range exchange matrix (appendix B) by its factorized form:
+        # the X_{j mu} grid tensors over the nb pairs of each mu, the mode
+        # products of all (orbital, function) tensors batched, then X Phi^T;
+        # on the Nb = 64 workload and on the Nb = 400 headline basis
         norb_x = 8
-        Mx = torch.empty((3, xP.n, xb.npair), dtype=torch.float64, device=dev)
-        ctx.moments(xba, xP, Mx)
-        Qx = torch.as_tensor(np.random.default_rng(19).standard_normal((norb_x, xb.nb)) / np.sqrt(xb.nb), device=dev)
-        Kx = torch.empty((xb.nb, xb.nb), dtype=torch.float64, device=dev)
-        exchange = {"workload": f"sp16: Nb={xb.nb}, {xb.npair} pairs, nq={xP.nq}, n={xP.n}, {norb_x} orbitals",
-                    "tensors": norb_x * xb.nb}
-        for name, Px, prec in (("fp64", xP, tai.FP64), ("fp32", xP, tai.FP32),
-                               ("fp64_compressed", dataclasses.replace(xP, rank_tol=RANK_TOL_J), tai.FP64)):
-            xparams = tai.make_params(Px, prec)
-            log(f"exchange {name}: Nb={xb.nb} norb={norb_x}")
-            for it in range(W + K):
-                if it == W:
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                ctx.exchange(Mx, xb.nb, xparams, Qx, norb_x, Kx)
-            torch.cuda.synchronize()
-            exchange[name] = {"ms_per_call": round((time.perf_counter() - t0) * 1e3 / K, 3),
-                              "symmetry_rel": float((Kx - Kx.T).abs().max() / Kx.abs().max())}
+        exchange = {"norb": norb_x,
+                    "flops": "2 n^3 nb^2 norb (X) + norb nb nq 6 n^4 (mode products) + 2 nb^2 norb n^3 (X Phi^T)"}
+        for xname, (xb, xP), legs in (("sp16", I.sp16(), ("fp64", "fp32", "fp64_compressed")),
+                                      ("spd400", I.spd400(omega=0.3), ("fp64",))):
+            xba = tai.BasisArrays(xb)
+            Mx = torch.empty((3, xP.n, xb.npair), dtype=torch.float64, device=dev)
+            ctx.moments(xba, xP, Mx)
+            Qx = torch.as_tensor(np.random.default_rng(19).standard_normal((norb_x, xb.nb)) / np.sqrt(xb.nb),
+                                 device=dev)
+            Kx = torch.empty((xb.nb, xb.nb), dtype=torch.float64, device=dev)
+            nx, nqx, nbx = xP.n, xP.nq, xb.nb
+            xfl = 2.0 * nx ** 3 * nbx ** 2 * norb_x + norb_x * nbx * nqx * 6.0 * nx ** 4 + 2.0 * nbx ** 2 * norb_x * nx ** 3
+            rec = {"workload": f"{xname}: Nb={nbx}, {xb.npair} pairs, nq={nqx}, n={nx}, {norb_x} orbitals",
+                   "tensors": norb_x * nbx, "flops_per_call": xfl}
+            for name in legs:
+                Px = dataclasses.replace(xP, rank_tol=RANK_TOL_J) if name.endswith("compressed") else xP
+                prec = tai.FP32 if name == "fp32" else tai.FP64
+                xparams = tai.make_params(Px, prec)
+                kx = K if xname == "sp16" else max(1, K // 2)
+                log(f"exchange {xname} {name}: Nb={nbx} norb={norb_x} calls={kx}")
+                for it in range(W + kx):
+                    if it == W:
+                        torch.cuda.synchronize()
+                        ctx.profile_enable(True)
+                        t0 = time.perf_counter()
+                    ctx.exchange(Mx, nbx, xparams, Qx, norb_x, Kx)
+                torch.cuda.synchronize()
+                ms_x = (time.perf_counter() - t0) * 1e3 / kx
+                kern = ctx.profile_read("apply_J")
+                ctx.profile_enable(False)
+                kms = kern[0] / max(1, kern[1])
+                rec[name] = {"ms_per_call": round(ms_x, 3), "kernels_ms": round(kms, 3),
+                             "symmetry_rel": float((Kx - Kx.T).abs().max() / Kx.abs().max())}
+                if name == "fp64":
+                    tf = xfl / (kms / 1e3) / 1e12
+                    rec[name]["tflops_algorithmic"] = round(tf, 2)
+                    rec[name]["frac_of_fp64_peak"] = round(tf / PEAK_TFLOPS["fp64"], 4)
+            exchange[xname] = rec
+            del Mx, Kx
+            torch.cuda.empty_cache()
         japply["exchange"] = exchange
-        del Mx, Kx
 
     # ---------------- the device's own sustained peaks ------------------------
     if not args.only_headline:

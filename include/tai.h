@@ -196,7 +196,7 @@ int tai_compress(tai_ctx* ctx, const double* M, int32_t npair, const tai_params*
    tai_compress returned (1 <= R <= params->n); U: DEVICE double
    [3][Rp][npk or npair] and Kc: DEVICE double [nq][Rp][Rp] as tai_compress
    wrote them, Rp = min(n, 8 ceil(R / 8)); params gives omega, nq, n, L, nodes
-   (for the weights w_k) and prec (TAI_FP64 or TAI_FP32); rank_tol and
+   (for the weights w_k) and prec (TAI_FP64, TAI_FP32, TAI_BF16X3 or TAI_BF16X6, as for tai_apply_J); rank_tol and
    degree_tol are not read.  The result equals that of tai_apply_J with the
    same rank_tol bit for bit. */
 int tai_apply_J_compressed(tai_ctx* ctx, const double* U, int32_t nb, const int32_t* pairs, int32_t npk,
@@ -256,12 +256,24 @@ int tai_assemble_B_batched(tai_ctx* ctx, int32_t nmol, const tai_mol* mols, void
    only its upper triangle is read; J: DEVICE double [nb][nb], fully written.
    params->prec selects the arithmetic of the two pair contractions (rho and
    the projection onto the pairs), both on the matrix cores:
-     TAI_FP64  FP64 throughout;
-     TAI_FP32  FP32 operands and products, summed in FP32 within a batch of
-               64 pairs (rho) or one 16-row block (projection) and in FP64
-               beyond; the mode products and the contraction with m_{p,0},
-               m_{p,1} stay FP64.
-   Other modes return TAI_ERR_UNSUPPORTED. */
+     TAI_FP64   FP64 throughout;
+     TAI_FP32   FP32 operands and products, summed in FP32 within a batch of
+                64 pairs (rho) or one 16-row block (projection) and in FP64
+                beyond; the mode products and the contraction with m_{p,0},
+                m_{p,1} stay FP64.
+     TAI_BF16X6 the projection onto the pairs in split BF16: Phi and the
+                FP32 moments cut into 3 bfloat16 slices, 6 slice products
+                per term (bf16 MFMA, FP32 accumulation, FP64 across a1);
+                rho as for TAI_FP32 (in split BF16 the matrix cores'
+                accumulation of the heavily cancelling pair sums costs
+                several times the FP32 accuracy).
+     TAI_BF16X3 both contractions in split BF16 with 2 slices and 3
+                products (16 significant bits: a few 1e-6 relative): rho's
+                operand Dt_q m_{q,0}(a0) m_{q,1}(a1) formed in FP32 and
+                split, summed in FP32 within a batch of 64 pairs and in FP64
+                beyond.
+   TAI_F16X3 returns TAI_ERR_UNSUPPORTED (its range scaling does not carry
+   across the sum over pairs). */
 int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* params,
                 const double* D, double* J, void* stream);
 
@@ -352,6 +364,46 @@ int tai_moments_pairs(tai_ctx* ctx, const tai_basis* basis, const tai_params* pa
    tai_apply_J. */
 int tai_apply_J_pairs(tai_ctx* ctx, const double* M, int32_t nb, const int32_t* pairs, int32_t npk,
                       const tai_params* params, const double* D, double* J, void* stream);
+
+/* ---- adaptive integration boxes (section 6.2) ----------------------------- */
+
+/* Clusters the pairs into nparts boxes.  The numerical support of pair p
+   (mu <= nu) is the centred box [-b_p, b_p]^3 outside which its Gaussian
+   factor exp(-p (x_d - P_d)^2) (Gaussian product rule, eq. gauss_prod) is
+   below tau in every direction: b_p = max_d |P_d| + sqrt(ln(1/tau) / p),
+   p = a_mu + a_nu, P = (a_mu A_mu + a_nu A_nu) / p.  The supports are cut
+   into equal-count quantiles (the paper leaves the clustering open): box s
+   (s = 0 .. nparts-1) is [-v_s, v_s] with v_s the ceil((s+1) npair / nparts)-th
+   smallest support, and pair p goes to the first box that holds its
+   support (v_{s-1} < b_p <= v_s), so equal supports share a partition and a
+   partition can be empty.  0 < tau < 1; 1 <= nparts <= 16.
+   pairs: DEVICE int32 [npair], written with the pair indices of partition 0,
+   then 1, ..., each partition's in ascending order; counts: HOST int32
+   [nparts], pairs per partition; boxes: HOST double [nparts], v_s
+   (ascending).  The call waits for `stream` to return counts and boxes. */
+int tai_partition_pairs(tai_ctx* ctx, const tai_basis* basis, double tau, int32_t nparts, int32_t* pairs,
+                        int32_t* counts, double* boxes, void* stream);
+
+/* J with adaptive boxes (eq. coulapprox with the boxes of section 6.2,
+   tai_partition_pairs): every pair of partition s carries its moments on
+   the Chebyshev grid of box s, and two partitions s, s' interact through the
+   interpolant of exp(-t_k^2 (x - y)^2) on [-v_s, v_s] x [-v_s', v_s'], with
+   node values K_k^(s,s')(a, b) = exp(-t_k^2 (xi^s_a - xi^s'_b)^2):
+     rho_s  = sum_{q in s} Dt_q (x)_d m_{q,d}                 (grid of box s)
+     Phi_s  = (2/sqrt(pi)) sum_k w_k sum_s' rho_s' x_1 K_k^(s,s') x_2 K_k^(s,s') x_3 K_k^(s,s')
+     J_p    = < (x)_d m_{p,d}, Phi_s >,  p in s,
+   i.e. sum over all pairs q of B(p, q) Dt_q with B(p, q) from Theorem 3.1 on
+   the two pairs' boxes.  M: DEVICE double, the partitions' moment blocks one
+   after another, block s = [3][n][counts[s]] as tai_moments_pairs writes it
+   for the pairs of partition s with params->L = boxes[s]; pairs, counts,
+   boxes as from tai_partition_pairs (counts adding up to npair(nb), boxes
+   > 0); D, J as for tai_apply_J.  params gives omega, nq, n, nodes and prec
+   (TAI_FP64, TAI_FP32, TAI_BF16X3, TAI_BF16X6; the mode products stay FP64);
+   params->L is not read; rank_tol and degree_tol must be 0
+   (TAI_ERR_UNSUPPORTED). */
+int tai_apply_J_partitioned(tai_ctx* ctx, const double* M, int32_t nb, const int32_t* pairs, const int32_t* counts,
+                            const double* boxes, int32_t nparts, const tai_params* params, const double* D, double* J,
+                            void* stream);
 
 /* ---- tuning ------------------------------------------------------------- */
 

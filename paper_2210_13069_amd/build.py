@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtai.so")
-SOURCES = ["tai_api.hip", "k_nodes.hip", "k_moments.hip", "k_assemble.hip", "k_assemble16.hip", "k_apply_j.hip", "k_probe.hip", "k_contract.hip", "k_assemble32.hip", "k_compress.hip"]
+SOURCES = ["tai_api.hip", "k_nodes.hip", "k_moments.hip", "k_assemble.hip", "k_assemble16.hip", "k_apply_j.hip", "k_probe.hip", "k_contract.hip", "k_assemble32.hip", "k_compress.hip", "k_exchange.hip", "k_partition.hip"]
 ARCH = os.environ.get("TAI_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

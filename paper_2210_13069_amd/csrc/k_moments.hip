@@ -134,13 +134,14 @@ moments_kernel(DevBasis bs, int n, double L, NodeTables tb, double* __restrict__
 // indices come out in ascending order.  The exponent is formed with
 // unfused, left-to-right operations.
 __device__ inline bool keep_pair(const DevBasis& bs, double tau, int mu, int nu) {
+#pragma clang fp contract(off)
   const double a = bs.alpha[mu], b = bs.alpha[nu];
   double r2 = 0.0;
   for (int d = 0; d < 3; ++d) {
-    const double x = __dsub_rn(bs.center[3 * mu + d], bs.center[3 * nu + d]);
-    r2 = __dadd_rn(r2, __dmul_rn(x, x));
+    const double x = bs.center[3 * mu + d] - bs.center[3 * nu + d];
+    r2 = r2 + x * x;
   }
-  const double e = __dmul_rn(__ddiv_rn(__dmul_rn(a, b), __dadd_rn(a, b)), r2);
+  const double e = (a * b) / (a + b) * r2;
   return tau <= 0.0 || exp(-e) > tau;
 }
 

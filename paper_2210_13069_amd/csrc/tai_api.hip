@@ -36,6 +36,7 @@ struct tai_ctx {
   Buf opMu;               // coefficient moments (per-node degrees)
   Buf cmp, cmpU;          // low-rank compression: basis, Gram, tables; compressed moments
   Buf screen;             // screening: row counts / offsets and the kept count
+  Buf part, partJ;        // adaptive boxes: supports, sort and lists; partitioned J intermediates
   Buf mo;                 // orbital-basis Coulomb matrix: rho and Phi of every orbital
   Buf ct, ct_work;        // contraction: member tables; primitive-basis D and J
   Buf ct_host;            // pinned staging of the member tables
@@ -81,12 +82,14 @@ int hip_fail(tai_ctx* c, hipError_t e, const char* where) {
 
 bool finite(double x) { return std::isfinite(x); }
 
-int validate_params(tai_ctx* c, const tai_params* p) {
+// check_L = false where the half-widths come from elsewhere (the boxes of
+// the partitioned J) and params->L is not read.
+int validate_params(tai_ctx* c, const tai_params* p, bool check_L = true) {
   if (!p) return fail(c, TAI_ERR_INVALID_ARG, "params is NULL");
   if (!finite(p->omega) || !(p->omega > 0)) return fail(c, TAI_ERR_INVALID_ARG, "omega must be finite and > 0");
   if (p->nq < 1 || p->nq > 128) return fail(c, TAI_ERR_INVALID_ARG, "nq must be in [1, 128]");
   if (p->n < 2 || p->n > 64) return fail(c, TAI_ERR_INVALID_ARG, "n must be in [2, 64]");
-  if (!finite(p->L) || !(p->L > 0)) return fail(c, TAI_ERR_INVALID_ARG, "L must be finite and > 0");
+  if (check_L && (!finite(p->L) || !(p->L > 0))) return fail(c, TAI_ERR_INVALID_ARG, "L must be finite and > 0");
   if (p->nodes != TAI_NODES_LOBATTO && p->nodes != TAI_NODES_GAUSS)
     return fail(c, TAI_ERR_INVALID_ARG, "nodes must be TAI_NODES_LOBATTO or TAI_NODES_GAUSS");
   if (p->prec < TAI_FP64 || p->prec > TAI_F16X3) return fail(c, TAI_ERR_INVALID_ARG, "unknown prec");
@@ -134,6 +137,10 @@ int need_device(tai_ctx* c) {
 }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Arithmetics of the pair contractions of J: FP64, FP32, and the split-BF16
+// forms (F16X3 would need the operands scaled across the sum over pairs).
+bool j_prec_ok(int prec) { return prec == TAI_FP64 || prec == TAI_FP32 || prec == TAI_BF16X3 || prec == TAI_BF16X6; }
 
 const char* const kStageNames[] = {"nodes", "moments", "pack", "project", "assemble", "apply_J", "batched", "compress"};
 constexpr int kNumStages = 8;
@@ -493,7 +500,7 @@ int tai_destroy(tai_ctx* c) {
   if (c->device >= 0) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->screen, &c->mo, &c->ct, &c->ct_work,
+    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->screen, &c->part, &c->partJ, &c->mo, &c->ct, &c->ct_work,
                    &c->asm_tab,
                    &c->asm_counter,
                    &c->jwork,
@@ -637,8 +644,8 @@ int tai_apply_J_compressed(tai_ctx* c, const double* U, int32_t nb, const int32_
   if (npair_of(nb) > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
   if (pairs && (npk < 1 || npk > npair_of(nb))) return fail(c, TAI_ERR_INVALID_ARG, "npk must be in [1, npair]");
   if (R < 1 || R > p->n) return fail(c, TAI_ERR_INVALID_ARG, "R must be in [1, n]");
-  if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
-    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_compressed supports prec TAI_FP64 and TAI_FP32");
+  if (!j_prec_ok(p->prec))
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_compressed supports prec TAI_FP64, TAI_FP32, TAI_BF16X3 and TAI_BF16X6");
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nq = p->nq;
@@ -702,6 +709,101 @@ int tai_screen_pairs(tai_ctx* c, const tai_basis* b, double tau, int32_t* pairs,
     return hip_fail(c, e, "count copy");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
   *nkept = host;
+  return TAI_OK;
+}
+
+int tai_partition_pairs(tai_ctx* c, const tai_basis* b, double tau, int32_t nparts, int32_t* pairs, int32_t* counts,
+                        double* boxes, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_basis(c, b))) return r;
+  if (!std::isfinite(tau) || !(tau > 0.0) || !(tau < 1.0)) return fail(c, TAI_ERR_INVALID_ARG, "tau must be in (0, 1)");
+  if (nparts < 1 || nparts > tai::kMaxParts)
+    return fail(c, TAI_ERR_INVALID_ARG, "nparts must be in [1, " + std::to_string(tai::kMaxParts) + "]");
+  if (!pairs || !counts || !boxes) return fail(c, TAI_ERR_INVALID_ARG, "pairs, counts or boxes is NULL");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tai::DevBasis db;
+  if ((r = upload_basis(c, b, s, &db))) return r;
+  if ((r = ensure(c, c->part, tai::partition_work_bytes(b->nb, nparts)))) return r;
+  const tai::PartWork w = tai::carve_partition_work(c->part.p, b->nb, nparts);
+  hipError_t e;
+  {
+    Timed tm(c, kStMoments, s);
+    e = tai::launch_partition(db, std::log(1.0 / tau), nparts, w, pairs, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "partition kernels");
+  double hb[tai::kMaxParts];
+  int32_t hc[tai::kMaxParts];
+  if ((e = hipMemcpyAsync(hb, w.boxes, sizeof(double) * nparts, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(c, e, "boxes copy");
+  if ((e = hipMemcpyAsync(hc, w.totals, sizeof(int32_t) * nparts, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(c, e, "counts copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  for (int i = 0; i < nparts; ++i) {
+    boxes[i] = hb[i];
+    counts[i] = hc[i];
+  }
+  return TAI_OK;
+}
+
+int tai_apply_J_partitioned(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs, const int32_t* counts,
+                            const double* boxes, int32_t nparts, const tai_params* p, const double* D, double* J,
+                            void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p, false))) return r;
+  if (!M || !pairs || !counts || !boxes || !D || !J) return fail(c, TAI_ERR_INVALID_ARG, "a pointer is NULL");
+  if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
+  const int64_t npair = npair_of(nb);
+  if (npair > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
+  if (nparts < 1 || nparts > tai::kMaxParts)
+    return fail(c, TAI_ERR_INVALID_ARG, "nparts must be in [1, " + std::to_string(tai::kMaxParts) + "]");
+  int64_t offs[tai::kMaxParts + 1];
+  offs[0] = 0;
+  tai::PartBoxes bx{};
+  bx.nparts = nparts;
+  for (int i = 0; i < nparts; ++i) {
+    if (counts[i] < 0) return fail(c, TAI_ERR_INVALID_ARG, "counts must be >= 0");
+    if (!std::isfinite(boxes[i]) || !(boxes[i] > 0)) return fail(c, TAI_ERR_INVALID_ARG, "boxes must be finite and > 0");
+    offs[i + 1] = offs[i] + counts[i];
+    bx.b[i] = boxes[i];
+  }
+  if (offs[nparts] != npair) return fail(c, TAI_ERR_INVALID_ARG, "the partition counts must add up to npair");
+  if (!j_prec_ok(p->prec))
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_partitioned supports prec TAI_FP64, TAI_FP32, TAI_BF16X3 and TAI_BF16X6");
+  if (p->rank_tol > 0 || p->degree_tol > 0)
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_partitioned: rank_tol and degree_tol must be 0");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nq = p->nq, n = p->n;
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
+  const size_t n3 = (size_t)n * n * n;
+  const size_t jb = align256(tai::j_work_bytes(p->prec, nq, n, (int)npair));
+  const size_t rb = align256(8 * n3 * nparts), tb2 = align256(8 * n3 * nq * nparts), wb = align256(8 * nq * nparts);
+  const size_t kb = align256(8 * (size_t)nparts * nparts * nq * n * n);
+  if ((r = ensure(c, c->partJ, jb + rb + tb2 + wb + kb))) return r;
+  char* base = static_cast<char*>(c->partJ.p);
+  tai::JWork w = tai::carve_j_work(base, p->prec, nq, n, (int)npair);
+  double* rho_all = reinterpret_cast<double*>(base + jb);
+  double* T2_all = reinterpret_cast<double*>(base + jb + rb);
+  double* wrep = reinterpret_cast<double*>(base + jb + rb + tb2);
+  double* Kx = reinterpret_cast<double*>(base + jb + rb + tb2 + wb);
+  hipError_t e;
+  {
+    Timed tm(c, kStNodes, s);
+    // t_k, w_k (the plain tables on the largest box are not used)
+    e = tai::launch_nodes(p->omega, nq, n, boxes[nparts - 1], p->nodes, 0.0, tb, s);
+    if (e == hipSuccess) e = tai::launch_cross_tables(tb.t, nq, n, p->nodes, bx, Kx, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "node kernels");
+  {
+    Timed tm(c, kStApplyJ, s);
+    e = tai::launch_apply_j_parts(p->prec, M, nb, pairs, offs, nparts, n, nq, tb.w, Kx, D, J, w, rho_all, T2_all,
+                                  wrep, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "partitioned apply_J kernels");
   return TAI_OK;
 }
 
@@ -1156,8 +1258,8 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
 static int apply_j_impl(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs, int64_t npair,
                         const tai_params* p, const double* D, double* J, void* stream) {
   int r;
-  if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
-    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J supports prec TAI_FP64 and TAI_FP32");
+  if (!j_prec_ok(p->prec))
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J supports prec TAI_FP64, TAI_FP32, TAI_BF16X3 and TAI_BF16X6");
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nq = p->nq;
@@ -1258,15 +1360,12 @@ int tai_exchange(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs, 
   const double* Mop = M;
   int n = p->n;
   if ((r = prepare_operands(c, M, npair, p, s, &tb, &Mop, &n, &tbp))) return r;
-  const size_t slots = (size_t)norb * nb * n * n * n;
-  if ((r = ensure(c, c->jwork, tai::j_work_bytes(p->prec, nq, n, (int)npair)))) return r;
-  if ((r = ensure(c, c->mo, 2 * sizeof(double) * slots))) return r;
+  const tai::ExchangeWork plan = tai::exchange_work_plan(n, nq, nb, norb, pairs != nullptr, npair_of(nb));
+  if ((r = ensure(c, c->mo, plan.bytes))) return r;
   hipError_t e;
-  tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, n, (int)npair);
-  double* R = static_cast<double*>(c->mo.p);
   {
     Timed tm(c, kStApplyJ, s);
-    e = tai::launch_exchange(p->prec, Mop, nb, (int)npair, pairs, n, nq, tbp, Q, norb, R, R + slots, Kx, w, s);
+    e = tai::launch_exchange(p->prec, Mop, nb, npair, pairs, n, nq, tbp, Q, norb, c->mo.p, plan, Kx, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "exchange kernels");
   return TAI_OK;
@@ -1343,8 +1442,8 @@ int tai_apply_J_contracted(tai_ctx* c, const double* M, int32_t nbp, const int32
   if (nbp < 1 || npair_of(nbp) > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "nbp out of range");
   const int32_t nb = contraction_nb(fmap, nbp);
   if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "fmap must start at 0 and step by 0 or 1");
-  if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
-    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_contracted supports prec TAI_FP64 and TAI_FP32");
+  if (!j_prec_ok(p->prec))
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_contracted supports prec TAI_FP64, TAI_FP32, TAI_BF16X3 and TAI_BF16X6");
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
   // device tables: fmap [nbp], first primitive of each function [nb + 1]

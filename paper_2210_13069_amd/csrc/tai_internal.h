@@ -228,7 +228,8 @@ struct JWork {
   double* T2;      // [nq][n^3] mode-0 products, before the sum over nodes
   double* Phi;     // [n^3]
   double* Jp;      // [npair]
-  float* M32;      // [3][n][npair] FP32 copy of the moments (FP32 only, else null)
+  float* M32;      // [3][n][npair] FP32 copy of the moments (FP32 and split BF16, else null)
+  void* Ps;        // [n][n][kc] bfloat16 slices of Phi (split BF16 only, else null)
   int nchunk;
 };
 int j_nchunk(int prec, int n, int npair);
@@ -297,9 +298,54 @@ hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const
 // Long-range exchange matrix (appendix B): X_{j mu} and Phi_{j nu} for every
 // orbital j and function mu into R and F ([norb][nb][n^3] each), then
 // Kx(mu, nu) = 2 sum_j <X_{j mu}, Phi_{j nu}>.
-hipError_t launch_exchange(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
-                           const NodeTables& tb, const double* Q, int norb, double* R, double* F, double* Kx,
-                           const JWork& w, hipStream_t s);
+// Adaptive integration boxes (section 6.2, k_partition.hip): the pair
+// supports, equal-count quantile boxes (sorted supports), the partitions'
+// pair lists (concatenated, each ascending) and the cross tables between the
+// boxes' Chebyshev grids.
+constexpr int kMaxParts = 16;
+struct PartBoxes {
+  double b[kMaxParts];
+  int nparts;
+};
+struct PartWork {
+  double* sup;        // [npair] support half-widths
+  double* sorted;     // [npair]
+  int32_t* counts;    // [nparts][nb] per-row counts, then list offsets
+  double* boxes;      // [nparts] box half-widths
+  int32_t* totals;    // [nparts] pairs per partition
+  void* temp;         // sort workspace
+  size_t temp_bytes;
+};
+size_t partition_work_bytes(int nb, int nparts);
+PartWork carve_partition_work(void* base, int nb, int nparts);
+// c = ln(1/tau)
+hipError_t launch_partition(const DevBasis& bs, double c, int nparts, const PartWork& w, int32_t* pairs,
+                            hipStream_t s);
+// Kx[s nparts + s'][k][a][b] = exp(-t_k^2 (b_s xi_a - b_s' xi_b)^2), xi the unit Chebyshev nodes
+hipError_t launch_cross_tables(const double* t, int nq, int n, int kind, const PartBoxes& bx, double* Kx,
+                               hipStream_t s);
+// J over adaptive boxes: M holds the partitions' moment blocks [3][n][count_s]
+// one after another (each on its own box), pairs the concatenated lists.
+// Kx from launch_cross_tables; w the node weights.
+hipError_t launch_apply_j_parts(int prec, const double* M, int nb, const int32_t* pairs, const int64_t* offs,
+                                int nparts, int n, int nq, const double* w, const double* Kx, const double* D,
+                                double* J, const JWork& wk, double* rho_all, double* T2_all, double* wrep,
+                                hipStream_t s);
+
+// Exchange matrix, factorized form (k_exchange.hip).  exchange_work_plan
+// lays out one workspace: the X and Phi grid tensors of all norb nb
+// (orbital, function) slots, the slab products of a chunk of tensors (at
+// most 4 GiB), the partial sums of the final product and, for a screened
+// pair list, the inverse map of the list.
+struct ExchangeWork {
+  int64_t ntensor, tchunk, slice;
+  int nsplit;
+  size_t off_X, off_Phi, off_T1, off_part, off_inv, bytes;
+};
+ExchangeWork exchange_work_plan(int n, int nq, int nb, int norb, bool listed, int64_t npair_full);
+hipError_t launch_exchange(int prec, const double* M, int nb, int64_t npair, const int32_t* pairs, int n, int nq,
+                           const NodeTables& tb, const double* Q, int norb, void* work, const ExchangeWork& p,
+                           double* Kx, hipStream_t s);
 // Achievable-peak probes (k_probe.hip): what 0 = FP16 MFMA, 1 = FP64 MFMA,
 // 2 = HBM copy.  probe_work is the flops (0, 1) or bytes (2) of one launch.
 hipError_t launch_probe(int what, int cus, float* out, const void* src, void* dst, int64_t n16, int iters,

@@ -30,7 +30,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
            "tai_quadrature", "tai_degrees", "tai_compress", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
            "tai_apply_J_pairs", "tai_apply_J_compressed", "tai_coulomb_mo", "tai_exchange", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
-           "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
+           "tai_partition_pairs", "tai_apply_J_partitioned", "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched", "compress"]
 
 
@@ -110,6 +110,11 @@ def load_library(path=LIB_PATH):
     lib.tai_assemble_B.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, ctypes.c_int64, vp]
     lib.tai_assemble_B_batched.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(tai_mol), vp]
     lib.tai_apply_J.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, vp, vp]
+    lib.tai_partition_pairs.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.c_double, ctypes.c_int32, vp,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), vp]
+    lib.tai_apply_J_partitioned.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                            ctypes.POINTER(tai_params), vp, vp, vp]
     lib.tai_peak_probe.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
     lib.tai_profile_enable.argtypes = [vp, ctypes.c_int]
     lib.tai_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -298,6 +303,23 @@ class Context:
         self.check(self.lib.tai_apply_J(self.h, _ptr(M), int(nb), ctypes.byref(p), _ptr(D), _ptr(J),
                                         _stream(stream)), "tai_apply_J")
 
+    def partition_pairs(self, basis_arrays, tau, nparts, pairs, stream=None):
+        """Adaptive boxes: the partitions' pair lists into `pairs` (int32 device
+        tensor of npair entries); returns (counts, boxes) as lists."""
+        cnt = (ctypes.c_int32 * int(nparts))()
+        box = (ctypes.c_double * int(nparts))()
+        self.check(self.lib.tai_partition_pairs(self.h, ctypes.byref(basis_arrays.struct), float(tau), int(nparts),
+                                                _ptr(pairs), cnt, box, _stream(stream)), "tai_partition_pairs")
+        return list(cnt), list(box)
+
+    def apply_J_partitioned(self, M, nb, pairs, counts, boxes, params, D, J, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        k = len(counts)
+        cnt = (ctypes.c_int32 * k)(*[int(x) for x in counts])
+        box = (ctypes.c_double * k)(*[float(x) for x in boxes])
+        self.check(self.lib.tai_apply_J_partitioned(self.h, _ptr(M), int(nb), _ptr(pairs), cnt, box, k, ctypes.byref(p),
+                                                    _ptr(D), _ptr(J), _stream(stream)), "tai_apply_J_partitioned")
+
 
 # ---- convenience wrappers allocating torch outputs ---------------------------
 _default = {}
@@ -369,6 +391,44 @@ def apply_J_compressed(U, Kc, D, params, R, prec=FP64, pairs=None, device=0):
     J = torch.empty((nb, nb), dtype=torch.float64, device=U.device)
     npk = 0 if pairs is None else int(pairs.shape[0])
     context(device).apply_J_compressed(U, nb, int(R), Kc, make_params(params, prec), D, J, pairs, npk)
+    return J
+
+
+def partition_pairs(basis, tau, nparts, device=0):
+    """(pairs int32 [npair] on the device, counts, boxes) of the adaptive
+    boxes of a basis."""
+    import torch
+    ba = BasisArrays(basis)
+    nb = ba.alpha.shape[0]
+    pairs = torch.empty(nb * (nb + 1) // 2, dtype=torch.int32, device=torch.device("cuda", device))
+    counts, boxes = context(device).partition_pairs(ba, tau, nparts, pairs)
+    return pairs, counts, boxes
+
+
+def moments_partitioned(basis, params, pairs, counts, boxes, device=0):
+    """The partitions' moment blocks, block s on box boxes[s], concatenated."""
+    import dataclasses
+    import torch
+    ba = BasisArrays(basis)
+    n = int(params.n)
+    total = int(sum(counts))
+    M = torch.empty(3 * n * total, dtype=torch.float64, device=torch.device("cuda", device))
+    off = 0
+    ctx = context(device)
+    for c, bx in zip(counts, boxes):
+        if c > 0:
+            Ps = dataclasses.replace(params, L=float(bx))
+            ctx.moments_pairs(ba, Ps, pairs[off:], int(c), M[3 * n * off:3 * n * (off + c)])
+        off += c
+    return M
+
+
+def apply_J_partitioned(M, D, pairs, counts, boxes, params, prec=FP64, device=0):
+    """J (nb x nb FP64) over adaptive boxes."""
+    import torch
+    nb = int(D.shape[0])
+    J = torch.empty((nb, nb), dtype=torch.float64, device=M.device)
+    context(device).apply_J_partitioned(M, nb, pairs, counts, boxes, make_params(params, prec), D, J)
     return J
 
 

@@ -207,7 +207,9 @@ def test_apply_j_argument_checks(hctx):
     p = _params()
     assert L.tai_apply_J(hctx.h, d, 0, ctypes.byref(p), d, d, None) == tai.TAI_ERR_INVALID_ARG
     assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(p), None, d, None) == tai.TAI_ERR_INVALID_ARG
-    assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(_params(prec=2)), d, d, None) == tai.TAI_ERR_UNSUPPORTED
+    assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(_params(prec=4)), d, d, None) == tai.TAI_ERR_UNSUPPORTED
+    for prec in (2, 3):    # the split-BF16 forms of J are valid
+        assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(_params(prec=prec)), d, d, None) == tai.TAI_ERR_NOT_READY
     assert L.tai_apply_J(hctx.h, d, 8, ctypes.byref(p), d, d, None) == tai.TAI_ERR_NOT_READY
 
 
@@ -314,3 +316,45 @@ def test_exchange_argument_checks(hctx):
     assert call(nb=60000, norb=1024, params=_params(n=64)) == tai.TAI_ERR_INVALID_ARG   # tensors > 64 GiB
     assert call(params=_params(prec=4)) == tai.TAI_ERR_UNSUPPORTED
     assert call() == tai.TAI_ERR_NOT_READY
+
+
+def test_partition_argument_checks(hctx):
+    lib, h = hctx.lib, hctx.h
+    b = I.small_random(3, natoms=2, shells=("s", "p"))
+    ba = tai.BasisArrays(b)
+    dummy = ctypes.c_void_p(16)
+    cnt = (ctypes.c_int32 * 16)()
+    box = (ctypes.c_double * 16)()
+    call = lambda tau=1e-12, k=3, pairs=dummy, c=cnt, bx=box: \
+        lib.tai_partition_pairs(h, ctypes.byref(ba.struct), tau, k, pairs, c, bx, None)
+    for tau in (0.0, 1.0, -1e-3, float("nan")):
+        assert call(tau=tau) == tai.TAI_ERR_INVALID_ARG
+    for k in (0, 17):
+        assert call(k=k) == tai.TAI_ERR_INVALID_ARG
+    assert call(pairs=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(c=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(bx=None) == tai.TAI_ERR_INVALID_ARG
+    assert call() == tai.TAI_ERR_NOT_READY
+
+
+def test_apply_J_partitioned_argument_checks(hctx):
+    lib, h = hctx.lib, hctx.h
+    dummy = ctypes.c_void_p(16)
+    nb = 4                        # npair = 10
+    mk = lambda vals, t: (t * len(vals))(*vals)
+    good_c = mk([4, 6], ctypes.c_int32)
+    good_b = mk([3.0, 5.0], ctypes.c_double)
+    p = _params()
+    call = lambda c=good_c, bx=good_b, k=2, params=p, M=dummy: \
+        lib.tai_apply_J_partitioned(h, M, nb, dummy, c, bx, k, ctypes.byref(params), dummy, dummy, None)
+    assert call(c=mk([4, 5], ctypes.c_int32)) == tai.TAI_ERR_INVALID_ARG       # does not add up to npair
+    assert call(c=mk([-1, 11], ctypes.c_int32)) == tai.TAI_ERR_INVALID_ARG
+    assert call(bx=mk([0.0, 5.0], ctypes.c_double)) == tai.TAI_ERR_INVALID_ARG
+    assert call(k=0) == tai.TAI_ERR_INVALID_ARG
+    assert call(M=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(params=_params(prec=4)) == tai.TAI_ERR_UNSUPPORTED
+    assert call(params=_params(rank_tol=1e-6)) == tai.TAI_ERR_UNSUPPORTED
+    assert call(params=_params(degree_tol=1e-8)) == tai.TAI_ERR_UNSUPPORTED
+    assert call() == tai.TAI_ERR_NOT_READY
+    # the boxes give the half-widths: params->L is not read
+    assert call(params=_params(L=0.0)) == tai.TAI_ERR_NOT_READY

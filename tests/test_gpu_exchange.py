@@ -72,3 +72,40 @@ def test_exchange_compressed(tai):
     Mg = tai.moments(b, P)
     got = tai.exchange(Mg, b.nb, torch.as_tensor(Q, device=Mg.device), P).cpu().numpy()
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+@pytest.fixture(scope="module")
+def multi_tile():
+    """nb = 92: two lambda batches per X tensor, two 64-row tiles of the
+    final product, a ragged tail in both."""
+    b = I.small_random(104, natoms=23, shells=("s", "p"), box=5.0, alpha_lo=0.2, alpha_hi=20.0)
+    P = I.Params(omega=0.5, nq=8, n=16, L=9.0)
+    Q = np.random.default_rng(10).standard_normal((3, b.nb)) / np.sqrt(b.nb)
+    K, w = _tables(P)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
+    return b, P, Q, T.exchange_grid(Mr, K, w, Q)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_exchange_multi_tile(tai, multi_tile, prec):
+    import torch
+    b, P, Q, ref = multi_tile
+    assert b.nb == 92
+    Mg = tai.moments(b, P)
+    got = tai.exchange(Mg, b.nb, torch.as_tensor(Q, device=Mg.device), P, prec=prec).cpu().numpy()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    assert err <= (1e-10 if prec == 0 else 1e-6), err
+
+
+def test_exchange_chunked_tensors_bit_equal(tai, multi_tile, monkeypatch):
+    """The mode products taken a few tensors at a time (TAI_EXCHANGE_CHUNK)
+    give the same bits as in one chunk, and the call is deterministic."""
+    import torch
+    b, P, Q, ref = multi_tile
+    Mg = tai.moments(b, P)
+    Qg = torch.as_tensor(Q, device=Mg.device)
+    one = tai.exchange(Mg, b.nb, Qg, P)
+    assert torch.equal(one, tai.exchange(Mg, b.nb, Qg, P))
+    monkeypatch.setenv("TAI_EXCHANGE_CHUNK", "7")
+    chunked = tai.exchange(Mg, b.nb, Qg, P)
+    assert torch.equal(one, chunked)

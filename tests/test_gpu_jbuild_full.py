@@ -9,8 +9,9 @@ the atomic-orbital basis), written once by tests/golden/make_jbuild1000.py
 test).  The GPU takes the grid route (eqs. coulapprox, ig1): the two routes
 share no step.
 
-Tolerances, relative 2-norm over the sampled entries: FP64 1e-10, FP32 1e-6
-(the targets of the two arithmetics)."""
+Tolerances, relative 2-norm over the sampled entries: FP64 1e-10, FP32 and
+split BF16X6 1e-6 (the targets of the arithmetics), BF16X3 3e-5 (16
+significant bits, reported)."""
 import json
 import os
 
@@ -37,7 +38,7 @@ def jbuild(tai):
     return b, P, D, pairs, Jref
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-6)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-6), (3, 1e-6), (2, 3e-5)])
 def test_J_full_size_against_oracle(tai, jbuild, prec, tol):
     import torch
     b, P, D, pairs, Jref = jbuild
@@ -52,5 +53,30 @@ def test_J_full_size_against_oracle(tai, jbuild, prec, tol):
     assert np.max(np.abs(got - Jref)) <= 2 * tol * np.max(np.abs(Jref))
     # J is written in full and symmetric
     assert bool(torch.equal(J, J.T)) and bool(torch.all(torch.isfinite(J)))
+    del Mg, J
+    torch.cuda.empty_cache()
+
+
+def test_J_full_size_adaptive_boxes_against_oracle(tai, jbuild):
+    """The same workload with adaptive boxes (tau = 1e-20, four boxes): the
+    partitions, each pair's moments on its own box and J over the box pairs,
+    against the oracle's direct route at the sampled pairs
+    (tests/golden/jbuild1000_Jparts.json), FP64 to 1e-10 and BF16X6 to 1e-6."""
+    import json
+    import torch
+    b, P, D, pairs, _ = jbuild
+    g = json.load(open(os.path.join(HERE, "golden", "jbuild1000_Jparts.json")))
+    gp = np.asarray(g["pairs"], dtype=np.int64)
+    Jref = np.asarray(g["J"], dtype=np.float64)
+    lst, counts, boxes = tai.partition_pairs(b, g["tau"], g["nparts"])
+    assert counts == g["counts"] and boxes == g["boxes"]
+    Mg = tai.moments_partitioned(b, P, lst, counts, boxes)
+    Dg = torch.as_tensor(D, device=Mg.device)
+    for prec, tol in ((0, 1e-10), (3, 1e-6)):
+        J = tai.apply_J_partitioned(Mg, Dg, lst, counts, boxes, P, prec=prec)
+        got = J[torch.as_tensor(gp[:, 0], device=J.device), torch.as_tensor(gp[:, 1], device=J.device)].cpu().numpy()
+        err = np.linalg.norm(got - Jref) / np.linalg.norm(Jref)
+        print(f"adaptive boxes, prec {prec}: relative 2-norm {err:.3e}")
+        assert err <= tol, (prec, err)
     del Mg, J
     torch.cuda.empty_cache()

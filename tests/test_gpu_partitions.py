@@ -1,0 +1,98 @@
+"""GPU parity of the adaptive integration boxes (section 6.2) through the C
+ABI: the partitions (counts, boxes and pair lists, exactly) against the
+oracle's supports and quantile clustering up to the Nb = 1000 workload, and
+the J of eq. coulapprox over the boxes against the oracle's partition-wise
+grid route, in every arithmetic of J; one partition against the plain J on
+the same box, bit for bit; empty partitions (tied supports)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import tairef as T
+from paper_2210_13069_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+J_TOL = {0: 1e-10, 1: 1e-6, 3: 1e-6, 2: 3e-5}
+
+
+def _oracle_parts(b, tau, nparts):
+    sup = T.pair_supports(b.center, b.alpha, tau)
+    return T.adaptive_partitions(sup, nparts)
+
+
+@pytest.mark.parametrize("nparts", [1, 3, 4])
+@pytest.mark.parametrize("tau", [1e-20, 1e-10])
+@pytest.mark.parametrize("case", ["sp16", "spd400", "jbuild1000"])
+def test_partitions_match_oracle(tai, case, tau, nparts):
+    if case == "sp16":
+        b, _ = I.sp16()
+    elif case == "spd400":
+        b, _ = I.spd400()
+    else:
+        b, _, _ = I.jbuild1000()
+    part, boxes = _oracle_parts(b, tau, nparts)
+    pairs, counts, gboxes = tai.partition_pairs(b, tau, nparts)
+    assert gboxes == boxes.tolist()
+    assert counts == np.bincount(part, minlength=nparts).tolist()
+    got = pairs.cpu().numpy().astype(np.int64)
+    ref = np.concatenate([np.flatnonzero(part == s) for s in range(nparts)])
+    assert np.array_equal(got, ref)
+
+
+def _small():
+    b = I.small_random(21, natoms=6, shells=("s", "p", "d"), box=4.0, alpha_lo=0.1, alpha_hi=40.0)
+    return b, I.Params(omega=0.4, nq=12, n=24, L=0.0)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 3, 2])
+@pytest.mark.parametrize("nparts", [2, 4])
+def test_apply_J_partitioned_matches_oracle(tai, prec, nparts):
+    import torch
+    b, P = _small()
+    tau = 1e-16
+    part, boxes = _oracle_parts(b, tau, nparts)
+    t, w = T.time_nodes(P.omega, P.nq)
+    D = I.random_density(np.random.default_rng(5), b)
+    pm = T.partition_moments(b.center, b.alpha, b.lxyz, part, boxes, P.n)
+    Jr = T.J_partitioned(pm, boxes, t, w, P.n, D)
+    pairs, counts, gboxes = tai.partition_pairs(b, tau, nparts)
+    Mg = tai.moments_partitioned(b, P, pairs, counts, gboxes)
+    Jg = tai.apply_J_partitioned(Mg, torch.as_tensor(D, device=Mg.device), pairs, counts, gboxes, P,
+                                 prec=prec).cpu().numpy()
+    err = np.linalg.norm(Jg - Jr, 2) / np.linalg.norm(Jr, 2)
+    assert err <= J_TOL[prec], (prec, err)
+    np.testing.assert_array_equal(Jg, Jg.T)
+
+
+def test_one_partition_is_the_plain_J(tai):
+    """One partition is the plain method on the box of the largest support:
+    the same kernels, the same bits."""
+    import torch
+    b, P = _small()
+    pairs, counts, boxes = tai.partition_pairs(b, 1e-16, 1)
+    assert counts == [b.npair]
+    Mg = tai.moments_partitioned(b, P, pairs, counts, boxes)
+    D = torch.as_tensor(I.random_density(np.random.default_rng(6), b), device=Mg.device)
+    for prec in (0, 3):
+        Jp = tai.apply_J_partitioned(Mg, D, pairs, counts, boxes, P, prec=prec)
+        Pl = dataclasses.replace(P, L=boxes[0])
+        Jl = tai.apply_J(tai.moments(b, Pl), D, Pl, prec=prec)
+        assert torch.equal(Jp, Jl), prec
+
+
+def test_empty_partitions(tai):
+    """All functions on one centre with one exponent: every support is the
+    same, so the first box holds every pair and the others are empty."""
+    import torch
+    b = I.small_random(22, natoms=1, shells=("p",), box=0.0, alpha_lo=0.7, alpha_hi=0.7)
+    P = I.Params(omega=0.5, nq=8, n=16, L=0.0)
+    pairs, counts, boxes = tai.partition_pairs(b, 1e-12, 3)
+    assert counts == [b.npair, 0, 0] and boxes[0] == boxes[1] == boxes[2]
+    Mg = tai.moments_partitioned(b, P, pairs, counts, boxes)
+    D = torch.as_tensor(I.random_density(np.random.default_rng(7), b), device=Mg.device)
+    J3 = tai.apply_J_partitioned(Mg, D, pairs, counts, boxes, P)
+    p1, c1, b1 = tai.partition_pairs(b, 1e-12, 1)
+    J1 = tai.apply_J_partitioned(tai.moments_partitioned(b, P, p1, c1, b1), D, p1, c1, b1, P)
+    assert torch.equal(J3, J1)
