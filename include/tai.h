@@ -277,6 +277,31 @@ int tai_assemble_B_batched(tai_ctx* ctx, int32_t nmol, const tai_mol* mols, void
 int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* params,
                 const double* D, double* J, void* stream);
 
+/* tai_apply_J for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same J, bit for bit, with every intermediate (node tables, pair
+   density, partial and final grid tensors, mode products, J on the pairs)
+   carved from a static device array of 256 MiB that the library holds on
+   each device it runs on until the process ends, looked up once per device
+   when a context is created.  The call makes no hipMalloc, hipFree or other
+   allocating call and does no host synchronisation; the caller passes M, D
+   and J as for tai_apply_J.
+   Limits: prec TAI_FP64 or TAI_FP32; rank_tol must be 0 (the compression
+   needs its own workspace: TAI_ERR_UNSUPPORTED); the call's scratch need,
+   the node tables plus 16 npair + 8 n^3 (nchunk + 2 + 2 nq) bytes (+ 12 n
+   npair for TAI_FP32), with nchunk = 512 / g for the g groups of the rho
+   contraction (g = ceil(n / 16) in FP64 up to n = 48, else ceil(n / 8)) and
+   at most ceil(npair / 256), must fit in 256 MiB, else TAI_ERR_INVALID_ARG
+   with the size in tai_last_error (Nb = 1000, n = 48, nq = 32 in FP64 needs
+   207 MiB).  Every call on a
+   device shares that device's array, which keeps the last call's contents;
+   nothing in it needs to start at zero (every intermediate is written
+   before it is read).  Calls that overlap in time on one device, from any
+   context or stream, race on the array: order them on one stream or
+   synchronise between them. */
+int tai_apply_J_noalloc(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* params,
+                        const double* D, double* J, void* stream);
+
 /* Coulomb matrix in the molecular-orbital basis (section 5, eq. Coul):
      Jmo[i][j] = sum over all ordered (mu,nu), (kappa,lambda) of
                  q_i(mu) q_i(nu) B(mu nu, kappa lambda) q_j(kappa) q_j(lambda)

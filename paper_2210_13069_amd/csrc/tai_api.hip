@@ -9,8 +9,18 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
+
+// Static device scratch of tai_apply_J_noalloc: the node tables and the J
+// intermediates of one call, for callers that cannot allocate.  Every device
+// the library runs on holds its own copy until the process ends.  In host
+// code `scratch` is only a stand-in symbol: its device address comes from
+// hipGetSymbolAddress, once per device (scratch_address), and only that
+// address is ever handed to a kernel or a copy.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -45,6 +55,7 @@ struct tai_ctx {
   Buf asm_host;           // pinned staging of the table
   hipEvent_t asm_host_done = nullptr;
   int cus = 0;            // compute units of the device
+  void* scratch = nullptr;  // this device's address of the static scratch
   // 16-bit kernel shapes: runtime facts per table entry, the tuned choice
   // (candidate index) per call signature, and the tuning state
   std::vector<tai::Asm16Shape> shapes16;
@@ -473,6 +484,25 @@ uint64_t pow2_at_least(int64_t v) {
 
 extern "C" {
 
+// Device address of the static scratch on `device`, looked up once per
+// device with that device current (each device holds its own copy of the
+// array at its own address).  nullptr if the lookup fails.
+static void* scratch_address(int device) {
+  static std::mutex mu;
+  static std::vector<void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= device) addr.resize(device + 1, nullptr);
+  if (!addr[device]) {
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    void* p = nullptr;
+    if (hipSetDevice(device) == hipSuccess && hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) addr[device] = p;
+    else (void)hipGetLastError();
+    if (prev >= 0) hipSetDevice(prev);
+  }
+  return addr[device];
+}
+
 int tai_create(tai_ctx** ctx, int hip_device) {
   if (!ctx) return TAI_ERR_INVALID_ARG;
   *ctx = nullptr;
@@ -490,6 +520,7 @@ int tai_create(tai_ctx** ctx, int hip_device) {
     }
     c->device = hip_device;
     if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess) c->cus = 256;
+    c->scratch = scratch_address(hip_device);
   }
   *ctx = c;
   return TAI_OK;
@@ -1274,6 +1305,39 @@ static int apply_j_impl(tai_ctx* c, const double* M, int32_t nb, const int32_t* 
     Timed tm(c, kStApplyJ, s);
     e = tai::launch_apply_j(p->prec, Mop, nb, (int)npair, pairs, n, nq, tbp, D, J, w, s);
   }
+  if (e != hipSuccess) return hip_fail(c, e, "apply_J kernels");
+  return TAI_OK;
+}
+
+int tai_apply_J_noalloc(tai_ctx* c, const double* M, int32_t nb, const tai_params* p, const double* D, double* J,
+                        void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p))) return r;
+  if (!M || !D || !J) return fail(c, TAI_ERR_INVALID_ARG, "M, D or J is NULL");
+  if (nb < 1) return fail(c, TAI_ERR_INVALID_ARG, "nb must be >= 1");
+  const int64_t npair = npair_of(nb);
+  if (npair > 2147483647LL) return fail(c, TAI_ERR_INVALID_ARG, "npair exceeds 2^31-1");
+  if (p->prec != TAI_FP64 && p->prec != TAI_FP32)
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_noalloc supports prec TAI_FP64 and TAI_FP32");
+  if (p->rank_tol > 0)
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_apply_J_noalloc: rank_tol > 0 needs the compression workspace");
+  const int nq = p->nq, n = p->n;
+  const size_t tab = align256(tai::node_tables_bytes(nq, n));
+  const size_t need = tab + tai::j_work_bytes(p->prec, nq, n, (int)npair);
+  if (need > kScratchBytes)
+    return fail(c, TAI_ERR_INVALID_ARG, "tai_apply_J_noalloc needs " + std::to_string(need) +
+                                            " bytes of scratch; the static scratch holds " +
+                                            std::to_string(kScratchBytes));
+  if ((r = need_device(c))) return r;
+  if (!c->scratch) return fail(c, TAI_ERR_HIP, "the static scratch has no device address on this device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(c->scratch);
+  NodeTables tb = tai::carve_node_tables(base, nq, n);
+  tai::JWork w = tai::carve_j_work(base + tab, p->prec, nq, n, (int)npair);
+  hipError_t e = tai::launch_nodes(p->omega, nq, n, p->L, p->nodes, p->degree_tol, tb, s);
+  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  e = tai::launch_apply_j(p->prec, M, nb, (int)npair, nullptr, n, nq, tb, D, J, w, s);
   if (e != hipSuccess) return hip_fail(c, e, "apply_J kernels");
   return TAI_OK;
 }

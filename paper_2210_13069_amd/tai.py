@@ -29,7 +29,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 # exported symbols declared in include/tai.h
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
            "tai_quadrature", "tai_degrees", "tai_compress", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
-           "tai_apply_J_pairs", "tai_apply_J_compressed", "tai_coulomb_mo", "tai_exchange", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J",
+           "tai_apply_J_pairs", "tai_apply_J_compressed", "tai_coulomb_mo", "tai_exchange", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J", "tai_apply_J_noalloc",
            "tai_partition_pairs", "tai_apply_J_partitioned", "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched", "compress"]
 
@@ -115,6 +115,7 @@ def load_library(path=LIB_PATH):
     lib.tai_apply_J_partitioned.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                             ctypes.POINTER(tai_params), vp, vp, vp]
+    lib.tai_apply_J_noalloc.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, vp, vp]
     lib.tai_peak_probe.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
     lib.tai_profile_enable.argtypes = [vp, ctypes.c_int]
     lib.tai_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -319,6 +320,13 @@ class Context:
         box = (ctypes.c_double * k)(*[float(x) for x in boxes])
         self.check(self.lib.tai_apply_J_partitioned(self.h, _ptr(M), int(nb), _ptr(pairs), cnt, box, k, ctypes.byref(p),
                                                     _ptr(D), _ptr(J), _stream(stream)), "tai_apply_J_partitioned")
+
+    def apply_J_noalloc(self, M, nb, params, D, J, stream=None):
+        """tai_apply_J with every intermediate in the library's static device
+        scratch (no allocation)."""
+        p = params if isinstance(params, tai_params) else make_params(params)
+        self.check(self.lib.tai_apply_J_noalloc(self.h, _ptr(M), int(nb), ctypes.byref(p), _ptr(D), _ptr(J),
+                                                _stream(stream)), "tai_apply_J_noalloc")
 
 
 # ---- convenience wrappers allocating torch outputs ---------------------------
