@@ -106,6 +106,12 @@ def load_j_fixture(name="jbuild1000_J.json"):
     return np.asarray(g["pairs"], dtype=np.int64), np.asarray(g["J"], dtype=np.float64)
 
 
+def stage_ms(stages, steps):
+    """HIP-event time of each library stage per step (a stage may be timed in
+    several sections per call)."""
+    return {k: round(v[0] / max(1, steps), 4) for k, v in stages.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,7 +201,7 @@ def main():
                 "launch_ms": round(asm_ms, 4)}
 
     paths = {args.prec: {"ms_per_step": round(ms_head, 3), "entries_per_s": value,
-                         "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st_head.items()}}}
+                         "stage_ms": stage_ms(st_head, K)}}
     samples = {args.prec: samp_head}
     samples_w1 = {}
     degrees = None
@@ -212,7 +218,7 @@ def main():
             log(f"path {name}: steps={steps}")
             ms, st, samp = run_steps(prec, B64 if prec == tai.FP64 else B32, steps, 1)
             paths[name] = {"ms_per_step": round(ms, 3), "entries_per_s": entries / (ms / 1e3),
-                           "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()}}
+                           "stage_ms": stage_ms(st, steps)}
             samples[name] = samp
         # per-node degrees N_k (the paper's N_i): FP64 and FP32 contract only
         # each node's leading coefficient indices
@@ -227,7 +233,7 @@ def main():
             ms, st, samp = run_steps(prec, B64 if prec == tai.FP64 else B32, steps, 1, Pd)
             a_ms = st["assemble"][0] / max(1, st["assemble"][1])
             degrees[name] = {"ms_per_step": round(ms, 3), "entries_per_s": entries / (ms / 1e3),
-                             "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()},
+                             "stage_ms": stage_ms(st, steps),
                              "assemble_tflops_algorithmic": round(deg_flops / (a_ms / 1e3) / 1e12, 2)}
             samples[name + "_degrees"] = samp
         # low-rank compression of the moments (section 6.1): every path
@@ -248,7 +254,7 @@ def main():
             ms, st, samp = run_steps(prec, B64 if prec == tai.FP64 else B32, steps, 1, Pc)
             a_ms = st["assemble"][0] / max(1, st["assemble"][1])
             compressed[name] = {"ms_per_step": round(ms, 3), "entries_per_s": entries / (ms / 1e3),
-                                "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()},
+                                "stage_ms": stage_ms(st, steps),
                                 "assemble_tflops_algorithmic": round(cmp_flops / (a_ms / 1e3) / 1e12, 2)}
             if name in paths:
                 compressed[name]["speedup_vs_uncompressed_step"] = round(paths[name]["ms_per_step"] / ms, 3)
@@ -270,7 +276,7 @@ def main():
             ms, st, samp = run_steps(prec, B64 if prec == tai.FP64 else B32, steps, 1, P1)
             a_ms = st["assemble"][0] / max(1, st["assemble"][1])
             omega1[name] = {"ms_per_step": round(ms, 3), "entries_per_s": entries / (ms / 1e3),
-                            "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()},
+                            "stage_ms": stage_ms(st, steps),
                             "assemble_tflops_algorithmic": round(flops / (a_ms / 1e3) / 1e12, 2)}
             samples_w1[name] = samp
         for name in omega1:
@@ -348,7 +354,7 @@ def main():
         ent_s = float(npk) * npk
         screened = {"tau": SCREEN_TAU, "kept_pairs": npk, "pairs": npair, "entries": ent_s,
                     "ms_per_step": round(ms_s, 3), "entries_per_s": ent_s / (ms_s / 1e3),
-                    "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in sts.items()},
+                    "stage_ms": stage_ms(sts, K),
                     "speedup_vs_unscreened_step": round(ms_head / ms_s, 3)}
         ki = rng.integers(0, npk, 240)
         kj = rng.integers(0, npk, 240)
@@ -433,7 +439,7 @@ def main():
             ctx.profile_enable(False)
             japply[name] = {"ms_per_step": round(ms_j, 3),
                             "effective_entries_per_s": float(jb.npair) ** 2 / (ms_j / 1e3),
-                            "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stj.items()}}
+                            "stage_ms": stage_ms(stj, K)}
         # against the oracle: J at 64 sampled pairs by the direct route
         # (J_p = sum_q B(p,q) Dt_q over all 500500 pairs, rows of B from
         # Theorem 3.1), written once by tests/golden/make_jbuild1000.py
@@ -482,7 +488,7 @@ def main():
         ctx.profile_enable(False)
         ref = Jj["fp64"]
         screened_j = {"tau": SCREEN_TAU, "kept_pairs": npk_j, "pairs": jb.npair, "ms_per_step": round(ms_js, 3),
-                      "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stj.items()},
+                      "stage_ms": stage_ms(stj, K),
                       "speedup_vs_unscreened": round(japply["fp64"]["ms_per_step"] / ms_js, 3),
                       "rel_2norm_vs_unscreened_gpu": float(torch.linalg.matrix_norm(Js - ref, 2) /
                                                            torch.linalg.matrix_norm(ref, 2))}
@@ -516,7 +522,7 @@ def main():
             stp = {s_: ctx.profile_read(s_) for s_ in ("nodes", "moments", "apply_J")}
             ctx.profile_enable(False)
             rec = {"ms_per_step": round(ms_pt, 3), "boxes": [round(x, 4) for x in boxes], "counts": counts,
-                   "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stp.items()},
+                   "stage_ms": stage_ms(stp, K),
                    "step_ratio_vs_fixed_box": round(ms_pt / japply[name]["ms_per_step"], 3),
                    "rel_2norm_vs_fixed_box_L24_gpu": float(torch.linalg.matrix_norm(Jpt - Jj["fp64"], 2) /
                                                            torch.linalg.matrix_norm(Jj["fp64"], 2))}
@@ -548,7 +554,7 @@ def main():
             ctx.profile_enable(False)
             japply["compressed_" + name] = {
                 "rank_tol": RANK_TOL_J, "rank": jrank, "n": jP.n, "ms_per_step": round(ms_jc, 3),
-                "stage_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stj.items()},
+                "stage_ms": stage_ms(stj, K),
                 "speedup_vs_uncompressed": round(japply[name]["ms_per_step"] / ms_jc, 3),
                 "rel_2norm_vs_uncompressed_fp64_gpu": float(torch.linalg.matrix_norm(Jc - Jj["fp64"], 2) /
                                                             torch.linalg.matrix_norm(Jj["fp64"], 2))}
@@ -643,7 +649,7 @@ def main():
                 ms_x = (time.perf_counter() - t0) * 1e3 / kx
                 kern = ctx.profile_read("apply_J")
                 ctx.profile_enable(False)
-                kms = kern[0] / max(1, kern[1])
+                kms = kern[0] / kx
                 rec[name] = {"ms_per_call": round(ms_x, 3), "kernels_ms": round(kms, 3),
                              "symmetry_rel": float((Kx - Kx.T).abs().max() / Kx.abs().max())}
                 if name == "fp64":

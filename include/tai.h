@@ -103,8 +103,15 @@ typedef struct {
    and tai_coulomb_mo contract U_d = V^T M_d and Kc_k = V^T K_k V instead,
    V the R leading left singular vectors of [M_1 | M_2 | M_3] with
    sigma_r > rank_tol * sigma_1 (tai_compress); those calls then wait on the
-   host for R.  rank_tol > 0 with degree_tol > 0 is TAI_ERR_UNSUPPORTED, and
-   so is rank_tol > 0 in tai_assemble_B_batched. */
+   host for R.  Both together: the moments are compressed as above and the
+   tables are those of the truncated factors, Kc_k = V^T Kt_k V with Kt_k the
+   node values of node k's degree-N_k polynomial (the nested tables of
+   section 3.2.2 in the compressed basis); the work is that of rank R at
+   every node.  In tai_assemble_B_batched each molecule with rank_tol > 0 is
+   compressed on the device with no host wait: its operands keep the full
+   length n with zero directions beyond its rank, which the FP64 and FP32
+   kernels skip node by node (the split 16-bit kernels run the full
+   length). */
 typedef struct {
   double  omega;
   int32_t nq;
@@ -242,7 +249,12 @@ typedef struct {
    batch description (sizes, parameters, M/B pointers) is unchanged; the
    bases themselves are uploaded on every call.  Setting the environment
    variable TAI_NO_GRAPH launches the kernels directly.  Results equal those
-   of tai_moments + tai_assemble_B per molecule. */
+   of tai_moments + tai_assemble_B per molecule (bit for bit in FP64 and
+   FP32, also for compressed molecules; the split 16-bit forms of a
+   compressed molecule run at inner length n instead of the padded rank and
+   agree to their tolerance).  Molecules with rank_tol > 0 are compressed
+   inside the launch sequence (section 6.1) without a host wait, so the
+   graph holds the compression too. */
 int tai_assemble_B_batched(tai_ctx* ctx, int32_t nmol, const tai_mol* mols, void* stream);
 
 /* Coulomb matrix through the grid tensor, B never formed (eq. coulapprox with

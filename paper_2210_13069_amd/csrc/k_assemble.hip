@@ -733,7 +733,7 @@ __global__ void __launch_bounds__(kRowsPerTile)
 pack_batch_kernel(int prec, const PrepMol* __restrict__ mols, int n, int kc) {
   const PrepMol& m = mols[blockIdx.z];
   if ((int64_t)blockIdx.x * kRowsPerTile >= m.prow) return;
-  pack_body<NMAX>(prec, m.Mu ? m.Mu : m.M, n, m.npair, m.prow, kc, static_cast<char*>(m.A), m.ex);
+  pack_body<NMAX>(prec, m.U ? m.U : (m.Mu ? m.Mu : m.M), n, m.npair, m.prow, kc, static_cast<char*>(m.A), m.ex);
 }
 
 template <int NT, int PREC>
@@ -749,9 +749,11 @@ __global__ void __launch_bounds__(256, 3)
 project_batch_kernel(const PrepMol* __restrict__ mols, int n, int nq, int kc) {
   const PrepMol& m = mols[blockIdx.z];
   if ((int64_t)blockIdx.x * kRowsPerTile >= m.prow) return;
-  // coefficient form (per-node degrees): moments against T_j, kept coefficients
-  project_mfma_body<NT, PREC>(m.Mu ? m.Mu : m.M, n, m.npair, m.prow, nq, kc, m.Mu ? m.tb.C : m.tb.K, m.tb.w, m.ex,
-                              m.ysh, static_cast<char*>(m.Y));
+  // compressed operands (rank_tol > 0), or the coefficient form (per-node
+  // degrees: moments against T_j, kept coefficients), or the node form
+  const double* src = m.U ? m.U : (m.Mu ? m.Mu : m.M);
+  const double* tab = m.U ? m.Kc : (m.Mu ? m.tb.C : m.tb.K);
+  project_mfma_body<NT, PREC>(src, n, m.npair, m.prow, nq, kc, tab, m.tb.w, m.ex, m.ysh, static_cast<char*>(m.Y));
 }
 
 size_t project_lds(int prec, int n) {

@@ -6,7 +6,8 @@
 // u_p^T Kc_k u_q with inner length R instead of n.
 //
 //  * Gram matrix G = W W^T = sum_d M_d M_d^T: chunks of pairs per work group,
-//    partial G per chunk, the partials summed in a fixed order.
+//    partial G per chunk, the partials of each entry summed in a fixed order
+//    by one work group per entry.
 //  * Eigenpairs of G (sigma_r^2 and the left singular vectors of W) by the
 //    cyclic Jacobi method in one work group: the n(n-1)/2 rotations of a
 //    sweep are applied in n-1 rounds of n/2 disjoint pairs (round-robin
@@ -33,72 +34,162 @@ namespace tai {
 namespace {
 
 constexpr int kMaxN = 64;        // largest n the library accepts
-constexpr int kGramPairs = 32;   // pairs staged per LDS tile of the Gram kernel
+constexpr int kGramPairs = 32;   // pairs per Gram chunk, at least
 constexpr int kMaxSweeps = 40;
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Partial Gram matrix of the pairs [c*chunk, min((c+1)*chunk, npair)) of the
-// three directions: part[c][a][b] = sum_d sum_q M_d(a, q) M_d(b, q).  Thread t
-// owns the 4 x 4 block (a0 + i, b0 + j) of G, a0 = 4 (t / 16), b0 = 4 (t % 16).
-__global__ void __launch_bounds__(256)
-gram_kernel(const double* __restrict__ M, int n, int64_t npair, int64_t chunk, double* __restrict__ part) {
-  __shared__ double s_m[kGramPairs][kMaxN + 2];
+// three directions on the FP64 matrix cores: part[a][b][c] =
+// sum_d sum_q M_d(a, q) M_d(b, q) (chunk index fastest, so that each entry's
+// partials are contiguous for the sum).  The pairs are staged kGramKB at a
+// time for the three directions (one batch ahead in registers), k = (d, pair)
+// running over the 3 kGramKB values, in LDS as s_m[k][a].  Every wave keeps
+// all the 16 x 16 tiles (I <= J) of G, independent MFMA chains, over its own
+// quarter of each batch's k values; the four waves' tiles are added in a
+// fixed order at the end, and each tile is written with its mirror.  The
+// v_mfma_f64_16x16x4 operands of both sides come from s_m (lane l: row
+// 16 I + l % 16, k0 + l / 16).
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kGramKB = 32;               // pairs per staged batch and direction
+constexpr int kGramK = 3 * kGramKB;       // k values per batch
+constexpr int kGramKW = kGramK / 4;       // k values per wave and batch
+constexpr int kGramPad = 65;              // LDS length of one k value's row (doubles; odd, so
+                                          // the staging stores of 32 pairs hit distinct banks)
+constexpr int kGramTiles = 10;            // tiles I <= J of G for n <= 64
+
+__device__ __forceinline__ void gram_body(const double* __restrict__ M, int n, int64_t npair, int64_t chunk,
+                                          int nchunk, double* __restrict__ part) {
+  // the staged batch, and at the end the tiles of waves 1..3
+  constexpr int kStage = kGramK * kGramPad, kSums = 3 * kGramTiles * 4 * 64;
+  __shared__ double s_m[kStage > kSums ? kStage : kSums];
   const int64_t q0 = (int64_t)blockIdx.x * chunk;
   const int64_t q1 = q0 + chunk < npair ? q0 + chunk : npair;
-  const int a0 = 4 * (threadIdx.x / 16), b0 = 4 * (threadIdx.x % 16);
-  double acc[4][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int T = (n + 15) / 16, ntile = T * (T + 1) / 2;
+  int ti[kGramTiles], tj[kGramTiles];
+  v4d acc[kGramTiles];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int u = 0; u < kGramTiles; ++u) {
+    acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    int t = u, I = 0;
+    while (I < T && t >= T - I) {   // row I holds the tiles (I, I .. T-1)
+      t -= T - I;
+      ++I;
+    }
+    ti[u] = I;
+    tj[u] = I + t;
+  }
+  // rows n .. 16 T - 1 of every k stay zero
+  for (int e = threadIdx.x; e < kStage; e += 256) s_m[e] = 0.0;
+  // staging: thread t reads pair qb + t % 32 of rows t / 32 + 8 i of each
+  // direction (256-byte runs of a moment row), one batch ahead in registers
+  constexpr int kRowStep = 256 / kGramKB, kRowsPer = (kMaxN + kRowStep - 1) / kRowStep;
+  const int j = threadIdx.x % kGramKB, a0 = threadIdx.x / kGramKB;
+  double pre[3][kRowsPer];
+  auto fetch = [&](int64_t qb) {
+    const bool inb = qb + j < q1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int d = 0; d < 3; ++d) {
-    const double* Md = M + (int64_t)d * n * npair;
-    for (int64_t qb = q0; qb < q1; qb += kGramPairs) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < kMaxN * kGramPairs; e += 256) {
-        const int a = e / kGramPairs, j = e % kGramPairs;
-        const int64_t q = qb + j;
-        s_m[j][a] = (a < n && q < q1) ? Md[(int64_t)a * npair + q] : 0.0;
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int i = 0; i < kRowsPer; ++i) {
+        const int a = a0 + kRowStep * i;
+        pre[d][i] = (inb && a < n) ? M[((int64_t)d * n + a) * npair + qb + j] : 0.0;
       }
-      __syncthreads();
-      for (int j = 0; j < kGramPairs; ++j) {
-        double x[4], y[4];
+  };
+  fetch(q0);
+  const double* base = s_m + (wave * kGramKW + (lane >> 4)) * kGramPad + (lane & 15);
+  for (int64_t qb = q0; qb < q1; qb += kGramKB) {
+    __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          x[i] = s_m[j][a0 + i];
-          y[i] = s_m[j][b0 + i];
-        }
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < kRowsPer; ++i) {
+        const int a = a0 + kRowStep * i;
+        if (a < n) s_m[(d * kGramKB + j) * kGramPad + a] = pre[d][i];
+      }
+    __syncthreads();
+    if (qb + kGramKB < q1) fetch(qb + kGramKB);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) acc[i][k] += x[i] * y[k];
+    for (int k0 = 0; k0 < kGramKW; k0 += 4) {
+#pragma unroll
+      for (int u = 0; u < kGramTiles; ++u)
+        if (u < ntile)
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(base[k0 * kGramPad + 16 * ti[u]],
+                                                        base[k0 * kGramPad + 16 * tj[u]], acc[u], 0, 0, 0);
+    }
+  }
+  // the four waves' tiles, added in wave order by wave 0 through LDS
+  __syncthreads();
+  double* s_acc = s_m;   // [wave 1..3][tile][4][64]
+  if (wave > 0) {
+#pragma unroll
+    for (int u = 0; u < kGramTiles; ++u)
+      if (u < ntile)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s_acc[(((wave - 1) * kGramTiles + u) * 4 + r) * 64 + lane] = acc[u][r];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int u = 0; u < kGramTiles; ++u) {
+    if (u >= ntile) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = acc[u][r];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) v += s_acc[(((w - 1) * kGramTiles + u) * 4 + r) * 64 + lane];
+      const int a = 16 * ti[u] + (lane >> 4) + 4 * r, b = 16 * tj[u] + (lane & 15);
+      if (a < n && b < n) {
+        part[((int64_t)a * n + b) * nchunk + blockIdx.x] = v;
+        if (ti[u] != tj[u]) part[((int64_t)b * n + a) * nchunk + blockIdx.x] = v;
       }
     }
   }
-  double* out = part + (int64_t)blockIdx.x * n * n;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (a0 + i < n && b0 + k < n) out[(a0 + i) * n + b0 + k] = acc[i][k];
 }
 
-// G[e] = sum over the chunks of part[c][e]: 64 entries per work group, four
-// groups of threads each summing every fourth chunk in order, the four group
-// sums then added in a fixed order.
 __global__ void __launch_bounds__(256)
-gram_sum_kernel(const double* __restrict__ part, int nchunk, int nn, double* __restrict__ G) {
-  __shared__ double s_sum[4][64];
-  const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int e = blockIdx.x * 64 + l;
+gram_kernel(const double* __restrict__ M, int n, int64_t npair, int64_t chunk, double* __restrict__ part) {
+  gram_body(M, n, npair, chunk, (int)gridDim.x, part);
+}
+
+// batched: molecule blockIdx.y, the moments (pass 0) or Y (pass 1)
+__global__ void __launch_bounds__(256)
+gram_batch_kernel(const CmpMol* __restrict__ tab, int n, int pass) {
+  const CmpMol& m = tab[blockIdx.y];
+  if ((int)blockIdx.x >= m.nchunk) return;
+  gram_body(pass == 0 ? m.M : m.Y, n, m.npair, m.chunk, m.nchunk, m.part);
+}
+
+// G[e] = sum over the chunks of part[e][c], one work group per entry: thread
+// t sums the chunks t, t + 256, ... in order, then a fixed-order tree over
+// the 256 thread sums.
+constexpr int kGramSumThreads = 256;
+__device__ __forceinline__ void gram_sum_body(const double* __restrict__ part, int nchunk, double* __restrict__ G) {
+  __shared__ double s_sum[kGramSumThreads];
+  const int e = blockIdx.x, t = threadIdx.x;
+  const double* pe = part + (int64_t)e * nchunk;
   double s = 0.0;
-  if (e < nn)
-    for (int c = g; c < nchunk; c += 4) s += part[(int64_t)c * nn + e];
-  s_sum[g][l] = s;
+  for (int c = t; c < nchunk; c += kGramSumThreads) s += pe[c];
+  s_sum[t] = s;
   __syncthreads();
-  if (g == 0 && e < nn) G[e] = ((s_sum[0][l] + s_sum[1][l]) + s_sum[2][l]) + s_sum[3][l];
+  for (int w = kGramSumThreads / 2; w > 0; w >>= 1) {
+    if (t < w) s_sum[t] += s_sum[t + w];
+    __syncthreads();
+  }
+  if (t == 0) G[e] = s_sum[0];
+}
+
+__global__ void __launch_bounds__(kGramSumThreads)
+gram_sum_kernel(const double* __restrict__ part, int nchunk, double* __restrict__ G) {
+  gram_sum_body(part, nchunk, G);
+}
+
+__global__ void __launch_bounds__(kGramSumThreads)
+gram_sum_batch_kernel(const CmpMol* __restrict__ tab) {
+  const CmpMol& m = tab[blockIdx.y];
+  gram_sum_body(m.part, m.nchunk, m.G);
 }
 
 // Cyclic Jacobi on the symmetric n x n matrix G (n <= 64, padded to an even
@@ -110,14 +201,12 @@ constexpr int kJacobiThreads = 1024;
 // Off-diagonal entries at most rel * sqrt(|a_pp a_qq|), or at most
 // floor_rel * trace(G), are left alone: below the floor an entry is rounding
 // noise of the Gram matrix itself, and rotating on it would never settle.
-__global__ void __launch_bounds__(kJacobiThreads)
-jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, double floor_rel,
-              double* __restrict__ sigma, double* __restrict__ V, int32_t* __restrict__ rank) {
+__device__ __forceinline__ void jacobi_body(const double* __restrict__ G, int n, double tol, double rel, double floor_rel,
+                                   double* __restrict__ sigma, double* __restrict__ V, int32_t* __restrict__ rank) {
   constexpr int S = kMaxN + 1;
   __shared__ double A[kMaxN * S];
   __shared__ double Q[kMaxN * S];
-  __shared__ double rc[kMaxN / 2], rs[kMaxN / 2];
-  __shared__ int rp[kMaxN / 2], rq[kMaxN / 2];
+  __shared__ double2 rcs[kMaxN / 2];  // (c, s) of the rotations of a round
   __shared__ int order[kMaxN];
   __shared__ int rotated;
   __shared__ double floor_abs;
@@ -132,39 +221,63 @@ jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, doubl
     A[i * S + j] = (i < n && j < n) ? G[i * n + j] : 0.0;
     Q[i * S + j] = i == j ? 1.0 : 0.0;
   }
+  // This thread's share of a round, the same in every round: at most
+  // kAItems 2 x 2 blocks (ai, aj) of A (half^2 of them) and at most kQItems
+  // (row, rotation) pairs of the eigenvector update (m half of them).
+  constexpr int kAItems = ((kMaxN / 2) * (kMaxN / 2) + kJacobiThreads - 1) / kJacobiThreads;
+  constexpr int kQItems = (kMaxN * (kMaxN / 2) + kJacobiThreads - 1) / kJacobiThreads;
+  const int tid = threadIdx.x;
+  int ai[kAItems], aj[kAItems];
+#pragma unroll
+  for (int k = 0; k < kAItems; ++k) {
+    const int f = tid + k * kJacobiThreads;
+    ai[k] = f < half * half ? f / half : -1;
+    aj[k] = f < half * half ? f % half : 0;
+  }
+  int qr[kQItems], qj[kQItems];
+#pragma unroll
+  for (int k = 0; k < kQItems; ++k) {
+    const int f = tid + k * kJacobiThreads;
+    qr[k] = f < m * half ? f / half : -1;
+    qj[k] = f < m * half ? f % half : 0;
+  }
   __syncthreads();
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < m - 1; ++round) {
-      // round-robin pairing: slot 0 fixed, the other m-1 slots rotate
+      // round-robin pairing: slot 0 fixed, the other m-1 slots rotate; the
+      // pair (p_i, q_i), p_i < q_i, of rotation i is recomputed wherever used
+      auto slot = [&](int k) {
+        int x = k - 1 + round;
+        x = x >= m - 1 ? x - (m - 1) : x;
+        return k == 0 ? 0 : 1 + x;
+      };
+      auto pair_of = [&](int i, int& p, int& q) {
+        const int a = slot(i), b = slot(m - 1 - i);
+        p = a < b ? a : b;
+        q = a < b ? b : a;
+      };
       if (threadIdx.x < half) {
         const int i = threadIdx.x;
-        auto slot = [&](int k) { return k == 0 ? 0 : 1 + (k - 1 + round) % (m - 1); };
-        int p = slot(i), q = slot(m - 1 - i);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
+        int p, q;
+        pair_of(i, p, q);
         const double app = A[p * S + p], aqq = A[q * S + q], apq = A[p * S + q];
         double c = 1.0, s = 0.0;
         // rotate unless apq is negligible against the diagonal pair (a
         // relative test, so tiny eigenvalues of a semi-definite G are still
         // resolved) or below the underflow range
         if (fabs(apq) > rel * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
-          // the rotation that zeroes A'(p, q): tan = t, the root of
-          // t^2 + 2 theta t - 1 = 0 of smaller size, theta = (aqq - app) / (2 apq)
-          const double theta = (aqq - app) / (2.0 * apq);
-          const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
+          // the rotation that zeroes A'(p, q): tan = t, the root of smaller
+          // size of t^2 + 2 theta t - 1 = 0, theta = x / y with
+          // x = aqq - app, y = 2 apq, i.e. t = sgn(x) y / (|x| + sqrt(x^2 + y^2))
+          const double x = aqq - app, y = 2.0 * apq;
+          const double t = (x >= 0 ? y : -y) / (fabs(x) + sqrt(x * x + y * y));
+          c = rsqrt(t * t + 1.0);
           s = t * c;
           rotated = 1;
         }
-        rp[i] = p;
-        rq[i] = q;
-        rc[i] = c;
-        rs[i] = s;
+        rcs[i] = double2{c, s};
       }
       __syncthreads();
       // A <- J^T A J and V <- V J for the block-diagonal J of this round's
@@ -172,28 +285,36 @@ jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, doubl
       // only on the same block, so every 2 x 2 block is updated in place by
       // one thread (columns by rotation j, then rows by rotation i); the
       // rotated entries (p, q), (q, p) are zero by construction of the angle
-      const int nblkA = half * half;
-      for (int e = threadIdx.x; e < nblkA + m * half; e += kJacobiThreads) {
-        if (e < nblkA) {
-          const int i = e / half, j = e % half;
-          const int p = rp[i], q = rq[i], u = rp[j], v = rq[j];
-          const double ci = rc[i], si = rs[i], cj = rc[j], sj = rs[j];
-          const double a_pu = A[p * S + u], a_pv = A[p * S + v], a_qu = A[q * S + u], a_qv = A[q * S + v];
-          const double b_pu = cj * a_pu - sj * a_pv, b_pv = sj * a_pu + cj * a_pv;
-          const double b_qu = cj * a_qu - sj * a_qv, b_qv = sj * a_qu + cj * a_qv;
-          const bool hit = i == j && si != 0.0;
-          A[p * S + u] = ci * b_pu - si * b_qu;
-          A[q * S + u] = hit ? 0.0 : si * b_pu + ci * b_qu;
-          A[p * S + v] = hit ? 0.0 : ci * b_pv - si * b_qv;
-          A[q * S + v] = si * b_pv + ci * b_qv;
-        } else {
-          const int f = e - nblkA, r = f / half, j = f % half;
-          const int u = rp[j], v = rq[j];
-          const double c = rc[j], sn = rs[j];
-          const double x = Q[r * S + u], y = Q[r * S + v];
-          Q[r * S + u] = c * x - sn * y;
-          Q[r * S + v] = sn * x + c * y;
-        }
+      // (each thread's items are fixed for the kernel: see below)
+#pragma unroll
+      for (int k = 0; k < kAItems; ++k) {
+        if (ai[k] < 0) continue;
+        const int i = ai[k], j = aj[k];
+        int p, q, u, v;
+        pair_of(i, p, q);
+        pair_of(j, u, v);
+        const double2 ri = rcs[i], rj = rcs[j];
+        const double ci = ri.x, si = ri.y, cj = rj.x, sj = rj.y;
+        const double a_pu = A[p * S + u], a_pv = A[p * S + v], a_qu = A[q * S + u], a_qv = A[q * S + v];
+        const double b_pu = cj * a_pu - sj * a_pv, b_pv = sj * a_pu + cj * a_pv;
+        const double b_qu = cj * a_qu - sj * a_qv, b_qv = sj * a_qu + cj * a_qv;
+        const bool hit = i == j && si != 0.0;
+        A[p * S + u] = ci * b_pu - si * b_qu;
+        A[q * S + u] = hit ? 0.0 : si * b_pu + ci * b_qu;
+        A[p * S + v] = hit ? 0.0 : ci * b_pv - si * b_qv;
+        A[q * S + v] = si * b_pv + ci * b_qv;
+      }
+#pragma unroll
+      for (int k = 0; k < kQItems; ++k) {
+        if (qr[k] < 0) continue;
+        const int r = qr[k];
+        int u, v;
+        pair_of(qj[k], u, v);
+        const double2 rj = rcs[qj[k]];
+        const double c = rj.x, sn = rj.y;
+        const double x = Q[r * S + u], y = Q[r * S + v];
+        Q[r * S + u] = c * x - sn * y;
+        Q[r * S + v] = sn * x + c * y;
       }
       __syncthreads();
     }
@@ -226,15 +347,28 @@ jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, doubl
   if (threadIdx.x < n) sigma[threadIdx.x] = sqrt(fmax(A[order[threadIdx.x] * S + order[threadIdx.x]], 0.0));
 }
 
+__global__ void __launch_bounds__(kJacobiThreads)
+jacobi_kernel(const double* __restrict__ G, int n, double tol, double rel, double floor_rel,
+              double* __restrict__ sigma, double* __restrict__ V, int32_t* __restrict__ rank) {
+  jacobi_body(G, n, tol, rel, floor_rel, sigma, V, rank);
+}
+
+// batched: molecule blockIdx.x; pass 0 writes V1, pass 1 V2 (and both the
+// singular values and the rank, the second pass's final)
+__global__ void __launch_bounds__(kJacobiThreads)
+jacobi_batch_kernel(const CmpMol* __restrict__ tab, int n, int pass, double rel, double floor_rel) {
+  const CmpMol& m = tab[blockIdx.x];
+  jacobi_body(m.G, n, m.tol, rel, floor_rel, m.sigma, pass == 0 ? m.V1 : m.V2, m.rank);
+}
+
 // U[d][r][q] = sum_a V[a][r] M[d][a][q] for r < R (V is n x n, its first R
 // columns used), with the columns from `keep` on taken as zero: rows
 // keep..R-1 of U are the zero padding of the kept rank up to the inner
 // length the contractions run at.  One thread per pair with the moment
 // column in registers.
 template <int NMAX>
-__global__ void __launch_bounds__(256)
-compress_moments_kernel(const double* __restrict__ M, int n, int64_t npair, const double* __restrict__ V, int R,
-                        int keep, double* __restrict__ U) {
+__device__ __forceinline__ void compress_moments_body(const double* __restrict__ M, int n, int64_t npair,
+                                             const double* __restrict__ V, int R, int keep, double* __restrict__ U) {
   __shared__ __align__(16) double s_v[NMAX * NMAX];
   for (int e = threadIdx.x; e < n * R; e += 256) {
     const int a = e / R, r = e % R;
@@ -271,22 +405,50 @@ compress_moments_kernel(const double* __restrict__ M, int n, int64_t npair, cons
   }
 }
 
-// V = V1 V2 (n x n), one work group.
+template <int NMAX>
 __global__ void __launch_bounds__(256)
+compress_moments_kernel(const double* __restrict__ M, int n, int64_t npair, const double* __restrict__ V, int R,
+                        int keep, double* __restrict__ U) {
+  compress_moments_body<NMAX>(M, n, npair, V, R, keep, U);
+}
+
+// batched, molecule blockIdx.z: pass 0 Y = V1^T M at full length, pass 1
+// U = V^T M at length n with the columns of V from the molecule's rank on
+// taken as zero
+template <int NMAX>
+__global__ void __launch_bounds__(256)
+compress_moments_batch_kernel(const CmpMol* __restrict__ tab, int n, int pass) {
+  const CmpMol& m = tab[blockIdx.z];
+  if ((int64_t)blockIdx.x * 256 >= m.npair) return;
+  if (pass == 0) compress_moments_body<NMAX>(m.M, n, m.npair, m.V1, n, n, m.Y);
+  else compress_moments_body<NMAX>(m.M, n, m.npair, m.V, n, *m.rank, m.U);
+}
+
+// V = V1 V2 (n x n): one work group per row a, one thread per column r.
+__device__ __forceinline__ void basis_product_body(const double* __restrict__ V1, const double* __restrict__ V2, int n,
+                                          double* __restrict__ V) {
+  const int a = blockIdx.x, r = threadIdx.x;
+  if (r >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < n; ++b) s += V1[a * n + b] * V2[b * n + r];
+  V[a * n + r] = s;
+}
+
+__global__ void __launch_bounds__(64)
 basis_product_kernel(const double* __restrict__ V1, const double* __restrict__ V2, int n, double* __restrict__ V) {
-  for (int e = threadIdx.x; e < n * n; e += 256) {
-    const int a = e / n, r = e % n;
-    double s = 0.0;
-    for (int b = 0; b < n; ++b) s += V1[a * n + b] * V2[b * n + r];
-    V[e] = s;
-  }
+  basis_product_body(V1, V2, n, V);
+}
+
+__global__ void __launch_bounds__(64)
+basis_product_batch_kernel(const CmpMol* __restrict__ tab, int n) {
+  const CmpMol& m = tab[blockIdx.y];
+  basis_product_body(m.V1, m.V2, n, m.V);
 }
 
 // Kc[k] = V_R^T K[k] V_R (R x R), one work group per node; the columns of V
 // from `keep` on are taken as zero (zero rows and columns of Kc).
-__global__ void __launch_bounds__(256)
-compress_tables_kernel(const double* __restrict__ K, int n, const double* __restrict__ V, int R, int keep,
-                       double* __restrict__ Kc) {
+__device__ __forceinline__ void compress_tables_body(const double* __restrict__ K, int n, const double* __restrict__ V, int R,
+                                            int keep, double* __restrict__ Kc) {
   constexpr int S = kMaxN + 1;
   __shared__ double s_k[kMaxN * S];
   __shared__ double s_v[kMaxN * S];
@@ -316,11 +478,31 @@ compress_tables_kernel(const double* __restrict__ K, int n, const double* __rest
   }
 }
 
+__global__ void __launch_bounds__(256)
+compress_tables_kernel(const double* __restrict__ K, int n, const double* __restrict__ V, int R, int keep,
+                       double* __restrict__ Kc) {
+  compress_tables_body(K, n, V, R, keep, Kc);
+}
+
+// batched, molecule blockIdx.y: tables at length n with the columns of V from
+// the rank on taken as zero, and the molecule's per-node inner length (its
+// rank) for the assembly kernels that skip the zero inner steps
+__global__ void __launch_bounds__(256)
+compress_tables_batch_kernel(const CmpMol* __restrict__ tab, int n, int nq) {
+  const CmpMol& m = tab[blockIdx.y];
+  const int keep = *m.rank;
+  compress_tables_body(m.K, n, m.V, n, keep, m.Kc);
+  if (blockIdx.x == 0 && m.nk)
+    for (int k = threadIdx.x; k < nq; k += 256) m.nk[k] = keep;
+}
+
 }  // namespace
 
+// Gram chunks: at most 512 (two work groups per compute unit), so that the
+// transposed partials stay small.
 int compress_nchunk(int64_t npair) {
   const int64_t c = (npair + kGramPairs - 1) / kGramPairs;
-  return (int)(c < 2048 ? c : 2048);
+  return (int)(c < 512 ? c : 512);
 }
 
 size_t compress_work_bytes(int n, int nq, int64_t npair) {
@@ -359,7 +541,7 @@ void launch_gram_eig(const double* M, int n, int64_t npair, double tol, double r
   const int64_t chunk = (npair + w.nchunk - 1) / w.nchunk;
   const int nchunk = (int)((npair + chunk - 1) / chunk);
   hipLaunchKernelGGL(gram_kernel, dim3(nchunk), dim3(256), 0, s, M, n, npair, chunk, w.part);
-  hipLaunchKernelGGL(gram_sum_kernel, dim3(nblk(n * n, 64)), dim3(256), 0, s, w.part, nchunk, n * n, w.G);
+  hipLaunchKernelGGL(gram_sum_kernel, dim3(n * n), dim3(kGramSumThreads), 0, s, w.part, nchunk, w.G);
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, s, w.G, n, tol, rel, floor_rel, w.sigma, V,
                      w.rank);
 }
@@ -371,10 +553,69 @@ hipError_t launch_compress_basis(const double* M, int n, int64_t npair, double t
   // entries below 1e-14 of the trace are the Gram matrix's own rounding
   launch_gram_eig(M, n, npair, tol, 1e-10, 1e-14, w, w.V1, s);
   launch_moments_in(M, n, npair, w.V1, n, n, Y, s);   // Y = V1^T W
-  // V2, sigma, rank from Y Y^T: a relative test only (its entries are
-  // rounded relative to sigma_r sigma_s)
-  launch_gram_eig(Y, n, npair, tol, 1e-13, 0.0, w, w.V2, s);
-  hipLaunchKernelGGL(basis_product_kernel, dim3(1), dim3(256), 0, s, w.V1, w.V2, n, w.V);
+  // V2, sigma, rank from Y Y^T: a relative test (its entries are rounded
+  // relative to sigma_r sigma_s), and a floor of 1e-28 of the trace, i.e.
+  // (1e-14 sigma_1)^2: rotating entries below it moves no singular value
+  // above 1e-14 sigma_1 and only lengthens the sweeps over the noise block
+  launch_gram_eig(Y, n, npair, tol, 1e-13, 1e-28, w, w.V2, s);
+  hipLaunchKernelGGL(basis_product_kernel, dim3(n), dim3(64), 0, s, w.V1, w.V2, n, w.V);
+  return hipGetLastError();
+}
+
+size_t cmp_mol_bytes(int n, int nq, int64_t npair) {
+  const size_t nn = (size_t)n * n;
+  return align256(8 * nn * compress_nchunk(npair)) + align256(8 * nn) * 4 + align256(8 * (size_t)n) +
+         align256(sizeof(int32_t)) + align256(8 * 3 * (size_t)n * npair) * 2 + align256(8 * (size_t)nq * nn);
+}
+
+CmpMol carve_cmp_mol(void* base, int n, int nq, int64_t npair, const double* M, double tol, const double* K,
+                     int32_t* nk) {
+  const size_t nn = (size_t)n * n;
+  CmpMol m;
+  m.M = M;
+  m.npair = npair;
+  const int64_t c0 = compress_nchunk(npair);
+  m.chunk = (npair + c0 - 1) / c0;
+  m.nchunk = (int32_t)((npair + m.chunk - 1) / m.chunk);
+  m.tol = tol;
+  char* p = static_cast<char*>(base);
+  m.part = reinterpret_cast<double*>(p); p += align256(8 * nn * c0);
+  m.G = reinterpret_cast<double*>(p); p += align256(8 * nn);
+  m.V1 = reinterpret_cast<double*>(p); p += align256(8 * nn);
+  m.V2 = reinterpret_cast<double*>(p); p += align256(8 * nn);
+  m.V = reinterpret_cast<double*>(p); p += align256(8 * nn);
+  m.sigma = reinterpret_cast<double*>(p); p += align256(8 * (size_t)n);
+  m.rank = reinterpret_cast<int32_t*>(p); p += align256(sizeof(int32_t));
+  m.Y = reinterpret_cast<double*>(p); p += align256(8 * 3 * (size_t)n * npair);
+  m.U = reinterpret_cast<double*>(p); p += align256(8 * 3 * (size_t)n * npair);
+  m.K = K;
+  m.Kc = reinterpret_cast<double*>(p);
+  m.nk = nk;
+  return m;
+}
+
+hipError_t launch_compress_batch(const CmpMol* tab, int ncm, int n, int nq, int64_t max_npair, int max_nchunk,
+                                 hipStream_t s) {
+  const unsigned mb = nblk(max_npair, 256);
+  auto moments_in = [&](int pass) {
+    const dim3 g(mb, 3, ncm);
+    if (n <= 16) hipLaunchKernelGGL(compress_moments_batch_kernel<16>, g, dim3(256), 0, s, tab, n, pass);
+    else if (n <= 32) hipLaunchKernelGGL(compress_moments_batch_kernel<32>, g, dim3(256), 0, s, tab, n, pass);
+    else if (n <= 48) hipLaunchKernelGGL(compress_moments_batch_kernel<48>, g, dim3(256), 0, s, tab, n, pass);
+    else hipLaunchKernelGGL(compress_moments_batch_kernel<64>, g, dim3(256), 0, s, tab, n, pass);
+  };
+  auto gram_eig = [&](int pass, double rel, double floor_rel) {
+    hipLaunchKernelGGL(gram_batch_kernel, dim3(max_nchunk, ncm), dim3(256), 0, s, tab, n, pass);
+    hipLaunchKernelGGL(gram_sum_batch_kernel, dim3(n * n, ncm), dim3(kGramSumThreads), 0, s, tab);
+    hipLaunchKernelGGL(jacobi_batch_kernel, dim3(ncm), dim3(kJacobiThreads), 0, s, tab, n, pass, rel, floor_rel);
+  };
+  // the two passes of launch_compress_basis, with its tolerances
+  gram_eig(0, 1e-10, 1e-14);
+  moments_in(0);
+  gram_eig(1, 1e-13, 1e-28);
+  hipLaunchKernelGGL(basis_product_batch_kernel, dim3(n, ncm), dim3(64), 0, s, tab, n);
+  moments_in(1);
+  hipLaunchKernelGGL(compress_tables_batch_kernel, dim3(nq, ncm), dim3(256), 0, s, tab, n, nq);
   return hipGetLastError();
 }
 

@@ -67,6 +67,7 @@ struct tai_ctx {
   Buf jwork;              // apply_J intermediates
   // batched path
   Buf b_nodes, b_basis, b_opA, b_opEx, b_opY, b_opMu, b_mols, b_counter;
+  Buf b_cmp;              // batched compression: per-molecule buffers and per-node ranks
   Buf b_host;             // pinned staging of all bases of a batch
   hipEvent_t b_host_done = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -108,8 +109,6 @@ int validate_params(tai_ctx* c, const tai_params* p, bool check_L = true) {
     return fail(c, TAI_ERR_INVALID_ARG, "degree_tol must be finite and >= 0");
   if (!finite(p->rank_tol) || p->rank_tol < 0 || !(p->rank_tol < 1))
     return fail(c, TAI_ERR_INVALID_ARG, "rank_tol must be finite and in [0, 1)");
-  if (p->rank_tol > 0 && p->degree_tol > 0)
-    return fail(c, TAI_ERR_UNSUPPORTED, "rank_tol and degree_tol cannot both be > 0");
   return TAI_OK;
 }
 
@@ -378,10 +377,23 @@ size_t opEx_bytes(int prow) { return align256(sizeof(int32_t) * 3 * (size_t)prow
 struct Items16 {
   std::vector<int4> q[tai::kAsm16Queues];
   int rr = 0;
-  void add(int mol, int64_t npair, int64_t R, int64_t C) {
-    const int64_t chunk = std::max<int64_t>(1, 512 / C);
+  // Items of (row panel, run of column blocks) in the upper triangle, with
+  // runs of up to 512 columns.  With min_items > 0 the runs are halved
+  // until there are at least that many items (or one block per item), so
+  // that a small molecule still spreads over the device; the entries and
+  // the order of every entry's node sum do not depend on the runs.
+  void add(int mol, int64_t npair, int64_t R, int64_t C, int64_t min_items = 0) {
     const int64_t ncb = (npair + C - 1) / C;
     const int64_t nrp = (npair + R - 1) / R;
+    int64_t chunk = std::max<int64_t>(1, 512 / C);
+    auto items_for = [&](int64_t ch) {
+      int64_t n = 0;
+      for (int64_t j = 0; j * ch < ncb; ++j)
+        for (int64_t rp = 0; rp < nrp; ++rp)
+          n += std::max(j * ch, rp * R / C) < std::min((j + 1) * ch, ncb) ? 1 : 0;
+      return n;
+    };
+    while (chunk > 1 && items_for(chunk) < min_items) chunk = (chunk + 1) / 2;
     for (int64_t j = 0; j * chunk < ncb; ++j) {
       std::vector<int4>& out = q[rr++ % tai::kAsm16Queues];
       for (int64_t rp = 0; rp < nrp; ++rp) {
@@ -531,11 +543,11 @@ int tai_destroy(tai_ctx* c) {
   if (c->device >= 0) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->screen, &c->part, &c->partJ, &c->mo, &c->ct, &c->ct_work,
-                   &c->asm_tab,
+    for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->cmp, &c->cmpU, &c->screen, &c->part,
+                   &c->partJ, &c->mo, &c->ct, &c->ct_work, &c->asm_tab,
                    &c->asm_counter,
                    &c->jwork,
-                   &c->b_nodes, &c->b_basis, &c->b_opA, &c->b_opEx, &c->b_opY, &c->b_opMu, &c->b_mols, &c->b_counter})
+                   &c->b_nodes, &c->b_basis, &c->b_opA, &c->b_opEx, &c->b_opY, &c->b_opMu, &c->b_mols, &c->b_counter, &c->b_cmp})
       free_buf(c, *b);
     if (c->host_basis.p) hipHostFree(c->host_basis.p);
     if (c->b_host.p) hipHostFree(c->b_host.p);
@@ -647,7 +659,7 @@ int tai_compress(tai_ctx* c, const double* M, int32_t npair, const tai_params* p
     if ((r = ensure(c, c->nodes, tai::node_tables_bytes(p->nq, p->n)))) return r;
     tb = tai::carve_node_tables(c->nodes.p, p->nq, p->n);
     Timed tm(c, kStNodes, s);
-    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, 0.0, tb, s);
+    e = tai::launch_nodes(p->omega, p->nq, p->n, p->L, p->nodes, p->degree_tol, tb, s);
     if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
   }
   if ((r = compress_impl(c, M, npair, p, tb, operands, s, &w, &R))) return r;
@@ -954,7 +966,10 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
   // with the truncated K tables: in coefficient form the moments of narrow
   // pairs cancel across indices and the slices lose about a factor of three
   // in accuracy.
-  const bool deg = p->degree_tol > 0 && !tai::is_split16(prec);
+  // With rank_tol > 0 the compressed tables already hold the truncated
+  // factors (Kc_k = V^T Kt_k V) and the operands are U, not moments: the
+  // node form throughout.
+  const bool deg = p->degree_tol > 0 && !tai::is_split16(prec) && !(p->rank_tol > 0);
   const int prow = prow_of(c, prec, n, nq, npair);
   if ((r = ensure(c, c->opA, opA_bytes(prec, n, prow)))) return r;
   if ((r = ensure(c, c->opEx, opEx_bytes(prow)))) return r;
@@ -1000,8 +1015,9 @@ static int assemble_impl(tai_ctx* c, const double* M, int32_t npair, const tai_p
   if (p16 || p32) {
     Items16 items;
     const tai::Asm16Shape sh = p16 ? shape16(c, prec, n, nq) : tai::Asm16Shape{};
-    if (p16) items.add(0, npair, sh.rows, sh.cols);
-    else items.add(0, npair, ring_rows(prec, n), tai::kAsm32Cols);
+    const int64_t slots = (int64_t)(c->cus > 0 ? c->cus : 256) * (p16 ? sh.wgs_per_cu : 1);
+    if (p16) items.add(0, npair, sh.rows, sh.cols, 2 * slots);
+    else items.add(0, npair, ring_rows(prec, n), tai::kAsm32Cols, 2 * slots);
     const size_t tab_bytes = align256(sizeof(tai::AsmMol)) + items.bytes();
     if ((r = ensure(c, c->asm_tab, tab_bytes))) return r;
     if ((r = ensure(c, c->asm_counter, 256))) return r;
@@ -1071,8 +1087,6 @@ int tai_assemble_B_batched(tai_ctx* c, int32_t nmol, const tai_mol* mols, void* 
     const tai_params& pi = mols[i].params;
     if (pi.nq != p0.nq || pi.n != p0.n || pi.nodes != p0.nodes || pi.prec != p0.prec)
       return fail(c, TAI_ERR_INVALID_ARG, "molecules of a batch must share nq, n, nodes and prec");
-    if (pi.rank_tol > 0)
-      return fail(c, TAI_ERR_UNSUPPORTED, "molecule " + std::to_string(i) + ": rank_tol > 0 is not batched");
   }
   if ((r = need_device(c))) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1094,17 +1108,25 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   const int tile = tai::assemble_tile(prec);
   // molecules with per-node degrees take their operands in coefficient form
   // in FP64 / FP32 (the split arithmetics keep the node form, see assemble_impl)
-  auto coef_form = [&](int i) { return mols[i].params.degree_tol > 0 && !tai::is_split16(prec); };
-  bool any_degree = false, any_tol = false;
+  // Molecules with rank_tol > 0 are compressed on the device (no host wait
+  // for their ranks): operands at the full length n with zero directions
+  // beyond the rank, which the FP64 / FP32 kernels skip node by node.
+  auto compressed = [&](int i) { return mols[i].params.rank_tol > 0; };
+  auto coef_form = [&](int i) {
+    return mols[i].params.degree_tol > 0 && !tai::is_split16(prec) && !compressed(i);
+  };
+  bool any_degree = false, any_tol = false, any_cmp = false;
   for (int i = 0; i < nmol; ++i) {
     any_degree = any_degree || coef_form(i);
     any_tol = any_tol || mols[i].params.degree_tol > 0;
+    any_cmp = any_cmp || compressed(i);
   }
 
   // layout of the batch workspace
-  std::vector<size_t> off_nodes(nmol), off_basis(nmol), off_A(nmol), off_Ex(nmol), off_Y(nmol), off_Mu(nmol);
+  std::vector<size_t> off_nodes(nmol), off_basis(nmol), off_A(nmol), off_Ex(nmol), off_Y(nmol), off_Mu(nmol),
+      off_cmp(nmol);
   std::vector<int> prow(nmol);
-  size_t sz_nodes = 0, sz_basis = 0, sz_A = 0, sz_Ex = 0, sz_Y = 0, sz_Mu = 0;
+  size_t sz_nodes = 0, sz_basis = 0, sz_A = 0, sz_Ex = 0, sz_Y = 0, sz_Mu = 0, sz_cmp = 0;
   int64_t nitems = 0;
   std::vector<tai::AsmMol> am(nmol);
   for (int i = 0; i < nmol; ++i) {
@@ -1117,6 +1139,8 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     off_Y[i] = sz_Y; sz_Y += opY_bytes(prec, n, nq, prow[i]);
     off_Mu[i] = sz_Mu;
     if (coef_form(i)) sz_Mu += align256(sizeof(double) * 3 * (size_t)n * np);
+    off_cmp[i] = sz_cmp;
+    if (compressed(i)) sz_cmp += align256(tai::cmp_mol_bytes(n, nq, np)) + align256(sizeof(int32_t) * nq);
   }
   if ((r = ensure(c, c->b_nodes, sz_nodes))) return r;
   if ((r = ensure(c, c->b_basis, sz_basis))) return r;
@@ -1124,6 +1148,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   if ((r = ensure(c, c->b_opEx, sz_Ex))) return r;
   if ((r = ensure(c, c->b_opY, sz_Y))) return r;
   if (sz_Mu > 0 && (r = ensure(c, c->b_opMu, sz_Mu))) return r;
+  if (sz_cmp > 0 && (r = ensure(c, c->b_cmp, sz_cmp))) return r;
   if ((r = ensure(c, c->b_counter, 256))) return r;
   for (int i = 0; i < nmol; ++i) {
     tai::AsmMol& m = am[i];
@@ -1156,14 +1181,18 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     for (int i : order)
       items16.add(i, am[i].npair, split16 ? sh16.rows : ring_rows(prec, n), split16 ? sh16.cols : tai::kAsm32Cols);
   }
-  // device tables: [AsmMol x nmol | PrepMol x nmol | items]
+  // device tables: [AsmMol x nmol | PrepMol x nmol | CmpMol x ncm | items]
   const size_t off_prep = align256(sizeof(tai::AsmMol) * nmol);
-  const size_t off_items = off_prep + align256(sizeof(tai::PrepMol) * nmol);
+  int ncm = 0;
+  for (int i = 0; i < nmol; ++i) ncm += compressed(i) ? 1 : 0;
+  const size_t off_cmptab = off_prep + align256(sizeof(tai::PrepMol) * nmol);
+  const size_t off_items = off_cmptab + align256(sizeof(tai::CmpMol) * (ncm > 0 ? ncm : 1));
   const size_t tab_bytes = off_items + (split16 || fp32p ? items16.bytes() : 0);
   if ((r = ensure(c, c->b_mols, tab_bytes))) return r;
   std::vector<tai::PrepMol> prep(nmol);
-  int64_t max_npair = 0;
-  int max_prow = 0;
+  std::vector<tai::CmpMol> cmp;
+  int64_t max_npair = 0, max_npair_cmp = 0;
+  int max_prow = 0, max_nchunk = 0;
   for (int i = 0; i < nmol; ++i) {
     tai::PrepMol& q = prep[i];
     q.omega = mols[i].params.omega;
@@ -1172,6 +1201,20 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     q.tb = tai::carve_node_tables(static_cast<char*>(c->b_nodes.p) + off_nodes[i], nq, n);
     q.Mu = coef_form(i) ? reinterpret_cast<double*>(static_cast<char*>(c->b_opMu.p) + off_Mu[i]) : nullptr;
     am[i].nk = q.Mu ? q.tb.nk : nullptr;
+    q.U = nullptr;
+    q.Kc = nullptr;
+    if (compressed(i)) {
+      char* cb = static_cast<char*>(c->b_cmp.p) + off_cmp[i];
+      int32_t* nk = reinterpret_cast<int32_t*>(cb + align256(tai::cmp_mol_bytes(n, nq, am[i].npair)));
+      tai::CmpMol cm = tai::carve_cmp_mol(cb, n, nq, am[i].npair, mols[i].M, mols[i].params.rank_tol, q.tb.K,
+                                          tai::is_split16(prec) ? nullptr : nk);
+      q.U = cm.U;
+      q.Kc = cm.Kc;
+      am[i].nk = cm.nk;
+      cmp.push_back(cm);
+      max_npair_cmp = std::max<int64_t>(max_npair_cmp, am[i].npair);
+      max_nchunk = std::max(max_nchunk, (int)cm.nchunk);
+    }
     q.basis = dev_basis_view(&mols[i].basis, static_cast<char*>(c->b_basis.p) + off_basis[i]);
     q.M = mols[i].M;
     q.npair = am[i].npair;
@@ -1191,6 +1234,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
   for (int i = 0; i < nmol; ++i) pack_basis_host(&mols[i].basis, hb + off_basis[i]);
   std::memcpy(hb + sz_basis, am.data(), sizeof(tai::AsmMol) * nmol);
   std::memcpy(hb + sz_basis + off_prep, prep.data(), sizeof(tai::PrepMol) * nmol);
+  if (ncm > 0) std::memcpy(hb + sz_basis + off_cmptab, cmp.data(), sizeof(tai::CmpMol) * ncm);
   if (split16 || fp32p) items16.write(hb + sz_basis + off_items);
   hipError_t e = hipMemcpyAsync(c->b_basis.p, hb, sz_basis, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->b_mols.p, hb + sz_basis, tab_bytes, hipMemcpyHostToDevice, s);
@@ -1203,6 +1247,10 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     const auto* prep_dev = reinterpret_cast<const tai::PrepMol*>(static_cast<char*>(c->b_mols.p) + off_prep);
     hipError_t err = tai::launch_nodes_batch(prep_dev, nmol, nq, n, mols[0].params.nodes, any_tol, st);
     if (err == hipSuccess) err = tai::launch_moments_batch(prep_dev, nmol, max_npair, n, st);
+    if (err == hipSuccess && ncm > 0) {
+      const auto* cmp_dev = reinterpret_cast<const tai::CmpMol*>(static_cast<char*>(c->b_mols.p) + off_cmptab);
+      err = tai::launch_compress_batch(cmp_dev, ncm, n, nq, max_npair_cmp, max_nchunk, st);
+    }
     if (err == hipSuccess && any_degree)
       err = tai::launch_coef_moments_batch(prep_dev, nmol, max_npair, n, mols[0].params.nodes, st);
     if (err == hipSuccess) err = tai::launch_pack_batch(prec, prep_dev, nmol, max_prow, n, st);
@@ -1218,13 +1266,15 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
       const auto* items_dev = reinterpret_cast<const int4*>(tab + Items16::seg_bytes());
       const int ni = (int)items16.count();
       const int blocks = std::min(ni, (c->cus > 0 ? c->cus : 256) * (split16 ? sh16.wgs_per_cu : 1));
-      if (fp32p) return launch_ring(prec, am[0].kc, any_degree, mols_dev, items_dev, seg_dev, counter, blocks, st);
+      if (fp32p)
+        return launch_ring(prec, am[0].kc, any_degree || any_cmp, mols_dev, items_dev, seg_dev, counter, blocks, st);
       return tai::launch_assemble16(prec, am[0].kc, tai::operand_dup_chunks(prec, n), sh16, mols_dev, items_dev,
                                     seg_dev, counter, blocks, st);
     }
     int blocks = tai::assemble_queue_blocks(prec, c->device);
     if (blocks > nitems) blocks = (int)nitems;
-    return tai::launch_assemble_queue(prec, am[0].kc, any_degree, mols_dev, nmol, nitems, counter, blocks, st);
+    return tai::launch_assemble_queue(prec, am[0].kc, any_degree || any_cmp, mols_dev, nmol, nitems, counter, blocks,
+                                      st);
   };
 
   const bool use_graph = allow_graph && s != nullptr && !std::getenv("TAI_NO_GRAPH");
@@ -1253,7 +1303,7 @@ static int batched_impl(tai_ctx* c, int32_t nmol, const tai_mol* mols, hipStream
     put(&mols[i].ldb, sizeof(int64_t));
   }
   void* bases[] = {c->b_nodes.p, c->b_basis.p, c->b_opA.p, c->b_opEx.p, c->b_opY.p, c->b_opMu.p, c->b_mols.p,
-                   c->b_counter.p};
+                   c->b_counter.p, c->b_cmp.p};
   put(bases, sizeof bases);
   put(&sh16.id, sizeof sh16.id);
   if (!c->graph || key != c->graph_key) {

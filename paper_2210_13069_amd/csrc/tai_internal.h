@@ -144,6 +144,8 @@ struct PrepMol {
   DevBasis basis;
   double* M;
   double* Mu;            // coefficient moments (per-node degrees, FP64 and FP32), else nullptr
+  const double* U;       // compressed moments [3][n][npair] (rank_tol > 0), else nullptr
+  const double* Kc;      // their tables [nq][n][n]
   int64_t npair;
   int32_t prow;
   void* A;
@@ -237,8 +239,7 @@ size_t j_work_bytes(int prec, int nq, int n, int npair);
 JWork carve_j_work(void* base, int prec, int nq, int n, int npair);
 // Low-rank compression of the moments (k_compress.hip): Gram matrix of
 // W = [M_1 | M_2 | M_3], its eigenpairs by Jacobi (V[a][r], sigma[r]
-// decreasing, *rank = #{sigma_r > tol sigma_1} rounded up to a multiple of 8,
-// capped at n), then compressed
+// decreasing, *rank = #{sigma_r > tol sigma_1}, at least 1), then compressed
 // moments U[d][r][q] = sum_a V[a][r] M[d][a][q] and tables Kc[k] = V_R^T K[k] V_R.
 struct CompressWork {
   double* part;    // [nchunk][n][n] partial Gram matrices
@@ -260,6 +261,39 @@ hipError_t launch_compress_basis(const double* M, int n, int64_t npair, double t
 // from `keep` on taken as zero (keep <= R: the kept rank, R its padding).
 hipError_t launch_compress_operands(const double* M, int n, int64_t npair, int R, int keep, int nq,
                                     const double* K, const CompressWork& w, double* U, hipStream_t s);
+// One molecule of a batched compression: every buffer is the molecule's
+// own, the rank stays on the device, and the operands are written at the
+// full length n with the basis columns from the rank on taken as zero
+// (U [3][n][npair], Kc [nq][n][n]); nk (if set) receives the rank for every
+// node, the inner length the FP64 / FP32 assembly kernels then run.
+struct CmpMol {
+  const double* M;     // [3][n][npair] moments
+  int64_t npair;
+  int64_t chunk;       // pairs per Gram chunk
+  int32_t nchunk;
+  double tol;
+  double* part;        // [n * n][nchunk]
+  double* G;           // [n][n]
+  double* V1;          // [n][n]
+  double* V2;          // [n][n]
+  double* V;           // [n][n]
+  double* sigma;       // [n]
+  int32_t* rank;       // [1]
+  double* Y;           // [3][n][npair]
+  double* U;           // [3][n][npair]
+  const double* K;     // [nq][n][n] the molecule's node tables
+  double* Kc;          // [nq][n][n]
+  int32_t* nk;         // [nq] or nullptr
+};
+// Bytes of one molecule's compression buffers (without the tables K), and
+// its Gram chunking.
+size_t cmp_mol_bytes(int n, int nq, int64_t npair);
+CmpMol carve_cmp_mol(void* base, int n, int nq, int64_t npair, const double* M, double tol, const double* K,
+                     int32_t* nk);
+// The whole compression of ncm molecules (tab on the device), no host wait.
+hipError_t launch_compress_batch(const CmpMol* tab, int ncm, int n, int nq, int64_t max_npair, int max_nchunk,
+                                 hipStream_t s);
+
 // Power of two 2^ysh that the projection folds into Y_{k,2} together with
 // the quadrature weight w_k, so that the split 16-bit operands stay clear of
 // the FP16 subnormals: without it w_k (about omega pi / (2 nq), 1e-3 .. 3e-2)

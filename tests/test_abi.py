@@ -121,9 +121,10 @@ def test_compress_argument_checks(hctx):
     assert lib.tai_compress(h, dummy, 0, ctypes.byref(p), ctypes.byref(rank), None, None, None, None, None) == tai.TAI_ERR_INVALID_ARG
     off = _params()
     assert lib.tai_compress(h, dummy, 10, ctypes.byref(off), ctypes.byref(rank), None, None, None, None, None) == tai.TAI_ERR_INVALID_ARG
+    # compression together with per-node degrees is accepted
     both = _params(rank_tol=1e-6, degree_tol=1e-8)
-    assert lib.tai_compress(h, dummy, 10, ctypes.byref(both), ctypes.byref(rank), None, None, None, None, None) == tai.TAI_ERR_UNSUPPORTED
-    assert lib.tai_assemble_B(h, dummy, 10, ctypes.byref(both), dummy, 10, None) == tai.TAI_ERR_UNSUPPORTED
+    assert lib.tai_compress(h, dummy, 10, ctypes.byref(both), ctypes.byref(rank), None, None, None, None, None) == tai.TAI_ERR_NOT_READY
+    assert lib.tai_assemble_B(h, dummy, 10, ctypes.byref(both), dummy, 10, None) == tai.TAI_ERR_NOT_READY
     assert lib.tai_compress(h, dummy, 10, ctypes.byref(p), ctypes.byref(rank), None, None, None, None, None) == tai.TAI_ERR_NOT_READY
     assert rank.value == -7
     assert lib.tai_assemble_B(h, dummy, 10, ctypes.byref(p), dummy, 10, None) == tai.TAI_ERR_NOT_READY

@@ -105,6 +105,39 @@ def test_compressed_J(tai, prec):
     assert err <= (1e-10 if prec == 0 else 1e-6), err
 
 
+@pytest.mark.parametrize("prec", [0, 1, 4])
+def test_compressed_with_node_degrees(tai, prec):
+    """rank_tol and degree_tol together: the compressed moments against the
+    tables of the truncated factors, Kc_k = V^T Kt_k V, for B (FP64, FP32 and
+    the split F16X3) and J (FP64), against the oracle's composition of its
+    truncated tables and its SVD basis."""
+    import torch
+    b, P = _spd()
+    P = dataclasses.replace(P, rank_tol=1e-6, degree_tol=1e-8)
+    t, w = T.time_nodes(P.omega, P.nq)
+    xi, _ = T.cheb_nodes(P.n, P.L, P.nodes)
+    N, _, Kt = T.truncated_tables(t, xi, P.L, P.degree_tol)
+    assert min(N) < P.n
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, kind=P.nodes)
+    V, s, R = T.compression_basis(Mr, P.rank_tol)
+    _check_cut(s, R, P.rank_tol)
+    U, Kc = T.compress(Mr, Kt, V)
+    Br = T.B_full(U, Kc, w)
+    Mg = tai.moments(b, P)
+    Bg = tai.assemble_B(Mg, P, prec=prec).cpu().numpy().astype(np.float64)
+    err = _normwise(Bg, Br)
+    assert err <= (1e-10 if prec == 0 else LOWP_TOL[prec]), (prec, err)
+    if prec == 0:
+        # the truncation shows at FP64: the result differs from compression
+        # alone (by about 4e-9 here), far above the tolerance
+        Bc = T.B_full(*T.compress(Mr, T.ktables(t, xi), V), w)
+        assert _normwise(Br, Bc) > 1e-9
+        D = I.random_density(np.random.default_rng(23), b)
+        Jr = T.J_grid(U, Kc, w, D)
+        Jg = tai.apply_J(Mg, torch.as_tensor(D, device=Mg.device), P, prec=0).cpu().numpy()
+        assert np.linalg.norm(Jg - Jr, 2) / np.linalg.norm(Jr, 2) <= 1e-10
+
+
 def test_compressed_J_screened_and_orbitals(tai):
     """The screened J and the orbital-basis J with the basis of the kept
     pairs' moments."""
@@ -285,3 +318,53 @@ def test_compressed_contracted_J(tai, prec):
     J = tai.apply_J_contracted(Mg, prim.nb, fmap, torch.as_tensor(D, device=Mg.device), P, prec=prec).cpu().numpy()
     err = np.linalg.norm(J - ref, 2) / np.linalg.norm(ref, 2)
     assert err <= (1e-10 if prec == 0 else 1e-6), err
+
+
+@pytest.mark.parametrize("prec", [0, 1, 4])
+def test_batched_compression(tai, prec):
+    """Compressed molecules inside a batch (rank_tol > 0, one also with
+    degree_tol > 0), next to uncompressed ones: the batch compresses every
+    molecule on the device without reading its rank back, writes the
+    operands at the full length n with zero directions beyond the rank, and
+    the FP64 / FP32 kernels skip those directions node by node.  Over three
+    hipGraph replays FP64 and FP32 equal the per-molecule calls bit for bit;
+    F16X3 (whose inner length then differs from the per-molecule call's)
+    agrees to its tolerance; the first compressed molecule matches the
+    oracle's compressed B."""
+    import torch
+    mols = I.batch64(nmol=6)
+    tols = [(1e-6, 0.0), (0.0, 0.0), (1e-5, 1e-9), (0.0, 1e-9), (1e-7, 0.0), (1e-6, 0.0)]
+    mols = [(b, dataclasses.replace(P, rank_tol=rt, degree_tol=dt)) for (b, P), (rt, dt) in zip(mols, tols)]
+    ctx = tai.context(0)
+    outs, Ms, keep, structs = [], [], [], []
+    dt_ = torch.float64 if prec == 0 else torch.float32
+    for b, P in mols:
+        ba = tai.BasisArrays(b)
+        keep.append(ba)
+        M = torch.empty((3, P.n, b.npair), dtype=torch.float64, device="cuda")
+        B = torch.full((b.npair, b.npair), float("nan"), dtype=dt_, device="cuda")
+        Ms.append(M)
+        outs.append(B)
+        structs.append(tai.tai_mol(ba.struct, tai.make_params(P, prec), M.data_ptr(), B.data_ptr(), b.npair))
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        for B in outs:
+            B.fill_(float("nan"))
+        torch.cuda.synchronize()
+        ctx.assemble_B_batched(structs, stream=stream)
+        torch.cuda.synchronize()
+        for (b, P), M, B in zip(mols, Ms, outs):
+            Bref = tai.assemble_B(tai.moments(b, P), P, prec=prec)
+            if prec in (0, 1):
+                assert torch.equal(B, Bref), f"replay {rep}"
+            else:
+                assert _normwise(B.double().cpu().numpy(), Bref.double().cpu().numpy()) <= 1e-6, f"replay {rep}"
+    b, P = mols[0]
+    K, w = _tables(P)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n, kind=P.nodes)
+    V, s, R = T.compression_basis(Mr, P.rank_tol)
+    _check_cut(s, R, P.rank_tol)
+    assert R < P.n
+    Br = T.B_full(*T.compress(Mr, K, V), w)
+    err = _normwise(outs[0].double().cpu().numpy(), Br)
+    assert err <= (1e-10 if prec == 0 else LOWP_TOL[prec]), err
