@@ -98,6 +98,10 @@ rho_mfma_kernel(const MT* __restrict__ M, const double* __restrict__ Dt, int n, 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
   const int a0base = blockIdx.x * A0G;
+  // batched densities (several orbitals in one launch): density z, its
+  // partial grids after those of densities 0 .. z-1
+  Dt += (int64_t)blockIdx.z * npair;
+  part += (int64_t)blockIdx.z * gridDim.y * n * n * n;
   const int64_t q0 = (int64_t)blockIdx.y * chunk;
   const int64_t q1 = (q0 + chunk < npair) ? q0 + chunk : npair;
   const MT* M0 = M;
@@ -662,6 +666,8 @@ __global__ void __launch_bounds__(256)
 sum_parts_kernel(const double* __restrict__ part, int nchunk, int64_t len, double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= len) return;
+  part += (int64_t)blockIdx.y * nchunk * len;   // batched: grid y
+  out += (int64_t)blockIdx.y * len;
   double s = 0.0;
   for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * len + i];
   out[i] = s;
@@ -681,6 +687,8 @@ slab_modes_kernel(const double* __restrict__ K, const double* __restrict__ rho, 
   const int a0 = blockIdx.x, k = blockIdx.y;
   const int64_t n2 = (int64_t)n * n;
   const double* Kk = K + (int64_t)k * n2;
+  rho += (int64_t)blockIdx.z * n * n2;          // batched: grid z, nq = grid y
+  T += (int64_t)blockIdx.z * gridDim.y * n * n2;
   const double* R = rho + a0 * n2;
   for (int e = threadIdx.x; e < n * n; e += 256) {
     const int i = e / n, j = e % n;
@@ -715,6 +723,8 @@ mode0_kernel(const double* __restrict__ K, const double* __restrict__ T, int n, 
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int k = blockIdx.y;
   const int64_t cc = c < n2 ? c : 0;
+  T += (int64_t)blockIdx.z * gridDim.y * n * n2;   // batched: grid z, nq = grid y
+  P += (int64_t)blockIdx.z * gridDim.y * n * n2;
   const double* Kk = K + (int64_t)k * n2;
   const double* Tk = T + (int64_t)k * n * n2;
   double acc[NMAX];
@@ -739,6 +749,8 @@ phi_kernel(const double* __restrict__ P, const double* __restrict__ w, int nq, i
            double* __restrict__ Phi) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n3) return;
+  P += (int64_t)blockIdx.y * nq * n3;   // batched: grid y
+  Phi += (int64_t)blockIdx.y * n3;
   double s = 0.0;
   for (int k = 0; k < nq; ++k) s += w[k] * P[(int64_t)k * n3 + i];
   Phi[i] = kTwoOverSqrtPi * s;
@@ -871,6 +883,8 @@ orbital_pairs_kernel(const double* __restrict__ q, int nb, int64_t npair, const 
                      double* __restrict__ Dt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npair) return;
+  q += (int64_t)blockIdx.y * nb;   // orbital blockIdx.y
+  Dt += (int64_t)blockIdx.y * npair;
   int mu, nu;
   Dt[p] = pair_of(pairs, nb, p, mu, nu) ? q[mu] * q[nu] * (mu == nu ? 1.0 : 2.0) : 0.0;
 }
@@ -952,9 +966,9 @@ JWork carve_j_work(void* base, int prec, int nq, int n, int npair) {
 }
 
 template <class Op, int A0W, class MT>
-void launch_pair_contraction_rho(const MT* M, int n, int npair, const JWork& w, hipStream_t s) {
+void launch_pair_contraction_rho(const MT* M, int n, int npair, const JWork& w, hipStream_t s, int ndens = 1) {
   const int64_t chunk = ((int64_t)npair + w.nchunk - 1) / w.nchunk;
-  const dim3 rg((n + 8 * A0W - 1) / (8 * A0W), w.nchunk);
+  const dim3 rg((n + 8 * A0W - 1) / (8 * A0W), w.nchunk, ndens);
   if (n <= 16) hipLaunchKernelGGL((rho_mfma_kernel<Op, 1, A0W, MT>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
   else if (n <= 32) hipLaunchKernelGGL((rho_mfma_kernel<Op, 2, A0W, MT>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
   else if (n <= 48) hipLaunchKernelGGL((rho_mfma_kernel<Op, 3, A0W, MT>), rg, dim3(512), 0, s, M, w.Dt, n, (int64_t)npair, chunk, w.rho_part);
@@ -1160,18 +1174,83 @@ hipError_t launch_apply_j_parts(int prec, const double* M, int nb, const int32_t
   return hipGetLastError();
 }
 
+// Orbitals per launch of the batched orbital densities, and the chunks of
+// pairs each orbital's density is split into (the launch holds enough work
+// groups for the device either way).
+constexpr int kMoBlock = 32;
+// The pair contraction runs one work group per compute unit: the chunk
+// count is the one between 2 and 4 waves of work groups over the device's
+// `cus` units whose last wave is fullest (the first such, at most the
+// single-density count).
+int mo_chunks(int prec, int n, int npair, int ob, int cus) {
+  const int groups = rho_groups(prec, n) * ob;
+  const int cap = j_nchunk(prec, n, npair);
+  int best = 1;
+  double best_eff = -1.0;
+  for (int c = (2 * cus + groups - 1) / groups; c <= (4 * cus + groups - 1) / groups && c <= cap; ++c) {
+    const int64_t total = (int64_t)groups * c;
+    const double eff = (double)total / (double)(((total + cus - 1) / cus) * cus);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = c;
+    }
+  }
+  if (best_eff < 0) best = cap < (2 * cus + groups - 1) / groups ? cap : (2 * cus + groups - 1) / groups;
+  return best < 1 ? 1 : best;
+}
+
+size_t mo_work_bytes(int prec, int n, int nq, int npair, int norb, int cus) {
+  const size_t n3 = (size_t)n * n * n;
+  const int ob = norb < kMoBlock ? norb : kMoBlock;
+  return align256(8 * n3 * norb) * 2 + align256(8 * (size_t)npair * ob) +
+         align256(8 * n3 * ob * mo_chunks(prec, n, npair, ob, cus)) + align256(8 * n3 * nq * ob) * 2;
+}
+
+// All orbitals' grid densities rho_i = Q(i,:) M_max (the paper's Q M_max,
+// eq. Coul) and Phi_i, in blocks of kMoBlock orbitals with one launch per
+// stage for the whole block: the orbital pair densities, the pair
+// contraction (grid z = orbital, each orbital's chunks of pairs), the chunk
+// sums, the mode products and the node sums; then J_mo(i, j) = <rho_i, Phi_j>.
 hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
-                             const NodeTables& tb, const double* Q, int norb, double* R, double* F, double* Jmo,
+                             const NodeTables& tb, const double* Q, int norb, int cus, void* work, double* Jmo,
                              const JWork& w, hipStream_t s) {
   const int64_t n3 = (int64_t)n * n * n;
   convert_moments(prec, M, n, npair, w, s);
-  for (int i = 0; i < norb; ++i) {
-    JWork wi = w;
-    wi.rho = R + (int64_t)i * n3;
-    wi.Phi = F + (int64_t)i * n3;
-    hipLaunchKernelGGL(orbital_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, Q + (int64_t)i * nb, nb,
-                       (int64_t)npair, pairs, wi.Dt);
-    launch_rho_phi(prec, M, npair, n, nq, tb, wi, s);
+  const int obmax = norb < kMoBlock ? norb : kMoBlock;
+  const int nc = mo_chunks(prec, n, npair, obmax, cus);
+  char* p = static_cast<char*>(work);
+  double* R = reinterpret_cast<double*>(p); p += align256(8 * n3 * norb);
+  double* F = reinterpret_cast<double*>(p); p += align256(8 * n3 * norb);
+  double* Dt = reinterpret_cast<double*>(p); p += align256(8 * (size_t)npair * obmax);
+  double* part = reinterpret_cast<double*>(p); p += align256(8 * n3 * obmax * nc);
+  double* T1 = reinterpret_cast<double*>(p); p += align256(8 * n3 * nq * obmax);
+  double* T2 = reinterpret_cast<double*>(p);
+  for (int i0 = 0; i0 < norb; i0 += obmax) {
+    const int ob = norb - i0 < obmax ? norb - i0 : obmax;
+    hipLaunchKernelGGL(orbital_pairs_kernel, dim3(nblk(npair, 256), ob), dim3(256), 0, s, Q + (int64_t)i0 * nb, nb,
+                       (int64_t)npair, pairs, Dt);
+    JWork wb = w;
+    wb.Dt = Dt;
+    wb.nchunk = nc;
+    wb.rho_part = part;
+    if (prec == kFP32)
+      launch_pair_contraction_rho<JF32, 1>(static_cast<const float*>(w.M32), n, npair, wb, s, ob);
+    else if (n <= 48) launch_pair_contraction_rho<JF64, 2>(M, n, npair, wb, s, ob);
+    else launch_pair_contraction_rho<JF64, 1>(M, n, npair, wb, s, ob);
+    double* Rb = R + (int64_t)i0 * n3;
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256), ob), dim3(256), 0, s, part, nc, n3, Rb);
+    const dim3 sg(n, nq, ob);
+    if (n <= 16) hipLaunchKernelGGL(slab_modes_kernel<16>, sg, dim3(256), 0, s, tb.K, Rb, n, T1);
+    else if (n <= 32) hipLaunchKernelGGL(slab_modes_kernel<32>, sg, dim3(256), 0, s, tb.K, Rb, n, T1);
+    else if (n <= 48) hipLaunchKernelGGL(slab_modes_kernel<48>, sg, dim3(256), 0, s, tb.K, Rb, n, T1);
+    else hipLaunchKernelGGL(slab_modes_kernel<64>, sg, dim3(256), 0, s, tb.K, Rb, n, T1);
+    const dim3 mg(nblk((int64_t)n * n, 256), nq, ob);
+    if (n <= 16) hipLaunchKernelGGL(mode0_kernel<16>, mg, dim3(256), 0, s, tb.K, T1, n, T2);
+    else if (n <= 32) hipLaunchKernelGGL(mode0_kernel<32>, mg, dim3(256), 0, s, tb.K, T1, n, T2);
+    else if (n <= 48) hipLaunchKernelGGL(mode0_kernel<48>, mg, dim3(256), 0, s, tb.K, T1, n, T2);
+    else hipLaunchKernelGGL(mode0_kernel<64>, mg, dim3(256), 0, s, tb.K, T1, n, T2);
+    hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256), ob), dim3(256), 0, s, T2, tb.w, nq, n3,
+                       F + (int64_t)i0 * n3);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

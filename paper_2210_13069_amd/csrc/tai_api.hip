@@ -1436,16 +1436,14 @@ int tai_coulomb_mo(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs
   const double* Mop = M;
   int n = p->n;
   if ((r = prepare_operands(c, M, npair, p, s, &tb, &Mop, &n, &tbp))) return r;
-  const size_t n3 = (size_t)n * n * n;
   if ((r = ensure(c, c->jwork, tai::j_work_bytes(p->prec, nq, n, (int)npair)))) return r;
-  if ((r = ensure(c, c->mo, 2 * sizeof(double) * n3 * (size_t)norb))) return r;
+  const int cus = c->cus > 0 ? c->cus : 256;
+  if ((r = ensure(c, c->mo, tai::mo_work_bytes(p->prec, n, nq, (int)npair, norb, cus)))) return r;
   hipError_t e;
   tai::JWork w = tai::carve_j_work(c->jwork.p, p->prec, nq, n, (int)npair);
-  double* R = static_cast<double*>(c->mo.p);
   {
     Timed tm(c, kStApplyJ, s);
-    e = tai::launch_coulomb_mo(p->prec, Mop, nb, (int)npair, pairs, n, nq, tbp, Q, norb, R, R + n3 * norb, Jmo, w,
-                               s);
+    e = tai::launch_coulomb_mo(p->prec, Mop, nb, (int)npair, pairs, n, nq, tbp, Q, norb, cus, c->mo.p, Jmo, w, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "coulomb_mo kernels");
   return TAI_OK;

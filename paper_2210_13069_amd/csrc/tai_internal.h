@@ -324,10 +324,12 @@ hipError_t launch_expand_density(const double* D, int nb, const int32_t* fmap, i
 hipError_t launch_contract_functions(const double* Jp, int nbp, const int32_t* first, int nb, double* J,
                                      hipStream_t s);
 // Coulomb matrix in the orbital basis: per orbital i (row i of Q, length nb)
-// the pair density of q_i q_i^T, rho_i -> R[i] and Phi_i -> F[i] (n^3 each),
-// then Jmo[i][j] = sum_a R[i][a] F[j][a].
+// the pair density of q_i q_i^T, rho_i and Phi_i (n^3 each) for blocks of
+// orbitals at a time, then Jmo[i][j] = <rho_i, Phi_j>.  work: mo_work_bytes.
+// cus: compute units of the device (the pair contraction's chunking).
+size_t mo_work_bytes(int prec, int n, int nq, int npair, int norb, int cus);
 hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const int32_t* pairs, int n, int nq,
-                             const NodeTables& tb, const double* Q, int norb, double* R, double* F, double* Jmo,
+                             const NodeTables& tb, const double* Q, int norb, int cus, void* work, double* Jmo,
                              const JWork& w, hipStream_t s);
 // Long-range exchange matrix (appendix B): X_{j mu} and Phi_{j nu} for every
 // orbital j and function mu into R and F ([norb][nb][n^3] each), then

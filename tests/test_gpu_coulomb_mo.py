@@ -69,3 +69,23 @@ def test_coulomb_mo_full_size_equals_ao_route(tai):
     err = float((got - ref).abs().max() / ref.abs().max())
     assert err <= 1e-11, err
     assert float((got - got.T).abs().max() / got.abs().max()) <= 1e-12
+
+
+def test_coulomb_mo_many_orbitals(tai):
+    """40 orbitals, more than one block of orbitals per launch (32 and 8):
+    every entry against the oracle, and each orbital block's densities equal
+    to what a call with that block's orbitals alone gives (to rounding: the
+    chunking of the pair sums follows the block size)."""
+    import torch
+    b = I.small_random(84, natoms=6, shells=("s", "p"), box=4.0, alpha_lo=0.2, alpha_hi=30.0)
+    P = I.Params(omega=0.4, nq=10, n=24, L=9.0)
+    Q = np.random.default_rng(17).standard_normal((40, b.nb))
+    K, w = _tables(P)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
+    ref = T.coulomb_mo(Mr, K, w, Q)
+    Mg = tai.moments(b, P)
+    got = tai.coulomb_mo(Mg, b.nb, torch.as_tensor(Q, device=Mg.device), P).cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert np.max(np.abs(got - got.T)) <= 1e-12 * np.max(np.abs(got))
+    tail = tai.coulomb_mo(Mg, b.nb, torch.as_tensor(Q[32:], device=Mg.device), P).cpu().numpy()
+    assert np.max(np.abs(got[32:, 32:] - tail)) <= 1e-13 * np.max(np.abs(tail))
