@@ -6,12 +6,15 @@
 // Three kernels:
 //   pack     A_d[p][:]    = M_d(:,p) scaled by 2^-e(p,d), split into slices
 //   project  Y_{k,d}[q][:] = (K_k M_d)(:,q) scaled by 2^-e(q,d) (and by w_k
-//            for d = 2), split into slices; FP64 arithmetic
+//            for d = 2), split into slices; FP64 arithmetic.  This k-dependent
+//            operand is written to HBM once per call (1.98 GB for F16X3 at
+//            Nb = 400) and streamed back by the assembly.
 //   assemble one work group per output tile; for each k it forms the three
 //            G tiles with MFMA (inner dimension = the concatenated slice
 //            products), multiplies them elementwise in registers and
-//            accumulates into the tile; no per-k matrix ever reaches memory.
-//            The tile (P,Q), P <= Q, is stored together with its mirror.
+//            accumulates into the tile: the G tiles and their products never
+//            reach memory.  The tile (P,Q), P <= Q, is stored together with
+//            its mirror.
 //
 // Operand rows are K-contiguous ("NT" product): G(p,q) = sum_c A[p][c] Y[q][c],
 // so both MFMA operands are read with the same per-lane addressing, and a
