@@ -892,7 +892,7 @@ orbital_pairs_kernel(const double* __restrict__ q, int nb, int64_t npair, const 
 // J_mo(i, j) = sum_a rho_i(a) Phi_j(a) over the n^3 grid, one work group per
 // (i, j), a fixed-order tree sum.
 __global__ void __launch_bounds__(256)
-mo_dot_kernel(const double* __restrict__ R, const double* __restrict__ F, int64_t n3, int norb,
+mo_dot_kernel(const double* __restrict__ R, const double* __restrict__ F, int64_t n3, int norb, double scale,
               double* __restrict__ Jmo) {
   __shared__ double red[256];
   const int i = blockIdx.y, j = blockIdx.x;
@@ -906,7 +906,7 @@ mo_dot_kernel(const double* __restrict__ R, const double* __restrict__ F, int64_
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) Jmo[(int64_t)i * norb + j] = red[0];
+  if (threadIdx.x == 0) Jmo[(int64_t)i * norb + j] = scale * red[0];
 }
 
 // J entries of the pairs that screening dropped are zero.
@@ -1098,9 +1098,9 @@ hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, const in
 
 namespace {
 __global__ void __launch_bounds__(256)
-repeat_weights_kernel(const double* __restrict__ w, int nq, int reps, double* __restrict__ out) {
+repeat_weights_kernel(const double* __restrict__ w, int nq, int reps, double scale, double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nq * reps) out[i] = w[i % nq];
+  if (i < nq * reps) out[i] = scale * w[i % nq];
 }
 }  // namespace
 
@@ -1112,14 +1112,18 @@ repeat_weights_kernel(const double* __restrict__ w, int nq, int reps, double* __
 // J_p for the pairs of s, unpacked into J.
 hipError_t launch_apply_j_parts(int prec, const double* M, int nb, const int32_t* pairs, const int64_t* offs,
                                 int nparts, int n, int nq, const double* w, const double* Kx, const double* D,
-                                double* J, const JWork& wk, double* rho_all, double* T2_all, double* wrep,
-                                hipStream_t s) {
+                                double* J, const JWork& wk, double* rho_all, double* T2_all, double* Phi_all,
+                                double* wrep, hipStream_t s) {
   const int64_t total = offs[nparts];
   const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
   hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(total, 256)), dim3(256), 0, s, D, nb, total, pairs, wk.Dt);
   convert_moments(prec, M, n, (int)total, wk, s);
+  // one box: the plain path's kernels (the same bits as tai_apply_J); more
+  // boxes: the mode products of all box pairs at once on the matrix cores,
+  // with 2/sqrt(pi) folded into the repeated weights
+  const bool one = nparts == 1;
   hipLaunchKernelGGL(repeat_weights_kernel, dim3(nblk((int64_t)nq * nparts, 256)), dim3(256), 0, s, w, nq, nparts,
-                     wrep);
+                     one ? 1.0 : kTwoOverSqrtPi, wrep);
   for (int p = 0; p < nparts; ++p) {
     const int64_t cnt = offs[p + 1] - offs[p];
     double* rho_p = rho_all + p * n3;
@@ -1138,10 +1142,18 @@ hipError_t launch_apply_j_parts(int prec, const double* M, int nb, const int32_t
     else launch_pair_contraction_rho<JF64, 1>(Mp, n, (int)cnt, wp, s);
     hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, wk.rho_part, wk.nchunk, n3, rho_p);
   }
+  if (!one) {
+    // T1 of box pair (p, q) = rho_q through the tables K^(p,q), at
+    // T2_all[(p nparts + q) nq]; Phi_p sums its nparts nq node blocks
+    const hipError_t e = launch_mode_products(rho_all, (int64_t)nparts * nparts, nparts, Kx, (int64_t)nq * n2, wrep,
+                                              n, nq, T2_all, nparts, (int64_t)nparts * nq * n2, nparts * nq, Phi_all,
+                                              s);
+    if (e != hipSuccess) return e;
+  }
   for (int p = 0; p < nparts; ++p) {
     const int64_t cnt = offs[p + 1] - offs[p];
     if (cnt == 0) continue;
-    for (int q = 0; q < nparts; ++q) {
+    for (int q = 0; q < nparts && one; ++q) {
       const double* Kpq = Kx + ((int64_t)p * nparts + q) * nq * n2;
       double* T2q = T2_all + (int64_t)q * nq * n3;
       const double* rho_q = rho_all + q * n3;
@@ -1155,13 +1167,14 @@ hipError_t launch_apply_j_parts(int prec, const double* M, int nb, const int32_t
       else if (n <= 48) hipLaunchKernelGGL(mode0_kernel<48>, mg, dim3(256), 0, s, Kpq, wk.T1, n, T2q);
       else hipLaunchKernelGGL(mode0_kernel<64>, mg, dim3(256), 0, s, Kpq, wk.T1, n, T2q);
     }
-    hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, T2_all, wrep, nq * nparts, n3, wk.Phi);
+    if (one) hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, T2_all, wrep, nq, n3, wk.Phi);
     JWork wp = wk;
     wp.Jp = wk.Jp + offs[p];
+    wp.Phi = one ? wk.Phi : Phi_all + (int64_t)p * n3;
     if (split_j(prec)) {
       const float* M32p = wk.M32 + 3 * (int64_t)n * offs[p];
-      if (j_slices(prec) == 3) launch_jp16_s<3>(M32p, wk.Phi, wk.Ps, n, (int)cnt, wp.Jp, s);
-      else launch_jp16_s<2>(M32p, wk.Phi, wk.Ps, n, (int)cnt, wp.Jp, s);
+      if (j_slices(prec) == 3) launch_jp16_s<3>(M32p, wp.Phi, wk.Ps, n, (int)cnt, wp.Jp, s);
+      else launch_jp16_s<2>(M32p, wp.Phi, wk.Ps, n, (int)cnt, wp.Jp, s);
     } else if (prec == kFP32) {
       launch_pair_contraction_jp<JF32>(M + 3 * (int64_t)n * offs[p], n, (int)cnt, wp, s);
     } else {
@@ -1203,7 +1216,7 @@ size_t mo_work_bytes(int prec, int n, int nq, int npair, int norb, int cus) {
   const size_t n3 = (size_t)n * n * n;
   const int ob = norb < kMoBlock ? norb : kMoBlock;
   return align256(8 * n3 * norb) * 2 + align256(8 * (size_t)npair * ob) +
-         align256(8 * n3 * ob * mo_chunks(prec, n, npair, ob, cus)) + align256(8 * n3 * nq * ob) * 2;
+         align256(8 * n3 * ob * mo_chunks(prec, n, npair, ob, cus)) + align256(8 * n3 * nq * ob);
 }
 
 // All orbitals' grid densities rho_i = Q(i,:) M_max (the paper's Q M_max,
@@ -1223,8 +1236,7 @@ hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const
   double* F = reinterpret_cast<double*>(p); p += align256(8 * n3 * norb);
   double* Dt = reinterpret_cast<double*>(p); p += align256(8 * (size_t)npair * obmax);
   double* part = reinterpret_cast<double*>(p); p += align256(8 * n3 * obmax * nc);
-  double* T1 = reinterpret_cast<double*>(p); p += align256(8 * n3 * nq * obmax);
-  double* T2 = reinterpret_cast<double*>(p);
+  double* T1 = reinterpret_cast<double*>(p);
   for (int i0 = 0; i0 < norb; i0 += obmax) {
     const int ob = norb - i0 < obmax ? norb - i0 : obmax;
     hipLaunchKernelGGL(orbital_pairs_kernel, dim3(nblk(npair, 256), ob), dim3(256), 0, s, Q + (int64_t)i0 * nb, nb,
@@ -1239,22 +1251,13 @@ hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const
     else launch_pair_contraction_rho<JF64, 1>(M, n, npair, wb, s, ob);
     double* Rb = R + (int64_t)i0 * n3;
     hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256), ob), dim3(256), 0, s, part, nc, n3, Rb);
-    const dim3 sg(n, nq, ob);
-    if (n <= 16) hipLaunchKernelGGL(slab_modes_kernel<16>, sg, dim3(256), 0, s, tb.K, Rb, n, T1);
-    else if (n <= 32) hipLaunchKernelGGL(slab_modes_kernel<32>, sg, dim3(256), 0, s, tb.K, Rb, n, T1);
-    else if (n <= 48) hipLaunchKernelGGL(slab_modes_kernel<48>, sg, dim3(256), 0, s, tb.K, Rb, n, T1);
-    else hipLaunchKernelGGL(slab_modes_kernel<64>, sg, dim3(256), 0, s, tb.K, Rb, n, T1);
-    const dim3 mg(nblk((int64_t)n * n, 256), nq, ob);
-    if (n <= 16) hipLaunchKernelGGL(mode0_kernel<16>, mg, dim3(256), 0, s, tb.K, T1, n, T2);
-    else if (n <= 32) hipLaunchKernelGGL(mode0_kernel<32>, mg, dim3(256), 0, s, tb.K, T1, n, T2);
-    else if (n <= 48) hipLaunchKernelGGL(mode0_kernel<48>, mg, dim3(256), 0, s, tb.K, T1, n, T2);
-    else hipLaunchKernelGGL(mode0_kernel<64>, mg, dim3(256), 0, s, tb.K, T1, n, T2);
-    hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256), ob), dim3(256), 0, s, T2, tb.w, nq, n3,
-                       F + (int64_t)i0 * n3);
-    const hipError_t e = hipGetLastError();
+    // the block's mode products on the matrix cores (Phi without 2/sqrt(pi),
+    // which the dot products apply)
+    const hipError_t e = launch_mode_products(Rb, ob, ob, tb.K, 0, tb.w, n, nq, T1, ob, 0, nq,
+                                              F + (int64_t)i0 * n3, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(mo_dot_kernel, dim3(norb, norb), dim3(256), 0, s, R, F, n3, norb, Jmo);
+  hipLaunchKernelGGL(mo_dot_kernel, dim3(norb, norb), dim3(256), 0, s, R, F, n3, norb, kTwoOverSqrtPi, Jmo);
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@
 #include "tai_device.h"
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 
 namespace tai {
@@ -212,11 +213,13 @@ exch_x_kernel(const double* __restrict__ M, int64_t npair, int n, int nb, const 
 // The work group takes SB slabs (t, a0) of consecutive index s = t n + a0,
 // keeps them in LDS (zero padded to NP x NP) and for every node k forms
 // U = K_k X(a0) and S = U K_k^T on the FP64 matrix cores, K_k staged in LDS,
-// writing S to T1[t][k][a0][a1 n + a2].
+// writing S to T1[t][k][a0][a1 n + a2].  Tensor t reads X[t % xmod] and the
+// tables K + t kstride (kstride 0: one table set; with kstride > 0 a work
+// group holds one slab, SB = 1).
 template <int NT, int SB>
 __global__ void __launch_bounds__(256)
 exch_slab_kernel(const double* __restrict__ X, const double* __restrict__ K, int n, int nq, int64_t nslab,
-                 double* __restrict__ T1) {
+                 double* __restrict__ T1, int64_t xmod, int64_t kstride) {
   constexpr int NP = 16 * NT, PS = NP + 1;
   constexpr int TILES = SB * NT * NT;
   __shared__ double Xs[SB * NP * PS];   // [SB][NP][PS]
@@ -232,12 +235,16 @@ exch_slab_kernel(const double* __restrict__ X, const double* __restrict__ K, int
     const int a1 = rem / NP, a2 = rem - a1 * NP;
     const int64_t sl = s0 + sb;
     double v = 0.0;
-    if (sl < nslab && a1 < n && a2 < n) v = X[sl * n2 + a1 * n + a2];
+    if (sl < nslab && a1 < n && a2 < n) {
+      const int64_t t = sl / n, a0 = sl - t * n;
+      v = X[((t % xmod) * n + a0) * n2 + a1 * n + a2];
+    }
     Xs[(sb * NP + a1) * PS + a2] = v;
   }
+  const double* Kt = K + (s0 / n) * kstride;
   for (int k = 0; k < nq; ++k) {
     __syncthreads();  // previous node's Ks and Us reads are done
-    const double* Kk = K + (int64_t)k * n2;
+    const double* Kk = Kt + (int64_t)k * n2;
     for (int e = threadIdx.x; e < NP * NP; e += 256) {
       const int a = e / NP, b = e - a * NP;
       Ks[a * PS + b] = (a < n && b < n) ? Kk[a * n + b] : 0.0;
@@ -282,11 +289,12 @@ exch_slab_kernel(const double* __restrict__ X, const double* __restrict__ K, int
 // Phi_t(i0, c) = sum_k w_k sum_a K_k(i0, a) T1[t][k][a][c], c = (a1, a2): grid
 // (ceil(n^2 / 64), Tc), 256 threads; wave w owns the 16 columns
 // c0 + 16 w .. + 16 and all NT tiles of i0.  Per node, w_k K_k is staged in
-// LDS; the T1 fragments stream from memory once.
+// LDS; the T1 fragments stream from memory once.  Tensor t's tables start at
+// K + t kstride.
 template <int NT>
 __global__ void __launch_bounds__(256)
 exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, const double* __restrict__ w, int n,
-                  int nq, double* __restrict__ Phi) {
+                  int nq, double* __restrict__ Phi, int64_t kstride) {
   constexpr int NP = 16 * NT, PS = NP + 1;
   __shared__ double Ws[NP * PS];
   const int lane = threadIdx.x & 63;
@@ -303,7 +311,7 @@ exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, c
   for (int k = 0; k < nq; ++k) {
     __syncthreads();
     const double wk = w[k];
-    const double* Kk = K + (int64_t)k * n2;
+    const double* Kk = K + t * kstride + (int64_t)k * n2;
     for (int e = threadIdx.x; e < NP * NP; e += 256) {
       const int a = e / NP, b = e - a * NP;
       Ws[a * PS + b] = (a < n && b < n) ? wk * Kk[a * n + b] : 0.0;
@@ -425,11 +433,37 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // SB slabs per work group: LDS (2 SB + 1) NP (NP + 1) doubles, 76 KB at
 // n <= 32 (SB 4), 94 KB at n <= 48 (SB 2), 100 KB at n <= 64 (SB 1)
 template <int NT, int SB>
-void launch_slab(const double* X, const double* K, int n, int nq, int64_t nslab, double* T1, hipStream_t s) {
-  hipLaunchKernelGGL((exch_slab_kernel<NT, SB>), dim3(nblk(nslab, SB)), dim3(256), 0, s, X, K, n, nq, nslab, T1);
+void launch_slab(const double* X, const double* K, int n, int nq, int64_t nslab, double* T1, hipStream_t s,
+                 int64_t xmod = INT64_MAX, int64_t kstride = 0) {
+  hipLaunchKernelGGL((exch_slab_kernel<NT, SB>), dim3(nblk(nslab, SB)), dim3(256), 0, s, X, K, n, nq, nslab, T1,
+                     xmod, kstride);
 }
 
 }  // namespace
+
+hipError_t launch_mode_products(const double* X, int64_t T, int64_t xmod, const double* K, int64_t kstride,
+                                const double* w, int n, int nq, double* T1, int64_t T0, int64_t kstride0,
+                                int nq0, double* Phi, hipStream_t s) {
+  const int NT = (n + 15) / 16;
+  const int64_t nslab = T * n, n2 = (int64_t)n * n;
+  if (kstride != 0) {
+    if (NT == 1) launch_slab<1, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride);
+    else if (NT == 2) launch_slab<2, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride);
+    else if (NT == 3) launch_slab<3, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride);
+    else launch_slab<4, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride);
+  } else {
+    if (NT == 1) launch_slab<1, 4>(X, K, n, nq, nslab, T1, s, xmod, 0);
+    else if (NT == 2) launch_slab<2, 4>(X, K, n, nq, nslab, T1, s, xmod, 0);
+    else if (NT == 3) launch_slab<3, 2>(X, K, n, nq, nslab, T1, s, xmod, 0);
+    else launch_slab<4, 1>(X, K, n, nq, nslab, T1, s, xmod, 0);
+  }
+  const dim3 mg(nblk(n2, 64), (unsigned)T0);
+  if (NT == 1) hipLaunchKernelGGL((exch_mode0_kernel<1>), mg, dim3(256), 0, s, T1, K, w, n, nq0, Phi, kstride0);
+  else if (NT == 2) hipLaunchKernelGGL((exch_mode0_kernel<2>), mg, dim3(256), 0, s, T1, K, w, n, nq0, Phi, kstride0);
+  else if (NT == 3) hipLaunchKernelGGL((exch_mode0_kernel<3>), mg, dim3(256), 0, s, T1, K, w, n, nq0, Phi, kstride0);
+  else hipLaunchKernelGGL((exch_mode0_kernel<4>), mg, dim3(256), 0, s, T1, K, w, n, nq0, Phi, kstride0);
+  return hipGetLastError();
+}
 
 ExchangeWork exchange_work_plan(int n, int nq, int nb, int norb, bool listed, int64_t npair_full) {
   ExchangeWork p{};
@@ -501,10 +535,10 @@ hipError_t launch_exchange(int prec, const double* M, int nb, int64_t npair, con
     else launch_slab<4, 1>(Xc, tb.K, n, nq, nslab, T1, s);
     const dim3 mg(nblk(n2, 64), (unsigned)tc);
     double* Pc = Phi + t0 * n3;
-    if (NT == 1) hipLaunchKernelGGL((exch_mode0_kernel<1>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc);
-    else if (NT == 2) hipLaunchKernelGGL((exch_mode0_kernel<2>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc);
-    else if (NT == 3) hipLaunchKernelGGL((exch_mode0_kernel<3>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc);
-    else hipLaunchKernelGGL((exch_mode0_kernel<4>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc);
+    if (NT == 1) hipLaunchKernelGGL((exch_mode0_kernel<1>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
+    else if (NT == 2) hipLaunchKernelGGL((exch_mode0_kernel<2>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
+    else if (NT == 3) hipLaunchKernelGGL((exch_mode0_kernel<3>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
+    else hipLaunchKernelGGL((exch_mode0_kernel<4>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -824,15 +824,18 @@ int tai_apply_J_partitioned(tai_ctx* c, const double* M, int32_t nb, const int32
   NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
   const size_t n3 = (size_t)n * n * n;
   const size_t jb = align256(tai::j_work_bytes(p->prec, nq, n, (int)npair));
-  const size_t rb = align256(8 * n3 * nparts), tb2 = align256(8 * n3 * nq * nparts), wb = align256(8 * nq * nparts);
+  // rho and Phi of every box; the node products of every box pair
+  const size_t rb = align256(8 * n3 * nparts), tb2 = align256(8 * n3 * nq * nparts * nparts),
+               wb = align256(8 * nq * nparts);
   const size_t kb = align256(8 * (size_t)nparts * nparts * nq * n * n);
-  if ((r = ensure(c, c->partJ, jb + rb + tb2 + wb + kb))) return r;
+  if ((r = ensure(c, c->partJ, jb + rb * 2 + tb2 + wb + kb))) return r;
   char* base = static_cast<char*>(c->partJ.p);
   tai::JWork w = tai::carve_j_work(base, p->prec, nq, n, (int)npair);
   double* rho_all = reinterpret_cast<double*>(base + jb);
-  double* T2_all = reinterpret_cast<double*>(base + jb + rb);
-  double* wrep = reinterpret_cast<double*>(base + jb + rb + tb2);
-  double* Kx = reinterpret_cast<double*>(base + jb + rb + tb2 + wb);
+  double* Phi_all = reinterpret_cast<double*>(base + jb + rb);
+  double* T2_all = reinterpret_cast<double*>(base + jb + 2 * rb);
+  double* wrep = reinterpret_cast<double*>(base + jb + 2 * rb + tb2);
+  double* Kx = reinterpret_cast<double*>(base + jb + 2 * rb + tb2 + wb);
   hipError_t e;
   {
     Timed tm(c, kStNodes, s);
@@ -844,7 +847,7 @@ int tai_apply_J_partitioned(tai_ctx* c, const double* M, int32_t nb, const int32
   {
     Timed tm(c, kStApplyJ, s);
     e = tai::launch_apply_j_parts(p->prec, M, nb, pairs, offs, nparts, n, nq, tb.w, Kx, D, J, w, rho_all, T2_all,
-                                  wrep, s);
+                                  Phi_all, wrep, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "partitioned apply_J kernels");
   return TAI_OK;

@@ -365,8 +365,8 @@ hipError_t launch_cross_tables(const double* t, int nq, int n, int kind, const P
 // Kx from launch_cross_tables; w the node weights.
 hipError_t launch_apply_j_parts(int prec, const double* M, int nb, const int32_t* pairs, const int64_t* offs,
                                 int nparts, int n, int nq, const double* w, const double* Kx, const double* D,
-                                double* J, const JWork& wk, double* rho_all, double* T2_all, double* wrep,
-                                hipStream_t s);
+                                double* J, const JWork& wk, double* rho_all, double* T2_all, double* Phi_all,
+                                double* wrep, hipStream_t s);
 
 // Exchange matrix, factorized form (k_exchange.hip).  exchange_work_plan
 // lays out one workspace: the X and Phi grid tensors of all norb nb
@@ -379,6 +379,14 @@ struct ExchangeWork {
   size_t off_X, off_Phi, off_T1, off_part, off_inv, bytes;
 };
 ExchangeWork exchange_work_plan(int n, int nq, int nb, int norb, bool listed, int64_t npair_full);
+// Mode products on the FP64 matrix cores for many tensors (k_exchange.hip):
+// slab products T1[t][k][a0] = K_k X_t(a0) K_k^T for T tensors, tensor t
+// reading X[t % xmod] and the tables K + t kstride; then for T0 groups of
+// consecutive T1 blocks, Phi_g = sum_k w_k K_k x_0 (group g's nq0 node
+// blocks, tables K + g kstride0), without the factor 2/sqrt(pi).
+hipError_t launch_mode_products(const double* X, int64_t T, int64_t xmod, const double* K, int64_t kstride,
+                                const double* w, int n, int nq, double* T1, int64_t T0, int64_t kstride0,
+                                int nq0, double* Phi, hipStream_t s);
 hipError_t launch_exchange(int prec, const double* M, int nb, int64_t npair, const int32_t* pairs, int n, int nq,
                            const NodeTables& tb, const double* Q, int norb, void* work, const ExchangeWork& p,
                            double* Kx, hipStream_t s);

@@ -84,7 +84,9 @@ def test_one_partition_is_the_plain_J(tai):
 
 def test_empty_partitions(tai):
     """All functions on one centre with one exponent: every support is the
-    same, so the first box holds every pair and the others are empty."""
+    same, so the first box holds every pair and the others are empty.  Three
+    boxes take the batched box-pair mode products, one box the plain path's
+    kernels: the same J to rounding."""
     import torch
     b = I.small_random(22, natoms=1, shells=("p",), box=0.0, alpha_lo=0.7, alpha_hi=0.7)
     P = I.Params(omega=0.5, nq=8, n=16, L=0.0)
@@ -95,4 +97,4 @@ def test_empty_partitions(tai):
     J3 = tai.apply_J_partitioned(Mg, D, pairs, counts, boxes, P)
     p1, c1, b1 = tai.partition_pairs(b, 1e-12, 1)
     J1 = tai.apply_J_partitioned(tai.moments_partitioned(b, P, p1, c1, b1), D, p1, c1, b1, P)
-    assert torch.equal(J3, J1)
+    assert float((J3 - J1).abs().max() / J1.abs().max()) <= 1e-13
