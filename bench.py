@@ -533,6 +533,46 @@ def main():
             adaptive[name] = rec
         japply["adaptive_boxes"] = adaptive
         del lst, Mpt, Jpt
+        # the same on the Nb = 400 basis (its J with the random density of
+        # the J workload's recipe), FP64, against the fixed box L = 16
+        b4, P4 = I.spd400(omega=0.3)
+        D4 = torch.as_tensor(I.random_density(np.random.default_rng(41), b4), device=dev)
+        ba4 = tai.BasisArrays(b4)
+        M4 = torch.empty(3 * P4.n * b4.npair, dtype=torch.float64, device=dev)
+        J4f = torch.empty((b4.nb, b4.nb), dtype=torch.float64, device=dev)
+        J4a = torch.empty_like(J4f)
+        lst4 = torch.empty(b4.npair, dtype=torch.int32, device=dev)
+        p4 = tai.make_params(P4, tai.FP64)
+        log(f"adaptive-box J Nb=400 fp64: nparts={PARTS_N}")
+        for it in range(W + K):
+            if it == W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            ctx.moments(ba4, P4, M4)
+            ctx.apply_J(M4, b4.nb, p4, D4, J4f)
+        torch.cuda.synchronize()
+        ms_f4 = (time.perf_counter() - t0) * 1e3 / K
+        for it in range(W + K):
+            if it == W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            counts4, boxes4 = ctx.partition_pairs(ba4, PARTS_TAU, PARTS_N, lst4)
+            off = 0
+            for c_, bx_ in zip(counts4, boxes4):
+                if c_:
+                    ctx.moments_pairs(ba4, dataclasses.replace(P4, L=bx_), lst4[off:], c_,
+                                      M4[3 * P4.n * off:3 * P4.n * (off + c_)])
+                off += c_
+            ctx.apply_J_partitioned(M4, b4.nb, lst4, counts4, boxes4, p4, D4, J4a)
+        torch.cuda.synchronize()
+        ms_a4 = (time.perf_counter() - t0) * 1e3 / K
+        adaptive["spd400_fp64"] = {
+            "workload": "spd400 basis (Nb=400, 80200 pairs), omega=0.3, nq=32, n=40; J of a random density",
+            "boxes": [round(x, 4) for x in boxes4], "counts": counts4,
+            "ms_per_step": round(ms_a4, 3), "fixed_box_L16_ms_per_step": round(ms_f4, 3),
+            "rel_2norm_vs_fixed_box_L16_gpu": float(torch.linalg.matrix_norm(J4a - J4f, 2) /
+                                                    torch.linalg.matrix_norm(J4f, 2))}
+        del M4, J4f, J4a, lst4
         # the same J-build on the compressed grid (R^3 instead of n^3)
         jPc = dataclasses.replace(jP, rank_tol=RANK_TOL_J)
         ctx.moments(jba, jP, Mj)
