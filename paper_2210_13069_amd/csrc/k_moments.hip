@@ -127,12 +127,14 @@ moments_kernel(DevBasis bs, int n, double L, NodeTables tb, double* __restrict__
   moments_body<NMAX>(bs, n, L, tb, M, npair, pairs);
 }
 
-// Screening (section 6.3, compression by screening).  One thread per row mu
-// of the pair list counts, then writes, the pairs (mu, nu >= mu) whose
-// Gaussian product prefactor exp(-ab/(a+b) |A - B|^2) exceeds tau; a single
-// work group turns the row counts into offsets in between, so the kept
-// indices come out in ascending order.  The exponent is formed with
-// unfused, left-to-right operations.
+// Screening (section 6.3, compression by screening).  One wave per row mu of
+// the pair list counts, then writes, the pairs (mu, nu >= mu) whose Gaussian
+// product prefactor exp(-ab/(a+b) |A - B|^2) exceeds tau, 64 columns nu at a
+// time: a ballot of the lanes that keep their pair gives each kept lane its
+// slot (the kept lanes below it) and the chunk's count.  A single work group
+// turns the row counts into offsets in between, so the kept indices come out
+// in ascending order.  The exponent is formed with unfused, left-to-right
+// operations.
 __device__ inline bool keep_pair(const DevBasis& bs, double tau, int mu, int nu) {
 #pragma clang fp contract(off)
   const double a = bs.alpha[mu], b = bs.alpha[nu];
@@ -145,14 +147,19 @@ __device__ inline bool keep_pair(const DevBasis& bs, double tau, int mu, int nu)
   return tau <= 0.0 || exp(-e) > tau;
 }
 
-constexpr int kScreenThreads = 256;
+constexpr int kScreenRows = 4;  // rows (one wave each) per work group
+constexpr int kScreenThreads = 64 * kScreenRows;
 
 __global__ void __launch_bounds__(kScreenThreads) screen_count_kernel(DevBasis bs, double tau, int32_t* rows) {
-  const int mu = blockIdx.x * kScreenThreads + threadIdx.x;
-  if (mu >= bs.nb) return;
+  const int mu = blockIdx.x * kScreenRows + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (mu >= bs.nb) return;  // whole waves
   int c = 0;
-  for (int nu = mu; nu < bs.nb; ++nu) c += keep_pair(bs, tau, mu, nu) ? 1 : 0;
-  rows[mu] = c;
+  for (int nu0 = mu; nu0 < bs.nb; nu0 += 64) {
+    const int nu = nu0 + lane;
+    c += __popcll(__ballot(nu < bs.nb && keep_pair(bs, tau, mu, nu)));
+  }
+  if (lane == 0) rows[mu] = c;
 }
 
 // exclusive scan of rows[0 .. nb) in place, total to rows[nb] and *count
@@ -185,12 +192,19 @@ __global__ void __launch_bounds__(1024) screen_scan_kernel(int nb, int32_t* rows
 
 __global__ void __launch_bounds__(kScreenThreads)
 screen_write_kernel(DevBasis bs, double tau, const int32_t* __restrict__ rows, int32_t* __restrict__ pairs) {
-  const int mu = blockIdx.x * kScreenThreads + threadIdx.x;
-  if (mu >= bs.nb) return;
+  const int mu = blockIdx.x * kScreenRows + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (mu >= bs.nb) return;  // whole waves
   int32_t o = rows[mu];
+  const uint64_t below = __lanemask_lt();
   const int64_t p0 = pair_row_start(bs.nb, mu);
-  for (int nu = mu; nu < bs.nb; ++nu)
-    if (keep_pair(bs, tau, mu, nu)) pairs[o++] = (int32_t)(p0 + (nu - mu));
+  for (int nu0 = mu; nu0 < bs.nb; nu0 += 64) {
+    const int nu = nu0 + lane;
+    const bool k = nu < bs.nb && keep_pair(bs, tau, mu, nu);
+    const uint64_t m = __ballot(k);
+    if (k) pairs[o + __popcll(m & below)] = (int32_t)(p0 + (nu - mu));
+    o += __popcll(m);
+  }
 }
 
 // blockIdx.y = molecule; blocks past a molecule's 3*npair threads return
@@ -298,7 +312,7 @@ hipError_t launch_moments(const DevBasis& b, int n, double L, const NodeTables& 
 
 hipError_t launch_screen(const DevBasis& b, double tau, int32_t* rows, int32_t* pairs, int32_t* count,
                          hipStream_t s) {
-  const unsigned blocks = (unsigned)((b.nb + kScreenThreads - 1) / kScreenThreads);
+  const unsigned blocks = (unsigned)((b.nb + kScreenRows - 1) / kScreenRows);
   hipLaunchKernelGGL(screen_count_kernel, dim3(blocks), dim3(kScreenThreads), 0, s, b, tau, rows);
   hipLaunchKernelGGL(screen_scan_kernel, dim3(1), dim3(1024), 0, s, b.nb, rows, count);
   hipLaunchKernelGGL(screen_write_kernel, dim3(blocks), dim3(kScreenThreads), 0, s, b, tau, rows, pairs);

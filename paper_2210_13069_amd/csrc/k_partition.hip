@@ -13,7 +13,8 @@
 //    boxes; a pair belongs to the first box that holds its support.
 //  * part_count_kernel / part_scan_kernel / part_write_kernel: the pair
 //    lists of the partitions, concatenated in partition order, each
-//    ascending, as the screening kernels build the kept list.
+//    ascending, as the screening kernels build the kept list (one wave per
+//    row, a ballot per partition).
 //  * cross_tables_kernel: K_k^(s,s')(a, b) = exp(-t_k^2 (xi^s_a - xi^s'_b)^2),
 //    xi^s the Chebyshev nodes of box s: the node values of the interpolant of
 //    exp(-t_k^2 (x - y)^2) on [-b_s, b_s] x [-b_s', b_s'].
@@ -58,17 +59,33 @@ __device__ inline int part_of(double v, const double* boxes, int nparts) {
   return s;
 }
 
-// counts[s][mu] = pairs (mu, nu >= mu) of partition s
-__global__ void __launch_bounds__(256)
+// One wave per row mu, 64 columns nu at a time.  Partition indices are
+// compared against every s < kMaxParts with static register indices (no
+// scratch arrays): counts[s][mu] = pairs (mu, nu >= mu) of partition s.
+constexpr int kPartRows = 4;  // rows (one wave each) per work group
+
+__global__ void __launch_bounds__(64 * kPartRows)
 part_count_kernel(int nb, const double* __restrict__ sup, const double* __restrict__ boxes, int nparts,
                   int32_t* __restrict__ counts) {
-  const int mu = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mu >= nb) return;
+  const int mu = blockIdx.x * kPartRows + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (mu >= nb) return;  // whole waves
   int32_t c[kMaxParts];
-  for (int s = 0; s < nparts; ++s) c[s] = 0;
+#pragma unroll
+  for (int s = 0; s < kMaxParts; ++s) c[s] = 0;
   const int64_t p0 = pair_row_start(nb, mu);
-  for (int nu = mu; nu < nb; ++nu) ++c[part_of(sup[p0 + (nu - mu)], boxes, nparts)];
-  for (int s = 0; s < nparts; ++s) counts[(int64_t)s * nb + mu] = c[s];
+  for (int nu0 = mu; nu0 < nb; nu0 += 64) {
+    const int nu = nu0 + lane;
+    const int sl = nu < nb ? part_of(sup[p0 + (nu - mu)], boxes, nparts) : kMaxParts;
+#pragma unroll
+    for (int s = 0; s < kMaxParts; ++s)
+      if (s < nparts) c[s] += __popcll(__ballot(sl == s));
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int s = 0; s < kMaxParts; ++s)
+      if (s < nparts) counts[(int64_t)s * nb + mu] = c[s];
+  }
 }
 
 // exclusive scan of counts[0 .. len) in place (partition-major order), the
@@ -110,18 +127,33 @@ part_scan_kernel(int nb, int nparts, int32_t* __restrict__ counts, int32_t* __re
   }
 }
 
-__global__ void __launch_bounds__(256)
+// each lane's slot: its partition's running offset plus the lanes below it
+// in the same partition
+__global__ void __launch_bounds__(64 * kPartRows)
 part_write_kernel(int nb, const double* __restrict__ sup, const double* __restrict__ boxes, int nparts,
                   const int32_t* __restrict__ starts, int32_t* __restrict__ pairs) {
-  const int mu = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mu >= nb) return;
+  const int mu = blockIdx.x * kPartRows + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (mu >= nb) return;  // whole waves
   int32_t pos[kMaxParts];
-  for (int s = 0; s < nparts; ++s) pos[s] = starts[(int64_t)s * nb + mu];
+#pragma unroll
+  for (int s = 0; s < kMaxParts; ++s) pos[s] = s < nparts ? starts[(int64_t)s * nb + mu] : 0;
+  const uint64_t below = __lanemask_lt();
   const int64_t p0 = pair_row_start(nb, mu);
-  for (int nu = mu; nu < nb; ++nu) {
+  for (int nu0 = mu; nu0 < nb; nu0 += 64) {
+    const int nu = nu0 + lane;
     const int64_t p = p0 + (nu - mu);
-    const int s = part_of(sup[p], boxes, nparts);
-    pairs[pos[s]++] = (int32_t)p;
+    const int sl = nu < nb ? part_of(sup[p], boxes, nparts) : kMaxParts;
+    int32_t slot = 0;
+#pragma unroll
+    for (int s = 0; s < kMaxParts; ++s) {
+      if (s < nparts) {
+        const uint64_t m = __ballot(sl == s);
+        if (sl == s) slot = pos[s] + __popcll(m & below);
+        pos[s] += __popcll(m);
+      }
+    }
+    if (sl < kMaxParts) pairs[slot] = (int32_t)p;
   }
 }
 
@@ -187,10 +219,11 @@ hipError_t launch_partition(const DevBasis& bs, double c, int nparts, const Part
   hipError_t e = hipcub::DeviceRadixSort::SortKeys(w.temp, temp, w.sup, w.sorted, (int)npair, 0, 64, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(box_kernel, dim3(1), dim3(64), 0, s, w.sorted, npair, nparts, w.boxes);
-  hipLaunchKernelGGL(part_count_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, w.sup, w.boxes, nparts, w.counts);
+  hipLaunchKernelGGL(part_count_kernel, dim3(nblk(nb, kPartRows)), dim3(64 * kPartRows), 0, s, nb, w.sup, w.boxes,
+                     nparts, w.counts);
   hipLaunchKernelGGL(part_scan_kernel, dim3(1), dim3(1024), 0, s, nb, nparts, w.counts, w.totals);
-  hipLaunchKernelGGL(part_write_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, w.sup, w.boxes, nparts, w.counts,
-                     pairs);
+  hipLaunchKernelGGL(part_write_kernel, dim3(nblk(nb, kPartRows)), dim3(64 * kPartRows), 0, s, nb, w.sup, w.boxes,
+                     nparts, w.counts, pairs);
   return hipGetLastError();
 }
 
