@@ -78,10 +78,9 @@ struct JF32 {
 // output tiles of 16 x 16 (n padded to 16*NT with zeros).
 // MT: the element type the moments are read in (the FP32 form reads an FP32
 // copy, half the bytes of the staging loads that bound it).
-template <class Op, int NT, int A0W, class MT = double>
-__global__ void __launch_bounds__(512, 1)
-rho_mfma_kernel(const MT* __restrict__ M, const double* __restrict__ Dt, int n, int64_t npair,
-                int64_t chunk, double* __restrict__ part) {
+template <class Op, int NT, int A0W, class MT>
+__device__ __forceinline__ void rho_mfma_body(const MT* __restrict__ M, const double* __restrict__ Dt, int n,
+                                              int64_t npair, int64_t chunk, double* __restrict__ part) {
   constexpr int NP = 16 * NT;                  // padded extent of a1 and a2
   constexpr int A0G = 8 * A0W;                 // a0 per work group
   constexpr int ROWS = A0G + 2 * NP;           // staged rows: c (A0G), m1 (NP), m2 (NP)
@@ -98,10 +97,6 @@ rho_mfma_kernel(const MT* __restrict__ M, const double* __restrict__ Dt, int n, 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
   const int a0base = blockIdx.x * A0G;
-  // batched densities (several orbitals in one launch): density z, its
-  // partial grids after those of densities 0 .. z-1
-  Dt += (int64_t)blockIdx.z * npair;
-  part += (int64_t)blockIdx.z * gridDim.y * n * n * n;
   const int64_t q0 = (int64_t)blockIdx.y * chunk;
   const int64_t q1 = (q0 + chunk < npair) ? q0 + chunk : npair;
   const MT* M0 = M;
@@ -222,6 +217,38 @@ rho_mfma_kernel(const MT* __restrict__ M, const double* __restrict__ Dt, int n, 
           if (a1 < n && a2 < n) out[a1 * n + a2] = v;
         }
   }
+}
+
+template <class Op, int NT, int A0W, class MT = double>
+__global__ void __launch_bounds__(512, 1)
+rho_mfma_kernel(const MT* __restrict__ M, const double* __restrict__ Dt, int n, int64_t npair,
+                int64_t chunk, double* __restrict__ part) {
+  // batched densities (several orbitals in one launch): density z, its
+  // partial grids after those of densities 0 .. z-1
+  rho_mfma_body<Op, NT, A0W, MT>(M, Dt + (int64_t)blockIdx.z * npair, n, npair, chunk,
+                                 part + (int64_t)blockIdx.z * gridDim.y * n * n * n);
+}
+
+// Pair lists cut into consecutive spans (the partitions of the adaptive
+// boxes): span z holds pairs off[z] .. off[z+1] of the list, its moments the
+// block M + 3 n off[z] (each span's own pair count as the stride); blk[z] is
+// the first work group of span z in a launch that covers all spans.
+struct Spans {
+  int64_t off[kMaxParts + 1];
+  int64_t blk[kMaxParts + 1];
+};
+
+// rho of every span in one launch: grid (ceil(n / (8*A0W)), nchunk, nspan),
+// span z's pairs cut into nchunk chunks, its partial grids after those of
+// spans 0 .. z-1.  An empty span writes zero partial grids.
+template <class Op, int NT, int A0W, class MT>
+__global__ void __launch_bounds__(512, 1)
+rho_spans_kernel(const MT* __restrict__ M, const double* __restrict__ Dt, int n, Spans sp, double* __restrict__ part) {
+  const int z = blockIdx.z;
+  const int64_t cnt = sp.off[z + 1] - sp.off[z];
+  const int64_t chunk = (cnt + gridDim.y - 1) / gridDim.y;
+  rho_mfma_body<Op, NT, A0W, MT>(M + 3 * (int64_t)n * sp.off[z], Dt + sp.off[z], n, cnt, chunk,
+                                 part + (int64_t)z * gridDim.y * n * n * n);
 }
 
 // ---------------------------------------------------------------------------
@@ -762,9 +789,8 @@ phi_kernel(const double* __restrict__ P, const double* __restrict__ w, int nq, i
 // MFMAs); X = Phi(a0) m_2 comes out of the matrix cores one 16-row block of
 // a1 at a time and is contracted at once with m_1 and m_0.
 template <class Op, int NT>
-__global__ void __launch_bounds__(512, 1)
-jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int n, int64_t npair,
-               double* __restrict__ Jp) {
+__device__ __forceinline__ void jp_mfma_body(const double* __restrict__ M, const double* __restrict__ Phi, int n,
+                                             int64_t npair, double* __restrict__ Jp, int64_t blk) {
   constexpr int NP = 16 * NT, NK = NP / 4, PT = 2;
   constexpr int PS = NP + 1;                        // LDS row stride (doubles)
   constexpr int SLAB = NP * NP;                     // padded slab values
@@ -784,7 +810,7 @@ jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int
   bool pok[PT];
 #pragma unroll
   for (int t = 0; t < PT; ++t) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + wave * 32 + 16 * t + r16;
+    const int64_t p = blk * 256 + wave * 32 + 16 * t + r16;
     pok[t] = p < npair;
     pc[t] = pok[t] ? p : 0;
   }
@@ -863,6 +889,26 @@ jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int
     v += __shfl_xor(v, 32);
     if (kg == 0 && pok[t]) Jp[pc[t]] = v;
   }
+}
+
+template <class Op, int NT>
+__global__ void __launch_bounds__(512, 1)
+jp_mfma_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int n, int64_t npair,
+               double* __restrict__ Jp) {
+  jp_mfma_body<Op, NT>(M, Phi, n, npair, Jp, blockIdx.x);
+}
+
+// J_p of every span in one launch: work groups blk[z] .. blk[z+1] take the
+// pairs of span z (256 each) against its own Phi (Phi + z n^3).
+template <class Op, int NT>
+__global__ void __launch_bounds__(512, 1)
+jp_spans_kernel(const double* __restrict__ M, const double* __restrict__ Phi, int n, int nspan, Spans sp,
+                double* __restrict__ Jp) {
+  int z = 0;
+  while (z + 1 < nspan && (int64_t)blockIdx.x >= sp.blk[z + 1]) ++z;
+  const int64_t o = sp.off[z];
+  jp_mfma_body<Op, NT>(M + 3 * (int64_t)n * o, Phi + (int64_t)z * n * n * n, n, sp.off[z + 1] - o, Jp + o,
+                       (int64_t)blockIdx.x - sp.blk[z]);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1110,6 +1156,35 @@ repeat_weights_kernel(const double* __restrict__ w, int nq, int reps, double sca
 // (the slab and mode-0 passes of each partition pair write their node
 // products side by side, one weighted sum over the (s', k) blocks follows),
 // J_p for the pairs of s, unpacked into J.
+//
+// One box runs the plain path's kernels (the same bits as tai_apply_J).
+// More boxes: rho of all partitions in one launch (the single list's chunk
+// count shared out among them), the mode products of all box pairs at once
+// on the matrix cores with 2/sqrt(pi) folded into the repeated weights, and
+// J_p of all partitions in one launch; the split-BF16 contractions keep a
+// launch per partition.
+namespace {
+template <class Op, int A0W, class MT>
+void launch_rho_spans(const MT* M, int n, const Spans& sp, int nspan, int nchunk, const double* Dt, double* part,
+                      hipStream_t s) {
+  const dim3 rg((n + 8 * A0W - 1) / (8 * A0W), nchunk, nspan);
+  if (n <= 16) hipLaunchKernelGGL((rho_spans_kernel<Op, 1, A0W, MT>), rg, dim3(512), 0, s, M, Dt, n, sp, part);
+  else if (n <= 32) hipLaunchKernelGGL((rho_spans_kernel<Op, 2, A0W, MT>), rg, dim3(512), 0, s, M, Dt, n, sp, part);
+  else if (n <= 48) hipLaunchKernelGGL((rho_spans_kernel<Op, 3, A0W, MT>), rg, dim3(512), 0, s, M, Dt, n, sp, part);
+  else hipLaunchKernelGGL((rho_spans_kernel<Op, 4, 1, MT>), rg, dim3(512), 0, s, M, Dt, n, sp, part);
+}
+template <class Op>
+void launch_jp_spans(const double* M, int n, const Spans& sp, int nspan, const double* Phi, double* Jp,
+                     hipStream_t s) {
+  const unsigned jb = (unsigned)sp.blk[nspan];
+  if (jb == 0) return;
+  if (n <= 16) hipLaunchKernelGGL((jp_spans_kernel<Op, 1>), dim3(jb), dim3(512), 0, s, M, Phi, n, nspan, sp, Jp);
+  else if (n <= 32) hipLaunchKernelGGL((jp_spans_kernel<Op, 2>), dim3(jb), dim3(512), 0, s, M, Phi, n, nspan, sp, Jp);
+  else if (n <= 48) hipLaunchKernelGGL((jp_spans_kernel<Op, 3>), dim3(jb), dim3(512), 0, s, M, Phi, n, nspan, sp, Jp);
+  else hipLaunchKernelGGL((jp_spans_kernel<Op, 4>), dim3(jb), dim3(512), 0, s, M, Phi, n, nspan, sp, Jp);
+}
+}  // namespace
+
 hipError_t launch_apply_j_parts(int prec, const double* M, int nb, const int32_t* pairs, const int64_t* offs,
                                 int nparts, int n, int nq, const double* w, const double* Kx, const double* D,
                                 double* J, const JWork& wk, double* rho_all, double* T2_all, double* Phi_all,
@@ -1118,56 +1193,76 @@ hipError_t launch_apply_j_parts(int prec, const double* M, int nb, const int32_t
   const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
   hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(total, 256)), dim3(256), 0, s, D, nb, total, pairs, wk.Dt);
   convert_moments(prec, M, n, (int)total, wk, s);
-  // one box: the plain path's kernels (the same bits as tai_apply_J); more
-  // boxes: the mode products of all box pairs at once on the matrix cores,
-  // with 2/sqrt(pi) folded into the repeated weights
   const bool one = nparts == 1;
   hipLaunchKernelGGL(repeat_weights_kernel, dim3(nblk((int64_t)nq * nparts, 256)), dim3(256), 0, s, w, nq, nparts,
                      one ? 1.0 : kTwoOverSqrtPi, wrep);
-  for (int p = 0; p < nparts; ++p) {
-    const int64_t cnt = offs[p + 1] - offs[p];
-    double* rho_p = rho_all + p * n3;
-    if (cnt == 0) {
-      hipLaunchKernelGGL(zero_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, rho_p, n3);
-      continue;
+  Spans sp{};
+  for (int p = 0; p <= nparts; ++p) {
+    sp.off[p] = offs[p];
+    sp.blk[p] = p == 0 ? 0 : sp.blk[p - 1] + nblk(offs[p] - offs[p - 1], 256);
+  }
+  // chunks per partition: the single list's count shared out, so that the
+  // partial grids of all partitions fit where the list's would
+  const int pchunk = wk.nchunk / nparts;
+  if (!one && !rho_split(prec) && pchunk >= 1) {
+    if (prec == kFP32 || split_j(prec))
+      launch_rho_spans<JF32, 1>(static_cast<const float*>(wk.M32), n, sp, nparts, pchunk, wk.Dt, wk.rho_part, s);
+    else if (n <= 48) launch_rho_spans<JF64, 2>(M, n, sp, nparts, pchunk, wk.Dt, wk.rho_part, s);
+    else launch_rho_spans<JF64, 1>(M, n, sp, nparts, pchunk, wk.Dt, wk.rho_part, s);
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256), nparts), dim3(256), 0, s, wk.rho_part, pchunk, n3,
+                       rho_all);
+  } else {
+    for (int p = 0; p < nparts; ++p) {
+      const int64_t cnt = offs[p + 1] - offs[p];
+      double* rho_p = rho_all + p * n3;
+      if (cnt == 0) {
+        hipLaunchKernelGGL(zero_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, rho_p, n3);
+        continue;
+      }
+      JWork wp = wk;
+      wp.Dt = wk.Dt + offs[p];
+      const double* Mp = M + 3 * (int64_t)n * offs[p];
+      if (rho_split(prec)) launch_rho16(prec, wk.M32 + 3 * (int64_t)n * offs[p], n, (int)cnt, wp, s);
+      else if (prec == kFP32 || split_j(prec))
+        launch_pair_contraction_rho<JF32, 1>(static_cast<const float*>(wk.M32 + 3 * (int64_t)n * offs[p]), n,
+                                             (int)cnt, wp, s);
+      else if (n <= 48) launch_pair_contraction_rho<JF64, 2>(Mp, n, (int)cnt, wp, s);
+      else launch_pair_contraction_rho<JF64, 1>(Mp, n, (int)cnt, wp, s);
+      hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, wk.rho_part, wk.nchunk, n3, rho_p);
     }
-    JWork wp = wk;
-    wp.Dt = wk.Dt + offs[p];
-    const double* Mp = M + 3 * (int64_t)n * offs[p];
-    if (rho_split(prec)) launch_rho16(prec, wk.M32 + 3 * (int64_t)n * offs[p], n, (int)cnt, wp, s);
-    else if (prec == kFP32 || split_j(prec))
-      launch_pair_contraction_rho<JF32, 1>(static_cast<const float*>(wk.M32 + 3 * (int64_t)n * offs[p]), n, (int)cnt,
-                                           wp, s);
-    else if (n <= 48) launch_pair_contraction_rho<JF64, 2>(Mp, n, (int)cnt, wp, s);
-    else launch_pair_contraction_rho<JF64, 1>(Mp, n, (int)cnt, wp, s);
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, wk.rho_part, wk.nchunk, n3, rho_p);
   }
   if (!one) {
     // T1 of box pair (p, q) = rho_q through the tables K^(p,q), at
-    // T2_all[(p nparts + q) nq]; Phi_p sums its nparts nq node blocks
+    // T2_all[(p nparts + q) nq]; Phi_p sums its nparts nq node blocks (the
+    // partial grids of rho are free again and hold the node runs' sums)
     const hipError_t e = launch_mode_products(rho_all, (int64_t)nparts * nparts, nparts, Kx, (int64_t)nq * n2, wrep,
                                               n, nq, T2_all, nparts, (int64_t)nparts * nq * n2, nparts * nq, Phi_all,
-                                              s);
+                                              wk.rho_part, (int64_t)wk.nchunk * n3, s);
     if (e != hipSuccess) return e;
+    if (!split_j(prec)) {
+      if (prec == kFP32) launch_jp_spans<JF32>(M, n, sp, nparts, Phi_all, wk.Jp, s);
+      else launch_jp_spans<JF64>(M, n, sp, nparts, Phi_all, wk.Jp, s);
+      hipLaunchKernelGGL(unpack_kernel, dim3(nblk(total, 256)), dim3(256), 0, s, wk.Jp, nb, total, pairs, J);
+      return hipGetLastError();
+    }
   }
   for (int p = 0; p < nparts; ++p) {
     const int64_t cnt = offs[p + 1] - offs[p];
     if (cnt == 0) continue;
-    for (int q = 0; q < nparts && one; ++q) {
-      const double* Kpq = Kx + ((int64_t)p * nparts + q) * nq * n2;
-      double* T2q = T2_all + (int64_t)q * nq * n3;
-      const double* rho_q = rho_all + q * n3;
-      if (n <= 16) hipLaunchKernelGGL(slab_modes_kernel<16>, dim3(n, nq), dim3(256), 0, s, Kpq, rho_q, n, wk.T1);
-      else if (n <= 32) hipLaunchKernelGGL(slab_modes_kernel<32>, dim3(n, nq), dim3(256), 0, s, Kpq, rho_q, n, wk.T1);
-      else if (n <= 48) hipLaunchKernelGGL(slab_modes_kernel<48>, dim3(n, nq), dim3(256), 0, s, Kpq, rho_q, n, wk.T1);
-      else hipLaunchKernelGGL(slab_modes_kernel<64>, dim3(n, nq), dim3(256), 0, s, Kpq, rho_q, n, wk.T1);
+    if (one) {
+      double* T2q = T2_all;
+      const double* rho_q = rho_all;
+      if (n <= 16) hipLaunchKernelGGL(slab_modes_kernel<16>, dim3(n, nq), dim3(256), 0, s, Kx, rho_q, n, wk.T1);
+      else if (n <= 32) hipLaunchKernelGGL(slab_modes_kernel<32>, dim3(n, nq), dim3(256), 0, s, Kx, rho_q, n, wk.T1);
+      else if (n <= 48) hipLaunchKernelGGL(slab_modes_kernel<48>, dim3(n, nq), dim3(256), 0, s, Kx, rho_q, n, wk.T1);
+      else hipLaunchKernelGGL(slab_modes_kernel<64>, dim3(n, nq), dim3(256), 0, s, Kx, rho_q, n, wk.T1);
       const dim3 mg(nblk(n2, 256), nq);
-      if (n <= 16) hipLaunchKernelGGL(mode0_kernel<16>, mg, dim3(256), 0, s, Kpq, wk.T1, n, T2q);
-      else if (n <= 32) hipLaunchKernelGGL(mode0_kernel<32>, mg, dim3(256), 0, s, Kpq, wk.T1, n, T2q);
-      else if (n <= 48) hipLaunchKernelGGL(mode0_kernel<48>, mg, dim3(256), 0, s, Kpq, wk.T1, n, T2q);
-      else hipLaunchKernelGGL(mode0_kernel<64>, mg, dim3(256), 0, s, Kpq, wk.T1, n, T2q);
+      if (n <= 16) hipLaunchKernelGGL(mode0_kernel<16>, mg, dim3(256), 0, s, Kx, wk.T1, n, T2q);
+      else if (n <= 32) hipLaunchKernelGGL(mode0_kernel<32>, mg, dim3(256), 0, s, Kx, wk.T1, n, T2q);
+      else if (n <= 48) hipLaunchKernelGGL(mode0_kernel<48>, mg, dim3(256), 0, s, Kx, wk.T1, n, T2q);
+      else hipLaunchKernelGGL(mode0_kernel<64>, mg, dim3(256), 0, s, Kx, wk.T1, n, T2q);
+      hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, T2_all, wrep, nq, n3, wk.Phi);
     }
-    if (one) hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, T2_all, wrep, nq, n3, wk.Phi);
     JWork wp = wk;
     wp.Jp = wk.Jp + offs[p];
     wp.Phi = one ? wk.Phi : Phi_all + (int64_t)p * n3;
@@ -1253,8 +1348,9 @@ hipError_t launch_coulomb_mo(int prec, const double* M, int nb, int npair, const
     hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256), ob), dim3(256), 0, s, part, nc, n3, Rb);
     // the block's mode products on the matrix cores (Phi without 2/sqrt(pi),
     // which the dot products apply)
+    // (the partial grids of rho are free again and hold the node runs' sums)
     const hipError_t e = launch_mode_products(Rb, ob, ob, tb.K, 0, tb.w, n, nq, T1, ob, 0, nq,
-                                              F + (int64_t)i0 * n3, s);
+                                              F + (int64_t)i0 * n3, part, (int64_t)ob * nc * n3, s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(mo_dot_kernel, dim3(norb, norb), dim3(256), 0, s, R, F, n3, norb, kTwoOverSqrtPi, Jmo);

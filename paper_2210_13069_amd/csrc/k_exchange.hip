@@ -209,13 +209,14 @@ exch_x_kernel(const double* __restrict__ M, int64_t npair, int n, int nb, const 
   }
 }
 
-// Slab products of a chunk of tensors: grid (ceil(Tc n / SB)), 256 threads.
-// The work group takes SB slabs (t, a0) of consecutive index s = t n + a0,
-// keeps them in LDS (zero padded to NP x NP) and for every node k forms
-// U = K_k X(a0) and S = U K_k^T on the FP64 matrix cores, K_k staged in LDS,
-// writing S to T1[t][k][a0][a1 n + a2].  Tensor t reads X[t % xmod] and the
-// tables K + t kstride (kstride 0: one table set; with kstride > 0 a work
-// group holds one slab, SB = 1).
+// Slab products of a chunk of tensors: grid (ceil(Tc n / SB), KC), 256
+// threads.  The work group takes SB slabs (t, a0) of consecutive index
+// s = t n + a0, keeps them in LDS (zero padded to NP x NP) and for every node
+// k of its share (grid y splits the nodes into KC equal runs, so that few
+// tensors still fill the device) forms U = K_k X(a0) and S = U K_k^T on the
+// FP64 matrix cores, K_k staged in LDS, writing S to T1[t][k][a0][a1 n + a2].
+// Tensor t reads X[t % xmod] and the tables K + t kstride (kstride 0: one
+// table set; with kstride > 0 a work group holds one slab, SB = 1).
 template <int NT, int SB>
 __global__ void __launch_bounds__(256)
 exch_slab_kernel(const double* __restrict__ X, const double* __restrict__ K, int n, int nq, int64_t nslab,
@@ -242,7 +243,9 @@ exch_slab_kernel(const double* __restrict__ X, const double* __restrict__ K, int
     Xs[(sb * NP + a1) * PS + a2] = v;
   }
   const double* Kt = K + (s0 / n) * kstride;
-  for (int k = 0; k < nq; ++k) {
+  const int kper = (nq + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int k0 = (int)blockIdx.y * kper, k1 = min(nq, k0 + kper);
+  for (int k = k0; k < k1; ++k) {
     __syncthreads();  // previous node's Ks and Us reads are done
     const double* Kk = Kt + (int64_t)k * n2;
     for (int e = threadIdx.x; e < NP * NP; e += 256) {
@@ -287,10 +290,11 @@ exch_slab_kernel(const double* __restrict__ X, const double* __restrict__ K, int
 }
 
 // Phi_t(i0, c) = sum_k w_k sum_a K_k(i0, a) T1[t][k][a][c], c = (a1, a2): grid
-// (ceil(n^2 / 64), Tc), 256 threads; wave w owns the 16 columns
+// (ceil(n^2 / 64), Tc, G), 256 threads; wave w owns the 16 columns
 // c0 + 16 w .. + 16 and all NT tiles of i0.  Per node, w_k K_k is staged in
 // LDS; the T1 fragments stream from memory once.  Tensor t's tables start at
-// K + t kstride.
+// K + t kstride.  With G > 1 the nodes are split into G equal runs and run g
+// writes its partial sums to the g-th block of Tc tensors at Phi.
 template <int NT>
 __global__ void __launch_bounds__(256)
 exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, const double* __restrict__ w, int n,
@@ -308,7 +312,9 @@ exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, c
   v4d acc[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int k = 0; k < nq; ++k) {
+  const int kper = (nq + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int k0 = (int)blockIdx.z * kper, k1 = min(nq, k0 + kper);
+  for (int k = k0; k < k1; ++k) {
     __syncthreads();
     const double wk = w[k];
     const double* Kk = K + t * kstride + (int64_t)k * n2;
@@ -328,7 +334,7 @@ exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, c
     }
   }
   if (!cok) return;
-  double* out = Phi + t * n * n2;
+  double* out = Phi + ((int64_t)blockIdx.z * gridDim.y + t) * n * n2;
 #pragma unroll
   for (int i = 0; i < NT; ++i)
 #pragma unroll
@@ -405,6 +411,16 @@ exch_dot_kernel(const double* __restrict__ X, const double* __restrict__ Phi, in
       }
 }
 
+// out[i] = sum_g part[g][i], runs in order
+__global__ void __launch_bounds__(256)
+sum_runs_kernel(const double* __restrict__ part, int nrun, int64_t len, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double s = 0.0;
+  for (int g = 0; g < nrun; ++g) s += part[(int64_t)g * len + i];
+  out[i] = s;
+}
+
 // K(mu, nu) = 2 (2/sqrt(pi)) sum_s part[s][mu][nu], slices in order.
 __global__ void __launch_bounds__(256)
 exch_dot_sum_kernel(const double* __restrict__ part, int nsplit, int64_t nn, double* __restrict__ Kx) {
@@ -432,36 +448,57 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // SB slabs per work group: LDS (2 SB + 1) NP (NP + 1) doubles, 76 KB at
 // n <= 32 (SB 4), 94 KB at n <= 48 (SB 2), 100 KB at n <= 64 (SB 1)
+// kc: node runs (grid y), 1 unless few tensors leave the device idle
 template <int NT, int SB>
 void launch_slab(const double* X, const double* K, int n, int nq, int64_t nslab, double* T1, hipStream_t s,
-                 int64_t xmod = INT64_MAX, int64_t kstride = 0) {
-  hipLaunchKernelGGL((exch_slab_kernel<NT, SB>), dim3(nblk(nslab, SB)), dim3(256), 0, s, X, K, n, nq, nslab, T1,
-                     xmod, kstride);
+                 int64_t xmod = INT64_MAX, int64_t kstride = 0, int kc = 1) {
+  hipLaunchKernelGGL((exch_slab_kernel<NT, SB>), dim3(nblk(nslab, SB), kc), dim3(256), 0, s, X, K, n, nq, nslab,
+                     T1, xmod, kstride);
+}
+
+// Work groups a launch of the mode products should hold at least: several
+// per compute unit, so that the latency of the staged loads is hidden.
+constexpr int64_t kModeGroups = 2048;
+
+// node runs for `groups` work groups over `nq` nodes: enough runs to reach
+// kModeGroups, at most one node per run
+int node_runs(int64_t groups, int nq) {
+  const int64_t r = (kModeGroups + groups - 1) / groups;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(r, nq));
 }
 
 }  // namespace
 
 hipError_t launch_mode_products(const double* X, int64_t T, int64_t xmod, const double* K, int64_t kstride,
                                 const double* w, int n, int nq, double* T1, int64_t T0, int64_t kstride0,
-                                int nq0, double* Phi, hipStream_t s) {
+                                int nq0, double* Phi, double* part, int64_t part_len, hipStream_t s) {
   const int NT = (n + 15) / 16;
   const int64_t nslab = T * n, n2 = (int64_t)n * n;
   if (kstride != 0) {
-    if (NT == 1) launch_slab<1, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride);
-    else if (NT == 2) launch_slab<2, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride);
-    else if (NT == 3) launch_slab<3, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride);
-    else launch_slab<4, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride);
+    const int kc = node_runs(nslab, nq);
+    if (NT == 1) launch_slab<1, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride, kc);
+    else if (NT == 2) launch_slab<2, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride, kc);
+    else if (NT == 3) launch_slab<3, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride, kc);
+    else launch_slab<4, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride, kc);
   } else {
-    if (NT == 1) launch_slab<1, 4>(X, K, n, nq, nslab, T1, s, xmod, 0);
-    else if (NT == 2) launch_slab<2, 4>(X, K, n, nq, nslab, T1, s, xmod, 0);
-    else if (NT == 3) launch_slab<3, 2>(X, K, n, nq, nslab, T1, s, xmod, 0);
-    else launch_slab<4, 1>(X, K, n, nq, nslab, T1, s, xmod, 0);
+    if (NT == 1) launch_slab<1, 4>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nblk(nslab, 4), nq));
+    else if (NT == 2) launch_slab<2, 4>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nblk(nslab, 4), nq));
+    else if (NT == 3) launch_slab<3, 2>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nblk(nslab, 2), nq));
+    else launch_slab<4, 1>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nslab, nq));
   }
-  const dim3 mg(nblk(n2, 64), (unsigned)T0);
-  if (NT == 1) hipLaunchKernelGGL((exch_mode0_kernel<1>), mg, dim3(256), 0, s, T1, K, w, n, nq0, Phi, kstride0);
-  else if (NT == 2) hipLaunchKernelGGL((exch_mode0_kernel<2>), mg, dim3(256), 0, s, T1, K, w, n, nq0, Phi, kstride0);
-  else if (NT == 3) hipLaunchKernelGGL((exch_mode0_kernel<3>), mg, dim3(256), 0, s, T1, K, w, n, nq0, Phi, kstride0);
-  else hipLaunchKernelGGL((exch_mode0_kernel<4>), mg, dim3(256), 0, s, T1, K, w, n, nq0, Phi, kstride0);
+  // mode 0: with few output tensors the node sum is split into runs whose
+  // partial tensors (in part, part_len doubles) are added in run order
+  const int64_t len = T0 * n * n2;
+  int g = node_runs((int64_t)nblk(n2, 64) * T0, nq0);
+  if (part == nullptr || part_len < 2 * len) g = 1;
+  else g = (int)std::min<int64_t>(g, part_len / len);
+  double* out = g > 1 ? part : Phi;
+  const dim3 mg(nblk(n2, 64), (unsigned)T0, (unsigned)g);
+  if (NT == 1) hipLaunchKernelGGL((exch_mode0_kernel<1>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
+  else if (NT == 2) hipLaunchKernelGGL((exch_mode0_kernel<2>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
+  else if (NT == 3) hipLaunchKernelGGL((exch_mode0_kernel<3>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
+  else hipLaunchKernelGGL((exch_mode0_kernel<4>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
+  if (g > 1) hipLaunchKernelGGL(sum_runs_kernel, dim3(nblk(len, 256)), dim3(256), 0, s, part, g, len, Phi);
   return hipGetLastError();
 }
 

@@ -383,10 +383,12 @@ ExchangeWork exchange_work_plan(int n, int nq, int nb, int norb, bool listed, in
 // slab products T1[t][k][a0] = K_k X_t(a0) K_k^T for T tensors, tensor t
 // reading X[t % xmod] and the tables K + t kstride; then for T0 groups of
 // consecutive T1 blocks, Phi_g = sum_k w_k K_k x_0 (group g's nq0 node
-// blocks, tables K + g kstride0), without the factor 2/sqrt(pi).
+// blocks, tables K + g kstride0), without the factor 2/sqrt(pi).  part
+// (part_len doubles, may be null) lets a launch with few groups split the
+// node sum into runs whose partial Phi are then added in order.
 hipError_t launch_mode_products(const double* X, int64_t T, int64_t xmod, const double* K, int64_t kstride,
                                 const double* w, int n, int nq, double* T1, int64_t T0, int64_t kstride0,
-                                int nq0, double* Phi, hipStream_t s);
+                                int nq0, double* Phi, double* part, int64_t part_len, hipStream_t s);
 hipError_t launch_exchange(int prec, const double* M, int nb, int64_t npair, const int32_t* pairs, int n, int nq,
                            const NodeTables& tb, const double* Q, int norb, void* work, const ExchangeWork& p,
                            double* Kx, hipStream_t s);

@@ -98,3 +98,30 @@ def test_empty_partitions(tai):
     p1, c1, b1 = tai.partition_pairs(b, 1e-12, 1)
     J1 = tai.apply_J_partitioned(tai.moments_partitioned(b, P, p1, c1, b1), D, p1, c1, b1, P)
     assert float((J3 - J1).abs().max() / J1.abs().max()) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_empty_middle_partition(tai, prec):
+    """Partition 1 emptied into partition 2 (whose box holds its supports):
+    three boxes with an empty one between two full ones, on a list long
+    enough that the rho and J_p launches cover all partitions at once; J
+    against the oracle's partition-wise grid route on the same partition."""
+    import torch
+    b, P = _small()
+    tau = 1e-16
+    part, boxes = _oracle_parts(b, tau, 3)
+    part = np.where(part == 1, 2, part)
+    counts = np.bincount(part, minlength=3).tolist()
+    assert counts[1] == 0 and counts[0] > 0 and counts[2] > 0
+    t, w = T.time_nodes(P.omega, P.nq)
+    D = I.random_density(np.random.default_rng(8), b)
+    pm = T.partition_moments(b.center, b.alpha, b.lxyz, part, boxes, P.n)
+    Jr = T.J_partitioned(pm, boxes, t, w, P.n, D)
+    order = np.concatenate([np.flatnonzero(part == s) for s in range(3)]).astype(np.int32)
+    pairs = torch.as_tensor(order, device="cuda")
+    Mg = tai.moments_partitioned(b, P, pairs, counts, boxes.tolist())
+    Jg = tai.apply_J_partitioned(Mg, torch.as_tensor(D, device=Mg.device), pairs, counts, boxes.tolist(), P,
+                                 prec=prec).cpu().numpy()
+    err = np.linalg.norm(Jg - Jr, 2) / np.linalg.norm(Jr, 2)
+    assert err <= J_TOL[prec], (prec, err)
+    np.testing.assert_array_equal(Jg, Jg.T)
