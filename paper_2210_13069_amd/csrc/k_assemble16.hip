@@ -9,7 +9,7 @@
 //   the operand, the Hadamard product and the FP32 accumulators fit in the
 //   256 architectural VGPRs (no AGPR round trips before each MFMA).
 // * The Y_{k,d} operand of one 32-column block is streamed per k through LDS
-//   with direct-to-LDS loads (global_load_lds_dwordx4), NBUF-buffered so the
+//   with direct-to-LDS buffer loads (buffer_load_dwordx4 ... lds), NBUF-buffered so the
 //   loads run NBUF-1 nodes ahead, and shared by the four waves.  Each 1 KB
 //   fragment holds the 16-byte MFMA operand of every lane in lane order, so
 //   the fragment reads are bank-conflict-free.  Each wave issues the same
@@ -37,6 +37,9 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 constexpr double kTwoOverSqrtPi = 1.1283791670955126;
+// fourth word of a raw buffer resource on gfx9 parts (32-bit data format,
+// no swizzle, no index stride)
+constexpr int kBufferWord3 = 0x00020000;
 // FP32 accumulation group of quadrature nodes: sixteen keep the FP32 part of
 // the error well below the split's own (F16X3 normwise 4e-8 at Nb = 400)
 // and flush the FP64 partial sums half as often as eight.
@@ -121,13 +124,18 @@ struct YLoads {
       off[i] = (uint32_t)(j * node_bytes + (((int64_t)d * prow + col0 + 16 * c + r16) * C::KC_ + 32 * ch + 8 * kg) * 2);
     }
   }
+  // Buffer loads (a resource built on the step's base pointer, the fixed
+  // offsets per lane): a load into LDS through the global segment would
+  // make the compiler count every later LDS read as possibly out of order,
+  // so each fragment read would wait for all of them (lgkmcnt(0)) instead of
+  // only the one the MFMAs need.
   __device__ void issue(const char* base, uint4* buf, int wave) const {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, 0x7fffffff, kBufferWord3);
 #pragma unroll
     for (int i = 0; i < C::LPW_HI; ++i) {
       const int f = wave + C::NW_ * i;
-      if (f < C::NFRAG)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(base + off[i]), (lds_ptr_t)(buf + f * 64),
-                                         16, 0, 0);
+      if (f < C::NFRAG) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)(buf + f * 64), 16, off[i], 0, 0, 0);
     }
   }
 };

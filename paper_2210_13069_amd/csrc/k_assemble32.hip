@@ -32,6 +32,16 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 constexpr double kTwoOverSqrtPi = 1.1283791670955126;
+
+// Raw buffer resource on a step's base pointer (fourth word: the gfx9 value,
+// 32-bit data format, no swizzle or index stride).  The FP64 kernel's Y
+// fragments go to LDS through buffer loads: a load into LDS through the
+// global segment makes the compiler treat every later LDS read as possibly
+// out of order and wait for all of them before each MFMA step (9% of the
+// FP64 kernel's time at Nb = 400).
+__device__ inline __amdgpu_buffer_rsrc_t y_rsrc(const char* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
 // FP32 accumulation group of quadrature nodes (as in the FP32 tile kernel)
 constexpr int kGroup32 = 8;
 constexpr int kQueues = kAsm16Queues;
@@ -128,6 +138,8 @@ __device__ inline void run_item32(const AsmMol& m, int rp, int cb0, int cb1, flo
   auto steps_of = [&](int node) { return (DEG && nkp) ? (nkp[node] + 3) / 4 : NCH; };
   int ib = 0, ik = 0;  // (block, node) of the next step to load
   auto issue_next = [&](float* buf) {
+    // (global-segment loads here: the buffer form, which helps the FP64
+    // kernel, measured 1.4% slower for this one)
     const char* base = Yb + ik * node_bytes + ib * block_bytes;
     const int nch = steps_of(ik);
 #pragma unroll
@@ -344,14 +356,13 @@ __device__ inline void run_item64(const AsmMol& m, int rp, int cb0, int cb1, uin
   auto steps_of = [&](int node) { return (DEG && nkp) ? (nkp[node] + 7) / 8 : NCH; };
   int ib = 0, ik = 0;
   auto issue_next = [&](uint4* buf) {
-    const char* base = Yb + ik * node_bytes + ib * block_bytes;
+    const __amdgpu_buffer_rsrc_t rs = y_rsrc(Yb + ik * node_bytes + ib * block_bytes);
     const int nch = steps_of(ik);
 #pragma unroll
     for (int i = 0; i < LPW; ++i) {
       const int f = wave + NW * i;
       if (f < NFRAG && f % NCH < nch)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(base + off[i]), (lds_ptr_t)(buf + f * 64), 16,
-                                         0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)(buf + f * 64), 16, off[i], 0, 0, 0);
     }
     if (++ik == nq) {
       ik = 0;

@@ -271,6 +271,12 @@ class Context:
     def assemble_B(self, M, npair, params, B, ldb=None, stream=None):
         p = params if isinstance(params, tai_params) else make_params(params)
         ldb = npair if ldb is None else ldb
+        # the library cannot see the size of the caller's buffer: B holds
+        # npair rows of ldb entries, FP64 for TAI_FP64 and FP32 otherwise
+        esize = 8 if p.prec == FP64 else 4
+        if B.element_size() != esize or B.numel() < (int(npair) - 1) * int(ldb) + int(npair):
+            raise ValueError(f"B must hold npair x ldb {'FP64' if esize == 8 else 'FP32'} entries "
+                             f"(got {B.dtype}, {B.numel()} entries)")
         self.check(self.lib.tai_assemble_B(self.h, _ptr(M), int(npair), ctypes.byref(p), _ptr(B), int(ldb),
                                            _stream(stream)), "tai_assemble_B")
 

@@ -444,3 +444,19 @@ def test_ring_and_tile_kernels_agree(tai, n):
             else:
                 os.environ["TAI_TILE_ASSEMBLY"] = old
         assert _normwise(ring, tile) <= (1e-13 if prec == 0 else 1e-6), (n, prec)
+
+
+def test_binding_rejects_a_wrong_output_buffer(tai):
+    """The binding checks the output buffer before the call: an FP32 buffer
+    for the FP64 arithmetic (half the bytes B needs), or one too short, is
+    refused with ValueError and no kernel runs."""
+    import torch
+    b, P = I.sp16()
+    ctx = tai.Context(0)
+    Mg = tai.moments(b, P)
+    small = torch.empty((b.npair, b.npair), dtype=torch.float32, device=Mg.device)
+    with pytest.raises(ValueError):
+        ctx.assemble_B(Mg, b.npair, tai.make_params(P, tai.FP64), small)
+    short = torch.empty((b.npair - 1, b.npair), dtype=torch.float32, device=Mg.device)
+    with pytest.raises(ValueError):
+        ctx.assemble_B(Mg, b.npair, tai.make_params(P, tai.F16X3), short)
