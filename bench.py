@@ -158,7 +158,9 @@ def main():
     npair, n, nq = b.npair, P.n, P.nq
     ba = tai.BasisArrays(b)
     M = torch.empty((3, n, npair), dtype=torch.float64, device=dev)
-    B32 = torch.empty((npair, npair), dtype=torch.float32, device=dev)
+    # B rows start on 64-byte boundaries (row stride rounded up to 16 entries)
+    ldb = tai.aligned_ldb(npair)
+    B32 = torch.empty((npair, ldb), dtype=torch.float32, device=dev)
     rng = np.random.default_rng(11)
     sp = np.concatenate([rng.integers(0, npair, 240), [0, npair - 1]])
     sq = np.concatenate([rng.integers(0, npair, 240), [npair - 1, 0]])
@@ -169,13 +171,13 @@ def main():
         params = tai.make_params(Pw, prec)
         for _ in range(warmup):
             ctx.moments(ba, Pw, M)
-            ctx.assemble_B(M, npair, params, Bbuf)
+            ctx.assemble_B(M, npair, params, Bbuf, ldb)
         torch.cuda.synchronize()
         ctx.profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(steps):
             ctx.moments(ba, Pw, M)
-            ctx.assemble_B(M, npair, params, Bbuf)
+            ctx.assemble_B(M, npair, params, Bbuf, ldb)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         stages = {s: ctx.profile_read(s) for s in ("nodes", "moments", "compress", "pack", "project", "assemble")}
@@ -185,7 +187,10 @@ def main():
         return ms, stages, sample
 
     log(f"headline {args.prec}: Nb={b.nb} npair={npair} steps={K} warmup={W}")
-    ms_head, st_head, samp_head = run_steps(head, B32 if head != tai.FP64 else None, K, W)
+    Bhead = B32 if head != tai.FP64 else torch.empty((npair, ldb), dtype=torch.float64, device=dev)
+    ms_head, st_head, samp_head = run_steps(head, Bhead, K, W)
+    if head == tai.FP64:
+        del Bhead
     asm_ms = st_head["assemble"][0] / max(1, st_head["assemble"][1])
     entries = float(npair) * npair
     value = entries / (ms_head / 1e3)
@@ -209,7 +214,7 @@ def main():
     omega1 = None
 
     if not args.only_headline:
-        B64 = torch.empty((npair, npair), dtype=torch.float64, device=dev)
+        B64 = torch.empty((npair, ldb), dtype=torch.float64, device=dev)
         for name in ("fp64", "fp32", "bf16x6", "bf16x3"):
             if name == args.prec:
                 continue
@@ -825,7 +830,7 @@ def main():
         "config": {"workload": "spd400: Nb=400 (40 atoms in [-8,8]^3, s+p+d shells), 80200 pairs, "
                                "omega=0.3, nq=32, n=40, L=16; step = moments + full B (6.43e9 entries)",
                    "nb": b.nb, "npair": npair, "entries": entries, "omega": P.omega, "nq": nq, "n": n, "L": P.L,
-                   "parallelism": "single GPU"},
+                   "ldb": ldb, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "rel_error_vs_oracle": rel_error,

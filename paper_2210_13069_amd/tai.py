@@ -274,7 +274,7 @@ class Context:
         # the library cannot see the size of the caller's buffer: B holds
         # npair rows of ldb entries, FP64 for TAI_FP64 and FP32 otherwise
         esize = 8 if p.prec == FP64 else 4
-        if B.element_size() != esize or B.numel() < (int(npair) - 1) * int(ldb) + int(npair):
+        if B is not None and (B.element_size() != esize or B.numel() < (int(npair) - 1) * int(ldb) + int(npair)):
             raise ValueError(f"B must hold npair x ldb {'FP64' if esize == 8 else 'FP32'} entries "
                              f"(got {B.dtype}, {B.numel()} entries)")
         self.check(self.lib.tai_assemble_B(self.h, _ptr(M), int(npair), ctypes.byref(p), _ptr(B), int(ldb),
@@ -454,6 +454,13 @@ def moments(basis, params, coef=None, device=0):
     M = torch.empty((3, int(params.n), npair), dtype=torch.float64, device=torch.device("cuda", device))
     context(device).moments(ba, params, M)
     return M
+
+
+def aligned_ldb(npair):
+    """A row stride for B (>= npair, a multiple of 16 entries) that starts
+    every row on a 64-byte boundary, so that the assembly's 64-byte row
+    pieces each fill whole memory segments."""
+    return (int(npair) + 15) // 16 * 16
 
 
 def assemble_B(M, params, prec=FP64, ldb=None, out=None, device=0):

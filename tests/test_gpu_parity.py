@@ -264,7 +264,7 @@ def test_assemble_B_full_size_sampled(tai, omega):
     pt = torch.as_tensor(p, device=Mg.device)
     qt = torch.as_tensor(q, device=Mg.device)
     for prec in (4, 0):
-        B = tai.assemble_B(Mg, P, prec=prec)
+        B = tai.assemble_B(Mg, P, prec=prec, ldb=tai.aligned_ldb(b.npair))
         got = B[pt, qt].cpu().numpy().astype(np.float64)
         tol = 1e-10 if prec == 0 else 1e-6
         err = np.max(np.abs(got - ref)) / scale
