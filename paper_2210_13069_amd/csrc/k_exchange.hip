@@ -209,97 +209,162 @@ exch_x_kernel(const double* __restrict__ M, int64_t npair, int n, int nb, const 
   }
 }
 
+// Work-group barrier for LDS hand-offs only: waits for this wave's LDS
+// operations, not for its global stores (a __syncthreads would drain the
+// slab outputs already on their way to memory at every node).
+__device__ inline void lds_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// One 16 x 16 FP64 tile product per wave and step on the matrix cores, the
+// fragments of a wave's next tile read from LDS while the MFMAs of the
+// current one run.  Wave w takes tiles w, w + 4, ...; frag(t, st, a, b)
+// reads tile t's A and B fragments of inner step st, put(t, acc) stores its
+// result.
+template <int NK, int TILES, class Frag, class Put>
+__device__ inline void tile_products(int wave, Frag&& frag, Put&& put) {
+  constexpr int MAXIT = (TILES + 3) / 4;
+  double fa[2][NK], fb[2][NK];
+  if (wave < TILES) {
+#pragma unroll
+    for (int st = 0; st < NK; ++st) frag(wave, st, fa[0][st], fb[0][st]);
+  }
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    const int tt = wave + 4 * it;
+    if (tt + 4 < TILES) {
+#pragma unroll
+      for (int st = 0; st < NK; ++st) frag(tt + 4, st, fa[(it + 1) & 1][st], fb[(it + 1) & 1][st]);
+    }
+    if (tt < TILES) {
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < NK; ++st)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[it & 1][st], fb[it & 1][st], acc, 0, 0, 0);
+      put(tt, acc);
+    }
+  }
+}
+
 // Slab products of a chunk of tensors: grid (ceil(Tc n / SB), KC), 256
 // threads.  The work group takes SB slabs (t, a0) of consecutive index
 // s = t n + a0, keeps them in LDS (zero padded to NP x NP) and for every node
 // k of its share (grid y splits the nodes into KC equal runs, so that few
 // tensors still fill the device) forms U = K_k X(a0) and S = U K_k^T on the
 // FP64 matrix cores, K_k staged in LDS, writing S to T1[t][k][a0][a1 n + a2].
-// Tensor t reads X[t % xmod] and the tables K + t kstride (kstride 0: one
-// table set; with kstride > 0 a work group holds one slab, SB = 1).
+// The next node's K_k values are loaded into registers while the current
+// node's products run.  Tensor t reads X[t % xmod] and the tables
+// K + t kstride (kstride 0: one table set; with kstride > 0 a work group
+// holds one slab, SB = 1).
 template <int NT, int SB>
 __global__ void __launch_bounds__(256)
 exch_slab_kernel(const double* __restrict__ X, const double* __restrict__ K, int n, int nq, int64_t nslab,
                  double* __restrict__ T1, int64_t xmod, int64_t kstride) {
-  constexpr int NP = 16 * NT, PS = NP + 1;
+  constexpr int NP = 16 * NT, PS = NP + 1, NK = NP / 4;
   constexpr int TILES = SB * NT * NT;
+  constexpr int XPER = (SB * NP * NP + 255) / 256, KPER = (NP * NP + 255) / 256;
   __shared__ double Xs[SB * NP * PS];   // [SB][NP][PS]
   __shared__ double Us[SB * NP * PS];   // [SB][NP][PS]
   __shared__ double Ks[NP * PS];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
   const int64_t s0 = (int64_t)blockIdx.x * SB;
   const int64_t n2 = (int64_t)n * n;
-  for (int e = threadIdx.x; e < SB * NP * NP; e += 256) {
-    const int sb = e / (NP * NP), rem = e - sb * NP * NP;
-    const int a1 = rem / NP, a2 = rem - a1 * NP;
-    const int64_t sl = s0 + sb;
-    double v = 0.0;
-    if (sl < nslab && a1 < n && a2 < n) {
-      const int64_t t = sl / n, a0 = sl - t * n;
-      v = X[((t % xmod) * n + a0) * n2 + a1 * n + a2];
+  {
+    double xr[XPER];
+#pragma unroll
+    for (int i = 0; i < XPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int sb = e / (NP * NP), rem = e - sb * NP * NP;
+      const int a1 = rem / NP, a2 = rem - a1 * NP;
+      const int64_t sl = s0 + sb;
+      xr[i] = 0.0;
+      if (e < SB * NP * NP && sl < nslab && a1 < n && a2 < n) {
+        const int64_t t = sl / n, a0 = sl - t * n;
+        xr[i] = X[((t % xmod) * n + a0) * n2 + a1 * n + a2];
+      }
     }
-    Xs[(sb * NP + a1) * PS + a2] = v;
+#pragma unroll
+    for (int i = 0; i < XPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int sb = e / (NP * NP), rem = e - sb * NP * NP;
+      if (e < SB * NP * NP) Xs[(sb * NP + rem / NP) * PS + rem % NP] = xr[i];
+    }
   }
   const double* Kt = K + (s0 / n) * kstride;
   const int kper = (nq + (int)gridDim.y - 1) / (int)gridDim.y;
   const int k0 = (int)blockIdx.y * kper, k1 = min(nq, k0 + kper);
-  for (int k = k0; k < k1; ++k) {
-    __syncthreads();  // previous node's Ks and Us reads are done
+  double kr[KPER];
+  auto load_k = [&](int k) {
     const double* Kk = Kt + (int64_t)k * n2;
-    for (int e = threadIdx.x; e < NP * NP; e += 256) {
+#pragma unroll
+    for (int i = 0; i < KPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
       const int a = e / NP, b = e - a * NP;
-      Ks[a * PS + b] = (a < n && b < n) ? Kk[a * n + b] : 0.0;
+      kr[i] = (e < NP * NP && a < n && b < n) ? Kk[a * n + b] : 0.0;
     }
-    __syncthreads();
+  };
+  if (k0 < k1) load_k(k0);
+  for (int k = k0; k < k1; ++k) {
+    lds_barrier();  // the previous node's Ks and Us reads are done (and Xs written)
+#pragma unroll
+    for (int i = 0; i < KPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < NP * NP) Ks[(e / NP) * PS + e % NP] = kr[i];
+    }
+    if (k + 1 < k1) load_k(k + 1);
+    lds_barrier();
     // U_sb = K_k X_sb
-    for (int tt = wave; tt < TILES; tt += 4) {
-      const int sb = tt / (NT * NT), ij = tt - sb * NT * NT, i = ij / NT, jj = ij - i * NT;
-      const double* xs = Xs + sb * NP * PS;
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    tile_products<NK, TILES>(
+        wave,
+        [&](int tt, int st, double& a, double& b) {
+          const int sb = tt / (NT * NT), ij = tt - sb * NT * NT, i = ij / NT, jj = ij - i * NT;
+          a = Ks[(16 * i + r16) * PS + 4 * st + kg];
+          b = Xs[(sb * NP + 4 * st + kg) * PS + 16 * jj + r16];
+        },
+        [&](int tt, const v4d& acc) {
+          const int sb = tt / (NT * NT), ij = tt - sb * NT * NT, i = ij / NT, jj = ij - i * NT;
+          double* us = Us + sb * NP * PS;
 #pragma unroll
-      for (int st = 0; st < NP / 4; ++st)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ks[(16 * i + r16) * PS + 4 * st + kg],
-                                                   xs[(4 * st + kg) * PS + 16 * jj + r16], acc, 0, 0, 0);
-      double* us = Us + sb * NP * PS;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) us[(16 * i + kg + 4 * r) * PS + 16 * jj + r16] = acc[r];
-    }
-    __syncthreads();
+          for (int r = 0; r < 4; ++r) us[(16 * i + kg + 4 * r) * PS + 16 * jj + r16] = acc[r];
+        });
+    lds_barrier();
     // S_sb = U_sb K_k^T, straight to T1
-    for (int tt = wave; tt < TILES; tt += 4) {
-      const int sb = tt / (NT * NT), ij = tt - sb * NT * NT, i = ij / NT, jj = ij - i * NT;
-      const int64_t sl = s0 + sb;
-      if (sl >= nslab) continue;
-      const double* us = Us + sb * NP * PS;
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    tile_products<NK, TILES>(
+        wave,
+        [&](int tt, int st, double& a, double& b) {
+          const int sb = tt / (NT * NT), ij = tt - sb * NT * NT, i = ij / NT, jj = ij - i * NT;
+          a = Us[(sb * NP + 16 * i + r16) * PS + 4 * st + kg];
+          b = Ks[(16 * jj + r16) * PS + 4 * st + kg];
+        },
+        [&](int tt, const v4d& acc) {
+          const int sb = tt / (NT * NT), ij = tt - sb * NT * NT, i = ij / NT, jj = ij - i * NT;
+          const int64_t sl = s0 + sb;
+          if (sl >= nslab) return;
+          const int64_t t = sl / n, a0 = sl - t * n;
+          double* out = T1 + ((t * nq + k) * n + a0) * n2;
 #pragma unroll
-      for (int st = 0; st < NP / 4; ++st)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(us[(16 * i + r16) * PS + 4 * st + kg],
-                                                   Ks[(16 * jj + r16) * PS + 4 * st + kg], acc, 0, 0, 0);
-      const int64_t t = sl / n, a0 = sl - t * n;
-      double* out = T1 + ((t * nq + k) * n + a0) * n2;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a1 = 16 * i + kg + 4 * r, a2 = 16 * jj + r16;
-        if (a1 < n && a2 < n) out[a1 * n + a2] = acc[r];
-      }
-    }
+          for (int r = 0; r < 4; ++r) {
+            const int a1 = 16 * i + kg + 4 * r, a2 = 16 * jj + r16;
+            if (a1 < n && a2 < n) out[a1 * n + a2] = acc[r];
+          }
+        });
   }
 }
 
 // Phi_t(i0, c) = sum_k w_k sum_a K_k(i0, a) T1[t][k][a][c], c = (a1, a2): grid
 // (ceil(n^2 / 64), Tc, G), 256 threads; wave w owns the 16 columns
 // c0 + 16 w .. + 16 and all NT tiles of i0.  Per node, w_k K_k is staged in
-// LDS; the T1 fragments stream from memory once.  Tensor t's tables start at
-// K + t kstride.  With G > 1 the nodes are split into G equal runs and run g
-// writes its partial sums to the g-th block of Tc tensors at Phi.
+// LDS; the T1 fragments stream from memory once, and the next node's w_k K_k
+// and T1 fragments are loaded into registers while the current node's MFMAs
+// run.  Tensor t's tables start at K + t kstride.  With G > 1 the nodes are
+// split into G equal runs and run g writes its partial sums to the g-th
+// block of Tc tensors at Phi.
 template <int NT>
 __global__ void __launch_bounds__(256)
 exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, const double* __restrict__ w, int n,
                   int nq, double* __restrict__ Phi, int64_t kstride) {
-  constexpr int NP = 16 * NT, PS = NP + 1;
+  constexpr int NP = 16 * NT, PS = NP + 1, NK = NP / 4;
+  constexpr int KPER = (NP * NP + 255) / 256;
   __shared__ double Ws[NP * PS];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -309,29 +374,50 @@ exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, c
   const int64_t c = (int64_t)blockIdx.x * 64 + 16 * wave + r16;
   const bool cok = c < n2;
   const double* Tt = T1 + t * nq * n * n2;
+  const double* Kt = K + t * kstride;
+  const int kper = (nq + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int k0 = (int)blockIdx.z * kper, k1 = min(nq, k0 + kper);
   v4d acc[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int kper = (nq + (int)gridDim.z - 1) / (int)gridDim.z;
-  const int k0 = (int)blockIdx.z * kper, k1 = min(nq, k0 + kper);
-  for (int k = k0; k < k1; ++k) {
-    __syncthreads();
+  double kr[KPER], bv[2][NK];
+  auto load = [&](int k, double (&b)[NK]) {
     const double wk = w[k];
-    const double* Kk = K + t * kstride + (int64_t)k * n2;
-    for (int e = threadIdx.x; e < NP * NP; e += 256) {
-      const int a = e / NP, b = e - a * NP;
-      Ws[a * PS + b] = (a < n && b < n) ? wk * Kk[a * n + b] : 0.0;
+    const double* Kk = Kt + (int64_t)k * n2;
+#pragma unroll
+    for (int i = 0; i < KPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int a = e / NP, bb = e - a * NP;
+      kr[i] = (e < NP * NP && a < n && bb < n) ? wk * Kk[a * n + bb] : 0.0;
     }
-    __syncthreads();
     const double* Tk = Tt + (int64_t)k * n * n2;
-#pragma unroll 4
-    for (int st = 0; st < NP / 4; ++st) {
+#pragma unroll
+    for (int st = 0; st < NK; ++st) {
       const int a = 4 * st + kg;
-      const double bv = (cok && a < n) ? Tk[a * n2 + c] : 0.0;
+      b[st] = (cok && a < n) ? Tk[a * n2 + c] : 0.0;
+    }
+  };
+  auto node = [&](int k, double (&cur)[NK], double (&nxt)[NK]) {
+    lds_barrier();  // the previous node's Ws reads are done
+#pragma unroll
+    for (int i = 0; i < KPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < NP * NP) Ws[(e / NP) * PS + e % NP] = kr[i];
+    }
+    if (k + 1 < k1) load(k + 1, nxt);
+    lds_barrier();
+#pragma unroll
+    for (int st = 0; st < NK; ++st) {
+      const int a = 4 * st + kg;
 #pragma unroll
       for (int i = 0; i < NT; ++i)
-        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(16 * i + r16) * PS + a], bv, acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(16 * i + r16) * PS + a], cur[st], acc[i], 0, 0, 0);
     }
+  };
+  if (k0 < k1) load(k0, bv[0]);
+  for (int k = k0; k < k1; k += 2) {
+    node(k, bv[0], bv[1]);
+    if (k + 1 < k1) node(k + 1, bv[1], bv[0]);
   }
   if (!cok) return;
   double* out = Phi + ((int64_t)blockIdx.z * gridDim.y + t) * n * n2;
@@ -446,8 +532,11 @@ invert_pairs_kernel(const int32_t* __restrict__ pairs, int64_t npk, int64_t npai
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// SB slabs per work group: LDS (2 SB + 1) NP (NP + 1) doubles, 76 KB at
-// n <= 32 (SB 4), 94 KB at n <= 48 (SB 2), 100 KB at n <= 64 (SB 1)
+// SB slabs per work group: LDS (2 SB + 1) NP (NP + 1) doubles.  The
+// launches take SB 4 at n <= 16, 2 at n <= 32 (41 KB: three work groups per
+// compute unit) and 1 beyond (56 KB at n <= 48: two work groups, two waves
+// per SIMD to hide each other's waits, 13% faster at Nb = 400 than one work
+// group of two slabs; 100 KB at n <= 64).
 // kc: node runs (grid y), 1 unless few tensors leave the device idle
 template <int NT, int SB>
 void launch_slab(const double* X, const double* K, int n, int nq, int64_t nslab, double* T1, hipStream_t s,
@@ -482,8 +571,8 @@ hipError_t launch_mode_products(const double* X, int64_t T, int64_t xmod, const 
     else launch_slab<4, 1>(X, K, n, nq, nslab, T1, s, xmod, kstride, kc);
   } else {
     if (NT == 1) launch_slab<1, 4>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nblk(nslab, 4), nq));
-    else if (NT == 2) launch_slab<2, 4>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nblk(nslab, 4), nq));
-    else if (NT == 3) launch_slab<3, 2>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nblk(nslab, 2), nq));
+    else if (NT == 2) launch_slab<2, 2>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nblk(nslab, 2), nq));
+    else if (NT == 3) launch_slab<3, 1>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nslab, nq));
     else launch_slab<4, 1>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nslab, nq));
   }
   // mode 0: with few output tensors the node sum is split into runs whose
@@ -567,8 +656,8 @@ hipError_t launch_exchange(int prec, const double* M, int nb, int64_t npair, con
     const double* Xc = X + t0 * n3;
     const int64_t nslab = tc * n;
     if (NT == 1) launch_slab<1, 4>(Xc, tb.K, n, nq, nslab, T1, s);
-    else if (NT == 2) launch_slab<2, 4>(Xc, tb.K, n, nq, nslab, T1, s);
-    else if (NT == 3) launch_slab<3, 2>(Xc, tb.K, n, nq, nslab, T1, s);
+    else if (NT == 2) launch_slab<2, 2>(Xc, tb.K, n, nq, nslab, T1, s);
+    else if (NT == 3) launch_slab<3, 1>(Xc, tb.K, n, nq, nslab, T1, s);
     else launch_slab<4, 1>(Xc, tb.K, n, nq, nslab, T1, s);
     const dim3 mg(nblk(n2, 64), (unsigned)tc);
     double* Pc = Phi + t0 * n3;
