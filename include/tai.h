@@ -300,7 +300,7 @@ int tai_apply_J(tai_ctx* ctx, const double* M, int32_t nb, const tai_params* par
    and J as for tai_apply_J.
    Limits: prec TAI_FP64 or TAI_FP32; rank_tol must be 0 (the compression
    needs its own workspace: TAI_ERR_UNSUPPORTED); the call's scratch need,
-   the node tables plus 16 npair + 8 n^3 (nchunk + 2 + 2 nq) bytes (+ 12 n
+   the node tables plus 16 npair + 8 n^3 (nchunk + 2 + 2 nq) + 8 nq bytes (+ 12 n
    npair for TAI_FP32), with nchunk = 512 / g for the g groups of the rho
    contraction (g = ceil(n / 16) in FP64 up to n = 48, else ceil(n / 8)) and
    at most ceil(npair / 256), must fit in 256 MiB, else TAI_ERR_INVALID_ARG

@@ -700,87 +700,12 @@ sum_parts_kernel(const double* __restrict__ part, int nchunk, int64_t len, doubl
   out[i] = s;
 }
 
-// Phi = (2/sqrt(pi)) sum_k w_k rho x_0 K_k x_1 K_k x_2 K_k in two passes.
-// Pass 1, one work group per (a0 slab, node k): S = K_k rho(a0, :, :) K_k^T,
-// both products in LDS, written to T[k][a0][:][:].
-template <int NMAX>
+// out[i] = scale w[i % nq] for i < nq reps: the quadrature weights, repeated
+// for each source box of the adaptive J, with 2/sqrt(pi) folded in.
 __global__ void __launch_bounds__(256)
-slab_modes_kernel(const double* __restrict__ K, const double* __restrict__ rho, int n,
-                  double* __restrict__ T) {
-  constexpr int ST = NMAX + 1;
-  __shared__ double s_k[NMAX * ST];
-  __shared__ double s_r[NMAX * ST];
-  __shared__ double s_u[NMAX * ST];
-  const int a0 = blockIdx.x, k = blockIdx.y;
-  const int64_t n2 = (int64_t)n * n;
-  const double* Kk = K + (int64_t)k * n2;
-  rho += (int64_t)blockIdx.z * n * n2;          // batched: grid z, nq = grid y
-  T += (int64_t)blockIdx.z * gridDim.y * n * n2;
-  const double* R = rho + a0 * n2;
-  for (int e = threadIdx.x; e < n * n; e += 256) {
-    const int i = e / n, j = e % n;
-    s_k[i * ST + j] = Kk[e];
-    s_r[i * ST + j] = R[e];
-  }
-  __syncthreads();
-  // U(i1, b) = sum_a K(i1, a) rho(a, b)
-  for (int e = threadIdx.x; e < n * n; e += 256) {
-    const int i1 = e / n, b = e % n;
-    double u = 0.0;
-    for (int a = 0; a < n; ++a) u += s_k[i1 * ST + a] * s_r[a * ST + b];
-    s_u[i1 * ST + b] = u;
-  }
-  __syncthreads();
-  // S(i1, i2) = sum_b U(i1, b) K(i2, b)
-  double* out = T + ((int64_t)k * n + a0) * n2;
-  for (int e = threadIdx.x; e < n * n; e += 256) {
-    const int i1 = e / n, i2 = e % n;
-    double v = 0.0;
-    for (int b = 0; b < n; ++b) v += s_u[i1 * ST + b] * s_k[i2 * ST + b];
-    out[e] = v;
-  }
-}
-
-// Pass 2: P[k](i0, c) = sum_a K_k(i0, a) T[k][a][c] for c = (i1, i2); one
-// thread per (c, k) with all i0 in registers, K_k read at uniform addresses.
-template <int NMAX>
-__global__ void __launch_bounds__(256)
-mode0_kernel(const double* __restrict__ K, const double* __restrict__ T, int n, double* __restrict__ P) {
-  const int64_t n2 = (int64_t)n * n;
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int k = blockIdx.y;
-  const int64_t cc = c < n2 ? c : 0;
-  T += (int64_t)blockIdx.z * gridDim.y * n * n2;   // batched: grid z, nq = grid y
-  P += (int64_t)blockIdx.z * gridDim.y * n * n2;
-  const double* Kk = K + (int64_t)k * n2;
-  const double* Tk = T + (int64_t)k * n * n2;
-  double acc[NMAX];
-#pragma unroll
-  for (int i = 0; i < NMAX; ++i) acc[i] = 0.0;
-  for (int a = 0; a < n; ++a) {
-    const double t = Tk[a * n2 + cc];
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i)
-      if (i < n) acc[i] += Kk[i * n + a] * t;
-  }
-  if (c >= n2) return;
-  double* out = P + (int64_t)k * n * n2;
-#pragma unroll
-  for (int i = 0; i < NMAX; ++i)
-    if (i < n) out[i * n2 + c] = acc[i];
-}
-
-// Phi = (2/sqrt(pi)) sum_k w_k P[k], summed in node order.
-__global__ void __launch_bounds__(256)
-phi_kernel(const double* __restrict__ P, const double* __restrict__ w, int nq, int64_t n3,
-           double* __restrict__ Phi) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n3) return;
-  P += (int64_t)blockIdx.y * nq * n3;   // batched: grid y
-  Phi += (int64_t)blockIdx.y * n3;
-  double s = 0.0;
-  for (int k = 0; k < nq; ++k) s += w[k] * P[(int64_t)k * n3 + i];
-  Phi[i] = kTwoOverSqrtPi * s;
+repeat_weights_kernel(const double* __restrict__ w, int nq, int reps, double scale, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nq * reps) out[i] = scale * w[i % nq];
 }
 
 // J_p for 256 pairs per work group of 512 threads: wave w owns the two
@@ -990,7 +915,7 @@ size_t j_work_bytes(int prec, int nq, int n, int npair) {
   const size_t m32 = (prec == kFP32 || split_j(prec)) ? align256(4 * 3 * (size_t)n * npair) : 0;
   const size_t ps = split_j(prec) ? align256(2 * (size_t)n * n * j16_kc(j_slices(prec), n)) : 0;
   return align256(8 * (size_t)npair) * 2 + align256(8 * n3 * nc) + align256(8 * n3) * 2 + align256(8 * n3 * nq) * 2 +
-         m32 + ps;
+         align256(8 * (size_t)nq) + m32 + ps;
 }
 
 JWork carve_j_work(void* base, int prec, int nq, int n, int npair) {
@@ -1005,6 +930,7 @@ JWork carve_j_work(void* base, int prec, int nq, int n, int npair) {
   w.Phi = reinterpret_cast<double*>(p); p += align256(8 * n3);
   w.T1 = reinterpret_cast<double*>(p); p += align256(8 * n3 * nq);
   w.T2 = reinterpret_cast<double*>(p); p += align256(8 * n3 * nq);
+  w.wsc = reinterpret_cast<double*>(p); p += align256(8 * (size_t)nq);
   w.M32 = (prec == kFP32 || split_j(prec)) ? reinterpret_cast<float*>(p) : nullptr;
   if (w.M32) p += align256(4 * 3 * (size_t)n * npair);
   w.Ps = split_j(prec) ? reinterpret_cast<void*>(p) : nullptr;
@@ -1099,10 +1025,20 @@ void convert_moments(int prec, const double* M, int n, int npair, const JWork& w
   hipLaunchKernelGGL(to_fp32_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, M, count, w.M32);
 }
 
+// Phi = sum_k wsc_k rho x_0 K_k x_1 K_k x_2 K_k (wsc = (2/sqrt(pi)) w) on the
+// FP64 matrix cores: the slab products into w.T1, the mode-0 products and
+// node sum with the node runs' partial tensors in w.T2.  The plain J and the
+// one-box adaptive J both take this exact sequence.
+hipError_t launch_phi_grid(const double* rho, const double* K, const double* wsc, int n, int nq, const JWork& w,
+                           double* Phi, hipStream_t s) {
+  const int64_t n3 = (int64_t)n * n * n;
+  return launch_mode_products(rho, 1, 1, K, 0, wsc, n, nq, w.T1, 1, 0, nq, Phi, w.T2, (int64_t)nq * n3, s);
+}
+
 // rho from the pair densities in w.Dt, then Phi = (2/sqrt(pi)) sum_k w_k rho x_d K_k
 // (into w.rho and w.Phi)
-void launch_rho_phi(int prec, const double* M, int npair, int n, int nq, const NodeTables& tb, const JWork& w,
-                    hipStream_t s) {
+hipError_t launch_rho_phi(int prec, const double* M, int npair, int n, int nq, const NodeTables& tb, const JWork& w,
+                          hipStream_t s) {
   const int64_t n3 = (int64_t)n * n * n;
   if (rho_split(prec)) launch_rho16(prec, w.M32, n, npair, w, s);
   else if (prec == kFP32 || split_j(prec))
@@ -1110,16 +1046,8 @@ void launch_rho_phi(int prec, const double* M, int npair, int n, int nq, const N
   else if (n <= 48) launch_pair_contraction_rho<JF64, 2>(M, n, npair, w, s);
   else launch_pair_contraction_rho<JF64, 1>(M, n, npair, w, s);
   hipLaunchKernelGGL(sum_parts_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.rho_part, w.nchunk, n3, w.rho);
-  if (n <= 16) hipLaunchKernelGGL(slab_modes_kernel<16>, dim3(n, nq), dim3(256), 0, s, tb.K, w.rho, n, w.T1);
-  else if (n <= 32) hipLaunchKernelGGL(slab_modes_kernel<32>, dim3(n, nq), dim3(256), 0, s, tb.K, w.rho, n, w.T1);
-  else if (n <= 48) hipLaunchKernelGGL(slab_modes_kernel<48>, dim3(n, nq), dim3(256), 0, s, tb.K, w.rho, n, w.T1);
-  else hipLaunchKernelGGL(slab_modes_kernel<64>, dim3(n, nq), dim3(256), 0, s, tb.K, w.rho, n, w.T1);
-  const dim3 mg(nblk((int64_t)n * n, 256), nq);
-  if (n <= 16) hipLaunchKernelGGL(mode0_kernel<16>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
-  else if (n <= 32) hipLaunchKernelGGL(mode0_kernel<32>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
-  else if (n <= 48) hipLaunchKernelGGL(mode0_kernel<48>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
-  else hipLaunchKernelGGL(mode0_kernel<64>, mg, dim3(256), 0, s, tb.K, w.T1, n, w.T2);
-  hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, w.T2, tb.w, nq, n3, w.Phi);
+  hipLaunchKernelGGL(repeat_weights_kernel, dim3(nblk(nq, 256)), dim3(256), 0, s, tb.w, nq, 1, kTwoOverSqrtPi, w.wsc);
+  return launch_phi_grid(w.rho, tb.K, w.wsc, n, nq, w, w.Phi, s);
 }
 }  // namespace
 
@@ -1128,7 +1056,8 @@ hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, const in
   hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(npair, 256)), dim3(256), 0, s, D, nb, (int64_t)npair, pairs,
                      w.Dt);
   convert_moments(prec, M, n, npair, w, s);
-  launch_rho_phi(prec, M, npair, n, nq, tb, w, s);
+  const hipError_t e = launch_rho_phi(prec, M, npair, n, nq, tb, w, s);
+  if (e != hipSuccess) return e;
   if (split_j(prec)) {
     if (j_slices(prec) == 3) launch_jp16_s<3>(w.M32, w.Phi, w.Ps, n, npair, w.Jp, s);
     else launch_jp16_s<2>(w.M32, w.Phi, w.Ps, n, npair, w.Jp, s);
@@ -1142,13 +1071,6 @@ hipError_t launch_apply_j(int prec, const double* M, int nb, int npair, const in
   return hipGetLastError();
 }
 
-namespace {
-__global__ void __launch_bounds__(256)
-repeat_weights_kernel(const double* __restrict__ w, int nq, int reps, double scale, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nq * reps) out[i] = scale * w[i % nq];
-}
-}  // namespace
 
 // J over adaptive boxes (section 6.2 with eq. coulapprox): rho_s of every
 // partition on its own grid, then for every partition s
@@ -1193,9 +1115,11 @@ hipError_t launch_apply_j_parts(int prec, const double* M, int nb, const int32_t
   const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
   hipLaunchKernelGGL(density_pairs_kernel, dim3(nblk(total, 256)), dim3(256), 0, s, D, nb, total, pairs, wk.Dt);
   convert_moments(prec, M, n, (int)total, wk, s);
+  // one box: the plain path's sequence (the same bits as tai_apply_J); the
+  // weights carry 2/sqrt(pi) either way
   const bool one = nparts == 1;
   hipLaunchKernelGGL(repeat_weights_kernel, dim3(nblk((int64_t)nq * nparts, 256)), dim3(256), 0, s, w, nq, nparts,
-                     one ? 1.0 : kTwoOverSqrtPi, wrep);
+                     kTwoOverSqrtPi, wrep);
   Spans sp{};
   for (int p = 0; p <= nparts; ++p) {
     sp.off[p] = offs[p];
@@ -1250,18 +1174,8 @@ hipError_t launch_apply_j_parts(int prec, const double* M, int nb, const int32_t
     const int64_t cnt = offs[p + 1] - offs[p];
     if (cnt == 0) continue;
     if (one) {
-      double* T2q = T2_all;
-      const double* rho_q = rho_all;
-      if (n <= 16) hipLaunchKernelGGL(slab_modes_kernel<16>, dim3(n, nq), dim3(256), 0, s, Kx, rho_q, n, wk.T1);
-      else if (n <= 32) hipLaunchKernelGGL(slab_modes_kernel<32>, dim3(n, nq), dim3(256), 0, s, Kx, rho_q, n, wk.T1);
-      else if (n <= 48) hipLaunchKernelGGL(slab_modes_kernel<48>, dim3(n, nq), dim3(256), 0, s, Kx, rho_q, n, wk.T1);
-      else hipLaunchKernelGGL(slab_modes_kernel<64>, dim3(n, nq), dim3(256), 0, s, Kx, rho_q, n, wk.T1);
-      const dim3 mg(nblk(n2, 256), nq);
-      if (n <= 16) hipLaunchKernelGGL(mode0_kernel<16>, mg, dim3(256), 0, s, Kx, wk.T1, n, T2q);
-      else if (n <= 32) hipLaunchKernelGGL(mode0_kernel<32>, mg, dim3(256), 0, s, Kx, wk.T1, n, T2q);
-      else if (n <= 48) hipLaunchKernelGGL(mode0_kernel<48>, mg, dim3(256), 0, s, Kx, wk.T1, n, T2q);
-      else hipLaunchKernelGGL(mode0_kernel<64>, mg, dim3(256), 0, s, Kx, wk.T1, n, T2q);
-      hipLaunchKernelGGL(phi_kernel, dim3(nblk(n3, 256)), dim3(256), 0, s, T2_all, wrep, nq, n3, wk.Phi);
+      const hipError_t e = launch_phi_grid(rho_all, Kx, wrep, n, nq, wk, wk.Phi, s);
+      if (e != hipSuccess) return e;
     }
     JWork wp = wk;
     wp.Jp = wk.Jp + offs[p];

@@ -227,7 +227,8 @@ struct JWork {
   double* rho_part;// [nchunk][n^3]
   double* rho;     // [n^3]
   double* T1;      // [nq][n^3] slab products K_k rho(a0) K_k^T
-  double* T2;      // [nq][n^3] mode-0 products, before the sum over nodes
+  double* T2;      // [nq][n^3] mode-0 partial sums over runs of nodes
+  double* wsc;     // [nq] quadrature weights times 2/sqrt(pi)
   double* Phi;     // [n^3]
   double* Jp;      // [npair]
   float* M32;      // [3][n][npair] FP32 copy of the moments (FP32 and split BF16, else null)
