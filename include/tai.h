@@ -421,6 +421,18 @@ int tai_apply_J_pairs(tai_ctx* ctx, const double* M, int32_t nb, const int32_t* 
 int tai_partition_pairs(tai_ctx* ctx, const tai_basis* basis, double tau, int32_t nparts, int32_t* pairs,
                         int32_t* counts, double* boxes, void* stream);
 
+/* The moments of every partition's pairs on its own box (section 6.2: each
+   pair's interpolant on the grid of its partition's box), in one launch:
+   block s of M, [3][n][counts[s]] at M + 3 n (counts[0] + ... +
+   counts[s-1]), holds what tai_moments_pairs writes for the pairs of
+   partition s with params->L = boxes[s], bit for bit.  pairs: DEVICE int32,
+   the partitions' lists one after another; counts: HOST int32 [nparts]
+   (>= 0, adding up to a number in [1, npair(nb)]); boxes: HOST double
+   [nparts] (finite, > 0); 1 <= nparts <= 16 (TAI_ERR_INVALID_ARG
+   otherwise).  params->L is not read; M: DEVICE double, written. */
+int tai_moments_partitioned(tai_ctx* ctx, const tai_basis* basis, const tai_params* params, const int32_t* pairs,
+                            const int32_t* counts, const double* boxes, int32_t nparts, double* M, void* stream);
+
 /* J with adaptive boxes (eq. coulapprox with the boxes of section 6.2,
    tai_partition_pairs): every pair of partition s carries its moments on
    the Chebyshev grid of box s, and two partitions s, s' interact through the

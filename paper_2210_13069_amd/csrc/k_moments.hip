@@ -16,6 +16,8 @@
 #include "tai_internal.h"
 #include "tai_device.h"
 
+#include <algorithm>
+
 #include <cmath>
 
 namespace tai {
@@ -207,6 +209,20 @@ screen_write_kernel(DevBasis bs, double tau, const int32_t* __restrict__ rows, i
   }
 }
 
+// blockIdx.y = partition z of the adaptive boxes: pairs pairs[off[z] ..),
+// box half-width L[z], moment block M + 3 n off[z].  Only L depends on the
+// box (the node map and panel rule do not), so one launch serves all boxes;
+// blocks past a partition's 3 count threads return as a whole.
+template <int NMAX>
+__global__ void __launch_bounds__(128)
+moments_parts_kernel(DevBasis bs, int n, PartSpans sp, NodeTables tb, double* __restrict__ M,
+                     const int32_t* __restrict__ pairs) {
+  const int z = blockIdx.y;
+  const int64_t o = sp.off[z], cnt = sp.off[z + 1] - o;
+  if ((int64_t)blockIdx.x * 128 >= 3 * cnt) return;
+  moments_body<NMAX>(bs, n, sp.L[z], tb, M + 3 * (int64_t)n * o, cnt, pairs + o);
+}
+
 // blockIdx.y = molecule; blocks past a molecule's 3*npair threads return
 template <int NMAX>
 __global__ void __launch_bounds__(128)
@@ -302,6 +318,19 @@ hipError_t launch_moments_pairs(const DevBasis& b, int n, double L, const NodeTa
     hipLaunchKernelGGL(moments_kernel<48>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair, pairs);
   else
     hipLaunchKernelGGL(moments_kernel<64>, dim3(blocks), dim3(threads), 0, s, b, n, L, tb, M, npair, pairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_parts(const DevBasis& b, int n, const NodeTables& tb, const int32_t* pairs,
+                                const PartSpans& sp, int nparts, double* M, hipStream_t s) {
+  int64_t maxc = 0;
+  for (int z = 0; z < nparts; ++z) maxc = std::max<int64_t>(maxc, sp.off[z + 1] - sp.off[z]);
+  if (maxc == 0) return hipSuccess;
+  const dim3 grid((unsigned)((3 * maxc + 127) / 128), (unsigned)nparts);
+  if (n <= 16) hipLaunchKernelGGL(moments_parts_kernel<16>, grid, dim3(128), 0, s, b, n, sp, tb, M, pairs);
+  else if (n <= 32) hipLaunchKernelGGL(moments_parts_kernel<32>, grid, dim3(128), 0, s, b, n, sp, tb, M, pairs);
+  else if (n <= 48) hipLaunchKernelGGL(moments_parts_kernel<48>, grid, dim3(128), 0, s, b, n, sp, tb, M, pairs);
+  else hipLaunchKernelGGL(moments_parts_kernel<64>, grid, dim3(128), 0, s, b, n, sp, tb, M, pairs);
   return hipGetLastError();
 }
 

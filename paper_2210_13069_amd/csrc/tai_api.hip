@@ -790,6 +790,46 @@ int tai_partition_pairs(tai_ctx* c, const tai_basis* b, double tau, int32_t npar
   return TAI_OK;
 }
 
+int tai_moments_partitioned(tai_ctx* c, const tai_basis* b, const tai_params* p, const int32_t* pairs,
+                            const int32_t* counts, const double* boxes, int32_t nparts, double* M, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_basis(c, b))) return r;
+  if ((r = validate_params(c, p, false))) return r;
+  if (!M || !pairs || !counts || !boxes) return fail(c, TAI_ERR_INVALID_ARG, "a pointer is NULL");
+  if (nparts < 1 || nparts > tai::kMaxParts)
+    return fail(c, TAI_ERR_INVALID_ARG, "nparts must be in [1, " + std::to_string(tai::kMaxParts) + "]");
+  tai::PartSpans sp{};
+  sp.off[0] = 0;
+  for (int i = 0; i < nparts; ++i) {
+    if (counts[i] < 0) return fail(c, TAI_ERR_INVALID_ARG, "counts must be >= 0");
+    if (!std::isfinite(boxes[i]) || !(boxes[i] > 0)) return fail(c, TAI_ERR_INVALID_ARG, "boxes must be finite and > 0");
+    sp.off[i + 1] = sp.off[i] + counts[i];
+    sp.L[i] = boxes[i];
+  }
+  if (sp.off[nparts] < 1 || sp.off[nparts] > npair_of(b->nb))
+    return fail(c, TAI_ERR_INVALID_ARG, "the partition counts must add up to a number in [1, npair]");
+  if ((r = need_device(c))) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(p->nq, p->n)))) return r;
+  tai::DevBasis db;
+  if ((r = upload_basis(c, b, s, &db))) return r;
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, p->nq, p->n);
+  hipError_t e;
+  {
+    // the node map and the panel rule of the moments do not depend on the box
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, p->nq, p->n, boxes[nparts - 1], p->nodes, 0.0, tb, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "nodes kernel");
+  {
+    Timed tm(c, kStMoments, s);
+    e = tai::launch_moments_parts(db, p->n, tb, pairs, sp, nparts, M, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "moments kernel");
+  return TAI_OK;
+}
+
 int tai_apply_J_partitioned(tai_ctx* c, const double* M, int32_t nb, const int32_t* pairs, const int32_t* counts,
                             const double* boxes, int32_t nparts, const tai_params* p, const double* D, double* J,
                             void* stream) {

@@ -344,6 +344,17 @@ struct PartBoxes {
   double b[kMaxParts];
   int nparts;
 };
+// The partitions' spans of the concatenated pair list (off[s] .. off[s+1])
+// and their box half-widths, passed by value to the batched moments kernel.
+struct PartSpans {
+  int64_t off[kMaxParts + 1];
+  double L[kMaxParts];
+};
+// Moments of every partition's pairs on its own box (k_moments.hip): block s
+// of M = [3][n][counts[s]] at M + 3 n off[s], the pairs pairs[off[s] ..),
+// box [-L[s], L[s]]; one launch, the partition as a grid dimension.
+hipError_t launch_moments_parts(const DevBasis& b, int n, const NodeTables& tb, const int32_t* pairs,
+                                const PartSpans& sp, int nparts, double* M, hipStream_t s);
 struct PartWork {
   double* sup;        // [npair] support half-widths
   double* sorted;     // [npair]

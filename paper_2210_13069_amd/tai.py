@@ -30,7 +30,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
            "tai_quadrature", "tai_degrees", "tai_compress", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
            "tai_apply_J_pairs", "tai_apply_J_compressed", "tai_coulomb_mo", "tai_exchange", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J", "tai_apply_J_noalloc",
-           "tai_partition_pairs", "tai_apply_J_partitioned", "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
+           "tai_partition_pairs", "tai_moments_partitioned", "tai_apply_J_partitioned", "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched", "compress"]
 
 
@@ -112,6 +112,9 @@ def load_library(path=LIB_PATH):
     lib.tai_apply_J.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, vp, vp]
     lib.tai_partition_pairs.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.c_double, ctypes.c_int32, vp,
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), vp]
+    lib.tai_moments_partitioned.argtypes = [vp, ctypes.POINTER(tai_basis), ctypes.POINTER(tai_params), vp,
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                            ctypes.c_int32, vp, vp]
     lib.tai_apply_J_partitioned.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                             ctypes.POINTER(tai_params), vp, vp, vp]
@@ -232,6 +235,15 @@ class Context:
         p = params if isinstance(params, tai_params) else make_params(params)
         self.check(self.lib.tai_moments_pairs(self.h, ctypes.byref(basis_arrays.struct), ctypes.byref(p),
                                               _ptr(pairs), int(npk), _ptr(M), _stream(stream)), "tai_moments_pairs")
+
+    def moments_partitioned(self, basis_arrays, params, pairs, counts, boxes, M, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        k = len(counts)
+        cnt = (ctypes.c_int32 * k)(*[int(x) for x in counts])
+        box = (ctypes.c_double * k)(*[float(x) for x in boxes])
+        self.check(self.lib.tai_moments_partitioned(self.h, ctypes.byref(basis_arrays.struct), ctypes.byref(p),
+                                                    _ptr(pairs), cnt, box, k, _ptr(M), _stream(stream)),
+                   "tai_moments_partitioned")
 
     def apply_J_pairs(self, M, nb, pairs, npk, params, D, J, stream=None):
         p = params if isinstance(params, tai_params) else make_params(params)
@@ -421,19 +433,12 @@ def partition_pairs(basis, tau, nparts, device=0):
 
 def moments_partitioned(basis, params, pairs, counts, boxes, device=0):
     """The partitions' moment blocks, block s on box boxes[s], concatenated."""
-    import dataclasses
     import torch
     ba = BasisArrays(basis)
     n = int(params.n)
     total = int(sum(counts))
     M = torch.empty(3 * n * total, dtype=torch.float64, device=torch.device("cuda", device))
-    off = 0
-    ctx = context(device)
-    for c, bx in zip(counts, boxes):
-        if c > 0:
-            Ps = dataclasses.replace(params, L=float(bx))
-            ctx.moments_pairs(ba, Ps, pairs[off:], int(c), M[3 * n * off:3 * n * (off + c)])
-        off += c
+    context(device).moments_partitioned(ba, params, pairs, counts, boxes, M)
     return M
 
 

@@ -359,3 +359,28 @@ def test_apply_J_partitioned_argument_checks(hctx):
     assert call() == tai.TAI_ERR_NOT_READY
     # the boxes give the half-widths: params->L is not read
     assert call(params=_params(L=0.0)) == tai.TAI_ERR_NOT_READY
+
+
+def test_moments_partitioned_argument_checks(hctx):
+    lib, h = hctx.lib, hctx.h
+    b = I.small_random(3, natoms=2, shells=("s", "p"))   # nb = 8, npair = 36
+    ba = tai.BasisArrays(b)
+    dummy = ctypes.c_void_p(16)
+    mk = lambda vals, t: (t * len(vals))(*vals)
+    good_c = mk([10, 20], ctypes.c_int32)
+    good_b = mk([3.0, 5.0], ctypes.c_double)
+    p = _params()
+    call = lambda c=good_c, bx=good_b, k=2, params=p, M=dummy, pairs=dummy: \
+        lib.tai_moments_partitioned(h, ctypes.byref(ba.struct), ctypes.byref(params), pairs, c, bx, k, M, None)
+    assert call(c=mk([-1, 20], ctypes.c_int32)) == tai.TAI_ERR_INVALID_ARG
+    assert call(c=mk([0, 0], ctypes.c_int32)) == tai.TAI_ERR_INVALID_ARG          # no pairs at all
+    assert call(c=mk([30, 7], ctypes.c_int32)) == tai.TAI_ERR_INVALID_ARG         # more than npair
+    assert call(bx=mk([3.0, float("inf")], ctypes.c_double)) == tai.TAI_ERR_INVALID_ARG
+    assert call(bx=mk([-1.0, 5.0], ctypes.c_double)) == tai.TAI_ERR_INVALID_ARG
+    for k in (0, 17):
+        assert call(k=k) == tai.TAI_ERR_INVALID_ARG
+    assert call(M=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(pairs=None) == tai.TAI_ERR_INVALID_ARG
+    assert call() == tai.TAI_ERR_NOT_READY
+    # the boxes give the half-widths: params->L is not read
+    assert call(params=_params(L=0.0)) == tai.TAI_ERR_NOT_READY

@@ -125,3 +125,36 @@ def test_empty_middle_partition(tai, prec):
     err = np.linalg.norm(Jg - Jr, 2) / np.linalg.norm(Jr, 2)
     assert err <= J_TOL[prec], (prec, err)
     np.testing.assert_array_equal(Jg, Jg.T)
+
+
+@pytest.mark.parametrize("case", ["small", "empty", "jbuild1000"])
+def test_moments_partitioned_equal_per_partition_calls(tai, case):
+    """tai_moments_partitioned (every partition in one launch) writes each
+    block exactly as tai_moments_pairs on that partition's list with
+    L = its box; also with an empty partition, and at Nb = 1000."""
+    import torch
+    if case == "jbuild1000":
+        b, P, _ = I.jbuild1000()
+        pairs, counts, boxes = tai.partition_pairs(b, 1e-20, 4)
+    else:
+        b, P = _small()
+        pairs, counts, boxes = tai.partition_pairs(b, 1e-16, 3)
+        if case == "empty":
+            # partition 1 emptied into partition 2 (its box holds the supports)
+            part, _ = _oracle_parts(b, 1e-16, 3)
+            part = np.where(part == 1, 2, part)
+            counts = np.bincount(part, minlength=3).tolist()
+            order = np.concatenate([np.flatnonzero(part == s) for s in range(3)]).astype(np.int32)
+            pairs = torch.as_tensor(order, device="cuda")
+    Mb = tai.moments_partitioned(b, P, pairs, counts, boxes)
+    ba = tai.BasisArrays(b)
+    ctx = tai.context(0)
+    off = 0
+    for c, bx in zip(counts, boxes):
+        if c == 0:
+            continue
+        Mp = torch.empty(3 * P.n * c, dtype=torch.float64, device=Mb.device)
+        ctx.moments_pairs(ba, dataclasses.replace(P, L=float(bx)), pairs[off:], int(c), Mp)
+        assert torch.equal(Mb[3 * P.n * off:3 * P.n * (off + c)], Mp), (case, off, c)
+        off += c
+    assert off == sum(counts)
