@@ -336,6 +336,7 @@ def main():
     # ---------------- the headline step over the pairs kept by screening -------
     screened = None
     screened_sample = None
+    adaptive_b_sample = None
     if not args.only_headline:
         pairs = torch.empty(npair, dtype=torch.int32, device=dev)
         params = tai.make_params(P, head)
@@ -515,12 +516,7 @@ def main():
                     ctx.profile_enable(True)
                     t0 = time.perf_counter()
                 counts, boxes = ctx.partition_pairs(jba, PARTS_TAU, PARTS_N, lst)
-                off = 0
-                for c_, bx_ in zip(counts, boxes):
-                    if c_:
-                        ctx.moments_pairs(jba, dataclasses.replace(jP, L=bx_), lst[off:], c_,
-                                          Mpt[3 * jP.n * off:3 * jP.n * (off + c_)])
-                    off += c_
+                ctx.moments_partitioned(jba, jP, lst, counts, boxes, Mpt)
                 ctx.apply_J_partitioned(Mpt, jb.nb, lst, counts, boxes, jparams, Dj, Jpt)
             torch.cuda.synchronize()
             ms_pt = (time.perf_counter() - t0) * 1e3 / K
@@ -562,12 +558,7 @@ def main():
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
             counts4, boxes4 = ctx.partition_pairs(ba4, PARTS_TAU, PARTS_N, lst4)
-            off = 0
-            for c_, bx_ in zip(counts4, boxes4):
-                if c_:
-                    ctx.moments_pairs(ba4, dataclasses.replace(P4, L=bx_), lst4[off:], c_,
-                                      M4[3 * P4.n * off:3 * P4.n * (off + c_)])
-                off += c_
+            ctx.moments_partitioned(ba4, P4, lst4, counts4, boxes4, M4)
             ctx.apply_J_partitioned(M4, b4.nb, lst4, counts4, boxes4, p4, D4, J4a)
         torch.cuda.synchronize()
         ms_a4 = (time.perf_counter() - t0) * 1e3 / K
@@ -577,6 +568,43 @@ def main():
             "ms_per_step": round(ms_a4, 3), "fixed_box_L16_ms_per_step": round(ms_f4, 3),
             "rel_2norm_vs_fixed_box_L16_gpu": float(torch.linalg.matrix_norm(J4a - J4f, 2) /
                                                     torch.linalg.matrix_norm(J4f, 2))}
+        # B over the same four boxes (the stored-matrix form): a step =
+        # partitions + moments on the boxes + B, in the headline arithmetic
+        # and FP64, against the fixed-box step of the headline workload;
+        # sampled entries against Algorithm 1 on the pairs' boxes
+        adaptive_b = {"workload": "spd400 basis (Nb=400, 80200 pairs), omega=0.3, nq=32, n=40, four boxes; "
+                                  "step = partitions + moments on the boxes + full B (6.43e9 entries)"}
+        lst4c = lst4.cpu().numpy().astype(np.int64)
+        offs4 = np.concatenate([[0], np.cumsum(counts4)])
+        rngb = np.random.default_rng(23)
+        bi = np.concatenate([rngb.integers(0, b4.npair, 160), [0, b4.npair - 1]])
+        bj = np.concatenate([rngb.integers(0, b4.npair, 160), [b4.npair - 1, 0]])
+        for name in (args.prec, "fp64"):
+            precb = tai.PREC_BY_NAME[name]
+            Bb = torch.empty((npair, ldb), dtype=torch.float64 if precb == tai.FP64 else torch.float32, device=dev)
+            pb = tai.make_params(P4, precb)
+            log(f"adaptive-box B {name}: nparts={PARTS_N}")
+            stepsb = K if precb != tai.FP64 else max(1, K // 2)
+            for it in range(1 + stepsb):
+                if it == 1:
+                    torch.cuda.synchronize()
+                    ctx.profile_enable(True)
+                    t0 = time.perf_counter()
+                counts4, boxes4 = ctx.partition_pairs(ba4, PARTS_TAU, PARTS_N, lst4)
+                ctx.moments_partitioned(ba4, P4, lst4, counts4, boxes4, M4)
+                ctx.assemble_B_partitioned(M4, counts4, boxes4, pb, Bb, ldb)
+            torch.cuda.synchronize()
+            ms_b = (time.perf_counter() - t0) * 1e3 / stepsb
+            stb = {s_: ctx.profile_read(s_) for s_ in ("nodes", "moments", "pack", "project", "assemble")}
+            ctx.profile_enable(False)
+            adaptive_b[name] = {"ms_per_step": round(ms_b, 3), "stage_ms": stage_ms(stb, stepsb),
+                                "step_ratio_vs_fixed_box": round(ms_b / paths[name]["ms_per_step"], 3),
+                                "sample": Bb[torch.as_tensor(bi, device=dev),
+                                             torch.as_tensor(bj, device=dev)].double().cpu().numpy()}
+            del Bb
+            torch.cuda.empty_cache()
+        adaptive["spd400_B"] = adaptive_b
+        adaptive_b_sample = (lst4c, offs4, list(boxes4), bi, bj)
         del M4, J4f, J4a, lst4
         # the same J-build on the compressed grid (R^3 instead of n^3)
         jPc = dataclasses.replace(jP, rank_tol=RANK_TOL_J)
@@ -787,6 +815,29 @@ def main():
             scale1 = float(np.max(np.abs(T.B_entries(Mr, Kt1, w1, np.searchsorted(allp, sel),
                                                       np.searchsorted(allp, sel)))))
             omega1["rel_error_vs_oracle"] = {name: errors(sv, ref1, scale1) for name, sv in samples_w1.items()}
+        # B over the four boxes of the Nb = 400 basis: the oracle's moments
+        # of the sampled pairs on their boxes, Algorithm 1 on the pairs' boxes
+        if adaptive_b_sample is not None:
+            order4, offs4, boxes4, bi, bj = adaptive_b_sample
+            part_of = np.searchsorted(offs4, np.arange(len(order4)), side="right") - 1
+            t4, w4 = T.time_nodes(P4.omega, P4.nq)
+            used = np.unique(np.concatenate([bi, bj]))
+            pm4 = []
+            for s_ in range(len(boxes4)):
+                pos = used[part_of[used] == s_]
+                sel4 = order4[pos]
+                o_ = np.argsort(sel4)
+                sel4 = sel4[o_]
+                Ms = (T.moments(b4.center, b4.alpha, b4.lxyz, boxes4[s_], P4.n, pairs=sel4) if len(sel4)
+                      else np.zeros((3, P4.n, 0)))
+                pm4.append((sel4, Ms))
+            ref4 = T.B_partitioned_entries(pm4, boxes4, t4, w4, P4.n, order4[bi], order4[bj])
+            scale4 = float(np.max(np.abs(T.B_partitioned_entries(pm4, boxes4, t4, w4, P4.n, order4[used],
+                                                                 order4[used]))))
+            for name in list(japply["adaptive_boxes"]["spd400_B"]):
+                rec_b = japply["adaptive_boxes"]["spd400_B"][name]
+                if isinstance(rec_b, dict) and "sample" in rec_b:
+                    rec_b["rel_error_vs_oracle"] = errors(rec_b.pop("sample"), ref4, scale4)
         # Nb = 64: every entry of B against the oracle's B (Theorem 3.1 matrix route)
         if small_B:
             Mo = T.moments(b2.center, b2.alpha, b2.lxyz, P2.L, P2.n)
@@ -814,6 +865,11 @@ def main():
         except ImportError:
             pass
 
+    # samples the oracle did not see (--no-cpu) do not go into the line
+    if japply is not None and "spd400_B" in japply.get("adaptive_boxes", {}):
+        for rec_b in japply["adaptive_boxes"]["spd400_B"].values():
+            if isinstance(rec_b, dict):
+                rec_b.pop("sample", None)
     out = {
         "metric": METRIC,
         "value": value,

@@ -454,6 +454,26 @@ int tai_apply_J_partitioned(tai_ctx* ctx, const double* M, int32_t nb, const int
                             const double* boxes, int32_t nparts, const tai_params* params, const double* D, double* J,
                             void* stream);
 
+/* B over adaptive boxes (section 6.2 with Theorem 3.1): B(p, q) =
+   (2/sqrt(pi)) sum_k w_k prod_d m_{p,d}^T K_k^(s,s') m_{q,d}, p in partition s
+   (moments on box s), q in s' (moments on box s'), K^(s,s') the interpolant
+   of exp(-t_k^2 (x - y)^2) on the two boxes' grids, the matrix whose products
+   with the pair densities tai_apply_J_partitioned applies.  Rows and columns
+   follow the concatenated partition lists (the order of the pairs of
+   tai_partition_pairs).  M: DEVICE double, the moment blocks of
+   tai_moments_partitioned; counts: HOST int32 [nparts] (>= 0, adding up to a
+   total of at least 1); boxes: HOST double [nparts] (finite, > 0);
+   1 <= nparts <= 16.  B: DEVICE, row-major total x ldb (ldb >= total),
+   double for TAI_FP64 else float, written in full (both triangles).  params
+   gives omega, nq, n, nodes and prec; params->L is not read; rank_tol and
+   degree_tol must be 0.  Runs on the persistent assembly kernels: TAI_FP64
+   and TAI_FP32 (n up to their inner length) and the split 16-bit forms with
+   a compiled shape for nq; otherwise TAI_ERR_UNSUPPORTED.  The library keeps
+   the cross tables and, per partition pair s <= s', the column operand
+   (about nparts (nparts + 1) / 2 times the single-box projection). */
+int tai_assemble_B_partitioned(tai_ctx* ctx, const double* M, const int32_t* counts, const double* boxes,
+                               int32_t nparts, const tai_params* params, void* B, int64_t ldb, void* stream);
+
 /* ---- tuning ------------------------------------------------------------- */
 
 /* Shape autotuner of the split 16-bit assembly (TAI_BF16X3, TAI_BF16X6,

@@ -220,6 +220,10 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
   const int64_t prow = m.prow;
+  // a rectangular block's columns have their own operand rows and exponents
+  const bool rect = m.rect != 0;
+  const int64_t pcol = rect ? (int64_t)m.pcol : prow;
+  const int32_t* __restrict__ exc = rect ? m.exc : m.ex;
   const int64_t row_wg = (int64_t)rp * ROWS;
   const int64_t row_base = row_wg + wave * 16 * RB;
   const char* __restrict__ Ab = static_cast<const char*>(m.A);
@@ -228,7 +232,8 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
   const int64_t npair = m.npair;
   const int64_t ldb = m.ldb;
   float* __restrict__ Bout = static_cast<float*>(m.B);
-  const bool vec_ok = ((ldb & 3) == 0) && ((reinterpret_cast<uintptr_t>(Bout) & 15) == 0);
+  float* __restrict__ Tout = static_cast<float*>(rect ? m.Bt : m.B);
+  const bool vec_ok = ((ldb & 3) == 0) && ((reinterpret_cast<uintptr_t>(Tout) & 15) == 0);
   double* mysum = sums + wave * NV * 64 + lane;   // value v at mysum[v * 64]
   const int nblk = cb1 - cb0;
   const int64_t col_first = (int64_t)cb0 * COLS;
@@ -240,7 +245,7 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
   }
   for (int i = threadIdx.x; i < nblk * COLS; i += NT) {
     const int64_t col = col_first + i;
-    ecol_s[i] = m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col] - m.ysh;
+    ecol_s[i] = exc[col] + exc[pcol + col] + exc[2 * pcol + col] - m.ysh;
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) mysum[v * 64] = 0.0;
@@ -259,11 +264,11 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
   __syncthreads();  // exponent tables written
 
   // step t = (block t / nq, node t % nq); its Y base pointer
-  const int64_t node_bytes = 3 * prow * C::KC_ * 2;
+  const int64_t node_bytes = 3 * pcol * C::KC_ * 2;
   const int64_t block_bytes = (int64_t)COLS * C::KC_ * 2;
   const int T = nblk * (nq / C::NPS_);
   YLoads<C> yl;
-  yl.init(prow, col_first, node_bytes, wave, lane);
+  yl.init(pcol, col_first, node_bytes, wave, lane);
   int ib = 0, ik = 0;  // (block, node) of the next step to load
   auto issue_next = [&](uint4* buf) {
     yl.issue(Yb + ik * node_bytes + ib * block_bytes, buf, wave);
@@ -292,8 +297,9 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
   typedef __attribute__((address_space(1))) v4f gv4f;
   typedef __attribute__((address_space(1))) char gchar;
   gchar* Bbytes = (gchar*)Bout;
+  gchar* Tbytes = (gchar*)Tout;
   const uint32_t ldb4 = (uint32_t)ldb * 4u;
-  const int npair32 = (int)npair;
+  const int ncol32 = rect ? m.ncol : (int)npair;
   auto finish_block = [&](int fb) {
     const int64_t col0 = col_first + (int64_t)fb * COLS;
     int ecol[CB];
@@ -310,6 +316,11 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
       for (int c = 0; c < CB; ++c) {
         const int64_t colu = col0 + 16 * c;                    // uniform first column
         const int dc = (int)(colu - rowu) + r16;               // col - rowu for this lane
+        // rows kept: row - rowu <= lim_row (upper triangle: row <= col);
+        // mirrored: row - rowu < lim_mir (row < col); a rectangular block
+        // keeps and mirrors every row below its row count
+        const int lim_row = rect ? (int)(npair - rowu) - 1 : dc;
+        const int lim_mir = rect ? (int)(npair - rowu) : dc;
         float val[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -317,21 +328,21 @@ __device__ inline void run_item(const AsmMol& m, int rp, int cb0, int cb1, uint4
           val[r] = (float)ldexp(mysum[v * 64] * kTwoOverSqrtPi, erow[r] + ecol[c]);
           mysum[v * 64] = 0.0;
         }
-        if ((int)colu + r16 < npair32) {
-          // rows: B[row][col] for row <= col
+        if ((int)colu + r16 < ncol32) {
+          // rows: B[row][col]
           gchar* rbase = Bbytes + (rowu * ldb + colu) * 4;
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            if (row0 + r <= dc) *(gfloat*)(rbase + ((uint32_t)(row0 + r) * ldb4 + (uint32_t)r16 * 4u)) = val[r];
-          // mirror: B[col][row .. row+3] for row < col
-          gchar* mbase = Bbytes + (colu * ldb + rowu) * 4;
+            if (row0 + r <= lim_row) *(gfloat*)(rbase + ((uint32_t)(row0 + r) * ldb4 + (uint32_t)r16 * 4u)) = val[r];
+          // mirror: B[col][row .. row+3] (Bt[col][row ..] for a rectangular block)
+          gchar* mbase = Tbytes + (colu * ldb + rowu) * 4;
           gfloat* dst = (gfloat*)(mbase + ((uint32_t)r16 * ldb4 + (uint32_t)row0 * 4u));
-          if (vec_ok && row0 + 3 < dc) {
+          if (vec_ok && row0 + 3 < lim_mir) {
             *(gv4f*)dst = v4f{val[0], val[1], val[2], val[3]};
           } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (row0 + r < dc) dst[r] = val[r];
+              if (row0 + r < lim_mir) dst[r] = val[r];
           }
         }
       }

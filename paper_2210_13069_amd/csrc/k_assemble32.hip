@@ -86,6 +86,10 @@ __device__ inline void run_item32(const AsmMol& m, int rp, int cb0, int cb1, flo
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
   const int64_t prow = m.prow;
+  // a rectangular block's columns have their own operand rows and exponents
+  const bool rect = m.rect != 0;
+  const int64_t pcol = rect ? (int64_t)m.pcol : prow;
+  const int32_t* __restrict__ exc = rect ? m.exc : m.ex;
   const int64_t row_wg = (int64_t)rp * ROWS;
   const int64_t row_base = row_wg + wave * 16 * RB;
   const float* __restrict__ Af = static_cast<const float*>(m.A);
@@ -94,7 +98,8 @@ __device__ inline void run_item32(const AsmMol& m, int rp, int cb0, int cb1, flo
   const int64_t npair = m.npair;
   const int64_t ldb = m.ldb;
   float* __restrict__ Bout = static_cast<float*>(m.B);
-  const bool vec_ok = ((ldb & 3) == 0) && ((reinterpret_cast<uintptr_t>(Bout) & 15) == 0);
+  float* __restrict__ Tout = static_cast<float*>(rect ? m.Bt : m.B);
+  const bool vec_ok = ((ldb & 3) == 0) && ((reinterpret_cast<uintptr_t>(Tout) & 15) == 0);
   double* mysum = sums + wave * NV * 64 + lane;  // value v at mysum[v * 64]
   const int nblk = cb1 - cb0;
   const int64_t col_first = (int64_t)cb0 * COLS;
@@ -105,7 +110,7 @@ __device__ inline void run_item32(const AsmMol& m, int rp, int cb0, int cb1, flo
   }
   for (int i = threadIdx.x; i < nblk * COLS; i += NT) {
     const int64_t col = col_first + i;
-    ecol_s[i] = m.ex[col] + m.ex[prow + col] + m.ex[2 * prow + col] - m.ysh;
+    ecol_s[i] = exc[col] + exc[pcol + col] + exc[2 * pcol + col] - m.ysh;
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) mysum[v * 64] = 0.0;
@@ -123,7 +128,7 @@ __device__ inline void run_item32(const AsmMol& m, int rp, int cb0, int cb1, flo
 
   // Y fragment f = d * NCH + ch of a (node, block): lane l loads
   // Y[k][d][col0 + l%16][4 ch + l/16]; wave w loads fragments w, w + NW, ...
-  const int64_t node_bytes = 3 * prow * C::KC_ * 4;
+  const int64_t node_bytes = 3 * pcol * C::KC_ * 4;
   const int64_t block_bytes = (int64_t)COLS * C::KC_ * 4;
   uint32_t off[LPW];
 #pragma unroll
@@ -131,7 +136,7 @@ __device__ inline void run_item32(const AsmMol& m, int rp, int cb0, int cb1, flo
     int f = wave + NW * i;
     f = f < NFRAG ? f : 0;
     const int d = f / NCH, ch = f % NCH;
-    off[i] = (uint32_t)((((int64_t)d * prow + col_first + r16) * C::KC_ + 4 * ch + kg) * 4);
+    off[i] = (uint32_t)((((int64_t)d * pcol + col_first + r16) * C::KC_ + 4 * ch + kg) * 4);
   }
   const int T = nblk * nq;
   const int32_t* __restrict__ nkp = DEG ? m.nk : nullptr;
@@ -164,8 +169,9 @@ __device__ inline void run_item32(const AsmMol& m, int rp, int cb0, int cb1, flo
   typedef __attribute__((address_space(1))) v4f gv4f;
   typedef __attribute__((address_space(1))) char gchar;
   gchar* Bbytes = (gchar*)Bout;
+  gchar* Tbytes = (gchar*)Tout;
   const uint32_t ldb4 = (uint32_t)ldb * 4u;
-  const int npair32 = (int)npair;
+  const int ncol32 = rect ? m.ncol : (int)npair;
   auto finish_block = [&](int fb) {
     const int64_t colu = col_first + (int64_t)fb * COLS;  // uniform first column
     const int ecol = ecol_s[fb * COLS + r16];
@@ -177,6 +183,11 @@ __device__ inline void run_item32(const AsmMol& m, int rp, int cb0, int cb1, flo
       const int64_t rowu = row_wg + wave * 16 * RB + 16 * rb;  // uniform first row of the block
       const int row0 = 4 * kg;                                 // this lane's first row, relative
       const int dc = (int)(colu - rowu) + r16;                 // col - rowu for this lane
+      // rows kept: row - rowu <= lim_row (upper triangle: row <= col);
+      // mirrored: row - rowu < lim_mir (row < col); a rectangular block keeps
+      // and mirrors every row below its row count
+      const int lim_row = rect ? (int)(npair - rowu) - 1 : dc;
+      const int lim_mir = rect ? (int)(npair - rowu) : dc;
       float val[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -184,19 +195,19 @@ __device__ inline void run_item32(const AsmMol& m, int rp, int cb0, int cb1, flo
         val[r] = (float)ldexp(mysum[v * 64] * kTwoOverSqrtPi, erow[r] + ecol);
         mysum[v * 64] = 0.0;
       }
-      if ((int)colu + r16 < npair32) {
+      if ((int)colu + r16 < ncol32) {
         gchar* rbase = Bbytes + (rowu * ldb + colu) * 4;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (row0 + r <= dc) *(gfloat*)(rbase + ((uint32_t)(row0 + r) * ldb4 + (uint32_t)r16 * 4u)) = val[r];
-        gchar* mbase = Bbytes + (colu * ldb + rowu) * 4;
+          if (row0 + r <= lim_row) *(gfloat*)(rbase + ((uint32_t)(row0 + r) * ldb4 + (uint32_t)r16 * 4u)) = val[r];
+        gchar* mbase = Tbytes + (colu * ldb + rowu) * 4;
         gfloat* dst = (gfloat*)(mbase + ((uint32_t)r16 * ldb4 + (uint32_t)row0 * 4u));
-        if (vec_ok && row0 + 3 < dc) {
+        if (vec_ok && row0 + 3 < lim_mir) {
           *(gv4f*)dst = v4f{val[0], val[1], val[2], val[3]};
         } else {
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            if (row0 + r < dc) dst[r] = val[r];
+            if (row0 + r < lim_mir) dst[r] = val[r];
         }
       }
     }
@@ -327,6 +338,10 @@ __device__ inline void run_item64(const AsmMol& m, int rp, int cb0, int cb1, uin
   const int nq = m.nq;
   const int64_t ldb = m.ldb;
   const int npair32 = (int)m.npair;
+  // a rectangular block: its own column operand rows, every entry, mirror to Bt
+  const bool rect = m.rect != 0;
+  const int64_t pcol = rect ? (int64_t)m.pcol : prow;
+  const int ncol32 = rect ? m.ncol : npair32;
   const int nblk = cb1 - cb0;
   const int64_t col_first = (int64_t)cb0 * COLS;
 
@@ -341,7 +356,7 @@ __device__ inline void run_item64(const AsmMol& m, int rp, int cb0, int cb1, uin
         af[d][rb][ch] = *(const __attribute__((address_space(1))) v2d*)(
             Ad + ((int64_t)d * prow + row_base + 16 * rb + r16) * C::KC_ + 8 * ch + 2 * kg);
 
-  const int64_t node_bytes = 3 * prow * C::KC_ * 8;
+  const int64_t node_bytes = 3 * pcol * C::KC_ * 8;
   const int64_t block_bytes = (int64_t)COLS * C::KC_ * 8;
   uint32_t off[LPW];
 #pragma unroll
@@ -349,7 +364,7 @@ __device__ inline void run_item64(const AsmMol& m, int rp, int cb0, int cb1, uin
     int f = wave + NW * i;
     f = f < NFRAG ? f : 0;
     const int d = f / NCH, ch = f % NCH;
-    off[i] = (uint32_t)((((int64_t)d * prow + col_first + r16) * C::KC_ + 8 * ch + 2 * kg) * 8);
+    off[i] = (uint32_t)((((int64_t)d * pcol + col_first + r16) * C::KC_ + 8 * ch + 2 * kg) * 8);
   }
   const int T = nblk * nq;
   const int32_t* __restrict__ nkp = DEG ? m.nk : nullptr;
@@ -377,6 +392,7 @@ __device__ inline void run_item64(const AsmMol& m, int rp, int cb0, int cb1, uin
 
   typedef __attribute__((address_space(1))) double gdouble;
   gdouble* Bd = (gdouble*)static_cast<double*>(m.B);
+  gdouble* Td = (gdouble*)static_cast<double*>(rect ? m.Bt : m.B);
   // lane l holds column col0 + l%16 and rows kg + 4 r of each 16-row block
   auto finish_block = [&](int fb) {
     const int64_t colu = col_first + (int64_t)fb * COLS;
@@ -388,7 +404,12 @@ __device__ inline void run_item64(const AsmMol& m, int rp, int cb0, int cb1, uin
       for (int r = 0; r < 4; ++r) {
         const int row = (int)rowu + kg + 4 * r;
         const double v = acc[rb][r] * kTwoOverSqrtPi;
-        if (col < npair32 && row <= col) {
+        if (rect) {
+          if (col < ncol32 && row < npair32) {
+            Bd[(int64_t)row * ldb + col] = v;
+            Td[(int64_t)col * ldb + row] = v;
+          }
+        } else if (col < npair32 && row <= col) {
           Bd[(int64_t)row * ldb + col] = v;
           if (row < col) Bd[(int64_t)col * ldb + row] = v;
         }

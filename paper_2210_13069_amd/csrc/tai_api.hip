@@ -47,6 +47,7 @@ struct tai_ctx {
   Buf cmp, cmpU;          // low-rank compression: basis, Gram, tables; compressed moments
   Buf screen;             // screening: row counts / offsets and the kept count
   Buf part, partJ;        // adaptive boxes: supports, sort and lists; partitioned J intermediates
+  Buf partB;              // partitioned B: cross tables and every block's operands
   Buf mo;                 // orbital-basis Coulomb matrix: rho and Phi of every orbital
   Buf ct, ct_work;        // contraction: member tables; primitive-basis D and J
   Buf ct_host;            // pinned staging of the member tables
@@ -403,6 +404,19 @@ struct Items16 {
       }
     }
   }
+  // Items of a rectangular block (nrow rows against ncol columns, every
+  // entry): all (row panel, run of column blocks), runs as in add.
+  void add_rect(int mol, int64_t nrow, int64_t ncol, int64_t R, int64_t C, int64_t min_items = 0) {
+    const int64_t ncb = (ncol + C - 1) / C;
+    const int64_t nrp = (nrow + R - 1) / R;
+    int64_t chunk = std::max<int64_t>(1, 512 / C);
+    while (chunk > 1 && ((ncb + chunk - 1) / chunk) * nrp < min_items) chunk = (chunk + 1) / 2;
+    for (int64_t j = 0; j * chunk < ncb; ++j) {
+      std::vector<int4>& out = q[rr++ % tai::kAsm16Queues];
+      for (int64_t rp = 0; rp < nrp; ++rp)
+        out.push_back(int4{mol, (int)rp, (int)(j * chunk), (int)std::min((j + 1) * chunk, ncb)});
+    }
+  }
   size_t count() const {
     size_t n = 0;
     for (const auto& v : q) n += v.size();
@@ -544,7 +558,7 @@ int tai_destroy(tai_ctx* c) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
     for (Buf* b : {&c->nodes, &c->basis, &c->opA, &c->opEx, &c->opY, &c->opMu, &c->cmp, &c->cmpU, &c->screen, &c->part,
-                   &c->partJ, &c->mo, &c->ct, &c->ct_work, &c->asm_tab,
+                   &c->partJ, &c->partB, &c->mo, &c->ct, &c->ct_work, &c->asm_tab,
                    &c->asm_counter,
                    &c->jwork,
                    &c->b_nodes, &c->b_basis, &c->b_opA, &c->b_opEx, &c->b_opY, &c->b_opMu, &c->b_mols, &c->b_counter, &c->b_cmp})
@@ -827,6 +841,158 @@ int tai_moments_partitioned(tai_ctx* c, const tai_basis* b, const tai_params* p,
     e = tai::launch_moments_parts(db, p->n, tb, pairs, sp, nparts, M, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "moments kernel");
+  return TAI_OK;
+}
+
+// B over adaptive boxes (section 6.2 with Theorem 3.1): for every pair of
+// partitions s <= s' the columns' operand Y^(s,s')_{k,d} = (K_k^(s,s') M_d)^T
+// of partition s' (the cross tables of the two boxes), then one persistent
+// assembly launch over all blocks: the diagonal blocks s = s' as symmetric
+// molecules, the others as rectangular blocks mirrored into B^T's block.
+int tai_assemble_B_partitioned(tai_ctx* c, const double* M, const int32_t* counts, const double* boxes,
+                               int32_t nparts, const tai_params* p, void* B, int64_t ldb, void* stream) {
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = validate_params(c, p, false))) return r;
+  if (!M || !counts || !boxes || !B) return fail(c, TAI_ERR_INVALID_ARG, "a pointer is NULL");
+  if (nparts < 1 || nparts > tai::kMaxParts)
+    return fail(c, TAI_ERR_INVALID_ARG, "nparts must be in [1, " + std::to_string(tai::kMaxParts) + "]");
+  int64_t offs[tai::kMaxParts + 1];
+  offs[0] = 0;
+  tai::PartBoxes bx{};
+  bx.nparts = nparts;
+  for (int i = 0; i < nparts; ++i) {
+    if (counts[i] < 0) return fail(c, TAI_ERR_INVALID_ARG, "counts must be >= 0");
+    if (!std::isfinite(boxes[i]) || !(boxes[i] > 0)) return fail(c, TAI_ERR_INVALID_ARG, "boxes must be finite and > 0");
+    offs[i + 1] = offs[i] + counts[i];
+    bx.b[i] = boxes[i];
+  }
+  const int64_t total = offs[nparts];
+  if (total < 1 || total > 2147483647LL)
+    return fail(c, TAI_ERR_INVALID_ARG, "the partition counts must add up to a number in [1, 2^31-1]");
+  if (ldb < total) return fail(c, TAI_ERR_INVALID_ARG, "ldb must be >= the total pair count");
+  if (p->rank_tol > 0 || p->degree_tol > 0)
+    return fail(c, TAI_ERR_UNSUPPORTED, "tai_assemble_B_partitioned: rank_tol and degree_tol must be 0");
+  const int prec = p->prec, n = p->n, nq = p->nq;
+  if ((r = need_device(c))) return r;
+  c->size_key = pow2_at_least(total);
+  const bool p16 = use16(c, prec, n, nq), p32 = !p16 && use32(prec, n);
+  if (!p16 && !p32)
+    return fail(c, TAI_ERR_UNSUPPORTED,
+                "tai_assemble_B_partitioned runs on the persistent kernels only (FP64 and FP32 up to their inner "
+                "length, the split 16-bit forms with a shape for nq)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((r = ensure(c, c->nodes, tai::node_tables_bytes(nq, n)))) return r;
+  NodeTables tb = tai::carve_node_tables(c->nodes.p, nq, n);
+  // workspace: cross tables, then per partition A and exponents, then the
+  // column operands of the blocks s <= s'
+  int prow[tai::kMaxParts];
+  size_t oA[tai::kMaxParts], oE[tai::kMaxParts], oY[tai::kMaxParts * tai::kMaxParts];
+  const size_t kx_bytes = align256(sizeof(double) * (size_t)nparts * nparts * nq * n * n);
+  size_t bytes = kx_bytes;
+  for (int i = 0; i < nparts; ++i) {
+    prow[i] = prow_of(c, prec, n, nq, std::max<int64_t>(1, counts[i]));
+    oA[i] = bytes;
+    bytes += opA_bytes(prec, n, prow[i]);
+    oE[i] = bytes;
+    bytes += opEx_bytes(prow[i]);
+  }
+  for (int i = 0; i < nparts; ++i)
+    for (int j = i; j < nparts; ++j) {
+      oY[i * nparts + j] = bytes;
+      if (counts[i] > 0 && counts[j] > 0) bytes += opY_bytes(prec, n, nq, prow[j]);
+    }
+  if ((r = ensure(c, c->partB, bytes))) return r;
+  char* base = static_cast<char*>(c->partB.p);
+  double* Kx = reinterpret_cast<double*>(base);
+  const int ysh = tai::y_shift(prec, p->omega, nq);
+  const size_t es = prec == tai::kFP64 ? 8 : 4;
+  hipError_t e;
+  {
+    Timed tm(c, kStNodes, s);
+    e = tai::launch_nodes(p->omega, nq, n, boxes[nparts - 1], p->nodes, 0.0, tb, s);
+    if (e == hipSuccess) e = tai::launch_cross_tables(tb.t, nq, n, p->nodes, bx, Kx, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "node kernels");
+  for (int i = 0; i < nparts && e == hipSuccess; ++i) {
+    if (counts[i] == 0) continue;
+    Timed tm(c, kStPack, s);
+    e = tai::launch_pack(prec, M + 3 * (int64_t)n * offs[i], n, counts[i], prow[i], base + oA[i],
+                         reinterpret_cast<int32_t*>(base + oE[i]), s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "pack kernel");
+  std::vector<tai::AsmMol> am;
+  for (int i = 0; i < nparts && e == hipSuccess; ++i)
+    for (int j = i; j < nparts && e == hipSuccess; ++j) {
+      if (counts[i] == 0 || counts[j] == 0) continue;
+      // Y of the columns (partition j) through K^(i,j): rows on box i's grid
+      NodeTables tbp = tb;
+      tbp.K = Kx + ((int64_t)i * nparts + j) * nq * n * n;
+      {
+        Timed tm(c, kStProject, s);
+        e = tai::launch_project(prec, M + 3 * (int64_t)n * offs[j], n, counts[j], prow[j], nq, tbp,
+                                reinterpret_cast<int32_t*>(base + oE[j]), ysh, base + oY[i * nparts + j], s);
+      }
+      tai::AsmMol m;
+      m.A = base + oA[i];
+      m.Y = base + oY[i * nparts + j];
+      m.ex = reinterpret_cast<int32_t*>(base + oE[i]);
+      m.B = static_cast<char*>(B) + ((int64_t)offs[i] * ldb + offs[j]) * es;
+      m.ldb = ldb;
+      m.npair = counts[i];
+      m.prow = prow[i];
+      m.nq = nq;
+      m.kc = tai::operand_kc(prec, n);
+      m.tiles = prow[i] / tai::assemble_tile(prec);
+      m.tile0 = 0;
+      m.nk = nullptr;
+      m.ysh = ysh;
+      if (i != j) {
+        m.rect = 1;
+        m.exc = reinterpret_cast<int32_t*>(base + oE[j]);
+        m.pcol = prow[j];
+        m.ncol = counts[j];
+        m.Bt = static_cast<char*>(B) + ((int64_t)offs[j] * ldb + offs[i]) * es;
+      }
+      am.push_back(m);
+    }
+  if (e != hipSuccess) return hip_fail(c, e, "project kernel");
+  Items16 items;
+  const tai::Asm16Shape sh = p16 ? shape16(c, prec, n, nq) : tai::Asm16Shape{};
+  const int64_t R = p16 ? sh.rows : ring_rows(prec, n), Cc = p16 ? sh.cols : tai::kAsm32Cols;
+  const int64_t slots = (int64_t)(c->cus > 0 ? c->cus : 256) * (p16 ? sh.wgs_per_cu : 1);
+  for (size_t k = 0; k < am.size(); ++k) {
+    if (am[k].rect) items.add_rect((int)k, am[k].npair, am[k].ncol, R, Cc, 2 * slots / (int64_t)am.size());
+    else items.add((int)k, am[k].npair, R, Cc, 2 * slots / (int64_t)am.size());
+  }
+  const size_t mol_bytes = align256(sizeof(tai::AsmMol) * am.size());
+  const size_t tab_bytes = mol_bytes + items.bytes();
+  if ((r = ensure(c, c->asm_tab, tab_bytes))) return r;
+  if ((r = ensure(c, c->asm_counter, 256))) return r;
+  if ((r = ensure_host(c, c->asm_host, c->asm_host_done, tab_bytes))) return r;
+  char* hb = static_cast<char*>(c->asm_host.p);
+  std::memcpy(hb, am.data(), sizeof(tai::AsmMol) * am.size());
+  items.write(hb + mol_bytes);
+  if ((e = hipMemcpyAsync(c->asm_tab.p, hb, tab_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(c, e, "table upload");
+  if ((e = hipEventRecord(c->asm_host_done, s)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+  unsigned* counter = static_cast<unsigned*>(c->asm_counter.p);
+  if ((e = tai::launch_reset_counter(counter, s)) != hipSuccess) return hip_fail(c, e, "reset kernel");
+  const int nitems = (int)items.count();
+  const int nblocks = (int)std::min<int64_t>(nitems, slots);
+  const auto* mols_dev = static_cast<const tai::AsmMol*>(c->asm_tab.p);
+  const char* tab = static_cast<const char*>(c->asm_tab.p) + mol_bytes;
+  const auto* seg_dev = reinterpret_cast<const int*>(tab);
+  const auto* items_dev = reinterpret_cast<const int4*>(tab + Items16::seg_bytes());
+  {
+    Timed tm(c, kStAssemble, s);
+    if (p16)
+      e = tai::launch_assemble16(prec, tai::operand_kc(prec, n), tai::operand_dup_chunks(prec, n), sh, mols_dev,
+                                 items_dev, seg_dev, counter, nblocks, s);
+    else
+      e = launch_ring(prec, tai::operand_kc(prec, n), false, mols_dev, items_dev, seg_dev, counter, nblocks, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "assemble kernel");
   return TAI_OK;
 }
 

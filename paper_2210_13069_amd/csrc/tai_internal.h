@@ -133,6 +133,16 @@ struct AsmMol {
   // power of two folded into Y_{k,2} with w_k (y_shift); the column
   // exponents are lowered by it when B is scaled back
   int32_t ysh;
+  // Rectangular block (the persistent ring and 16-bit kernels only): rows
+  // from A (npair of them, exponents ex over prow), columns from Y (ncol of
+  // them, padded count pcol, exponents exc), every entry computed, written
+  // to B and mirrored to Bt (B^T's block).  rect 0: the symmetric block
+  // (upper triangle, mirror into B itself; exc, pcol, ncol, Bt unused).
+  int32_t rect = 0;
+  const int32_t* exc = nullptr;
+  int32_t pcol = 0;
+  int32_t ncol = 0;
+  void* Bt = nullptr;
 };
 
 // Per-molecule arguments of the preparation stages of a batch (nodes,

@@ -30,7 +30,7 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 SYMBOLS = ["tai_create", "tai_destroy", "tai_status_string", "tai_last_error", "tai_sync",
            "tai_quadrature", "tai_degrees", "tai_compress", "tai_moments", "tai_screen_pairs", "tai_moments_pairs",
            "tai_apply_J_pairs", "tai_apply_J_compressed", "tai_coulomb_mo", "tai_exchange", "tai_contract_pairs", "tai_apply_J_contracted", "tai_assemble_B", "tai_assemble_B_batched", "tai_apply_J", "tai_apply_J_noalloc",
-           "tai_partition_pairs", "tai_moments_partitioned", "tai_apply_J_partitioned", "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
+           "tai_partition_pairs", "tai_moments_partitioned", "tai_apply_J_partitioned", "tai_assemble_B_partitioned", "tai_tune", "tai_profile_enable", "tai_profile_read", "tai_peak_probe"]
 STAGES = ["nodes", "moments", "pack", "project", "assemble", "apply_J", "batched", "compress"]
 
 
@@ -118,6 +118,8 @@ def load_library(path=LIB_PATH):
     lib.tai_apply_J_partitioned.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                             ctypes.POINTER(tai_params), vp, vp, vp]
+    lib.tai_assemble_B_partitioned.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                               ctypes.c_int32, ctypes.POINTER(tai_params), vp, ctypes.c_int64, vp]
     lib.tai_apply_J_noalloc.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(tai_params), vp, vp, vp]
     lib.tai_peak_probe.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
     lib.tai_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -244,6 +246,20 @@ class Context:
         self.check(self.lib.tai_moments_partitioned(self.h, ctypes.byref(basis_arrays.struct), ctypes.byref(p),
                                                     _ptr(pairs), cnt, box, k, _ptr(M), _stream(stream)),
                    "tai_moments_partitioned")
+
+    def assemble_B_partitioned(self, M, counts, boxes, params, B, ldb=None, stream=None):
+        p = params if isinstance(params, tai_params) else make_params(params)
+        k = len(counts)
+        total = int(sum(counts))
+        ldb = total if ldb is None else ldb
+        esize = 8 if p.prec == FP64 else 4
+        if B.element_size() != esize or B.numel() < (total - 1) * int(ldb) + total:
+            raise ValueError(f"B must hold total x ldb {'FP64' if esize == 8 else 'FP32'} entries "
+                             f"(got {B.dtype}, {B.numel()} entries)")
+        cnt = (ctypes.c_int32 * k)(*[int(x) for x in counts])
+        box = (ctypes.c_double * k)(*[float(x) for x in boxes])
+        self.check(self.lib.tai_assemble_B_partitioned(self.h, _ptr(M), cnt, box, k, ctypes.byref(p), _ptr(B),
+                                                       int(ldb), _stream(stream)), "tai_assemble_B_partitioned")
 
     def apply_J_pairs(self, M, nb, pairs, npk, params, D, J, stream=None):
         p = params if isinstance(params, tai_params) else make_params(params)
@@ -440,6 +456,18 @@ def moments_partitioned(basis, params, pairs, counts, boxes, device=0):
     M = torch.empty(3 * n * total, dtype=torch.float64, device=torch.device("cuda", device))
     context(device).moments_partitioned(ba, params, pairs, counts, boxes, M)
     return M
+
+
+def assemble_B_partitioned(M, counts, boxes, params, prec=FP64, ldb=None, device=0):
+    """B over adaptive boxes (total x total, FP64 for prec FP64 else FP32),
+    rows and columns in the order of the concatenated partition lists."""
+    import torch
+    total = int(sum(counts))
+    ldb = total if ldb is None else ldb
+    dt = torch.float64 if prec == FP64 else torch.float32
+    B = torch.empty((total, ldb), dtype=dt, device=M.device)
+    context(device).assemble_B_partitioned(M, counts, boxes, make_params(params, prec), B, ldb)
+    return B
 
 
 def apply_J_partitioned(M, D, pairs, counts, boxes, params, prec=FP64, device=0):

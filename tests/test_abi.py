@@ -384,3 +384,27 @@ def test_moments_partitioned_argument_checks(hctx):
     assert call() == tai.TAI_ERR_NOT_READY
     # the boxes give the half-widths: params->L is not read
     assert call(params=_params(L=0.0)) == tai.TAI_ERR_NOT_READY
+
+
+def test_assemble_B_partitioned_argument_checks(hctx):
+    lib, h = hctx.lib, hctx.h
+    dummy = ctypes.c_void_p(16)
+    mk = lambda vals, t: (t * len(vals))(*vals)
+    good_c = mk([4, 6], ctypes.c_int32)
+    good_b = mk([3.0, 5.0], ctypes.c_double)
+    p = _params()
+    call = lambda c=good_c, bx=good_b, k=2, params=p, M=dummy, B=dummy, ldb=10: \
+        lib.tai_assemble_B_partitioned(h, M, c, bx, k, ctypes.byref(params), B, ldb, None)
+    assert call(c=mk([-1, 6], ctypes.c_int32)) == tai.TAI_ERR_INVALID_ARG
+    assert call(c=mk([0, 0], ctypes.c_int32)) == tai.TAI_ERR_INVALID_ARG
+    assert call(bx=mk([0.0, 5.0], ctypes.c_double)) == tai.TAI_ERR_INVALID_ARG
+    assert call(bx=mk([3.0, float("nan")], ctypes.c_double)) == tai.TAI_ERR_INVALID_ARG
+    for k in (0, 17):
+        assert call(k=k) == tai.TAI_ERR_INVALID_ARG
+    assert call(M=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(B=None) == tai.TAI_ERR_INVALID_ARG
+    assert call(ldb=9) == tai.TAI_ERR_INVALID_ARG
+    assert call(params=_params(rank_tol=1e-6)) == tai.TAI_ERR_UNSUPPORTED
+    assert call(params=_params(degree_tol=1e-8)) == tai.TAI_ERR_UNSUPPORTED
+    assert call() == tai.TAI_ERR_NOT_READY
+    assert call(params=_params(L=0.0)) == tai.TAI_ERR_NOT_READY   # params->L is not read

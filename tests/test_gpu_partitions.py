@@ -158,3 +158,78 @@ def test_moments_partitioned_equal_per_partition_calls(tai, case):
         assert torch.equal(Mb[3 * P.n * off:3 * P.n * (off + c)], Mp), (case, off, c)
         off += c
     assert off == sum(counts)
+
+
+B_TOL = {0: 1e-10, 1: 1e-6, 2: 3e-5, 3: 1e-6, 4: 1e-6}
+
+
+@pytest.mark.parametrize("prec", [0, 1, 4, 3, 2])
+def test_assemble_B_partitioned_matches_oracle(tai, prec):
+    """B over three boxes (diagonal blocks symmetric, the others rectangular
+    and mirrored) against Algorithm 1 on the pairs' boxes at sampled entries,
+    in every arithmetic; B is exactly symmetric (the mirror copies)."""
+    import torch
+    b, P = _small()
+    tau = 1e-16
+    part, boxes = _oracle_parts(b, tau, 3)
+    t, w = T.time_nodes(P.omega, P.nq)
+    pm = T.partition_moments(b.center, b.alpha, b.lxyz, part, boxes, P.n)
+    pairs, counts, gboxes = tai.partition_pairs(b, tau, 3)
+    Mg = tai.moments_partitioned(b, P, pairs, counts, gboxes)
+    Bg = tai.assemble_B_partitioned(Mg, counts, gboxes, P, prec=prec).cpu().numpy().astype(np.float64)
+    order = pairs.cpu().numpy().astype(np.int64)
+    assert np.array_equal(Bg, Bg.T)
+    rng = np.random.default_rng(9)
+    total = len(order)
+    i = np.concatenate([rng.integers(0, total, 300), [0, total - 1, total - 1]])
+    j = np.concatenate([rng.integers(0, total, 300), [total - 1, 0, total - 1]])
+    ref = T.B_partitioned_entries(pm, boxes, t, w, P.n, order[i], order[j])
+    diag = T.B_partitioned_entries(pm, boxes, t, w, P.n, order, order)
+    scale = np.max(np.abs(diag))
+    err = np.max(np.abs(Bg[i, j] - ref)) / scale
+    assert err <= B_TOL[prec], (prec, err)
+
+
+def test_assemble_B_partitioned_one_box_is_the_plain_B(tai):
+    """One partition is the plain B on the box of the largest support: the
+    same operands and kernels, the same bits (FP64 and F16X3)."""
+    import torch
+    b, P = _small()
+    pairs, counts, boxes = tai.partition_pairs(b, 1e-16, 1)
+    Mg = tai.moments_partitioned(b, P, pairs, counts, boxes)
+    Pl = dataclasses.replace(P, L=boxes[0])
+    Ml = tai.moments(b, Pl)
+    for prec in (0, 4):
+        Bp = tai.assemble_B_partitioned(Mg, counts, boxes, P, prec=prec)
+        Bl = tai.assemble_B(Ml, Pl, prec=prec)
+        assert torch.equal(Bp, Bl), prec
+
+
+@pytest.mark.parametrize("case,prec", [("small", 0), ("spd400", 0), ("spd400", 4)])
+def test_assemble_B_partitioned_times_density_is_the_partitioned_J(tai, case, prec):
+    """B over boxes times the pair densities, unpacked, is the J of
+    tai_apply_J_partitioned (the grid route through the same cross tables):
+    a property of the whole matrix that holds at any size, here up to the
+    Nb = 400 workload with four boxes (80200 pairs)."""
+    import torch
+    if case == "small":
+        b, P = _small()
+        pairs, counts, boxes = tai.partition_pairs(b, 1e-16, 3)
+    else:
+        b, P = I.spd400(omega=0.3)
+        pairs, counts, boxes = tai.partition_pairs(b, 1e-20, 4)
+    Mg = tai.moments_partitioned(b, P, pairs, counts, boxes)
+    D = I.random_density(np.random.default_rng(12), b)
+    Dg = torch.as_tensor(D, device=Mg.device)
+    Jg = tai.apply_J_partitioned(Mg, Dg, pairs, counts, boxes, P).cpu().numpy()
+    Bg = tai.assemble_B_partitioned(Mg, counts, boxes, P, prec=prec, ldb=tai.aligned_ldb(sum(counts)))
+    order = pairs.long()
+    Dt = torch.as_tensor(T.density_pairs(D), device=Mg.device)[order]
+    Jp = (Bg[:, :len(order)] @ Dt.to(Bg.dtype)).double().cpu().numpy()
+    full = np.zeros(b.npair)
+    full[order.cpu().numpy()] = Jp
+    Jb = T.unpack_pairs(full, b.nb)
+    del Bg
+    torch.cuda.empty_cache()
+    err = np.linalg.norm(Jb - Jg, 2) / np.linalg.norm(Jg, 2)
+    assert err <= (1e-12 if prec == 0 else 1e-6), (case, prec, err)
