@@ -684,7 +684,21 @@ def main():
             "norb": NORB, "rank_tol": RANK_TOL_J, "ms_per_call": round(ms_mc, 3),
             "speedup_vs_uncompressed": round(ms_mo / ms_mc, 3),
             "normwise_vs_uncompressed_gpu": float((Jmo_c - Jmo).abs().max() / Jmo.abs().max())}
-        del Jmo_c
+        # the FP32 pair contraction (the grid sums stay FP64)
+        jparams_m32 = tai.make_params(jP, tai.FP32)
+        Jmo_32 = torch.empty_like(Jmo)
+        log(f"orbital-basis Coulomb matrix fp32: norb={NORB}")
+        for it in range(W + K):
+            if it == W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            ctx.coulomb_mo(Mj, jb.nb, jparams_m32, Qo, NORB, Jmo_32)
+        torch.cuda.synchronize()
+        ms_m32 = (time.perf_counter() - t0) * 1e3 / K
+        japply["coulomb_mo_fp32"] = {
+            "norb": NORB, "ms_per_call": round(ms_m32, 3), "speedup_vs_fp64": round(ms_mo / ms_m32, 3),
+            "normwise_vs_fp64_gpu": float((Jmo_32 - Jmo).abs().max() / Jmo.abs().max())}
+        del Jmo_c, Jmo_32
         del Mj, Jj, Js, Mjs, Jmo
         torch.cuda.empty_cache()
         # the long-range exchange matrix (appendix B) by its factorized form:
