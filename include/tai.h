@@ -340,8 +340,10 @@ int tai_coulomb_mo(tai_ctx* ctx, const double* M, int32_t nb, const int32_t* pai
    Kx: DEVICE double [nb][nb], written in full.  The context keeps
    2 norb nb n^3 doubles of grid tensors (at most 64 GiB, else
    TAI_ERR_INVALID_ARG).  prec TAI_FP64 or TAI_FP32 (the rho contractions);
-   rank_tol > 0 runs it on the compressed grid.  Each (j, mu) costs one rho
-   over all listed pairs, so the call is meant for small bases. */
+   rank_tol > 0 runs it on the compressed grid.  Each (j, mu) costs a
+   contraction over the Nb pairs that hold mu (2 n^3 Nb flops) and the mode
+   products of one grid tensor (6 nq n^4); the grid tensors of all (j, mu)
+   run through the mode products in chunks of at most 4 GiB. */
 int tai_exchange(tai_ctx* ctx, const double* M, int32_t nb, const int32_t* pairs, int32_t npk,
                  const tai_params* params, const double* Q, int32_t norb, double* Kx, void* stream);
 
