@@ -21,9 +21,10 @@
 //    columns from R on taken as zero: zero rows of U and zero rows and
 //    columns of Kc add nothing to any product, and the result is that of
 //    rank R.
-//  * One refinement pass: Y = V1^T W in the first basis V1, then the Gram
-//    matrix of Y (nearly diagonal, its entries (r, s) rounded relative to
-//    sigma_r sigma_s rather than sigma_1^2) and its Jacobi eigenvectors V2;
+//  * One refinement pass: Y = V1^T W in the first basis V1 (formed batch by
+//    batch inside the Gram kernel, never stored), then the Gram matrix of Y
+//    (nearly diagonal, its entries (r, s) rounded relative to sigma_r
+//    sigma_s rather than sigma_1^2) and its Jacobi eigenvectors V2;
 //    the basis is V = V1 V2.  Forming W W^T alone resolves sigma_r only to
 //    about 1e-16 sigma_1^2 / sigma_r; after the pass the values and the kept
 //    subspace carry errors of about 1e-16 sigma_1 / sigma_r, as an SVD of W.
@@ -51,6 +52,13 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // fixed order at the end, and each tile is written with its mirror.  The
 // v_mfma_f64_16x16x4 operands of both sides come from s_m (lane l: row
 // 16 I + l % 16, k0 + l / 16).
+//
+// With XF (the refinement pass) the Gram matrix is that of Y = V1^T W: each
+// staged batch is first turned into its columns of Y in place, y_k =
+// V1^T w_k, on the matrix cores (V1 in dynamic LDS, padded with zeros to
+// whole 16 x 16 tiles); a wave takes whole groups of 16 k values, reads
+// all their rows before it writes them, and one barrier separates the
+// transform from the Gram products.  Y itself never reaches memory.
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kGramKB = 32;               // pairs per staged batch and direction
 constexpr int kGramK = 3 * kGramKB;       // k values per batch
@@ -59,15 +67,17 @@ constexpr int kGramPad = 65;              // LDS length of one k value's row (do
                                           // the staging stores of 32 pairs hit distinct banks)
 constexpr int kGramTiles = 10;            // tiles I <= J of G for n <= 64
 
-__device__ __forceinline__ void gram_body(const double* __restrict__ M, int n, int64_t npair, int64_t chunk,
-                                          int nchunk, double* __restrict__ part) {
+template <bool XF>
+__device__ __forceinline__ void gram_body(const double* __restrict__ M, const double* __restrict__ V1, int n,
+                                          int64_t npair, int64_t chunk, int nchunk, double* __restrict__ part) {
   // the staged batch, and at the end the tiles of waves 1..3
   constexpr int kStage = kGramK * kGramPad, kSums = 3 * kGramTiles * 4 * 64;
   __shared__ double s_m[kStage > kSums ? kStage : kSums];
+  extern __shared__ double s_v1[];   // XF: [16 T][16 T] V1 with zero padding
   const int64_t q0 = (int64_t)blockIdx.x * chunk;
   const int64_t q1 = q0 + chunk < npair ? q0 + chunk : npair;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int T = (n + 15) / 16, ntile = T * (T + 1) / 2;
+  const int T = (n + 15) / 16, ntile = T * (T + 1) / 2, NP = 16 * T;
   int ti[kGramTiles], tj[kGramTiles];
   v4d acc[kGramTiles];
 #pragma unroll
@@ -81,8 +91,14 @@ __device__ __forceinline__ void gram_body(const double* __restrict__ M, int n, i
     ti[u] = I;
     tj[u] = I + t;
   }
-  // rows n .. 16 T - 1 of every k stay zero
+  // rows n .. 16 T - 1 of every k stay zero (with XF the transform writes
+  // zeros there too: the padded columns of V1 are zero)
   for (int e = threadIdx.x; e < kStage; e += 256) s_m[e] = 0.0;
+  if (XF)
+    for (int e = threadIdx.x; e < NP * NP; e += 256) {
+      const int a = e / NP, r = e % NP;
+      s_v1[e] = (a < n && r < n) ? V1[a * n + r] : 0.0;
+    }
   // staging: thread t reads pair qb + t % 32 of rows t / 32 + 8 i of each
   // direction (256-byte runs of a moment row), one batch ahead in registers
   constexpr int kRowStep = 256 / kGramKB, kRowsPer = (kMaxN + kRowStep - 1) / kRowStep;
@@ -111,6 +127,33 @@ __device__ __forceinline__ void gram_body(const double* __restrict__ M, int n, i
       }
     __syncthreads();
     if (qb + kGramKB < q1) fetch(qb + kGramKB);
+    if (XF) {
+      // y_k(r) = sum_a V1(a, r) w_k(a) for the k groups kt = wave, wave + 4:
+      // lane l holds the A operand w_{16 kt + l % 16}(a0 + l / 16) and the
+      // B operand V1(a0 + l / 16, 16 R + l % 16); the result tile (k, r)
+      // lands on lane l as rows k = 16 kt + l / 16 + 4 x, column l % 16
+      constexpr int kKT = kGramK / 16;
+      for (int kt = wave; kt < kKT; kt += 4) {
+        v4d y[4];
+#pragma unroll
+        for (int R = 0; R < 4; ++R) y[R] = v4d{0.0, 0.0, 0.0, 0.0};
+        const double* arow = s_m + (16 * kt + (lane & 15)) * kGramPad + (lane >> 4);
+        const double* brow = s_v1 + (lane >> 4) * NP + (lane & 15);
+        for (int ab = 0; ab < NP; ab += 4) {
+          const double av = arow[ab];
+#pragma unroll
+          for (int R = 0; R < 4; ++R)
+            if (R < T) y[R] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, brow[ab * NP + 16 * R], y[R], 0, 0, 0);
+        }
+#pragma unroll
+        for (int R = 0; R < 4; ++R)
+          if (R < T)
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+              s_m[(16 * kt + (lane >> 4) + 4 * x) * kGramPad + 16 * R + (lane & 15)] = y[R][x];
+      }
+      __syncthreads();
+    }
 #pragma unroll
     for (int k0 = 0; k0 < kGramKW; k0 += 4) {
 #pragma unroll
@@ -149,17 +192,37 @@ __device__ __forceinline__ void gram_body(const double* __restrict__ M, int n, i
   }
 }
 
+// pass 0: the Gram matrix of W; pass 1 (dynamic LDS of gram_v1_bytes):
+// that of Y = V1^T W
 __global__ void __launch_bounds__(256)
 gram_kernel(const double* __restrict__ M, int n, int64_t npair, int64_t chunk, double* __restrict__ part) {
-  gram_body(M, n, npair, chunk, (int)gridDim.x, part);
+  gram_body<false>(M, nullptr, n, npair, chunk, (int)gridDim.x, part);
 }
 
-// batched: molecule blockIdx.y, the moments (pass 0) or Y (pass 1)
 __global__ void __launch_bounds__(256)
-gram_batch_kernel(const CmpMol* __restrict__ tab, int n, int pass) {
+gram_y_kernel(const double* __restrict__ M, const double* __restrict__ V1, int n, int64_t npair, int64_t chunk,
+              double* __restrict__ part) {
+  gram_body<true>(M, V1, n, npair, chunk, (int)gridDim.x, part);
+}
+
+// batched: molecule blockIdx.y
+__global__ void __launch_bounds__(256)
+gram_batch_kernel(const CmpMol* __restrict__ tab, int n) {
   const CmpMol& m = tab[blockIdx.y];
   if ((int)blockIdx.x >= m.nchunk) return;
-  gram_body(pass == 0 ? m.M : m.Y, n, m.npair, m.chunk, m.nchunk, m.part);
+  gram_body<false>(m.M, nullptr, n, m.npair, m.chunk, m.nchunk, m.part);
+}
+
+__global__ void __launch_bounds__(256)
+gram_y_batch_kernel(const CmpMol* __restrict__ tab, int n) {
+  const CmpMol& m = tab[blockIdx.y];
+  if ((int)blockIdx.x >= m.nchunk) return;
+  gram_body<true>(m.M, m.V1, n, m.npair, m.chunk, m.nchunk, m.part);
+}
+
+inline size_t gram_v1_bytes(int n) {
+  const size_t np = 16 * (size_t)((n + 15) / 16);
+  return 8 * np * np;
 }
 
 // G[e] = sum over the chunks of part[e][c], one work group per entry: thread
@@ -412,16 +475,14 @@ compress_moments_kernel(const double* __restrict__ M, int n, int64_t npair, cons
   compress_moments_body<NMAX>(M, n, npair, V, R, keep, U);
 }
 
-// batched, molecule blockIdx.z: pass 0 Y = V1^T M at full length, pass 1
-// U = V^T M at length n with the columns of V from the molecule's rank on
-// taken as zero
+// batched, molecule blockIdx.z: U = V^T M at length n with the columns of V
+// from the molecule's rank on taken as zero
 template <int NMAX>
 __global__ void __launch_bounds__(256)
-compress_moments_batch_kernel(const CmpMol* __restrict__ tab, int n, int pass) {
+compress_moments_batch_kernel(const CmpMol* __restrict__ tab, int n) {
   const CmpMol& m = tab[blockIdx.z];
   if ((int64_t)blockIdx.x * 256 >= m.npair) return;
-  if (pass == 0) compress_moments_body<NMAX>(m.M, n, m.npair, m.V1, n, n, m.Y);
-  else compress_moments_body<NMAX>(m.M, n, m.npair, m.V, n, *m.rank, m.U);
+  compress_moments_body<NMAX>(m.M, n, m.npair, m.V, n, *m.rank, m.U);
 }
 
 // V = V1 V2 (n x n): one work group per row a, one thread per column r.
@@ -536,11 +597,15 @@ void launch_moments_in(const double* M, int n, int64_t npair, const double* V, i
   else if (n <= 48) hipLaunchKernelGGL(compress_moments_kernel<48>, g, dim3(256), 0, s, M, n, npair, V, R, keep, U);
   else hipLaunchKernelGGL(compress_moments_kernel<64>, g, dim3(256), 0, s, M, n, npair, V, R, keep, U);
 }
-void launch_gram_eig(const double* M, int n, int64_t npair, double tol, double rel, double floor_rel,
-                     const CompressWork& w, double* V, hipStream_t s) {
+// eigenpairs of the Gram matrix of W (V1 null) or of Y = V1^T W
+void launch_gram_eig(const double* M, const double* V1, int n, int64_t npair, double tol, double rel,
+                     double floor_rel, const CompressWork& w, double* V, hipStream_t s) {
   const int64_t chunk = (npair + w.nchunk - 1) / w.nchunk;
   const int nchunk = (int)((npair + chunk - 1) / chunk);
-  hipLaunchKernelGGL(gram_kernel, dim3(nchunk), dim3(256), 0, s, M, n, npair, chunk, w.part);
+  if (V1)
+    hipLaunchKernelGGL(gram_y_kernel, dim3(nchunk), dim3(256), gram_v1_bytes(n), s, M, V1, n, npair, chunk, w.part);
+  else
+    hipLaunchKernelGGL(gram_kernel, dim3(nchunk), dim3(256), 0, s, M, n, npair, chunk, w.part);
   hipLaunchKernelGGL(gram_sum_kernel, dim3(n * n), dim3(kGramSumThreads), 0, s, w.part, nchunk, w.G);
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, s, w.G, n, tol, rel, floor_rel, w.sigma, V,
                      w.rank);
@@ -548,16 +613,16 @@ void launch_gram_eig(const double* M, int n, int64_t npair, double tol, double r
 }  // namespace
 
 hipError_t launch_compress_basis(const double* M, int n, int64_t npair, double tol, const CompressWork& w,
-                                 double* Y, hipStream_t s) {
+                                 hipStream_t s) {
   // V1 from W W^T need only be close: the refinement pass corrects it, and
   // entries below 1e-14 of the trace are the Gram matrix's own rounding
-  launch_gram_eig(M, n, npair, tol, 1e-10, 1e-14, w, w.V1, s);
-  launch_moments_in(M, n, npair, w.V1, n, n, Y, s);   // Y = V1^T W
-  // V2, sigma, rank from Y Y^T: a relative test (its entries are rounded
-  // relative to sigma_r sigma_s), and a floor of 1e-28 of the trace, i.e.
-  // (1e-14 sigma_1)^2: rotating entries below it moves no singular value
-  // above 1e-14 sigma_1 and only lengthens the sweeps over the noise block
-  launch_gram_eig(Y, n, npair, tol, 1e-13, 1e-28, w, w.V2, s);
+  launch_gram_eig(M, nullptr, n, npair, tol, 1e-10, 1e-14, w, w.V1, s);
+  // V2, sigma, rank from Y Y^T, Y = V1^T W formed inside the Gram kernel: a
+  // relative test (its entries are rounded relative to sigma_r sigma_s), and
+  // a floor of 1e-28 of the trace, i.e. (1e-14 sigma_1)^2: rotating entries
+  // below it moves no singular value above 1e-14 sigma_1 and only lengthens
+  // the sweeps over the noise block
+  launch_gram_eig(M, w.V1, n, npair, tol, 1e-13, 1e-28, w, w.V2, s);
   hipLaunchKernelGGL(basis_product_kernel, dim3(n), dim3(64), 0, s, w.V1, w.V2, n, w.V);
   return hipGetLastError();
 }
@@ -565,7 +630,7 @@ hipError_t launch_compress_basis(const double* M, int n, int64_t npair, double t
 size_t cmp_mol_bytes(int n, int nq, int64_t npair) {
   const size_t nn = (size_t)n * n;
   return align256(8 * nn * compress_nchunk(npair)) + align256(8 * nn) * 4 + align256(8 * (size_t)n) +
-         align256(sizeof(int32_t)) + align256(8 * 3 * (size_t)n * npair) * 2 + align256(8 * (size_t)nq * nn);
+         align256(sizeof(int32_t)) + align256(8 * 3 * (size_t)n * npair) + align256(8 * (size_t)nq * nn);
 }
 
 CmpMol carve_cmp_mol(void* base, int n, int nq, int64_t npair, const double* M, double tol, const double* K,
@@ -586,7 +651,6 @@ CmpMol carve_cmp_mol(void* base, int n, int nq, int64_t npair, const double* M, 
   m.V = reinterpret_cast<double*>(p); p += align256(8 * nn);
   m.sigma = reinterpret_cast<double*>(p); p += align256(8 * (size_t)n);
   m.rank = reinterpret_cast<int32_t*>(p); p += align256(sizeof(int32_t));
-  m.Y = reinterpret_cast<double*>(p); p += align256(8 * 3 * (size_t)n * npair);
   m.U = reinterpret_cast<double*>(p); p += align256(8 * 3 * (size_t)n * npair);
   m.K = K;
   m.Kc = reinterpret_cast<double*>(p);
@@ -597,24 +661,24 @@ CmpMol carve_cmp_mol(void* base, int n, int nq, int64_t npair, const double* M, 
 hipError_t launch_compress_batch(const CmpMol* tab, int ncm, int n, int nq, int64_t max_npair, int max_nchunk,
                                  hipStream_t s) {
   const unsigned mb = nblk(max_npair, 256);
-  auto moments_in = [&](int pass) {
+  auto moments_in = [&]() {
     const dim3 g(mb, 3, ncm);
-    if (n <= 16) hipLaunchKernelGGL(compress_moments_batch_kernel<16>, g, dim3(256), 0, s, tab, n, pass);
-    else if (n <= 32) hipLaunchKernelGGL(compress_moments_batch_kernel<32>, g, dim3(256), 0, s, tab, n, pass);
-    else if (n <= 48) hipLaunchKernelGGL(compress_moments_batch_kernel<48>, g, dim3(256), 0, s, tab, n, pass);
-    else hipLaunchKernelGGL(compress_moments_batch_kernel<64>, g, dim3(256), 0, s, tab, n, pass);
+    if (n <= 16) hipLaunchKernelGGL(compress_moments_batch_kernel<16>, g, dim3(256), 0, s, tab, n);
+    else if (n <= 32) hipLaunchKernelGGL(compress_moments_batch_kernel<32>, g, dim3(256), 0, s, tab, n);
+    else if (n <= 48) hipLaunchKernelGGL(compress_moments_batch_kernel<48>, g, dim3(256), 0, s, tab, n);
+    else hipLaunchKernelGGL(compress_moments_batch_kernel<64>, g, dim3(256), 0, s, tab, n);
   };
   auto gram_eig = [&](int pass, double rel, double floor_rel) {
-    hipLaunchKernelGGL(gram_batch_kernel, dim3(max_nchunk, ncm), dim3(256), 0, s, tab, n, pass);
+    if (pass == 0) hipLaunchKernelGGL(gram_batch_kernel, dim3(max_nchunk, ncm), dim3(256), 0, s, tab, n);
+    else hipLaunchKernelGGL(gram_y_batch_kernel, dim3(max_nchunk, ncm), dim3(256), gram_v1_bytes(n), s, tab, n);
     hipLaunchKernelGGL(gram_sum_batch_kernel, dim3(n * n, ncm), dim3(kGramSumThreads), 0, s, tab);
     hipLaunchKernelGGL(jacobi_batch_kernel, dim3(ncm), dim3(kJacobiThreads), 0, s, tab, n, pass, rel, floor_rel);
   };
   // the two passes of launch_compress_basis, with its tolerances
   gram_eig(0, 1e-10, 1e-14);
-  moments_in(0);
   gram_eig(1, 1e-13, 1e-28);
   hipLaunchKernelGGL(basis_product_batch_kernel, dim3(n, ncm), dim3(64), 0, s, tab, n);
-  moments_in(1);
+  moments_in();
   hipLaunchKernelGGL(compress_tables_batch_kernel, dim3(nq, ncm), dim3(256), 0, s, tab, n, nq);
   return hipGetLastError();
 }

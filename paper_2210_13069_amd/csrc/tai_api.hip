@@ -1116,7 +1116,7 @@ static int compress_impl(tai_ctx* c, const double* M, int64_t npair, const tai_p
   hipError_t e;
   {
     Timed tm(c, kStCompress, s);
-    e = tai::launch_compress_basis(M, n, npair, p->rank_tol, *w, static_cast<double*>(c->cmpU.p), s);
+    e = tai::launch_compress_basis(M, n, npair, p->rank_tol, *w, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "compression basis kernels");
   int32_t host = 0;

@@ -257,7 +257,7 @@ struct CompressWork {
   double* G;       // [n][n]
   double* V;       // [n][n] the basis V1 V2
   double* V1;      // [n][n] eigenvectors of W W^T
-  double* V2;      // [n][n] eigenvectors of Y Y^T, Y = V1^T W
+  double* V2;      // [n][n] eigenvectors of Y Y^T, Y = V1^T W (never stored)
   double* sigma;   // [n]
   double* Kc;      // [nq][R][R]
   int32_t* rank;   // [1]
@@ -265,9 +265,8 @@ struct CompressWork {
 };
 size_t compress_work_bytes(int n, int nq, int64_t npair);
 CompressWork carve_compress_work(void* base, int n, int nq, int64_t npair);
-// Y: workspace [3][n][npair]
 hipError_t launch_compress_basis(const double* M, int n, int64_t npair, double tol, const CompressWork& w,
-                                 double* Y, hipStream_t s);
+                                 hipStream_t s);
 // U [3][R][npair] and Kc [nq][R][R] at inner length R with the basis columns
 // from `keep` on taken as zero (keep <= R: the kept rank, R its padding).
 hipError_t launch_compress_operands(const double* M, int n, int64_t npair, int R, int keep, int nq,
@@ -290,7 +289,6 @@ struct CmpMol {
   double* V;           // [n][n]
   double* sigma;       // [n]
   int32_t* rank;       // [1]
-  double* Y;           // [3][n][npair]
   double* U;           // [3][n][npair]
   const double* K;     // [nq][n][n] the molecule's node tables
   double* Kc;          // [nq][n][n]
