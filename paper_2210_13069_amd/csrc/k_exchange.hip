@@ -351,6 +351,119 @@ exch_slab_kernel(const double* __restrict__ X, const double* __restrict__ K, int
   }
 }
 
+// The slab products of exch_slab_kernel for 33 <= n <= 40 and one table set,
+// two slabs per work group side by side: U = K_k [X(s0) X(s0 + 1)] is one
+// n x 2n product and S = [U(s0); U(s0 + 1)] K_k^T one 2n x n product, so the
+// 16-wide tiles pad only K_k's side (n to 48; 2n is at most 80 = 5 tiles)
+// and the inner index runs to 40 instead of 48: 15 tiles per product on four
+// waves instead of 9 per slab.  Grid (ceil(nslab / 2), KC), 256 threads; the
+// node runs, the K_k prefetch and the output T1[t][k][a0][a1 n + a2] are
+// those of exch_slab_kernel.
+template <int NT, int CT, int NK>
+__global__ void __launch_bounds__(256)
+exch_slab2_kernel(const double* __restrict__ X, const double* __restrict__ K, int n, int nq, int64_t nslab,
+                  double* __restrict__ T1, int64_t xmod) {
+  constexpr int SB = 2;
+  constexpr int XR = 4 * NK;                 // rows of Xs and Us: the inner index, zero from n on
+  constexpr int XC = 16 * CT, XPS = XC + 1;  // packed columns sb n + a2, zero from SB n on
+  constexpr int KR = 16 * NT, KC4 = 4 * NK, KPS = KC4 + 1;
+  constexpr int TILES = NT * CT;
+  constexpr int XPER = (XR * XC + 255) / 256, KPER = (KR * KC4 + 255) / 256;
+  __shared__ double Xs[XR * XPS];
+  __shared__ double Us[XR * XPS];
+  __shared__ double Ks[KR * KPS];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int64_t s0 = (int64_t)blockIdx.x * SB;
+  const int64_t n2 = (int64_t)n * n;
+  {
+    double xr[XPER];
+#pragma unroll
+    for (int i = 0; i < XPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int a1 = e / XC, col = e - a1 * XC;
+      const int sb = col / n, a2 = col - sb * n;
+      const int64_t sl = s0 + sb;
+      xr[i] = 0.0;
+      if (e < XR * XC && a1 < n && sb < SB && sl < nslab) {
+        const int64_t t = sl / n, a0 = sl - t * n;
+        xr[i] = X[((t % xmod) * n + a0) * n2 + a1 * n + a2];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < XPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < XR * XC) Xs[(e / XC) * XPS + e % XC] = xr[i];
+    }
+  }
+  const int kper = (nq + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int k0 = (int)blockIdx.y * kper, k1 = min(nq, k0 + kper);
+  double kr[KPER];
+  auto load_k = [&](int k) {
+    const double* Kk = K + (int64_t)k * n2;
+#pragma unroll
+    for (int i = 0; i < KPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int a = e / KC4, b = e - a * KC4;
+      kr[i] = (e < KR * KC4 && a < n && b < n) ? Kk[a * n + b] : 0.0;
+    }
+  };
+  if (k0 < k1) load_k(k0);
+  for (int k = k0; k < k1; ++k) {
+    lds_barrier();  // the previous node's Ks and Us reads are done (and Xs written)
+#pragma unroll
+    for (int i = 0; i < KPER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < KR * KC4) Ks[(e / KC4) * KPS + e % KC4] = kr[i];
+    }
+    if (k + 1 < k1) load_k(k + 1);
+    lds_barrier();
+    // U = K_k [X(s0) X(s0 + 1)]: tile (i, jj) of rows 16 i (i1) and packed
+    // columns 16 jj; rows from XR on are K_k's zero padding and are dropped
+    tile_products<NK, TILES>(
+        wave,
+        [&](int tt, int st, double& a, double& b) {
+          const int i = tt / CT, jj = tt - i * CT;
+          a = Ks[(16 * i + r16) * KPS + 4 * st + kg];
+          b = Xs[(4 * st + kg) * XPS + 16 * jj + r16];
+        },
+        [&](int tt, const v4d& acc) {
+          const int i = tt / CT, jj = tt - i * CT;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i1 = 16 * i + kg + 4 * r;
+            if (i1 < XR) Us[i1 * XPS + 16 * jj + r16] = acc[r];
+          }
+        });
+    lds_barrier();
+    // S = [U(s0); U(s0 + 1)] K_k^T: tile (ri, jj) of packed rows 16 ri
+    // (sb n + i1) and columns 16 jj (i2).  An inner index a2 >= n reads the
+    // next slab's column of U, against a zero column of K_k.
+    tile_products<NK, TILES>(
+        wave,
+        [&](int tt, int st, double& a, double& b) {
+          const int ri = tt / NT, jj = tt - ri * NT;
+          const int r = 16 * ri + r16, sb = r / n, i1 = r - sb * n;
+          a = sb < SB ? Us[i1 * XPS + sb * n + 4 * st + kg] : 0.0;
+          b = Ks[(16 * jj + r16) * KPS + 4 * st + kg];
+        },
+        [&](int tt, const v4d& acc) {
+          const int ri = tt / NT, jj = tt - ri * NT;
+          const int i2 = 16 * jj + r16;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int r = 16 * ri + kg + 4 * rr, sb = r / n, i1 = r - sb * n;
+            const int64_t sl = s0 + sb;
+            if (sb < SB && sl < nslab && i2 < n) {
+              const int64_t t = sl / n, a0 = sl - t * n;
+              T1[((t * nq + k) * n + a0) * n2 + i1 * n + i2] = acc[rr];
+            }
+          }
+        });
+  }
+}
+
 // Phi_t(i0, c) = sum_k w_k sum_a K_k(i0, a) T1[t][k][a][c], c = (a1, a2): grid
 // (ceil(n^2 / 64), Tc, G), 256 threads; wave w owns the 16 columns
 // c0 + 16 w .. + 16 and all NT tiles of i0.  Per node, w_k K_k is staged in
@@ -545,6 +658,13 @@ void launch_slab(const double* X, const double* K, int n, int nq, int64_t nslab,
                      T1, xmod, kstride);
 }
 
+// two slabs per work group for 33 <= n <= 40 (NT 3), one table set
+void launch_slab2(const double* X, const double* K, int n, int nq, int64_t nslab, double* T1, hipStream_t s,
+                  int64_t xmod = INT64_MAX, int kc = 1) {
+  hipLaunchKernelGGL((exch_slab2_kernel<3, 5, 10>), dim3(nblk(nslab, 2), kc), dim3(256), 0, s, X, K, n, nq, nslab,
+                     T1, xmod);
+}
+
 // Work groups a launch of the mode products should hold at least: several
 // per compute unit, so that the latency of the staged loads is hidden.
 constexpr int64_t kModeGroups = 2048;
@@ -572,6 +692,7 @@ hipError_t launch_mode_products(const double* X, int64_t T, int64_t xmod, const 
   } else {
     if (NT == 1) launch_slab<1, 4>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nblk(nslab, 4), nq));
     else if (NT == 2) launch_slab<2, 2>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nblk(nslab, 2), nq));
+    else if (NT == 3 && n <= 40) launch_slab2(X, K, n, nq, nslab, T1, s, xmod, node_runs(nblk(nslab, 2), nq));
     else if (NT == 3) launch_slab<3, 1>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nslab, nq));
     else launch_slab<4, 1>(X, K, n, nq, nslab, T1, s, xmod, 0, node_runs(nslab, nq));
   }
@@ -657,6 +778,7 @@ hipError_t launch_exchange(int prec, const double* M, int nb, int64_t npair, con
     const int64_t nslab = tc * n;
     if (NT == 1) launch_slab<1, 4>(Xc, tb.K, n, nq, nslab, T1, s);
     else if (NT == 2) launch_slab<2, 2>(Xc, tb.K, n, nq, nslab, T1, s);
+    else if (NT == 3 && n <= 40) launch_slab2(Xc, tb.K, n, nq, nslab, T1, s);
     else if (NT == 3) launch_slab<3, 1>(Xc, tb.K, n, nq, nslab, T1, s);
     else launch_slab<4, 1>(Xc, tb.K, n, nq, nslab, T1, s);
     const dim3 mg(nblk(n2, 64), (unsigned)tc);

@@ -275,11 +275,13 @@ def test_apply_J_from_prepared_operands(tai, prec):
     assert torch.equal(tai.apply_J_compressed(Uk, Kck, D, P, Rk, prec=prec, pairs=pairs), Jref)
 
 
-@pytest.mark.parametrize("n,nodes", [(29, 0), (41, 0), (24, 1)])
+@pytest.mark.parametrize("n,nodes", [(29, 0), (41, 0), (24, 1), (17, 0), (64, 0)])
 def test_compressed_B_odd_n_and_gauss_nodes(tai, n, nodes):
     """Odd n (the Jacobi sweep pads to an even order with a zero row and
-    column; n = 41 is no multiple of 8, the operands' padding step) and
-    Chebyshev-Gauss nodes, FP64 and F16X3 against the oracle's compressed
+    column; n = 41 is no multiple of 8, the operands' padding step),
+    Chebyshev-Gauss nodes, n = 17 (one row past a 16 x 16 tile of the Gram
+    kernels, whose refinement pass forms V1^T W on padded tiles) and the
+    largest n, 64; FP64 and F16X3 against the oracle's compressed
     operands."""
     b = I.small_random(93, natoms=4, shells=("s", "p", "d"), box=3.0, alpha_lo=0.2, alpha_hi=20.0)
     P = I.Params(omega=0.5, nq=10, n=n, L=8.0, nodes=nodes, rank_tol=1e-6)

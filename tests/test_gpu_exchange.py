@@ -109,3 +109,28 @@ def test_exchange_chunked_tensors_bit_equal(tai, multi_tile, monkeypatch):
     monkeypatch.setenv("TAI_EXCHANGE_CHUNK", "7")
     chunked = tai.exchange(Mg, b.nb, Qg, P)
     assert torch.equal(one, chunked)
+
+
+@pytest.mark.parametrize("n", [37, 40])
+def test_exchange_two_slab_products(tai, n, monkeypatch):
+    """33 <= n <= 40 takes the slab products two slabs per work group (the
+    products K [X X'] and [U; U'] K^T packed side by side). 5 s functions
+    and 3 orbitals give 15 tensors: at n = 37 the slab count is odd, so the
+    last work group holds one slab, and for n < 40 the inner index runs past
+    n against the zero columns of K. Against the oracle's grid form, and
+    bit-equal when the tensors run in chunks of 7."""
+    import torch
+    b = I.small_random(105, natoms=5, shells=("s",), box=4.0, alpha_lo=0.2, alpha_hi=20.0)
+    assert b.nb == 5
+    P = I.Params(omega=0.5, nq=6, n=n, L=8.0)
+    Q = np.random.default_rng(11).standard_normal((3, b.nb)) / np.sqrt(b.nb)
+    K, w = _tables(P)
+    Mr = T.moments(b.center, b.alpha, b.lxyz, P.L, P.n)
+    ref = T.exchange_grid(Mr, K, w, Q)
+    Mg = tai.moments(b, P)
+    Qg = torch.as_tensor(Q, device=Mg.device)
+    got = tai.exchange(Mg, b.nb, Qg, P)
+    err = np.max(np.abs(got.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-10, (n, err)
+    monkeypatch.setenv("TAI_EXCHANGE_CHUNK", "7")
+    assert torch.equal(tai.exchange(Mg, b.nb, Qg, P), got)
