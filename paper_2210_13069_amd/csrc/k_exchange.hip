@@ -471,12 +471,13 @@ exch_slab2_kernel(const double* __restrict__ X, const double* __restrict__ K, in
 // and T1 fragments are loaded into registers while the current node's MFMAs
 // run.  Tensor t's tables start at K + t kstride.  With G > 1 the nodes are
 // split into G equal runs and run g writes its partial sums to the g-th
-// block of Tc tensors at Phi.
-template <int NT>
+// block of Tc tensors at Phi.  NK inner steps of 4 (NP / 4, or 10 for
+// 33 <= n <= 40: the inner index stops at 40).
+template <int NT, int NK = 4 * NT>
 __global__ void __launch_bounds__(256)
 exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, const double* __restrict__ w, int n,
                   int nq, double* __restrict__ Phi, int64_t kstride) {
-  constexpr int NP = 16 * NT, PS = NP + 1, NK = NP / 4;
+  constexpr int NP = 16 * NT, PS = NP + 1;
   constexpr int KPER = (NP * NP + 255) / 256;
   __shared__ double Ws[NP * PS];
   const int lane = threadIdx.x & 63;
@@ -706,6 +707,8 @@ hipError_t launch_mode_products(const double* X, int64_t T, int64_t xmod, const 
   const dim3 mg(nblk(n2, 64), (unsigned)T0, (unsigned)g);
   if (NT == 1) hipLaunchKernelGGL((exch_mode0_kernel<1>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
   else if (NT == 2) hipLaunchKernelGGL((exch_mode0_kernel<2>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
+  else if (NT == 3 && n <= 40)
+    hipLaunchKernelGGL((exch_mode0_kernel<3, 10>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
   else if (NT == 3) hipLaunchKernelGGL((exch_mode0_kernel<3>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
   else hipLaunchKernelGGL((exch_mode0_kernel<4>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
   if (g > 1) hipLaunchKernelGGL(sum_runs_kernel, dim3(nblk(len, 256)), dim3(256), 0, s, part, g, len, Phi);
@@ -785,6 +788,8 @@ hipError_t launch_exchange(int prec, const double* M, int nb, int64_t npair, con
     double* Pc = Phi + t0 * n3;
     if (NT == 1) hipLaunchKernelGGL((exch_mode0_kernel<1>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
     else if (NT == 2) hipLaunchKernelGGL((exch_mode0_kernel<2>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
+    else if (NT == 3 && n <= 40)
+      hipLaunchKernelGGL((exch_mode0_kernel<3, 10>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
     else if (NT == 3) hipLaunchKernelGGL((exch_mode0_kernel<3>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
     else hipLaunchKernelGGL((exch_mode0_kernel<4>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
     const hipError_t e = hipGetLastError();
