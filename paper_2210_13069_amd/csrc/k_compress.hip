@@ -358,6 +358,9 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ G, int n,
         pair_of(j, u, v);
         const double2 ri = rcs[i], rj = rcs[j];
         const double ci = ri.x, si = ri.y, cj = rj.x, sj = rj.y;
+        // two identity rotations (c = 1, s = 0) give back the block exactly:
+        // in late sweeps most blocks are left as they are
+        if (si == 0.0 && sj == 0.0) continue;
         const double a_pu = A[p * S + u], a_pv = A[p * S + v], a_qu = A[q * S + u], a_qv = A[q * S + v];
         const double b_pu = cj * a_pu - sj * a_pv, b_pv = sj * a_pu + cj * a_pv;
         const double b_qu = cj * a_qu - sj * a_qv, b_qv = sj * a_qu + cj * a_qv;
@@ -375,6 +378,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ G, int n,
         pair_of(qj[k], u, v);
         const double2 rj = rcs[qj[k]];
         const double c = rj.x, sn = rj.y;
+        if (sn == 0.0) continue;   // the identity rotation
         const double x = Q[r * S + u], y = Q[r * S + v];
         Q[r * S + u] = c * x - sn * y;
         Q[r * S + v] = sn * x + c * y;
