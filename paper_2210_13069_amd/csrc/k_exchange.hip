@@ -18,8 +18,9 @@
 //  * exch_mode0_kernel: Phi_t(i0, c) = sum_{k, a0} w_k K_k(i0, a0) T1[t][k][a0][c]
 //    for c = (a1, a2): one FP64 product with inner length nq n per tensor;
 //  * exch_dot_kernel: K = 2 (2/sqrt(pi)) X Phi^T over the flattened (j, a)
-//    index, 64 x 64 output tiles staged through LDS, split along the inner
-//    index into partials that exch_dot_sum_kernel adds in a fixed order.
+//    index, the 64 x 64 output tiles on and above the diagonal staged through
+//    LDS, split along the inner index into partials that exch_dot_sum_kernel
+//    adds in a fixed order (each entry and its mirror from the same tile).
 //
 // No atomics: every sum runs in a fixed order, so the result is deterministic.
 #include "tai_internal.h"
@@ -549,7 +550,10 @@ exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, c
 // f = (j, a) over norb n^3 values, split into nsplit equal slices; rows mu of
 // X and nu of Phi are staged in LDS 32 inner values at a time (rows
 // contiguous in memory).  Wave w owns the 32 x 32 quarter (w / 2, w % 2) of the
-// 64 x 64 tile.  part[s][mu][nu] = sum over slice s of X(mu, f) Phi(nu, f).
+// 64 x 64 tile.  part[s][mu][nu] = sum over slice s of X(mu, f) Phi(nu, f),
+// for the tiles on and above the diagonal only (K is symmetric; the sum
+// kernel reads entry (min, max) for both orders, so K comes out exactly
+// symmetric).
 constexpr int kDK = 32;
 __global__ void __launch_bounds__(256)
 exch_dot_kernel(const double* __restrict__ X, const double* __restrict__ Phi, int nb, int norb, int64_t n3,
@@ -560,6 +564,8 @@ exch_dot_kernel(const double* __restrict__ X, const double* __restrict__ Phi, in
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
+  // K is symmetric: only the tiles on and above the diagonal are formed
+  if (blockIdx.y < blockIdx.x) return;
   const int mu0 = blockIdx.x * 64, nu0 = blockIdx.y * 64;
   const int64_t total = (int64_t)norb * n3;
   const int64_t f0 = (int64_t)blockIdx.z * slice;
@@ -623,11 +629,15 @@ sum_runs_kernel(const double* __restrict__ part, int nrun, int64_t len, double* 
 
 // K(mu, nu) = 2 (2/sqrt(pi)) sum_s part[s][mu][nu], slices in order.
 __global__ void __launch_bounds__(256)
-exch_dot_sum_kernel(const double* __restrict__ part, int nsplit, int64_t nn, double* __restrict__ Kx) {
+exch_dot_sum_kernel(const double* __restrict__ part, int nsplit, int nb, double* __restrict__ Kx) {
+  const int64_t nn = (int64_t)nb * nb;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;
+  // both (mu, nu) and (nu, mu) take the entry of the upper tiles
+  const int64_t mu = i / nb, nu = i - mu * nb;
+  const int64_t src = mu <= nu ? i : nu * nb + mu;
   double s = 0.0;
-  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * nn + i];
+  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * nn + src];
   Kx[i] = 2.0 * kTwoOverSqrtPi * s;
 }
 
@@ -727,7 +737,7 @@ ExchangeWork exchange_work_plan(int n, int nq, int nb, int norb, bool listed, in
     if (cap > 0) p.tchunk = std::min<int64_t>(p.tchunk, cap);
   }
   const int64_t total = (int64_t)norb * n3;
-  const int64_t tiles = (int64_t)((nb + 63) / 64) * ((nb + 63) / 64);
+  const int64_t tb64 = (nb + 63) / 64, tiles = tb64 * (tb64 + 1) / 2;   // tiles on and above the diagonal
   int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(1024, 2048 / tiles));
   const int64_t slice = ((total + nsplit - 1) / nsplit + kDK - 1) / kDK * kDK;
   p.nsplit = (int)((total + slice - 1) / slice);
@@ -799,7 +809,7 @@ hipError_t launch_exchange(int prec, const double* M, int nb, int64_t npair, con
   const dim3 dg(nblk(nb, 64), nblk(nb, 64), p.nsplit);
   hipLaunchKernelGGL(exch_dot_kernel, dg, dim3(256), 0, s, X, Phi, nb, norb, n3, p.slice, part);
   const int64_t nn = (int64_t)nb * nb;
-  hipLaunchKernelGGL(exch_dot_sum_kernel, dim3(nblk(nn, 256)), dim3(256), 0, s, part, p.nsplit, nn, Kx);
+  hipLaunchKernelGGL(exch_dot_sum_kernel, dim3(nblk(nn, 256)), dim3(256), 0, s, part, p.nsplit, nb, Kx);
   return hipGetLastError();
 }
 
