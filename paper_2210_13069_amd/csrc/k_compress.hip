@@ -128,29 +128,30 @@ __device__ __forceinline__ void gram_body(const double* __restrict__ M, const do
     __syncthreads();
     if (qb + kGramKB < q1) fetch(qb + kGramKB);
     if (XF) {
-      // y_k(r) = sum_a V1(a, r) w_k(a) for the k groups kt = wave, wave + 4:
-      // lane l holds the A operand w_{16 kt + l % 16}(a0 + l / 16) and the
-      // B operand V1(a0 + l / 16, 16 R + l % 16); the result tile (k, r)
-      // lands on lane l as rows k = 16 kt + l / 16 + 4 x, column l % 16
+      // y_k(r) = sum_a V1(a, r) w_k(a) for the k groups kt = wave, wave + 4,
+      // in steps of 4 values of a from ab: lane l holds the A operand
+      // w_{16 kt + l % 16}(ab + l / 16) and the B operand V1(ab + l / 16,
+      // 16 rt + l % 16) of column tile rt; the result tile (k, r) lands on
+      // lane l as rows k = 16 kt + l / 16 + 4 x, column 16 rt + l % 16
       constexpr int kKT = kGramK / 16;
       for (int kt = wave; kt < kKT; kt += 4) {
         v4d y[4];
 #pragma unroll
-        for (int R = 0; R < 4; ++R) y[R] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int rt = 0; rt < 4; ++rt) y[rt] = v4d{0.0, 0.0, 0.0, 0.0};
         const double* arow = s_m + (16 * kt + (lane & 15)) * kGramPad + (lane >> 4);
         const double* brow = s_v1 + (lane >> 4) * NP + (lane & 15);
         for (int ab = 0; ab < NP; ab += 4) {
           const double av = arow[ab];
 #pragma unroll
-          for (int R = 0; R < 4; ++R)
-            if (R < T) y[R] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, brow[ab * NP + 16 * R], y[R], 0, 0, 0);
+          for (int rt = 0; rt < 4; ++rt)
+            if (rt < T) y[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, brow[ab * NP + 16 * rt], y[rt], 0, 0, 0);
         }
 #pragma unroll
-        for (int R = 0; R < 4; ++R)
-          if (R < T)
+        for (int rt = 0; rt < 4; ++rt)
+          if (rt < T)
 #pragma unroll
             for (int x = 0; x < 4; ++x)
-              s_m[(16 * kt + (lane >> 4) + 4 * x) * kGramPad + 16 * R + (lane & 15)] = y[R][x];
+              s_m[(16 * kt + (lane >> 4) + 4 * x) * kGramPad + 16 * rt + (lane & 15)] = y[rt][x];
       }
       __syncthreads();
     }
