@@ -292,6 +292,13 @@ exch_slab_kernel(const double* __restrict__ X, const double* __restrict__ K, int
     }
   }
   const double* Kt = K + (s0 / n) * kstride;
+  // T1 offset of each slab's node 0 (the node adds k n^3), -1 past the end
+  int64_t tbase[SB];
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb) {
+    const int64_t sl = s0 + sb, t = sl / n, a0 = sl - t * n;
+    tbase[sb] = sl < nslab ? (t * nq * n + a0) * n2 : -1;
+  }
   const int kper = (nq + (int)gridDim.y - 1) / (int)gridDim.y;
   const int k0 = (int)blockIdx.y * kper, k1 = min(nq, k0 + kper);
   double kr[KPER];
@@ -339,10 +346,8 @@ exch_slab_kernel(const double* __restrict__ X, const double* __restrict__ K, int
         },
         [&](int tt, const v4d& acc) {
           const int sb = tt / (NT * NT), ij = tt - sb * NT * NT, i = ij / NT, jj = ij - i * NT;
-          const int64_t sl = s0 + sb;
-          if (sl >= nslab) return;
-          const int64_t t = sl / n, a0 = sl - t * n;
-          double* out = T1 + ((t * nq + k) * n + a0) * n2;
+          if (tbase[sb] < 0) return;
+          double* out = T1 + tbase[sb] + (int64_t)k * n * n2;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int a1 = 16 * i + kg + 4 * r, a2 = 16 * jj + r16;
@@ -378,13 +383,15 @@ exch_slab2_kernel(const double* __restrict__ X, const double* __restrict__ K, in
   const int r16 = lane & 15, kg = lane >> 4;
   const int64_t s0 = (int64_t)blockIdx.x * SB;
   const int64_t n2 = (int64_t)n * n;
+  // slab of a packed index x < 16 CT = 80 <= 3 n: two compares, no division
+  auto slab_of = [n](int x) { return (x >= n ? 1 : 0) + (x >= 2 * n ? 1 : 0); };
   {
     double xr[XPER];
 #pragma unroll
     for (int i = 0; i < XPER; ++i) {
       const int e = threadIdx.x + 256 * i;
       const int a1 = e / XC, col = e - a1 * XC;
-      const int sb = col / n, a2 = col - sb * n;
+      const int sb = slab_of(col), a2 = col - sb * n;
       const int64_t sl = s0 + sb;
       xr[i] = 0.0;
       if (e < XR * XC && a1 < n && sb < SB && sl < nslab) {
@@ -397,6 +404,13 @@ exch_slab2_kernel(const double* __restrict__ X, const double* __restrict__ K, in
       const int e = threadIdx.x + 256 * i;
       if (e < XR * XC) Xs[(e / XC) * XPS + e % XC] = xr[i];
     }
+  }
+  // T1 offset of each slab's node 0 (the node adds k n^3), -1 past the end
+  int64_t tbase[SB];
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb) {
+    const int64_t sl = s0 + sb, t = sl / n, a0 = sl - t * n;
+    tbase[sb] = sl < nslab ? (t * nq * n + a0) * n2 : -1;
   }
   const int kper = (nq + (int)gridDim.y - 1) / (int)gridDim.y;
   const int k0 = (int)blockIdx.y * kper, k1 = min(nq, k0 + kper);
@@ -445,7 +459,7 @@ exch_slab2_kernel(const double* __restrict__ X, const double* __restrict__ K, in
         wave,
         [&](int tt, int st, double& a, double& b) {
           const int ri = tt / NT, jj = tt - ri * NT;
-          const int r = 16 * ri + r16, sb = r / n, i1 = r - sb * n;
+          const int r = 16 * ri + r16, sb = slab_of(r), i1 = r - sb * n;
           a = sb < SB ? Us[i1 * XPS + sb * n + 4 * st + kg] : 0.0;
           b = Ks[(16 * jj + r16) * KPS + 4 * st + kg];
         },
@@ -454,12 +468,9 @@ exch_slab2_kernel(const double* __restrict__ X, const double* __restrict__ K, in
           const int i2 = 16 * jj + r16;
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) {
-            const int r = 16 * ri + kg + 4 * rr, sb = r / n, i1 = r - sb * n;
-            const int64_t sl = s0 + sb;
-            if (sb < SB && sl < nslab && i2 < n) {
-              const int64_t t = sl / n, a0 = sl - t * n;
-              T1[((t * nq + k) * n + a0) * n2 + i1 * n + i2] = acc[rr];
-            }
+            const int r = 16 * ri + kg + 4 * rr, sb = slab_of(r), i1 = r - sb * n;
+            const int64_t base = sb == 0 ? tbase[0] : sb == 1 ? tbase[1] : -1;
+            if (base >= 0 && i2 < n) T1[base + (int64_t)k * n * n2 + i1 * n + i2] = acc[rr];
           }
         });
   }
@@ -576,16 +587,22 @@ exch_dot_kernel(const double* __restrict__ X, const double* __restrict__ Phi, in
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj) acc[i][jj] = v4d{0.0, 0.0, 0.0, 0.0};
   const int wi = wave >> 1, wj = wave & 1;
+  // this thread stages column col of every batch, rows row0, row0 + 8, ...
+  static_assert(256 % kDK == 0, "a thread's column is the same in every row step");
+  const int col = threadIdx.x % kDK, row0 = threadIdx.x / kDK;
   for (int64_t fb = f0; fb < f1; fb += kDK) {
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * kDK; e += 256) {
-      const int row = e / kDK, col = e - row * kDK;
-      const int64_t f = fb + col;
+    const int64_t f = fb + col;
+    const bool fin = f < f1;
+    const int64_t fc = fin ? f : f0;              // past the slice: no load
+    const int64_t j = fc / n3, a = fc - j * n3;   // once per batch, not per row
+    const double* xcol = X + (j * nb + mu0) * n3 + a;
+    const double* pcol = Phi + (j * nb + nu0) * n3 + a;
+    for (int row = row0; row < 64; row += 256 / kDK) {
       double xv = 0.0, pv = 0.0;
-      if (f < f1) {
-        const int64_t j = f / n3, a = f - j * n3;
-        if (mu0 + row < nb) xv = X[(j * nb + mu0 + row) * n3 + a];
-        if (nu0 + row < nb) pv = Phi[(j * nb + nu0 + row) * n3 + a];
+      if (fin) {
+        if (mu0 + row < nb) xv = xcol[row * n3];
+        if (nu0 + row < nb) pv = pcol[row * n3];
       }
       xs[row * DS + col] = xv;
       ps[row * DS + col] = pv;
