@@ -477,15 +477,17 @@ exch_slab2_kernel(const double* __restrict__ X, const double* __restrict__ K, in
 }
 
 // Phi_t(i0, c) = sum_k w_k sum_a K_k(i0, a) T1[t][k][a][c], c = (a1, a2): grid
-// (ceil(n^2 / 64), Tc, G), 256 threads; wave w owns the 16 columns
-// c0 + 16 w .. + 16 and all NT tiles of i0.  Per node, w_k K_k is staged in
+// (ceil(n^2 / (64 CW)), Tc, G), 256 threads; wave w owns the CW tiles of 16
+// columns from c0 + 16 CW w and all NT tiles of i0 (with CW = 2 each read of
+// w_k K_k from LDS feeds two MFMAs and a wave has twice the T1 loads in
+// flight).  Per node, w_k K_k is staged in
 // LDS; the T1 fragments stream from memory once, and the next node's w_k K_k
 // and T1 fragments are loaded into registers while the current node's MFMAs
 // run.  Tensor t's tables start at K + t kstride.  With G > 1 the nodes are
 // split into G equal runs and run g writes its partial sums to the g-th
 // block of Tc tensors at Phi.  NK inner steps of 4 (NP / 4, or 10 for
 // 33 <= n <= 40: the inner index stops at 40).
-template <int NT, int NK = 4 * NT>
+template <int NT, int NK = 4 * NT, int CW = 1>
 __global__ void __launch_bounds__(256)
 exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, const double* __restrict__ w, int n,
                   int nq, double* __restrict__ Phi, int64_t kstride) {
@@ -497,17 +499,24 @@ exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, c
   const int r16 = lane & 15, kg = lane >> 4;
   const int64_t n2 = (int64_t)n * n;
   const int64_t t = blockIdx.y;
-  const int64_t c = (int64_t)blockIdx.x * 64 + 16 * wave + r16;
-  const bool cok = c < n2;
+  int64_t c[CW];
+  bool cok[CW];
+#pragma unroll
+  for (int j = 0; j < CW; ++j) {
+    c[j] = (int64_t)blockIdx.x * (64 * CW) + 16 * (CW * wave + j) + r16;
+    cok[j] = c[j] < n2;
+  }
   const double* Tt = T1 + t * nq * n * n2;
   const double* Kt = K + t * kstride;
   const int kper = (nq + (int)gridDim.z - 1) / (int)gridDim.z;
   const int k0 = (int)blockIdx.z * kper, k1 = min(nq, k0 + kper);
-  v4d acc[NT];
+  v4d acc[CW][NT];
 #pragma unroll
-  for (int i = 0; i < NT; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
-  double kr[KPER], bv[2][NK];
-  auto load = [&](int k, double (&b)[NK]) {
+  for (int j = 0; j < CW; ++j)
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[j][i] = v4d{0.0, 0.0, 0.0, 0.0};
+  double kr[KPER], bv[2][CW][NK];
+  auto load = [&](int k, double (&b)[CW][NK]) {
     const double wk = w[k];
     const double* Kk = Kt + (int64_t)k * n2;
 #pragma unroll
@@ -518,12 +527,14 @@ exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, c
     }
     const double* Tk = Tt + (int64_t)k * n * n2;
 #pragma unroll
-    for (int st = 0; st < NK; ++st) {
-      const int a = 4 * st + kg;
-      b[st] = (cok && a < n) ? Tk[a * n2 + c] : 0.0;
-    }
+    for (int j = 0; j < CW; ++j)
+#pragma unroll
+      for (int st = 0; st < NK; ++st) {
+        const int a = 4 * st + kg;
+        b[j][st] = (cok[j] && a < n) ? Tk[a * n2 + c[j]] : 0.0;
+      }
   };
-  auto node = [&](int k, double (&cur)[NK], double (&nxt)[NK]) {
+  auto node = [&](int k, double (&cur)[CW][NK], double (&nxt)[CW][NK]) {
     lds_barrier();  // the previous node's Ws reads are done
 #pragma unroll
     for (int i = 0; i < KPER; ++i) {
@@ -536,8 +547,12 @@ exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, c
     for (int st = 0; st < NK; ++st) {
       const int a = 4 * st + kg;
 #pragma unroll
-      for (int i = 0; i < NT; ++i)
-        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[(16 * i + r16) * PS + a], cur[st], acc[i], 0, 0, 0);
+      for (int i = 0; i < NT; ++i) {
+        const double av = Ws[(16 * i + r16) * PS + a];
+#pragma unroll
+        for (int j = 0; j < CW; ++j)
+          acc[j][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cur[j][st], acc[j][i], 0, 0, 0);
+      }
     }
   };
   if (k0 < k1) load(k0, bv[0]);
@@ -545,15 +560,18 @@ exch_mode0_kernel(const double* __restrict__ T1, const double* __restrict__ K, c
     node(k, bv[0], bv[1]);
     if (k + 1 < k1) node(k + 1, bv[1], bv[0]);
   }
-  if (!cok) return;
   double* out = Phi + ((int64_t)blockIdx.z * gridDim.y + t) * n * n2;
 #pragma unroll
-  for (int i = 0; i < NT; ++i)
+  for (int j = 0; j < CW; ++j) {
+    if (!cok[j]) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i0 = 16 * i + kg + 4 * r;
-      if (i0 < n) out[i0 * n2 + c] = acc[i][r];
-    }
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i0 = 16 * i + kg + 4 * r;
+        if (i0 < n) out[i0 * n2 + c[j]] = acc[j][i][r];
+      }
+  }
 }
 
 // Partial exchange matrix over one slice of the inner index: grid
@@ -727,15 +745,16 @@ hipError_t launch_mode_products(const double* X, int64_t T, int64_t xmod, const 
   // mode 0: with few output tensors the node sum is split into runs whose
   // partial tensors (in part, part_len doubles) are added in run order
   const int64_t len = T0 * n * n2;
-  int g = node_runs((int64_t)nblk(n2, 64) * T0, nq0);
+  const int cw = (NT == 3 && n <= 40) ? 2 : 1;   // 16-column tiles per wave of the mode-0 pass
+  int g = node_runs((int64_t)nblk(n2, 64 * cw) * T0, nq0);
   if (part == nullptr || part_len < 2 * len) g = 1;
   else g = (int)std::min<int64_t>(g, part_len / len);
   double* out = g > 1 ? part : Phi;
-  const dim3 mg(nblk(n2, 64), (unsigned)T0, (unsigned)g);
+  const dim3 mg(nblk(n2, 64 * cw), (unsigned)T0, (unsigned)g);
   if (NT == 1) hipLaunchKernelGGL((exch_mode0_kernel<1>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
   else if (NT == 2) hipLaunchKernelGGL((exch_mode0_kernel<2>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
   else if (NT == 3 && n <= 40)
-    hipLaunchKernelGGL((exch_mode0_kernel<3, 10>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
+    hipLaunchKernelGGL((exch_mode0_kernel<3, 10, 2>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
   else if (NT == 3) hipLaunchKernelGGL((exch_mode0_kernel<3>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
   else hipLaunchKernelGGL((exch_mode0_kernel<4>), mg, dim3(256), 0, s, T1, K, w, n, nq0, out, kstride0);
   if (g > 1) hipLaunchKernelGGL(sum_runs_kernel, dim3(nblk(len, 256)), dim3(256), 0, s, part, g, len, Phi);
@@ -811,12 +830,12 @@ hipError_t launch_exchange(int prec, const double* M, int nb, int64_t npair, con
     else if (NT == 3 && n <= 40) launch_slab2(Xc, tb.K, n, nq, nslab, T1, s);
     else if (NT == 3) launch_slab<3, 1>(Xc, tb.K, n, nq, nslab, T1, s);
     else launch_slab<4, 1>(Xc, tb.K, n, nq, nslab, T1, s);
-    const dim3 mg(nblk(n2, 64), (unsigned)tc);
+    const dim3 mg(nblk(n2, NT == 3 && n <= 40 ? 128 : 64), (unsigned)tc);
     double* Pc = Phi + t0 * n3;
     if (NT == 1) hipLaunchKernelGGL((exch_mode0_kernel<1>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
     else if (NT == 2) hipLaunchKernelGGL((exch_mode0_kernel<2>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
     else if (NT == 3 && n <= 40)
-      hipLaunchKernelGGL((exch_mode0_kernel<3, 10>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
+      hipLaunchKernelGGL((exch_mode0_kernel<3, 10, 2>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
     else if (NT == 3) hipLaunchKernelGGL((exch_mode0_kernel<3>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
     else hipLaunchKernelGGL((exch_mode0_kernel<4>), mg, dim3(256), 0, s, T1, tb.K, tb.w, n, nq, Pc, 0);
     const hipError_t e = hipGetLastError();
