@@ -95,6 +95,9 @@ def test_exchange_multi_tile(tai, multi_tile, prec):
     got = tai.exchange(Mg, b.nb, torch.as_tensor(Q, device=Mg.device), P, prec=prec).cpu().numpy()
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     assert err <= (1e-10 if prec == 0 else 1e-6), err
+    # each entry and its mirror come from the same partial sums (the tiles on
+    # and above the diagonal), across the two 64-row tiles too
+    assert np.array_equal(got, got.T)
 
 
 def test_exchange_chunked_tensors_bit_equal(tai, multi_tile, monkeypatch):
